@@ -1,0 +1,47 @@
+"""CPU FP64 oracle for sketch-preconditioned Tikhonov least squares.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product (the HIP library and its
+Python binding) may import, call, link or execute anything in this package;
+only the tests, the smoke check and the benchmark's CPU-baseline leg do.  It
+shares no code with the GPU path: it never touches the GPU, the binding or
+the C library, and it receives its inputs from the seeded generators in
+``workloads``.
+
+What it computes (each function cites the passage it follows):
+
+* ``tikhonov.solve``  x_lam = argmin ||Ax-b||^2 + lam ||x||^2 for every lam
+  (eq. regLLS), by the direct Householder-QR route the paper names as the
+  classical alternative (Section 1.2): QR of [A; sqrt(lam) I] with right-hand
+  side [b; 0] (eq. regLLSover) when m >= n, and the minimum-norm solution of
+  [A sqrt(lam) I] z = b (eq. regLLSunder) when m < n.
+* ``tikhonov.statistical_dimension`` (Definition 1) and ``sd_hat`` (the
+  estimate from the sketch's singular values, Section 3.1.2).
+* ``tikhonov.chol_precond`` / ``lowrank_factors`` / ``lowrank_rinv``: the
+  preconditioners of Algorithms 1-3 written out densely for small checks.
+* ``tikhonov.lsqr_iteration_bound`` and the Lemma 2.1 / Theorem 3.2 bounds.
+* ``tikhonov.certify``: an a-posteriori bound on the forward error of a
+  candidate solution that holds at any size.
+
+Parity status: every function above is pinned by tests in
+tests/test_oracle_pins.py against closed forms, exact rational arithmetic,
+a LAPACK cross-check or the paper's own identities.
+"""
+
+from .tikhonov import (  # noqa: F401
+    solve,
+    solve_over,
+    solve_under,
+    statistical_dimension,
+    sd_hat,
+    lowrank_S,
+    lowrank_factors,
+    lowrank_rinv,
+    chol_precond,
+    chol_precond_under,
+    lsqr_iteration_bound,
+    lemma21_bound,
+    thm32_bound,
+    thm32_eps,
+    rel_err,
+    certify,
+)

@@ -1,0 +1,226 @@
+"""Plain FP64 reference computations (test infrastructure only; see package doc).
+
+Every routine is the textbook definition written out with numpy/LAPACK
+primitives (Householder QR, triangular solve, SVD, Cholesky) as steps; there
+is no blocking, fusion or reordering beyond what the definition states.
+"""
+
+from __future__ import annotations
+
+import math
+from typing import Iterable, Optional, Tuple
+
+import numpy as np
+from scipy.linalg import solve_triangular
+
+
+def _as_f64(A: np.ndarray) -> np.ndarray:
+    # FP32-stored problems are solved exactly as stored: the upcast is exact.
+    return np.asarray(A, dtype=np.float64)
+
+
+def solve_over(A: np.ndarray, b: np.ndarray, lams: Iterable[float]) -> np.ndarray:
+    """x_lam for m >= n via Householder QR of B = [A; sqrt(lam) I_n] (eq. regLLSover).
+
+    QR is taken in two stages that are exactly the QR of [A; sqrt(lam) I] with
+    right-hand side [b; 0]: first A = Q R_A together with c = Q^T b (the QR of
+    the bordered matrix [A b] delivers both), then for each lam the QR of the
+    2n x n matrix [R_A; sqrt(lam) I] bordered by [c; 0].  Since
+    diag(Q, I) has orthonormal columns, both stages minimise the same norm up
+    to the constant ||(I - Q Q^T) b||.  Back substitution gives x_lam.
+    Returns an (n, N) array, column i for lams[i].
+    """
+    A = _as_f64(A)
+    m, n = A.shape
+    if m < n:
+        raise ValueError("solve_over needs m >= n")
+    b = np.asarray(b, dtype=np.float64).reshape(m)
+    Rb = np.linalg.qr(np.column_stack([A, b]), mode="r")       # (n+1) x (n+1)
+    RA = Rb[:n, :n]
+    c = Rb[:n, n]
+    lams = np.asarray(list(lams), dtype=np.float64)
+    X = np.empty((n, lams.size))
+    for i, lam in enumerate(lams):
+        K = np.zeros((2 * n, n + 1))
+        K[:n, :n] = RA
+        K[:n, n] = c
+        K[n:, :n] = math.sqrt(lam) * np.eye(n)
+        R2 = np.linalg.qr(K, mode="r")
+        X[:, i] = solve_triangular(R2[:n, :n], R2[:n, n], lower=False)
+    return X
+
+
+def solve_under(A: np.ndarray, b: np.ndarray, lams: Iterable[float]) -> np.ndarray:
+    """x_lam for m < n as the top n entries of the minimum-norm solution of
+    [A sqrt(lam) I_m] z = b (eq. regLLSunder).
+
+    With the Householder QR A^T = Q_A R_L (so A = R_L^T Q_A^T), the QR of the
+    2m x m matrix [R_L; sqrt(lam) I] = Q_2 R_2 gives R_2^T R_2 = A A^T + lam I
+    and the minimum-norm solution of [R_L^T sqrt(lam) I] z = b is
+    z = Q_2 R_2^{-T} b; the first m entries of z mapped back by Q_A are x_lam.
+    Returns an (n, N) array.
+    """
+    A = _as_f64(A)
+    m, n = A.shape
+    if m >= n:
+        raise ValueError("solve_under needs m < n")
+    b = np.asarray(b, dtype=np.float64).reshape(m)
+    QA, RL = np.linalg.qr(A.T, mode="reduced")                  # n x m, m x m
+    lams = np.asarray(list(lams), dtype=np.float64)
+    X = np.empty((n, lams.size))
+    for i, lam in enumerate(lams):
+        K = np.vstack([RL, math.sqrt(lam) * np.eye(m)])
+        Q2, R2 = np.linalg.qr(K, mode="reduced")
+        w = solve_triangular(R2, b, trans="T", lower=False)      # R_2^{-T} b
+        z = Q2 @ w
+        X[:, i] = QA @ z[:m]
+    return X
+
+
+def solve(A: np.ndarray, b: np.ndarray, lams: Iterable[float]) -> np.ndarray:
+    """x_lam = argmin ||A x - b||^2 + lam ||x||^2 (eq. regLLS) for each lam."""
+    m, n = np.shape(A)
+    return solve_over(A, b, lams) if m >= n else solve_under(A, b, lams)
+
+
+def rel_err(x: np.ndarray, xref: np.ndarray) -> np.ndarray:
+    """Per-column ||x - xref||_2 / ||xref||_2."""
+    x = np.asarray(x, dtype=np.float64)
+    xref = np.asarray(xref, dtype=np.float64)
+    if x.ndim == 1:
+        return float(np.linalg.norm(x - xref) / np.linalg.norm(xref))
+    return np.linalg.norm(x - xref, axis=0) / np.linalg.norm(xref, axis=0)
+
+
+# ----------------------------------------------------------------------------
+# Statistical dimension (Definition 1) and its sketch estimate (Section 3.1.2)
+
+def statistical_dimension(sigma: np.ndarray, lam: float) -> float:
+    """sd_lam(A) = sum_i 1 / (1 + lam / sigma_i^2) over the nonzero sigma_i."""
+    s = np.asarray(sigma, dtype=np.float64)
+    s = s[s > 0]
+    return float(np.sum(1.0 / (1.0 + lam / (s * s))))
+
+
+def sd_hat(sigma_Y: np.ndarray, lam: float) -> float:
+    """Estimate of sd_lam(A) from the singular values of the sketch Y."""
+    return statistical_dimension(sigma_Y, lam)
+
+
+# ----------------------------------------------------------------------------
+# Preconditioners written out densely (Algorithms 1-3)
+
+def chol_precond(Y: np.ndarray, lam: float) -> np.ndarray:
+    """Upper-triangular R with R^T R = Y^T Y + lam I_n (Algorithm 1, steps 3-4)."""
+    Y = _as_f64(Y)
+    C = Y.T @ Y + lam * np.eye(Y.shape[1])
+    return np.linalg.cholesky(C).T
+
+
+def chol_precond_under(Y: np.ndarray, lam: float) -> np.ndarray:
+    """Upper-triangular R with R^T R = Y Y^T + lam I_m (Algorithm 2, steps 3-4)."""
+    Y = _as_f64(Y)
+    C = Y @ Y.T + lam * np.eye(Y.shape[0])
+    return np.linalg.cholesky(C).T
+
+
+def lowrank_factors(Y: np.ndarray, side: str = "right") -> Tuple[np.ndarray, np.ndarray]:
+    """Economy SVD of the sketch (Algorithm 3 step 4 / Algorithm 4 step 4).
+
+    side="right": Y = XA (s x n), returns (sigma, V) with V n x s.
+    side="left":  Y = AX (m x s), returns (sigma, U) with U m x s.
+    """
+    Y = _as_f64(Y)
+    U, sig, Vt = np.linalg.svd(Y, full_matrices=False)
+    return (sig, Vt.T.copy()) if side == "right" else (sig, U)
+
+
+def lowrank_S(sigma: np.ndarray, lam: float) -> np.ndarray:
+    """Diagonal of S: S_jj = 1 - (1 + sigma_j^2 / lam)^(-1/2) (Section 3.1, Algorithm 3 step 7)."""
+    s = np.asarray(sigma, dtype=np.float64)
+    return 1.0 - 1.0 / np.sqrt(1.0 + s * s / lam)
+
+
+def lowrank_rinv(V: np.ndarray, sigma: np.ndarray, lam: float,
+                 k: Optional[int] = None) -> np.ndarray:
+    """Dense R^{-1} = lam^{-1/2} (I - V_k S_k V_k^T) (eq. RinvOver), first k columns kept."""
+    V = np.asarray(V, dtype=np.float64)
+    k = V.shape[1] if k is None else k
+    Vk = V[:, :k]
+    S = lowrank_S(np.asarray(sigma)[:k], lam)
+    return (np.eye(V.shape[0]) - (Vk * S[None, :]) @ Vk.T) / math.sqrt(lam)
+
+
+# ----------------------------------------------------------------------------
+# Convergence statements
+
+def lsqr_iteration_bound(kappa: float, eps: float) -> int:
+    """Iterations after which LSQR's error has contracted by eps.
+
+    LSQR is CG on the normal equations of the preconditioned operator, whose
+    error in the energy norm contracts by at least (k-1)/(k+1) per step with
+    k its condition number (Golub & Van Loan, Section 11.3, applied to the
+    matrix M^T M whose condition number is k^2; Section 3.3 of the paper
+    states this bound).  With the factor 2 of the CG bound, l >= log(2/eps) /
+    log((k+1)/(k-1)) steps suffice.
+    """
+    if kappa <= 1.0:
+        return 1
+    return int(math.ceil(math.log(2.0 / eps) / math.log((kappa + 1.0) / (kappa - 1.0))))
+
+
+def lemma21_bound(XU: np.ndarray) -> float:
+    """Lemma 2.1: kappa(B R^{-1}) <= max(1, s_max(XU_A)) / min(1, s_min(XU_A))."""
+    s = np.linalg.svd(np.asarray(XU, dtype=np.float64), compute_uv=False)
+    return max(1.0, s[0]) / min(1.0, s[-1])
+
+
+def thm32_eps(U1: np.ndarray, X: np.ndarray) -> float:
+    """epsilon of condition (eq. cond1over): || U1^T X^T X U1 - U1^T U1 ||_2."""
+    XU = X @ U1
+    return float(np.linalg.norm(XU.T @ XU - U1.T @ U1, 2))
+
+
+def thm32_bound(eps: float) -> float:
+    """Theorem 3.2: kappa(B R^{-1}) <= sqrt((1 + eps) / (1 - eps))."""
+    return math.sqrt((1.0 + eps) / (1.0 - eps))
+
+
+# ----------------------------------------------------------------------------
+# A-posteriori certificate
+
+def certify(A: np.ndarray, b: np.ndarray, lams: Iterable[float], X: np.ndarray,
+            col_chunk: int = 256) -> np.ndarray:
+    """Upper bound on ||x - x_lam|| / ||x_lam|| for candidate solutions X (n, N).
+
+    x_lam solves the normal equations (A^T A + lam I) x = A^T b of eq. regLLS,
+    whose matrix has smallest eigenvalue at least lam.  With the gradient
+    g = A^T (b - A x) - lam x, ||x - x_lam|| <= ||g|| / lam, and the triangle
+    inequality turns that into the relative bound
+    (||g|| / lam) / (||x|| - ||g|| / lam).  g is accumulated in 80-bit extended
+    precision, column block by column block, so its own rounding error stays
+    far below the FP64 errors being certified.  Returns one bound per column
+    (inf where the bound is vacuous).
+    """
+    A = np.asarray(A)
+    m, n = A.shape
+    lams = np.asarray(list(lams), dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64).reshape(n, -1)
+    ld = np.longdouble
+    R = np.tile(np.asarray(b, dtype=ld).reshape(m, 1), (1, X.shape[1]))
+    Xl = X.astype(ld)
+    for c0 in range(0, n, col_chunk):
+        Ac = A[:, c0:c0 + col_chunk].astype(ld)
+        R -= Ac @ Xl[c0:c0 + col_chunk]
+    G = np.empty((n, X.shape[1]), dtype=ld)
+    for c0 in range(0, n, col_chunk):
+        Ac = A[:, c0:c0 + col_chunk].astype(ld)
+        G[c0:c0 + col_chunk] = Ac.T @ R
+    G -= Xl * lams.astype(ld)[None, :]
+    gn = np.sqrt(np.sum(G * G, axis=0)).astype(np.float64)
+    dx = gn / lams
+    xn = np.linalg.norm(X, axis=0)
+    out = np.full(X.shape[1], np.inf)
+    ok = xn > dx
+    out[ok] = dx[ok] / (xn[ok] - dx[ok])
+    return out

@@ -1,0 +1,289 @@
+"""Pins for the CPU oracle: each check ties it to something other than itself.
+
+* closed forms on A = U diag(sigma) V^T with known factors (SVD identity);
+* exact rational arithmetic on tiny inputs (brute force);
+* a LAPACK least-squares cross-check (SVD-based gelsd, a different route);
+* the paper's identities (Definition 1 vs Lemma 3.1, eq. RinvOver, the BP2
+  equivalence of Section 4.1, Lemma 2.1, Theorem 3.2);
+* planted mistakes: a plausible slip in the oracle must break one pin.
+"""
+
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import tikhonov as T
+import workloads as W
+
+
+# ----------------------------------------------------------------------------
+# helpers
+
+def closed_form(U, sigma, V, b, lams):
+    """x_lam = V diag(sigma / (sigma^2 + lam)) U^T b for A = U diag(sigma) V^T."""
+    c = U.T @ b
+    return np.stack([V @ (sigma / (sigma ** 2 + lam) * c) for lam in lams], axis=1)
+
+
+def exact_tikhonov(A, b, lam):
+    """Exact rational solution of (A^T A + lam I) x = A^T b (Gauss-Jordan on Fractions)."""
+    m, n = A.shape
+    Af = [[Fraction(float(A[i, j])) for j in range(n)] for i in range(m)]
+    bf = [Fraction(float(v)) for v in b]
+    lf = Fraction(float(lam))
+    M = [[sum(Af[k][i] * Af[k][j] for k in range(m)) + (lf if i == j else 0) for j in range(n)]
+         for i in range(n)]
+    r = [sum(Af[k][i] * bf[k] for k in range(m)) for i in range(n)]
+    for col in range(n):
+        piv = next(i for i in range(col, n) if M[i][col] != 0)
+        M[col], M[piv] = M[piv], M[col]
+        r[col], r[piv] = r[piv], r[col]
+        for i in range(n):
+            if i != col and M[i][col] != 0:
+                f = M[i][col] / M[col][col]
+                M[i] = [a - f * c for a, c in zip(M[i], M[col])]
+                r[i] -= f * r[col]
+    return np.array([float(r[i] / M[i][i]) for i in range(n)])
+
+
+def small_under(m=30, n=120, seed=3, sig_lo=1e-3):
+    rng = np.random.default_rng(seed)
+    U = W.haar(rng, m, m)
+    V = W.haar(rng, n, m)
+    sigma = np.logspace(0, math.log10(sig_lo), m)
+    A = (U * sigma) @ V.T
+    b = A @ rng.standard_normal(n) + 1e-3 * rng.standard_normal(m)
+    return A, b, U, sigma, V
+
+
+# ----------------------------------------------------------------------------
+# x_lam pins
+
+@pytest.mark.parametrize("m,n", [(300, 40), (2000, 100)])
+def test_closed_form_over(m, n):
+    p = W.over_svd(m=m, n=n, N=10)
+    X = oracle.solve(p.A, p.b, p.lams)
+    Xc = closed_form(p.U, p.sigma, p.V, p.b, p.lams)
+    err = T.rel_err(X, Xc)
+    # A is formed from its factors with rounding; kappa(B) <= 1e3 here
+    assert np.all(err < 1e-11), err
+
+
+def test_closed_form_under():
+    A, b, U, sigma, V = small_under()
+    lams = np.logspace(-6, 0, 7)
+    X = oracle.solve(A, b, lams)
+    Xc = closed_form(U, sigma, V, b, lams)
+    assert np.all(T.rel_err(X, Xc) < 1e-10)
+
+
+@pytest.mark.parametrize("shape", [(6, 3), (3, 6), (5, 5), (7, 2)])
+@pytest.mark.parametrize("lam", [0.5, 1e-3, 3.0])
+def test_brute_force_rational(shape, lam):
+    rng = np.random.default_rng(abs(hash(shape)) % 1000)
+    A = rng.standard_normal(shape)
+    b = rng.standard_normal(shape[0])
+    x = oracle.solve(A, b, [lam])[:, 0]
+    xe = exact_tikhonov(A, b, lam)
+    assert T.rel_err(x, xe) < 1e-13
+
+
+def test_lapack_crosscheck():
+    p = W.over_svd(m=500, n=60, N=5, sig_lo=1e-3)
+    X = oracle.solve(p.A, p.b, p.lams)
+    for i, lam in enumerate(p.lams):
+        B = np.vstack([p.A, math.sqrt(lam) * np.eye(p.n)])
+        bh = np.concatenate([p.b, np.zeros(p.n)])
+        xl = np.linalg.lstsq(B, bh, rcond=None)[0]
+        assert T.rel_err(X[:, i], xl) < 1e-11
+    A, b, *_ = small_under(m=20, n=70)
+    Xu = oracle.solve(A, b, [1e-2, 1.0])
+    for i, lam in enumerate([1e-2, 1.0]):
+        D = np.hstack([A, math.sqrt(lam) * np.eye(20)])
+        z = np.linalg.lstsq(D, b, rcond=None)[0]
+        assert T.rel_err(Xu[:, i], z[:70]) < 1e-11
+
+
+def test_fp32_storage_is_exact_upcast():
+    p = W.under_scaled(m=40, n=300, N=3)
+    assert p.A.dtype == np.float32
+    X1 = oracle.solve(p.A, p.b, p.lams)
+    X2 = oracle.solve(p.A.astype(np.float64), p.b, p.lams)
+    assert np.array_equal(X1, X2)
+
+
+# ----------------------------------------------------------------------------
+# statistical dimension
+
+def test_sd_definition_matches_lemma31():
+    # ||U_1||_F^2 = sd_lam(A), U_1 the top m rows of B's left singular vectors
+    rng = np.random.default_rng(5)
+    m, n = 120, 25
+    A = rng.standard_normal((m, n)) * np.logspace(0, -4, n)
+    sig = np.linalg.svd(A, compute_uv=False)
+    for lam in [1e-6, 1e-3, 1.0]:
+        B = np.vstack([A, math.sqrt(lam) * np.eye(n)])
+        UB = np.linalg.svd(B, full_matrices=False)[0]
+        assert abs(np.sum(UB[:m] ** 2) - oracle.statistical_dimension(sig, lam)) < 1e-10
+
+
+def test_sd_special_cases_and_integral():
+    sig = np.ones(8)
+    assert oracle.statistical_dimension(sig, 0.0) == 8.0          # lam = 0: the rank
+    assert abs(oracle.statistical_dimension(sig, 1.0) - 4.0) < 1e-15  # sigma^2 = lam: half
+    sigma = np.exp(-np.arange(1, 10001) / 200.0)
+    for lam in [1e-4, 1e-1]:
+        integral = 100.0 * math.log((1.0 + lam) / lam)
+        sd = oracle.statistical_dimension(sigma, lam)
+        assert abs(sd - integral) <= 1.0, (lam, sd, integral)
+    # the low-sd workload's sketch size: 2 * ceil(sd at lam=1e-4)
+    assert 2 * math.ceil(oracle.statistical_dimension(sigma, 1e-4)) == 1842
+
+
+# ----------------------------------------------------------------------------
+# preconditioners and their quality bounds
+
+def _kappa(M):
+    s = np.linalg.svd(M, compute_uv=False)
+    return s[0] / s[-1]
+
+
+def test_bp2_equivalence():
+    # R from QR of [XA; sqrt(lam) I] (BP2, Section 4.1) equals chol(C + lam I)
+    rng = np.random.default_rng(7)
+    Y = rng.standard_normal((80, 30)) * np.logspace(0, -5, 30)
+    for lam in [1e-8, 1e-2]:
+        R = oracle.chol_precond(Y, lam)
+        Rq = np.linalg.qr(np.vstack([Y, math.sqrt(lam) * np.eye(30)]), mode="r")
+        Rq = Rq * np.sign(np.diag(Rq))[:, None]
+        assert np.allclose(R, Rq, rtol=1e-9, atol=1e-12 * np.abs(R).max())
+        C = Y.T @ Y + lam * np.eye(30)
+        assert np.linalg.norm(R.T @ R - C) <= 1e-13 * np.linalg.norm(C)
+
+
+def test_lowrank_rinv_identity():
+    # with untruncated V (s < n), R^{-T}(Y^T Y + lam I)R^{-1} = I (eq. RinvOver)
+    rng = np.random.default_rng(11)
+    Y = rng.standard_normal((15, 60))
+    sig, V = oracle.lowrank_factors(Y)
+    for lam in [1e-4, 1e-1, 10.0]:
+        Ri = oracle.lowrank_rinv(V, sig, lam)
+        assert np.allclose(Ri, Ri.T)
+        G = Ri.T @ (Y.T @ Y + lam * np.eye(60)) @ Ri
+        # rounding grows with the spread (sigma_1^2 + lam) / lam of the factors
+        assert np.linalg.norm(G - np.eye(60)) < 1e-13 * (1 + sig[0] ** 2 / lam)
+        # eigenvalues (sigma^2 + lam)^(-1/2) on span V, lam^(-1/2) elsewhere
+        ev = np.sort(np.linalg.eigvalsh(Ri))
+        want = np.sort(np.concatenate([1 / np.sqrt(sig ** 2 + lam),
+                                       np.full(60 - 15, 1 / math.sqrt(lam))]))
+        assert np.allclose(ev, want, rtol=1e-10)
+
+
+def _lowsd_problem(m=600, n=80, decay=8.0, seed=2):
+    rng = np.random.default_rng(seed)
+    U = W.haar(rng, m, n)
+    V = W.haar(rng, n, n)
+    sig = np.exp(-np.arange(1, n + 1) / decay)
+    return (U * sig) @ V.T, U, sig, V
+
+
+def test_lemma21_bound():
+    A, UA, sig, V = _lowsd_problem(m=500, n=20, decay=4.0)
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((80, 500)) / math.sqrt(80)
+    for lam in [1e-10, 1e-4, 1e-1]:
+        R = oracle.chol_precond(X @ A, lam)
+        B = np.vstack([A, math.sqrt(lam) * np.eye(20)])
+        k = _kappa(B @ np.linalg.inv(R))
+        assert k <= oracle.lemma21_bound(X @ UA) * (1 + 1e-8)
+
+
+def test_thm32_bound_chol_and_lowrank():
+    A, UA, sig, V = _lowsd_problem()
+    m, n = A.shape
+    rng = np.random.default_rng(9)
+    for lam in [1e-3, 1e-2]:
+        sd = oracle.statistical_dimension(sig, lam)
+        s = min(m, int(16 * math.ceil(sd)))
+        X = rng.standard_normal((s, m)) / math.sqrt(s)
+        U1 = UA * (sig / np.sqrt(sig ** 2 + lam))[None, :]
+        eps = oracle.thm32_eps(U1, X)
+        assert eps < 1
+        bound = oracle.thm32_bound(eps)
+        B = np.vstack([A, math.sqrt(lam) * np.eye(n)])
+        Y = X @ A
+        kc = _kappa(B @ np.linalg.inv(oracle.chol_precond(Y, lam)))
+        sY, VY = oracle.lowrank_factors(Y)
+        kl = _kappa(B @ oracle.lowrank_rinv(VY, sY, lam))
+        assert kc <= bound * (1 + 1e-8) and kl <= bound * (1 + 1e-8), (kc, kl, bound)
+        assert abs(kc - kl) < 1e-6 * kc      # any R with R^T R = Y^T Y + lam I
+
+
+def test_iteration_bound():
+    assert oracle.lsqr_iteration_bound(1.0, 1e-10) == 1
+    assert oracle.lsqr_iteration_bound(3.0, 1e-10) == math.ceil(math.log(2e10) / math.log(2.0))
+    ks = [1.5, 2, 4, 8, 16]
+    its = [oracle.lsqr_iteration_bound(k, 1e-8) for k in ks]
+    assert its == sorted(its)
+
+
+def test_certify_bounds_error():
+    p = W.over_svd(m=400, n=30, N=4, sig_lo=1e-4)
+    X = oracle.solve(p.A, p.b, p.lams)
+    rng = np.random.default_rng(1)
+    for scale in [1e-6, 1e-9]:
+        Xp = X + scale * rng.standard_normal(X.shape) * np.linalg.norm(X, axis=0)
+        true = T.rel_err(Xp, X)
+        bound = oracle.certify(p.A, p.b, p.lams, Xp)
+        assert np.all(bound >= true * (1 - 1e-6)), (bound, true)
+    assert np.all(oracle.certify(p.A, p.b, p.lams, X) < 1e-9)
+
+
+# ----------------------------------------------------------------------------
+# planted mistakes: each slip must break a pin above
+
+def test_planted_dropped_sqrt(monkeypatch):
+    monkeypatch.setattr(T.math, "sqrt", lambda v: v)       # uses lam for sqrt(lam)
+    p = W.over_svd(m=300, n=40, N=4)
+    err = T.rel_err(T.solve_over(p.A, p.b, p.lams), closed_form(p.U, p.sigma, p.V, p.b, p.lams))
+    assert np.max(err) > 1e-3
+
+
+def test_planted_transposed_solve(monkeypatch):
+    real = T.solve_triangular
+    monkeypatch.setattr(T, "solve_triangular",
+                        lambda R, y, trans=0, lower=False: real(R, y, trans="N" if trans == "T" else "T",
+                                                                lower=lower))
+    A, b, U, sigma, V = small_under()
+    lams = [1e-3, 1e-1]
+    assert np.max(T.rel_err(T.solve_under(A, b, lams), closed_form(U, sigma, V, b, lams))) > 1e-3
+
+
+def test_planted_S_without_square():
+    rng = np.random.default_rng(11)
+    Y = rng.standard_normal((15, 60))
+    sig, V = oracle.lowrank_factors(Y)
+    lam = 1e-1
+    S_wrong = 1.0 - 1.0 / np.sqrt(1.0 + sig / lam)                    # sigma in place of sigma^2
+    Ri = (np.eye(60) - (V * S_wrong) @ V.T) / math.sqrt(lam)
+    G = Ri.T @ (Y.T @ Y + lam * np.eye(60)) @ Ri
+    assert np.linalg.norm(G - np.eye(60)) > 1e-2
+
+
+# ----------------------------------------------------------------------------
+# generators
+
+def test_generators_deterministic():
+    a = W.over_svd(m=200, n=20, N=3)
+    b = W.over_svd(m=200, n=20, N=3)
+    assert np.array_equal(a.A, b.A) and np.array_equal(a.b, b.b)
+    assert a.A.flags.f_contiguous
+    c = W.over_svd(m=200, n=20, N=3, seed=1)
+    assert not np.array_equal(a.A, c.A)
+    full = W.ragged(nprob=6, m_lo=50, m_hi=90, n_lo=5, n_hi=20)
+    part = W.ragged(nprob=6, m_lo=50, m_hi=90, n_lo=5, n_hi=20, first=3, count=2)
+    assert np.array_equal(full[3].A, part[0].A) and np.array_equal(full[4].b, part[1].b)
+    assert [(q.m, q.n) for q in full] == W.ragged_shapes(6, 50, 90, 5, 20)
