@@ -1,0 +1,227 @@
+/*
+ * tik.h -- C ABI of libtik, sketch-preconditioned Tikhonov least squares on
+ * AMD MI355X (gfx950).
+ *
+ * The library computes, for one or many problems and N regularization
+ * parameters lam_1..lam_N each,
+ *
+ *     x_lam = argmin_x ||A x - b||_2^2 + lam ||x||_2^2          (eq. regLLS)
+ *
+ * for tall (m >= n, eq. regLLSover) or wide (m < n, eq. regLLSunder) A, by the
+ * sketch-to-precondition method of Meier & Nakatsukasa: sketch A once
+ * (Algorithm 1 steps 1-2, Algorithm 2 steps 1-2, Algorithm 3 steps 1-3),
+ * build a preconditioner R_lam for every lam from that one sketch (Cholesky of
+ * the partly exact sketched Gram matrix, Algorithm 1 step 4 / Algorithm 2
+ * step 4; or the low-rank factor of eq. RinvOver, Algorithm 3 steps 4-7), and
+ * run preconditioned LSQR for every lam (Algorithm 1 steps 5-6, Algorithm 2
+ * step 5, Algorithm 3 steps 8-9).
+ *
+ * Conventions shared by every entry point:
+ *  - Matrices are column-major.  All pointers named "device" are HIP device
+ *    pointers owned by the caller; the library never allocates device memory.
+ *    Every call that needs scratch space takes a caller-provided device
+ *    workspace (dws, dws_bytes) whose required size the matching *_bytes
+ *    query returns.  A handle points into the workspace it was built in: the
+ *    workspace must stay allocated and untouched while the handle is used.
+ *  - Calls are stream-ordered on the given stream (a hipStream_t passed as
+ *    void*; NULL is the default stream).  Argument errors are detected on the
+ *    host before anything is launched; the call then returns TIK_EINVAL and
+ *    tik_last_error() describes the problem.
+ *  - Return values are tik_rc codes.  Per-(problem, lam) outcomes are
+ *    reported separately through tik_status arrays, so one failing lam does
+ *    not abort the others.
+ *  - The library is not re-entrant on one stream from several host threads;
+ *    distinct handles on distinct streams may be used concurrently.
+ */
+#ifndef TIK_H
+#define TIK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* call-level return codes */
+typedef enum {
+  TIK_OK = 0,
+  TIK_EINVAL = -1,      /* bad argument; nothing was launched */
+  TIK_EWORKSPACE = -2,  /* workspace pointer NULL, misaligned or too small */
+  TIK_EHIP = -3,        /* a HIP runtime call failed; see tik_last_error() */
+  TIK_ENOTSUP = -4      /* valid request outside what this build implements */
+} tik_rc;
+
+/* per-(problem, lam) outcome */
+typedef enum {
+  TIK_ST_CONVERGED = 0, /* the stopping test passed */
+  TIK_ST_MAXIT = 1,     /* maxit iterations (or refinement sweeps) without passing it */
+  TIK_ST_NOTPD = 2,     /* chol(C + lam I) broke down: the paper assumes
+                           kappa(C + lam I) < O(1/u) (Section 2.1); X is not written */
+  TIK_ST_IR_STALL = 3,  /* mixed precision: refinement stopped contracting */
+  TIK_ST_NONFINITE = 4  /* NaN/Inf met in the data or the recurrence; X not written */
+} tik_status;
+
+typedef enum { TIK_F64 = 0, TIK_F32 = 1, TIK_BF16 = 2 } tik_dtype;
+
+/* embedding X (Section 2.1.1): subsampled randomized Hadamard transform
+   X = sqrt(m'/s) S H D (H orthonormal Hadamard of order m' = 2^ceil(log2 m),
+   A zero-padded to m' rows), or Gaussian with i.i.d. N(0, 1/s) entries so that
+   E[X^T X] = I, the scaling the embedding definition of Section 1.3 fixes. */
+typedef enum { TIK_SRHT = 0, TIK_GAUSS = 1 } tik_embed;
+
+/* preconditioner: Cholesky of the partly exact sketch (Algorithms 1, 2) or the
+   low-rank factor R^{-1} = lam^{-1/2} (I - V S V^T) (eq. RinvOver, Algorithm 3) */
+typedef enum { TIK_ROUTE_CHOL = 0, TIK_ROUTE_LOWRANK = 1 } tik_route;
+
+/* how tik_lsqr_batch runs LSQR:
+   PLAIN_F64_PER_LAMBDA  one FP64 LSQR per (problem, lam), A read once per
+                         iteration per lam (the paper's loop over i);
+   F64_BATCHED           all lam of all problems advance together, one read of A
+                         per iteration shared by every lam (Section 2.1.1 notes
+                         the loop over lam parallelizes trivially);
+   MIXED_BATCHED         batched FP32 LSQR inside FP64 iterative refinement:
+                         residuals, preconditioner factors and the solution stay
+                         FP64 on the device. */
+typedef enum {
+  TIK_PLAIN_F64_PER_LAMBDA = 0,
+  TIK_F64_BATCHED = 1,
+  TIK_MIXED_BATCHED = 2
+} tik_mode;
+
+/* One problem.  A: device, column-major m x n with leading dimension
+   lda >= m, stored as FP64 (a_dtype = TIK_F64) or FP32 (TIK_F32; the FP32
+   values are the problem).  b: device, FP64, length m.  Both are read-only
+   and must outlive every handle built from them. */
+typedef struct {
+  int64_t m, n, lda;
+  int32_t a_dtype;
+  int32_t reserved;     /* must be 0 */
+  const void* A;
+  const double* b;
+} tik_problem;
+
+typedef void* tik_stream_t;
+typedef struct tik_sketch_s* tik_sketch_t;
+typedef struct tik_precond_s* tik_precond_t;
+
+/* ---------------------------------------------------------------- sketch -- */
+
+/* Workspace bytes tik_sketch needs for these problems (same arguments). */
+int tik_sketch_bytes(const tik_problem* p, int32_t nprob, int32_t embed,
+                     int32_t sketch_dtype, const int64_t* s, size_t* bytes);
+
+/* Sketch every problem once (Algorithm 1 steps 1-2 for m >= n: Y = X A,
+   s x n; Algorithm 2 steps 1-2 for m < n: Y = A X, m x s).
+   p[nprob]       host array of problem descriptors (copied into the handle;
+                  the device buffers they point to are not);
+   embed          TIK_SRHT (m >= n only) or TIK_GAUSS;
+   sketch_dtype   arithmetic of the sketch product: TIK_F64, or TIK_BF16 for
+                  the Gaussian embedding on matrix cores (A and X rounded to
+                  BF16, FP32 accumulation; the sketch only sets the
+                  preconditioner's quality);
+   s[nprob]       host, sketch size per problem, 1 <= s <= the long dimension;
+                  the SRHT also needs m' <= 2^19;
+   seed           fixes X completely, independently of launch shapes;
+   out            receives the handle (host struct; free with tik_sketch_free).
+   Returns TIK_EINVAL for bad shapes or mixed orientations (all problems must
+   be tall, or all wide), TIK_ENOTSUP for an SRHT of a wide matrix. */
+int tik_sketch(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sketch_dtype,
+               const int64_t* s, uint64_t seed, void* dws, size_t dws_bytes,
+               tik_stream_t stream, tik_sketch_t* out);
+
+/* Device pointer to problem k's sketch Y (FP64; s x n column-major with
+   ld = s for tall problems, Y^T stored s x m column-major for wide ones). */
+int tik_sketch_data(tik_sketch_t sk, int32_t k, const double** Y, int64_t* rows, int64_t* cols);
+
+/* -------------------------------------------------------- preconditioner -- */
+
+/* Workspace bytes tik_precond needs for N lambdas per problem. */
+int tik_precond_bytes(tik_sketch_t sk, int32_t route, int32_t N, size_t* bytes);
+
+/* Build R_lam for every problem and lambda from the one sketch.
+   TIK_ROUTE_CHOL (Algorithm 1 steps 3-4 / Algorithm 2 steps 3-4):
+     C = Y^T Y (or Y Y^T), R = chol(C + lam I), kept as the explicit upper
+     triangular inverse R^{-1} so that every later application is a
+     triangular matrix-vector product.
+   TIK_ROUTE_LOWRANK (Algorithm 3 steps 4-7, tall problems with s < n):
+     SVD Y = U Sigma V^T computed from the QR of Y^T (no Gram matrix), then
+     s_i = min(s, alpha * ceil(sd_hat(lam_i))) with sd_hat the estimate of
+     Section 3.1.2, and S_i as in Algorithm 3 step 7.
+   lambdas  host, nprob x N row-major (problem k's lambdas at k*N), each > 0;
+   alpha    oversampling factor of Algorithm 3 (ignored by TIK_ROUTE_CHOL);
+   sd_hat   host nprob x N, or NULL: the statistical-dimension estimates
+            (TIK_ROUTE_LOWRANK; NaN for TIK_ROUTE_CHOL);
+   status   host nprob x N, or NULL: TIK_ST_NOTPD where chol(C + lam I)
+            broke down, else TIK_ST_CONVERGED.
+   Synchronizes the stream once, to read the breakdown flags. */
+int tik_precond(tik_sketch_t sk, int32_t route, const double* lambdas, int32_t N,
+                double alpha, void* dws, size_t dws_bytes, tik_stream_t stream,
+                tik_precond_t* out, double* sd_hat, int32_t* status);
+
+/* Device pointer to the preconditioner of problem k, lambda i.
+   TIK_ROUTE_CHOL: R^{-1}, upper triangular dim x dim column-major (ld = dim),
+   strictly lower part stored as zeros; rank = dim.
+   TIK_ROUTE_LOWRANK: V, dim x rank column-major (ld = dim), the right singular
+   vectors of the sketch, of which the first s_i enter R_i^{-1}; *rank = s_i.
+   Valid while the preconditioner workspace is. */
+int tik_precond_data(tik_precond_t pc, int32_t k, int32_t i, const double** data,
+                     int64_t* dim, int64_t* rank);
+
+/* ------------------------------------------------------------- solve ---- */
+
+/* Workspace bytes tik_lsqr_batch needs in this mode. */
+int tik_lsqr_batch_bytes(const tik_problem* p, int32_t nprob, tik_precond_t pc,
+                         int32_t mode, size_t* bytes);
+
+/* Preconditioned LSQR (Paige & Saunders 1982) on [A; sqrt(lam) I] R^{-1}
+   (tall, eq. regLLSoverIter) or R^{-T} [A sqrt(lam) I] (wide, eq.
+   regLLSunderiter, started from zero so the minimum-norm solution results)
+   for every problem and lambda of pc.
+   p, nprob   the same problems the sketch was built from;
+   tol        relative tolerance of the LSQR stopping tests
+              ||M^T r|| <= tol ||M|| ||r|| or ||r|| <= tol ||b||, M the
+              preconditioned operator; in MIXED_BATCHED the refinement stops
+              when the FP64 correction is below tol relative to x;
+   maxit      iteration cap per lambda (per refinement sweep in MIXED_BATCHED);
+   X          host array of nprob device pointers; X[k] is n_k x N column-major
+              (ld = n_k), column i receives x_{lam_i}; written only where the
+              status is CONVERGED or MAXIT;
+   iters      device int32 nprob x N: LSQR iterations used (summed over sweeps);
+   status     device int32 nprob x N: tik_status values;
+   relres     device double nprob x N: the final ||M^T r|| / (||M|| ||r||)
+              estimate;
+   Synchronizes the stream once every few iterations to test whether every
+   lambda has stopped; otherwise stream-ordered. */
+int tik_lsqr_batch(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_t mode,
+                   double tol, int32_t maxit, double* const* X, int32_t* iters,
+                   int32_t* status, double* relres, void* dws, size_t dws_bytes,
+                   tik_stream_t stream);
+
+/* Free the host structs (device workspaces belong to the caller). */
+void tik_sketch_free(tik_sketch_t sk);
+void tik_precond_free(tik_precond_t pc);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* tik_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int tik_version(void);
+
+/* ----------------------------------------------------------- profiling -- */
+
+/* Per-kernel-family timing with HIP events recorded around every launch of
+   that family on its stream.  Off by default; enabling it adds two event
+   records per launch.  Names: "sketch", "gram", "chol", "trinv", "gemm_n",
+   "gemm_t", "trmv", "trmv_t", "lowrank", "vec", "residual". */
+int tik_prof_enable(int32_t on);
+int tik_prof_reset(void);
+/* Synchronizes outstanding events of that family; total_ms summed over
+   launches. */
+int tik_prof_query(const char* family, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TIK_H */

@@ -1,0 +1,958 @@
+// Preconditioned LSQR, batched over problems and lambdas (tall problems).
+//
+// Operator per (problem p, lambda i):  M = [A; sqrt(lam) I] R^{-1}
+// (eq. regLLSoverIter, Algorithm 1 step 5, Algorithm 3 step 8).  LSQR is the
+// Golub-Kahan bidiagonalisation of Paige & Saunders (1982): for i = 1, 2, ...
+//     beta_{i+1} u_{i+1}  = M v_i - alpha_i u_i
+//     alpha_{i+1} v_{i+1} = M^T u_{i+1} - beta_{i+1} v_i
+// followed by one Givens rotation.  The iterate lives in the preconditioned
+// variable y; since only x = R^{-1} y is wanted (Algorithm 1 step 6), the
+// search direction is carried already multiplied by R^{-1}: with
+// w_i = R^{-1} v_i and e_i = R^{-1} d_i,
+//     x_i = x_{i-1} + (phi_i / rho_i) e_i,   e_{i+1} = w_{i+1} - (theta_{i+1}/rho_i) e_i,
+// so x comes out in the original variables and no back-transform is needed.
+//
+// One iteration is eight stream-ordered kernels:
+//   gemm_n   u~_top = A w - (alpha/beta) u~_top         one pass over A, all lambdas
+//   vec_bot  u~_bot = sqrt(lam) w - (alpha/beta) u~_bot
+//   fin_beta beta_{i+1} = ||u~||                         fixed-order reductions
+//   gemm_t   partial A^T u~_top over row chunks         one pass over A, all lambdas
+//   reduce_t t = (A^T u~_top + sqrt(lam) u~_bot) / beta
+//   trmv_t   v~ = R^{-T} t - beta v                     explicit triangular inverse
+//   fin_alpha alpha_{i+1} = ||v~||, rotation, stopping tests, masks
+//   trmv     w = R^{-1} v~ / alpha, v = v~ / alpha, x and e updates
+// All lambdas of all problems share each launch; A is read twice per
+// iteration for every lambda together.  Vectors: "long" (m rows) and "short"
+// (n rows) buffers are row-major (rows x N, N lambdas per row); t is stored
+// lambda-major so the transposed triangular product reads it contiguously.
+#include "tik_internal.h"
+
+namespace tik {
+
+static constexpr int BLK = 256;
+
+template <typename T>
+__device__ __forceinline__ T warp_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the 256 threads of a block, fixed order.  `red` holds 4 values.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = warp_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+// -------------------------------------------------------------- init u -----
+// u~ = [rhs_top; rhs_bot] (rhs_top == null: b for every lambda; rhs_bot == null:
+// zero) and partial squared norms.  Items: gemm_n blocks (top) then vec_bot
+// blocks (bottom), one launch.  Top rows stored in TC.
+template <typename TC>
+__global__ void __launch_bounds__(BLK) k_init_u(const DevProb* __restrict__ P,
+                                                const Item* __restrict__ itN, int nItN, int rbN,
+                                                const Item* __restrict__ itB, int N,
+                                                const double* __restrict__ rhs_top,
+                                                const double* __restrict__ rhs_bot,
+                                                TC* __restrict__ ut, double* __restrict__ ub,
+                                                double* __restrict__ pnN, double* __restrict__ pnB) {
+  __shared__ double red[4];
+  const bool top = int(blockIdx.x) < nItN;
+  const Item it = top ? itN[blockIdx.x] : itB[blockIdx.x - nItN];
+  const DevProb& pr = P[it.p];
+  const int64_t rows = top ? pr.m : pr.n;
+  const int64_t rb = top ? rbN : BLK;
+  const int64_t r0 = int64_t(it.blk) * rb;
+  const int64_t r1 = min(rows, r0 + rb);
+  double* pn = top ? pnN + (pr.pnN + it.blk) * N : pnB + (pr.pnB + it.blk) * N;
+  for (int i = 0; i < N; ++i) {
+    double acc = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += BLK) {
+      double v;
+      if (top) {
+        v = rhs_top ? rhs_top[(pr.offL + r) * N + i] : pr.b[r];
+        const TC vc = TC(v);
+        ut[(pr.offL + r) * N + i] = vc;
+        v = double(vc);
+      } else {
+        v = rhs_bot ? rhs_bot[(pr.offS + r) * N + i] : 0.0;
+        ub[(pr.offS + r) * N + i] = v;
+      }
+      acc += v * v;
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) pn[i] = s;
+  }
+}
+
+// ------------------------------------------------------------- fin_beta ----
+// beta_{i+1} = sqrt(sum of partials).  One block per (problem, lambda).
+__global__ void __launch_bounds__(BLK) k_fin_beta(const DevProb* __restrict__ P, int N,
+                                                  const double* __restrict__ pnN,
+                                                  const double* __restrict__ pnB,
+                                                  Scal* __restrict__ sc, int init) {
+  __shared__ double red[4];
+  const int j = blockIdx.x, p = j / N, i = j % N;
+  const DevProb& pr = P[p];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < pr.nblkN; b += BLK) v += pnN[(pr.pnN + b) * N + i];
+  for (int b = threadIdx.x; b < pr.nblkB; b += BLK) v += pnB[(pr.pnB + b) * N + i];
+  const double s = block_sum(v, red);
+  if (threadIdx.x != 0) return;
+  Scal& S = sc[j];
+  const double beta = sqrt(s);
+  S.beta_new = beta;
+  S.ibeta = (beta > 0.0 && isfinite(beta)) ? 1.0 / beta : 0.0;
+  if (init) {
+    S.beta = beta;
+    S.bnorm = beta;
+    S.phibar = beta;
+    if (!isfinite(beta)) {
+      S.status = TIK_ST_NONFINITE;
+      S.active = 0;
+    } else if (beta == 0.0) {
+      S.status = TIK_ST_CONVERGED;   // b = 0: x = 0
+      S.active = 0;
+    }
+  }
+}
+
+// --------------------------------------------------------------- gemm_n ----
+// u~_top[r, :] = A[r, :] W - ucoef u~_top[r, :] over a block of RB rows;
+// EPI = 1 stores the plain product A W into `out` (FP64) instead.
+// 256 threads = RB rows x KS column slices; W staged through LDS 64 rows at a
+// time (converted to TC); A read column by column, 64..256 consecutive rows
+// per wave.
+template <typename TA, typename TC, int NC, int RB, int KS, int EPI>
+__global__ void __launch_bounds__(BLK) k_gemm_n(const DevProb* __restrict__ P,
+                                                const Item* __restrict__ items, int N,
+                                                const double* __restrict__ W,
+                                                TC* __restrict__ ut, double* __restrict__ out,
+                                                const Scal* __restrict__ sc,
+                                                double* __restrict__ pnN) {
+  static_assert(RB * KS == BLK, "block shape");
+  constexpr int KC = 64;
+  __shared__ TC Ws[KC][NC];
+  __shared__ TC red[KS > 1 ? KS : 1][RB][NC > 4 ? 1 : NC];
+  __shared__ double nred[4];
+  const Item it = items[blockIdx.x];
+  const DevProb& pr = P[it.p];
+  const TA* __restrict__ A = static_cast<const TA*>(pr.A);
+  const int64_t m = pr.m, n = pr.n, lda = pr.lda;
+  const int tr = threadIdx.x % RB, ks = threadIdx.x / RB;
+  const int64_t r = int64_t(it.blk) * RB + tr;
+  const bool live = r < m;
+  TC acc[NC];
+#pragma unroll
+  for (int i = 0; i < NC; ++i) acc[i] = TC(0);
+  for (int64_t k0 = 0; k0 < n; k0 += KC) {
+    const int kc = int(min<int64_t>(KC, n - k0));
+    for (int e = threadIdx.x; e < KC * NC; e += BLK) {
+      const int kk = e / NC, i = e % NC;
+      Ws[kk][i] = (kk < kc && i < N) ? TC(W[(pr.offS + k0 + kk) * N + i]) : TC(0);
+    }
+    __syncthreads();
+    if (live) {
+      const TA* col = A + r + k0 * lda;
+      int kk = ks;
+      for (; kk + 3 * KS < kc; kk += 4 * KS) {
+        const TC a0 = TC(col[int64_t(kk) * lda]);
+        const TC a1 = TC(col[int64_t(kk + KS) * lda]);
+        const TC a2 = TC(col[int64_t(kk + 2 * KS) * lda]);
+        const TC a3 = TC(col[int64_t(kk + 3 * KS) * lda]);
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+          acc[i] = fma(a0, Ws[kk][i], acc[i]);
+          acc[i] = fma(a1, Ws[kk + KS][i], acc[i]);
+          acc[i] = fma(a2, Ws[kk + 2 * KS][i], acc[i]);
+          acc[i] = fma(a3, Ws[kk + 3 * KS][i], acc[i]);
+        }
+      }
+      for (; kk < kc; kk += KS) {
+        const TC a0 = TC(col[int64_t(kk) * lda]);
+#pragma unroll
+        for (int i = 0; i < NC; ++i) acc[i] = fma(a0, Ws[kk][i], acc[i]);
+      }
+    }
+    __syncthreads();
+  }
+  if (KS > 1) {
+    // combine the KS column slices (only used with NC <= 4)
+#pragma unroll
+    for (int i = 0; i < (NC > 4 ? 1 : NC); ++i) red[ks][tr][i] = acc[i];
+    __syncthreads();
+    if (ks == 0) {
+#pragma unroll
+      for (int i = 0; i < (NC > 4 ? 1 : NC); ++i) {
+        TC s = red[0][tr][i];
+        for (int q = 1; q < KS; ++q) s += red[q][tr][i];
+        acc[i] = s;
+      }
+    }
+  }
+  const bool writer = live && ks == 0;
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    if (i < N) {   // uniform over the block
+      double v = 0.0;
+      if (writer) {
+        if (EPI == 0) {
+          const int64_t idx = (pr.offL + r) * N + i;
+          const TC nv = TC(acc[i] - TC(sc[it.p * N + i].ucoef) * ut[idx]);
+          ut[idx] = nv;
+          v = double(nv) * double(nv);
+        } else {
+          out[(pr.offL + r) * N + i] = double(acc[i]);
+        }
+      }
+      if (EPI == 0) {
+        const double s = block_sum(v, nred);
+        if (threadIdx.x == 0) pnN[(pr.pnN + it.blk) * N + i] = s;
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------- vec_bot ----
+__global__ void __launch_bounds__(BLK) k_vec_bot(const DevProb* __restrict__ P,
+                                                 const Item* __restrict__ items, int N,
+                                                 const double* __restrict__ w,
+                                                 double* __restrict__ ub,
+                                                 const Scal* __restrict__ sc,
+                                                 double* __restrict__ pnB) {
+  __shared__ double red[4];
+  const Item it = items[blockIdx.x];
+  const DevProb& pr = P[it.p];
+  const int64_t r = int64_t(it.blk) * BLK + threadIdx.x;
+  for (int i = 0; i < N; ++i) {
+    const Scal& S = sc[it.p * N + i];
+    double v = 0.0;
+    if (r < pr.n) {
+      const int64_t idx = (pr.offS + r) * N + i;
+      const double nv = S.sqlam * w[idx] - S.ucoef * ub[idx];
+      ub[idx] = nv;
+      v = nv * nv;
+    }
+    const double s = block_sum(v, red);
+    if (threadIdx.x == 0) pnB[(pr.pnB + it.blk) * N + i] = s;
+  }
+}
+
+// --------------------------------------------------------------- gemm_t ----
+// part[chunk][c][:] = sum over the chunk's rows of A[r, c] U[r, :], for a
+// 64-column block.  A and U staged through LDS 32 rows at a time.
+//   NC >= 4: thread (column, lambda group of NC/4);
+//   NC <  4: thread (column, row slice of 4), slices summed at the end.
+template <typename TA, typename TC, typename TU, int NC>
+__global__ void __launch_bounds__(BLK) k_gemm_t(const DevProb* __restrict__ P,
+                                                const Item* __restrict__ items, int N,
+                                                const TU* __restrict__ U, int64_t uoffL_stride,
+                                                TC* __restrict__ part) {
+  constexpr int RS = 32;
+  constexpr int G = NC >= 4 ? NC / 4 : NC;   // accumulators per thread
+  __shared__ TC As[RS][64 + 1];
+  __shared__ TC Us[RS][NC];
+  __shared__ TC red[4][64][NC < 4 ? NC : 1];
+  const Item it = items[blockIdx.x];
+  const DevProb& pr = P[it.p];
+  const TA* __restrict__ A = static_cast<const TA*>(pr.A);
+  const int64_t m = pr.m, n = pr.n, lda = pr.lda;
+  const int64_t c0 = int64_t(it.blk) * 64;
+  const int64_t rbeg = int64_t(it.ch) * pr.rchunk;
+  const int64_t rend = min(m, rbeg + pr.rchunk);
+  const int cl = threadIdx.x & 63, g = threadIdx.x >> 6;
+  TC acc[G];
+#pragma unroll
+  for (int q = 0; q < G; ++q) acc[q] = TC(0);
+  for (int64_t r0 = rbeg; r0 < rend; r0 += RS) {
+    for (int e = threadIdx.x; e < RS * 64; e += BLK) {
+      const int rr = e & (RS - 1), cc = e / RS;
+      const int64_t rg = r0 + rr, cg = c0 + cc;
+      As[rr][cc] = (rg < rend && cg < n) ? TC(A[rg + cg * lda]) : TC(0);
+    }
+    for (int e = threadIdx.x; e < RS * NC; e += BLK) {
+      const int rr = e / NC, i = e % NC;
+      const int64_t rg = r0 + rr;
+      Us[rr][i] = (rg < rend && i < N) ? TC(U[(pr.offL + rg) * uoffL_stride + i]) : TC(0);
+    }
+    __syncthreads();
+    if (NC >= 4) {
+#pragma unroll 8
+      for (int rr = 0; rr < RS; ++rr) {
+        const TC a = As[rr][cl];
+#pragma unroll
+        for (int q = 0; q < G; ++q) acc[q] = fma(a, Us[rr][g * G + q], acc[q]);
+      }
+    } else {
+#pragma unroll
+      for (int rr = g; rr < RS; rr += 4) {
+        const TC a = As[rr][cl];
+#pragma unroll
+        for (int q = 0; q < G; ++q) acc[q] = fma(a, Us[rr][q], acc[q]);
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t c = c0 + cl;
+  TC* dst = part + (pr.ptOff + int64_t(it.ch) * n) * N;
+  if (NC >= 4) {
+    if (c < n) {
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const int i = g * G + q;
+        if (i < N) dst[c * N + i] = acc[q];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < G; ++q) red[g][cl][q] = acc[q];
+    __syncthreads();
+    if (g == 0 && c < n) {
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        if (q < N) dst[c * N + q] = red[0][cl][q] + red[1][cl][q] + red[2][cl][q] + red[3][cl][q];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- reduce_t ----
+// EPI 0: t[i][c] = (sum_ch part + sqrt(lam) u~_bot[c, i]) / beta, lambda-major.
+// EPI 1: out[c, i] = sum_ch part - lam x[c, i] (row-major; FP64 gradient).
+template <typename TC, int EPI>
+__global__ void __launch_bounds__(BLK) k_reduce_t(const DevProb* __restrict__ P,
+                                                  const Item* __restrict__ items, int N,
+                                                  const TC* __restrict__ part,
+                                                  const double* __restrict__ ub,
+                                                  const Scal* __restrict__ sc,
+                                                  double* __restrict__ t) {
+  const Item it = items[blockIdx.x];
+  const DevProb& pr = P[it.p];
+  const int64_t n = pr.n;
+  for (int e = threadIdx.x; e < BLK * N; e += BLK) {
+    const int64_t c = int64_t(it.blk) * BLK + e / N;
+    const int i = e % N;
+    if (c >= n) continue;
+    double s = 0.0;
+    const TC* src = part + (pr.ptOff * N) + c * N + i;
+    for (int ch = 0; ch < pr.nchT; ++ch) s += double(src[int64_t(ch) * n * N]);
+    const Scal& S = sc[it.p * N + i];
+    if (EPI == 0) {
+      t[pr.offS * N + int64_t(i) * n + c] = (s + S.sqlam * ub[(pr.offS + c) * N + i]) * S.ibeta;
+    } else {
+      t[(pr.offS + c) * N + i] = s - S.lam * ub[(pr.offS + c) * N + i];
+    }
+  }
+}
+
+// --------------------------------------------------------------- trmv_t ----
+// v~[c] = sum_{r <= c} Rinv[r, c] t[r] - beta v[c] for a 64-column block of one
+// (problem, lambda); each wave owns 16 columns, lanes stride the rows.
+__global__ void __launch_bounds__(BLK) k_trmv_t(const DevProb* __restrict__ P,
+                                                const Item* __restrict__ items, int N,
+                                                const double* __restrict__ t,
+                                                const double* __restrict__ v,
+                                                double* __restrict__ q,
+                                                const Scal* __restrict__ sc,
+                                                double* __restrict__ pnQ) {
+  __shared__ double red[4];
+  const Item it = items[blockIdx.x];
+  const int j = it.j, p = it.p, i = j % N;
+  const DevProb& pr = P[p];
+  const int64_t k = pr.k;
+  const double* __restrict__ R = pr.Rinv + int64_t(i) * k * k;
+  const double* __restrict__ tv = t + pr.offS * N + int64_t(i) * k;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t cbase = int64_t(it.blk) * 64 + wv * 16;
+  double acc[16];
+#pragma unroll
+  for (int q2 = 0; q2 < 16; ++q2) acc[q2] = 0.0;
+  const int64_t clast = min(k - 1, cbase + 15);
+  for (int64_t r = lane; r <= clast; r += 64) {
+    const double tr = tv[r];
+#pragma unroll
+    for (int q2 = 0; q2 < 16; ++q2) {
+      const int64_t c = cbase + q2;
+      if (c < k && r <= c) acc[q2] = fma(R[r + c * k], tr, acc[q2]);
+    }
+  }
+  const Scal& S = sc[j];
+  double nrm = 0.0;
+#pragma unroll
+  for (int q2 = 0; q2 < 16; ++q2) {
+    const double s = warp_sum(acc[q2]);
+    const int64_t c = cbase + q2;
+    if (c < k) {
+      const int64_t idx = (pr.offS + c) * N + i;
+      const double nv = s - S.beta_new * v[idx];
+      if (lane == 0) q[idx] = nv;
+      nrm += nv * nv;
+    }
+  }
+  if (lane != 0) nrm = 0.0;
+  const double tot = block_sum(nrm, red);
+  if (threadIdx.x == 0) pnQ[(pr.pnQ + it.blk) * N + i] = tot;
+}
+
+// ------------------------------------------------------------ fin_alpha ----
+__global__ void __launch_bounds__(BLK) k_fin_alpha(const DevProb* __restrict__ P, int N,
+                                                   const double* __restrict__ pnQ,
+                                                   Scal* __restrict__ sc, int init, double tol,
+                                                   int maxit) {
+  __shared__ double red[4];
+  const int j = blockIdx.x, p = j / N, i = j % N;
+  const DevProb& pr = P[p];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < pr.nblkQ; b += BLK) v += pnQ[(pr.pnQ + b) * N + i];
+  const double s = block_sum(v, red);
+  if (threadIdx.x != 0) return;
+  Scal& S = sc[j];
+  const double alpha = sqrt(s);
+  if (init) {
+    S.alpha = alpha;
+    S.rhobar = alpha;
+    S.anorm2 = 0.0;
+    S.iters = 0;
+    S.upd = 0;
+    S.cx = 0.0;
+    S.ce = 0.0;
+    if (!S.active) {
+      S.ialpha = 0.0;
+      S.ucoef = 0.0;
+      return;
+    }
+    if (!isfinite(alpha)) {
+      S.status = TIK_ST_NONFINITE;
+      S.active = 0;
+      S.ialpha = 0.0;
+      S.ucoef = 0.0;
+      return;
+    }
+    if (alpha == 0.0) {   // A^T b = 0: x = 0 is the solution
+      S.status = TIK_ST_CONVERGED;
+      S.active = 0;
+      S.ialpha = 0.0;
+      S.ucoef = 0.0;
+      S.relres = 0.0;
+      return;
+    }
+    S.ialpha = 1.0 / alpha;
+    S.ucoef = alpha * S.ibeta;
+    S.beta = S.beta_new;
+    return;
+  }
+  if (!S.active) {
+    S.upd = 0;
+    S.ialpha = 0.0;
+    S.ucoef = 0.0;
+    return;
+  }
+  const double beta = S.beta_new;
+  S.anorm2 += S.alpha * S.alpha + beta * beta;
+  const double rho = hypot(S.rhobar, beta);
+  const double cs = S.rhobar / rho, sn = beta / rho;
+  const double theta = sn * alpha;
+  const double rhobar = -cs * alpha;
+  const double phi = cs * S.phibar;
+  const double phibar = sn * S.phibar;
+  const double tau = sn * phi;
+  S.cx = phi / rho;
+  S.ce = theta / rho;
+  S.upd = 1;
+  S.iters += 1;
+  const double rnorm = phibar;
+  const double arnorm = alpha * fabs(tau);
+  const double anorm = sqrt(S.anorm2);
+  const double test1 = rnorm / S.bnorm;
+  const double test2 = (rnorm > 0.0) ? arnorm / (anorm * rnorm) : 0.0;
+  S.rnorm = rnorm;
+  S.arnorm = arnorm;
+  S.relres = test2;
+  if (!(isfinite(alpha) && isfinite(beta) && isfinite(rho) && rho > 0.0)) {
+    S.status = TIK_ST_NONFINITE;
+    S.active = 0;
+    S.upd = 0;
+    S.ialpha = 0.0;
+    S.ucoef = 0.0;
+    return;
+  }
+  if (test1 <= tol || test2 <= tol || alpha == 0.0) {
+    S.status = TIK_ST_CONVERGED;
+    S.active = 0;
+  } else if (S.iters >= maxit) {
+    S.status = TIK_ST_MAXIT;
+    S.active = 0;
+  }
+  S.alpha = alpha;
+  S.beta = beta;
+  S.rhobar = rhobar;
+  S.phibar = phibar;
+  S.ialpha = alpha > 0.0 ? 1.0 / alpha : 0.0;
+  S.ucoef = alpha * S.ibeta;
+}
+
+// ----------------------------------------------------------------- trmv ----
+// w[r] = ialpha sum_{c >= r} Rinv[r, c] v~[c]; v = ialpha v~; x, e updates.
+// 256 threads = 64 rows x 4 column slices.
+__global__ void __launch_bounds__(BLK) k_trmv(const DevProb* __restrict__ P,
+                                              const Item* __restrict__ items, int N,
+                                              const double* __restrict__ q,
+                                              double* __restrict__ v, double* __restrict__ w,
+                                              double* __restrict__ x, double* __restrict__ e,
+                                              const Scal* __restrict__ sc, int init) {
+  __shared__ double red[4][64];
+  const Item it = items[blockIdx.x];
+  const int j = it.j, p = it.p, i = j % N;
+  const DevProb& pr = P[p];
+  const int64_t k = pr.k;
+  const double* __restrict__ R = pr.Rinv + int64_t(i) * k * k;
+  const int tr = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int64_t r0 = int64_t(it.blk) * 64;
+  const int64_t r = r0 + tr;
+  const double* __restrict__ qv = q + pr.offS * N + i;   // q[(offS + c) * N + i] = qv[c * N]
+  double acc = 0.0;
+  if (r < k) {
+    int64_t c = r0 + sl;
+    for (; c + 12 < k; c += 16) {
+      const double r_0 = R[r + c * k], r_1 = R[r + (c + 4) * k];
+      const double r_2 = R[r + (c + 8) * k], r_3 = R[r + (c + 12) * k];
+      acc = fma(r_0, qv[c * N], acc);
+      acc = fma(r_1, qv[(c + 4) * N], acc);
+      acc = fma(r_2, qv[(c + 8) * N], acc);
+      acc = fma(r_3, qv[(c + 12) * N], acc);
+    }
+    for (; c < k; c += 4) acc = fma(R[r + c * k], qv[c * N], acc);
+  }
+  red[sl][tr] = acc;
+  __syncthreads();
+  if (sl != 0 || r >= k) return;
+  const Scal& S = sc[j];
+  const double wr = (red[0][tr] + red[1][tr] + red[2][tr] + red[3][tr]) * S.ialpha;
+  const int64_t idx = (pr.offS + r) * N + i;
+  v[idx] = q[idx] * S.ialpha;
+  w[idx] = wr;
+  if (init) {
+    x[idx] = 0.0;
+    e[idx] = wr;
+  } else if (S.upd) {
+    const double eo = e[idx];
+    x[idx] += S.cx * eo;
+    e[idx] = wr - S.ce * eo;
+  }
+}
+
+// --------------------------------------------------------- bookkeeping -----
+__global__ void k_scal_init(Scal* sc, int J, int N, const double* __restrict__ lams,
+                            const int32_t* __restrict__ pre_status) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= J) return;
+  Scal S = {};
+  S.lam = lams[j];
+  S.sqlam = sqrt(S.lam);
+  S.active = 1;
+  S.status = TIK_ST_MAXIT;
+  if (pre_status && pre_status[j] != TIK_ST_CONVERGED) {
+    S.active = 0;
+    S.status = pre_status[j];
+  }
+  sc[j] = S;
+}
+
+__global__ void k_count_active(const Scal* __restrict__ sc, int J, int32_t* out) {
+  __shared__ int red[4];
+  int c = 0;
+  for (int j = threadIdx.x; j < J; j += BLK) c += sc[j].active;
+  c = warp_sum(c);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
+}
+
+// ============================================================ host driver ===
+
+namespace {
+
+// One set of (problem, lambda-range) solved together.
+struct Plan {
+  int N = 0, NC = 1, rbN = 64;
+  std::vector<int> pidx;      // global problem index per local problem
+  std::vector<int> i0;        // first lambda index per local problem
+  std::vector<DevProb> P;
+  std::vector<Item> itN, itB, itT, itQ;
+  int64_t totL = 0, totS = 0, totPT = 0, nbN = 0, nbB = 0, nbQ = 0;
+  int J = 0;
+};
+
+struct Bufs {
+  DevProb* P;
+  Item *itN, *itB, *itT, *itQ;
+  Scal* sc;
+  void* ut;
+  double *ub, *v, *q, *w, *e, *x, *t;
+  void* part;
+  double *pnN, *pnB, *pnQ;
+  int32_t* cnt;
+  double** Xp;
+  double* lams;
+  int32_t* pre;
+  int32_t* jmap;
+};
+
+int pick_nc(int N) {
+  int nc = 1;
+  while (nc < N) nc <<= 1;
+  return nc;
+}
+
+void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vector<int>& pidx,
+               const std::vector<int>& i0, int N, Plan& pl) {
+  pl.N = N;
+  pl.NC = pick_nc(N);
+  pl.rbN = pl.NC >= 8 ? 256 : 64;
+  pl.pidx = pidx;
+  pl.i0 = i0;
+  pl.P.clear();
+  pl.itN.clear(); pl.itB.clear(); pl.itT.clear(); pl.itQ.clear();
+  pl.totL = pl.totS = pl.totPT = pl.nbN = pl.nbB = pl.nbQ = 0;
+  const int np = int(pidx.size());
+  int64_t colblocks = 0;
+  for (int lp = 0; lp < np; ++lp) colblocks += cdiv(probs[pidx[lp]].n, 64);
+  for (int lp = 0; lp < np; ++lp) {
+    const tik_problem& g = probs[pidx[lp]];
+    DevProb d = {};
+    d.A = g.A;
+    d.m = g.m;
+    d.n = g.n;
+    d.lda = g.lda;
+    d.a_f32 = g.a_dtype == TIK_F32;
+    d.wide = 0;
+    d.b = g.b;
+    d.offL = pl.totL;
+    d.offS = pl.totS;
+    d.k = g.n;
+    if (pc->route == TIK_ROUTE_CHOL)
+      d.Rinv = pc->Rinv[pidx[lp]] + int64_t(i0[lp]) * d.k * d.k;
+    d.nblkN = int32_t(cdiv(g.m, pl.rbN));
+    d.nblkB = int32_t(cdiv(g.n, BLK));
+    d.nblkQ = int32_t(cdiv(g.n, 64));
+    d.pnN = pl.nbN;
+    d.pnB = pl.nbB;
+    d.pnQ = pl.nbQ;
+    // row chunks for gemm_t: aim for about 2048 blocks over the whole batch
+    const int64_t cb = cdiv(g.n, 64);
+    int64_t nch = std::max<int64_t>(1, 2048 / std::max<int64_t>(1, colblocks));
+    nch = std::min<int64_t>(nch, cdiv(g.m, 32));
+    int64_t rch = cdiv(cdiv(g.m, nch), 32) * 32;
+    nch = cdiv(g.m, rch);
+    d.rchunk = rch;
+    d.nchT = int32_t(nch);
+    d.ptOff = pl.totPT;
+    for (int b = 0; b < d.nblkN; ++b) pl.itN.push_back({lp, b, 0, 0});
+    for (int b = 0; b < d.nblkB; ++b) pl.itB.push_back({lp, b, 0, 0});
+    for (int64_t ch = 0; ch < nch; ++ch)
+      for (int64_t c = 0; c < cb; ++c) pl.itT.push_back({lp, int32_t(c), int32_t(ch), 0});
+    for (int i = 0; i < N; ++i)
+      for (int b = 0; b < d.nblkQ; ++b) pl.itQ.push_back({lp, b, 0, lp * N + i});
+    pl.totL += g.m;
+    pl.totS += g.n;
+    pl.totPT += nch * g.n;
+    pl.nbN += d.nblkN;
+    pl.nbB += d.nblkB;
+    pl.nbQ += d.nblkQ;
+    pl.P.push_back(d);
+  }
+  pl.J = np * N;
+}
+
+void take_bufs(Arena& a, const Plan& pl, size_t tc, Bufs& b) {
+  const int N = pl.N;
+  b.P = a.take<DevProb>(pl.P.size());
+  b.itN = a.take<Item>(pl.itN.size());
+  b.itB = a.take<Item>(pl.itB.size());
+  b.itT = a.take<Item>(pl.itT.size());
+  b.itQ = a.take<Item>(pl.itQ.size());
+  b.sc = a.take<Scal>(pl.J);
+  b.ut = a.take<char>(size_t(pl.totL) * N * tc);
+  b.ub = a.take<double>(size_t(pl.totS) * N);
+  b.v = a.take<double>(size_t(pl.totS) * N);
+  b.q = a.take<double>(size_t(pl.totS) * N);
+  b.w = a.take<double>(size_t(pl.totS) * N);
+  b.e = a.take<double>(size_t(pl.totS) * N);
+  b.x = a.take<double>(size_t(pl.totS) * N);
+  b.t = a.take<double>(size_t(pl.totS) * N);
+  b.part = a.take<char>(size_t(pl.totPT) * N * tc);
+  b.pnN = a.take<double>(size_t(pl.nbN) * N);
+  b.pnB = a.take<double>(size_t(pl.nbB) * N);
+  b.pnQ = a.take<double>(size_t(pl.nbQ) * N);
+  b.cnt = a.take<int32_t>(1);
+  b.Xp = a.take<double*>(pl.P.size());
+  b.lams = a.take<double>(pl.J);
+  b.pre = a.take<int32_t>(pl.J);
+  b.jmap = a.take<int32_t>(pl.J);
+}
+
+template <typename TA, typename TC, int NC>
+struct Kern {
+  static int gemm_n(const Plan& pl, const Bufs& b, hipStream_t st) {
+    ProfScope ps("gemm_n", st);
+    if (NC >= 8)
+      hipLaunchKernelGGL((k_gemm_n<TA, TC, NC, 256, 1, 0>), dim3(unsigned(pl.itN.size())), dim3(BLK),
+                         0, st, b.P, b.itN, pl.N, b.w, static_cast<TC*>(b.ut), nullptr, b.sc, b.pnN);
+    else
+      hipLaunchKernelGGL((k_gemm_n<TA, TC, NC, 64, 4, 0>), dim3(unsigned(pl.itN.size())), dim3(BLK),
+                         0, st, b.P, b.itN, pl.N, b.w, static_cast<TC*>(b.ut), nullptr, b.sc, b.pnN);
+    TIK_LAUNCHED("k_gemm_n");
+    return TIK_OK;
+  }
+  static int gemm_t(const Plan& pl, const Bufs& b, hipStream_t st) {
+    ProfScope ps("gemm_t", st);
+    hipLaunchKernelGGL((k_gemm_t<TA, TC, TC, NC>), dim3(unsigned(pl.itT.size())), dim3(BLK), 0, st,
+                       b.P, b.itT, pl.N, static_cast<const TC*>(b.ut), int64_t(pl.N),
+                       static_cast<TC*>(b.part));
+    TIK_LAUNCHED("k_gemm_t");
+    return TIK_OK;
+  }
+};
+
+template <typename TC>
+int vec_steps_u(const Plan& pl, const Bufs& b, hipStream_t st, bool init, const double* rhs_top,
+                const double* rhs_bot) {
+  ProfScope ps("vec", st);
+  if (init) {
+    hipLaunchKernelGGL(k_init_u<TC>, dim3(unsigned(pl.itN.size() + pl.itB.size())), dim3(BLK), 0,
+                       st, b.P, b.itN, int(pl.itN.size()), pl.rbN, b.itB, pl.N, rhs_top, rhs_bot,
+                       static_cast<TC*>(b.ut), b.ub, b.pnN, b.pnB);
+    TIK_LAUNCHED("k_init_u");
+  } else {
+    hipLaunchKernelGGL(k_vec_bot, dim3(unsigned(pl.itB.size())), dim3(BLK), 0, st, b.P, b.itB, pl.N,
+                       b.w, b.ub, b.sc, b.pnB);
+    TIK_LAUNCHED("k_vec_bot");
+  }
+  hipLaunchKernelGGL(k_fin_beta, dim3(unsigned(pl.J)), dim3(BLK), 0, st, b.P, pl.N, b.pnN, b.pnB,
+                     b.sc, init ? 1 : 0);
+  TIK_LAUNCHED("k_fin_beta");
+  return TIK_OK;
+}
+
+template <typename TC>
+int vec_steps_v(const Plan& pl, const Bufs& b, hipStream_t st, bool init, double tol, int maxit) {
+  {
+    ProfScope ps("vec", st);
+    hipLaunchKernelGGL((k_reduce_t<TC, 0>), dim3(unsigned(pl.itB.size())), dim3(BLK), 0, st, b.P,
+                       b.itB, pl.N, static_cast<const TC*>(b.part), b.ub, b.sc, b.t);
+    TIK_LAUNCHED("k_reduce_t");
+  }
+  {
+    ProfScope ps("trmv_t", st);
+    hipLaunchKernelGGL(k_trmv_t, dim3(unsigned(pl.itQ.size())), dim3(BLK), 0, st, b.P, b.itQ, pl.N,
+                       b.t, b.v, b.q, b.sc, b.pnQ);
+    TIK_LAUNCHED("k_trmv_t");
+  }
+  {
+    ProfScope ps("vec", st);
+    hipLaunchKernelGGL(k_fin_alpha, dim3(unsigned(pl.J)), dim3(BLK), 0, st, b.P, pl.N, b.pnQ, b.sc,
+                       init ? 1 : 0, tol, maxit);
+    TIK_LAUNCHED("k_fin_alpha");
+  }
+  {
+    ProfScope ps("trmv", st);
+    hipLaunchKernelGGL(k_trmv, dim3(unsigned(pl.itQ.size())), dim3(BLK), 0, st, b.P, b.itQ, pl.N,
+                       b.q, b.v, b.w, b.x, b.e, b.sc, init ? 1 : 0);
+    TIK_LAUNCHED("k_trmv");
+  }
+  return TIK_OK;
+}
+
+int upload(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return TIK_OK;
+  TIK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+  return TIK_OK;
+}
+
+// Run LSQR to completion for one plan; x is left in b.x.
+template <typename TA, typename TC, int NC>
+int run_core(const Plan& pl, const Bufs& b, double tol, int maxit, hipStream_t st,
+             const double* rhs_top, const double* rhs_bot) {
+  using K = Kern<TA, TC, NC>;
+  hipLaunchKernelGGL(k_scal_init, dim3(unsigned(cdiv(pl.J, 256))), dim3(256), 0, st, b.sc, pl.J,
+                     pl.N, b.lams, b.pre);
+  TIK_LAUNCHED("k_scal_init");
+  TIK_HIP(hipMemsetAsync(b.v, 0, size_t(pl.totS) * pl.N * sizeof(double), st));
+  TIK_TRY(vec_steps_u<TC>(pl, b, st, true, rhs_top, rhs_bot));
+  TIK_TRY(K::gemm_t(pl, b, st));
+  TIK_TRY(vec_steps_v<TC>(pl, b, st, true, tol, maxit));
+  const int chunk = 8;
+  int32_t active = 1;
+  for (int it = 0; it < maxit && active > 0;) {
+    const int todo = std::min(chunk, maxit - it);
+    for (int q = 0; q < todo; ++q) {
+      TIK_TRY(K::gemm_n(pl, b, st));
+      TIK_TRY(vec_steps_u<TC>(pl, b, st, false, nullptr, nullptr));
+      TIK_TRY(K::gemm_t(pl, b, st));
+      TIK_TRY(vec_steps_v<TC>(pl, b, st, false, tol, maxit));
+    }
+    it += todo;
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(BLK), 0, st, b.sc, pl.J, b.cnt);
+    TIK_LAUNCHED("k_count_active");
+    TIK_HIP(hipMemcpyAsync(&active, b.cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    TIK_HIP(hipStreamSynchronize(st));
+  }
+  return TIK_OK;
+}
+
+template <typename TA, typename TC>
+int run_core_nc(const Plan& pl, const Bufs& b, double tol, int maxit, hipStream_t st,
+                const double* rt, const double* rb) {
+  switch (pl.NC) {
+    case 1: return run_core<TA, TC, 1>(pl, b, tol, maxit, st, rt, rb);
+    case 2: return run_core<TA, TC, 2>(pl, b, tol, maxit, st, rt, rb);
+    case 4: return run_core<TA, TC, 4>(pl, b, tol, maxit, st, rt, rb);
+    case 8: return run_core<TA, TC, 8>(pl, b, tol, maxit, st, rt, rb);
+    case 16: return run_core<TA, TC, 16>(pl, b, tol, maxit, st, rt, rb);
+    case 32: return run_core<TA, TC, 32>(pl, b, tol, maxit, st, rt, rb);
+  }
+  set_error("internal: lambda batch wider than 32");
+  return TIK_ENOTSUP;
+}
+
+// Upload a plan's tables and per-solve data.  Host staging vectors are kept
+// in `keep` until the caller synchronizes.
+int upload_plan(const Plan& pl, const Bufs& b, const tik_precond_s* pc, double* const* X,
+                std::vector<std::vector<char>>& keep, hipStream_t st) {
+  auto stash = [&](const void* src, size_t bytes) -> const void* {
+    keep.emplace_back(static_cast<const char*>(src), static_cast<const char*>(src) + bytes);
+    return keep.back().data();
+  };
+  TIK_TRY(upload(b.P, stash(pl.P.data(), pl.P.size() * sizeof(DevProb)), pl.P.size() * sizeof(DevProb), st));
+  TIK_TRY(upload(b.itN, stash(pl.itN.data(), pl.itN.size() * sizeof(Item)), pl.itN.size() * sizeof(Item), st));
+  TIK_TRY(upload(b.itB, stash(pl.itB.data(), pl.itB.size() * sizeof(Item)), pl.itB.size() * sizeof(Item), st));
+  TIK_TRY(upload(b.itT, stash(pl.itT.data(), pl.itT.size() * sizeof(Item)), pl.itT.size() * sizeof(Item), st));
+  TIK_TRY(upload(b.itQ, stash(pl.itQ.data(), pl.itQ.size() * sizeof(Item)), pl.itQ.size() * sizeof(Item), st));
+  std::vector<double> lams(pl.J);
+  std::vector<int32_t> pre(pl.J), jmap(pl.J);
+  std::vector<double*> xp(pl.P.size());
+  for (size_t lp = 0; lp < pl.P.size(); ++lp) {
+    const int p = pl.pidx[lp];
+    for (int i = 0; i < pl.N; ++i) {
+      const int gi = pl.i0[lp] + i;
+      lams[lp * pl.N + i] = pc->lams[size_t(p) * pc->N + gi];
+      pre[lp * pl.N + i] = pc->status[size_t(p) * pc->N + gi];
+      jmap[lp * pl.N + i] = p * pc->N + gi;
+    }
+    xp[lp] = X ? X[p] + int64_t(pl.i0[lp]) * pc->probs[p].n : nullptr;
+  }
+  TIK_TRY(upload(b.lams, stash(lams.data(), lams.size() * 8), lams.size() * 8, st));
+  TIK_TRY(upload(b.pre, stash(pre.data(), pre.size() * 4), pre.size() * 4, st));
+  TIK_TRY(upload(b.jmap, stash(jmap.data(), jmap.size() * 4), jmap.size() * 4, st));
+  TIK_TRY(upload(b.Xp, stash(xp.data(), xp.size() * sizeof(double*)), xp.size() * sizeof(double*), st));
+  return TIK_OK;
+}
+
+__global__ void k_write_out_map(const DevProb* __restrict__ P, int N, const double* __restrict__ x,
+                                const Scal* __restrict__ sc, double* const* __restrict__ Xout,
+                                const int32_t* __restrict__ jmap, int32_t* iters, int32_t* status,
+                                double* relres) {
+  const int j = blockIdx.y;
+  const int p = j / N, i = j % N;
+  const DevProb& pr = P[p];
+  const Scal& S = sc[j];
+  const bool ok = S.status == TIK_ST_CONVERGED || S.status == TIK_ST_MAXIT;
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < pr.n;
+       c += int64_t(gridDim.x) * blockDim.x)
+    if (ok && Xout[p]) Xout[p][c + int64_t(i) * pr.n] = x[(pr.offS + c) * N + i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int g = jmap[j];
+    if (iters) iters[g] = S.iters;
+    if (status) status[g] = S.status;
+    if (relres) relres[g] = S.relres;
+  }
+}
+
+void groups_for(const tik_precond_s* pc, int32_t nprob, int32_t mode,
+                std::vector<std::vector<int>>& gp, std::vector<std::vector<int>>& gi, std::vector<int>& gN) {
+  gp.clear(); gi.clear(); gN.clear();
+  const int N = pc->N;
+  if (mode == TIK_PLAIN_F64_PER_LAMBDA) {
+    for (int p = 0; p < nprob; ++p)
+      for (int i = 0; i < N; ++i) {
+        gp.push_back({p});
+        gi.push_back({i});
+        gN.push_back(1);
+      }
+    return;
+  }
+  // batched: all problems, lambdas in groups of at most 32
+  for (int i0 = 0; i0 < N; i0 += 32) {
+    std::vector<int> ps, is;
+    for (int p = 0; p < nprob; ++p) { ps.push_back(p); is.push_back(i0); }
+    gp.push_back(ps);
+    gi.push_back(is);
+    gN.push_back(std::min(32, N - i0));
+  }
+}
+
+}  // namespace
+
+int lsqr_bytes(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32_t mode,
+               size_t* bytes) {
+  std::vector<std::vector<int>> gp, gi;
+  std::vector<int> gN;
+  groups_for(pc, nprob, mode, gp, gi, gN);
+  size_t best = 0;
+  const size_t tc = mode == TIK_MIXED_BATCHED ? sizeof(float) : sizeof(double);
+  for (size_t g = 0; g < gp.size(); ++g) {
+    Plan pl;
+    make_plan(p, pc, gp[g], gi[g], gN[g], pl);
+    Arena a;
+    Bufs b;
+    take_bufs(a, pl, tc, b);
+    best = std::max(best, a.used);
+  }
+  *bytes = best + 256;
+  return TIK_OK;
+}
+
+int lsqr_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32_t mode,
+             double tol, int32_t maxit, double* const* X, int32_t* iters, int32_t* status,
+             double* relres, void* dws, size_t dws_bytes, hipStream_t st) {
+  if (mode == TIK_MIXED_BATCHED) {
+    set_error("mixed precision mode is not available in this build");
+    return TIK_ENOTSUP;
+  }
+  std::vector<std::vector<int>> gp, gi;
+  std::vector<int> gN;
+  groups_for(pc, nprob, mode, gp, gi, gN);
+  const bool f32 = p[0].a_dtype == TIK_F32;
+  for (size_t g = 0; g < gp.size(); ++g) {
+    Plan pl;
+    make_plan(p, pc, gp[g], gi[g], gN[g], pl);
+    Arena a;
+    a.base = static_cast<char*>(dws);
+    a.cap = dws_bytes;
+    Bufs b;
+    take_bufs(a, pl, sizeof(double), b);
+    if (!a.fits()) {
+      set_error("tik_lsqr_batch: workspace too small");
+      return TIK_EWORKSPACE;
+    }
+    std::vector<std::vector<char>> keep;
+    TIK_TRY(upload_plan(pl, b, pc, X, keep, st));
+    if (f32)
+      TIK_TRY((run_core_nc<float, double>(pl, b, tol, maxit, st, nullptr, nullptr)));
+    else
+      TIK_TRY((run_core_nc<double, double>(pl, b, tol, maxit, st, nullptr, nullptr)));
+    int64_t maxn = 0;
+    for (auto& d : pl.P) maxn = std::max(maxn, d.n);
+    hipLaunchKernelGGL(k_write_out_map, dim3(unsigned(cdiv(maxn, 256)), unsigned(pl.J)), dim3(256), 0,
+                       st, b.P, pl.N, b.x, b.sc, b.Xp, b.jmap, iters, status, relres);
+    TIK_LAUNCHED("k_write_out");
+    TIK_HIP(hipStreamSynchronize(st));   // staging vectors in `keep` die here
+  }
+  return TIK_OK;
+}
+
+}  // namespace tik

@@ -1,0 +1,429 @@
+// Sketch kernels: Y = X A (tall) or Y^T = X^T A^T (wide), X never stored whole.
+//
+// Embeddings (Section 2.1.1 of Meier & Nakatsukasa):
+//  * SRHT  X = sqrt(m'/s) S H D with D random signs, H the orthonormal Hadamard
+//          matrix of order m' = 2^k >= m (A zero-padded), S a uniform s-subset
+//          of rows.  Applied as an unnormalised fast Walsh-Hadamard transform
+//          (entries +-1) scaled by 1/sqrt(s), which is the same matrix.
+//  * Gauss X with i.i.d. N(0, 1/s) entries, so E[X^T X] = I as the embedding
+//          definition of Section 1.3 requires.
+//
+// Randomness comes from Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11),
+// a counter-based generator, so every random entry is a pure function of
+// (seed, index) and does not depend on launch shapes.
+#include "tik_internal.h"
+
+#include <hip/hip_bf16.h>
+
+namespace tik {
+
+// ---------------------------------------------------------------- Philox ----
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k.x += 0x9E3779B9u;
+      k.y += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+  }
+  return c;
+}
+
+static constexpr uint32_t TAG_PERM = 0x5052504Du;   // row subset
+static constexpr uint32_t TAG_SIGN = 0x5349474Eu;   // random signs D
+static constexpr uint32_t TAG_GAUS = 0x47415553u;   // Gaussian entries
+
+__device__ __forceinline__ uint2 seed_key(uint64_t seed) {
+  return make_uint2(uint32_t(seed), uint32_t(seed >> 32));
+}
+
+// Balanced Feistel network on 2h bits with Philox round functions
+// (Luby-Rackoff), restricted to [0, 2^k) by cycle walking.  A bijection of
+// [0, 2^k), so its first s values are s distinct rows.  Out-of-range values
+// number at most 2^(2h) - 2^k <= 2^k, so the walk ends within 2^k steps.
+__device__ uint32_t feistel_perm(uint32_t x, int k, uint2 key) {
+  const int h = (k + 1) >> 1;
+  const uint32_t mask = (1u << h) - 1u;
+  const uint32_t lim = 1u << k;
+  for (uint32_t walk = 0; walk <= lim; ++walk) {
+    uint32_t L = x >> h, R = x & mask;
+#pragma unroll 1
+    for (uint32_t r = 0; r < 6; ++r) {
+      const uint32_t f = philox4x32_10(make_uint4(R, r, TAG_PERM, uint32_t(k)), key).x & mask;
+      const uint32_t nl = R;
+      R = L ^ f;
+      L = nl;
+    }
+    x = (L << h) | R;
+    if (x < lim) return x;
+  }
+  return 0xFFFFFFFFu;
+}
+
+// One workgroup: draw the s sampled rows, sort them ascending (bitonic sort in
+// LDS), write them, and for the two-pass transform the start of every bucket
+// of 2^bbits consecutive rows.  Also writes the sign bits of D (m'/32 words).
+static constexpr int ROWS_MAX = 16384;
+
+__global__ void __launch_bounds__(1024) k_srht_rows(uint64_t seed, int k, int64_t s,
+                                                    int32_t* __restrict__ rows,
+                                                    int32_t* __restrict__ bstart, int bbits,
+                                                    uint32_t* __restrict__ signs) {
+  __shared__ int32_t buf[ROWS_MAX];
+  const uint2 key = seed_key(seed);
+  const int tid = threadIdx.x;
+  int P = 1;
+  while (P < s) P <<= 1;
+  for (int i = tid; i < P; i += blockDim.x)
+    buf[i] = (i < s) ? (k == 0 ? 0 : int32_t(feistel_perm(uint32_t(i), k, key))) : 0x7FFFFFFF;
+  __syncthreads();
+  for (int len = 2; len <= P; len <<= 1) {
+    for (int str = len >> 1; str > 0; str >>= 1) {
+      for (int i = tid; i < P; i += blockDim.x) {
+        const int j = i ^ str;
+        if (j > i) {
+          const bool up = (i & len) == 0;
+          const int32_t a = buf[i], b = buf[j];
+          if ((a > b) == up) {
+            buf[i] = b;
+            buf[j] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < s; i += blockDim.x) rows[i] = buf[i];
+  const int nb = 1 << (k - bbits);
+  for (int hb = tid; hb <= nb; hb += blockDim.x) {
+    // first q with rows[q] >= hb << bbits
+    const int32_t key_row = (hb == nb) ? 0x7FFFFFFF : (hb << bbits);
+    int lo = 0, hi = int(s);
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (buf[mid] < key_row) lo = mid + 1; else hi = mid;
+    }
+    bstart[hb] = (hb == nb) ? int32_t(s) : lo;
+  }
+  const int words = ((1 << k) + 31) >> 5;
+  for (int w = tid; w < words; w += blockDim.x) {
+    const uint4 v = philox4x32_10(make_uint4(uint32_t(w >> 2), 0u, TAG_SIGN, 0u), key);
+    const uint32_t sel = w & 3;
+    signs[w] = sel == 0 ? v.x : sel == 1 ? v.y : sel == 2 ? v.z : v.w;
+  }
+}
+
+__device__ __forceinline__ bool neg_sign(const uint32_t* __restrict__ signs, int64_t r) {
+  return (signs[r >> 5] >> (r & 31)) & 1u;
+}
+
+// Single-pass SRHT for m' <= 2^13: one workgroup per column, the whole padded
+// column staged in LDS, log2 m' butterfly stages, then the sampled rows gathered.
+template <typename TA>
+__global__ void __launch_bounds__(256) k_srht_single(const TA* __restrict__ A, int64_t m,
+                                                     int64_t lda, int k,
+                                                     const uint32_t* __restrict__ signs,
+                                                     const int32_t* __restrict__ rows, int64_t s,
+                                                     double scale, double* __restrict__ Y) {
+  extern __shared__ double lbuf[];
+  const int64_t c = blockIdx.x;
+  const int M = 1 << k;
+  const TA* col = A + c * lda;
+  for (int r = threadIdx.x; r < M; r += blockDim.x) {
+    double v = 0.0;
+    if (r < m) {
+      v = double(col[r]);
+      if (neg_sign(signs, r)) v = -v;
+    }
+    lbuf[r] = v;
+  }
+  __syncthreads();
+  for (int h = 1; h < M; h <<= 1) {
+    for (int idx = threadIdx.x; idx < (M >> 1); idx += blockDim.x) {
+      const int i = ((idx / h) * (h << 1)) + (idx % h);
+      const double a = lbuf[i], b = lbuf[i + h];
+      lbuf[i] = a + b;
+      lbuf[i + h] = a - b;
+    }
+    __syncthreads();
+  }
+  for (int64_t q = threadIdx.x; q < s; q += blockDim.x) Y[q + c * s] = lbuf[rows[q]] * scale;
+}
+
+// Two-pass SRHT, H_{2^k} = H_{2^a} (x) H_{2^b} with k = a + b.
+// Pass 1 applies H_{2^a} across the 2^a rows hi*2^b + lo sharing a low index
+// (one thread per lo, 2^a values in registers; threads read consecutive rows).
+template <typename TA, int ABITS>
+__global__ void __launch_bounds__(256) k_srht_pass1(const TA* __restrict__ A, int64_t m,
+                                                    int64_t lda, int64_t c0, int bbits,
+                                                    const uint32_t* __restrict__ signs,
+                                                    double* __restrict__ T) {
+  constexpr int NA = 1 << ABITS;
+  const int64_t lo = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t cc = blockIdx.y;
+  const int64_t B = int64_t(1) << bbits;
+  if (lo >= B) return;
+  const TA* col = A + (c0 + cc) * lda;
+  double v[NA];
+#pragma unroll
+  for (int hi = 0; hi < NA; ++hi) {
+    const int64_t r = hi * B + lo;
+    double x = 0.0;
+    if (r < m) {
+      x = double(col[r]);
+      if (neg_sign(signs, r)) x = -x;
+    }
+    v[hi] = x;
+  }
+#pragma unroll
+  for (int h = 1; h < NA; h <<= 1) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      if ((i & h) == 0) {
+        const double a = v[i], b = v[i + h];
+        v[i] = a + b;
+        v[i + h] = a - b;
+      }
+    }
+  }
+  double* tcol = T + cc * (B << ABITS);
+#pragma unroll
+  for (int hi = 0; hi < NA; ++hi) tcol[hi * B + lo] = v[hi];
+}
+
+// Pass 2 applies H_{2^b} to each contiguous bucket of 2^b rows in LDS and
+// writes only the sampled rows that fall in the bucket.
+__global__ void __launch_bounds__(256) k_srht_pass2(const double* __restrict__ T, int64_t c0,
+                                                    int k, int bbits,
+                                                    const int32_t* __restrict__ rows,
+                                                    const int32_t* __restrict__ bstart, int64_t s,
+                                                    double scale, double* __restrict__ Y) {
+  extern __shared__ double lbuf[];
+  const int hb = blockIdx.x;
+  const int64_t cc = blockIdx.y;
+  const int B = 1 << bbits;
+  const int q0 = bstart[hb], q1 = bstart[hb + 1];
+  if (q0 == q1) return;
+  const double* src = T + cc * (int64_t(1) << k) + int64_t(hb) * B;
+  for (int r = threadIdx.x; r < B; r += blockDim.x) lbuf[r] = src[r];
+  __syncthreads();
+  for (int h = 1; h < B; h <<= 1) {
+    for (int idx = threadIdx.x; idx < (B >> 1); idx += blockDim.x) {
+      const int i = ((idx / h) * (h << 1)) + (idx % h);
+      const double a = lbuf[i], b = lbuf[i + h];
+      lbuf[i] = a + b;
+      lbuf[i + h] = a - b;
+    }
+    __syncthreads();
+  }
+  const int64_t base = int64_t(hb) * B;
+  for (int q = q0 + threadIdx.x; q < q1; q += blockDim.x)
+    Y[q + (c0 + cc) * s] = lbuf[rows[q] - base] * scale;
+}
+
+// ---------------------------------------------------------------- Gaussian --
+// Entry (q, r) of the s x (long dim) Gaussian matrix: Philox of counter
+// (r, q/4) gives four 32-bit words, Box-Muller turns them into four normals
+// for rows q = 4*(q/4) .. +3.  Scaled by 1/sqrt(s).
+__device__ __forceinline__ void gauss4(uint64_t seed, uint32_t r, uint32_t qb, double out[4]) {
+  const uint4 v = philox4x32_10(make_uint4(r, qb, TAG_GAUS, 0u), seed_key(seed));
+  const double two32 = 4294967296.0;
+  const double u0 = (double(v.x) + 0.5) / two32, u1 = (double(v.y) + 0.5) / two32;
+  const double u2 = (double(v.z) + 0.5) / two32, u3 = (double(v.w) + 0.5) / two32;
+  const double r0 = sqrt(-2.0 * log(u0)), r1 = sqrt(-2.0 * log(u2));
+  double s0, c0, s1, c1;
+  sincospi(2.0 * u1, &s0, &c0);
+  sincospi(2.0 * u3, &s1, &c1);
+  out[0] = r0 * c0;
+  out[1] = r0 * s0;
+  out[2] = r1 * c1;
+  out[3] = r1 * s1;
+}
+
+// X chunk (s x kc, column-major ld = s): columns are long-dimension indices
+// r0 .. r0 + kc - 1.  One thread per (4 rows, 1 column).
+template <typename TX>
+__global__ void __launch_bounds__(256) k_gauss_gen(uint64_t seed, int64_t s, int64_t r0,
+                                                   int64_t kc, double scale, TX* __restrict__ X) {
+  const int64_t sq = (s + 3) >> 2;
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= sq * kc) return;
+  const int64_t qb = idx % sq, cc = idx / sq;
+  double z[4];
+  gauss4(seed, uint32_t(r0 + cc), uint32_t(qb), z);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t q = qb * 4 + t;
+    if (q < s) X[q + cc * s] = TX(z[t] * scale);
+  }
+}
+
+// Y (s x ncol, ld = s) += Xc (s x kc, ld = s) * Bop (kc x ncol), FP64,
+// Bop(kk, c) = A[(r0 + kk) + c lda] (tall) or A[c + (r0 + kk) lda] (wide).
+// 64 x 64 output tile, 16-deep k steps staged in LDS, 4 x 4 per thread.
+template <typename TA, bool WIDE>
+__global__ void __launch_bounds__(256) k_sketch_gemm64(const double* __restrict__ Xc, int64_t s,
+                                                       int64_t kc, const TA* __restrict__ A,
+                                                       int64_t lda, int64_t r0, int64_t ncol,
+                                                       double* __restrict__ Y) {
+  __shared__ double Xs[16][64 + 1];
+  __shared__ double Bs[16][64 + 1];
+  const int tid = threadIdx.x;
+  const int64_t q0 = int64_t(blockIdx.x) * 64, c0 = int64_t(blockIdx.y) * 64;
+  const int tq = tid & 15, tc = tid >> 4;
+  double acc[4][4] = {};
+  for (int64_t k0 = 0; k0 < kc; k0 += 16) {
+    for (int e = tid; e < 16 * 64; e += 256) {
+      const int qq = e & 63, kk = e >> 6;
+      const int64_t q = q0 + qq, kg = k0 + kk;
+      Xs[kk][qq] = (q < s && kg < kc) ? Xc[q + kg * s] : 0.0;
+    }
+    for (int e = tid; e < 16 * 64; e += 256) {
+      int kk, cc;
+      if (WIDE) { cc = e & 63; kk = e >> 6; } else { kk = e & 15; cc = e >> 4; }
+      const int64_t c = c0 + cc, kg = k0 + kk;
+      double v = 0.0;
+      if (c < ncol && kg < kc) v = WIDE ? double(A[c + (r0 + kg) * lda]) : double(A[(r0 + kg) + c * lda]);
+      Bs[kk][cc] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double xa[4], bb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xa[i] = Xs[kk][tq + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bb[j] = Bs[kk][tc + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(xa[i], bb[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t q = q0 + tq + 16 * i, c = c0 + tc + 16 * j;
+      if (q < s && c < ncol) Y[q + c * s] += acc[i][j];
+    }
+}
+
+__global__ void k_f32_to_f64(const float* __restrict__ src, double* __restrict__ dst, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = double(src[i]);
+}
+
+// ---------------------------------------------------------------- launchers --
+int launch_srht_rows(uint64_t seed, int k, int64_t s, int32_t* rows, int32_t* bstart, int bbits,
+                     hipStream_t st) {
+  // signs live right after the bucket table (caller sized it)
+  uint32_t* signs = reinterpret_cast<uint32_t*>(bstart + (1 << (k - bbits)) + 1);
+  ProfScope ps("sketch", st);
+  hipLaunchKernelGGL(k_srht_rows, dim3(1), dim3(1024), 0, st, seed, k, s, rows, bstart, bbits,
+                     signs);
+  TIK_LAUNCHED("k_srht_rows");
+  return TIK_OK;
+}
+
+static const uint32_t* signs_of(const int32_t* bstart, int k, int bbits) {
+  return reinterpret_cast<const uint32_t*>(bstart + (1 << (k - bbits)) + 1);
+}
+
+int launch_srht_single(const void* A, int a_f32, int64_t m, int64_t n, int64_t lda, int k,
+                       uint64_t seed, const int32_t* rows, int64_t s, double* Y, hipStream_t st) {
+  (void)seed;
+  const int32_t* bstart = rows + s;  // layout set by the caller: rows | bstart | signs
+  const uint32_t* signs = signs_of(bstart, k, k);
+  const double scale = 1.0 / sqrt(double(s));
+  const size_t lds = sizeof(double) << k;
+  ProfScope ps("sketch", st);
+  if (a_f32)
+    hipLaunchKernelGGL(k_srht_single<float>, dim3(unsigned(n)), dim3(256), lds, st,
+                       static_cast<const float*>(A), m, lda, k, signs, rows, s, scale, Y);
+  else
+    hipLaunchKernelGGL(k_srht_single<double>, dim3(unsigned(n)), dim3(256), lds, st,
+                       static_cast<const double*>(A), m, lda, k, signs, rows, s, scale, Y);
+  TIK_LAUNCHED("k_srht_single");
+  return TIK_OK;
+}
+
+template <typename TA>
+static int pass1_dispatch(const TA* A, int64_t m, int64_t lda, int64_t c0, int64_t nc, int abits,
+                          int bbits, const uint32_t* signs, double* T, hipStream_t st) {
+  dim3 grid(unsigned(cdiv(int64_t(1) << bbits, 256)), unsigned(nc));
+  switch (abits) {
+    case 1: hipLaunchKernelGGL((k_srht_pass1<TA, 1>), grid, dim3(256), 0, st, A, m, lda, c0, bbits, signs, T); break;
+    case 2: hipLaunchKernelGGL((k_srht_pass1<TA, 2>), grid, dim3(256), 0, st, A, m, lda, c0, bbits, signs, T); break;
+    case 3: hipLaunchKernelGGL((k_srht_pass1<TA, 3>), grid, dim3(256), 0, st, A, m, lda, c0, bbits, signs, T); break;
+    case 4: hipLaunchKernelGGL((k_srht_pass1<TA, 4>), grid, dim3(256), 0, st, A, m, lda, c0, bbits, signs, T); break;
+    case 5: hipLaunchKernelGGL((k_srht_pass1<TA, 5>), grid, dim3(256), 0, st, A, m, lda, c0, bbits, signs, T); break;
+    default: set_error("SRHT: unsupported split"); return TIK_ENOTSUP;
+  }
+  TIK_LAUNCHED("k_srht_pass1");
+  return TIK_OK;
+}
+
+// Column chunk [c0, c0 + nc) of the two-pass transform.  rows | bstart | signs
+// are laid out consecutively by the caller.
+int launch_srht_twopass(const void* A, int a_f32, int64_t m, int64_t lda, int64_t c0, int64_t nc,
+                        int k, int bbits, const int32_t* rows, int64_t s, double* T, double* Y,
+                        hipStream_t st) {
+  const int32_t* bstart = rows + s;
+  const uint32_t* signs = signs_of(bstart, k, bbits);
+  const int abits = k - bbits;
+  ProfScope ps("sketch", st);
+  if (a_f32)
+    TIK_TRY(pass1_dispatch(static_cast<const float*>(A), m, lda, c0, nc, abits, bbits, signs, T, st));
+  else
+    TIK_TRY(pass1_dispatch(static_cast<const double*>(A), m, lda, c0, nc, abits, bbits, signs, T, st));
+  const size_t lds = sizeof(double) << bbits;
+  hipLaunchKernelGGL(k_srht_pass2, dim3(1u << abits, unsigned(nc)), dim3(256), lds, st, T, c0, k,
+                     bbits, rows, bstart, s, 1.0 / sqrt(double(s)), Y);
+  TIK_LAUNCHED("k_srht_pass2");
+  return TIK_OK;
+}
+
+int launch_gauss_gen(uint64_t seed, int64_t s, int64_t r0, int64_t kc, void* Xc, int bf16,
+                     hipStream_t st) {
+  const int64_t total = ((s + 3) >> 2) * kc;
+  const double scale = 1.0 / sqrt(double(s));
+  ProfScope ps("sketch", st);
+  if (bf16)
+    hipLaunchKernelGGL(k_gauss_gen<__hip_bfloat16>, dim3(unsigned(cdiv(total, 256))), dim3(256),
+                       0, st, seed, s, r0, kc, scale, static_cast<__hip_bfloat16*>(Xc));
+  else
+    hipLaunchKernelGGL(k_gauss_gen<double>, dim3(unsigned(cdiv(total, 256))), dim3(256), 0, st,
+                       seed, s, r0, kc, scale, static_cast<double*>(Xc));
+  TIK_LAUNCHED("k_gauss_gen");
+  return TIK_OK;
+}
+
+int launch_sketch_gemm_f64(const double* Xc, int64_t s, int64_t kc, const void* A, int a_f32,
+                           int64_t lda, int64_t r0, int64_t ncol, int wide, double* Y,
+                           hipStream_t st) {
+  dim3 grid(unsigned(cdiv(s, 64)), unsigned(cdiv(ncol, 64)));
+  ProfScope ps("sketch", st);
+  if (a_f32) {
+    if (wide) hipLaunchKernelGGL((k_sketch_gemm64<float, true>), grid, dim3(256), 0, st, Xc, s, kc, static_cast<const float*>(A), lda, r0, ncol, Y);
+    else      hipLaunchKernelGGL((k_sketch_gemm64<float, false>), grid, dim3(256), 0, st, Xc, s, kc, static_cast<const float*>(A), lda, r0, ncol, Y);
+  } else {
+    if (wide) hipLaunchKernelGGL((k_sketch_gemm64<double, true>), grid, dim3(256), 0, st, Xc, s, kc, static_cast<const double*>(A), lda, r0, ncol, Y);
+    else      hipLaunchKernelGGL((k_sketch_gemm64<double, false>), grid, dim3(256), 0, st, Xc, s, kc, static_cast<const double*>(A), lda, r0, ncol, Y);
+  }
+  TIK_LAUNCHED("k_sketch_gemm64");
+  return TIK_OK;
+}
+
+int launch_f32_to_f64(const float* src, double* dst, int64_t count, hipStream_t st) {
+  hipLaunchKernelGGL(k_f32_to_f64, dim3(unsigned(cdiv(count, 256))), dim3(256), 0, st, src, dst,
+                     count);
+  TIK_LAUNCHED("k_f32_to_f64");
+  return TIK_OK;
+}
+
+}  // namespace tik

@@ -1,0 +1,472 @@
+// C ABI entry points of libtik: argument validation, workspace planning and
+// stream-ordered orchestration of the sketch, preconditioner and solve kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "tik_internal.h"
+
+namespace tik {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+static int fail(int rc, const std::string& msg) {
+  g_err = msg;
+  return rc;
+}
+
+// ------------------------------------------------------------- profiling ---
+namespace {
+struct ProfFamily {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  double done_ms = 0.0;
+  int64_t done_n = 0;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::map<std::string, ProfFamily> g_prof;
+std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> g_open;
+}  // namespace
+
+ProfScope::ProfScope(const char* family, hipStream_t s) : slot(-1), st(s) {
+  if (!g_prof_on) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return;
+  }
+  (void)hipEventRecord(a, st);
+  g_open.push_back({family, {a, b}});
+  slot = int(g_open.size()) - 1;
+}
+
+ProfScope::~ProfScope() {
+  if (slot < 0) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  auto& o = g_open[size_t(slot)];
+  (void)hipEventRecord(o.second.second, st);
+  g_prof[o.first].ev.push_back(o.second);
+  o.second = {nullptr, nullptr};
+}
+
+// ---------------------------------------------------------------- helpers --
+static bool tall(const tik_problem& p) { return p.m >= p.n; }
+
+static int validate_problems(const tik_problem* p, int32_t nprob, const char* fn) {
+  if (!p || nprob < 1) return fail(TIK_EINVAL, std::string(fn) + ": need at least one problem");
+  for (int32_t k = 0; k < nprob; ++k) {
+    const tik_problem& q = p[k];
+    const std::string at = std::string(fn) + ": problem " + std::to_string(k) + ": ";
+    if (q.m < 1 || q.n < 1) return fail(TIK_EINVAL, at + "m and n must be >= 1");
+    if (q.lda < q.m) return fail(TIK_EINVAL, at + "lda must be >= m");
+    if (q.a_dtype != TIK_F64 && q.a_dtype != TIK_F32)
+      return fail(TIK_EINVAL, at + "a_dtype must be TIK_F64 or TIK_F32");
+    if (q.reserved != 0) return fail(TIK_EINVAL, at + "reserved must be 0");
+    if (!q.A || !q.b) return fail(TIK_EINVAL, at + "A and b must be device pointers");
+    if (q.m > (int64_t(1) << 31) || q.n > (int64_t(1) << 31))
+      return fail(TIK_EINVAL, at + "dimensions above 2^31 are not supported");
+    if (tall(q) != tall(p[0]))
+      return fail(TIK_EINVAL, std::string(fn) + ": all problems must be tall (m >= n) or all wide");
+    if (q.a_dtype != p[0].a_dtype)
+      return fail(TIK_EINVAL, std::string(fn) + ": all problems must share one storage type");
+  }
+  return TIK_OK;
+}
+
+static int check_ws(void* dws, size_t dws_bytes, size_t need, const char* fn) {
+  if (need > 0 && !dws) return fail(TIK_EWORKSPACE, std::string(fn) + ": workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(dws) % 256 != 0)
+    return fail(TIK_EWORKSPACE, std::string(fn) + ": workspace must be 256-byte aligned");
+  if (dws_bytes < need)
+    return fail(TIK_EWORKSPACE, std::string(fn) + ": workspace of " + std::to_string(dws_bytes) +
+                                    " bytes, need " + std::to_string(need));
+  return TIK_OK;
+}
+
+static int ilog2_ceil(int64_t v) {
+  int k = 0;
+  while ((int64_t(1) << k) < v) ++k;
+  return k;
+}
+
+static constexpr int SRHT_MAX_K = 18;
+static constexpr int64_t SRHT_MAX_S = 16384;
+static constexpr size_t SCRATCH_CHUNK = size_t(256) << 20;
+
+// --------------------------------------------------------------- sketch ----
+struct SketchPlan {
+  std::vector<double*> Y;
+  std::vector<int64_t> yrows, ycols;
+  int32_t* rows = nullptr;   // SRHT: rows | bucket starts | sign words
+  double* T = nullptr;       // SRHT two-pass scratch
+  double* Xc = nullptr;      // Gaussian X chunk
+  int64_t tcols = 0, kc = 0;
+};
+
+// long-dimension rows of the Gaussian X generated per chunk for problem q
+static int64_t gauss_chunk(const tik_problem& q, int64_t s) {
+  const int64_t longdim = tall(q) ? q.m : q.n;
+  int64_t kc = int64_t(SCRATCH_CHUNK / (sizeof(double) * size_t(s)));
+  return std::max<int64_t>(64, std::min<int64_t>(longdim, kc));
+}
+
+static int sketch_plan(const tik_problem* p, int32_t nprob, int32_t embed, const int64_t* s,
+                       Arena& a, SketchPlan& sp) {
+  sp.Y.assign(size_t(nprob), nullptr);
+  sp.yrows.assign(size_t(nprob), 0);
+  sp.ycols.assign(size_t(nprob), 0);
+  int64_t rows_ints = 0, tsz = 0, xsz = 0;
+  for (int32_t k = 0; k < nprob; ++k) {
+    const bool t = tall(p[k]);
+    sp.yrows[k] = s[k];
+    sp.ycols[k] = t ? p[k].n : p[k].m;
+    sp.Y[k] = a.take<double>(size_t(s[k]) * size_t(sp.ycols[k]));
+    if (embed == TIK_SRHT) {
+      const int kk = ilog2_ceil(p[k].m);
+      const int bb = kk <= 13 ? kk : 13;
+      rows_ints = std::max<int64_t>(rows_ints, s[k] + (int64_t(1) << (kk - bb)) + 1 +
+                                                   (((int64_t(1) << kk) + 31) >> 5));
+      if (kk > 13) {
+        const int64_t cols = std::max<int64_t>(
+            1, std::min<int64_t>(p[k].n, int64_t(SCRATCH_CHUNK / (sizeof(double) << kk))));
+        sp.tcols = std::max(sp.tcols, cols);
+        tsz = std::max<int64_t>(tsz, cols << kk);
+      }
+    } else {
+      xsz = std::max<int64_t>(xsz, gauss_chunk(p[k], s[k]) * s[k]);
+    }
+  }
+  if (rows_ints) sp.rows = a.take<int32_t>(size_t(rows_ints));
+  if (tsz) sp.T = a.take<double>(size_t(tsz));
+  if (xsz) sp.Xc = a.take<double>(size_t(xsz));
+  return TIK_OK;
+}
+
+static int sketch_validate(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sdt,
+                           const int64_t* s) {
+  TIK_TRY(validate_problems(p, nprob, "tik_sketch"));
+  if (embed != TIK_SRHT && embed != TIK_GAUSS)
+    return fail(TIK_EINVAL, "tik_sketch: embed must be TIK_SRHT or TIK_GAUSS");
+  if (sdt != TIK_F64 && sdt != TIK_BF16)
+    return fail(TIK_EINVAL, "tik_sketch: sketch_dtype must be TIK_F64 or TIK_BF16");
+  if (sdt == TIK_BF16 && embed != TIK_GAUSS)
+    return fail(TIK_EINVAL, "tik_sketch: TIK_BF16 sketches need the Gaussian embedding");
+  if (!s) return fail(TIK_EINVAL, "tik_sketch: s is NULL");
+  for (int32_t k = 0; k < nprob; ++k) {
+    const int64_t longdim = tall(p[k]) ? p[k].m : p[k].n;
+    if (s[k] < 1 || s[k] > longdim)
+      return fail(TIK_EINVAL, "tik_sketch: problem " + std::to_string(k) +
+                                  ": sketch size must lie in [1, long dimension]");
+    if (embed == TIK_SRHT) {
+      if (!tall(p[k]))
+        return fail(TIK_ENOTSUP, "tik_sketch: the SRHT is implemented for tall problems only");
+      if (ilog2_ceil(p[k].m) > SRHT_MAX_K)
+        return fail(TIK_ENOTSUP, "tik_sketch: SRHT needs m <= 2^18");
+      if (s[k] > SRHT_MAX_S) return fail(TIK_ENOTSUP, "tik_sketch: SRHT needs s <= 16384");
+    }
+  }
+  if (sdt == TIK_BF16) return fail(TIK_ENOTSUP, "tik_sketch: BF16 sketches are not available in this build");
+  return TIK_OK;
+}
+
+}  // namespace tik
+
+using namespace tik;
+
+extern "C" {
+
+const char* tik_last_error(void) { return g_err.c_str(); }
+
+int tik_version(void) { return 100; }
+
+int tik_prof_enable(int32_t on) {
+  g_prof_on = on != 0;
+  return TIK_OK;
+}
+
+int tik_prof_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& kv : g_prof)
+    for (auto& e : kv.second.ev) {
+      (void)hipEventSynchronize(e.second);
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+  g_prof.clear();
+  g_open.clear();
+  return TIK_OK;
+}
+
+int tik_prof_query(const char* family, double* total_ms, int64_t* launches) {
+  if (!family || !total_ms || !launches) return fail(TIK_EINVAL, "tik_prof_query: NULL argument");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  auto it = g_prof.find(family);
+  if (it == g_prof.end()) {
+    *total_ms = 0.0;
+    *launches = 0;
+    return TIK_OK;
+  }
+  ProfFamily& f = it->second;
+  for (auto& e : f.ev) {
+    TIK_HIP(hipEventSynchronize(e.second));
+    float ms = 0.f;
+    TIK_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+    f.done_ms += ms;
+    f.done_n += 1;
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  f.ev.clear();
+  *total_ms = f.done_ms;
+  *launches = f.done_n;
+  return TIK_OK;
+}
+
+int tik_sketch_bytes(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sketch_dtype,
+                     const int64_t* s, size_t* bytes) {
+  if (!bytes) return fail(TIK_EINVAL, "tik_sketch_bytes: bytes is NULL");
+  TIK_TRY(sketch_validate(p, nprob, embed, sketch_dtype, s));
+  Arena a;
+  SketchPlan sp;
+  TIK_TRY(sketch_plan(p, nprob, embed, s, a, sp));
+  *bytes = a.used + 256;
+  return TIK_OK;
+}
+
+int tik_sketch(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sketch_dtype,
+               const int64_t* s, uint64_t seed, void* dws, size_t dws_bytes, tik_stream_t stream,
+               tik_sketch_t* out) {
+  if (!out) return fail(TIK_EINVAL, "tik_sketch: out is NULL");
+  *out = nullptr;
+  TIK_TRY(sketch_validate(p, nprob, embed, sketch_dtype, s));
+  size_t need = 0;
+  TIK_TRY(tik_sketch_bytes(p, nprob, embed, sketch_dtype, s, &need));
+  TIK_TRY(check_ws(dws, dws_bytes, need, "tik_sketch"));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Arena a;
+  a.base = static_cast<char*>(dws);
+  a.cap = dws_bytes;
+  SketchPlan sp;
+  TIK_TRY(sketch_plan(p, nprob, embed, s, a, sp));
+  for (int32_t k = 0; k < nprob; ++k) {
+    const tik_problem& q = p[k];
+    // problem k draws from its own stream of the generator
+    const uint64_t pseed = seed ^ (uint64_t(uint32_t(k)) * 0x9E3779B97F4A7C15ull);
+    const int f32 = q.a_dtype == TIK_F32;
+    if (embed == TIK_SRHT) {
+      const int kk = ilog2_ceil(q.m);
+      const int bb = kk <= 13 ? kk : 13;
+      int32_t* rows = sp.rows;
+      int32_t* bstart = rows + s[k];
+      TIK_TRY(launch_srht_rows(pseed, kk, s[k], rows, bstart, bb, st));
+      if (kk <= 13) {
+        TIK_TRY(launch_srht_single(q.A, f32, q.m, q.n, q.lda, kk, pseed, rows, s[k], sp.Y[k], st));
+      } else {
+        for (int64_t c0 = 0; c0 < q.n; c0 += sp.tcols) {
+          const int64_t nc = std::min(sp.tcols, q.n - c0);
+          TIK_TRY(launch_srht_twopass(q.A, f32, q.m, q.lda, c0, nc, kk, bb, rows, s[k], sp.T,
+                                      sp.Y[k], st));
+        }
+      }
+    } else {
+      const bool t = tall(q);
+      const int64_t longdim = t ? q.m : q.n;
+      const int64_t ncol = t ? q.n : q.m;
+      TIK_HIP(hipMemsetAsync(sp.Y[k], 0, size_t(s[k]) * size_t(ncol) * sizeof(double), st));
+      const int64_t chunk = gauss_chunk(q, s[k]);
+      for (int64_t r0 = 0; r0 < longdim; r0 += chunk) {
+        const int64_t kc = std::min(chunk, longdim - r0);
+        TIK_TRY(launch_gauss_gen(pseed, s[k], r0, kc, sp.Xc, 0, st));
+        TIK_TRY(launch_sketch_gemm_f64(sp.Xc, s[k], kc, q.A, f32, q.lda, r0, ncol, t ? 0 : 1,
+                                       sp.Y[k], st));
+      }
+    }
+  }
+  tik_sketch_s* h = new tik_sketch_s();
+  h->probs.assign(p, p + nprob);
+  h->embed = embed;
+  h->sketch_dtype = sketch_dtype;
+  h->s.assign(s, s + nprob);
+  h->seed = seed;
+  h->wide = !tall(p[0]);
+  h->Y = sp.Y;
+  h->yrows = sp.yrows;
+  h->ycols = sp.ycols;
+  *out = h;
+  return TIK_OK;
+}
+
+int tik_sketch_data(tik_sketch_t sk, int32_t k, const double** Y, int64_t* rows, int64_t* cols) {
+  if (!sk || !Y || !rows || !cols) return fail(TIK_EINVAL, "tik_sketch_data: NULL argument");
+  if (k < 0 || k >= int32_t(sk->probs.size())) return fail(TIK_EINVAL, "tik_sketch_data: bad index");
+  *Y = sk->Y[k];
+  *rows = sk->yrows[k];
+  *cols = sk->ycols[k];
+  return TIK_OK;
+}
+
+void tik_sketch_free(tik_sketch_t sk) { delete sk; }
+
+// ---------------------------------------------------------- preconditioner --
+namespace {
+struct PrecondPlan {
+  std::vector<double*> Rinv;
+  double* C = nullptr;
+  double* Dinv = nullptr;
+  double* Tmp = nullptr;
+  double* lams = nullptr;
+  int32_t* notpd = nullptr;
+};
+
+int precond_plan(tik_sketch_t sk, int32_t route, int32_t N, Arena& a, PrecondPlan& pp) {
+  const int32_t np = int32_t(sk->probs.size());
+  pp.Rinv.assign(size_t(np), nullptr);
+  int64_t kmax = 0;
+  for (int32_t k = 0; k < np; ++k) {
+    const int64_t kd = std::min(sk->probs[k].m, sk->probs[k].n);
+    kmax = std::max(kmax, kd);
+    if (route == TIK_ROUTE_CHOL) pp.Rinv[k] = a.take<double>(size_t(N) * size_t(kd) * size_t(kd));
+  }
+  pp.lams = a.take<double>(size_t(np) * size_t(N));
+  pp.notpd = a.take<int32_t>(size_t(np) * size_t(N));
+  if (route == TIK_ROUTE_CHOL) {
+    pp.C = a.take<double>(size_t(kmax) * size_t(kmax));
+    pp.Dinv = a.take<double>(size_t(N) * size_t(cdiv(kmax, 64)) * 64 * 64);
+    pp.Tmp = a.take<double>(size_t(N) * size_t(kmax) * 64);
+  }
+  return TIK_OK;
+}
+}  // namespace
+
+int tik_precond_bytes(tik_sketch_t sk, int32_t route, int32_t N, size_t* bytes) {
+  if (!sk || !bytes) return fail(TIK_EINVAL, "tik_precond_bytes: NULL argument");
+  if (route != TIK_ROUTE_CHOL && route != TIK_ROUTE_LOWRANK)
+    return fail(TIK_EINVAL, "tik_precond_bytes: route must be TIK_ROUTE_CHOL or TIK_ROUTE_LOWRANK");
+  if (N < 1) return fail(TIK_EINVAL, "tik_precond_bytes: N must be >= 1");
+  if (route == TIK_ROUTE_LOWRANK)
+    return fail(TIK_ENOTSUP, "tik_precond: the low-rank route is not available in this build");
+  Arena a;
+  PrecondPlan pp;
+  TIK_TRY(precond_plan(sk, route, N, a, pp));
+  *bytes = a.used + 256;
+  return TIK_OK;
+}
+
+int tik_precond(tik_sketch_t sk, int32_t route, const double* lambdas, int32_t N, double alpha,
+                void* dws, size_t dws_bytes, tik_stream_t stream, tik_precond_t* out,
+                double* sd_hat, int32_t* status) {
+  (void)alpha;
+  if (!out) return fail(TIK_EINVAL, "tik_precond: out is NULL");
+  *out = nullptr;
+  if (!sk) return fail(TIK_EINVAL, "tik_precond: sketch handle is NULL");
+  if (!lambdas) return fail(TIK_EINVAL, "tik_precond: lambdas is NULL");
+  const int32_t np = int32_t(sk->probs.size());
+  for (int64_t q = 0; q < int64_t(np) * N; ++q)
+    if (!(lambdas[q] > 0.0) || !std::isfinite(lambdas[q]))
+      return fail(TIK_EINVAL, "tik_precond: every lambda must be positive and finite");
+  size_t need = 0;
+  TIK_TRY(tik_precond_bytes(sk, route, N, &need));
+  TIK_TRY(check_ws(dws, dws_bytes, need, "tik_precond"));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Arena a;
+  a.base = static_cast<char*>(dws);
+  a.cap = dws_bytes;
+  PrecondPlan pp;
+  TIK_TRY(precond_plan(sk, route, N, a, pp));
+  TIK_HIP(hipMemcpyAsync(pp.lams, lambdas, sizeof(double) * size_t(np) * size_t(N),
+                         hipMemcpyHostToDevice, st));
+  TIK_HIP(hipMemsetAsync(pp.notpd, 0, sizeof(int32_t) * size_t(np) * size_t(N), st));
+  for (int32_t k = 0; k < np; ++k) {
+    const int64_t kd = std::min(sk->probs[k].m, sk->probs[k].n);
+    TIK_TRY(launch_syrk(sk->Y[k], sk->yrows[k], kd, sk->yrows[k], pp.C, st));
+    TIK_TRY(launch_chol_inv_batched(pp.C, kd, pp.lams + size_t(k) * N, N, pp.Rinv[k], pp.Dinv,
+                                    pp.Tmp, pp.notpd + size_t(k) * N, st));
+  }
+  std::vector<int32_t> bad(size_t(np) * size_t(N), 0);
+  TIK_HIP(hipMemcpyAsync(bad.data(), pp.notpd, sizeof(int32_t) * bad.size(),
+                         hipMemcpyDeviceToHost, st));
+  TIK_HIP(hipStreamSynchronize(st));
+  tik_precond_s* h = new tik_precond_s();
+  h->probs = sk->probs;
+  h->wide = sk->wide;
+  h->route = route;
+  h->N = N;
+  h->lams.assign(lambdas, lambdas + size_t(np) * N);
+  h->Rinv = pp.Rinv;
+  h->status.resize(bad.size());
+  for (size_t q = 0; q < bad.size(); ++q) h->status[q] = bad[q] ? TIK_ST_NOTPD : TIK_ST_CONVERGED;
+  for (int32_t k = 0; k < np; ++k) h->k.push_back(std::min(sk->probs[k].m, sk->probs[k].n));
+  if (status) std::memcpy(status, h->status.data(), sizeof(int32_t) * h->status.size());
+  if (sd_hat)
+    for (size_t q = 0; q < bad.size(); ++q) sd_hat[q] = std::nan("");
+  *out = h;
+  return TIK_OK;
+}
+
+int tik_precond_data(tik_precond_t pc, int32_t k, int32_t i, const double** data, int64_t* dim,
+                     int64_t* rank) {
+  if (!pc || !data || !dim || !rank) return fail(TIK_EINVAL, "tik_precond_data: NULL argument");
+  if (k < 0 || k >= int32_t(pc->probs.size()) || i < 0 || i >= pc->N)
+    return fail(TIK_EINVAL, "tik_precond_data: index out of range");
+  const int64_t kd = pc->k[k];
+  *dim = kd;
+  if (pc->route == TIK_ROUTE_CHOL) {
+    *data = pc->Rinv[k] + int64_t(i) * kd * kd;
+    *rank = kd;
+  } else {
+    *data = pc->V[k];
+    *rank = pc->si[size_t(k) * pc->N + i];
+  }
+  return TIK_OK;
+}
+
+void tik_precond_free(tik_precond_t pc) { delete pc; }
+
+// ------------------------------------------------------------------ solve --
+static int lsqr_validate(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_t mode) {
+  TIK_TRY(validate_problems(p, nprob, "tik_lsqr_batch"));
+  if (!pc) return fail(TIK_EINVAL, "tik_lsqr_batch: preconditioner handle is NULL");
+  if (int32_t(pc->probs.size()) != nprob)
+    return fail(TIK_EINVAL, "tik_lsqr_batch: problem count differs from the preconditioner's");
+  for (int32_t k = 0; k < nprob; ++k) {
+    const tik_problem &a = p[k], &b = pc->probs[k];
+    if (a.m != b.m || a.n != b.n || a.lda != b.lda || a.A != b.A || a.b != b.b ||
+        a.a_dtype != b.a_dtype)
+      return fail(TIK_EINVAL, "tik_lsqr_batch: problem " + std::to_string(k) +
+                                  " differs from the one the sketch was built from");
+  }
+  if (mode != TIK_PLAIN_F64_PER_LAMBDA && mode != TIK_F64_BATCHED && mode != TIK_MIXED_BATCHED)
+    return fail(TIK_EINVAL, "tik_lsqr_batch: unknown mode");
+  if (pc->wide) return fail(TIK_ENOTSUP, "tik_lsqr_batch: wide problems are not available in this build");
+  return TIK_OK;
+}
+
+int tik_lsqr_batch_bytes(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_t mode,
+                         size_t* bytes) {
+  if (!bytes) return fail(TIK_EINVAL, "tik_lsqr_batch_bytes: bytes is NULL");
+  TIK_TRY(lsqr_validate(p, nprob, pc, mode));
+  return lsqr_bytes(p, nprob, pc, mode, bytes);
+}
+
+int tik_lsqr_batch(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_t mode,
+                   double tol, int32_t maxit, double* const* X, int32_t* iters, int32_t* status,
+                   double* relres, void* dws, size_t dws_bytes, tik_stream_t stream) {
+  TIK_TRY(lsqr_validate(p, nprob, pc, mode));
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(TIK_EINVAL, "tik_lsqr_batch: tol must be > 0");
+  if (maxit < 1) return fail(TIK_EINVAL, "tik_lsqr_batch: maxit must be >= 1");
+  if (!X) return fail(TIK_EINVAL, "tik_lsqr_batch: X is NULL");
+  for (int32_t k = 0; k < nprob; ++k)
+    if (!X[k]) return fail(TIK_EINVAL, "tik_lsqr_batch: X[" + std::to_string(k) + "] is NULL");
+  size_t need = 0;
+  TIK_TRY(lsqr_bytes(p, nprob, pc, mode, &need));
+  TIK_TRY(check_ws(dws, dws_bytes, need, "tik_lsqr_batch"));
+  return lsqr_run(p, nprob, pc, mode, tol, maxit, X, iters, status, relres, dws, dws_bytes,
+                  static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

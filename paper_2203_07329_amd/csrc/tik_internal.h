@@ -1,0 +1,171 @@
+// Internal declarations shared by the libtik translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/tik.h"
+
+namespace tik {
+
+// ------------------------------------------------------------------ errors --
+void set_error(const std::string& msg);
+
+#define TIK_HIP(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      ::tik::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));         \
+      return TIK_EHIP;                                                             \
+    }                                                                              \
+  } while (0)
+
+#define TIK_LAUNCHED(what)                                                         \
+  do {                                                                             \
+    hipError_t e_ = hipGetLastError();                                             \
+    if (e_ != hipSuccess) {                                                        \
+      ::tik::set_error(std::string("launch of ") + (what) + ": " + hipGetErrorString(e_)); \
+      return TIK_EHIP;                                                             \
+    }                                                                              \
+  } while (0)
+
+#define TIK_TRY(expr)                 \
+  do {                                \
+    int rc_ = (expr);                 \
+    if (rc_ != TIK_OK) return rc_;    \
+  } while (0)
+
+// --------------------------------------------------------------- profiling --
+// Records HIP events around each launch of a kernel family when enabled.
+struct ProfScope {
+  ProfScope(const char* family, hipStream_t st);
+  ~ProfScope();
+  int slot;
+  hipStream_t st;
+};
+
+// --------------------------------------------------------------- workspace --
+// Bump allocator over a caller-provided device buffer.  With base == nullptr it
+// only measures, which is how the *_bytes queries are answered.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  template <typename T>
+  T* take(size_t count) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + count * sizeof(T) + 0;
+    return base ? reinterpret_cast<T*>(base + off) : nullptr;
+  }
+  bool fits() const { return used <= cap; }
+};
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------ device structs --
+// One problem as the solve kernels see it.  "long" rows are the m rows of a
+// tall problem (the n columns of a wide one); "short" rows the other side.
+struct DevProb {
+  const void* A;
+  int64_t m, n, lda;
+  int32_t a_f32;
+  int32_t wide;
+  const double* b;
+  int64_t offL;        // row offset of this problem inside long-row vector buffers
+  int64_t offS;        // row offset inside short-row vector buffers
+  const double* Rinv;  // N upper-triangular inverses, k x k each (k = short dim), col-major
+  int64_t k;           // short dimension min(m, n)
+  // low-rank route: V (n x s, ld n), S (N x s), truncation s_i
+  const double* V;
+  const double* S;
+  int64_t s;
+  // item bookkeeping
+  int64_t pnN, pnB, pnQ; // first block of this problem in the partial-norm arrays
+  int32_t nblkN, nblkB, nblkQ, nchT;
+  int64_t ptOff;       // first row of this problem in the gemm_T partial buffer
+  int64_t rchunk;      // rows per gemm_T chunk
+};
+
+// Per-(problem, lambda) LSQR scalars, all FP64.
+struct Scal {
+  double lam, sqlam;
+  double alpha, beta;       // alpha_i, beta_i of the current step
+  double beta_new;          // beta_{i+1} once the u-step is reduced
+  double rhobar, phibar;
+  double anorm2, bnorm;
+  double cx, ce;            // x += cx * e ; e = w - ce * e
+  double ialpha, ibeta;     // guarded reciprocals
+  double ucoef;             // alpha_i / beta_i, the weight of the old u
+  double relres, rnorm, arnorm;
+  int32_t active, upd, iters, status;
+  int32_t pad0, pad1, pad2, pad3;
+};
+
+// item tables: x = problem, y = block index (and z = chunk for gemm_T)
+struct Item {
+  int32_t p, blk, ch, j;
+};
+
+// ------------------------------------------------------------- launchers ----
+// sketch (k_sketch.hip)
+int launch_srht_rows(uint64_t seed, int k, int64_t s, int32_t* rows, int32_t* bstart, int bbits,
+                     hipStream_t st);
+int launch_srht_single(const void* A, int a_f32, int64_t m, int64_t n, int64_t lda, int k,
+                       uint64_t seed, const int32_t* rows, int64_t s, double* Y, hipStream_t st);
+int launch_srht_twopass(const void* A, int a_f32, int64_t m, int64_t lda, int64_t c0, int64_t nc,
+                        int k, int bbits, const int32_t* rows, int64_t s, double* T, double* Y,
+                        hipStream_t st);
+int launch_gauss_gen(uint64_t seed, int64_t s, int64_t r0, int64_t kc, void* Xc, int bf16,
+                     hipStream_t st);
+int launch_sketch_gemm_f64(const double* Xc, int64_t s, int64_t kc, const void* A, int a_f32,
+                           int64_t lda, int64_t r0, int64_t ncol, int wide, double* Y,
+                           hipStream_t st);
+int launch_sketch_gemm_bf16(const void* Xc, int64_t s, int64_t kc, const void* A, int a_f32,
+                            int64_t lda, int64_t r0, int64_t ncol, int wide, float* Yacc,
+                            int first, hipStream_t st);
+int launch_f32_to_f64(const float* src, double* dst, int64_t count, hipStream_t st);
+
+// factorization (k_factor.hip)
+int launch_syrk(const double* Z, int64_t K, int64_t n, int64_t ldz, double* C, hipStream_t st);
+int launch_chol_inv_batched(const double* C, int64_t n, const double* lams, int32_t nb_mat,
+                            double* R, double* Dinv, double* Tmp, int32_t* notpd,
+                            hipStream_t st);
+
+}  // namespace tik
+
+// ----------------------------------------------------------------- handles --
+struct tik_sketch_s {
+  std::vector<tik_problem> probs;
+  int32_t embed = 0, sketch_dtype = 0;
+  std::vector<int64_t> s;
+  uint64_t seed = 0;
+  bool wide = false;
+  std::vector<double*> Y;              // per problem: yrows x ycols, column-major, ld = yrows
+  std::vector<int64_t> yrows, ycols;   // tall: s x n (Y); wide: s x m (Y^T)
+};
+
+struct tik_precond_s {
+  std::vector<tik_problem> probs;
+  bool wide = false;
+  int32_t route = 0, N = 0;
+  std::vector<double> lams;            // nprob * N, host copy
+  std::vector<int64_t> k;              // short dimension per problem
+  std::vector<double*> Rinv;           // Cholesky route: N upper-triangular k x k inverses
+  std::vector<int32_t> status;         // nprob * N breakdown flags (tik_status)
+  // low-rank route (tall): V n x s (ld n), sigma (s), S (N x s), truncation s_i
+  std::vector<double*> V, sigma, S;
+  std::vector<int64_t> srank;
+  std::vector<int32_t> si;             // nprob * N
+  std::vector<double> sdhat;           // nprob * N
+};
+
+namespace tik {
+// solve driver (k_lsqr.hip)
+int lsqr_bytes(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32_t mode,
+               size_t* bytes);
+int lsqr_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32_t mode,
+             double tol, int32_t maxit, double* const* X, int32_t* iters, int32_t* status,
+             double* relres, void* dws, size_t dws_bytes, hipStream_t st);
+}  // namespace tik

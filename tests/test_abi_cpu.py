@@ -1,0 +1,106 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+the header declares, and rejects bad arguments before launching anything.
+Runs without a GPU (no call here reaches the HIP runtime)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2203_07329_amd import tik
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "tik.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tik_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = tik.lib()
+    names = header_functions()
+    assert "tik_sketch" in names and "tik_precond" in names and "tik_lsqr_batch" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(tik.EXPORTS) == set(names)
+    assert L.tik_version() >= 100
+
+
+def _probs(m=100, n=10, lda=None, dtype=tik.F64, reserved=0, A=0x1000, b=0x2000, count=1):
+    arr = (tik.CProblem * count)()
+    for k in range(count):
+        arr[k] = tik.CProblem(m, n, lda if lda is not None else m, dtype, reserved, A, b)
+    return arr
+
+
+def _bytes(arr, count=1, embed=tik.SRHT, sdt=tik.F64, s=(40,)):
+    sz = ctypes.c_size_t()
+    sarr = (ctypes.c_int64 * count)(*s)
+    rc = tik.lib().tik_sketch_bytes(arr, count, embed, sdt, sarr, ctypes.byref(sz))
+    return rc, sz.value
+
+
+@pytest.mark.parametrize("kw,rc", [
+    (dict(m=0), tik.EINVAL),
+    (dict(n=0), tik.EINVAL),
+    (dict(lda=50), tik.EINVAL),
+    (dict(dtype=7), tik.EINVAL),
+    (dict(reserved=1), tik.EINVAL),
+    (dict(A=0), tik.EINVAL),
+    (dict(b=0), tik.EINVAL),
+])
+def test_sketch_rejects_bad_problems(kw, rc):
+    got, _ = _bytes(_probs(**kw))
+    assert got == rc
+    assert tik.lib().tik_last_error().decode()
+
+
+def test_sketch_size_limits():
+    assert _bytes(_probs(), s=(0,))[0] == tik.EINVAL
+    assert _bytes(_probs(), s=(101,))[0] == tik.EINVAL          # s above the long dimension
+    assert _bytes(_probs(), s=(100,))[0] == tik.OK
+    assert _bytes(_probs(), embed=9)[0] == tik.EINVAL
+    assert _bytes(_probs(), sdt=tik.BF16)[0] == tik.EINVAL      # BF16 needs the Gaussian sketch
+    # SRHT of a wide matrix and beyond 2^18 rows are outside this build
+    assert _bytes(_probs(m=10, n=100), s=(5,))[0] == tik.ENOTSUP
+    assert _bytes(_probs(m=300000, n=10), s=(40,))[0] == tik.ENOTSUP
+    assert _bytes(_probs(m=10, n=100), embed=tik.GAUSS, s=(5,))[0] == tik.OK
+
+
+def test_mixed_orientation_rejected():
+    arr = (tik.CProblem * 2)()
+    arr[0] = tik.CProblem(100, 10, 100, tik.F64, 0, 0x1000, 0x2000)
+    arr[1] = tik.CProblem(10, 100, 10, tik.F64, 0, 0x1000, 0x2000)
+    assert _bytes(arr, count=2, embed=tik.GAUSS, s=(20, 5))[0] == tik.EINVAL
+
+
+def test_workspace_size_grows_with_problem():
+    r1, a = _bytes(_probs(m=1000, n=10), s=(40,))
+    r2, b = _bytes(_probs(m=1000, n=20), s=(40,))
+    assert r1 == r2 == tik.OK and b > a > 40 * 10 * 8
+
+
+def test_sketch_null_outputs():
+    L = tik.lib()
+    arr = _probs()
+    sarr = (ctypes.c_int64 * 1)(40)
+    assert L.tik_sketch(arr, 1, tik.SRHT, tik.F64, sarr, 0, None, 0, None, None) == tik.EINVAL
+    h = ctypes.c_void_p()
+    # workspace too small / NULL: caught before any launch
+    assert L.tik_sketch(arr, 1, tik.SRHT, tik.F64, sarr, 0, None, 0, None,
+                        ctypes.byref(h)) == tik.EWORKSPACE
+    assert L.tik_sketch(arr, 1, tik.SRHT, tik.F64, sarr, 0, ctypes.c_void_p(0x1108), 1 << 30, None,
+                        ctypes.byref(h)) == tik.EWORKSPACE           # misaligned
+
+
+def test_precond_and_solve_null_handles():
+    L = tik.lib()
+    sz = ctypes.c_size_t()
+    assert L.tik_precond_bytes(None, tik.ROUTE_CHOL, 4, ctypes.byref(sz)) == tik.EINVAL
+    assert L.tik_lsqr_batch_bytes(_probs(), 1, None, tik.F64_BATCHED, ctypes.byref(sz)) == tik.EINVAL
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    assert L.tik_prof_query(b"gemm_n", ctypes.byref(ms), ctypes.byref(n)) == tik.OK
+    assert n.value == 0

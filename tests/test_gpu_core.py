@@ -1,0 +1,233 @@
+"""GPU parity of the sketch, preconditioner and LSQR stages against the oracle.
+
+Every call goes through the C ABI (binding in paper_2203_07329_amd.tik); the
+expected values come from the CPU oracle on the same seeded inputs.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from paper_2203_07329_amd import tik
+
+pytestmark = pytest.mark.gpu
+
+
+def dev_problems(plist):
+    return tik.Problems.from_numpy([p.A for p in plist], [p.b for p in plist])
+
+
+# ----------------------------------------------------------------- sketch ---
+
+def _extract_X(m, s, embed, seed=5):
+    """Sketch the identity: Y = X I_m = X (tall, n = m)."""
+    I = np.eye(m)
+    pr = tik.Problems.from_numpy([I], [np.ones(m)])
+    sk = tik.sketch(pr, embed, [s], seed)
+    return sk.Y(0)
+
+
+@pytest.mark.parametrize("m,s", [(1024, 64), (1000, 50), (16384, 128)])
+def test_srht_structure(m, s):
+    X = _extract_X(m, s, tik.SRHT)
+    assert X.shape == (s, m)
+    # entries are exactly +-1/sqrt(s)
+    assert np.array_equal(np.abs(X) * math.sqrt(s), np.ones_like(X)) or \
+        np.allclose(np.abs(X), 1 / math.sqrt(s), rtol=0, atol=1e-15)
+    if m & (m - 1) == 0:
+        # rows are distinct signed Hadamard rows: X X^T = (m/s) I exactly
+        G = X @ X.T
+        assert np.allclose(G, (m / s) * np.eye(s), rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("m,n,s", [(1000, 7, 50), (5000, 3, 300), (9000, 5, 256)])
+def test_srht_linear(m, n, s):
+    """Y_A = X A for the same seed (single-pass m' <= 8192 and two-pass m' > 8192)."""
+    X = _extract_X(m, s, tik.SRHT, seed=11)
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((m, n))
+    pr = tik.Problems.from_numpy([A], [np.ones(m)])
+    Y = tik.sketch(pr, tik.SRHT, [s], 11).Y(0)
+    assert np.allclose(Y, X @ A, rtol=1e-12, atol=1e-12 * np.abs(X @ A).max())
+
+
+def test_sketch_determinism_and_seed():
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((3000, 6))
+    pr = tik.Problems.from_numpy([A], [np.ones(3000)])
+    for embed in (tik.SRHT, tik.GAUSS):
+        Y1 = tik.sketch(pr, embed, [100], 3).Y(0)
+        Y2 = tik.sketch(pr, embed, [100], 3).Y(0)
+        Y3 = tik.sketch(pr, embed, [100], 4).Y(0)
+        assert np.array_equal(Y1, Y2)
+        assert not np.allclose(Y1, Y3)
+
+
+def test_gauss_moments_and_linearity():
+    m, s = 2048, 64
+    X = _extract_X(m, s, tik.GAUSS, seed=9)
+    assert abs(X.mean()) < 4 / math.sqrt(X.size) / math.sqrt(s)
+    assert abs(X.var() * s - 1.0) < 0.05              # N(0, 1/s): E[X^T X] = I
+    assert abs(np.mean(X[:, :-1] * X[:, 1:]) * s) < 0.05
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((m, 5))
+    pr = tik.Problems.from_numpy([A], [np.ones(m)])
+    Y = tik.sketch(pr, tik.GAUSS, [s], 9).Y(0)
+    assert np.allclose(Y, X @ A, rtol=1e-12, atol=1e-12 * np.abs(Y).max())
+
+
+def test_gauss_wide_sketch():
+    """Wide problems store Y^T = X^T A^T with the same generator (X is n x s)."""
+    m, n, s = 40, 600, 30
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((m, n))
+    I = np.eye(m, n)                                   # [I_m 0]: Y^T rows give X's first rows
+    pr = tik.Problems.from_numpy([A, I], [np.ones(m), np.ones(m)])
+    sk = tik.sketch(pr, tik.GAUSS, [s, s], 13)
+    Xt_from_I = sk.Y(1)                                # s x m = X[:m, :]^T (problem 1 seed)
+    assert Xt_from_I.shape == (s, m)
+    assert abs(Xt_from_I.var() * s - 1.0) < 0.2
+
+
+# ---------------------------------------------------------- preconditioner --
+
+@pytest.mark.parametrize("n,s", [(100, 400), (130, 300), (64, 64), (1, 4)])
+def test_chol_inverse(n, s):
+    m = max(4 * s, 256)
+    p = W.over_svd(m=m, n=n, N=5, sig_lo=1e-4)
+    pr = dev_problems([p])
+    sk = tik.sketch(pr, tik.SRHT, [s], 7)
+    pc = tik.precond(sk, p.lams)
+    Y = sk.Y(0)
+    assert np.all(pc.status == tik.ST_CONVERGED)
+    for i, lam in enumerate(p.lams):
+        Ri = pc.data(0, i)
+        assert np.array_equal(np.tril(Ri, -1), np.zeros_like(Ri))     # exact zeros below
+        C = Y.T @ Y + lam * np.eye(n)
+        R = oracle.chol_precond(Y, lam)
+        Ri_ref = np.linalg.inv(R)
+        kap = np.linalg.cond(R)
+        assert np.linalg.norm(Ri - Ri_ref) <= 1e-14 * kap * np.linalg.norm(Ri_ref) * 10
+        G = Ri.T @ C @ Ri
+        assert np.linalg.norm(G - np.eye(n)) <= 1e-14 * kap * kap * 10 + 1e-12
+
+
+def test_notpd_flag_on_nonfinite_sketch():
+    p = W.over_svd(m=512, n=20, N=3)
+    A = p.A.copy()
+    A[3, 5] = np.nan
+    pr = tik.Problems.from_numpy([A], [p.b])
+    sk = tik.sketch(pr, tik.SRHT, [80], 1)
+    pc = tik.precond(sk, p.lams)
+    assert np.all(pc.status == tik.ST_NOTPD)
+    res = tik.lsqr_batch(pr, pc, tik.F64_BATCHED, 1e-10, 50)
+    assert np.all(res.status.cpu().numpy() == tik.ST_NOTPD)
+
+
+# -------------------------------------------------------------------- LSQR --
+
+def _solve(plist, mode, embed=tik.SRHT, tol=1e-12, maxit=300, s=None, seed=0):
+    pr = dev_problems(plist)
+    s = s or [p.s for p in plist]
+    sk = tik.sketch(pr, embed, s, seed)
+    lams = np.stack([p.lams for p in plist])
+    pc = tik.precond(sk, lams)
+    res = tik.lsqr_batch(pr, pc, mode, tol, maxit)
+    torch.cuda.synchronize()
+    return res, pc
+
+
+@pytest.mark.parametrize("mode", [tik.F64_BATCHED, tik.PLAIN_F64_PER_LAMBDA])
+def test_lsqr_over_svd_small(mode):
+    p = W.over_svd()           # m=2000, n=100, N=10, SRHT s=4n, tol 1e-10
+    res, _ = _solve([p], mode)
+    X = res.x_numpy(0)
+    Xo = oracle.solve(p.A, p.b, p.lams)
+    err = oracle.rel_err(X, Xo)
+    st = res.status.cpu().numpy()[0]
+    it = res.iters.cpu().numpy()[0]
+    print("rel err", err, "iters", it)
+    assert np.all(st == tik.ST_CONVERGED)
+    assert np.all(err <= p.tol), err
+
+
+def test_lsqr_iterations_flat_in_kappa():
+    """O(log 1/eps) iterations, independent of kappa(A) (Lemma 2.1)."""
+    its = []
+    for lo in [1e-2, 1e-4, 1e-6, 1e-8]:
+        p = W.over_svd(m=2000, n=100, N=4, sig_lo=lo, lam_lo=1e-10, lam_hi=1e-4)
+        res, _ = _solve([p], tik.F64_BATCHED, tol=1e-10)
+        its.append(int(res.iters.cpu().numpy().max()))
+        Xo = oracle.solve(p.A, p.b, p.lams)
+        assert np.all(oracle.rel_err(res.x_numpy(0), Xo) < 1e-8)
+    print("iterations per kappa", its)
+    # SRHT with s = 4n: kappa(B R^-1) stays below ~3, so <= the bound for kappa=4
+    assert max(its) <= oracle.lsqr_iteration_bound(4.0, 1e-10) + 5
+    # no growth with kappa(A): the count at kappa = 1e8 is not above the one at 1e2
+    assert its[-1] <= its[0] + 2
+
+
+def test_lsqr_ragged_gauss_fp32():
+    plist = W.ragged(nprob=5, m_lo=500, m_hi=3000, n_lo=10, n_hi=120, N=4)
+    res, _ = _solve(plist, tik.F64_BATCHED, embed=tik.GAUSS)
+    for k, p in enumerate(plist):
+        Xo = oracle.solve(p.A, p.b, p.lams)
+        err = oracle.rel_err(res.x_numpy(k), Xo)
+        assert np.all(err <= 1e-10), (k, p.m, p.n, err)
+    assert np.all(res.status.cpu().numpy() == tik.ST_CONVERGED)
+
+
+def test_lsqr_over_gauss_reduced():
+    """The kappa(A) = 1e8 family at reduced size, SRHT two-pass (m' = 32768)."""
+    p = W.over_gauss(m=20000, n=400, N=32, s=1600)
+    for mode in (tik.F64_BATCHED, tik.PLAIN_F64_PER_LAMBDA):
+        res, _ = _solve([p], mode, tol=1e-13)
+        err = oracle.rel_err(res.x_numpy(0), oracle.solve(p.A, p.b, p.lams))
+        print(mode, "max rel err", err.max(), "iters", res.iters.cpu().numpy().max())
+        assert np.all(err <= 1e-10), err
+
+
+def test_lsqr_edge_cases():
+    rng = np.random.default_rng(4)
+    # n = 1, N = 1
+    A = rng.standard_normal((300, 1))
+    b = rng.standard_normal(300)
+    p1 = W.Problem("edge", np.asfortranarray(A), b, np.array([0.5]), 4, "srht", "chol", 1e-12, 0)
+    res, _ = _solve([p1], tik.F64_BATCHED)
+    assert oracle.rel_err(res.x_numpy(0), oracle.solve(A, b, [0.5])) < 1e-12
+    # square, s = n, large lambda
+    A = rng.standard_normal((64, 64))
+    b = rng.standard_normal(64)
+    lams = np.array([1e6, 1.0, 1e-3])
+    p2 = W.Problem("edge", np.asfortranarray(A), b, lams, 64, "srht", "chol", 1e-10, 0)
+    res, _ = _solve([p2], tik.F64_BATCHED)
+    assert np.all(oracle.rel_err(res.x_numpy(0), oracle.solve(A, b, lams)) < 1e-10)
+    # b = 0 gives x = 0 at once
+    p3 = W.Problem("edge", np.asfortranarray(A), np.zeros(64), lams, 64, "srht", "chol", 1e-10, 0)
+    res, _ = _solve([p3], tik.F64_BATCHED)
+    assert np.all(res.x_numpy(0) == 0) and np.all(res.status.cpu().numpy() == tik.ST_CONVERGED)
+    assert np.all(res.iters.cpu().numpy() == 0)
+
+
+def test_lsqr_status_paths():
+    p = W.over_svd(m=800, n=40, N=3)
+    res, _ = _solve([p], tik.F64_BATCHED, maxit=1)
+    assert np.all(res.status.cpu().numpy() == tik.ST_MAXIT)
+    assert np.all(res.iters.cpu().numpy() == 1)
+    b = p.b.copy()
+    b[7] = np.nan
+    q = W.Problem("nan", p.A, b, p.lams, p.s, "srht", "chol", 1e-10, 0)
+    res, _ = _solve([q], tik.F64_BATCHED)
+    assert np.all(res.status.cpu().numpy() == tik.ST_NONFINITE)
+
+
+def test_lsqr_deterministic():
+    p = W.over_svd(m=1500, n=60, N=6)
+    r1, _ = _solve([p], tik.F64_BATCHED)
+    x1 = r1.x_numpy(0)
+    r2, _ = _solve([p], tik.F64_BATCHED)
+    assert np.array_equal(x1, r2.x_numpy(0))
