@@ -1,0 +1,218 @@
+"""Benchmark: lambda-solves/s of sketch-preconditioned Tikhonov least squares.
+
+One step = the whole hot path for one batch: sketch A once (SRHT), build the
+32 preconditioners, run preconditioned LSQR for all 32 lambdas.  The default
+workload is the tall kappa(A) = 1e8 problem (m = 200000, n = 2000, N = 32,
+lambda in [1e-8, 1e-1], sketch size 4n).  A and b are resident on the GPU
+before timing starts.
+
+value = (number of lambdas whose solution is within 1e-8 relative error of
+the CPU FP64 oracle) / (seconds per step), for the batched solve; the plain
+FP64 per-lambda loop is timed beside it.  roofline: the dominant kernel's
+algorithmic bytes per launch over its average launch time, from HIP events
+recorded by the library around every launch during the timed steps.
+cpu_baseline: the oracle itself (direct Householder-QR route), timed on the
+host while it produces the reference solutions.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "λ-solves/s to 1e-8 rel err: mixed batched vs plain FP64; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+TOL_ERR = 1e-8
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--m", type=int, default=200000)
+    ap.add_argument("--n", type=int, default=2000)
+    ap.add_argument("--N", type=int, default=32)
+    ap.add_argument("--mode", default="auto", choices=["auto", "mixed", "f64"])
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--no-oracle", action="store_true", help="skip the oracle (profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of "
+              "this path is described in DESIGN.md but not built", file=sys.stderr)
+        return 2
+
+    import torch
+    import workloads as W
+    from paper_2203_07329_amd import tik
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    p = W.over_gauss(m=args.m, n=args.n, N=args.N)
+    log(f"generated A {p.m}x{p.n} in {time.perf_counter() - t0:.1f}s")
+    pr = tik.Problems.from_numpy([p.A], [p.b], device=dev)
+    torch.cuda.synchronize()
+
+    mode = tik.F64_BATCHED
+    dtype = "f64"
+    if args.mode in ("auto", "mixed"):
+        try:
+            sk = tik.sketch(pr, tik.SRHT, [p.s], 0)
+            pc = tik.precond(sk, p.lams)
+            tik.Solver(pr, pc, tik.MIXED_BATCHED)
+            mode, dtype = tik.MIXED_BATCHED, "f32+f64"
+        except tik.TikError as e:
+            if args.mode == "mixed":
+                raise
+            log("mixed mode unavailable, timing FP64 batched:", e)
+    tol = 1e-11 if mode == tik.F64_BATCHED else 1e-8
+    maxit = 300
+
+    def one_step(m_):
+        sk = tik.sketch(pr, tik.SRHT, [p.s], 0)
+        pc = tik.precond(sk, p.lams)
+        res = tik.Solver(pr, pc, m_)(tol if m_ != tik.PLAIN_F64_PER_LAMBDA else 1e-11, maxit)
+        return res
+
+    # ---- warmup
+    for _ in range(args.warmup):
+        one_step(mode)
+    torch.cuda.synchronize()
+
+    # ---- timed steps (per-kernel events on)
+    tik.prof_reset()
+    tik.prof_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    w0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = one_step(mode)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    tik.prof_enable(False)
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    fam = {}
+    for f in ("sketch", "gram", "chol", "trinv", "gemm_n", "gemm_t", "trmv", "trmv_t", "vec",
+              "residual", "lowrank"):
+        ms, n = tik.prof_query(f)
+        if n:
+            fam[f] = (ms / args.steps, n // args.steps, ms / n)
+    X = res.x_numpy(0)
+    iters = res.iters.cpu().numpy()[0]
+    status = res.status.cpu().numpy()[0]
+
+    # ---- plain FP64 per-lambda loop
+    plain = None
+    if args.plain_steps > 0:
+        torch.cuda.synchronize()
+        q0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            rp = one_step(tik.PLAIN_F64_PER_LAMBDA)
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - q0) * 1000.0 / args.plain_steps
+        plain = {"ms_per_step": plain_ms, "X": rp.x_numpy(0), "iters": rp.iters.cpu().numpy()[0]}
+
+    # ---- oracle (timed: the CPU baseline) and accuracy
+    out = {}
+    n_ok = p.lams.size
+    err = None
+    cpu = None
+    if not args.no_oracle:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [os.cpu_count()])
+        except Exception:  # pragma: no cover
+            cores = os.cpu_count()
+        c0 = time.perf_counter()
+        Xo = oracle.solve(p.A, p.b, p.lams)
+        tcpu = time.perf_counter() - c0
+        err = oracle.rel_err(X, Xo)
+        n_ok = int(np.sum(err <= TOL_ERR))
+        cpu = {"value": p.lams.size / tcpu, "unit": "λ-solves/s", "cores": int(cores),
+               "kind": "oracle",
+               "sample": f"full workload: Householder QR of the {p.m}x{p.n} A once plus "
+                         f"{p.lams.size} per-lambda QR solves ({tcpu:.1f} s)"}
+        if plain is not None:
+            perr = oracle.rel_err(plain["X"], Xo)
+            plain["n_ok"] = int(np.sum(perr <= TOL_ERR))
+            plain["max_rel_err"] = float(perr.max())
+    value = n_ok / (ms_step / 1000.0)
+
+    # ---- roofline of the dominant kernel family
+    dom = max(fam.items(), key=lambda kv: kv[1][0]) if fam else None
+    roof = None
+    if dom:
+        name, (ms_per_step, launches, avg_ms) = dom
+        a_bytes = (8 if p.A.dtype == np.float64 else 4) if mode != tik.MIXED_BATCHED else 4
+        N = p.lams.size
+        per_launch = {
+            # A once, plus the N-wide long vector read and written (gemm_n) or read (gemm_t)
+            "gemm_n": p.m * p.n * a_bytes + 2 * p.m * N * (8 if mode != tik.MIXED_BATCHED else 4),
+            "gemm_t": p.m * p.n * a_bytes + p.m * N * (8 if mode != tik.MIXED_BATCHED else 4),
+            "trmv": N * p.n * p.n * 4,       # upper triangles of all N inverses (8 B, half)
+            "trmv_t": N * p.n * p.n * 4,
+        }.get(name)
+        if per_launch:
+            ach = per_launch / (avg_ms / 1000.0) / 1e9
+            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                    "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": per_launch}
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "λ-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": f"tall Gaussian, sigma logspaced 1..1e-8: m={p.m} n={p.n} N={p.lams.size} "
+                               f"lambda 1e-8..1e-1, SRHT s={p.s}, Cholesky route",
+                   "mode": {tik.F64_BATCHED: "f64_batched", tik.MIXED_BATCHED: "mixed_batched"}[mode],
+                   "tol": tol},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "solves_ok": n_ok,
+        "max_rel_err": None if err is None else float(np.max(err)),
+        "iters_max": int(iters.max()),
+        "status_ok": bool(np.all(status <= 1)),
+        "phases_ms_per_step": {k: round(v[0], 3) for k, v in fam.items()},
+        "launches_per_step": {k: v[1] for k, v in fam.items()},
+        "wall_s_timed": round(wall, 3),
+    }
+    if plain is not None:
+        pv = plain.get("n_ok", p.lams.size) / (plain["ms_per_step"] / 1000.0)
+        line["plain_f64_per_lambda"] = {"value": round(pv, 3), "ms_per_step": round(plain["ms_per_step"], 2),
+                                        "max_rel_err": plain.get("max_rel_err"),
+                                        "iters_max": int(plain["iters"].max())}
+        line["speedup_vs_plain"] = round(value / pv, 2) if pv > 0 else None
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -340,6 +340,44 @@ __global__ void __launch_bounds__(256) k_trinv_fin(double* __restrict__ R, int64
     }
 }
 
+// Column absolute sums of the symmetric Gram matrix C (k x k): their maximum
+// bounds ||C||_2 from above (Gershgorin), which bounds kappa(B)^2 by
+// (||C|| + lambda) / lambda for the sketched B = [XA; sqrt(lambda) I].
+__global__ void __launch_bounds__(256) k_col_abs_sum(const double* __restrict__ C, int64_t n,
+                                                     double* __restrict__ out) {
+  __shared__ double red[4];
+  const int64_t c = blockIdx.x;
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += 256) s += fabs(C[r + c * n]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[c] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(256) k_max_reduce(const double* __restrict__ v, int64_t n,
+                                                    double* __restrict__ out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s = fmax(s, v[i]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s = fmax(s, __shfl_xor(s, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+int launch_gram_norm_bound(const double* C, int64_t n, double* scratch, double* out,
+                           hipStream_t st) {
+  ProfScope ps("gram", st);
+  hipLaunchKernelGGL(k_col_abs_sum, dim3(unsigned(n)), dim3(256), 0, st, C, n, scratch);
+  TIK_LAUNCHED("k_col_abs_sum");
+  hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, st, scratch, n, out);
+  TIK_LAUNCHED("k_max_reduce");
+  return TIK_OK;
+}
+
 // ---------------------------------------------------------------- launchers --
 int launch_syrk(const double* Z, int64_t K, int64_t n, int64_t ldz, double* C, hipStream_t st) {
   const int nt = int(cdiv(n, 64));

@@ -27,6 +27,9 @@
 // lambda-major so the transposed triangular product reads it contiguously.
 #include "tik_internal.h"
 
+#include <algorithm>
+#include <type_traits>
+
 namespace tik {
 
 static constexpr int BLK = 256;
@@ -323,35 +326,47 @@ __global__ void __launch_bounds__(BLK) k_gemm_t(const DevProb* __restrict__ P,
 // ------------------------------------------------------------- reduce_t ----
 // EPI 0: t[i][c] = (sum_ch part + sqrt(lam) u~_bot[c, i]) / beta, lambda-major.
 // EPI 1: out[c, i] = sum_ch part - lam x[c, i] (row-major; FP64 gradient).
-template <typename TC, int EPI>
+// One thread per (row c, lambda i): 256 / NC rows per block.
+template <typename TC, int EPI, int NC>
 __global__ void __launch_bounds__(BLK) k_reduce_t(const DevProb* __restrict__ P,
                                                   const Item* __restrict__ items, int N,
                                                   const TC* __restrict__ part,
                                                   const double* __restrict__ ub,
                                                   const Scal* __restrict__ sc,
                                                   double* __restrict__ t) {
+  constexpr int RR = BLK / NC;
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
   const int64_t n = pr.n;
-  for (int e = threadIdx.x; e < BLK * N; e += BLK) {
-    const int64_t c = int64_t(it.blk) * BLK + e / N;
-    const int i = e % N;
-    if (c >= n) continue;
-    double s = 0.0;
-    const TC* src = part + (pr.ptOff * N) + c * N + i;
-    for (int ch = 0; ch < pr.nchT; ++ch) s += double(src[int64_t(ch) * n * N]);
-    const Scal& S = sc[it.p * N + i];
-    if (EPI == 0) {
-      t[pr.offS * N + int64_t(i) * n + c] = (s + S.sqlam * ub[(pr.offS + c) * N + i]) * S.ibeta;
-    } else {
-      t[(pr.offS + c) * N + i] = s - S.lam * ub[(pr.offS + c) * N + i];
-    }
+  const int64_t c = int64_t(it.blk) * RR + threadIdx.x / NC;
+  const int i = threadIdx.x % NC;
+  if (c >= n || i >= N) return;
+  double s = 0.0;
+  const TC* src = part + (pr.ptOff + c) * N + i;
+  const int64_t stride = n * N;
+  int ch = 0;
+  for (; ch + 3 < pr.nchT; ch += 4) {
+    const double a0 = double(src[int64_t(ch) * stride]), a1 = double(src[int64_t(ch + 1) * stride]);
+    const double a2 = double(src[int64_t(ch + 2) * stride]), a3 = double(src[int64_t(ch + 3) * stride]);
+    s += a0;
+    s += a1;
+    s += a2;
+    s += a3;
+  }
+  for (; ch < pr.nchT; ++ch) s += double(src[int64_t(ch) * stride]);
+  const Scal& S = sc[it.p * N + i];
+  if (EPI == 0) {
+    t[pr.offS * N + int64_t(i) * n + c] = (s + S.sqlam * ub[(pr.offS + c) * N + i]) * S.ibeta;
+  } else {
+    t[(pr.offS + c) * N + i] = s - S.lam * ub[(pr.offS + c) * N + i];
   }
 }
 
 // --------------------------------------------------------------- trmv_t ----
-// v~[c] = sum_{r <= c} Rinv[r, c] t[r] - beta v[c] for a 64-column block of one
-// (problem, lambda); each wave owns 16 columns, lanes stride the rows.
+// v~[c] = sum_{r <= c} Rinv[r, c] t[r] - beta v[c] for a block of 4 * CPW
+// columns of one (problem, lambda); each wave owns CPW columns, lanes stride
+// the rows (coalesced along the columns of Rinv and along t).
+template <int CPW>
 __global__ void __launch_bounds__(BLK) k_trmv_t(const DevProb* __restrict__ P,
                                                 const Item* __restrict__ items, int N,
                                                 const double* __restrict__ t,
@@ -364,18 +379,18 @@ __global__ void __launch_bounds__(BLK) k_trmv_t(const DevProb* __restrict__ P,
   const int j = it.j, p = it.p, i = j % N;
   const DevProb& pr = P[p];
   const int64_t k = pr.k;
-  const double* __restrict__ R = pr.Rinv + int64_t(i) * k * k;
+  const double* __restrict__ R = pr.Rinv + int64_t(sc[j].li) * k * k;
   const double* __restrict__ tv = t + pr.offS * N + int64_t(i) * k;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t cbase = int64_t(it.blk) * 64 + wv * 16;
-  double acc[16];
+  const int64_t cbase = int64_t(it.blk) * (4 * CPW) + wv * CPW;
+  double acc[CPW];
 #pragma unroll
-  for (int q2 = 0; q2 < 16; ++q2) acc[q2] = 0.0;
-  const int64_t clast = min(k - 1, cbase + 15);
+  for (int q2 = 0; q2 < CPW; ++q2) acc[q2] = 0.0;
+  const int64_t clast = min(k - 1, cbase + CPW - 1);
   for (int64_t r = lane; r <= clast; r += 64) {
     const double tr = tv[r];
 #pragma unroll
-    for (int q2 = 0; q2 < 16; ++q2) {
+    for (int q2 = 0; q2 < CPW; ++q2) {
       const int64_t c = cbase + q2;
       if (c < k && r <= c) acc[q2] = fma(R[r + c * k], tr, acc[q2]);
     }
@@ -383,7 +398,7 @@ __global__ void __launch_bounds__(BLK) k_trmv_t(const DevProb* __restrict__ P,
   const Scal& S = sc[j];
   double nrm = 0.0;
 #pragma unroll
-  for (int q2 = 0; q2 < 16; ++q2) {
+  for (int q2 = 0; q2 < CPW; ++q2) {
     const double s = warp_sum(acc[q2]);
     const int64_t c = cbase + q2;
     if (c < k) {
@@ -497,41 +512,45 @@ __global__ void __launch_bounds__(BLK) k_fin_alpha(const DevProb* __restrict__ P
 
 // ----------------------------------------------------------------- trmv ----
 // w[r] = ialpha sum_{c >= r} Rinv[r, c] v~[c]; v = ialpha v~; x, e updates.
-// 256 threads = 64 rows x 4 column slices.
+// 256 threads = 16 rows x 16 column slices; a wave reads 16 consecutive rows
+// of 4 columns (full 128-byte lines) per load.
 __global__ void __launch_bounds__(BLK) k_trmv(const DevProb* __restrict__ P,
                                               const Item* __restrict__ items, int N,
                                               const double* __restrict__ q,
                                               double* __restrict__ v, double* __restrict__ w,
                                               double* __restrict__ x, double* __restrict__ e,
                                               const Scal* __restrict__ sc, int init) {
-  __shared__ double red[4][64];
+  __shared__ double red[16][17];
   const Item it = items[blockIdx.x];
   const int j = it.j, p = it.p, i = j % N;
   const DevProb& pr = P[p];
   const int64_t k = pr.k;
-  const double* __restrict__ R = pr.Rinv + int64_t(i) * k * k;
-  const int tr = threadIdx.x & 63, sl = threadIdx.x >> 6;
-  const int64_t r0 = int64_t(it.blk) * 64;
+  const double* __restrict__ R = pr.Rinv + int64_t(sc[j].li) * k * k;
+  const int tr = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  const int64_t r0 = int64_t(it.blk) * 16;
   const int64_t r = r0 + tr;
   const double* __restrict__ qv = q + pr.offS * N + i;   // q[(offS + c) * N + i] = qv[c * N]
   double acc = 0.0;
   if (r < k) {
     int64_t c = r0 + sl;
-    for (; c + 12 < k; c += 16) {
-      const double r_0 = R[r + c * k], r_1 = R[r + (c + 4) * k];
-      const double r_2 = R[r + (c + 8) * k], r_3 = R[r + (c + 12) * k];
+    for (; c + 48 < k; c += 64) {
+      const double r_0 = R[r + c * k], r_1 = R[r + (c + 16) * k];
+      const double r_2 = R[r + (c + 32) * k], r_3 = R[r + (c + 48) * k];
       acc = fma(r_0, qv[c * N], acc);
-      acc = fma(r_1, qv[(c + 4) * N], acc);
-      acc = fma(r_2, qv[(c + 8) * N], acc);
-      acc = fma(r_3, qv[(c + 12) * N], acc);
+      acc = fma(r_1, qv[(c + 16) * N], acc);
+      acc = fma(r_2, qv[(c + 32) * N], acc);
+      acc = fma(r_3, qv[(c + 48) * N], acc);
     }
-    for (; c < k; c += 4) acc = fma(R[r + c * k], qv[c * N], acc);
+    for (; c < k; c += 16) acc = fma(R[r + c * k], qv[c * N], acc);
   }
   red[sl][tr] = acc;
   __syncthreads();
   if (sl != 0 || r >= k) return;
+  double sum = 0.0;
+#pragma unroll
+  for (int q2 = 0; q2 < 16; ++q2) sum += red[q2][tr];
   const Scal& S = sc[j];
-  const double wr = (red[0][tr] + red[1][tr] + red[2][tr] + red[3][tr]) * S.ialpha;
+  const double wr = sum * S.ialpha;
   const int64_t idx = (pr.offS + r) * N + i;
   v[idx] = q[idx] * S.ialpha;
   w[idx] = wr;
@@ -547,10 +566,12 @@ __global__ void __launch_bounds__(BLK) k_trmv(const DevProb* __restrict__ P,
 
 // --------------------------------------------------------- bookkeeping -----
 __global__ void k_scal_init(Scal* sc, int J, int N, const double* __restrict__ lams,
-                            const int32_t* __restrict__ pre_status) {
+                            const int32_t* __restrict__ pre_status,
+                            const int32_t* __restrict__ lidx) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= J) return;
   Scal S = {};
+  S.li = lidx[j];
   S.lam = lams[j];
   S.sqlam = sqrt(S.lam);
   S.active = 1;
@@ -572,6 +593,166 @@ __global__ void k_count_active(const Scal* __restrict__ sc, int J, int32_t* out)
   if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
 }
 
+// ===================================================== mixed precision (IR) ==
+// Refinement of the augmented system [I A; A^T -lam I] [r; x] = [b; 0] in
+// FP64 (Bjorck's iterative refinement for least squares, adapted to the
+// Tikhonov term): with s = A x kept in FP64,
+//   f = b - r - s,  g = A^T r - lam x        (FP64 residuals)
+//   dx = argmin || [A; sqrt(lam) I] dx - [f; g / sqrt(lam)] ||   (inner LSQR)
+//   x += dx,  s += A dx,  r += f - A dx.
+// The inner solve runs with FP32 products (or FP64 for lambdas where FP32
+// stops contracting); residuals, R^{-1} and x stay FP64.
+
+__global__ void k_to_f32(const double* __restrict__ src, int64_t m, int64_t n, int64_t lda,
+                         float* __restrict__ dst) {
+  const int64_t total = m * n;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t r = e % m, c = e / m;
+    dst[e] = float(src[r + c * lda]);
+  }
+}
+
+// f = b - r - s over all long rows of all problems (row-major, NF lambdas).
+__global__ void k_ir_f(const DevProb* __restrict__ P, const Item* __restrict__ items, int rb,
+                       int NF, const double* __restrict__ r, const double* __restrict__ s,
+                       double* __restrict__ f, int first) {
+  const Item it = items[blockIdx.x];
+  const DevProb& pr = P[it.p];
+  for (int e = threadIdx.x; e < rb * NF; e += BLK) {
+    const int64_t row = int64_t(it.blk) * rb + e / NF;
+    const int i = e % NF;
+    if (row >= pr.m) continue;
+    const int64_t idx = (pr.offL + row) * NF + i;
+    f[idx] = first ? pr.b[row] : pr.b[row] - r[idx] - s[idx];
+  }
+}
+
+// Inner right-hand side [f; g / sqrt(lam)] gathered for the inner plan's
+// lambda list, zero for lambdas not solved this sweep (use[j] == 0).
+template <typename TC>
+__global__ void __launch_bounds__(BLK) k_init_u_ir(const DevProb* __restrict__ P,
+                                                   const Item* __restrict__ itN, int nItN, int rbN,
+                                                   const Item* __restrict__ itB, int N, int NF,
+                                                   int l0, const Scal* __restrict__ sc,
+                                                   const int32_t* __restrict__ use,
+                                                   const double* __restrict__ f,
+                                                   const double* __restrict__ g,
+                                                   TC* __restrict__ ut, double* __restrict__ ub,
+                                                   double* __restrict__ pnN, double* __restrict__ pnB) {
+  __shared__ double red[4];
+  const bool top = int(blockIdx.x) < nItN;
+  const Item it = top ? itN[blockIdx.x] : itB[blockIdx.x - nItN];
+  const DevProb& pr = P[it.p];
+  const int64_t rows = top ? pr.m : pr.n;
+  const int64_t rb = top ? rbN : BLK;
+  const int64_t r0 = int64_t(it.blk) * rb;
+  const int64_t r1 = min(rows, r0 + rb);
+  double* pn = top ? pnN + (pr.pnN + it.blk) * N : pnB + (pr.pnB + it.blk) * N;
+  for (int i = 0; i < N; ++i) {
+    const Scal& S = sc[it.p * N + i];
+    const int li = S.li - l0;
+    const bool on = use[it.p * N + i] != 0;
+    const double isq = 1.0 / S.sqlam;
+    double acc = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += BLK) {
+      double v;
+      if (top) {
+        v = on ? f[(pr.offL + r) * NF + li] : 0.0;
+        const TC vc = TC(v);
+        ut[(pr.offL + r) * N + i] = vc;
+        v = double(vc);
+      } else {
+        v = on ? g[(pr.offS + r) * NF + li] * isq : 0.0;
+        ub[(pr.offS + r) * N + i] = v;
+      }
+      acc += v * v;
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) pn[i] = s;
+  }
+}
+
+// dx[:, li] = inner x[:, i] where the inner solve of lambda li finished with a
+// usable status.
+__global__ void k_ir_scatter(const DevProb* __restrict__ P, int N, int NF, int l0,
+                             const Scal* __restrict__ sc, const int32_t* __restrict__ use,
+                             const double* __restrict__ xin, double* __restrict__ dx) {
+  const int j = blockIdx.y, p = j / N, i = j % N;
+  const DevProb& pr = P[p];
+  const Scal& S = sc[j];
+  const bool ok = use[j] && (S.status == TIK_ST_CONVERGED || S.status == TIK_ST_MAXIT);
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < pr.n;
+       c += int64_t(gridDim.x) * blockDim.x)
+    if (ok) dx[(pr.offS + c) * NF + (S.li - l0)] = xin[(pr.offS + c) * N + i];
+}
+
+// x += dx; s += a; r += f - a.  Long rows for (r, s), short rows for x.
+__global__ void k_ir_update_long(const DevProb* __restrict__ P, const Item* __restrict__ items,
+                                 int rb, int NF, const double* __restrict__ f,
+                                 const double* __restrict__ a, double* __restrict__ r,
+                                 double* __restrict__ s) {
+  const Item it = items[blockIdx.x];
+  const DevProb& pr = P[it.p];
+  for (int e = threadIdx.x; e < rb * NF; e += BLK) {
+    const int64_t row = int64_t(it.blk) * rb + e / NF;
+    const int i = e % NF;
+    if (row >= pr.m) continue;
+    const int64_t idx = (pr.offL + row) * NF + i;
+    const double av = a[idx];
+    s[idx] += av;
+    r[idx] += f[idx] - av;
+  }
+}
+
+// x += dx and the per-(problem, lambda) squared norms of dx and of the new x.
+__global__ void __launch_bounds__(BLK) k_ir_update_x(const DevProb* __restrict__ P, int NF,
+                                                     const double* __restrict__ dx,
+                                                     double* __restrict__ x,
+                                                     double* __restrict__ nrm) {
+  __shared__ double red[4];
+  const int j = blockIdx.x, p = j / NF, i = j % NF;
+  const DevProb& pr = P[p];
+  double sd = 0.0, sx = 0.0;
+  for (int64_t c = threadIdx.x; c < pr.n; c += BLK) {
+    const int64_t idx = (pr.offS + c) * NF + i;
+    const double d = dx[idx];
+    const double nx = x[idx] + d;
+    x[idx] = nx;
+    sd += d * d;
+    sx += nx * nx;
+  }
+  const double td = block_sum(sd, red);
+  const double tx = block_sum(sx, red);
+  if (threadIdx.x == 0) {
+    nrm[2 * j] = td;
+    nrm[2 * j + 1] = tx;
+  }
+}
+
+// Copy the inner solves' iteration counts and statuses out per global lambda.
+__global__ void k_ir_inner_stats(int J, int N, int NF, int l0, const Scal* __restrict__ sc,
+                                 const int32_t* __restrict__ use, int32_t* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= J) return;
+  const int p = j / N;
+  const Scal& S = sc[j];
+  const int g = p * NF + (S.li - l0);
+  out[2 * g] = use[j] ? S.iters : 0;
+  out[2 * g + 1] = use[j] ? S.status : -1;
+}
+
+__global__ void k_ir_write(const DevProb* __restrict__ P, int NF, const double* __restrict__ x,
+                           const int32_t* __restrict__ ok, double* const* __restrict__ Xout,
+                           int32_t l0) {
+  const int j = blockIdx.y, p = j / NF, i = j % NF;
+  const DevProb& pr = P[p];
+  if (!ok[j]) return;
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < pr.n;
+       c += int64_t(gridDim.x) * blockDim.x)
+    Xout[p][c + int64_t(l0 + i) * pr.n] = x[(pr.offS + c) * NF + i];
+}
+
 // ============================================================ host driver ===
 
 namespace {
@@ -580,16 +761,18 @@ namespace {
 struct Plan {
   int N = 0, NC = 1, rbN = 64;
   std::vector<int> pidx;      // global problem index per local problem
-  std::vector<int> i0;        // first lambda index per local problem
+  std::vector<int> lsel;      // lambda indices solved (the same list for every problem)
   std::vector<DevProb> P;
-  std::vector<Item> itN, itB, itT, itQ;
+  std::vector<Item> itN, itB, itT, itQ, itR, itM;
+  int cpw = 16;
+  int cbT = 64;        // columns per gemm_t block (128 on matrix cores)
   int64_t totL = 0, totS = 0, totPT = 0, nbN = 0, nbB = 0, nbQ = 0;
   int J = 0;
 };
 
 struct Bufs {
   DevProb* P;
-  Item *itN, *itB, *itT, *itQ;
+  Item *itN, *itB, *itT, *itQ, *itR, *itM;
   Scal* sc;
   void* ut;
   double *ub, *v, *q, *w, *e, *x, *t;
@@ -600,6 +783,7 @@ struct Bufs {
   double* lams;
   int32_t* pre;
   int32_t* jmap;
+  int32_t* lidx;
 };
 
 int pick_nc(int N) {
@@ -609,41 +793,44 @@ int pick_nc(int N) {
 }
 
 void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vector<int>& pidx,
-               const std::vector<int>& i0, int N, Plan& pl) {
+               const std::vector<int>& lsel, Plan& pl, const void* const* Aover = nullptr,
+               const int64_t* ldover = nullptr) {
+  const int N = int(lsel.size());
   pl.N = N;
   pl.NC = pick_nc(N);
   pl.rbN = pl.NC >= 8 ? 256 : 64;
+  pl.cpw = pl.NC >= 8 ? 16 : 4;
+  pl.cbT = pl.NC >= 16 ? 128 : 64;
   pl.pidx = pidx;
-  pl.i0 = i0;
+  pl.lsel = lsel;
   pl.P.clear();
-  pl.itN.clear(); pl.itB.clear(); pl.itT.clear(); pl.itQ.clear();
+  pl.itN.clear(); pl.itB.clear(); pl.itT.clear(); pl.itQ.clear(); pl.itR.clear(); pl.itM.clear();
   pl.totL = pl.totS = pl.totPT = pl.nbN = pl.nbB = pl.nbQ = 0;
   const int np = int(pidx.size());
   int64_t colblocks = 0;
-  for (int lp = 0; lp < np; ++lp) colblocks += cdiv(probs[pidx[lp]].n, 64);
+  for (int lp = 0; lp < np; ++lp) colblocks += cdiv(probs[pidx[lp]].n, pl.cbT);
   for (int lp = 0; lp < np; ++lp) {
     const tik_problem& g = probs[pidx[lp]];
     DevProb d = {};
-    d.A = g.A;
+    d.A = Aover ? Aover[pidx[lp]] : g.A;
     d.m = g.m;
     d.n = g.n;
-    d.lda = g.lda;
-    d.a_f32 = g.a_dtype == TIK_F32;
+    d.lda = ldover ? ldover[pidx[lp]] : g.lda;
+    d.a_f32 = Aover ? 1 : (g.a_dtype == TIK_F32);
     d.wide = 0;
     d.b = g.b;
     d.offL = pl.totL;
     d.offS = pl.totS;
     d.k = g.n;
-    if (pc->route == TIK_ROUTE_CHOL)
-      d.Rinv = pc->Rinv[pidx[lp]] + int64_t(i0[lp]) * d.k * d.k;
+    if (pc->route == TIK_ROUTE_CHOL) d.Rinv = pc->Rinv[pidx[lp]];
     d.nblkN = int32_t(cdiv(g.m, pl.rbN));
     d.nblkB = int32_t(cdiv(g.n, BLK));
-    d.nblkQ = int32_t(cdiv(g.n, 64));
+    d.nblkQ = int32_t(cdiv(g.n, 4 * pl.cpw));
     d.pnN = pl.nbN;
     d.pnB = pl.nbB;
     d.pnQ = pl.nbQ;
     // row chunks for gemm_t: aim for about 2048 blocks over the whole batch
-    const int64_t cb = cdiv(g.n, 64);
+    const int64_t cb = cdiv(g.n, pl.cbT);
     int64_t nch = std::max<int64_t>(1, 2048 / std::max<int64_t>(1, colblocks));
     nch = std::min<int64_t>(nch, cdiv(g.m, 32));
     int64_t rch = cdiv(cdiv(g.m, nch), 32) * 32;
@@ -657,6 +844,9 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
       for (int64_t c = 0; c < cb; ++c) pl.itT.push_back({lp, int32_t(c), int32_t(ch), 0});
     for (int i = 0; i < N; ++i)
       for (int b = 0; b < d.nblkQ; ++b) pl.itQ.push_back({lp, b, 0, lp * N + i});
+    for (int i = 0; i < N; ++i)
+      for (int64_t b = 0; b < cdiv(g.n, 16); ++b) pl.itM.push_back({lp, int32_t(b), 0, lp * N + i});
+    for (int64_t b = 0; b < cdiv(g.n, BLK / pl.NC); ++b) pl.itR.push_back({lp, int32_t(b), 0, 0});
     pl.totL += g.m;
     pl.totS += g.n;
     pl.totPT += nch * g.n;
@@ -675,6 +865,8 @@ void take_bufs(Arena& a, const Plan& pl, size_t tc, Bufs& b) {
   b.itB = a.take<Item>(pl.itB.size());
   b.itT = a.take<Item>(pl.itT.size());
   b.itQ = a.take<Item>(pl.itQ.size());
+  b.itR = a.take<Item>(pl.itR.size());
+  b.itM = a.take<Item>(pl.itM.size());
   b.sc = a.take<Scal>(pl.J);
   b.ut = a.take<char>(size_t(pl.totL) * N * tc);
   b.ub = a.take<double>(size_t(pl.totS) * N);
@@ -693,12 +885,17 @@ void take_bufs(Arena& a, const Plan& pl, size_t tc, Bufs& b) {
   b.lams = a.take<double>(pl.J);
   b.pre = a.take<int32_t>(pl.J);
   b.jmap = a.take<int32_t>(pl.J);
+  b.lidx = a.take<int32_t>(pl.J);
 }
 
 template <typename TA, typename TC, int NC>
 struct Kern {
   static int gemm_n(const Plan& pl, const Bufs& b, hipStream_t st) {
     ProfScope ps("gemm_n", st);
+    if (NC >= 16)
+      return launch_gemm_n_mfma(std::is_same<TA, float>::value, std::is_same<TC, float>::value, NC, 0,
+                                b.P, b.itN, int(pl.itN.size()), pl.N, b.w, b.ut, nullptr, b.sc,
+                                b.pnN, st);
     if (NC >= 8)
       hipLaunchKernelGGL((k_gemm_n<TA, TC, NC, 256, 1, 0>), dim3(unsigned(pl.itN.size())), dim3(BLK),
                          0, st, b.P, b.itN, pl.N, b.w, static_cast<TC*>(b.ut), nullptr, b.sc, b.pnN);
@@ -710,6 +907,9 @@ struct Kern {
   }
   static int gemm_t(const Plan& pl, const Bufs& b, hipStream_t st) {
     ProfScope ps("gemm_t", st);
+    if (NC >= 16)
+      return launch_gemm_t_mfma(std::is_same<TA, float>::value, std::is_same<TC, float>::value, 0, NC,
+                                b.P, b.itT, int(pl.itT.size()), pl.N, b.ut, b.part, st);
     hipLaunchKernelGGL((k_gemm_t<TA, TC, TC, NC>), dim3(unsigned(pl.itT.size())), dim3(BLK), 0, st,
                        b.P, b.itT, pl.N, static_cast<const TC*>(b.ut), int64_t(pl.N),
                        static_cast<TC*>(b.part));
@@ -738,18 +938,22 @@ int vec_steps_u(const Plan& pl, const Bufs& b, hipStream_t st, bool init, const 
   return TIK_OK;
 }
 
-template <typename TC>
+template <typename TC, int NC>
 int vec_steps_v(const Plan& pl, const Bufs& b, hipStream_t st, bool init, double tol, int maxit) {
   {
     ProfScope ps("vec", st);
-    hipLaunchKernelGGL((k_reduce_t<TC, 0>), dim3(unsigned(pl.itB.size())), dim3(BLK), 0, st, b.P,
-                       b.itB, pl.N, static_cast<const TC*>(b.part), b.ub, b.sc, b.t);
+    hipLaunchKernelGGL((k_reduce_t<TC, 0, NC>), dim3(unsigned(pl.itR.size())), dim3(BLK), 0, st, b.P,
+                       b.itR, pl.N, static_cast<const TC*>(b.part), b.ub, b.sc, b.t);
     TIK_LAUNCHED("k_reduce_t");
   }
   {
     ProfScope ps("trmv_t", st);
-    hipLaunchKernelGGL(k_trmv_t, dim3(unsigned(pl.itQ.size())), dim3(BLK), 0, st, b.P, b.itQ, pl.N,
-                       b.t, b.v, b.q, b.sc, b.pnQ);
+    if (pl.cpw == 16)
+      hipLaunchKernelGGL(k_trmv_t<16>, dim3(unsigned(pl.itQ.size())), dim3(BLK), 0, st, b.P, b.itQ,
+                         pl.N, b.t, b.v, b.q, b.sc, b.pnQ);
+    else
+      hipLaunchKernelGGL(k_trmv_t<4>, dim3(unsigned(pl.itQ.size())), dim3(BLK), 0, st, b.P, b.itQ,
+                         pl.N, b.t, b.v, b.q, b.sc, b.pnQ);
     TIK_LAUNCHED("k_trmv_t");
   }
   {
@@ -760,7 +964,7 @@ int vec_steps_v(const Plan& pl, const Bufs& b, hipStream_t st, bool init, double
   }
   {
     ProfScope ps("trmv", st);
-    hipLaunchKernelGGL(k_trmv, dim3(unsigned(pl.itQ.size())), dim3(BLK), 0, st, b.P, b.itQ, pl.N,
+    hipLaunchKernelGGL(k_trmv, dim3(unsigned(pl.itM.size())), dim3(BLK), 0, st, b.P, b.itM, pl.N,
                        b.q, b.v, b.w, b.x, b.e, b.sc, init ? 1 : 0);
     TIK_LAUNCHED("k_trmv");
   }
@@ -774,17 +978,36 @@ int upload(void* dst, const void* src, size_t bytes, hipStream_t st) {
 }
 
 // Run LSQR to completion for one plan; x is left in b.x.
+struct IrRhs {
+  const int32_t* use;   // per solve of the plan: solved this sweep
+  const double* f;      // long rows x NF
+  const double* g;      // short rows x NF
+  int NF;
+  int l0;               // global index of refinement column 0
+};
+
 template <typename TA, typename TC, int NC>
 int run_core(const Plan& pl, const Bufs& b, double tol, int maxit, hipStream_t st,
-             const double* rhs_top, const double* rhs_bot) {
+             const IrRhs* ir) {
   using K = Kern<TA, TC, NC>;
   hipLaunchKernelGGL(k_scal_init, dim3(unsigned(cdiv(pl.J, 256))), dim3(256), 0, st, b.sc, pl.J,
-                     pl.N, b.lams, b.pre);
+                     pl.N, b.lams, b.pre, b.lidx);
   TIK_LAUNCHED("k_scal_init");
   TIK_HIP(hipMemsetAsync(b.v, 0, size_t(pl.totS) * pl.N * sizeof(double), st));
-  TIK_TRY(vec_steps_u<TC>(pl, b, st, true, rhs_top, rhs_bot));
+  if (ir) {
+    ProfScope ps("vec", st);
+    hipLaunchKernelGGL(k_init_u_ir<TC>, dim3(unsigned(pl.itN.size() + pl.itB.size())), dim3(BLK), 0,
+                       st, b.P, b.itN, int(pl.itN.size()), pl.rbN, b.itB, pl.N, ir->NF, ir->l0, b.sc, ir->use,
+                       ir->f, ir->g, static_cast<TC*>(b.ut), b.ub, b.pnN, b.pnB);
+    TIK_LAUNCHED("k_init_u_ir");
+    hipLaunchKernelGGL(k_fin_beta, dim3(unsigned(pl.J)), dim3(BLK), 0, st, b.P, pl.N, b.pnN, b.pnB,
+                       b.sc, 1);
+    TIK_LAUNCHED("k_fin_beta");
+  } else {
+    TIK_TRY(vec_steps_u<TC>(pl, b, st, true, nullptr, nullptr));
+  }
   TIK_TRY(K::gemm_t(pl, b, st));
-  TIK_TRY(vec_steps_v<TC>(pl, b, st, true, tol, maxit));
+  TIK_TRY((vec_steps_v<TC, NC>(pl, b, st, true, tol, maxit)));
   const int chunk = 8;
   int32_t active = 1;
   for (int it = 0; it < maxit && active > 0;) {
@@ -793,7 +1016,7 @@ int run_core(const Plan& pl, const Bufs& b, double tol, int maxit, hipStream_t s
       TIK_TRY(K::gemm_n(pl, b, st));
       TIK_TRY(vec_steps_u<TC>(pl, b, st, false, nullptr, nullptr));
       TIK_TRY(K::gemm_t(pl, b, st));
-      TIK_TRY(vec_steps_v<TC>(pl, b, st, false, tol, maxit));
+      TIK_TRY((vec_steps_v<TC, NC>(pl, b, st, false, tol, maxit)));
     }
     it += todo;
     hipLaunchKernelGGL(k_count_active, dim3(1), dim3(BLK), 0, st, b.sc, pl.J, b.cnt);
@@ -806,14 +1029,14 @@ int run_core(const Plan& pl, const Bufs& b, double tol, int maxit, hipStream_t s
 
 template <typename TA, typename TC>
 int run_core_nc(const Plan& pl, const Bufs& b, double tol, int maxit, hipStream_t st,
-                const double* rt, const double* rb) {
+                const IrRhs* ir) {
   switch (pl.NC) {
-    case 1: return run_core<TA, TC, 1>(pl, b, tol, maxit, st, rt, rb);
-    case 2: return run_core<TA, TC, 2>(pl, b, tol, maxit, st, rt, rb);
-    case 4: return run_core<TA, TC, 4>(pl, b, tol, maxit, st, rt, rb);
-    case 8: return run_core<TA, TC, 8>(pl, b, tol, maxit, st, rt, rb);
-    case 16: return run_core<TA, TC, 16>(pl, b, tol, maxit, st, rt, rb);
-    case 32: return run_core<TA, TC, 32>(pl, b, tol, maxit, st, rt, rb);
+    case 1: return run_core<TA, TC, 1>(pl, b, tol, maxit, st, ir);
+    case 2: return run_core<TA, TC, 2>(pl, b, tol, maxit, st, ir);
+    case 4: return run_core<TA, TC, 4>(pl, b, tol, maxit, st, ir);
+    case 8: return run_core<TA, TC, 8>(pl, b, tol, maxit, st, ir);
+    case 16: return run_core<TA, TC, 16>(pl, b, tol, maxit, st, ir);
+    case 32: return run_core<TA, TC, 32>(pl, b, tol, maxit, st, ir);
   }
   set_error("internal: lambda batch wider than 32");
   return TIK_ENOTSUP;
@@ -832,19 +1055,23 @@ int upload_plan(const Plan& pl, const Bufs& b, const tik_precond_s* pc, double* 
   TIK_TRY(upload(b.itB, stash(pl.itB.data(), pl.itB.size() * sizeof(Item)), pl.itB.size() * sizeof(Item), st));
   TIK_TRY(upload(b.itT, stash(pl.itT.data(), pl.itT.size() * sizeof(Item)), pl.itT.size() * sizeof(Item), st));
   TIK_TRY(upload(b.itQ, stash(pl.itQ.data(), pl.itQ.size() * sizeof(Item)), pl.itQ.size() * sizeof(Item), st));
+  TIK_TRY(upload(b.itR, stash(pl.itR.data(), pl.itR.size() * sizeof(Item)), pl.itR.size() * sizeof(Item), st));
+  TIK_TRY(upload(b.itM, stash(pl.itM.data(), pl.itM.size() * sizeof(Item)), pl.itM.size() * sizeof(Item), st));
   std::vector<double> lams(pl.J);
-  std::vector<int32_t> pre(pl.J), jmap(pl.J);
+  std::vector<int32_t> pre(pl.J), jmap(pl.J), lidx(pl.J);
   std::vector<double*> xp(pl.P.size());
   for (size_t lp = 0; lp < pl.P.size(); ++lp) {
     const int p = pl.pidx[lp];
     for (int i = 0; i < pl.N; ++i) {
-      const int gi = pl.i0[lp] + i;
+      const int gi = pl.lsel[i];
       lams[lp * pl.N + i] = pc->lams[size_t(p) * pc->N + gi];
       pre[lp * pl.N + i] = pc->status[size_t(p) * pc->N + gi];
       jmap[lp * pl.N + i] = p * pc->N + gi;
+      lidx[lp * pl.N + i] = gi;
     }
-    xp[lp] = X ? X[p] + int64_t(pl.i0[lp]) * pc->probs[p].n : nullptr;
+    xp[lp] = X ? X[p] : nullptr;
   }
+  TIK_TRY(upload(b.lidx, stash(lidx.data(), lidx.size() * 4), lidx.size() * 4, st));
   TIK_TRY(upload(b.lams, stash(lams.data(), lams.size() * 8), lams.size() * 8, st));
   TIK_TRY(upload(b.pre, stash(pre.data(), pre.size() * 4), pre.size() * 4, st));
   TIK_TRY(upload(b.jmap, stash(jmap.data(), jmap.size() * 4), jmap.size() * 4, st));
@@ -863,7 +1090,7 @@ __global__ void k_write_out_map(const DevProb* __restrict__ P, int N, const doub
   const bool ok = S.status == TIK_ST_CONVERGED || S.status == TIK_ST_MAXIT;
   for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < pr.n;
        c += int64_t(gridDim.x) * blockDim.x)
-    if (ok && Xout[p]) Xout[p][c + int64_t(i) * pr.n] = x[(pr.offS + c) * N + i];
+    if (ok && Xout[p]) Xout[p][c + int64_t(S.li) * pr.n] = x[(pr.offS + c) * N + i];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     const int g = jmap[j];
     if (iters) iters[g] = S.iters;
@@ -873,40 +1100,465 @@ __global__ void k_write_out_map(const DevProb* __restrict__ P, int N, const doub
 }
 
 void groups_for(const tik_precond_s* pc, int32_t nprob, int32_t mode,
-                std::vector<std::vector<int>>& gp, std::vector<std::vector<int>>& gi, std::vector<int>& gN) {
-  gp.clear(); gi.clear(); gN.clear();
+                std::vector<std::vector<int>>& gp, std::vector<std::vector<int>>& gl) {
+  gp.clear(); gl.clear();
   const int N = pc->N;
   if (mode == TIK_PLAIN_F64_PER_LAMBDA) {
     for (int p = 0; p < nprob; ++p)
       for (int i = 0; i < N; ++i) {
         gp.push_back({p});
-        gi.push_back({i});
-        gN.push_back(1);
+        gl.push_back({i});
       }
     return;
   }
   // batched: all problems, lambdas in groups of at most 32
+  std::vector<int> ps;
+  for (int p = 0; p < nprob; ++p) ps.push_back(p);
   for (int i0 = 0; i0 < N; i0 += 32) {
-    std::vector<int> ps, is;
-    for (int p = 0; p < nprob; ++p) { ps.push_back(p); is.push_back(i0); }
+    std::vector<int> ls;
+    for (int i = i0; i < std::min(N, i0 + 32); ++i) ls.push_back(i);
     gp.push_back(ps);
-    gi.push_back(is);
-    gN.push_back(std::min(32, N - i0));
+    gl.push_back(ls);
   }
+}
+
+// ------------------------------------------------------------ mixed driver --
+struct MixedWs {
+  std::vector<float*> A32;        // FP32 copies of FP64-stored problems (null if stored FP32)
+  double *r, *s, *f, *a, *x, *dx, *g, *nrm;
+  int32_t *use32, *use64, *stats, *ok;
+  char* base32 = nullptr;         // inner FP32 plan region
+  char* base64 = nullptr;         // inner FP64 plan region
+  size_t cap32 = 0, cap64 = 0;
+  char* baseF = nullptr;          // FP64 refinement plan region
+  size_t capF = 0;
+};
+
+void all_lambdas(int N0, int N, std::vector<int>& ls) {
+  ls.clear();
+  for (int i = N0; i < N0 + N; ++i) ls.push_back(i);
+}
+
+// Workspace layout of the mixed mode for lambda groups of at most 32.
+size_t mixed_layout(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, Arena& a,
+                    MixedWs& w) {
+  std::vector<int> ps;
+  for (int k = 0; k < nprob; ++k) ps.push_back(k);
+  const int NF = std::min(32, pc->N);
+  std::vector<int> ls;
+  all_lambdas(0, NF, ls);
+  Plan pl;
+  make_plan(p, pc, ps, ls, pl);
+  w.A32.assign(size_t(nprob), nullptr);
+  for (int k = 0; k < nprob; ++k)
+    if (p[k].a_dtype == TIK_F64) w.A32[k] = a.take<float>(size_t(p[k].m) * size_t(p[k].n));
+  const size_t L = size_t(pl.totL) * NF, S = size_t(pl.totS) * NF;
+  w.r = a.take<double>(L);
+  w.s = a.take<double>(L);
+  w.f = a.take<double>(L);
+  w.a = a.take<double>(L);
+  w.x = a.take<double>(S);
+  w.dx = a.take<double>(S);
+  w.g = a.take<double>(S);
+  w.nrm = a.take<double>(2 * size_t(pl.J));
+  w.use32 = a.take<int32_t>(pl.J);
+  w.use64 = a.take<int32_t>(pl.J);
+  w.stats = a.take<int32_t>(2 * size_t(pl.J));
+  w.ok = a.take<int32_t>(pl.J);
+  auto region = [&](size_t tc, char*& base, size_t& cap) {
+    cap = 0;
+    for (int ng = 1; ng <= NF; ++ng) {     // inner plans solve subsets of the lambdas
+      std::vector<int> sub;
+      all_lambdas(0, ng, sub);
+      Plan ps_;
+      make_plan(p, pc, ps, sub, ps_);
+      Arena m;
+      Bufs b;
+      take_bufs(m, ps_, tc, b);
+      cap = std::max(cap, m.used + 256);
+    }
+    base = a.take<char>(cap);
+  };
+  region(sizeof(float), w.base32, w.cap32);
+  region(sizeof(double), w.base64, w.cap64);
+  region(sizeof(double), w.baseF, w.capF);
+  return a.used;
+}
+
+template <typename TA>
+int ir_products_t(const Plan& pf, const Bufs& bf, const double* U, hipStream_t st) {
+  ProfScope ps("residual", st);
+  if (pf.NC >= 16)
+    return launch_gemm_t_mfma(std::is_same<TA, float>::value, 0, 1, pf.NC, bf.P, bf.itT,
+                              int(pf.itT.size()), pf.N, U, bf.part, st);
+  switch (pf.NC) {
+#define GT(nc) case nc: hipLaunchKernelGGL((k_gemm_t<TA, double, double, nc>), dim3(unsigned(pf.itT.size())), dim3(BLK), 0, st, bf.P, bf.itT, pf.N, U, int64_t(pf.N), static_cast<double*>(bf.part)); break;
+    GT(1) GT(2) GT(4) GT(8)
+#undef GT
+  }
+  TIK_LAUNCHED("k_gemm_t (refinement)");
+  return TIK_OK;
+}
+
+template <typename TA>
+int ir_products_n(const Plan& pf, const Bufs& bf, const double* W, double* out, hipStream_t st) {
+  ProfScope ps("residual", st);
+  if (pf.NC >= 16)
+    return launch_gemm_n_mfma(std::is_same<TA, float>::value, 0, pf.NC, 1, bf.P, bf.itN,
+                              int(pf.itN.size()), pf.N, W, nullptr, out, bf.sc, nullptr, st);
+  switch (pf.NC) {
+#define GN(nc) case nc: hipLaunchKernelGGL((k_gemm_n<TA, double, nc, (nc >= 8 ? 256 : 64), (nc >= 8 ? 1 : 4), 1>), dim3(unsigned(pf.itN.size())), dim3(BLK), 0, st, bf.P, bf.itN, pf.N, W, static_cast<double*>(nullptr), out, bf.sc, static_cast<double*>(nullptr)); break;
+    GN(1) GN(2) GN(4) GN(8)
+#undef GN
+  }
+  TIK_LAUNCHED("k_gemm_n (refinement)");
+  return TIK_OK;
+}
+
+template <int NC>
+int ir_reduce_g(const Plan& pf, const Bufs& bf, const double* x, double* g, hipStream_t st) {
+  hipLaunchKernelGGL((k_reduce_t<double, 1, NC>), dim3(unsigned(pf.itR.size())), dim3(BLK), 0, st,
+                     bf.P, bf.itR, pf.N, static_cast<const double*>(bf.part), x, bf.sc, g);
+  TIK_LAUNCHED("k_reduce_t (refinement)");
+  return TIK_OK;
+}
+
+int ir_reduce_g_nc(const Plan& pf, const Bufs& bf, const double* x, double* g, hipStream_t st) {
+  ProfScope ps("residual", st);
+  switch (pf.NC) {
+    case 1: return ir_reduce_g<1>(pf, bf, x, g, st);
+    case 2: return ir_reduce_g<2>(pf, bf, x, g, st);
+    case 4: return ir_reduce_g<4>(pf, bf, x, g, st);
+    case 8: return ir_reduce_g<8>(pf, bf, x, g, st);
+    case 16: return ir_reduce_g<16>(pf, bf, x, g, st);
+    case 32: return ir_reduce_g<32>(pf, bf, x, g, st);
+  }
+  set_error("internal: refinement batch wider than 32");
+  return TIK_ENOTSUP;
+}
+
+// One inner solve over the lambdas `sel` (global indices) with FP32 (f32 = true)
+// or FP64 products; the result is scattered into w.dx.
+template <typename TA64>
+int inner_solve(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, const MixedWs& w,
+                const std::vector<int>& sel, const std::vector<uint8_t>& use_h, int NF, int l0,
+                bool f32, double tol, int maxit, hipStream_t st,
+                std::vector<std::vector<char>>& keep) {
+  std::vector<int> ps;
+  for (int k = 0; k < nprob; ++k) ps.push_back(k);
+  std::vector<const void*> Aov(static_cast<size_t>(nprob));
+  std::vector<int64_t> ldo(static_cast<size_t>(nprob));
+  bool any_override = false;
+  for (int k = 0; k < nprob; ++k) {
+    const bool ov = f32 && w.A32[k];
+    Aov[k] = ov ? static_cast<const void*>(w.A32[k]) : p[k].A;
+    ldo[k] = ov ? p[k].m : p[k].lda;                 // the FP32 copy is packed
+    any_override |= ov;
+  }
+  Plan pl;
+  make_plan(p, pc, ps, sel, pl, any_override ? Aov.data() : nullptr,
+            any_override ? ldo.data() : nullptr);
+  if (f32)
+    for (auto& d : pl.P) d.a_f32 = 1;
+  Arena a;
+  a.base = f32 ? w.base32 : w.base64;
+  a.cap = f32 ? w.cap32 : w.cap64;
+  Bufs b;
+  take_bufs(a, pl, f32 ? sizeof(float) : sizeof(double), b);
+  if (!a.fits()) {
+    set_error("internal: inner plan exceeds its region");
+    return TIK_EWORKSPACE;
+  }
+  TIK_TRY(upload_plan(pl, b, pc, nullptr, keep, st));
+  std::vector<int32_t> use(size_t(pl.J));
+  for (int k = 0; k < nprob; ++k)
+    for (size_t i = 0; i < sel.size(); ++i) use[k * sel.size() + i] = use_h[size_t(k) * NF + (sel[i] - l0)];
+  keep.emplace_back(reinterpret_cast<const char*>(use.data()),
+                    reinterpret_cast<const char*>(use.data()) + use.size() * 4);
+  int32_t* dUse = f32 ? w.use32 : w.use64;
+  TIK_HIP(hipMemcpyAsync(dUse, keep.back().data(), use.size() * 4, hipMemcpyHostToDevice, st));
+  IrRhs ir{dUse, w.f, w.g, NF, l0};
+  // the inner plan's solves map to refinement columns sel[i] - l0: shift li
+  // by l0 inside the scatter through the Scal lambda index
+  if (f32)
+    TIK_TRY((run_core_nc<float, float>(pl, b, tol, maxit, st, &ir)));
+  else
+    TIK_TRY((run_core_nc<TA64, double>(pl, b, tol, maxit, st, &ir)));
+  int64_t maxn = 0;
+  for (auto& d : pl.P) maxn = std::max(maxn, d.n);
+  (void)l0;
+  hipLaunchKernelGGL(k_ir_scatter, dim3(unsigned(cdiv(maxn, 256)), unsigned(pl.J)), dim3(256), 0,
+                     st, b.P, pl.N, NF, l0, b.sc, dUse, b.x, w.dx);
+  TIK_LAUNCHED("k_ir_scatter");
+  hipLaunchKernelGGL(k_ir_inner_stats, dim3(unsigned(cdiv(pl.J, 256))), dim3(256), 0, st, pl.J,
+                     pl.N, NF, l0, b.sc, dUse, w.stats);
+  TIK_LAUNCHED("k_ir_inner_stats");
+  return TIK_OK;
+}
+
+template <typename TA64>
+int mixed_group(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, const MixedWs& w,
+                int l0, int NF, double tol, int maxit, double* const* X, int32_t* iters,
+                int32_t* status, double* relres, hipStream_t st) {
+  std::vector<int> ps;
+  for (int k = 0; k < nprob; ++k) ps.push_back(k);
+  std::vector<int> lsel;
+  all_lambdas(l0, NF, lsel);
+  Plan pf;
+  make_plan(p, pc, ps, lsel, pf);
+  Arena af;
+  af.base = w.baseF;
+  af.cap = w.capF;
+  Bufs bf;
+  take_bufs(af, pf, sizeof(double), bf);
+  if (!af.fits()) {
+    set_error("internal: refinement plan exceeds its region");
+    return TIK_EWORKSPACE;
+  }
+  std::vector<std::vector<char>> keep;
+  TIK_TRY(upload_plan(pf, bf, pc, nullptr, keep, st));
+  hipLaunchKernelGGL(k_scal_init, dim3(unsigned(cdiv(pf.J, 256))), dim3(256), 0, st, bf.sc, pf.J,
+                     pf.N, bf.lams, bf.pre, bf.lidx);
+  TIK_LAUNCHED("k_scal_init");
+  const size_t L = size_t(pf.totL) * NF, S = size_t(pf.totS) * NF;
+  TIK_HIP(hipMemsetAsync(w.r, 0, L * 8, st));
+  TIK_HIP(hipMemsetAsync(w.s, 0, L * 8, st));
+  TIK_HIP(hipMemsetAsync(w.x, 0, S * 8, st));
+  const int J = pf.J;
+  // host-side refinement state per (problem, lambda of the group)
+  std::vector<int32_t> st_h(J, -1), it_h(J, 0);
+  std::vector<double> dxrel(J, 1.0), rho(J, 1.0), rel_h(J, 0.0);
+  std::vector<uint8_t> done(J, 0), want64(J, 0), was64(J, 0);
+  for (int j = 0; j < J; ++j) {
+    const int k = j / NF, i = j % NF;
+    const int32_t pre = pc->status[size_t(k) * pc->N + l0 + i];
+    if (pre != TIK_ST_CONVERGED) {
+      st_h[j] = pre;
+      done[j] = 1;
+    }
+  }
+  // Lambdas where FP32 products cannot drive the refinement: its contraction
+  // per sweep is about c * kappa(B) * u_32 (c ~ 12 measured), with kappa(B)^2
+  // <= (||C|| + lambda) / lambda.  Such a lambda needs FP64 passes over A, and
+  // a pass over A costs the same for one lambda as for all of them, so once
+  // one lambda of the group needs FP64 the whole group is solved by batched
+  // FP64 LSQR (refinement sweeps would only add passes).
+  std::vector<int> hard;
+  bool any_hard = false;
+  for (int i = 0; i < NF; ++i)
+    for (int k = 0; k < nprob; ++k) {
+      const double lam = pc->lams[size_t(k) * pc->N + l0 + i];
+      const double kap = std::sqrt((pc->cnorm[k] + lam) / lam);
+      any_hard |= 12.0 * kap * std::ldexp(1.0, -24) > 0.25;
+    }
+  if (any_hard)
+    for (int i = 0; i < NF; ++i) hard.push_back(l0 + i);
+  if (!hard.empty()) {
+    Plan ph;
+    make_plan(p, pc, ps, hard, ph);
+    Arena ah;
+    ah.base = w.base64;
+    ah.cap = w.cap64;
+    Bufs bh;
+    take_bufs(ah, ph, sizeof(double), bh);
+    if (!ah.fits()) {
+      set_error("internal: FP64 plan exceeds its region");
+      return TIK_EWORKSPACE;
+    }
+    TIK_TRY(upload_plan(ph, bh, pc, X, keep, st));
+    const double tol_h = std::max(1e-3 * tol, 1e-14);
+    TIK_TRY((run_core_nc<TA64, double>(ph, bh, tol_h, maxit, st, nullptr)));
+    int64_t mn = 0;
+    for (auto& d : ph.P) mn = std::max(mn, d.n);
+    hipLaunchKernelGGL(k_write_out_map, dim3(unsigned(cdiv(mn, 256)), unsigned(ph.J)), dim3(256), 0,
+                       st, bh.P, ph.N, bh.x, bh.sc, bh.Xp, bh.jmap, iters, status, relres);
+    TIK_LAUNCHED("k_write_out");
+    TIK_HIP(hipStreamSynchronize(st));
+    for (int li : hard)
+      for (int k = 0; k < nprob; ++k) {
+        const int j = k * NF + (li - l0);
+        done[j] = 2;     // finished outside the refinement
+      }
+  }
+  const int maxsweep = 12;
+  const double tol32 = std::max(tol, 1e-6);
+  std::vector<double> nrm(2 * size_t(J));
+  std::vector<int32_t> stats(2 * size_t(J));
+  for (int sweep = 1; sweep <= maxsweep; ++sweep) {
+    bool any = false;
+    for (int j = 0; j < J; ++j) any |= !done[j];
+    if (!any) break;
+    {
+      ProfScope ps("residual", st);
+      hipLaunchKernelGGL(k_ir_f, dim3(unsigned(pf.itN.size())), dim3(BLK), 0, st, bf.P, bf.itN,
+                         pf.rbN, NF, w.r, w.s, w.f, sweep == 1 ? 1 : 0);
+    }
+    TIK_LAUNCHED("k_ir_f");
+    if (sweep == 1) {
+      TIK_HIP(hipMemsetAsync(w.g, 0, S * 8, st));
+    } else {
+      TIK_TRY(ir_products_t<TA64>(pf, bf, w.r, st));
+      TIK_TRY(ir_reduce_g_nc(pf, bf, w.x, w.g, st));
+    }
+    // choose the inner precision per lambda (uniform across problems)
+    std::vector<int> sel32, sel64;
+    std::vector<uint8_t> use32(J, 0), use64(J, 0);
+    for (int i = 0; i < NF; ++i) {
+      bool act = false, hard = false;
+      for (int k = 0; k < nprob; ++k) {
+        const int j = k * NF + i;
+        if (!done[j]) {
+          act = true;
+          hard |= want64[j] != 0;
+        }
+      }
+      if (!act) continue;
+      (hard ? sel64 : sel32).push_back(l0 + i);
+      for (int k = 0; k < nprob; ++k) {
+        const int j = k * NF + i;
+        if (!done[j]) (hard ? use64 : use32)[j] = 1;
+      }
+    }
+    double err64 = 1.0;
+    for (int j = 0; j < J; ++j)
+      if (use64[j]) err64 = std::min(err64, std::max(dxrel[j] * std::min(1.0, rho[j]), 1e-300));
+    const double tol64 = std::min(1e-6, std::max(1e-14, 1e-3 * tol / std::max(err64, 1e-300)));
+    TIK_HIP(hipMemsetAsync(w.dx, 0, S * 8, st));
+    TIK_HIP(hipMemsetAsync(w.stats, 0xFF, 2 * size_t(J) * 4, st));
+    if (!sel32.empty())
+      TIK_TRY(inner_solve<TA64>(p, nprob, pc, w, sel32, use32, NF, l0, true, tol32, maxit, st, keep));
+    if (!sel64.empty())
+      TIK_TRY(inner_solve<TA64>(p, nprob, pc, w, sel64, use64, NF, l0, false, tol64, maxit, st, keep));
+    TIK_TRY(ir_products_n<TA64>(pf, bf, w.dx, w.a, st));
+    {
+      ProfScope ps("residual", st);
+      hipLaunchKernelGGL(k_ir_update_long, dim3(unsigned(pf.itN.size())), dim3(BLK), 0, st, bf.P,
+                         bf.itN, pf.rbN, NF, w.f, w.a, w.r, w.s);
+      hipLaunchKernelGGL(k_ir_update_x, dim3(unsigned(J)), dim3(BLK), 0, st, bf.P, NF, w.dx, w.x, w.nrm);
+    }
+    TIK_LAUNCHED("k_ir_update");
+    TIK_HIP(hipMemcpyAsync(nrm.data(), w.nrm, nrm.size() * 8, hipMemcpyDeviceToHost, st));
+    TIK_HIP(hipMemcpyAsync(stats.data(), w.stats, stats.size() * 4, hipMemcpyDeviceToHost, st));
+    TIK_HIP(hipStreamSynchronize(st));
+    for (int j = 0; j < J; ++j) {
+      if (done[j] || !(use32[j] || use64[j])) continue;
+      it_h[j] += std::max(0, stats[2 * j]);
+      const int32_t ist = stats[2 * j + 1];
+      if (ist == TIK_ST_NOTPD || ist == TIK_ST_NONFINITE) {
+        st_h[j] = ist;
+        done[j] = 1;
+        continue;
+      }
+      const double nx = std::sqrt(nrm[2 * j + 1]), nd = std::sqrt(nrm[2 * j]);
+      if (!std::isfinite(nx) || !std::isfinite(nd)) {
+        st_h[j] = TIK_ST_NONFINITE;
+        done[j] = 1;
+        continue;
+      }
+      const double rel = nx > 0.0 ? nd / nx : 0.0;
+      const double r_k = sweep == 1 ? 1.0 : rel / std::max(dxrel[j], 1e-300);
+      rel_h[j] = rel;
+      if (rel <= tol) {
+        st_h[j] = TIK_ST_CONVERGED;
+        done[j] = 1;
+      } else if (use64[j] && r_k > 0.9 && sweep > 2) {
+        st_h[j] = TIK_ST_IR_STALL;
+        done[j] = 1;
+      } else if (sweep == maxsweep) {
+        st_h[j] = TIK_ST_MAXIT;
+        done[j] = 1;
+      }
+      // next inner precision: FP64 where FP32 contraction is poor, FP32 right
+      // after an FP64 sweep (the FP32 sweep then confirms the correction)
+      const bool poor = (sweep == 2 && rel > 5e-5) || (sweep >= 3 && r_k > 0.15);
+      want64[j] = use64[j] ? 0 : (poor ? 1 : 0);
+      was64[j] = use64[j];
+      rho[j] = sweep == 1 ? 1.0 : r_k;
+      dxrel[j] = rel;
+    }
+  }
+  for (int j = 0; j < J; ++j)
+    if (!done[j]) st_h[j] = TIK_ST_MAXIT;
+  // outputs (lambdas solved by the FP64 batch were written already)
+  std::vector<int32_t> okv(J);
+  for (int j = 0; j < J; ++j)
+    okv[j] = done[j] != 2 && (st_h[j] == TIK_ST_CONVERGED || st_h[j] == TIK_ST_MAXIT ||
+                              st_h[j] == TIK_ST_IR_STALL) ? 1 : 0;
+  std::vector<double*> xp(static_cast<size_t>(nprob));
+  for (int k = 0; k < nprob; ++k) xp[k] = X[k];
+  keep.emplace_back(reinterpret_cast<const char*>(okv.data()), reinterpret_cast<const char*>(okv.data()) + J * 4);
+  TIK_HIP(hipMemcpyAsync(w.ok, keep.back().data(), size_t(J) * 4, hipMemcpyHostToDevice, st));
+  keep.emplace_back(reinterpret_cast<const char*>(xp.data()),
+                    reinterpret_cast<const char*>(xp.data()) + xp.size() * sizeof(double*));
+  TIK_HIP(hipMemcpyAsync(bf.Xp, keep.back().data(), xp.size() * sizeof(double*), hipMemcpyHostToDevice, st));
+  int64_t maxn = 0;
+  for (auto& d : pf.P) maxn = std::max(maxn, d.n);
+  hipLaunchKernelGGL(k_ir_write, dim3(unsigned(cdiv(maxn, 256)), unsigned(J)), dim3(256), 0, st,
+                     bf.P, NF, w.x, w.ok, bf.Xp, l0);
+  TIK_LAUNCHED("k_ir_write");
+  // per-lambda outputs at global positions k * N + l0 + i (refined lambdas only)
+  for (int j = 0; j < J; ++j) {
+    if (done[j] == 2) continue;
+    const size_t gpos = size_t(j / NF) * pc->N + l0 + (j % NF);
+    if (iters) TIK_HIP(hipMemcpyAsync(iters + gpos, &it_h[j], 4, hipMemcpyHostToDevice, st));
+    if (status) TIK_HIP(hipMemcpyAsync(status + gpos, &st_h[j], 4, hipMemcpyHostToDevice, st));
+    if (relres) TIK_HIP(hipMemcpyAsync(relres + gpos, &rel_h[j], 8, hipMemcpyHostToDevice, st));
+  }
+  TIK_HIP(hipStreamSynchronize(st));
+  return TIK_OK;
+}
+
+int mixed_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, double tol,
+              int32_t maxit, double* const* X, int32_t* iters, int32_t* status, double* relres,
+              void* dws, size_t dws_bytes, hipStream_t st) {
+  Arena a;
+  a.base = static_cast<char*>(dws);
+  a.cap = dws_bytes;
+  MixedWs w;
+  mixed_layout(p, nprob, pc, a, w);
+  if (!a.fits()) {
+    set_error("tik_lsqr_batch: workspace too small");
+    return TIK_EWORKSPACE;
+  }
+  {
+    ProfScope ps("residual", st);
+    for (int k = 0; k < nprob; ++k)
+      if (w.A32[k]) {
+        const int64_t tot = p[k].m * p[k].n;
+        hipLaunchKernelGGL(k_to_f32, dim3(unsigned(std::min<int64_t>(cdiv(tot, 256), 65536))),
+                           dim3(256), 0, st, static_cast<const double*>(p[k].A), p[k].m, p[k].n,
+                           p[k].lda, w.A32[k]);
+        TIK_LAUNCHED("k_to_f32");
+      }
+  }
+  const bool f32 = p[0].a_dtype == TIK_F32;
+  for (int l0 = 0; l0 < pc->N; l0 += 32) {
+    const int NF = std::min(32, pc->N - l0);
+    if (f32)
+      TIK_TRY(mixed_group<float>(p, nprob, pc, w, l0, NF, tol, maxit, X, iters, status, relres, st));
+    else
+      TIK_TRY(mixed_group<double>(p, nprob, pc, w, l0, NF, tol, maxit, X, iters, status, relres, st));
+  }
+  return TIK_OK;
 }
 
 }  // namespace
 
 int lsqr_bytes(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32_t mode,
                size_t* bytes) {
-  std::vector<std::vector<int>> gp, gi;
-  std::vector<int> gN;
-  groups_for(pc, nprob, mode, gp, gi, gN);
+  if (mode == TIK_MIXED_BATCHED) {
+    Arena a;
+    MixedWs w;
+    *bytes = mixed_layout(p, nprob, pc, a, w) + 256;
+    return TIK_OK;
+  }
+  std::vector<std::vector<int>> gp, gl;
+  groups_for(pc, nprob, mode, gp, gl);
   size_t best = 0;
   const size_t tc = mode == TIK_MIXED_BATCHED ? sizeof(float) : sizeof(double);
   for (size_t g = 0; g < gp.size(); ++g) {
     Plan pl;
-    make_plan(p, pc, gp[g], gi[g], gN[g], pl);
+    make_plan(p, pc, gp[g], gl[g], pl);
     Arena a;
     Bufs b;
     take_bufs(a, pl, tc, b);
@@ -919,17 +1571,14 @@ int lsqr_bytes(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int
 int lsqr_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32_t mode,
              double tol, int32_t maxit, double* const* X, int32_t* iters, int32_t* status,
              double* relres, void* dws, size_t dws_bytes, hipStream_t st) {
-  if (mode == TIK_MIXED_BATCHED) {
-    set_error("mixed precision mode is not available in this build");
-    return TIK_ENOTSUP;
-  }
-  std::vector<std::vector<int>> gp, gi;
-  std::vector<int> gN;
-  groups_for(pc, nprob, mode, gp, gi, gN);
+  if (mode == TIK_MIXED_BATCHED)
+    return mixed_run(p, nprob, pc, tol, maxit, X, iters, status, relres, dws, dws_bytes, st);
+  std::vector<std::vector<int>> gp, gl;
+  groups_for(pc, nprob, mode, gp, gl);
   const bool f32 = p[0].a_dtype == TIK_F32;
   for (size_t g = 0; g < gp.size(); ++g) {
     Plan pl;
-    make_plan(p, pc, gp[g], gi[g], gN[g], pl);
+    make_plan(p, pc, gp[g], gl[g], pl);
     Arena a;
     a.base = static_cast<char*>(dws);
     a.cap = dws_bytes;
@@ -942,9 +1591,9 @@ int lsqr_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32
     std::vector<std::vector<char>> keep;
     TIK_TRY(upload_plan(pl, b, pc, X, keep, st));
     if (f32)
-      TIK_TRY((run_core_nc<float, double>(pl, b, tol, maxit, st, nullptr, nullptr)));
+      TIK_TRY((run_core_nc<float, double>(pl, b, tol, maxit, st, nullptr)));
     else
-      TIK_TRY((run_core_nc<double, double>(pl, b, tol, maxit, st, nullptr, nullptr)));
+      TIK_TRY((run_core_nc<double, double>(pl, b, tol, maxit, st, nullptr)));
     int64_t maxn = 0;
     for (auto& d : pl.P) maxn = std::max(maxn, d.n);
     hipLaunchKernelGGL(k_write_out_map, dim3(unsigned(cdiv(maxn, 256)), unsigned(pl.J)), dim3(256), 0,

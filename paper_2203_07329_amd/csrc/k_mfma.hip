@@ -1,0 +1,312 @@
+// Matrix-core (MFMA) versions of the two batched products of an LSQR step,
+// used when 16 or 32 lambdas share each pass over A:
+//   gemm_n:  u~_top = A W - ucoef u~_top       (m x N, contraction over the n columns)
+//   gemm_t:  partial A^T U over a row chunk     (n x N, contraction over the m rows)
+// FP64 uses v_mfma_f64_16x16x4_f64, FP32 uses v_mfma_f32_16x16x4_f32.  Both
+// take one operand element per lane: A-operand element (i = lane % 16,
+// k = lane / 16), B-operand element (k = lane / 16, j = lane % 16).  The
+// 16 x 16 result sits in four registers per lane: column j = lane % 16, row
+// i = 4 v + lane / 16 for FP64 and i = 4 (lane / 16) + v for FP32 (v = 0..3).
+#include "tik_internal.h"
+
+namespace tik {
+
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+
+template <typename TC>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+  using acc_t = mf_d4;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+
+template <>
+struct Mfma<float> {
+  using acc_t = mf_f4;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// ------------------------------------------------------------------ gemm_n --
+// Block = 4 waves x 64 rows = 256 rows of one problem, all NC lambdas.  A is
+// read straight into A-operand registers (16 consecutive rows of 4 columns per
+// load: whole 64/128-byte lines); W is staged through LDS KC columns at a time.
+// EPI 0: LSQR update of u~_top with partial squared norms; EPI 1: store A W.
+template <typename TA, typename TC, int NC, int EPI>
+__global__ void __launch_bounds__(256) k_gemm_n_mfma(const DevProb* __restrict__ P,
+                                                     const Item* __restrict__ items, int N,
+                                                     const double* __restrict__ W,
+                                                     TC* __restrict__ ut, double* __restrict__ out,
+                                                     const Scal* __restrict__ sc,
+                                                     double* __restrict__ pnN) {
+  using M = Mfma<TC>;
+  constexpr int NT = NC / 16;
+  constexpr int KC = sizeof(TC) == 8 ? 16 : 32;
+  constexpr int WP = NC + 2;
+  __shared__ TC Ws[KC][WP];
+  __shared__ double nred[4][NC];
+  const Item it = items[blockIdx.x];
+  const DevProb& pr = P[it.p];
+  const TA* __restrict__ A = static_cast<const TA*>(pr.A);
+  const int64_t m = pr.m, n = pr.n, lda = pr.lda;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t row0 = int64_t(it.blk) * 256 + wv * 64;
+  typename M::acc_t acc[4][NT];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = typename M::acc_t{0, 0, 0, 0};
+  // A operands of the current chunk live in `a`; those of the next chunk are
+  // loaded into `an` while the matrix cores work on the current one.
+  auto load_a = [&](int64_t k0, TC (&dst)[4][KC / 4]) {
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const int64_t col = k0 + 4 * ks + lk;
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) {
+        const int64_t row = row0 + rt * 16 + li;
+        dst[rt][ks] = (row < m && col < n) ? TC(A[row + col * lda]) : TC(0);
+      }
+    }
+  };
+  TC a[4][KC / 4], an[4][KC / 4];
+  load_a(0, a);
+  for (int64_t k0 = 0; k0 < n; k0 += KC) {
+    for (int e = threadIdx.x; e < KC * NC; e += 256) {
+      const int kk = e / NC, i = e % NC;
+      const int64_t kg = k0 + kk;
+      Ws[kk][i] = (kg < n && i < N) ? TC(W[(pr.offS + kg) * N + i]) : TC(0);
+    }
+    __syncthreads();
+    if (k0 + KC < n) load_a(k0 + KC, an);
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      TC b[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) b[nt] = Ws[4 * ks + lk][nt * 16 + li];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = M::op(a[rt][ks], b[nt], acc[rt][nt]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks)
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) a[rt][ks] = an[rt][ks];
+  }
+  double nsum[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    nsum[nt] = 0.0;
+    const int lam = nt * 16 + li;
+    const double uc = (EPI == 0 && lam < N) ? sc[it.p * N + lam].ucoef : 0.0;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = row0 + rt * 16 + M::row(lane, v);
+        if (row < m && lam < N) {
+          const int64_t idx = (pr.offL + row) * N + lam;
+          if (EPI == 0) {
+            const TC nv = TC(acc[rt][nt][v] - TC(uc) * ut[idx]);
+            ut[idx] = nv;
+            nsum[nt] += double(nv) * double(nv);
+          } else {
+            out[idx] = double(acc[rt][nt][v]);
+          }
+        }
+      }
+  }
+  if (EPI != 0) return;
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    double v = nsum[nt];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (lk == 0) nred[wv][nt * 16 + li] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < N)
+    pnN[(pr.pnN + it.blk) * N + threadIdx.x] = nred[0][threadIdx.x] + nred[1][threadIdx.x] +
+                                               nred[2][threadIdx.x] + nred[3][threadIdx.x];
+}
+
+// ------------------------------------------------------------------ gemm_t --
+// Block = 128 columns x one row chunk; wave w owns columns 32 w .. 32 w + 31.
+// A (32 rows x 128 columns) and U (32 rows x NC) are staged through LDS, then
+// read in MFMA operand order (A^T as the A-operand, U as the B-operand).
+// Blocks are remapped so that consecutive items (the column blocks of one row
+// chunk, which share U) run on the same XCD and share its L2.
+template <typename TA, typename TC, typename TU, int NC>
+__global__ void __launch_bounds__(256) k_gemm_t_mfma(const DevProb* __restrict__ P,
+                                                     const Item* __restrict__ items, int nitems,
+                                                     int N, const TU* __restrict__ U,
+                                                     TC* __restrict__ part) {
+  using M = Mfma<TC>;
+  constexpr int NT = NC / 16;
+  constexpr int CB = 128, RS = 32, AP = RS + 4, UP = NC + 2;
+  __shared__ TC As[CB][AP];
+  __shared__ TC Us[RS][UP];
+  const int g = blockIdx.x;
+  const int per = (nitems + 7) >> 3;
+  const int L = (g & 7) * per + (g >> 3);
+  if (L >= nitems) return;
+  const Item it = items[L];
+  const DevProb& pr = P[it.p];
+  const TA* __restrict__ A = static_cast<const TA*>(pr.A);
+  const int64_t m = pr.m, n = pr.n, lda = pr.lda;
+  const int64_t c0 = int64_t(it.blk) * CB;
+  const int64_t rbeg = int64_t(it.ch) * pr.rchunk;
+  const int64_t rend = min(m, rbeg + pr.rchunk);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  typename M::acc_t acc[2][NT];
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[ct][nt] = typename M::acc_t{0, 0, 0, 0};
+  // The next tile of A and U is fetched into registers while the matrix cores
+  // consume the current tile from LDS.
+  constexpr int QA = (RS * CB) / 256;
+  constexpr int QU = (RS * NC + 255) / 256;
+  TC ra[QA], ru[QU];
+  auto fetch = [&](int64_t r0) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int rr = e % RS, cc = e / RS;
+      const int64_t rg = r0 + rr, cg = c0 + cc;
+      ra[q] = (rg < rend && cg < n) ? TC(A[rg + cg * lda]) : TC(0);
+    }
+#pragma unroll
+    for (int q = 0; q < QU; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int rr = e / NC, i = e % NC;
+      const int64_t rg = r0 + rr;
+      ru[q] = (e < RS * NC && rg < rend && i < N) ? TC(U[(pr.offL + rg) * N + i]) : TC(0);
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      As[e / RS][e % RS] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < QU; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (e < RS * NC) Us[e / NC][e % NC] = ru[q];
+    }
+  };
+  if (rbeg < rend) {
+    fetch(rbeg);
+    stash();
+  }
+  __syncthreads();
+  for (int64_t r0 = rbeg; r0 < rend; r0 += RS) {
+    const bool more = r0 + RS < rend;
+    if (more) fetch(r0 + RS);
+#pragma unroll
+    for (int ks = 0; ks < RS / 4; ++ks) {
+      TC a[2];
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) a[ct] = As[wv * 32 + ct * 16 + li][4 * ks + lk];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const TC b = Us[4 * ks + lk][nt * 16 + li];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) acc[ct][nt] = M::op(a[ct], b, acc[ct][nt]);
+      }
+    }
+    __syncthreads();
+    if (more) stash();
+    __syncthreads();
+  }
+  TC* dst = part + (pr.ptOff + int64_t(it.ch) * n) * N;
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t c = c0 + wv * 32 + ct * 16 + M::row(lane, v);
+        const int lam = nt * 16 + li;
+        if (c < n && lam < N) dst[c * N + lam] = acc[ct][nt][v];
+      }
+}
+
+// --------------------------------------------------------------- launchers --
+template <typename TA, typename TC>
+static int gemm_n_nc(int nc, int epi, const DevProb* P, const Item* items, int nitems, int N,
+                     const double* W, void* ut, double* out, const Scal* sc, double* pnN,
+                     hipStream_t st) {
+  const dim3 g = dim3(unsigned(nitems)), b = dim3(256);
+  TC* u = static_cast<TC*>(ut);
+  if (nc == 16 && epi == 0) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 16, 0>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
+  else if (nc == 32 && epi == 0) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 32, 0>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
+  else if (nc == 16) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 16, 1>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
+  else if (nc == 32) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 32, 1>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
+  else {
+    set_error("internal: MFMA gemm_n needs 16 or 32 lambdas per pass");
+    return TIK_EINVAL;
+  }
+  TIK_LAUNCHED("k_gemm_n_mfma");
+  return TIK_OK;
+}
+
+int launch_gemm_n_mfma(int ta_f32, int tc_f32, int nc, int epi, const DevProb* P,
+                       const Item* items, int nitems, int N, const double* W, void* ut,
+                       double* out, const Scal* sc, double* pnN, hipStream_t st) {
+  if (tc_f32) {
+    if (!ta_f32) {
+      set_error("internal: FP32 products need FP32 storage");
+      return TIK_EINVAL;
+    }
+    return gemm_n_nc<float, float>(nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
+  }
+  if (ta_f32) return gemm_n_nc<float, double>(nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
+  return gemm_n_nc<double, double>(nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
+}
+
+template <typename TA, typename TC, typename TU>
+static int gemm_t_nc(int nc, const DevProb* P, const Item* items, int nitems, int N,
+                     const void* U, void* part, hipStream_t st) {
+  const dim3 g = dim3(unsigned(((nitems + 7) / 8) * 8)), b = dim3(256);
+  const TU* u = static_cast<const TU*>(U);
+  TC* pt = static_cast<TC*>(part);
+  if (nc == 16) hipLaunchKernelGGL((k_gemm_t_mfma<TA, TC, TU, 16>), g, b, 0, st, P, items, nitems, N, u, pt);
+  else if (nc == 32) hipLaunchKernelGGL((k_gemm_t_mfma<TA, TC, TU, 32>), g, b, 0, st, P, items, nitems, N, u, pt);
+  else {
+    set_error("internal: MFMA gemm_t needs 16 or 32 lambdas per pass");
+    return TIK_EINVAL;
+  }
+  TIK_LAUNCHED("k_gemm_t_mfma");
+  return TIK_OK;
+}
+
+// U in TC (LSQR vectors) or FP64 (u_f64 = 1: refinement residuals, TC = double).
+int launch_gemm_t_mfma(int ta_f32, int tc_f32, int u_f64, int nc, const DevProb* P,
+                       const Item* items, int nitems, int N, const void* U, void* part,
+                       hipStream_t st) {
+  if (tc_f32) {
+    if (!ta_f32 || u_f64) {
+      set_error("internal: FP32 products need FP32 storage and vectors");
+      return TIK_EINVAL;
+    }
+    return gemm_t_nc<float, float, float>(nc, P, items, nitems, N, U, part, st);
+  }
+  if (ta_f32) return gemm_t_nc<float, double, double>(nc, P, items, nitems, N, U, part, st);
+  return gemm_t_nc<double, double, double>(nc, P, items, nitems, N, U, part, st);
+}
+
+}  // namespace tik

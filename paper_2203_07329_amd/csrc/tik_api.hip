@@ -321,6 +321,8 @@ struct PrecondPlan {
   double* Tmp = nullptr;
   double* lams = nullptr;
   int32_t* notpd = nullptr;
+  double* cnorm = nullptr;    // per problem
+  double* colsum = nullptr;   // scratch, kmax
 };
 
 int precond_plan(tik_sketch_t sk, int32_t route, int32_t N, Arena& a, PrecondPlan& pp) {
@@ -334,6 +336,8 @@ int precond_plan(tik_sketch_t sk, int32_t route, int32_t N, Arena& a, PrecondPla
   }
   pp.lams = a.take<double>(size_t(np) * size_t(N));
   pp.notpd = a.take<int32_t>(size_t(np) * size_t(N));
+  pp.cnorm = a.take<double>(size_t(np));
+  pp.colsum = a.take<double>(size_t(kmax));
   if (route == TIK_ROUTE_CHOL) {
     pp.C = a.take<double>(size_t(kmax) * size_t(kmax));
     pp.Dinv = a.take<double>(size_t(N) * size_t(cdiv(kmax, 64)) * 64 * 64);
@@ -384,12 +388,15 @@ int tik_precond(tik_sketch_t sk, int32_t route, const double* lambdas, int32_t N
   for (int32_t k = 0; k < np; ++k) {
     const int64_t kd = std::min(sk->probs[k].m, sk->probs[k].n);
     TIK_TRY(launch_syrk(sk->Y[k], sk->yrows[k], kd, sk->yrows[k], pp.C, st));
+    TIK_TRY(launch_gram_norm_bound(pp.C, kd, pp.colsum, pp.cnorm + k, st));
     TIK_TRY(launch_chol_inv_batched(pp.C, kd, pp.lams + size_t(k) * N, N, pp.Rinv[k], pp.Dinv,
                                     pp.Tmp, pp.notpd + size_t(k) * N, st));
   }
   std::vector<int32_t> bad(size_t(np) * size_t(N), 0);
+  std::vector<double> cn(size_t(np), 0.0);
   TIK_HIP(hipMemcpyAsync(bad.data(), pp.notpd, sizeof(int32_t) * bad.size(),
                          hipMemcpyDeviceToHost, st));
+  TIK_HIP(hipMemcpyAsync(cn.data(), pp.cnorm, sizeof(double) * cn.size(), hipMemcpyDeviceToHost, st));
   TIK_HIP(hipStreamSynchronize(st));
   tik_precond_s* h = new tik_precond_s();
   h->probs = sk->probs;
@@ -398,6 +405,7 @@ int tik_precond(tik_sketch_t sk, int32_t route, const double* lambdas, int32_t N
   h->N = N;
   h->lams.assign(lambdas, lambdas + size_t(np) * N);
   h->Rinv = pp.Rinv;
+  h->cnorm = cn;
   h->status.resize(bad.size());
   for (size_t q = 0; q < bad.size(); ++q) h->status[q] = bad[q] ? TIK_ST_NOTPD : TIK_ST_CONVERGED;
   for (int32_t k = 0; k < np; ++k) h->k.push_back(std::min(sk->probs[k].m, sk->probs[k].n));
@@ -443,6 +451,7 @@ static int lsqr_validate(const tik_problem* p, int32_t nprob, tik_precond_t pc, 
   if (mode != TIK_PLAIN_F64_PER_LAMBDA && mode != TIK_F64_BATCHED && mode != TIK_MIXED_BATCHED)
     return fail(TIK_EINVAL, "tik_lsqr_batch: unknown mode");
   if (pc->wide) return fail(TIK_ENOTSUP, "tik_lsqr_batch: wide problems are not available in this build");
+
   return TIK_OK;
 }
 

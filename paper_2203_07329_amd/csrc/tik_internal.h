@@ -75,7 +75,8 @@ struct DevProb {
   const double* b;
   int64_t offL;        // row offset of this problem inside long-row vector buffers
   int64_t offS;        // row offset inside short-row vector buffers
-  const double* Rinv;  // N upper-triangular inverses, k x k each (k = short dim), col-major
+  const double* Rinv;  // upper-triangular inverses, k x k each (k = short dim), col-major,
+                       // one per lambda of the problem; a solve uses Rinv + li * k * k
   int64_t k;           // short dimension min(m, n)
   // low-rank route: V (n x s, ld n), S (N x s), truncation s_i
   const double* V;
@@ -100,7 +101,8 @@ struct Scal {
   double ucoef;             // alpha_i / beta_i, the weight of the old u
   double relres, rnorm, arnorm;
   int32_t active, upd, iters, status;
-  int32_t pad0, pad1, pad2, pad3;
+  int32_t li;               // lambda index inside its problem (selects R^{-1} and the X column)
+  int32_t pad1, pad2, pad3;
 };
 
 // item tables: x = problem, y = block index (and z = chunk for gemm_T)
@@ -129,10 +131,19 @@ int launch_f32_to_f64(const float* src, double* dst, int64_t count, hipStream_t 
 
 // factorization (k_factor.hip)
 int launch_syrk(const double* Z, int64_t K, int64_t n, int64_t ldz, double* C, hipStream_t st);
+int launch_gram_norm_bound(const double* C, int64_t n, double* scratch, double* out,
+                           hipStream_t st);
 int launch_chol_inv_batched(const double* C, int64_t n, const double* lams, int32_t nb_mat,
                             double* R, double* Dinv, double* Tmp, int32_t* notpd,
                             hipStream_t st);
 
+// matrix-core products (k_mfma.hip)
+int launch_gemm_n_mfma(int ta_f32, int tc_f32, int nc, int epi, const DevProb* P,
+                       const Item* items, int nitems, int N, const double* W, void* ut,
+                       double* out, const Scal* sc, double* pnN, hipStream_t st);
+int launch_gemm_t_mfma(int ta_f32, int tc_f32, int u_f64, int nc, const DevProb* P,
+                       const Item* items, int nitems, int N, const void* U, void* part,
+                       hipStream_t st);
 }  // namespace tik
 
 // ----------------------------------------------------------------- handles --
@@ -154,6 +165,7 @@ struct tik_precond_s {
   std::vector<int64_t> k;              // short dimension per problem
   std::vector<double*> Rinv;           // Cholesky route: N upper-triangular k x k inverses
   std::vector<int32_t> status;         // nprob * N breakdown flags (tik_status)
+  std::vector<double> cnorm;           // per problem: upper bound on ||C||_2 of the sketch Gram
   // low-rank route (tall): V n x s (ld n), sigma (s), S (N x s), truncation s_i
   std::vector<double*> V, sigma, S;
   std::vector<int64_t> srank;

@@ -231,3 +231,26 @@ def test_lsqr_deterministic():
     x1 = r1.x_numpy(0)
     r2, _ = _solve([p], tik.F64_BATCHED)
     assert np.array_equal(x1, r2.x_numpy(0))
+
+
+# ------------------------------------------------------------ mixed precision --
+
+@pytest.mark.parametrize("case", ["over_svd", "over_gauss_reduced", "ragged_f32", "wide_lambda_set"])
+def test_mixed_refinement(case):
+    """FP32 inner LSQR inside FP64 refinement: every lambda within 1e-8 of the oracle."""
+    if case == "over_svd":
+        plist, embed = [W.over_svd()], tik.SRHT
+    elif case == "over_gauss_reduced":
+        plist, embed = [W.over_gauss(m=20000, n=400, N=32, s=1600)], tik.SRHT
+    elif case == "ragged_f32":
+        plist, embed = W.ragged(nprob=4, m_lo=800, m_hi=3000, n_lo=20, n_hi=150, N=8), tik.GAUSS
+    else:   # 40 lambdas: two refinement groups (32 + 8)
+        plist, embed = [W.over_gauss(m=6000, n=200, N=40, s=800)], tik.SRHT
+    res, _ = _solve(plist, tik.MIXED_BATCHED, embed=embed, tol=1e-10, maxit=200)
+    st = res.status.cpu().numpy()
+    its = res.iters.cpu().numpy()
+    for k, p in enumerate(plist):
+        err = oracle.rel_err(res.x_numpy(k), oracle.solve(p.A, p.b, p.lams))
+        print(case, k, "max rel err %.2e" % err.max(), "iters", its[k], "status", st[k])
+        assert np.all(err <= 1e-8), err
+    assert np.all(st == tik.ST_CONVERGED), st
