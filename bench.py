@@ -50,6 +50,8 @@ def main() -> int:
     ap.add_argument("--mode", default="auto", choices=["auto", "mixed", "f64"])
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle (profiling runs)")
+    ap.add_argument("--calibrate-copy", type=float, default=0.0,
+                    help="GiB: also run one plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of "
@@ -115,9 +117,21 @@ def main() -> int:
         ms, n = tik.prof_query(f)
         if n:
             fam[f] = (ms / args.steps, n // args.steps, ms / n)
+    n32, n64 = tik.lsqr_info()
+    if mode == tik.MIXED_BATCHED:
+        dtype = "f32+f64" if n32 > 0 else "f64"
     X = res.x_numpy(0)
     iters = res.iters.cpu().numpy()[0]
     status = res.status.cpu().numpy()[0]
+    if args.calibrate_copy > 0:
+        nel = int(args.calibrate_copy * (1 << 30)) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nel * 8} bytes read, {nel * 8} bytes written")
+        del src, dst
 
     # ---- plain FP64 per-lambda loop
     plain = None
@@ -197,6 +211,8 @@ def main() -> int:
         "roofline": roof,
         "cpu_baseline": cpu,
         "solves_ok": n_ok,
+        "lambdas_fp32_refined": n32,
+        "lambdas_fp64": n64,
         "max_rel_err": None if err is None else float(np.max(err)),
         "iters_max": int(iters.max()),
         "status_ok": bool(np.all(status <= 1)),

@@ -198,6 +198,11 @@ int tik_lsqr_batch(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_
                    int32_t* status, double* relres, void* dws, size_t dws_bytes,
                    tik_stream_t stream);
 
+/* How the calling thread's last tik_lsqr_batch split its lambdas: solved with
+   FP32 products inside FP64 refinement (*fp32) or with FP64 products
+   (*fp64).  PLAIN_F64_PER_LAMBDA and F64_BATCHED count every lambda as FP64. */
+int tik_lsqr_info(int32_t* fp32, int32_t* fp64);
+
 /* Free the host structs (device workspaces belong to the caller). */
 void tik_sketch_free(tik_sketch_t sk);
 void tik_precond_free(tik_precond_t pc);

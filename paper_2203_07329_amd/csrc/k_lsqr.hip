@@ -1132,6 +1132,7 @@ struct MixedWs {
   size_t cap32 = 0, cap64 = 0;
   char* baseF = nullptr;          // FP64 refinement plan region
   size_t capF = 0;
+  bool converted = false;         // FP32 copies made
 };
 
 void all_lambdas(int N0, int N, std::vector<int>& ls) {
@@ -1297,7 +1298,7 @@ int inner_solve(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, co
 }
 
 template <typename TA64>
-int mixed_group(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, const MixedWs& w,
+int mixed_group(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, MixedWs& w,
                 int l0, int NF, double tol, int maxit, double* const* X, int32_t* iters,
                 int32_t* status, double* relres, hipStream_t st) {
   std::vector<int> ps;
@@ -1367,6 +1368,7 @@ int mixed_group(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, co
     }
     TIK_TRY(upload_plan(ph, bh, pc, X, keep, st));
     const double tol_h = std::max(1e-3 * tol, 1e-14);
+    note_split(0, int32_t(hard.size()) * nprob);
     TIK_TRY((run_core_nc<TA64, double>(ph, bh, tol_h, maxit, st, nullptr)));
     int64_t mn = 0;
     for (auto& d : ph.P) mn = std::max(mn, d.n);
@@ -1382,6 +1384,24 @@ int mixed_group(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, co
   }
   const int maxsweep = 12;
   const double tol32 = std::max(tol, 1e-6);
+  {
+    int32_t n32 = 0;
+    for (int j = 0; j < J; ++j) n32 += done[j] == 0;
+    note_split(n32, 0);
+    if (n32 > 0 && !w.converted) {
+      // FP32 copies of FP64-stored problems, made once per call
+      ProfScope ps("residual", st);
+      for (int k = 0; k < nprob; ++k)
+        if (w.A32[k]) {
+          const int64_t tot = p[k].m * p[k].n;
+          hipLaunchKernelGGL(k_to_f32, dim3(unsigned(std::min<int64_t>(cdiv(tot, 256), 65536))),
+                             dim3(256), 0, st, static_cast<const double*>(p[k].A), p[k].m, p[k].n,
+                             p[k].lda, w.A32[k]);
+          TIK_LAUNCHED("k_to_f32");
+        }
+      w.converted = true;
+    }
+  }
   std::vector<double> nrm(2 * size_t(J));
   std::vector<int32_t> stats(2 * size_t(J));
   for (int sweep = 1; sweep <= maxsweep; ++sweep) {
@@ -1520,17 +1540,6 @@ int mixed_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, doub
     set_error("tik_lsqr_batch: workspace too small");
     return TIK_EWORKSPACE;
   }
-  {
-    ProfScope ps("residual", st);
-    for (int k = 0; k < nprob; ++k)
-      if (w.A32[k]) {
-        const int64_t tot = p[k].m * p[k].n;
-        hipLaunchKernelGGL(k_to_f32, dim3(unsigned(std::min<int64_t>(cdiv(tot, 256), 65536))),
-                           dim3(256), 0, st, static_cast<const double*>(p[k].A), p[k].m, p[k].n,
-                           p[k].lda, w.A32[k]);
-        TIK_LAUNCHED("k_to_f32");
-      }
-  }
   const bool f32 = p[0].a_dtype == TIK_F32;
   for (int l0 = 0; l0 < pc->N; l0 += 32) {
     const int NF = std::min(32, pc->N - l0);
@@ -1590,6 +1599,7 @@ int lsqr_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32
     }
     std::vector<std::vector<char>> keep;
     TIK_TRY(upload_plan(pl, b, pc, X, keep, st));
+    note_split(0, pl.J);
     if (f32)
       TIK_TRY((run_core_nc<float, double>(pl, b, tol, maxit, st, nullptr)));
     else

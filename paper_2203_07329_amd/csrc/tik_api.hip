@@ -13,6 +13,16 @@ namespace tik {
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 
+static thread_local int32_t g_split32 = 0, g_split64 = 0;
+void note_split(int32_t fp32, int32_t fp64) {
+  g_split32 += fp32;
+  g_split64 += fp64;
+}
+void last_split(int32_t* fp32, int32_t* fp64) {
+  *fp32 = g_split32;
+  *fp64 = g_split64;
+}
+
 static int fail(int rc, const std::string& msg) {
   g_err = msg;
   return rc;
@@ -474,8 +484,15 @@ int tik_lsqr_batch(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_
   size_t need = 0;
   TIK_TRY(lsqr_bytes(p, nprob, pc, mode, &need));
   TIK_TRY(check_ws(dws, dws_bytes, need, "tik_lsqr_batch"));
+  g_split32 = g_split64 = 0;
   return lsqr_run(p, nprob, pc, mode, tol, maxit, X, iters, status, relres, dws, dws_bytes,
                   static_cast<hipStream_t>(stream));
+}
+
+int tik_lsqr_info(int32_t* fp32, int32_t* fp64) {
+  if (!fp32 || !fp64) return fail(TIK_EINVAL, "tik_lsqr_info: NULL argument");
+  last_split(fp32, fp64);
+  return TIK_OK;
 }
 
 }  // extern "C"

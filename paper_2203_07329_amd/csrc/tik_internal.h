@@ -174,6 +174,9 @@ struct tik_precond_s {
 };
 
 namespace tik {
+// split of the last solve on this thread (fp32-refined, fp64) lambdas
+void note_split(int32_t fp32, int32_t fp64);
+void last_split(int32_t* fp32, int32_t* fp64);
 // solve driver (k_lsqr.hip)
 int lsqr_bytes(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32_t mode,
                size_t* bytes);

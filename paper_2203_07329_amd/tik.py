@@ -36,6 +36,7 @@ EXPORTS = [
     "tik_precond_data",
     "tik_lsqr_batch_bytes", "tik_lsqr_batch", "tik_sketch_free", "tik_precond_free",
     "tik_last_error", "tik_version", "tik_prof_enable", "tik_prof_reset", "tik_prof_query",
+    "tik_lsqr_info",
 ]
 
 
@@ -81,9 +82,10 @@ def lib() -> ctypes.CDLL:
     L.tik_last_error.restype = ctypes.c_char_p
     L.tik_prof_enable.argtypes = [i32]
     L.tik_prof_query.argtypes = [ctypes.c_char_p, P(dbl), P(i64)]
+    L.tik_lsqr_info.argtypes = [P(i32), P(i32)]
     for name in ("tik_sketch_bytes", "tik_sketch", "tik_sketch_data", "tik_precond_bytes",
                  "tik_precond", "tik_precond_data", "tik_lsqr_batch_bytes", "tik_lsqr_batch", "tik_version",
-                 "tik_prof_enable", "tik_prof_reset", "tik_prof_query"):
+                 "tik_prof_enable", "tik_prof_reset", "tik_prof_query", "tik_lsqr_info"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -283,6 +285,13 @@ def solve(probs: Problems, lambdas, embed: int = SRHT, s: Optional[Sequence[int]
     sk = sketch(probs, embed, s, seed, sketch_dtype)
     pc = precond(sk, lambdas, route, alpha)
     return lsqr_batch(probs, pc, mode, tol, maxit), pc
+
+
+def lsqr_info():
+    """(lambdas refined with FP32 products, lambdas solved with FP64 products) of the last call."""
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().tik_lsqr_info(ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 # ------------------------------------------------------------- profiling ---
