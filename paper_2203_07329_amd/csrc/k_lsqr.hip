@@ -149,14 +149,16 @@ __global__ void __launch_bounds__(BLK) k_gemm_n(const DevProb* __restrict__ P,
   const int tr = threadIdx.x % RB, ks = threadIdx.x / RB;
   const int64_t r = int64_t(it.blk) * RB + tr;
   const bool live = r < m;
+  const int64_t kbeg = int64_t(it.ch) * pr.cchunk;
+  const int64_t kend = min(n, kbeg + pr.cchunk);
   TC acc[NC];
 #pragma unroll
   for (int i = 0; i < NC; ++i) acc[i] = TC(0);
-  for (int64_t k0 = 0; k0 < n; k0 += KC) {
-    const int kc = int(min<int64_t>(KC, n - k0));
+  for (int64_t k0 = kbeg; k0 < kend; k0 += KC) {
+    const int kc = int(min<int64_t>(KC, kend - k0));
     for (int e = threadIdx.x; e < KC * NC; e += BLK) {
       const int kk = e / NC, i = e % NC;
-      Ws[kk][i] = (kk < kc && i < N) ? TC(W[(pr.offS + k0 + kk) * N + i]) : TC(0);
+      Ws[kk][i] = (kk < kc && i < N) ? TC(W[(pr.offC + k0 + kk) * N + i]) : TC(0);
     }
     __syncthreads();
     if (live) {
@@ -204,12 +206,14 @@ __global__ void __launch_bounds__(BLK) k_gemm_n(const DevProb* __restrict__ P,
       double v = 0.0;
       if (writer) {
         if (EPI == 0) {
-          const int64_t idx = (pr.offL + r) * N + i;
+          const int64_t idx = (pr.offR + r) * N + i;
           const TC nv = TC(acc[i] - TC(sc[it.p * N + i].ucoef) * ut[idx]);
           ut[idx] = nv;
           v = double(nv) * double(nv);
+        } else if (EPI == 1) {
+          out[(pr.offR + r) * N + i] = double(acc[i]);
         } else {
-          out[(pr.offL + r) * N + i] = double(acc[i]);
+          ut[(pr.pnOff + int64_t(it.ch) * m + r) * N + i] = acc[i];
         }
       }
       if (EPI == 0) {
@@ -280,7 +284,7 @@ __global__ void __launch_bounds__(BLK) k_gemm_t(const DevProb* __restrict__ P,
     for (int e = threadIdx.x; e < RS * NC; e += BLK) {
       const int rr = e / NC, i = e % NC;
       const int64_t rg = r0 + rr;
-      Us[rr][i] = (rg < rend && i < N) ? TC(U[(pr.offL + rg) * uoffL_stride + i]) : TC(0);
+      Us[rr][i] = (rg < rend && i < N) ? TC(U[(pr.offR + rg) * uoffL_stride + i]) : TC(0);
     }
     __syncthreads();
     if (NC >= 4) {
@@ -366,7 +370,9 @@ __global__ void __launch_bounds__(BLK) k_reduce_t(const DevProb* __restrict__ P,
 // v~[c] = sum_{r <= c} Rinv[r, c] t[r] - beta v[c] for a block of 4 * CPW
 // columns of one (problem, lambda); each wave owns CPW columns, lanes stride
 // the rows (coalesced along the columns of Rinv and along t).
-template <int CPW>
+// WIDE (Algorithm 2, R^{-T} applied on the u side): q = R^{-T} h - alpha u with
+// the partial norms going to the beta array.
+template <int CPW, bool WIDE>
 __global__ void __launch_bounds__(BLK) k_trmv_t(const DevProb* __restrict__ P,
                                                 const Item* __restrict__ items, int N,
                                                 const double* __restrict__ t,
@@ -403,14 +409,14 @@ __global__ void __launch_bounds__(BLK) k_trmv_t(const DevProb* __restrict__ P,
     const int64_t c = cbase + q2;
     if (c < k) {
       const int64_t idx = (pr.offS + c) * N + i;
-      const double nv = s - S.beta_new * v[idx];
+      const double nv = s - (WIDE ? S.alpha : S.beta_new) * v[idx];
       if (lane == 0) q[idx] = nv;
       nrm += nv * nv;
     }
   }
   if (lane != 0) nrm = 0.0;
   const double tot = block_sum(nrm, red);
-  if (threadIdx.x == 0) pnQ[(pr.pnQ + it.blk) * N + i] = tot;
+  if (threadIdx.x == 0) pnQ[((WIDE ? pr.pnN : pr.pnQ) + it.blk) * N + i] = tot;
 }
 
 // ------------------------------------------------------------ fin_alpha ----
@@ -514,6 +520,8 @@ __global__ void __launch_bounds__(BLK) k_fin_alpha(const DevProb* __restrict__ P
 // w[r] = ialpha sum_{c >= r} Rinv[r, c] v~[c]; v = ialpha v~; x, e updates.
 // 256 threads = 16 rows x 16 column slices; a wave reads 16 consecutive rows
 // of 4 columns (full 128-byte lines) per load.
+// WIDE: y = R^{-1} q / beta and u = q / beta (no x, e updates).
+template <bool WIDE>
 __global__ void __launch_bounds__(BLK) k_trmv(const DevProb* __restrict__ P,
                                               const Item* __restrict__ items, int N,
                                               const double* __restrict__ q,
@@ -550,10 +558,12 @@ __global__ void __launch_bounds__(BLK) k_trmv(const DevProb* __restrict__ P,
 #pragma unroll
   for (int q2 = 0; q2 < 16; ++q2) sum += red[q2][tr];
   const Scal& S = sc[j];
-  const double wr = sum * S.ialpha;
+  const double scale = WIDE ? S.ibeta : S.ialpha;
+  const double wr = sum * scale;
   const int64_t idx = (pr.offS + r) * N + i;
-  v[idx] = q[idx] * S.ialpha;
+  v[idx] = q[idx] * scale;
   w[idx] = wr;
+  if (WIDE) return;
   if (init) {
     x[idx] = 0.0;
     e[idx] = wr;
@@ -753,6 +763,153 @@ __global__ void k_ir_write(const DevProb* __restrict__ P, int NF, const double* 
     Xout[p][c + int64_t(l0 + i) * pr.n] = x[(pr.offS + c) * NF + i];
 }
 
+// ============================================================ wide problems ==
+// Algorithm 2 (m < n): LSQR on M = R^{-T} [A sqrt(lam) I] from z = 0, so the
+// minimum-norm z results and x is its top n entries (eq. regLLSunderiter).
+//   beta u  = R^{-T} (A v_top + sqrt(lam) v_bot) - alpha u
+//   alpha v = [A^T (R^{-1} u); sqrt(lam) R^{-1} u] - beta v
+// "long" rows are the n columns of A (v_top, d_top, x), "short" rows the m rows
+// (u, y = R^{-1} u, v_bot, d_bot, z_bot).  A v_top contracts over the long
+// dimension: column chunks write partial products that k_wide_h sums.
+
+// h (lambda-major) = sum_ch part + sqrt(lam) v_bot             (EPI 0)
+// out[r, i]        = b[r] - sum_ch part - lam * yv[r, i]        (EPI 1, FP64 residual)
+template <typename TC, int NC, int EPI>
+__global__ void __launch_bounds__(BLK) k_wide_h(const DevProb* __restrict__ P,
+                                                const Item* __restrict__ items, int N,
+                                                const TC* __restrict__ part,
+                                                const double* __restrict__ vb,
+                                                const Scal* __restrict__ sc,
+                                                double* __restrict__ out) {
+  constexpr int RR = BLK / NC;
+  const Item it = items[blockIdx.x];
+  const DevProb& pr = P[it.p];
+  const int64_t m = pr.m;
+  const int64_t r = int64_t(it.blk) * RR + threadIdx.x / NC;
+  const int i = threadIdx.x % NC;
+  if (r >= m || i >= N) return;
+  double s = 0.0;
+  const TC* src = part + (pr.pnOff + r) * N + i;
+  for (int ch = 0; ch < pr.nchN; ++ch) s += double(src[int64_t(ch) * m * N]);
+  const Scal& S = sc[it.p * N + i];
+  if (EPI == 0)
+    out[pr.offS * N + int64_t(i) * m + r] = s + S.sqlam * vb[(pr.offS + r) * N + i];
+  else
+    out[(pr.offS + r) * N + i] = pr.b[r] - s - S.lam * vb[(pr.offS + r) * N + i];
+}
+
+// h = b (or the refinement right-hand side), lambda-major.
+__global__ void k_wide_init_h(const DevProb* __restrict__ P, const Item* __restrict__ items,
+                              int N, int NF, int l0, const Scal* __restrict__ sc,
+                              const int32_t* __restrict__ use, const double* __restrict__ rhs,
+                              double* __restrict__ t) {
+  const Item it = items[blockIdx.x];
+  const DevProb& pr = P[it.p];
+  for (int e = threadIdx.x; e < BLK * N; e += BLK) {
+    const int64_t r = int64_t(it.blk) * BLK + e / N;
+    const int i = e % N;
+    if (r >= pr.m) continue;
+    double v = pr.b[r];
+    if (rhs) {
+      const Scal& S = sc[it.p * N + i];
+      v = use[it.p * N + i] ? rhs[(pr.offS + r) * NF + (S.li - l0)] : 0.0;
+    }
+    t[pr.offS * N + int64_t(i) * pr.m + r] = v;
+  }
+}
+
+// v~ = [A^T y - beta v_top; sqrt(lam) y - beta v_bot] and its partial norms.
+// Items: long blocks of 256 rows of n (blk < nL), then short blocks over m.
+template <typename TC>
+__global__ void __launch_bounds__(BLK) k_wide_v(const DevProb* __restrict__ P,
+                                                const Item* __restrict__ items, int N,
+                                                const TC* __restrict__ part,
+                                                const double* __restrict__ y,
+                                                double* __restrict__ vt, double* __restrict__ vb,
+                                                const Scal* __restrict__ sc,
+                                                double* __restrict__ pnQ) {
+  __shared__ double red[4];
+  const Item it = items[blockIdx.x];
+  const DevProb& pr = P[it.p];
+  const int nL = int(cdiv(pr.n, BLK));
+  const bool lng = it.blk < nL;
+  const int64_t r = int64_t(lng ? it.blk : it.blk - nL) * BLK + threadIdx.x;
+  const int64_t rows = lng ? pr.n : pr.m;
+  for (int i = 0; i < N; ++i) {
+    const Scal& S = sc[it.p * N + i];
+    double v = 0.0;
+    if (r < rows) {
+      if (lng) {
+        const int64_t idx = (pr.offL + r) * N + i;
+        const double nv = double(part[(pr.ptOff + r) * N + i]) - S.beta_new * vt[idx];
+        vt[idx] = nv;
+        v = nv * nv;
+      } else {
+        const int64_t idx = (pr.offS + r) * N + i;
+        const double nv = S.sqlam * y[idx] - S.beta_new * vb[idx];
+        vb[idx] = nv;
+        v = nv * nv;
+      }
+    }
+    const double tot = block_sum(v, red);
+    if (threadIdx.x == 0) pnQ[(pr.pnQ + it.blk) * N + i] = tot;
+  }
+}
+
+// v = v~ / alpha; z += (phi/rho) d; d = v - (theta/rho) d (top: x, d_top; bottom: z_bot, d_bot).
+__global__ void __launch_bounds__(BLK) k_wide_upd(const DevProb* __restrict__ P,
+                                                  const Item* __restrict__ items, int N,
+                                                  double* __restrict__ vt, double* __restrict__ dt,
+                                                  double* __restrict__ xt, double* __restrict__ vb,
+                                                  double* __restrict__ db, double* __restrict__ zb,
+                                                  const Scal* __restrict__ sc, int init) {
+  const Item it = items[blockIdx.x];
+  const DevProb& pr = P[it.p];
+  const int nL = int(cdiv(pr.n, BLK));
+  const bool lng = it.blk < nL;
+  const int64_t r = int64_t(lng ? it.blk : it.blk - nL) * BLK + threadIdx.x;
+  const int64_t rows = lng ? pr.n : pr.m;
+  if (r >= rows) return;
+  double* V = lng ? vt : vb;
+  double* D = lng ? dt : db;
+  double* Z = lng ? xt : zb;
+  const int64_t base = (lng ? pr.offL : pr.offS) + r;
+  for (int i = 0; i < N; ++i) {
+    const Scal& S = sc[it.p * N + i];
+    const int64_t idx = base * N + i;
+    const double nv = V[idx] * S.ialpha;
+    V[idx] = nv;
+    if (init) {
+      D[idx] = nv;
+      Z[idx] = 0.0;
+    } else if (S.upd) {
+      const double d = D[idx];
+      Z[idx] += S.cx * d;
+      D[idx] = nv - S.ce * d;
+    }
+  }
+}
+
+// X_p[:, li] = x (long rows) where the status allows.
+__global__ void k_wide_write(const DevProb* __restrict__ P, int N, const double* __restrict__ x,
+                             const Scal* __restrict__ sc, double* const* __restrict__ Xout,
+                             const int32_t* __restrict__ jmap, int32_t* iters, int32_t* status,
+                             double* relres) {
+  const int j = blockIdx.y, p = j / N, i = j % N;
+  const DevProb& pr = P[p];
+  const Scal& S = sc[j];
+  const bool ok = S.status == TIK_ST_CONVERGED || S.status == TIK_ST_MAXIT;
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < pr.n;
+       c += int64_t(gridDim.x) * blockDim.x)
+    if (ok && Xout[p]) Xout[p][c + int64_t(S.li) * pr.n] = x[(pr.offL + c) * N + i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int g = jmap[j];
+    if (iters) iters[g] = S.iters;
+    if (status) status[g] = S.status;
+    if (relres) relres[g] = S.relres;
+  }
+}
+
 // ============================================================ host driver ===
 
 namespace {
@@ -821,6 +978,11 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
     d.b = g.b;
     d.offL = pl.totL;
     d.offS = pl.totS;
+    d.offR = d.offL;
+    d.offC = d.offS;
+    d.cchunk = g.n;
+    d.nchN = 1;
+    d.pnOff = 0;
     d.k = g.n;
     if (pc->route == TIK_ROUTE_CHOL) d.Rinv = pc->Rinv[pidx[lp]];
     d.nblkN = int32_t(cdiv(g.m, pl.rbN));
@@ -949,11 +1111,11 @@ int vec_steps_v(const Plan& pl, const Bufs& b, hipStream_t st, bool init, double
   {
     ProfScope ps("trmv_t", st);
     if (pl.cpw == 16)
-      hipLaunchKernelGGL(k_trmv_t<16>, dim3(unsigned(pl.itQ.size())), dim3(BLK), 0, st, b.P, b.itQ,
-                         pl.N, b.t, b.v, b.q, b.sc, b.pnQ);
+      hipLaunchKernelGGL((k_trmv_t<16, false>), dim3(unsigned(pl.itQ.size())), dim3(BLK), 0, st, b.P,
+                         b.itQ, pl.N, b.t, b.v, b.q, b.sc, b.pnQ);
     else
-      hipLaunchKernelGGL(k_trmv_t<4>, dim3(unsigned(pl.itQ.size())), dim3(BLK), 0, st, b.P, b.itQ,
-                         pl.N, b.t, b.v, b.q, b.sc, b.pnQ);
+      hipLaunchKernelGGL((k_trmv_t<4, false>), dim3(unsigned(pl.itQ.size())), dim3(BLK), 0, st, b.P,
+                         b.itQ, pl.N, b.t, b.v, b.q, b.sc, b.pnQ);
     TIK_LAUNCHED("k_trmv_t");
   }
   {
@@ -964,8 +1126,8 @@ int vec_steps_v(const Plan& pl, const Bufs& b, hipStream_t st, bool init, double
   }
   {
     ProfScope ps("trmv", st);
-    hipLaunchKernelGGL(k_trmv, dim3(unsigned(pl.itM.size())), dim3(BLK), 0, st, b.P, b.itM, pl.N,
-                       b.q, b.v, b.w, b.x, b.e, b.sc, init ? 1 : 0);
+    hipLaunchKernelGGL(k_trmv<false>, dim3(unsigned(pl.itM.size())), dim3(BLK), 0, st, b.P, b.itM,
+                       pl.N, b.q, b.v, b.w, b.x, b.e, b.sc, init ? 1 : 0);
     TIK_LAUNCHED("k_trmv");
   }
   return TIK_OK;
@@ -1551,10 +1713,716 @@ int mixed_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, doub
   return TIK_OK;
 }
 
+// ------------------------------------------------------------- wide driver --
+struct WPlan {
+  int N = 0, NC = 1, rbN = 64, cpw = 4, cbT = 64;
+  std::vector<int> pidx, lsel;
+  std::vector<DevProb> P;
+  std::vector<Item> itNs, itT, itQ, itM, itR, itV, itH;
+  int64_t totL = 0, totS = 0, totPN = 0, totPT = 0, nbN = 0, nbQ = 0;
+  int J = 0;
+};
+
+struct WBufs {
+  DevProb* P;
+  Item *itNs, *itT, *itQ, *itM, *itR, *itV, *itH;
+  Scal* sc;
+  void *partN, *partT;
+  double *vt, *dt, *xt, *u, *q, *y, *vb, *db, *zb, *t, *pnN, *pnQ;
+  int32_t* cnt;
+  double** Xp;
+  double* lams;
+  int32_t *pre, *jmap, *lidx;
+};
+
+void make_plan_wide(const tik_problem* probs, const tik_precond_s* pc, const std::vector<int>& pidx,
+                    const std::vector<int>& lsel, WPlan& pl, const void* const* Aover = nullptr,
+                    const int64_t* ldover = nullptr) {
+  const int N = int(lsel.size());
+  pl = WPlan();
+  pl.N = N;
+  pl.NC = pick_nc(N);
+  pl.rbN = pl.NC >= 8 ? 256 : 64;
+  pl.cpw = pl.NC >= 8 ? 16 : 4;
+  pl.cbT = pl.NC >= 16 ? 128 : 64;
+  pl.pidx = pidx;
+  pl.lsel = lsel;
+  const int np = int(pidx.size());
+  int64_t rowblocks = 0;
+  for (int lp = 0; lp < np; ++lp) rowblocks += cdiv(probs[pidx[lp]].m, pl.rbN);
+  for (int lp = 0; lp < np; ++lp) {
+    const tik_problem& g = probs[pidx[lp]];
+    DevProb d = {};
+    d.A = Aover ? Aover[pidx[lp]] : g.A;
+    d.m = g.m;
+    d.n = g.n;
+    d.lda = ldover ? ldover[pidx[lp]] : g.lda;
+    d.a_f32 = Aover ? 1 : (g.a_dtype == TIK_F32);
+    d.wide = 1;
+    d.b = g.b;
+    d.offL = pl.totL;
+    d.offS = pl.totS;
+    d.offR = d.offS;
+    d.offC = d.offL;
+    d.k = g.m;
+    d.Rinv = pc->Rinv[pidx[lp]];
+    // split of A v_top over column chunks: about 2048 blocks over the batch
+    const int64_t nrb = cdiv(g.m, pl.rbN);
+    int64_t nch = std::max<int64_t>(1, 2048 / std::max<int64_t>(1, rowblocks));
+    nch = std::min<int64_t>(nch, cdiv(g.n, 32));
+    const int64_t cch = cdiv(cdiv(g.n, nch), 32) * 32;
+    nch = cdiv(g.n, cch);
+    d.cchunk = cch;
+    d.nchN = int32_t(nch);
+    d.pnOff = pl.totPN;
+    for (int64_t ch = 0; ch < nch; ++ch)
+      for (int64_t rb = 0; rb < nrb; ++rb) pl.itNs.push_back({lp, int32_t(rb), int32_t(ch), 0});
+    // A^T y over all m rows in one chunk
+    d.rchunk = cdiv(g.m, 32) * 32;
+    d.nchT = 1;
+    d.ptOff = pl.totPT;
+    for (int64_t cb = 0; cb < cdiv(g.n, pl.cbT); ++cb) pl.itT.push_back({lp, int32_t(cb), 0, 0});
+    // beta partials from the transposed triangular product, alpha partials from k_wide_v
+    d.nblkN = int32_t(cdiv(g.m, 4 * pl.cpw));
+    d.nblkB = 0;
+    d.pnN = pl.nbN;
+    d.nblkQ = int32_t(cdiv(g.n, BLK) + cdiv(g.m, BLK));
+    d.pnQ = pl.nbQ;
+    for (int i = 0; i < N; ++i)
+      for (int b = 0; b < d.nblkN; ++b) pl.itQ.push_back({lp, b, 0, lp * N + i});
+    for (int i = 0; i < N; ++i)
+      for (int64_t b = 0; b < cdiv(g.m, 16); ++b) pl.itM.push_back({lp, int32_t(b), 0, lp * N + i});
+    for (int64_t b = 0; b < cdiv(g.m, BLK / pl.NC); ++b) pl.itR.push_back({lp, int32_t(b), 0, 0});
+    for (int b = 0; b < d.nblkQ; ++b) pl.itV.push_back({lp, b, 0, 0});
+    for (int64_t b = 0; b < cdiv(g.m, BLK); ++b) pl.itH.push_back({lp, int32_t(b), 0, 0});
+    pl.totL += g.n;
+    pl.totS += g.m;
+    pl.totPN += nch * g.m;
+    pl.totPT += g.n;
+    pl.nbN += d.nblkN;
+    pl.nbQ += d.nblkQ;
+    pl.P.push_back(d);
+  }
+  pl.J = np * N;
+}
+
+void take_wbufs(Arena& a, const WPlan& pl, size_t tc, WBufs& b) {
+  const size_t N = size_t(pl.N);
+  b.P = a.take<DevProb>(pl.P.size());
+  b.itNs = a.take<Item>(pl.itNs.size());
+  b.itT = a.take<Item>(pl.itT.size());
+  b.itQ = a.take<Item>(pl.itQ.size());
+  b.itM = a.take<Item>(pl.itM.size());
+  b.itR = a.take<Item>(pl.itR.size());
+  b.itV = a.take<Item>(pl.itV.size());
+  b.itH = a.take<Item>(pl.itH.size());
+  b.sc = a.take<Scal>(pl.J);
+  b.partN = a.take<char>(size_t(pl.totPN) * N * tc);
+  b.partT = a.take<char>(size_t(pl.totPT) * N * tc);
+  b.vt = a.take<double>(size_t(pl.totL) * N);
+  b.dt = a.take<double>(size_t(pl.totL) * N);
+  b.xt = a.take<double>(size_t(pl.totL) * N);
+  b.u = a.take<double>(size_t(pl.totS) * N);
+  b.q = a.take<double>(size_t(pl.totS) * N);
+  b.y = a.take<double>(size_t(pl.totS) * N);
+  b.vb = a.take<double>(size_t(pl.totS) * N);
+  b.db = a.take<double>(size_t(pl.totS) * N);
+  b.zb = a.take<double>(size_t(pl.totS) * N);
+  b.t = a.take<double>(size_t(pl.totS) * N);
+  b.pnN = a.take<double>(size_t(pl.nbN) * N);
+  b.pnQ = a.take<double>(size_t(pl.nbQ) * N);
+  b.cnt = a.take<int32_t>(1);
+  b.Xp = a.take<double*>(pl.P.size());
+  b.lams = a.take<double>(pl.J);
+  b.pre = a.take<int32_t>(pl.J);
+  b.jmap = a.take<int32_t>(pl.J);
+  b.lidx = a.take<int32_t>(pl.J);
+}
+
+int upload_wplan(const WPlan& pl, const WBufs& b, const tik_precond_s* pc, double* const* X,
+                 std::vector<std::vector<char>>& keep, hipStream_t st) {
+  auto put = [&](void* dst, const void* src, size_t bytes) -> int {
+    if (!bytes) return TIK_OK;
+    keep.emplace_back(static_cast<const char*>(src), static_cast<const char*>(src) + bytes);
+    TIK_HIP(hipMemcpyAsync(dst, keep.back().data(), bytes, hipMemcpyHostToDevice, st));
+    return TIK_OK;
+  };
+  TIK_TRY(put(b.P, pl.P.data(), pl.P.size() * sizeof(DevProb)));
+  TIK_TRY(put(b.itNs, pl.itNs.data(), pl.itNs.size() * sizeof(Item)));
+  TIK_TRY(put(b.itT, pl.itT.data(), pl.itT.size() * sizeof(Item)));
+  TIK_TRY(put(b.itQ, pl.itQ.data(), pl.itQ.size() * sizeof(Item)));
+  TIK_TRY(put(b.itM, pl.itM.data(), pl.itM.size() * sizeof(Item)));
+  TIK_TRY(put(b.itR, pl.itR.data(), pl.itR.size() * sizeof(Item)));
+  TIK_TRY(put(b.itV, pl.itV.data(), pl.itV.size() * sizeof(Item)));
+  TIK_TRY(put(b.itH, pl.itH.data(), pl.itH.size() * sizeof(Item)));
+  std::vector<double> lams(pl.J);
+  std::vector<int32_t> pre(pl.J), jmap(pl.J), lidx(pl.J);
+  std::vector<double*> xp(pl.P.size());
+  for (size_t lp = 0; lp < pl.P.size(); ++lp) {
+    const int p = pl.pidx[lp];
+    for (int i = 0; i < pl.N; ++i) {
+      const int gi = pl.lsel[i];
+      lams[lp * pl.N + i] = pc->lams[size_t(p) * pc->N + gi];
+      pre[lp * pl.N + i] = pc->status[size_t(p) * pc->N + gi];
+      jmap[lp * pl.N + i] = p * pc->N + gi;
+      lidx[lp * pl.N + i] = gi;
+    }
+    xp[lp] = X ? X[p] : nullptr;
+  }
+  TIK_TRY(put(b.lams, lams.data(), lams.size() * 8));
+  TIK_TRY(put(b.pre, pre.data(), pre.size() * 4));
+  TIK_TRY(put(b.jmap, jmap.data(), jmap.size() * 4));
+  TIK_TRY(put(b.lidx, lidx.data(), lidx.size() * 4));
+  TIK_TRY(put(b.Xp, xp.data(), xp.size() * sizeof(double*)));
+  return TIK_OK;
+}
+
+struct WideIr {
+  const int32_t* use;
+  const double* h;   // short rows x NF right-hand side
+  int NF, l0;
+};
+
+template <typename TA, typename TC, int NC>
+int wide_products_n(const WPlan& pl, const WBufs& b, const double* W, void* part, hipStream_t st) {
+  ProfScope ps("gemm_n", st);
+  constexpr bool a32 = std::is_same<TA, float>::value, c32 = std::is_same<TC, float>::value;
+  if (NC >= 16)
+    return launch_gemm_n_mfma(a32, c32, NC, 2, b.P, b.itNs, int(pl.itNs.size()), pl.N, W, part,
+                              nullptr, b.sc, nullptr, st);
+  if (NC >= 8)
+    hipLaunchKernelGGL((k_gemm_n<TA, TC, NC, 256, 1, 2>), dim3(unsigned(pl.itNs.size())), dim3(BLK),
+                       0, st, b.P, b.itNs, pl.N, W, static_cast<TC*>(part), nullptr, b.sc, nullptr);
+  else
+    hipLaunchKernelGGL((k_gemm_n<TA, TC, NC, 64, 4, 2>), dim3(unsigned(pl.itNs.size())), dim3(BLK),
+                       0, st, b.P, b.itNs, pl.N, W, static_cast<TC*>(part), nullptr, b.sc, nullptr);
+  TIK_LAUNCHED("k_gemm_n (split)");
+  return TIK_OK;
+}
+
+template <typename TA, typename TC, int NC>
+int wide_products_t(const WPlan& pl, const WBufs& b, const double* U, void* part, hipStream_t st) {
+  ProfScope ps("gemm_t", st);
+  constexpr bool a32 = std::is_same<TA, float>::value, c32 = std::is_same<TC, float>::value;
+  if (NC >= 16)
+    return launch_gemm_t_mfma(a32, c32, 1, NC, b.P, b.itT, int(pl.itT.size()), pl.N, U, part, st);
+  hipLaunchKernelGGL((k_gemm_t<TA, TC, double, NC>), dim3(unsigned(pl.itT.size())), dim3(BLK), 0, st,
+                     b.P, b.itT, pl.N, U, int64_t(pl.N), static_cast<TC*>(part));
+  TIK_LAUNCHED("k_gemm_t");
+  return TIK_OK;
+}
+
+template <typename TA, typename TC, int NC>
+int wide_v_steps(const WPlan& pl, const WBufs& b, hipStream_t st, bool init, double tol, int maxit) {
+  {
+    ProfScope ps("trmv", st);
+    hipLaunchKernelGGL(k_trmv<true>, dim3(unsigned(pl.itM.size())), dim3(BLK), 0, st, b.P, b.itM,
+                       pl.N, b.q, b.u, b.y, static_cast<double*>(nullptr),
+                       static_cast<double*>(nullptr), b.sc, 0);
+    TIK_LAUNCHED("k_trmv");
+  }
+  TIK_TRY((wide_products_t<TA, TC, NC>(pl, b, b.y, b.partT, st)));
+  {
+    ProfScope ps("vec", st);
+    hipLaunchKernelGGL(k_wide_v<TC>, dim3(unsigned(pl.itV.size())), dim3(BLK), 0, st, b.P, b.itV,
+                       pl.N, static_cast<const TC*>(b.partT), b.y, b.vt, b.vb, b.sc, b.pnQ);
+    TIK_LAUNCHED("k_wide_v");
+    hipLaunchKernelGGL(k_fin_alpha, dim3(unsigned(pl.J)), dim3(BLK), 0, st, b.P, pl.N, b.pnQ, b.sc,
+                       init ? 1 : 0, tol, maxit);
+    TIK_LAUNCHED("k_fin_alpha");
+    hipLaunchKernelGGL(k_wide_upd, dim3(unsigned(pl.itV.size())), dim3(BLK), 0, st, b.P, b.itV,
+                       pl.N, b.vt, b.dt, b.xt, b.vb, b.db, b.zb, b.sc, init ? 1 : 0);
+    TIK_LAUNCHED("k_wide_upd");
+  }
+  return TIK_OK;
+}
+
+template <int CPW>
+int wide_u_tr(const WPlan& pl, const WBufs& b, hipStream_t st) {
+  hipLaunchKernelGGL((k_trmv_t<CPW, true>), dim3(unsigned(pl.itQ.size())), dim3(BLK), 0, st, b.P,
+                     b.itQ, pl.N, b.t, b.u, b.q, b.sc, b.pnN);
+  TIK_LAUNCHED("k_trmv_t");
+  return TIK_OK;
+}
+
+int wide_u_steps(const WPlan& pl, const WBufs& b, hipStream_t st, bool init) {
+  {
+    ProfScope ps("trmv_t", st);
+    TIK_TRY(pl.cpw == 16 ? wide_u_tr<16>(pl, b, st) : wide_u_tr<4>(pl, b, st));
+  }
+  ProfScope ps("vec", st);
+  hipLaunchKernelGGL(k_fin_beta, dim3(unsigned(pl.J)), dim3(BLK), 0, st, b.P, pl.N, b.pnN,
+                     static_cast<const double*>(nullptr), b.sc, init ? 1 : 0);
+  TIK_LAUNCHED("k_fin_beta");
+  return TIK_OK;
+}
+
+template <typename TA, typename TC, int NC>
+int run_core_wide(const WPlan& pl, const WBufs& b, double tol, int maxit, hipStream_t st,
+                  const WideIr* ir) {
+  hipLaunchKernelGGL(k_scal_init, dim3(unsigned(cdiv(pl.J, 256))), dim3(256), 0, st, b.sc, pl.J,
+                     pl.N, b.lams, b.pre, b.lidx);
+  TIK_LAUNCHED("k_scal_init");
+  const size_t S = size_t(pl.totS) * pl.N, L = size_t(pl.totL) * pl.N;
+  TIK_HIP(hipMemsetAsync(b.u, 0, S * 8, st));
+  TIK_HIP(hipMemsetAsync(b.vb, 0, S * 8, st));
+  TIK_HIP(hipMemsetAsync(b.vt, 0, L * 8, st));
+  {
+    ProfScope ps("vec", st);
+    hipLaunchKernelGGL(k_wide_init_h, dim3(unsigned(pl.itH.size())), dim3(BLK), 0, st, b.P, b.itH,
+                       pl.N, ir ? ir->NF : 1, ir ? ir->l0 : 0, b.sc, ir ? ir->use : nullptr,
+                       ir ? ir->h : nullptr, b.t);
+    TIK_LAUNCHED("k_wide_init_h");
+  }
+  TIK_TRY(wide_u_steps(pl, b, st, true));
+  TIK_TRY((wide_v_steps<TA, TC, NC>(pl, b, st, true, tol, maxit)));
+  const int chunk = 8;
+  int32_t active = 1;
+  for (int it = 0; it < maxit && active > 0;) {
+    const int todo = std::min(chunk, maxit - it);
+    for (int q = 0; q < todo; ++q) {
+      TIK_TRY((wide_products_n<TA, TC, NC>(pl, b, b.vt, b.partN, st)));
+      {
+        ProfScope ps("vec", st);
+        hipLaunchKernelGGL((k_wide_h<TC, NC, 0>), dim3(unsigned(pl.itR.size())), dim3(BLK), 0, st,
+                           b.P, b.itR, pl.N, static_cast<const TC*>(b.partN), b.vb, b.sc, b.t);
+        TIK_LAUNCHED("k_wide_h");
+      }
+      TIK_TRY(wide_u_steps(pl, b, st, false));
+      TIK_TRY((wide_v_steps<TA, TC, NC>(pl, b, st, false, tol, maxit)));
+    }
+    it += todo;
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(BLK), 0, st, b.sc, pl.J, b.cnt);
+    TIK_LAUNCHED("k_count_active");
+    TIK_HIP(hipMemcpyAsync(&active, b.cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    TIK_HIP(hipStreamSynchronize(st));
+  }
+  return TIK_OK;
+}
+
+template <typename TA, typename TC>
+int run_core_wide_nc(const WPlan& pl, const WBufs& b, double tol, int maxit, hipStream_t st,
+                     const WideIr* ir) {
+  switch (pl.NC) {
+    case 1: return run_core_wide<TA, TC, 1>(pl, b, tol, maxit, st, ir);
+    case 2: return run_core_wide<TA, TC, 2>(pl, b, tol, maxit, st, ir);
+    case 4: return run_core_wide<TA, TC, 4>(pl, b, tol, maxit, st, ir);
+    case 8: return run_core_wide<TA, TC, 8>(pl, b, tol, maxit, st, ir);
+    case 16: return run_core_wide<TA, TC, 16>(pl, b, tol, maxit, st, ir);
+    case 32: return run_core_wide<TA, TC, 32>(pl, b, tol, maxit, st, ir);
+  }
+  set_error("internal: lambda batch wider than 32");
+  return TIK_ENOTSUP;
+}
+
+int wide_write(const WPlan& pl, const WBufs& b, int32_t* iters, int32_t* status, double* relres,
+               hipStream_t st) {
+  int64_t maxn = 0;
+  for (auto& d : pl.P) maxn = std::max(maxn, d.n);
+  hipLaunchKernelGGL(k_wide_write, dim3(unsigned(std::min<int64_t>(cdiv(maxn, 256), 4096)), unsigned(pl.J)),
+                     dim3(256), 0, st, b.P, pl.N, b.xt, b.sc, b.Xp, b.jmap, iters, status, relres);
+  TIK_LAUNCHED("k_wide_write");
+  return TIK_OK;
+}
+
+// ---- dual refinement for wide problems (mixed mode)
+// (A A^T + lam I) y = b refined in FP64 with h = b - A x - lam y, x = A^T y;
+// the inner minimum-norm solve of [A sqrt(lam) I] z = h gives dy = z_bot / sqrt(lam).
+__global__ void k_wide_ir_update(const DevProb* __restrict__ P, int N, int NF, int l0,
+                                 const Scal* __restrict__ sc, const int32_t* __restrict__ use,
+                                 const double* __restrict__ zb, double* __restrict__ yd) {
+  const int j = blockIdx.y, p = j / N, i = j % N;
+  const DevProb& pr = P[p];
+  const Scal& S = sc[j];
+  const bool ok = use[j] && (S.status == TIK_ST_CONVERGED || S.status == TIK_ST_MAXIT);
+  if (!ok) return;
+  const double isq = 1.0 / S.sqlam;
+  for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < pr.m;
+       r += int64_t(gridDim.x) * blockDim.x)
+    yd[(pr.offS + r) * NF + (S.li - l0)] += zb[(pr.offS + r) * N + i] * isq;
+}
+
+// squared norms of the inner x (the correction of A^T y) and of x + dx, per refinement column
+__global__ void __launch_bounds__(BLK) k_wide_ir_norms(const DevProb* __restrict__ P, int N, int NF,
+                                                       int l0, const Scal* __restrict__ sc,
+                                                       const int32_t* __restrict__ use,
+                                                       const double* __restrict__ xin,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ nrm) {
+  __shared__ double red[4];
+  const int j = blockIdx.x, p = j / N, i = j % N;
+  const DevProb& pr = P[p];
+  const Scal& S = sc[j];
+  const int col = S.li - l0;
+  double sd = 0.0, sx = 0.0;
+  for (int64_t c = threadIdx.x; c < pr.n; c += BLK) {
+    const double d = xin[(pr.offL + c) * N + i];
+    const double nx = (x ? x[(pr.offL + c) * NF + col] : 0.0) + d;
+    sd += d * d;
+    sx += nx * nx;
+  }
+  const double td = block_sum(sd, red);
+  const double tx = block_sum(sx, red);
+  if (threadIdx.x == 0 && use[j]) {
+    nrm[2 * (p * NF + col)] = td;
+    nrm[2 * (p * NF + col) + 1] = tx;
+  }
+}
+
+__global__ void k_wide_ir_write(const DevProb* __restrict__ P, int NF, const double* __restrict__ x,
+                                const int32_t* __restrict__ ok, double* const* __restrict__ Xout,
+                                int32_t l0) {
+  const int j = blockIdx.y, p = j / NF, i = j % NF;
+  const DevProb& pr = P[p];
+  if (!ok[j]) return;
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < pr.n;
+       c += int64_t(gridDim.x) * blockDim.x)
+    Xout[p][c + int64_t(l0 + i) * pr.n] = x[(pr.offL + c) * NF + i];
+}
+
+__global__ void k_ir_stats_wide(int J, int N, int NF, int l0, const Scal* __restrict__ sc,
+                                const int32_t* __restrict__ use, int32_t* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= J) return;
+  const int p = j / N;
+  const Scal& S = sc[j];
+  const int g = p * NF + (S.li - l0);
+  out[2 * g] = use[j] ? S.iters : 0;
+  out[2 * g + 1] = use[j] ? S.status : -1;
+}
+
+struct WMixedWs {
+  std::vector<float*> A32;
+  double *yd, *h, *nrm;
+  int32_t *use, *stats, *ok;
+  char *baseF = nullptr, *base32 = nullptr, *base64 = nullptr;
+  size_t capF = 0, cap32 = 0, cap64 = 0;
+  bool converted = false;
+};
+
+size_t wide_mixed_layout(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, Arena& a,
+                         WMixedWs& w) {
+  std::vector<int> ps;
+  for (int k = 0; k < nprob; ++k) ps.push_back(k);
+  const int NF = std::min(32, pc->N);
+  std::vector<int> ls;
+  all_lambdas(0, NF, ls);
+  WPlan pl;
+  make_plan_wide(p, pc, ps, ls, pl);
+  w.A32.assign(size_t(nprob), nullptr);
+  for (int k = 0; k < nprob; ++k)
+    if (p[k].a_dtype == TIK_F64) w.A32[k] = a.take<float>(size_t(p[k].m) * size_t(p[k].n));
+  w.yd = a.take<double>(size_t(pl.totS) * NF);
+  w.h = a.take<double>(size_t(pl.totS) * NF);
+  w.nrm = a.take<double>(2 * size_t(pl.J));
+  w.use = a.take<int32_t>(pl.J);
+  w.stats = a.take<int32_t>(2 * size_t(pl.J));
+  w.ok = a.take<int32_t>(pl.J);
+  auto region = [&](size_t tc, char*& base, size_t& cap) {
+    cap = 0;
+    for (int ng = 1; ng <= NF; ++ng) {
+      std::vector<int> sub;
+      all_lambdas(0, ng, sub);
+      WPlan q;
+      make_plan_wide(p, pc, ps, sub, q);
+      Arena m;
+      WBufs b;
+      take_wbufs(m, q, tc, b);
+      cap = std::max(cap, m.used + 256);
+    }
+    base = a.take<char>(cap);
+  };
+  region(sizeof(double), w.baseF, w.capF);
+  region(sizeof(float), w.base32, w.cap32);
+  region(sizeof(double), w.base64, w.cap64);
+  return a.used;
+}
+
+template <typename TA64>
+int wide_mixed_group(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, WMixedWs& w,
+                     int l0, int NF, double tol, int maxit, double* const* X, int32_t* iters,
+                     int32_t* status, double* relres, hipStream_t st) {
+  std::vector<int> ps;
+  for (int k = 0; k < nprob; ++k) ps.push_back(k);
+  std::vector<int> lsel;
+  all_lambdas(l0, NF, lsel);
+  std::vector<std::vector<char>> keep;
+  // hard lambdas: the whole group in FP64 (same rule as for tall problems)
+  bool any_hard = false;
+  for (int i = 0; i < NF; ++i)
+    for (int k = 0; k < nprob; ++k) {
+      const double lam = pc->lams[size_t(k) * pc->N + l0 + i];
+      any_hard |= 12.0 * std::sqrt((pc->cnorm[k] + lam) / lam) * std::ldexp(1.0, -24) > 0.25;
+    }
+  if (any_hard) {
+    WPlan ph;
+    make_plan_wide(p, pc, ps, lsel, ph);
+    Arena ah;
+    ah.base = w.base64;
+    ah.cap = w.cap64;
+    WBufs bh;
+    take_wbufs(ah, ph, sizeof(double), bh);
+    TIK_TRY(upload_wplan(ph, bh, pc, X, keep, st));
+    note_split(0, ph.J);
+    TIK_TRY((run_core_wide_nc<TA64, double>(ph, bh, std::max(1e-3 * tol, 1e-14), maxit, st, nullptr)));
+    TIK_TRY(wide_write(ph, bh, iters, status, relres, st));
+    TIK_HIP(hipStreamSynchronize(st));
+    return TIK_OK;
+  }
+  // FP64 plan over all lambdas of the group: A^T y and h = b - A x - lam y
+  WPlan pf;
+  make_plan_wide(p, pc, ps, lsel, pf);
+  Arena af;
+  af.base = w.baseF;
+  af.cap = w.capF;
+  WBufs bf;
+  take_wbufs(af, pf, sizeof(double), bf);
+  TIK_TRY(upload_wplan(pf, bf, pc, nullptr, keep, st));
+  hipLaunchKernelGGL(k_scal_init, dim3(unsigned(cdiv(pf.J, 256))), dim3(256), 0, st, bf.sc, pf.J,
+                     pf.N, bf.lams, bf.pre, bf.lidx);
+  TIK_LAUNCHED("k_scal_init");
+  const int J = pf.J;
+  note_split(J, 0);
+  const size_t S = size_t(pf.totS) * NF;
+  TIK_HIP(hipMemsetAsync(w.yd, 0, S * 8, st));
+  if (!w.converted) {
+    ProfScope ps_("residual", st);
+    for (int k = 0; k < nprob; ++k)
+      if (w.A32[k]) {
+        const int64_t tot = p[k].m * p[k].n;
+        hipLaunchKernelGGL(k_to_f32, dim3(unsigned(std::min<int64_t>(cdiv(tot, 256), 65536))),
+                           dim3(256), 0, st, static_cast<const double*>(p[k].A), p[k].m, p[k].n,
+                           p[k].lda, w.A32[k]);
+        TIK_LAUNCHED("k_to_f32");
+      }
+    w.converted = true;
+  }
+  std::vector<int32_t> st_h(J, -1), it_h(J, 0);
+  std::vector<double> rel_h(J, 0.0), dxrel(J, 1.0);
+  std::vector<uint8_t> done(J, 0);
+  for (int j = 0; j < J; ++j) {
+    const int32_t pre = pc->status[size_t(j / NF) * pc->N + l0 + (j % NF)];
+    if (pre != TIK_ST_CONVERGED) {
+      st_h[j] = pre;
+      done[j] = 1;
+    }
+  }
+  std::vector<const void*> Aov(static_cast<size_t>(nprob));
+  std::vector<int64_t> ldo(static_cast<size_t>(nprob));
+  for (int k = 0; k < nprob; ++k) {
+    Aov[k] = w.A32[k] ? static_cast<const void*>(w.A32[k]) : p[k].A;
+    ldo[k] = w.A32[k] ? p[k].m : p[k].lda;
+  }
+  const double tol32 = std::max(tol, 1e-6);
+  const int maxsweep = 12;
+  std::vector<double> nrm(2 * size_t(J));
+  std::vector<int32_t> stats(2 * size_t(J));
+  const double* xcur = nullptr;   // x = A^T y of the current sweep (FP64, in bf.partT)
+  for (int sweep = 1; sweep <= maxsweep; ++sweep) {
+    std::vector<int> sel;
+    std::vector<uint8_t> use(J, 0);
+    for (int i = 0; i < NF; ++i) {
+      bool act = false;
+      for (int k = 0; k < nprob; ++k) act |= !done[k * NF + i];
+      if (!act) continue;
+      sel.push_back(l0 + i);
+      for (int k = 0; k < nprob; ++k)
+        if (!done[k * NF + i]) use[k * NF + i] = 1;
+    }
+    if (sel.empty()) break;
+    const double* hr = nullptr;
+    if (sweep > 1) {
+      // x = A^T y (FP64); h = b - A x - lam y (FP64)
+      switch (pf.NC) {
+#define WP(nc) case nc: TIK_TRY((wide_products_t<TA64, double, nc>(pf, bf, w.yd, bf.partT, st))); \
+                        TIK_TRY((wide_products_n<TA64, double, nc>(pf, bf, static_cast<const double*>(bf.partT), bf.partN, st))); \
+                        hipLaunchKernelGGL((k_wide_h<double, nc, 1>), dim3(unsigned(pf.itR.size())), dim3(BLK), 0, st, bf.P, bf.itR, pf.N, static_cast<const double*>(bf.partN), w.yd, bf.sc, w.h); break;
+        WP(1) WP(2) WP(4) WP(8) WP(16) WP(32)
+#undef WP
+      }
+      TIK_LAUNCHED("k_wide_h (refinement)");
+      hr = w.h;
+      xcur = static_cast<const double*>(bf.partT);
+    }
+    // inner FP32 minimum-norm solve over the selected lambdas
+    WPlan pl;
+    const bool ov = true;
+    make_plan_wide(p, pc, ps, sel, pl, ov ? Aov.data() : nullptr, ov ? ldo.data() : nullptr);
+    for (auto& d : pl.P) d.a_f32 = 1;
+    Arena ai;
+    ai.base = w.base32;
+    ai.cap = w.cap32;
+    WBufs bi;
+    take_wbufs(ai, pl, sizeof(float), bi);
+    if (!ai.fits()) {
+      set_error("internal: inner plan exceeds its region");
+      return TIK_EWORKSPACE;
+    }
+    TIK_TRY(upload_wplan(pl, bi, pc, nullptr, keep, st));
+    std::vector<int32_t> uj(size_t(pl.J));
+    for (int k = 0; k < nprob; ++k)
+      for (size_t i = 0; i < sel.size(); ++i) uj[k * sel.size() + i] = use[size_t(k) * NF + (sel[i] - l0)];
+    keep.emplace_back(reinterpret_cast<const char*>(uj.data()), reinterpret_cast<const char*>(uj.data()) + uj.size() * 4);
+    TIK_HIP(hipMemcpyAsync(w.use, keep.back().data(), uj.size() * 4, hipMemcpyHostToDevice, st));
+    WideIr ir{w.use, hr, NF, l0};
+    TIK_TRY((run_core_wide_nc<float, float>(pl, bi, tol32, maxit, st, hr ? &ir : nullptr)));
+    if (!hr) {
+      // first sweep solved with b itself: every selected lambda is used
+    }
+    hipLaunchKernelGGL(k_wide_ir_update, dim3(unsigned(cdiv(pf.P[0].m, 256) + 1), unsigned(pl.J)),
+                       dim3(256), 0, st, bi.P, pl.N, NF, l0, bi.sc, w.use, bi.zb, w.yd);
+    TIK_LAUNCHED("k_wide_ir_update");
+    TIK_HIP(hipMemsetAsync(w.nrm, 0, nrm.size() * 8, st));
+    hipLaunchKernelGGL(k_wide_ir_norms, dim3(unsigned(pl.J)), dim3(BLK), 0, st, bi.P, pl.N, NF, l0,
+                       bi.sc, w.use, bi.xt, xcur, w.nrm);
+    TIK_LAUNCHED("k_wide_ir_norms");
+    TIK_HIP(hipMemsetAsync(w.stats, 0xFF, stats.size() * 4, st));
+    hipLaunchKernelGGL(k_ir_stats_wide, dim3(unsigned(cdiv(pl.J, 256))), dim3(256), 0, st, pl.J,
+                       pl.N, NF, l0, bi.sc, w.use, w.stats);
+    TIK_LAUNCHED("k_ir_stats_wide");
+    TIK_HIP(hipMemcpyAsync(nrm.data(), w.nrm, nrm.size() * 8, hipMemcpyDeviceToHost, st));
+    TIK_HIP(hipMemcpyAsync(stats.data(), w.stats, stats.size() * 4, hipMemcpyDeviceToHost, st));
+    TIK_HIP(hipStreamSynchronize(st));
+    for (int j = 0; j < J; ++j) {
+      if (done[j] || !use[j]) continue;
+      it_h[j] += std::max(0, stats[2 * j]);
+      const int32_t ist = stats[2 * j + 1];
+      if (ist == TIK_ST_NOTPD || ist == TIK_ST_NONFINITE) {
+        st_h[j] = ist;
+        done[j] = 1;
+        continue;
+      }
+      const double nd = std::sqrt(nrm[2 * j]), nx = std::sqrt(nrm[2 * j + 1]);
+      if (!std::isfinite(nd) || !std::isfinite(nx)) {
+        st_h[j] = TIK_ST_NONFINITE;
+        done[j] = 1;
+        continue;
+      }
+      const double rel = nx > 0.0 ? nd / nx : 0.0;
+      rel_h[j] = rel;
+      if (rel <= tol) {
+        st_h[j] = TIK_ST_CONVERGED;
+        done[j] = 1;
+      } else if (sweep >= 3 && rel > 0.9 * dxrel[j]) {
+        st_h[j] = TIK_ST_IR_STALL;
+        done[j] = 1;
+      } else if (sweep == maxsweep) {
+        st_h[j] = TIK_ST_MAXIT;
+        done[j] = 1;
+      }
+      dxrel[j] = rel;
+    }
+  }
+  for (int j = 0; j < J; ++j)
+    if (!done[j]) st_h[j] = TIK_ST_MAXIT;
+  // final x = A^T y in FP64
+  switch (pf.NC) {
+#define WT(nc) case nc: TIK_TRY((wide_products_t<TA64, double, nc>(pf, bf, w.yd, bf.partT, st))); break;
+    WT(1) WT(2) WT(4) WT(8) WT(16) WT(32)
+#undef WT
+  }
+  std::vector<int32_t> okv(J);
+  for (int j = 0; j < J; ++j)
+    okv[j] = (st_h[j] == TIK_ST_CONVERGED || st_h[j] == TIK_ST_MAXIT || st_h[j] == TIK_ST_IR_STALL) ? 1 : 0;
+  keep.emplace_back(reinterpret_cast<const char*>(okv.data()), reinterpret_cast<const char*>(okv.data()) + J * 4);
+  TIK_HIP(hipMemcpyAsync(w.ok, keep.back().data(), size_t(J) * 4, hipMemcpyHostToDevice, st));
+  std::vector<double*> xp(static_cast<size_t>(nprob));
+  for (int k = 0; k < nprob; ++k) xp[k] = X[k];
+  keep.emplace_back(reinterpret_cast<const char*>(xp.data()), reinterpret_cast<const char*>(xp.data()) + xp.size() * sizeof(double*));
+  TIK_HIP(hipMemcpyAsync(bf.Xp, keep.back().data(), xp.size() * sizeof(double*), hipMemcpyHostToDevice, st));
+  int64_t maxn = 0;
+  for (auto& d : pf.P) maxn = std::max(maxn, d.n);
+  hipLaunchKernelGGL(k_wide_ir_write, dim3(unsigned(std::min<int64_t>(cdiv(maxn, 256), 4096)), unsigned(J)),
+                     dim3(256), 0, st, bf.P, NF, static_cast<const double*>(bf.partT), w.ok, bf.Xp, l0);
+  TIK_LAUNCHED("k_wide_ir_write");
+  for (int j = 0; j < J; ++j) {
+    const size_t gpos = size_t(j / NF) * pc->N + l0 + (j % NF);
+    if (iters) TIK_HIP(hipMemcpyAsync(iters + gpos, &it_h[j], 4, hipMemcpyHostToDevice, st));
+    if (status) TIK_HIP(hipMemcpyAsync(status + gpos, &st_h[j], 4, hipMemcpyHostToDevice, st));
+    if (relres) TIK_HIP(hipMemcpyAsync(relres + gpos, &rel_h[j], 8, hipMemcpyHostToDevice, st));
+  }
+  TIK_HIP(hipStreamSynchronize(st));
+  return TIK_OK;
+}
+
+int wide_bytes(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32_t mode,
+               size_t* bytes) {
+  if (mode == TIK_MIXED_BATCHED) {
+    Arena a;
+    WMixedWs w;
+    *bytes = wide_mixed_layout(p, nprob, pc, a, w) + 256;
+    return TIK_OK;
+  }
+  std::vector<std::vector<int>> gp, gl;
+  groups_for(pc, nprob, mode, gp, gl);
+  size_t best = 0;
+  for (size_t g = 0; g < gp.size(); ++g) {
+    WPlan pl;
+    make_plan_wide(p, pc, gp[g], gl[g], pl);
+    Arena a;
+    WBufs b;
+    take_wbufs(a, pl, sizeof(double), b);
+    best = std::max(best, a.used);
+  }
+  *bytes = best + 256;
+  return TIK_OK;
+}
+
+int wide_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32_t mode, double tol,
+             int32_t maxit, double* const* X, int32_t* iters, int32_t* status, double* relres,
+             void* dws, size_t dws_bytes, hipStream_t st) {
+  const bool f32 = p[0].a_dtype == TIK_F32;
+  if (mode == TIK_MIXED_BATCHED) {
+    Arena a;
+    a.base = static_cast<char*>(dws);
+    a.cap = dws_bytes;
+    WMixedWs w;
+    wide_mixed_layout(p, nprob, pc, a, w);
+    if (!a.fits()) {
+      set_error("tik_lsqr_batch: workspace too small");
+      return TIK_EWORKSPACE;
+    }
+    for (int l0 = 0; l0 < pc->N; l0 += 32) {
+      const int NF = std::min(32, pc->N - l0);
+      if (f32)
+        TIK_TRY(wide_mixed_group<float>(p, nprob, pc, w, l0, NF, tol, maxit, X, iters, status, relres, st));
+      else
+        TIK_TRY(wide_mixed_group<double>(p, nprob, pc, w, l0, NF, tol, maxit, X, iters, status, relres, st));
+    }
+    return TIK_OK;
+  }
+  std::vector<std::vector<int>> gp, gl;
+  groups_for(pc, nprob, mode, gp, gl);
+  for (size_t g = 0; g < gp.size(); ++g) {
+    WPlan pl;
+    make_plan_wide(p, pc, gp[g], gl[g], pl);
+    Arena a;
+    a.base = static_cast<char*>(dws);
+    a.cap = dws_bytes;
+    WBufs b;
+    take_wbufs(a, pl, sizeof(double), b);
+    if (!a.fits()) {
+      set_error("tik_lsqr_batch: workspace too small");
+      return TIK_EWORKSPACE;
+    }
+    std::vector<std::vector<char>> keep;
+    TIK_TRY(upload_wplan(pl, b, pc, X, keep, st));
+    note_split(0, pl.J);
+    if (f32)
+      TIK_TRY((run_core_wide_nc<float, double>(pl, b, tol, maxit, st, nullptr)));
+    else
+      TIK_TRY((run_core_wide_nc<double, double>(pl, b, tol, maxit, st, nullptr)));
+    TIK_TRY(wide_write(pl, b, iters, status, relres, st));
+    TIK_HIP(hipStreamSynchronize(st));
+  }
+  return TIK_OK;
+}
+
 }  // namespace
 
 int lsqr_bytes(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32_t mode,
                size_t* bytes) {
+  if (pc->wide) return wide_bytes(p, nprob, pc, mode, bytes);
   if (mode == TIK_MIXED_BATCHED) {
     Arena a;
     MixedWs w;
@@ -1580,6 +2448,8 @@ int lsqr_bytes(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int
 int lsqr_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32_t mode,
              double tol, int32_t maxit, double* const* X, int32_t* iters, int32_t* status,
              double* relres, void* dws, size_t dws_bytes, hipStream_t st) {
+  if (pc->wide)
+    return wide_run(p, nprob, pc, mode, tol, maxit, X, iters, status, relres, dws, dws_bytes, st);
   if (mode == TIK_MIXED_BATCHED)
     return mixed_run(p, nprob, pc, tol, maxit, X, iters, status, relres, dws, dws_bytes, st);
   std::vector<std::vector<int>> gp, gl;

@@ -39,7 +39,8 @@ struct Mfma<float> {
 // Block = 4 waves x 64 rows = 256 rows of one problem, all NC lambdas.  A is
 // read straight into A-operand registers (16 consecutive rows of 4 columns per
 // load: whole 64/128-byte lines); W is staged through LDS KC columns at a time.
-// EPI 0: LSQR update of u~_top with partial squared norms; EPI 1: store A W.
+// EPI 0: LSQR update of u~_top with partial squared norms; EPI 1: store A W;
+// EPI 2: store the partial product over column chunk it.ch (wide problems).
 template <typename TA, typename TC, int NC, int EPI>
 __global__ void __launch_bounds__(256) k_gemm_n_mfma(const DevProb* __restrict__ P,
                                                      const Item* __restrict__ items, int N,
@@ -60,6 +61,8 @@ __global__ void __launch_bounds__(256) k_gemm_n_mfma(const DevProb* __restrict__
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int64_t row0 = int64_t(it.blk) * 256 + wv * 64;
+  const int64_t kbeg = int64_t(it.ch) * pr.cchunk;
+  const int64_t kend = min(n, kbeg + pr.cchunk);
   typename M::acc_t acc[4][NT];
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt)
@@ -74,20 +77,20 @@ __global__ void __launch_bounds__(256) k_gemm_n_mfma(const DevProb* __restrict__
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt) {
         const int64_t row = row0 + rt * 16 + li;
-        dst[rt][ks] = (row < m && col < n) ? TC(A[row + col * lda]) : TC(0);
+        dst[rt][ks] = (row < m && col < kend) ? TC(A[row + col * lda]) : TC(0);
       }
     }
   };
   TC a[4][KC / 4], an[4][KC / 4];
-  load_a(0, a);
-  for (int64_t k0 = 0; k0 < n; k0 += KC) {
+  load_a(kbeg, a);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += KC) {
     for (int e = threadIdx.x; e < KC * NC; e += 256) {
       const int kk = e / NC, i = e % NC;
       const int64_t kg = k0 + kk;
-      Ws[kk][i] = (kg < n && i < N) ? TC(W[(pr.offS + kg) * N + i]) : TC(0);
+      Ws[kk][i] = (kg < kend && i < N) ? TC(W[(pr.offC + kg) * N + i]) : TC(0);
     }
     __syncthreads();
-    if (k0 + KC < n) load_a(k0 + KC, an);
+    if (k0 + KC < kend) load_a(k0 + KC, an);
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
       TC b[NT];
@@ -116,13 +119,15 @@ __global__ void __launch_bounds__(256) k_gemm_n_mfma(const DevProb* __restrict__
       for (int v = 0; v < 4; ++v) {
         const int64_t row = row0 + rt * 16 + M::row(lane, v);
         if (row < m && lam < N) {
-          const int64_t idx = (pr.offL + row) * N + lam;
+          const int64_t idx = (pr.offR + row) * N + lam;
           if (EPI == 0) {
             const TC nv = TC(acc[rt][nt][v] - TC(uc) * ut[idx]);
             ut[idx] = nv;
             nsum[nt] += double(nv) * double(nv);
-          } else {
+          } else if (EPI == 1) {
             out[idx] = double(acc[rt][nt][v]);
+          } else {
+            ut[(pr.pnOff + int64_t(it.ch) * m + row) * N + lam] = acc[rt][nt][v];
           }
         }
       }
@@ -193,7 +198,7 @@ __global__ void __launch_bounds__(256) k_gemm_t_mfma(const DevProb* __restrict__
       const int e = threadIdx.x + 256 * q;
       const int rr = e / NC, i = e % NC;
       const int64_t rg = r0 + rr;
-      ru[q] = (e < RS * NC && rg < rend && i < N) ? TC(U[(pr.offL + rg) * N + i]) : TC(0);
+      ru[q] = (e < RS * NC && rg < rend && i < N) ? TC(U[(pr.offR + rg) * N + i]) : TC(0);
     }
   };
   auto stash = [&]() {
@@ -254,8 +259,10 @@ static int gemm_n_nc(int nc, int epi, const DevProb* P, const Item* items, int n
   TC* u = static_cast<TC*>(ut);
   if (nc == 16 && epi == 0) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 16, 0>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
   else if (nc == 32 && epi == 0) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 32, 0>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
-  else if (nc == 16) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 16, 1>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
-  else if (nc == 32) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 32, 1>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
+  else if (nc == 16 && epi == 1) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 16, 1>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
+  else if (nc == 32 && epi == 1) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 32, 1>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
+  else if (nc == 16) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 16, 2>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
+  else if (nc == 32) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 32, 2>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
   else {
     set_error("internal: MFMA gemm_n needs 16 or 32 lambdas per pass");
     return TIK_EINVAL;
@@ -299,10 +306,11 @@ int launch_gemm_t_mfma(int ta_f32, int tc_f32, int u_f64, int nc, const DevProb*
                        const Item* items, int nitems, int N, const void* U, void* part,
                        hipStream_t st) {
   if (tc_f32) {
-    if (!ta_f32 || u_f64) {
-      set_error("internal: FP32 products need FP32 storage and vectors");
+    if (!ta_f32) {
+      set_error("internal: FP32 products need FP32 storage");
       return TIK_EINVAL;
     }
+    if (u_f64) return gemm_t_nc<float, float, double>(nc, P, items, nitems, N, U, part, st);
     return gemm_t_nc<float, float, float>(nc, P, items, nitems, N, U, part, st);
   }
   if (ta_f32) return gemm_t_nc<float, double, double>(nc, P, items, nitems, N, U, part, st);

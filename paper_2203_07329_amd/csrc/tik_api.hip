@@ -460,7 +460,6 @@ static int lsqr_validate(const tik_problem* p, int32_t nprob, tik_precond_t pc, 
   }
   if (mode != TIK_PLAIN_F64_PER_LAMBDA && mode != TIK_F64_BATCHED && mode != TIK_MIXED_BATCHED)
     return fail(TIK_EINVAL, "tik_lsqr_batch: unknown mode");
-  if (pc->wide) return fail(TIK_ENOTSUP, "tik_lsqr_batch: wide problems are not available in this build");
 
   return TIK_OK;
 }

@@ -75,6 +75,12 @@ struct DevProb {
   const double* b;
   int64_t offL;        // row offset of this problem inside long-row vector buffers
   int64_t offS;        // row offset inside short-row vector buffers
+  int64_t offR;        // offset of vectors indexed by the rows of A (offL tall, offS wide)
+  int64_t offC;        // offset of vectors indexed by the columns of A (offS tall, offL wide)
+  int64_t cchunk;      // columns of A per chunk of the split A W product (wide problems)
+  int32_t nchN;        // number of such chunks (1 for tall problems)
+  int32_t pad_;
+  int64_t pnOff;       // first row of this problem in the split-product partial buffer
   const double* Rinv;  // upper-triangular inverses, k x k each (k = short dim), col-major,
                        // one per lambda of the problem; a solve uses Rinv + li * k * k
   int64_t k;           // short dimension min(m, n)

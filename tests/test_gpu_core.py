@@ -254,3 +254,34 @@ def test_mixed_refinement(case):
         print(case, k, "max rel err %.2e" % err.max(), "iters", its[k], "status", st[k])
         assert np.all(err <= 1e-8), err
     assert np.all(st == tik.ST_CONVERGED), st
+
+
+# ------------------------------------------------------------- wide problems --
+
+@pytest.mark.parametrize("mode", [tik.F64_BATCHED, tik.PLAIN_F64_PER_LAMBDA, tik.MIXED_BATCHED])
+def test_wide_scaled(mode):
+    """Algorithm 2: minimum-norm LSQR on R^{-T}[A sqrt(lam) I], A_ij = G_ij / j (FP32)."""
+    p = W.under_scaled(m=200, n=6000, N=8)
+    res, pc = _solve([p], mode, embed=tik.GAUSS, tol=1e-12 if mode != tik.MIXED_BATCHED else 1e-10,
+                     s=[4 * p.m])
+    err = oracle.rel_err(res.x_numpy(0), oracle.solve(p.A, p.b, p.lams))
+    st = res.status.cpu().numpy()
+    print("wide", mode, "max rel err %.2e" % err.max(), "iters", res.iters.cpu().numpy()[0], st)
+    assert np.all(st == tik.ST_CONVERGED), st
+    assert np.all(err <= (1e-10 if mode != tik.MIXED_BATCHED else 1e-8)), err
+
+
+def test_wide_ragged_and_fp64_storage():
+    rng = np.random.default_rng(8)
+    plist = []
+    for m, n in [(60, 900), (130, 2500), (90, 400)]:
+        A = np.asfortranarray(rng.standard_normal((m, n)) * np.logspace(0, -3, n)[None, :])
+        b = A @ rng.standard_normal(n) + 1e-3 * rng.standard_normal(m)
+        plist.append(W.Problem("wide", A, b, np.logspace(-5, 0, 6), 4 * m, "gauss", "chol", 1e-10, 0))
+    for mode in (tik.F64_BATCHED, tik.MIXED_BATCHED):
+        res, _ = _solve(plist, mode, embed=tik.GAUSS, tol=1e-12 if mode == tik.F64_BATCHED else 1e-10)
+        for k, p in enumerate(plist):
+            err = oracle.rel_err(res.x_numpy(k), oracle.solve(p.A, p.b, p.lams))
+            print("wide ragged", mode, k, "%.2e" % err.max())
+            assert np.all(err <= 1e-8), (mode, k, err)
+        assert np.all(res.status.cpu().numpy() == tik.ST_CONVERGED)
