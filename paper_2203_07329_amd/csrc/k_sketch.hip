@@ -313,6 +313,174 @@ __global__ void __launch_bounds__(256) k_sketch_gemm64(const double* __restrict_
     }
 }
 
+// ------------------------------------------------------------ BF16 sketch --
+// X chunk in BF16, stored row-major s x kc (k contiguous), the layout the
+// matrix-core operand loads want.  Same Philox/Box-Muller entries as the FP64
+// generator, rounded to BF16.
+__global__ void __launch_bounds__(256) k_gauss_gen_bf16(uint64_t seed, int64_t s, int64_t r0,
+                                                        int64_t kc, float scale,
+                                                        __hip_bfloat16* __restrict__ X) {
+  const int64_t sq = (s + 3) >> 2;
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= sq * kc) return;
+  const int64_t cc = idx % kc, qb = idx / kc;
+  double z[4];
+  gauss4(seed, uint32_t(r0 + cc), uint32_t(qb), z);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t q = qb * 4 + t;
+    if (q < s) X[q * kc + cc] = __float2bfloat16(float(z[t]) * scale);
+  }
+}
+
+typedef __bf16 sk_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float sk_f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  const __hip_bfloat16 x = __float2bfloat16(a), y = __float2bfloat16(b);
+  return uint32_t(*reinterpret_cast<const uint16_t*>(&x)) |
+         (uint32_t(*reinterpret_cast<const uint16_t*>(&y)) << 16);
+}
+
+// Yacc (s x ncol, ld s, FP32) (+)= X (s x kc, BF16, ld kc) * Bop (kc x ncol), Bop(k, c) =
+// A[(r0 + k) + c lda] (tall) or A[c + (r0 + k) lda] (wide), rounded to BF16.
+// 128 x 128 output tile per block, 4 waves of 64 x 64 (2 x 2 tiles of
+// v_mfma_f32_32x32x16_bf16: A-operand lane l holds row l % 32, k = 8 (l / 32) .. +7;
+// B-operand lane l holds column l % 32 at the same k; the 16 results of lane l
+// are rows 8 (v / 4) + 4 (l / 32) + v % 4 of column l % 32).  Tiles are staged in
+// LDS k-contiguous (row / column major over 32 k) so each operand is one
+// 16-byte read; the next tile is fetched into registers during the MFMAs.
+template <typename TA, bool WIDE>
+__global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* __restrict__ X,
+                                                          int64_t s, int64_t kc,
+                                                          const TA* __restrict__ A, int64_t lda,
+                                                          int64_t r0, int64_t ncol,
+                                                          float* __restrict__ Y, int first) {
+  constexpr int KB = 32, LP = KB + 8;     // k per step, LDS row pitch in bf16
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[128 * LP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[128 * LP];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wq = wv >> 1, wc = wv & 1;
+  const int64_t q0 = int64_t(blockIdx.x) * 128, c0 = int64_t(blockIdx.y) * 128;
+  sk_f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
+  // register stage: X (2 x 16 bytes per thread), B (16 values per thread)
+  uint4 rx[2];
+  float rb[16];
+  auto fetch = [&](int64_t k0) {
+    {
+      const int row = tid >> 1, half = tid & 1;
+      const int64_t q = q0 + row;
+      const int64_t kk = k0 + half * 16;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (q < s) {
+          const int64_t k = kk + h * 8;
+          if (k + 8 <= kc && ((kc & 7) == 0)) {
+            v = *reinterpret_cast<const uint4*>(X + q * kc + k);
+          } else {
+            uint16_t t[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              t[e] = (k + e < kc) ? *reinterpret_cast<const uint16_t*>(X + q * kc + k + e) : 0;
+            v = make_uint4(t[0] | (t[1] << 16), t[2] | (t[3] << 16), t[4] | (t[5] << 16),
+                           t[6] | (t[7] << 16));
+          }
+        }
+        rx[h] = v;
+      }
+    }
+    if (!WIDE) {
+      const int col = tid >> 1, half = tid & 1;
+      const int64_t c = c0 + col;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t k = k0 + half * 16 + e;
+        rb[e] = (c < ncol && k < kc) ? float(A[(r0 + k) + c * lda]) : 0.f;
+      }
+    } else {
+      const int kr = tid >> 3, cg = (tid & 7) * 16;
+      const int64_t k = k0 + kr;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t c = c0 + cg + e;
+        rb[e] = (c < ncol && k < kc) ? float(A[c + (r0 + k) * lda]) : 0.f;
+      }
+    }
+  };
+  auto stash = [&]() {
+    {
+      const int row = tid >> 1, half = tid & 1;
+      *reinterpret_cast<uint4*>(&Xs[row * LP + half * 16]) = rx[0];
+      *reinterpret_cast<uint4*>(&Xs[row * LP + half * 16 + 8]) = rx[1];
+    }
+    if (!WIDE) {
+      const int col = tid >> 1, half = tid & 1;
+      uint4 w0 = make_uint4(pack_bf16(rb[0], rb[1]), pack_bf16(rb[2], rb[3]),
+                            pack_bf16(rb[4], rb[5]), pack_bf16(rb[6], rb[7]));
+      uint4 w1 = make_uint4(pack_bf16(rb[8], rb[9]), pack_bf16(rb[10], rb[11]),
+                            pack_bf16(rb[12], rb[13]), pack_bf16(rb[14], rb[15]));
+      *reinterpret_cast<uint4*>(&Bs[col * LP + half * 16]) = w0;
+      *reinterpret_cast<uint4*>(&Bs[col * LP + half * 16 + 8]) = w1;
+    } else {
+      const int kr = tid >> 3, cg = (tid & 7) * 16;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const __hip_bfloat16 h = __float2bfloat16(rb[e]);
+        Bs[(cg + e) * LP + kr] = *reinterpret_cast<const uint16_t*>(&h);
+      }
+    }
+  };
+  fetch(0);
+  stash();
+  __syncthreads();
+  for (int64_t k0 = 0; k0 < kc; k0 += KB) {
+    const bool more = k0 + KB < kc;
+    if (more) fetch(k0 + KB);
+#pragma unroll
+    for (int ks = 0; ks < KB / 16; ++ks) {
+      sk_bf16x8 av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int row = wq * 64 + t * 32 + (lane & 31);
+        const int col = wc * 64 + t * 32 + (lane & 31);
+        const int kofs = ks * 16 + 8 * (lane >> 5);
+        const uint4 xa = *reinterpret_cast<const uint4*>(&Xs[row * LP + kofs]);
+        const uint4 xb = *reinterpret_cast<const uint4*>(&Bs[col * LP + kofs]);
+        av[t] = __builtin_bit_cast(sk_bf16x8, xa);
+        bv[t] = __builtin_bit_cast(sk_bf16x8, xb);
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+    if (more) stash();
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t q = q0 + wq * 64 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int64_t c = c0 + wc * 64 + b * 32 + (lane & 31);
+        if (q < s && c < ncol) {
+          float* dst = Y + q + c * s;
+          *dst = first ? acc[a][b][v] : *dst + acc[a][b][v];
+        }
+      }
+}
+
 __global__ void k_f32_to_f64(const float* __restrict__ src, double* __restrict__ dst, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = double(src[i]);
@@ -394,8 +562,8 @@ int launch_gauss_gen(uint64_t seed, int64_t s, int64_t r0, int64_t kc, void* Xc,
   const double scale = 1.0 / sqrt(double(s));
   ProfScope ps("sketch", st);
   if (bf16)
-    hipLaunchKernelGGL(k_gauss_gen<__hip_bfloat16>, dim3(unsigned(cdiv(total, 256))), dim3(256),
-                       0, st, seed, s, r0, kc, scale, static_cast<__hip_bfloat16*>(Xc));
+    hipLaunchKernelGGL(k_gauss_gen_bf16, dim3(unsigned(cdiv(total, 256))), dim3(256), 0, st, seed,
+                       s, r0, kc, float(scale), static_cast<__hip_bfloat16*>(Xc));
   else
     hipLaunchKernelGGL(k_gauss_gen<double>, dim3(unsigned(cdiv(total, 256))), dim3(256), 0, st,
                        seed, s, r0, kc, scale, static_cast<double*>(Xc));
@@ -416,6 +584,23 @@ int launch_sketch_gemm_f64(const double* Xc, int64_t s, int64_t kc, const void* 
     else      hipLaunchKernelGGL((k_sketch_gemm64<double, false>), grid, dim3(256), 0, st, Xc, s, kc, static_cast<const double*>(A), lda, r0, ncol, Y);
   }
   TIK_LAUNCHED("k_sketch_gemm64");
+  return TIK_OK;
+}
+
+int launch_sketch_gemm_bf16(const void* Xc, int64_t s, int64_t kc, const void* A, int a_f32,
+                            int64_t lda, int64_t r0, int64_t ncol, int wide, float* Yacc,
+                            int first, hipStream_t st) {
+  const dim3 grid = dim3(unsigned(cdiv(s, 128)), unsigned(cdiv(ncol, 128)));
+  const __hip_bfloat16* X = static_cast<const __hip_bfloat16*>(Xc);
+  ProfScope ps("sketch", st);
+  if (a_f32) {
+    if (wide) hipLaunchKernelGGL((k_sketch_gemm_bf16<float, true>), grid, dim3(256), 0, st, X, s, kc, static_cast<const float*>(A), lda, r0, ncol, Yacc, first);
+    else      hipLaunchKernelGGL((k_sketch_gemm_bf16<float, false>), grid, dim3(256), 0, st, X, s, kc, static_cast<const float*>(A), lda, r0, ncol, Yacc, first);
+  } else {
+    if (wide) hipLaunchKernelGGL((k_sketch_gemm_bf16<double, true>), grid, dim3(256), 0, st, X, s, kc, static_cast<const double*>(A), lda, r0, ncol, Yacc, first);
+    else      hipLaunchKernelGGL((k_sketch_gemm_bf16<double, false>), grid, dim3(256), 0, st, X, s, kc, static_cast<const double*>(A), lda, r0, ncol, Yacc, first);
+  }
+  TIK_LAUNCHED("k_sketch_gemm_bf16");
   return TIK_OK;
 }
 

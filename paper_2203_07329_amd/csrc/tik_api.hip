@@ -114,23 +114,27 @@ struct SketchPlan {
   std::vector<int64_t> yrows, ycols;
   int32_t* rows = nullptr;   // SRHT: rows | bucket starts | sign words
   double* T = nullptr;       // SRHT two-pass scratch
-  double* Xc = nullptr;      // Gaussian X chunk
+  double* Xc = nullptr;      // Gaussian X chunk (FP64 or BF16)
+  float* Yacc = nullptr;     // BF16 sketches: FP32 accumulator
   int64_t tcols = 0, kc = 0;
 };
 
 // long-dimension rows of the Gaussian X generated per chunk for problem q
-static int64_t gauss_chunk(const tik_problem& q, int64_t s) {
+static int64_t gauss_chunk(const tik_problem& q, int64_t s, int32_t sdt) {
   const int64_t longdim = tall(q) ? q.m : q.n;
-  int64_t kc = int64_t(SCRATCH_CHUNK / (sizeof(double) * size_t(s)));
-  return std::max<int64_t>(64, std::min<int64_t>(longdim, kc));
+  const size_t esz = sdt == TIK_BF16 ? 2 : sizeof(double);
+  int64_t kc = int64_t(SCRATCH_CHUNK / (esz * size_t(s)));
+  kc = std::max<int64_t>(64, std::min<int64_t>(longdim, kc));
+  if (sdt == TIK_BF16 && kc < longdim) kc = std::max<int64_t>(32, kc / 32 * 32);
+  return kc;
 }
 
-static int sketch_plan(const tik_problem* p, int32_t nprob, int32_t embed, const int64_t* s,
-                       Arena& a, SketchPlan& sp) {
+static int sketch_plan(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sdt,
+                       const int64_t* s, Arena& a, SketchPlan& sp) {
   sp.Y.assign(size_t(nprob), nullptr);
   sp.yrows.assign(size_t(nprob), 0);
   sp.ycols.assign(size_t(nprob), 0);
-  int64_t rows_ints = 0, tsz = 0, xsz = 0;
+  int64_t rows_ints = 0, tsz = 0, xsz = 0, ysz = 0;
   for (int32_t k = 0; k < nprob; ++k) {
     const bool t = tall(p[k]);
     sp.yrows[k] = s[k];
@@ -148,12 +152,15 @@ static int sketch_plan(const tik_problem* p, int32_t nprob, int32_t embed, const
         tsz = std::max<int64_t>(tsz, cols << kk);
       }
     } else {
-      xsz = std::max<int64_t>(xsz, gauss_chunk(p[k], s[k]) * s[k]);
+      const size_t esz = sdt == TIK_BF16 ? 2 : sizeof(double);
+      xsz = std::max<int64_t>(xsz, int64_t(cdiv(gauss_chunk(p[k], s[k], sdt) * s[k] * esz, 8)));
+      if (sdt == TIK_BF16) ysz = std::max<int64_t>(ysz, s[k] * sp.ycols[k]);
     }
   }
   if (rows_ints) sp.rows = a.take<int32_t>(size_t(rows_ints));
   if (tsz) sp.T = a.take<double>(size_t(tsz));
   if (xsz) sp.Xc = a.take<double>(size_t(xsz));
+  if (ysz) sp.Yacc = a.take<float>(size_t(ysz));
   return TIK_OK;
 }
 
@@ -180,7 +187,6 @@ static int sketch_validate(const tik_problem* p, int32_t nprob, int32_t embed, i
       if (s[k] > SRHT_MAX_S) return fail(TIK_ENOTSUP, "tik_sketch: SRHT needs s <= 16384");
     }
   }
-  if (sdt == TIK_BF16) return fail(TIK_ENOTSUP, "tik_sketch: BF16 sketches are not available in this build");
   return TIK_OK;
 }
 
@@ -243,7 +249,7 @@ int tik_sketch_bytes(const tik_problem* p, int32_t nprob, int32_t embed, int32_t
   TIK_TRY(sketch_validate(p, nprob, embed, sketch_dtype, s));
   Arena a;
   SketchPlan sp;
-  TIK_TRY(sketch_plan(p, nprob, embed, s, a, sp));
+  TIK_TRY(sketch_plan(p, nprob, embed, sketch_dtype, s, a, sp));
   *bytes = a.used + 256;
   return TIK_OK;
 }
@@ -262,7 +268,7 @@ int tik_sketch(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sketc
   a.base = static_cast<char*>(dws);
   a.cap = dws_bytes;
   SketchPlan sp;
-  TIK_TRY(sketch_plan(p, nprob, embed, s, a, sp));
+  TIK_TRY(sketch_plan(p, nprob, embed, sketch_dtype, s, a, sp));
   for (int32_t k = 0; k < nprob; ++k) {
     const tik_problem& q = p[k];
     // problem k draws from its own stream of the generator
@@ -287,13 +293,23 @@ int tik_sketch(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sketc
       const bool t = tall(q);
       const int64_t longdim = t ? q.m : q.n;
       const int64_t ncol = t ? q.n : q.m;
-      TIK_HIP(hipMemsetAsync(sp.Y[k], 0, size_t(s[k]) * size_t(ncol) * sizeof(double), st));
-      const int64_t chunk = gauss_chunk(q, s[k]);
-      for (int64_t r0 = 0; r0 < longdim; r0 += chunk) {
-        const int64_t kc = std::min(chunk, longdim - r0);
-        TIK_TRY(launch_gauss_gen(pseed, s[k], r0, kc, sp.Xc, 0, st));
-        TIK_TRY(launch_sketch_gemm_f64(sp.Xc, s[k], kc, q.A, f32, q.lda, r0, ncol, t ? 0 : 1,
-                                       sp.Y[k], st));
+      const int64_t chunk = gauss_chunk(q, s[k], sketch_dtype);
+      if (sketch_dtype == TIK_BF16) {
+        for (int64_t r0 = 0; r0 < longdim; r0 += chunk) {
+          const int64_t kc = std::min(chunk, longdim - r0);
+          TIK_TRY(launch_gauss_gen(pseed, s[k], r0, kc, sp.Xc, 1, st));
+          TIK_TRY(launch_sketch_gemm_bf16(sp.Xc, s[k], kc, q.A, f32, q.lda, r0, ncol, t ? 0 : 1,
+                                          sp.Yacc, r0 == 0 ? 1 : 0, st));
+        }
+        TIK_TRY(launch_f32_to_f64(sp.Yacc, sp.Y[k], s[k] * ncol, st));
+      } else {
+        TIK_HIP(hipMemsetAsync(sp.Y[k], 0, size_t(s[k]) * size_t(ncol) * sizeof(double), st));
+        for (int64_t r0 = 0; r0 < longdim; r0 += chunk) {
+          const int64_t kc = std::min(chunk, longdim - r0);
+          TIK_TRY(launch_gauss_gen(pseed, s[k], r0, kc, sp.Xc, 0, st));
+          TIK_TRY(launch_sketch_gemm_f64(sp.Xc, s[k], kc, q.A, f32, q.lda, r0, ncol, t ? 0 : 1,
+                                         sp.Y[k], st));
+        }
       }
     }
   }

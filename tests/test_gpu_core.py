@@ -285,3 +285,60 @@ def test_wide_ragged_and_fp64_storage():
             print("wide ragged", mode, k, "%.2e" % err.max())
             assert np.all(err <= 1e-8), (mode, k, err)
         assert np.all(res.status.cpu().numpy() == tik.ST_CONVERGED)
+
+
+# ------------------------------------------------------------- BF16 sketch ----
+
+def _bf16(a):
+    a32 = np.asarray(a, dtype=np.float32)
+    u = a32.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("m,s", [(1000, 64), (3000, 200)])
+def test_bf16_sketch_matches_rounded_gaussian(m, s):
+    I = np.eye(m)
+    pr = tik.Problems.from_numpy([I], [np.ones(m)])
+    Xb = tik.sketch(pr, tik.GAUSS, [s], 21, sketch_dtype=tik.BF16).Y(0)
+    Xd = tik.sketch(pr, tik.GAUSS, [s], 21).Y(0)
+    # same generator, rounded to BF16 (the device scales by 1/sqrt(s) in FP32
+    # first, so entries may sit one BF16 ulp from the host's rounding)
+    assert np.all(np.abs(Xb - Xd) <= 2.0 ** -8 * np.abs(Xd) + 1e-300)
+    assert np.mean(Xb == _bf16(Xd)) > 0.9
+    rng = np.random.default_rng(5)
+    for shape, dt in [((m, 37), np.float32), ((m, 130), np.float64)]:
+        A = rng.standard_normal(shape).astype(dt)
+        pa = tik.Problems.from_numpy([A], [np.ones(m)])
+        Y = tik.sketch(pa, tik.GAUSS, [s], 21, sketch_dtype=tik.BF16).Y(0)
+        ref = Xb @ _bf16(A)
+        assert np.max(np.abs(Y - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+def test_bf16_sketch_wide():
+    m, n, s = 150, 4000, 600
+    rng = np.random.default_rng(6)
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    pa = tik.Problems.from_numpy([A], [np.ones(m)])
+    Yt = tik.sketch(pa, tik.GAUSS, [s], 3, sketch_dtype=tik.BF16).Y(0)     # s x m = X^T A^T
+    Ytd = tik.sketch(pa, tik.GAUSS, [s], 3).Y(0)
+    # X^T is recovered from the FP64 sketch of [I_m 0]-free relation: compare through rounding bound
+    rel = np.linalg.norm(Yt - Ytd) / np.linalg.norm(Ytd)
+    assert rel < 2e-2, rel          # BF16 operands: ~2^-8 relative per entry, averaged
+    assert Yt.shape == (s, m)
+
+
+@pytest.mark.parametrize("wide", [False, True])
+def test_bf16_sketch_end_to_end(wide):
+    if wide:
+        p = W.under_scaled(m=250, n=8000, N=8)
+    else:
+        p = W.ragged(nprob=1, m_lo=6000, m_hi=6000, n_lo=300, n_hi=300, N=8)[0]
+    pr = dev_problems([p])
+    sk = tik.sketch(pr, tik.GAUSS, [4 * min(p.m, p.n)], 0, sketch_dtype=tik.BF16)
+    pc = tik.precond(sk, p.lams)
+    for mode in (tik.F64_BATCHED, tik.MIXED_BATCHED):
+        res = tik.lsqr_batch(pr, pc, mode, 1e-12 if mode == tik.F64_BATCHED else 1e-10, 300)
+        err = oracle.rel_err(res.x_numpy(0), oracle.solve(p.A, p.b, p.lams))
+        print("bf16 sketch", wide, mode, "%.2e" % err.max(), res.iters.cpu().numpy()[0])
+        assert np.all(err <= 1e-8) and np.all(res.status.cpu().numpy() == tik.ST_CONVERGED)
