@@ -144,12 +144,15 @@ int tik_precond_bytes(tik_sketch_t sk, int32_t route, int32_t N, size_t* bytes);
      C = Y^T Y (or Y Y^T), R = chol(C + lam I), kept as the explicit upper
      triangular inverse R^{-1} so that every later application is a
      triangular matrix-vector product.
-   TIK_ROUTE_LOWRANK (Algorithm 3 steps 4-7, tall problems with s < n):
-     SVD Y = U Sigma V^T computed from the QR of Y^T (no Gram matrix), then
-     s_i = min(s, alpha * ceil(sd_hat(lam_i))) with sd_hat the estimate of
-     Section 3.1.2, and S_i as in Algorithm 3 step 7.
+   TIK_ROUTE_LOWRANK (Algorithm 3 steps 4-7; Algorithm 4 for wide problems):
+     SVD of the sketch computed from the Householder QR of its transpose and
+     a one-sided Jacobi SVD of the triangular factor (no Gram matrix is
+     formed), then s_i = min(s, ceil(alpha * ceil(sd_hat(lam_i)))) with
+     sd_hat the estimate of Section 3.1.2, and S_i as in Algorithm 3 step 7.
+     Needs s <= min(m, n) and s <= 4096 (else TIK_EINVAL).  Synchronizes the
+     stream once per Jacobi sweep and once per problem.
    lambdas  host, nprob x N row-major (problem k's lambdas at k*N), each > 0;
-   alpha    oversampling factor of Algorithm 3 (ignored by TIK_ROUTE_CHOL);
+   alpha    oversampling factor of Algorithm 3, >= 1 (ignored by TIK_ROUTE_CHOL);
    sd_hat   host nprob x N, or NULL: the statistical-dimension estimates
             (TIK_ROUTE_LOWRANK; NaN for TIK_ROUTE_CHOL);
    status   host nprob x N, or NULL: TIK_ST_NOTPD where chol(C + lam I)
@@ -167,6 +170,11 @@ int tik_precond(tik_sketch_t sk, int32_t route, const double* lambdas, int32_t N
    Valid while the preconditioner workspace is. */
 int tik_precond_data(tik_precond_t pc, int32_t k, int32_t i, const double** data,
                      int64_t* dim, int64_t* rank);
+
+/* Device pointer to the singular values of problem k's sketch, in decreasing
+   order, *count = s (TIK_ROUTE_LOWRANK only; TIK_EINVAL otherwise).  Valid
+   while the preconditioner workspace is. */
+int tik_precond_sigma(tik_precond_t pc, int32_t k, const double** sigma, int64_t* count);
 
 /* ------------------------------------------------------------- solve ---- */
 
@@ -218,7 +226,7 @@ int tik_version(void);
 /* Per-kernel-family timing with HIP events recorded around every launch of
    that family on its stream.  Off by default; enabling it adds two event
    records per launch.  Names: "sketch", "gram", "chol", "trinv", "gemm_n",
-   "gemm_t", "trmv", "trmv_t", "lowrank", "vec", "residual". */
+   "gemm_t", "trmv", "trmv_t", "lowrank", "lr_apply", "vec", "residual". */
 int tik_prof_enable(int32_t on);
 int tik_prof_reset(void);
 /* Synchronizes outstanding events of that family; total_ms summed over

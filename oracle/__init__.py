@@ -17,7 +17,8 @@ What it computes (each function cites the passage it follows):
 * ``tikhonov.statistical_dimension`` (Definition 1) and ``sd_hat`` (the
   estimate from the sketch's singular values, Section 3.1.2).
 * ``tikhonov.chol_precond`` / ``lowrank_factors`` / ``lowrank_rinv``: the
-  preconditioners of Algorithms 1-3 written out densely for small checks.
+  preconditioners of Algorithms 1-3 written out densely for small checks;
+  ``lowrank_truncation`` the rank s_i each lambda keeps (Algorithm 3).
 * ``tikhonov.lsqr_iteration_bound`` and the Lemma 2.1 / Theorem 3.2 bounds.
 * ``tikhonov.certify``: an a-posteriori bound on the forward error of a
   candidate solution that holds at any size.
@@ -36,6 +37,7 @@ from .tikhonov import (  # noqa: F401
     lowrank_S,
     lowrank_factors,
     lowrank_rinv,
+    lowrank_truncation,
     chol_precond,
     chol_precond_under,
     lsqr_iteration_bound,

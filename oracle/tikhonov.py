@@ -151,6 +151,18 @@ def lowrank_rinv(V: np.ndarray, sigma: np.ndarray, lam: float,
     return (np.eye(V.shape[0]) - (Vk * S[None, :]) @ Vk.T) / math.sqrt(lam)
 
 
+def lowrank_truncation(sigma_Y: np.ndarray, lam: float, alpha: float, s: int) -> int:
+    """Rank s_i kept for lam (Algorithm 3 steps 1 and 5, Algorithm 4 likewise).
+
+    The algorithm sets s_i = alpha * ceil(sd_lam_i(A)) with the estimate of
+    Section 3.1.2 in place of sd; it is capped at the sketch size s (the
+    algorithm's own requirement alpha sd_lam_N <= n makes the cap inactive
+    for exact estimates), and rounded up when alpha is not an integer.
+    """
+    sd = sd_hat(sigma_Y, lam)
+    return int(min(s, math.ceil(alpha * math.ceil(sd))))
+
+
 # ----------------------------------------------------------------------------
 # Convergence statements
 

@@ -1,0 +1,777 @@
+// Low-statistical-dimension preconditioner (Algorithm 3, Section 3.1).
+//
+// From the short, fat sketch Y = XA (s x n, s < n) the route needs the economy
+// SVD Y = U Sigma V^T (Algorithm 3 step 4) without ever forming a Gram matrix:
+//   1. Householder QR of Y^T (n x s) in FP64: Y^T = Q R_y, blocked in panels of
+//      32 columns with compact-WY trailing updates (Schreiber & Van Loan).
+//   2. One-sided Jacobi SVD (Hestenes) of the s x s triangle R_y: plane
+//      rotations orthogonalise its columns, R_y W = Z Sigma, so the normalised
+//      columns are the left singular vectors Z of R_y and their norms are the
+//      singular values.  Round-robin ordering: every round rotates s/2
+//      disjoint column pairs in parallel, s - 1 rounds make a sweep.
+//   3. Since Y = R_y^T Q^T = W Sigma (Q Z)^T, the right singular vectors of Y
+//      are V = Q Z, obtained by applying the reflectors to [Z; 0] backwards.
+// sd_hat (Section 3.1.2), s_i and S_i (Algorithm 3 steps 5-7) are formed from
+// the singular values per lambda.
+#include "tik_internal.h"
+
+namespace tik {
+
+static constexpr int LR_NB = 32;      // Householder panel width
+
+__device__ __forceinline__ double lr_wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int NT>
+__device__ __forceinline__ double lr_block_sum(double v, double* red) {
+  v = lr_wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) s += red[w];
+  return s;
+}
+
+// Z (n x s, ld n) = Y^T with Y s x n (ld s).
+__global__ void k_lr_transpose(const double* __restrict__ Y, int64_t s, int64_t n,
+                               double* __restrict__ Z) {
+  __shared__ double tile[32][33];
+  const int64_t r0 = int64_t(blockIdx.x) * 32, c0 = int64_t(blockIdx.y) * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t r = r0 + k, c = c0 + tx;          // Y(r, c), r < s, c < n
+    tile[k][tx] = (r < s && c < n) ? Y[r + c * s] : 0.0;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t c = c0 + k, r = r0 + tx;          // Z(c, r) = Y(r, c)
+    if (c < n && r < s) Z[c + r * n] = tile[tx][k];
+  }
+}
+
+// Householder vector of column j (LAPACK dlarfg): on exit Z[j, j] = beta,
+// Z[j+1:n, j] = v (v_0 = 1 implied), tau[j].  One block of 1024 threads.
+__global__ void __launch_bounds__(1024) k_lr_house(double* __restrict__ Z, int64_t n, int64_t j,
+                                                   double* __restrict__ tau) {
+  __shared__ double red[16];
+  __shared__ double sh_scale;
+  double* col = Z + j * n;
+  double ss = 0.0;
+  for (int64_t r = j + 1 + threadIdx.x; r < n; r += blockDim.x) ss += col[r] * col[r];
+  const double sigma = lr_block_sum<1024>(ss, red);
+  if (threadIdx.x == 0) {
+    const double alpha = col[j];
+    if (sigma == 0.0) {
+      tau[j] = 0.0;
+      sh_scale = 0.0;
+    } else {
+      const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+      tau[j] = (beta - alpha) / beta;
+      sh_scale = 1.0 / (alpha - beta);
+      col[j] = beta;
+    }
+  }
+  __syncthreads();
+  const double sc = sh_scale;
+  if (sc != 0.0)
+    for (int64_t r = j + 1 + threadIdx.x; r < n; r += blockDim.x) col[r] *= sc;
+}
+
+// Apply H_j = I - tau v v^T to columns j+1 .. cend-1 of Z (one block per column).
+__global__ void __launch_bounds__(256) k_lr_apply_house(double* __restrict__ Z, int64_t n, int64_t j,
+                                                        const double* __restrict__ tau) {
+  __shared__ double red[4];
+  const int64_t c = j + 1 + blockIdx.x;
+  const double* v = Z + j * n;
+  double* col = Z + c * n;
+  double w = 0.0;
+  for (int64_t r = j + 1 + threadIdx.x; r < n; r += 256) w += v[r] * col[r];
+  double tot = lr_block_sum<256>(w, red);
+  tot = (tot + col[j]) * tau[j];
+  if (threadIdx.x == 0) col[j] -= tot;
+  for (int64_t r = j + 1 + threadIdx.x; r < n; r += 256) col[r] -= tot * v[r];
+}
+
+// Explicit panel V (rows k0..n-1, LR_NB columns, ld = n - k0): unit diagonal,
+// zeros above, the stored reflectors below.
+__global__ void k_lr_copy_v(const double* __restrict__ Z, int64_t n, int64_t k0, int nb,
+                            double* __restrict__ Vc) {
+  const int64_t rows = n - k0;
+  const int64_t total = rows * nb;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t r = e % rows, c = e / rows;
+    double v;
+    if (r < c) v = 0.0;
+    else if (r == c) v = 1.0;
+    else v = Z[(k0 + r) + (k0 + c) * n];
+    Vc[e] = v;
+  }
+}
+
+// C (M x N, ld ldc) = alpha * op(A) B + beta * C_in, FP64, op = transpose when TA.
+// op(A) is M x K: A col-major K x M (TA) or M x K (!TA), lda; B col-major K x N, ldb.
+// Split over K: block z handles k in [z kc, (z+1) kc) and writes its own slice
+// part + z * ldc * N (alpha, no beta), reduced by k_lr_reduce.
+template <bool TA>
+__global__ void __launch_bounds__(256) k_lr_dgemm(int64_t M, int64_t N, int64_t K, int64_t kc,
+                                                  const double* __restrict__ A, int64_t lda,
+                                                  const double* __restrict__ B, int64_t ldb,
+                                                  double* __restrict__ part, int64_t ldc) {
+  __shared__ double As[16][64 + 1];
+  __shared__ double Bs[16][64 + 1];
+  const int tid = threadIdx.x, tm = tid & 15, tn = tid >> 4;
+  const int64_t m0 = int64_t(blockIdx.x) * 64, n0 = int64_t(blockIdx.y) * 64;
+  const int64_t kb = int64_t(blockIdx.z) * kc, ke = min(K, kb + kc);
+  double acc[4][4] = {};
+  for (int64_t k0 = kb; k0 < ke; k0 += 16) {
+    for (int e = tid; e < 16 * 64; e += 256) {
+      int kk, mm;
+      if (TA) { kk = e & 15; mm = e >> 4; } else { mm = e & 63; kk = e >> 6; }
+      const int64_t k = k0 + kk, mi = m0 + mm;
+      double v = 0.0;
+      if (k < ke && mi < M) v = TA ? A[k + mi * lda] : A[mi + k * lda];
+      As[kk][mm] = v;
+    }
+    for (int e = tid; e < 16 * 64; e += 256) {
+      const int kk = e & 15, nn = e >> 4;
+      const int64_t k = k0 + kk, ni = n0 + nn;
+      Bs[kk][nn] = (k < ke && ni < N) ? B[k + ni * ldb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][tm + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tn + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  double* C = part + int64_t(blockIdx.z) * ldc * N;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t mi = m0 + tm + 16 * i, ni = n0 + tn + 16 * j;
+      if (mi < M && ni < N) C[mi + ni * ldc] = acc[i][j];
+    }
+}
+
+// C = beta C + alpha sum_z part[z] (M x N, ld ldc for both).
+__global__ void k_lr_reduce(const double* __restrict__ part, int nz, int64_t M, int64_t N,
+                            int64_t ldc, double alpha, double beta, double* __restrict__ C) {
+  const int64_t total = M * N;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t mi = e % M, ni = e / M;
+    double s = 0.0;
+    for (int z = 0; z < nz; ++z) s += part[int64_t(z) * ldc * N + mi + ni * ldc];
+    const int64_t idx = mi + ni * ldc;
+    C[idx] = (beta == 0.0 ? 0.0 : beta * C[idx]) + alpha * s;
+  }
+}
+
+// T of the compact WY form H_0 ... H_{nb-1} = I - V T V^T from G = V^T V:
+// T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j].  One block.
+__global__ void k_lr_form_t(const double* __restrict__ G, int nb, const double* __restrict__ tau,
+                            double* __restrict__ T) {
+  __shared__ double Ts[LR_NB][LR_NB + 1];
+  __shared__ double z[LR_NB];
+  const int t = threadIdx.x;
+  for (int e = t; e < LR_NB * LR_NB; e += blockDim.x) Ts[e % LR_NB][e / LR_NB] = 0.0;
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    if (t < j) {
+      double s = 0.0;
+      for (int k = t; k < j; ++k) s += Ts[t][k] * G[k + j * nb];
+      z[t] = s;
+    }
+    __syncthreads();
+    if (t < j) Ts[t][j] = -tau[j] * z[t];
+    if (t == j) Ts[j][j] = tau[j];
+    __syncthreads();
+  }
+  for (int e = t; e < nb * nb; e += blockDim.x) T[e] = Ts[e % nb][e / nb];
+}
+
+// W2 (nb x N) = op(T) W1 with T upper triangular nb x nb; op = transpose when TT.
+template <bool TT>
+__global__ void k_lr_tmul(const double* __restrict__ T, int nb, const double* __restrict__ W1,
+                          int64_t N, double* __restrict__ W2) {
+  const int64_t total = int64_t(nb) * N;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int i = int(e % nb);
+    const int64_t c = e / nb;
+    double s = 0.0;
+    if (TT)
+      for (int k = 0; k <= i; ++k) s += T[k + i * nb] * W1[k + c * nb];   // (T^T)[i][k] = T[k][i]
+    else
+      for (int k = i; k < nb; ++k) s += T[i + k * nb] * W1[k + c * nb];
+    W2[e] = s;
+  }
+}
+
+// Rz (s x s, ld s): the upper triangle of the factored Z, zeros below.
+__global__ void k_lr_get_r(const double* __restrict__ Z, int64_t n, int64_t s,
+                           double* __restrict__ Rz) {
+  const int64_t total = s * s;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t r = e % s, c = e / s;
+    Rz[e] = r <= c ? Z[r + c * n] : 0.0;
+  }
+}
+
+// One round of one-sided Jacobi on the columns of G (s x s, ld s): one wave
+// per column pair of the round-robin schedule over sp = s rounded up to even.
+// Pair 0 is (r, sp - 1); pair i > 0 is ((r + i) mod (sp - 1), (r - i) mod (sp - 1)).
+// A pair is rotated when |g_p . g_q| > tol sqrt(|g_p|^2 |g_q|^2); the number of
+// rotations is added to *count.
+__global__ void __launch_bounds__(256) k_lr_jacobi_round(double* __restrict__ G, int64_t s, int sp,
+                                                         int r, double tol,
+                                                         unsigned int* __restrict__ count) {
+  const int lane = threadIdx.x & 63;
+  const int pair = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (pair >= sp / 2) return;
+  const int m = sp - 1;
+  int p, q;
+  if (pair == 0) {
+    p = r;
+    q = m;
+  } else {
+    p = (r + pair) % m;
+    q = ((r - pair) % m + m) % m;
+  }
+  if (p >= s || q >= s) return;   // the padding column
+  double* gp = G + int64_t(p) * s;
+  double* gq = G + int64_t(q) * s;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int64_t i = lane; i < s; i += 64) {
+    const double x = gp[i], y = gq[i];
+    a += x * x;
+    b += y * y;
+    c += x * y;
+  }
+  a = lr_wave_sum(a);
+  b = lr_wave_sum(b);
+  c = lr_wave_sum(c);
+  if (!(fabs(c) > tol * sqrt(a * b))) return;
+  const double zeta = (b - a) / (2.0 * c);
+  const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+  for (int64_t i = lane; i < s; i += 64) {
+    const double x = gp[i], y = gq[i];
+    gp[i] = cs * x - sn * y;
+    gq[i] = sn * x + cs * y;
+  }
+  if (lane == 0) atomicAdd(count, 1u);
+}
+
+// sigma_j = ||g_j||, g_j /= sigma_j (one block per column).
+__global__ void __launch_bounds__(256) k_lr_normalize(double* __restrict__ G, int64_t s,
+                                                      double* __restrict__ sig) {
+  __shared__ double red[4];
+  double* g = G + int64_t(blockIdx.x) * s;
+  double ss = 0.0;
+  for (int64_t i = threadIdx.x; i < s; i += 256) ss += g[i] * g[i];
+  const double nrm = sqrt(lr_block_sum<256>(ss, red));
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  for (int64_t i = threadIdx.x; i < s; i += 256) g[i] *= inv;
+  if (threadIdx.x == 0) sig[blockIdx.x] = nrm;
+}
+
+// Descending order of sigma (bitonic sort of (sigma, index) in LDS, s <= 4096);
+// Zs[:, k] = G[:, perm[k]] padded with n - s zero rows (X = [Z; 0], n x s).
+__global__ void __launch_bounds__(1024) k_lr_sort(const double* __restrict__ sig, int64_t s,
+                                                  int32_t* __restrict__ perm,
+                                                  double* __restrict__ sig_sorted) {
+  __shared__ double key[4096];
+  __shared__ int32_t idx[4096];
+  int P = 1;
+  while (P < s) P <<= 1;
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {
+    key[i] = i < s ? sig[i] : -1.0;
+    idx[i] = i;
+  }
+  __syncthreads();
+  for (int len = 2; len <= P; len <<= 1) {
+    for (int str = len >> 1; str > 0; str >>= 1) {
+      for (int i = threadIdx.x; i < P; i += blockDim.x) {
+        const int j = i ^ str;
+        if (j > i) {
+          const bool desc = (i & len) == 0;
+          const double a = key[i], b = key[j];
+          const bool swap = desc ? (a < b || (a == b && idx[i] > idx[j]))
+                                 : (a > b || (a == b && idx[i] < idx[j]));
+          if (swap) {
+            key[i] = b;
+            key[j] = a;
+            const int32_t t = idx[i];
+            idx[i] = idx[j];
+            idx[j] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < s; i += blockDim.x) {
+    perm[i] = idx[i];
+    sig_sorted[i] = key[i];
+  }
+}
+
+__global__ void k_lr_gather(const double* __restrict__ G, int64_t s, int64_t n,
+                            const int32_t* __restrict__ perm, double* __restrict__ X) {
+  const int64_t total = n * s;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t r = e % n, c = e / n;
+    X[e] = r < s ? G[r + int64_t(perm[c]) * s] : 0.0;
+  }
+}
+
+// S_i[j] = 1 - (1 + sigma_j^2 / lam_i)^(-1/2) for j < s_i, else 0 (Algorithm 3 step 7).
+__global__ void k_lr_S(const double* __restrict__ sig, int64_t s, const double* __restrict__ lams,
+                       const int32_t* __restrict__ si, int N, double* __restrict__ S) {
+  const int64_t total = int64_t(N) * s;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int i = int(e / s);
+    const int64_t j = e % s;
+    const double sg = sig[j];
+    S[e] = j < si[i] ? 1.0 - 1.0 / sqrt(1.0 + sg * sg / lams[i]) : 0.0;
+  }
+}
+
+// ------------------------------------------------------------- host side ----
+static unsigned lr_grid(int64_t total) {
+  return unsigned(std::min<int64_t>(std::max<int64_t>(cdiv(total, 256), 1), 8192));
+}
+
+// op(A) B for the QR updates, split over K into nz slices of `part`.
+static int lr_gemm(bool ta, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                   const double* B, int64_t ldb, double* C, double alpha, double beta,
+                   double* part, int64_t part_cap, hipStream_t st) {
+  int nz = int(std::max<int64_t>(1, std::min<int64_t>(cdiv(K, 512), 64)));
+  while (nz > 1 && M * N * nz > part_cap) --nz;
+  const int64_t kc = cdiv(cdiv(K, nz), 16) * 16;
+  nz = int(cdiv(K, kc));
+  const dim3 grid = dim3(unsigned(cdiv(M, 64)), unsigned(cdiv(N, 64)), unsigned(nz));
+  if (ta)
+    hipLaunchKernelGGL(k_lr_dgemm<true>, grid, dim3(256), 0, st, M, N, K, kc, A, lda, B, ldb, part, M);
+  else
+    hipLaunchKernelGGL(k_lr_dgemm<false>, grid, dim3(256), 0, st, M, N, K, kc, A, lda, B, ldb, part, M);
+  TIK_LAUNCHED("k_lr_dgemm");
+  // C has leading dimension M here (callers pass compact C) unless beta == 1 with ldc > M
+  hipLaunchKernelGGL(k_lr_reduce, dim3(lr_grid(M * N)), dim3(256), 0, st, part, nz, M, N, M, alpha,
+                     beta, C);
+  TIK_LAUNCHED("k_lr_reduce");
+  return TIK_OK;
+}
+
+// C (M x N, ld ldc) += alpha * A (M x K, ld lda) * B (K x N, ld K): rows independent,
+// computed by the dgemm kernel into `part` (ld M) and added by a strided reduce.
+__global__ void k_lr_add_strided(const double* __restrict__ part, int64_t M, int64_t N,
+                                 double alpha, double* __restrict__ C, int64_t ldc) {
+  const int64_t total = M * N;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t mi = e % M, ni = e / M;
+    C[mi + ni * ldc] += alpha * part[e];
+  }
+}
+
+static int lr_gemm_add(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                       const double* B, double* C, int64_t ldc, double alpha, double* part,
+                       hipStream_t st) {
+  const dim3 grid = dim3(unsigned(cdiv(M, 64)), unsigned(cdiv(N, 64)), 1u);
+  hipLaunchKernelGGL(k_lr_dgemm<false>, grid, dim3(256), 0, st, M, N, K, K, A, lda, B, K, part, M);
+  TIK_LAUNCHED("k_lr_dgemm");
+  hipLaunchKernelGGL(k_lr_add_strided, dim3(lr_grid(M * N)), dim3(256), 0, st, part, M, N, alpha, C,
+                     ldc);
+  TIK_LAUNCHED("k_lr_add_strided");
+  return TIK_OK;
+}
+
+size_t lowrank_scratch_doubles(int64_t n, int64_t s) {
+  // Z (n s) + Rz (s s) + X (n s) + Vc (n nb) + tau (s) + T (panels nb nb)
+  // + G (nb nb) + W1, W2 (nb s each) + part (max of 64 nb nb, n s)
+  const int64_t np = cdiv(s, LR_NB);
+  return size_t(n * s + s * s + n * s + n * LR_NB + s + np * LR_NB * LR_NB + LR_NB * LR_NB +
+                2 * LR_NB * s + std::max<int64_t>(64 * LR_NB * std::max<int64_t>(s, LR_NB), n * s) +
+                64);
+}
+
+// V (n x s, ld n, columns by decreasing sigma) and sigma (s) of Y (s x n, ld s).
+// `scratch` holds lowrank_scratch_doubles(n, s) doubles; `cnt` one counter.
+int launch_lowrank_svd(const double* Y, int64_t s, int64_t n, double* V, double* sig,
+                       double* scratch, unsigned int* cnt, int32_t* perm, int* sweeps_out,
+                       hipStream_t st) {
+  ProfScope ps("lowrank", st);
+  double* Z = scratch;
+  double* Rz = Z + n * s;
+  double* X = Rz + s * s;
+  double* Vc = X + n * s;
+  double* tau = Vc + n * LR_NB;
+  const int64_t np = cdiv(s, LR_NB);
+  double* T = tau + s;
+  double* Gm = T + np * LR_NB * LR_NB;
+  double* W1 = Gm + LR_NB * LR_NB;
+  double* W2 = W1 + LR_NB * s;
+  double* part = W2 + LR_NB * s;
+  const int64_t part_cap = std::max<int64_t>(64 * LR_NB * std::max<int64_t>(s, LR_NB), n * s);
+  double* sig_raw = X;          // reused before X is needed
+  // 1. Z = Y^T, Householder QR
+  hipLaunchKernelGGL(k_lr_transpose, dim3(unsigned(cdiv(s, 32)), unsigned(cdiv(n, 32))), dim3(256),
+                     0, st, Y, s, n, Z);
+  TIK_LAUNCHED("k_lr_transpose");
+  for (int64_t pnl = 0; pnl < np; ++pnl) {
+    const int64_t k0 = pnl * LR_NB;
+    const int nb = int(std::min<int64_t>(LR_NB, s - k0));
+    for (int jj = 0; jj < nb; ++jj) {
+      const int64_t j = k0 + jj;
+      hipLaunchKernelGGL(k_lr_house, dim3(1), dim3(1024), 0, st, Z, n, j, tau);
+      TIK_LAUNCHED("k_lr_house");
+      if (jj + 1 < nb) {
+        hipLaunchKernelGGL(k_lr_apply_house, dim3(unsigned(nb - jj - 1)), dim3(256), 0, st, Z, n, j,
+                           tau);
+        TIK_LAUNCHED("k_lr_apply_house");
+      }
+    }
+    const int64_t rows = n - k0;
+    hipLaunchKernelGGL(k_lr_copy_v, dim3(lr_grid(rows * nb)), dim3(256), 0, st, Z, n, k0, nb, Vc);
+    TIK_LAUNCHED("k_lr_copy_v");
+    // G = Vc^T Vc, T
+    TIK_TRY(lr_gemm(true, nb, nb, rows, Vc, rows, Vc, rows, Gm, 1.0, 0.0, part, part_cap, st));
+    hipLaunchKernelGGL(k_lr_form_t, dim3(1), dim3(64), 0, st, Gm, nb, tau + k0,
+                       T + pnl * LR_NB * LR_NB);
+    TIK_LAUNCHED("k_lr_form_t");
+    const int64_t ntr = s - k0 - nb;
+    if (ntr > 0) {
+      double* Ztr = Z + k0 + (k0 + nb) * n;
+      // W1 = Vc^T Ztr (nb x ntr), W2 = T^T W1, Ztr -= Vc W2
+      TIK_TRY(lr_gemm(true, nb, ntr, rows, Vc, rows, Ztr, n, W1, 1.0, 0.0, part, part_cap, st));
+      hipLaunchKernelGGL(k_lr_tmul<true>, dim3(lr_grid(nb * ntr)), dim3(256), 0, st,
+                         T + pnl * LR_NB * LR_NB, nb, W1, ntr, W2);
+      TIK_LAUNCHED("k_lr_tmul");
+      TIK_TRY(lr_gemm_add(rows, ntr, nb, Vc, rows, W2, Ztr, n, -1.0, part, st));
+    }
+  }
+  // 2. one-sided Jacobi on R_y
+  hipLaunchKernelGGL(k_lr_get_r, dim3(lr_grid(s * s)), dim3(256), 0, st, Z, n, s, Rz);
+  TIK_LAUNCHED("k_lr_get_r");
+  const int sp = int(s + (s & 1));
+  const double tol = 1e-15 * std::sqrt(double(s));
+  int sweeps = 0;
+  const int maxsweeps = 30;
+  for (; sweeps < maxsweeps;) {
+    TIK_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned int), st));
+    for (int r = 0; r < sp - 1; ++r) {
+      hipLaunchKernelGGL(k_lr_jacobi_round, dim3(unsigned(cdiv(sp / 2, 4))), dim3(256), 0, st, Rz, s,
+                         sp, r, tol, cnt);
+    }
+    TIK_LAUNCHED("k_lr_jacobi_round");
+    ++sweeps;
+    unsigned int h = 0;
+    TIK_HIP(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
+    TIK_HIP(hipStreamSynchronize(st));
+    if (h == 0) break;
+  }
+  if (sweeps_out) *sweeps_out = sweeps;
+  hipLaunchKernelGGL(k_lr_normalize, dim3(unsigned(s)), dim3(256), 0, st, Rz, s, sig_raw);
+  TIK_LAUNCHED("k_lr_normalize");
+  hipLaunchKernelGGL(k_lr_sort, dim3(1), dim3(1024), 0, st, sig_raw, s, perm, sig);
+  TIK_LAUNCHED("k_lr_sort");
+  // 3. V = Q [Z; 0], reflector panels applied last to first
+  hipLaunchKernelGGL(k_lr_gather, dim3(lr_grid(n * s)), dim3(256), 0, st, Rz, s, n, perm, V);
+  TIK_LAUNCHED("k_lr_gather");
+  for (int64_t pnl = np - 1; pnl >= 0; --pnl) {
+    const int64_t k0 = pnl * LR_NB;
+    const int nb = int(std::min<int64_t>(LR_NB, s - k0));
+    const int64_t rows = n - k0;
+    hipLaunchKernelGGL(k_lr_copy_v, dim3(lr_grid(rows * nb)), dim3(256), 0, st, Z, n, k0, nb, Vc);
+    TIK_LAUNCHED("k_lr_copy_v");
+    double* Xr = V + k0;    // rows k0..n-1 of V, all s columns, ld n
+    TIK_TRY(lr_gemm(true, nb, s, rows, Vc, rows, Xr, n, W1, 1.0, 0.0, part, part_cap, st));
+    hipLaunchKernelGGL(k_lr_tmul<false>, dim3(lr_grid(nb * s)), dim3(256), 0, st,
+                       T + pnl * LR_NB * LR_NB, nb, W1, s, W2);
+    TIK_LAUNCHED("k_lr_tmul");
+    TIK_TRY(lr_gemm_add(rows, s, nb, Vc, rows, W2, Xr, n, -1.0, part, st));
+  }
+  return TIK_OK;
+}
+
+int launch_lowrank_S(const double* sig, int64_t s, const double* lams, const int32_t* si, int N,
+                     double* S, hipStream_t st) {
+  hipLaunchKernelGGL(k_lr_S, dim3(lr_grid(int64_t(N) * s)), dim3(256), 0, st, sig, s, lams, si, N, S);
+  TIK_LAUNCHED("k_lr_S");
+  return TIK_OK;
+}
+
+
+// ===================================================== low-rank apply =======
+// R_i^{-1} x = lam_i^{-1/2} (x - V S_i V^T x) (eq. RinvOver, Algorithm 3 step 8)
+// for all lambdas of a solve at once; the matrix is symmetric, so the same
+// three kernels give R^{-T}.  V (k x s, ld k) is read twice per application:
+//   proj    part[ch][j][i] = sum_{r in chunk ch} V[r, j] x_i[r]     (j < smax)
+//   expand  opart[jc][i][r] = sum_{j in column chunk jc} V[r, j] c[j, i],
+//           c[j, i] = S_i[j] sum_ch part[ch][j][i]
+//   fin     the LSQR step that consumes R^{-1} x, with the chunk sums of opart.
+// S_i[j] is zero for j >= s_i, which truncates every lambda to its own rank.
+
+// K values per lane reduced over the 64 lanes: halving exchanges (K/2 + K/4
+// + ... shuffles) leave lane l with the total of value l >> (6 - log2 K).
+template <int K>
+__device__ __forceinline__ void lr_xreduce(double (&v)[K], int lane) {
+  int h = K;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    if (h > 1) {
+      h >>= 1;
+      const bool up = (lane & o) != 0;
+#pragma unroll
+      for (int q = 0; q < K / 2; ++q) {
+        if (q < h) {
+          const double send = up ? v[q] : v[q + h];
+          const double keep = up ? v[q + h] : v[q];
+          v[q] = keep + __shfl_xor(send, o, 64);
+        }
+      }
+    } else {
+      v[0] += __shfl_xor(v[0], o, 64);
+    }
+  }
+}
+
+template <int NC, int CPW, bool LMAJ>
+__global__ void __launch_bounds__(256) k_lr_proj(const DevProb* __restrict__ P,
+                                                 const Item* __restrict__ items, int N,
+                                                 const double* __restrict__ src,
+                                                 double* __restrict__ part) {
+  constexpr int K = CPW * NC;
+  static_assert(K <= 64, "values per lane");
+  const Item it = items[blockIdx.x];
+  const DevProb& pr = P[it.p];
+  const int64_t k = pr.k;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t j0 = int64_t(it.blk) * (4 * CPW) + int64_t(wv) * CPW;
+  const int64_t rb = int64_t(it.ch) * pr.lrRch, re = min(k, rb + pr.lrRch);
+  const double* __restrict__ V = pr.V;
+  double acc[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) acc[q] = 0.0;
+  for (int64_t r = rb + lane; r < re; r += 64) {
+    double xv[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i)
+      xv[i] = i < N ? (LMAJ ? src[pr.offS * N + int64_t(i) * k + r] : src[(pr.offS + r) * N + i]) : 0.0;
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) {
+      const double vq = (j0 + q < pr.smax) ? V[r + (j0 + q) * k] : 0.0;
+#pragma unroll
+      for (int i = 0; i < NC; ++i) acc[q * NC + i] = fma(vq, xv[i], acc[q * NC + i]);
+    }
+  }
+  lr_xreduce<K>(acc, lane);
+  constexpr int G = 64 / K;
+  if ((lane & (G - 1)) == 0) {
+    const int idx = lane / G, q = idx / NC, i = idx % NC;
+    const int64_t j = j0 + q;
+    if (j < pr.smax && i < N) part[pr.lrPart + (int64_t(it.ch) * pr.s + j) * N + i] = acc[0];
+  }
+}
+
+static constexpr int LR_JC = 256;    // columns of V per expand block
+
+template <int NC>
+__global__ void __launch_bounds__(256) k_lr_expand(const DevProb* __restrict__ P,
+                                                   const Item* __restrict__ items, int N,
+                                                   const double* __restrict__ part,
+                                                   double* __restrict__ opart,
+                                                   const Scal* __restrict__ sc) {
+  __shared__ double cs[LR_JC * NC];
+  const Item it = items[blockIdx.x];
+  const DevProb& pr = P[it.p];
+  const int64_t k = pr.k;
+  const int64_t j0 = int64_t(it.ch) * LR_JC;
+  const int jn = int(min<int64_t>(pr.smax - j0, LR_JC));
+  for (int e = threadIdx.x; e < LR_JC * NC; e += 256) {
+    const int jj = e / NC, i = e % NC;
+    double c = 0.0;
+    if (jj < jn && i < N) {
+      const int64_t j = j0 + jj;
+      for (int ch = 0; ch < pr.lrNch; ++ch) c += part[pr.lrPart + (int64_t(ch) * pr.s + j) * N + i];
+      c *= pr.S[int64_t(sc[it.p * N + i].li) * pr.s + j];
+    }
+    cs[e] = c;
+  }
+  __syncthreads();
+  const int64_t r = int64_t(it.blk) * 256 + threadIdx.x;
+  if (r >= k) return;
+  double acc[NC];
+#pragma unroll
+  for (int i = 0; i < NC; ++i) acc[i] = 0.0;
+  const double* __restrict__ Vr = pr.V + r + j0 * k;
+  int jj = 0;
+  for (; jj + 4 <= jn; jj += 4) {
+    const double v0 = Vr[int64_t(jj) * k], v1 = Vr[int64_t(jj + 1) * k];
+    const double v2 = Vr[int64_t(jj + 2) * k], v3 = Vr[int64_t(jj + 3) * k];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      double a = acc[i];
+      a = fma(v0, cs[jj * NC + i], a);
+      a = fma(v1, cs[(jj + 1) * NC + i], a);
+      a = fma(v2, cs[(jj + 2) * NC + i], a);
+      a = fma(v3, cs[(jj + 3) * NC + i], a);
+      acc[i] = a;
+    }
+  }
+  for (; jj < jn; ++jj) {
+    const double v0 = Vr[int64_t(jj) * k];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) acc[i] = fma(v0, cs[jj * NC + i], acc[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < NC; ++i)
+    if (i < N) opart[pr.lrOpart + (int64_t(it.ch) * N + i) * k + r] = acc[i];
+}
+
+// STAGE 0 (the R^{-T} step of the v-update): q = R^{-1} t - beta_{i+1} v with
+//   t stored lambda-major, and per-block partial squared norms of q;
+//   TALL = false (Algorithm 4, the R^{-T} step of the u-update): the same
+//   with alpha_i in place of beta_{i+1} and the partials in the beta array.
+// STAGE 1 (the R^{-1} step): w = R^{-1} q / alpha, v = q / alpha and the x, e
+//   recurrences (TALL); w = R^{-1} q / beta, u = q / beta (not TALL).
+template <int NC, int STAGE, bool TALL>
+__global__ void __launch_bounds__(256) k_lr_fin(const DevProb* __restrict__ P,
+                                                const Item* __restrict__ items, int N,
+                                                const double* __restrict__ src,
+                                                const double* __restrict__ opart,
+                                                double* __restrict__ q, double* __restrict__ v,
+                                                double* __restrict__ w, double* __restrict__ x,
+                                                double* __restrict__ e,
+                                                const Scal* __restrict__ sc,
+                                                double* __restrict__ pn, int init) {
+  constexpr int FR = 256 / NC;
+  __shared__ double sh[256];
+  const Item it = items[blockIdx.x];
+  const DevProb& pr = P[it.p];
+  const int64_t k = pr.k;
+  const int i = threadIdx.x % NC;
+  const int64_t r = int64_t(it.blk) * FR + threadIdx.x / NC;
+  double nrm = 0.0;
+  if (r < k && i < N) {
+    double o = 0.0;
+    for (int jc = 0; jc < pr.lrNjc; ++jc) o += opart[pr.lrOpart + (int64_t(jc) * N + i) * k + r];
+    const Scal& S = sc[it.p * N + i];
+    const double il = 1.0 / S.sqlam;
+    const int64_t idx = (pr.offS + r) * N + i;
+    if (STAGE == 0) {
+      const double tv = src[pr.offS * N + int64_t(i) * k + r];
+      const double nv = (tv - o) * il - (TALL ? S.beta_new : S.alpha) * v[idx];
+      q[idx] = nv;
+      nrm = nv * nv;
+    } else {
+      const double qv = src[idx];
+      const double scale = TALL ? S.ialpha : S.ibeta;
+      const double wr = (qv - o) * il * scale;
+      v[idx] = qv * scale;
+      w[idx] = wr;
+      if (TALL) {
+        if (init) {
+          x[idx] = 0.0;
+          e[idx] = wr;
+        } else if (S.upd) {
+          const double eo = e[idx];
+          x[idx] += S.cx * eo;
+          e[idx] = wr - S.ce * eo;
+        }
+      }
+    }
+  }
+  if (STAGE != 0) return;
+  sh[threadIdx.x] = nrm;
+  __syncthreads();
+  if (threadIdx.x < NC && int(threadIdx.x) < N) {
+    double s = 0.0;
+    for (int rr = 0; rr < FR; ++rr) s += sh[rr * NC + threadIdx.x];
+    pn[((TALL ? pr.pnQ : pr.pnN) + it.blk) * N + threadIdx.x] = s;
+  }
+}
+
+template <int NC>
+static int lr_apply_nc(int stage, int tall, const DevProb* P, const Item* itP, int nP,
+                       const Item* itE, int nE, const Item* itF, int nF, int N, const double* src,
+                       double* part, double* opart, double* q, double* v, double* w, double* x,
+                       double* e, const Scal* sc, double* pn, int init, hipStream_t st) {
+  constexpr int CPW = NC >= 32 ? 2 : 4;
+  if (nP > 0) {
+    if (stage == 0)   // t is stored lambda-major
+      hipLaunchKernelGGL((k_lr_proj<NC, CPW, true>), dim3(unsigned(nP)), dim3(256), 0, st, P, itP, N,
+                         src, part);
+    else
+      hipLaunchKernelGGL((k_lr_proj<NC, CPW, false>), dim3(unsigned(nP)), dim3(256), 0, st, P, itP, N,
+                         src, part);
+    TIK_LAUNCHED("k_lr_proj");
+  }
+  if (nE > 0) {
+    hipLaunchKernelGGL(k_lr_expand<NC>, dim3(unsigned(nE)), dim3(256), 0, st, P, itE, N, part, opart,
+                       sc);
+    TIK_LAUNCHED("k_lr_expand");
+  }
+  if (nF > 0) {
+    if (stage == 0) {
+      if (tall)
+        hipLaunchKernelGGL((k_lr_fin<NC, 0, true>), dim3(unsigned(nF)), dim3(256), 0, st, P, itF, N, src,
+                           opart, q, v, w, x, e, sc, pn, init);
+      else
+        hipLaunchKernelGGL((k_lr_fin<NC, 0, false>), dim3(unsigned(nF)), dim3(256), 0, st, P, itF, N,
+                           src, opart, q, v, w, x, e, sc, pn, init);
+    } else {
+      if (tall)
+        hipLaunchKernelGGL((k_lr_fin<NC, 1, true>), dim3(unsigned(nF)), dim3(256), 0, st, P, itF, N, src,
+                           opart, q, v, w, x, e, sc, pn, init);
+      else
+        hipLaunchKernelGGL((k_lr_fin<NC, 1, false>), dim3(unsigned(nF)), dim3(256), 0, st, P, itF, N,
+                           src, opart, q, v, w, x, e, sc, pn, init);
+    }
+    TIK_LAUNCHED("k_lr_fin");
+  }
+  return TIK_OK;
+}
+
+int launch_lr_apply(int nc, int stage, int tall, const DevProb* P, const Item* itP, int nP,
+                    const Item* itE, int nE, const Item* itF, int nF, int N, const double* src,
+                    double* part, double* opart, double* q, double* v, double* w, double* x,
+                    double* e, const Scal* sc, double* pn, int init, hipStream_t st) {
+  switch (nc) {
+#define TIK_LR_CASE(C)                                                                          \
+  case C:                                                                                       \
+    return lr_apply_nc<C>(stage, tall, P, itP, nP, itE, nE, itF, nF, N, src, part, opart, q, v, \
+                          w, x, e, sc, pn, init, st);
+    TIK_LR_CASE(1)
+    TIK_LR_CASE(2)
+    TIK_LR_CASE(4)
+    TIK_LR_CASE(8)
+    TIK_LR_CASE(16)
+    TIK_LR_CASE(32)
+#undef TIK_LR_CASE
+  }
+  set_error("internal: lambda batch wider than 32");
+  return TIK_ENOTSUP;
+}
+
+}  // namespace tik

@@ -914,6 +914,16 @@ __global__ void k_wide_write(const DevProb* __restrict__ P, int N, const double*
 
 namespace {
 
+// Item tables and partial-buffer sizes of the low-rank apply kernels.
+struct LrTables {
+  std::vector<Item> itLP, itLE, itLF;
+  int64_t totLP = 0, totLO = 0;
+  void clear() {
+    itLP.clear(); itLE.clear(); itLF.clear();
+    totLP = totLO = 0;
+  }
+};
+
 // One set of (problem, lambda-range) solved together.
 struct Plan {
   int N = 0, NC = 1, rbN = 64;
@@ -921,6 +931,8 @@ struct Plan {
   std::vector<int> lsel;      // lambda indices solved (the same list for every problem)
   std::vector<DevProb> P;
   std::vector<Item> itN, itB, itT, itQ, itR, itM;
+  LrTables lr;                          // low-rank apply: proj, expand, fin
+  bool lowrank = false;
   int cpw = 16;
   int cbT = 64;        // columns per gemm_t block (128 on matrix cores)
   int64_t totL = 0, totS = 0, totPT = 0, nbN = 0, nbB = 0, nbQ = 0;
@@ -930,6 +942,8 @@ struct Plan {
 struct Bufs {
   DevProb* P;
   Item *itN, *itB, *itT, *itQ, *itR, *itM;
+  Item *itLP, *itLE, *itLF;
+  double *lpart, *lopart;
   Scal* sc;
   void* ut;
   double *ub, *v, *q, *w, *e, *x, *t;
@@ -949,6 +963,41 @@ int pick_nc(int N) {
   return nc;
 }
 
+// Low-rank apply tables of one problem (k = its short dimension; V holds the
+// right singular vectors of a tall problem's sketch, the left ones of a wide
+// problem's).  Buffer sizes depend on s only, so any subset of the lambdas
+// fits the same space.  Returns the number of fin blocks (norm partials).
+int32_t lowrank_items(const tik_precond_s* pc, int p, int lp, const std::vector<int>& lsel, int NC,
+                      LrTables& t, DevProb& d) {
+  const int N = int(lsel.size());
+  const int64_t k = d.k, s = pc->srank[p];
+  int64_t smax = 0;
+  for (int gi : lsel) smax = std::max<int64_t>(smax, pc->si[size_t(p) * pc->N + gi]);
+  d.V = pc->V[p];
+  d.S = pc->S[p];
+  d.s = s;
+  d.smax = smax;
+  const int cols = 4 * (NC >= 32 ? 2 : 4);                // columns per projection block
+  const int64_t cbs = std::max<int64_t>(1, cdiv(s, cols));
+  int64_t nch = std::max<int64_t>(1, std::min<int64_t>(1024 / cbs, cdiv(k, 64)));
+  const int64_t rch = cdiv(cdiv(k, nch), 64) * 64;
+  nch = cdiv(k, rch);
+  d.lrRch = rch;
+  d.lrNch = int32_t(nch);
+  d.lrNjc = int32_t(cdiv(smax, 256));
+  d.lrPart = t.totLP;
+  d.lrOpart = t.totLO;
+  t.totLP += nch * s * N;
+  t.totLO += cdiv(s, 256) * k * N;
+  for (int64_t ch = 0; ch < nch; ++ch)
+    for (int64_t jb = 0; jb < cdiv(smax, cols); ++jb) t.itLP.push_back({lp, int32_t(jb), int32_t(ch), 0});
+  for (int64_t jc = 0; jc < d.lrNjc; ++jc)
+    for (int64_t rb = 0; rb < cdiv(k, 256); ++rb) t.itLE.push_back({lp, int32_t(rb), int32_t(jc), 0});
+  const int64_t nf = cdiv(k, 256 / NC);
+  for (int64_t fb = 0; fb < nf; ++fb) t.itLF.push_back({lp, int32_t(fb), 0, 0});
+  return int32_t(nf);
+}
+
 void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vector<int>& pidx,
                const std::vector<int>& lsel, Plan& pl, const void* const* Aover = nullptr,
                const int64_t* ldover = nullptr) {
@@ -962,7 +1011,9 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
   pl.lsel = lsel;
   pl.P.clear();
   pl.itN.clear(); pl.itB.clear(); pl.itT.clear(); pl.itQ.clear(); pl.itR.clear(); pl.itM.clear();
+  pl.lr.clear();
   pl.totL = pl.totS = pl.totPT = pl.nbN = pl.nbB = pl.nbQ = 0;
+  pl.lowrank = pc->route == TIK_ROUTE_LOWRANK;
   const int np = int(pidx.size());
   int64_t colblocks = 0;
   for (int lp = 0; lp < np; ++lp) colblocks += cdiv(probs[pidx[lp]].n, pl.cbT);
@@ -988,6 +1039,7 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
     d.nblkN = int32_t(cdiv(g.m, pl.rbN));
     d.nblkB = int32_t(cdiv(g.n, BLK));
     d.nblkQ = int32_t(cdiv(g.n, 4 * pl.cpw));
+    if (pl.lowrank) d.nblkQ = lowrank_items(pc, pidx[lp], lp, lsel, pl.NC, pl.lr, d);
     d.pnN = pl.nbN;
     d.pnB = pl.nbB;
     d.pnQ = pl.nbQ;
@@ -1004,10 +1056,12 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
     for (int b = 0; b < d.nblkB; ++b) pl.itB.push_back({lp, b, 0, 0});
     for (int64_t ch = 0; ch < nch; ++ch)
       for (int64_t c = 0; c < cb; ++c) pl.itT.push_back({lp, int32_t(c), int32_t(ch), 0});
-    for (int i = 0; i < N; ++i)
-      for (int b = 0; b < d.nblkQ; ++b) pl.itQ.push_back({lp, b, 0, lp * N + i});
-    for (int i = 0; i < N; ++i)
-      for (int64_t b = 0; b < cdiv(g.n, 16); ++b) pl.itM.push_back({lp, int32_t(b), 0, lp * N + i});
+    if (!pl.lowrank) {
+      for (int i = 0; i < N; ++i)
+        for (int b = 0; b < d.nblkQ; ++b) pl.itQ.push_back({lp, b, 0, lp * N + i});
+      for (int i = 0; i < N; ++i)
+        for (int64_t b = 0; b < cdiv(g.n, 16); ++b) pl.itM.push_back({lp, int32_t(b), 0, lp * N + i});
+    }
     for (int64_t b = 0; b < cdiv(g.n, BLK / pl.NC); ++b) pl.itR.push_back({lp, int32_t(b), 0, 0});
     pl.totL += g.m;
     pl.totS += g.n;
@@ -1029,6 +1083,11 @@ void take_bufs(Arena& a, const Plan& pl, size_t tc, Bufs& b) {
   b.itQ = a.take<Item>(pl.itQ.size());
   b.itR = a.take<Item>(pl.itR.size());
   b.itM = a.take<Item>(pl.itM.size());
+  b.itLP = a.take<Item>(pl.lr.itLP.size());
+  b.itLE = a.take<Item>(pl.lr.itLE.size());
+  b.itLF = a.take<Item>(pl.lr.itLF.size());
+  b.lpart = a.take<double>(size_t(pl.lr.totLP));
+  b.lopart = a.take<double>(size_t(pl.lr.totLO));
   b.sc = a.take<Scal>(pl.J);
   b.ut = a.take<char>(size_t(pl.totL) * N * tc);
   b.ub = a.take<double>(size_t(pl.totS) * N);
@@ -1108,7 +1167,12 @@ int vec_steps_v(const Plan& pl, const Bufs& b, hipStream_t st, bool init, double
                        b.itR, pl.N, static_cast<const TC*>(b.part), b.ub, b.sc, b.t);
     TIK_LAUNCHED("k_reduce_t");
   }
-  {
+  if (pl.lowrank) {
+    ProfScope ps("lr_apply", st);
+    TIK_TRY(launch_lr_apply(pl.NC, 0, 1, b.P, b.itLP, int(pl.lr.itLP.size()), b.itLE,
+                            int(pl.lr.itLE.size()), b.itLF, int(pl.lr.itLF.size()), pl.N, b.t, b.lpart, b.lopart, b.q, b.v, b.w,
+                            b.x, b.e, b.sc, b.pnQ, init ? 1 : 0, st));
+  } else {
     ProfScope ps("trmv_t", st);
     if (pl.cpw == 16)
       hipLaunchKernelGGL((k_trmv_t<16, false>), dim3(unsigned(pl.itQ.size())), dim3(BLK), 0, st, b.P,
@@ -1124,7 +1188,12 @@ int vec_steps_v(const Plan& pl, const Bufs& b, hipStream_t st, bool init, double
                        init ? 1 : 0, tol, maxit);
     TIK_LAUNCHED("k_fin_alpha");
   }
-  {
+  if (pl.lowrank) {
+    ProfScope ps("lr_apply", st);
+    TIK_TRY(launch_lr_apply(pl.NC, 1, 1, b.P, b.itLP, int(pl.lr.itLP.size()), b.itLE,
+                            int(pl.lr.itLE.size()), b.itLF, int(pl.lr.itLF.size()), pl.N, b.q, b.lpart, b.lopart, b.q, b.v, b.w,
+                            b.x, b.e, b.sc, b.pnQ, init ? 1 : 0, st));
+  } else {
     ProfScope ps("trmv", st);
     hipLaunchKernelGGL(k_trmv<false>, dim3(unsigned(pl.itM.size())), dim3(BLK), 0, st, b.P, b.itM,
                        pl.N, b.q, b.v, b.w, b.x, b.e, b.sc, init ? 1 : 0);
@@ -1219,6 +1288,10 @@ int upload_plan(const Plan& pl, const Bufs& b, const tik_precond_s* pc, double* 
   TIK_TRY(upload(b.itQ, stash(pl.itQ.data(), pl.itQ.size() * sizeof(Item)), pl.itQ.size() * sizeof(Item), st));
   TIK_TRY(upload(b.itR, stash(pl.itR.data(), pl.itR.size() * sizeof(Item)), pl.itR.size() * sizeof(Item), st));
   TIK_TRY(upload(b.itM, stash(pl.itM.data(), pl.itM.size() * sizeof(Item)), pl.itM.size() * sizeof(Item), st));
+  const LrTables& lr = pl.lr;
+  TIK_TRY(upload(b.itLP, stash(lr.itLP.data(), lr.itLP.size() * sizeof(Item)), lr.itLP.size() * sizeof(Item), st));
+  TIK_TRY(upload(b.itLE, stash(lr.itLE.data(), lr.itLE.size() * sizeof(Item)), lr.itLE.size() * sizeof(Item), st));
+  TIK_TRY(upload(b.itLF, stash(lr.itLF.data(), lr.itLF.size() * sizeof(Item)), lr.itLF.size() * sizeof(Item), st));
   std::vector<double> lams(pl.J);
   std::vector<int32_t> pre(pl.J), jmap(pl.J), lidx(pl.J);
   std::vector<double*> xp(pl.P.size());
@@ -1719,6 +1792,8 @@ struct WPlan {
   std::vector<int> pidx, lsel;
   std::vector<DevProb> P;
   std::vector<Item> itNs, itT, itQ, itM, itR, itV, itH;
+  LrTables lr;
+  bool lowrank = false;
   int64_t totL = 0, totS = 0, totPN = 0, totPT = 0, nbN = 0, nbQ = 0;
   int J = 0;
 };
@@ -1726,6 +1801,8 @@ struct WPlan {
 struct WBufs {
   DevProb* P;
   Item *itNs, *itT, *itQ, *itM, *itR, *itV, *itH;
+  Item *itLP, *itLE, *itLF;
+  double *lpart, *lopart;
   Scal* sc;
   void *partN, *partT;
   double *vt, *dt, *xt, *u, *q, *y, *vb, *db, *zb, *t, *pnN, *pnQ;
@@ -1747,6 +1824,7 @@ void make_plan_wide(const tik_problem* probs, const tik_precond_s* pc, const std
   pl.cbT = pl.NC >= 16 ? 128 : 64;
   pl.pidx = pidx;
   pl.lsel = lsel;
+  pl.lowrank = pc->route == TIK_ROUTE_LOWRANK;
   const int np = int(pidx.size());
   int64_t rowblocks = 0;
   for (int lp = 0; lp < np; ++lp) rowblocks += cdiv(probs[pidx[lp]].m, pl.rbN);
@@ -1765,7 +1843,7 @@ void make_plan_wide(const tik_problem* probs, const tik_precond_s* pc, const std
     d.offR = d.offS;
     d.offC = d.offL;
     d.k = g.m;
-    d.Rinv = pc->Rinv[pidx[lp]];
+    if (!pl.lowrank) d.Rinv = pc->Rinv[pidx[lp]];
     // split of A v_top over column chunks: about 2048 blocks over the batch
     const int64_t nrb = cdiv(g.m, pl.rbN);
     int64_t nch = std::max<int64_t>(1, 2048 / std::max<int64_t>(1, rowblocks));
@@ -1784,14 +1862,17 @@ void make_plan_wide(const tik_problem* probs, const tik_precond_s* pc, const std
     for (int64_t cb = 0; cb < cdiv(g.n, pl.cbT); ++cb) pl.itT.push_back({lp, int32_t(cb), 0, 0});
     // beta partials from the transposed triangular product, alpha partials from k_wide_v
     d.nblkN = int32_t(cdiv(g.m, 4 * pl.cpw));
+    if (pl.lowrank) d.nblkN = lowrank_items(pc, pidx[lp], lp, lsel, pl.NC, pl.lr, d);
     d.nblkB = 0;
     d.pnN = pl.nbN;
     d.nblkQ = int32_t(cdiv(g.n, BLK) + cdiv(g.m, BLK));
     d.pnQ = pl.nbQ;
-    for (int i = 0; i < N; ++i)
-      for (int b = 0; b < d.nblkN; ++b) pl.itQ.push_back({lp, b, 0, lp * N + i});
-    for (int i = 0; i < N; ++i)
-      for (int64_t b = 0; b < cdiv(g.m, 16); ++b) pl.itM.push_back({lp, int32_t(b), 0, lp * N + i});
+    if (!pl.lowrank) {
+      for (int i = 0; i < N; ++i)
+        for (int b = 0; b < d.nblkN; ++b) pl.itQ.push_back({lp, b, 0, lp * N + i});
+      for (int i = 0; i < N; ++i)
+        for (int64_t b = 0; b < cdiv(g.m, 16); ++b) pl.itM.push_back({lp, int32_t(b), 0, lp * N + i});
+    }
     for (int64_t b = 0; b < cdiv(g.m, BLK / pl.NC); ++b) pl.itR.push_back({lp, int32_t(b), 0, 0});
     for (int b = 0; b < d.nblkQ; ++b) pl.itV.push_back({lp, b, 0, 0});
     for (int64_t b = 0; b < cdiv(g.m, BLK); ++b) pl.itH.push_back({lp, int32_t(b), 0, 0});
@@ -1816,6 +1897,11 @@ void take_wbufs(Arena& a, const WPlan& pl, size_t tc, WBufs& b) {
   b.itR = a.take<Item>(pl.itR.size());
   b.itV = a.take<Item>(pl.itV.size());
   b.itH = a.take<Item>(pl.itH.size());
+  b.itLP = a.take<Item>(pl.lr.itLP.size());
+  b.itLE = a.take<Item>(pl.lr.itLE.size());
+  b.itLF = a.take<Item>(pl.lr.itLF.size());
+  b.lpart = a.take<double>(size_t(pl.lr.totLP));
+  b.lopart = a.take<double>(size_t(pl.lr.totLO));
   b.sc = a.take<Scal>(pl.J);
   b.partN = a.take<char>(size_t(pl.totPN) * N * tc);
   b.partT = a.take<char>(size_t(pl.totPT) * N * tc);
@@ -1855,6 +1941,9 @@ int upload_wplan(const WPlan& pl, const WBufs& b, const tik_precond_s* pc, doubl
   TIK_TRY(put(b.itR, pl.itR.data(), pl.itR.size() * sizeof(Item)));
   TIK_TRY(put(b.itV, pl.itV.data(), pl.itV.size() * sizeof(Item)));
   TIK_TRY(put(b.itH, pl.itH.data(), pl.itH.size() * sizeof(Item)));
+  TIK_TRY(put(b.itLP, pl.lr.itLP.data(), pl.lr.itLP.size() * sizeof(Item)));
+  TIK_TRY(put(b.itLE, pl.lr.itLE.data(), pl.lr.itLE.size() * sizeof(Item)));
+  TIK_TRY(put(b.itLF, pl.lr.itLF.data(), pl.lr.itLF.size() * sizeof(Item)));
   std::vector<double> lams(pl.J);
   std::vector<int32_t> pre(pl.J), jmap(pl.J), lidx(pl.J);
   std::vector<double*> xp(pl.P.size());
@@ -1914,7 +2003,12 @@ int wide_products_t(const WPlan& pl, const WBufs& b, const double* U, void* part
 
 template <typename TA, typename TC, int NC>
 int wide_v_steps(const WPlan& pl, const WBufs& b, hipStream_t st, bool init, double tol, int maxit) {
-  {
+  if (pl.lowrank) {
+    ProfScope ps("lr_apply", st);
+    TIK_TRY(launch_lr_apply(pl.NC, 1, 0, b.P, b.itLP, int(pl.lr.itLP.size()), b.itLE,
+                            int(pl.lr.itLE.size()), b.itLF, int(pl.lr.itLF.size()), pl.N, b.q,
+                            b.lpart, b.lopart, b.q, b.u, b.y, nullptr, nullptr, b.sc, nullptr, 0, st));
+  } else {
     ProfScope ps("trmv", st);
     hipLaunchKernelGGL(k_trmv<true>, dim3(unsigned(pl.itM.size())), dim3(BLK), 0, st, b.P, b.itM,
                        pl.N, b.q, b.u, b.y, static_cast<double*>(nullptr),
@@ -1946,7 +2040,13 @@ int wide_u_tr(const WPlan& pl, const WBufs& b, hipStream_t st) {
 }
 
 int wide_u_steps(const WPlan& pl, const WBufs& b, hipStream_t st, bool init) {
-  {
+  if (pl.lowrank) {
+    ProfScope ps("lr_apply", st);
+    TIK_TRY(launch_lr_apply(pl.NC, 0, 0, b.P, b.itLP, int(pl.lr.itLP.size()), b.itLE,
+                            int(pl.lr.itLE.size()), b.itLF, int(pl.lr.itLF.size()), pl.N, b.t,
+                            b.lpart, b.lopart, b.q, b.u, nullptr, nullptr, nullptr, b.sc, b.pnN, 0,
+                            st));
+  } else {
     ProfScope ps("trmv_t", st);
     TIK_TRY(pl.cpw == 16 ? wide_u_tr<16>(pl, b, st) : wide_u_tr<4>(pl, b, st));
   }

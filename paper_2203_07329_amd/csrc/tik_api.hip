@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 
 #include "tik_internal.h"
@@ -349,16 +350,42 @@ struct PrecondPlan {
   int32_t* notpd = nullptr;
   double* cnorm = nullptr;    // per problem
   double* colsum = nullptr;   // scratch, kmax
+  // low-rank route
+  std::vector<double*> V, sigma, S;
+  double* lr_scratch = nullptr;
+  int32_t* perm = nullptr;
+  int32_t* si = nullptr;
+  unsigned int* cnt = nullptr;
 };
+
+constexpr int64_t kLowrankMaxS = 4096;
 
 int precond_plan(tik_sketch_t sk, int32_t route, int32_t N, Arena& a, PrecondPlan& pp) {
   const int32_t np = int32_t(sk->probs.size());
   pp.Rinv.assign(size_t(np), nullptr);
-  int64_t kmax = 0;
+  pp.V.assign(size_t(np), nullptr);
+  pp.sigma.assign(size_t(np), nullptr);
+  pp.S.assign(size_t(np), nullptr);
+  int64_t kmax = 0, smax = 0;
+  size_t scratch = 0;
   for (int32_t k = 0; k < np; ++k) {
     const int64_t kd = std::min(sk->probs[k].m, sk->probs[k].n);
     kmax = std::max(kmax, kd);
-    if (route == TIK_ROUTE_CHOL) pp.Rinv[k] = a.take<double>(size_t(N) * size_t(kd) * size_t(kd));
+    if (route == TIK_ROUTE_CHOL) {
+      pp.Rinv[k] = a.take<double>(size_t(N) * size_t(kd) * size_t(kd));
+    } else {
+      const int64_t s = sk->yrows[k];
+      if (s > kd)
+        return fail(TIK_EINVAL, "tik_precond: the low-rank route needs a sketch size s <= min(m, n) (problem " +
+                                    std::to_string(k) + " has s = " + std::to_string(s) + ")");
+      if (s > kLowrankMaxS)
+        return fail(TIK_EINVAL, "tik_precond: the low-rank route supports s <= 4096");
+      smax = std::max(smax, s);
+      pp.V[k] = a.take<double>(size_t(kd) * size_t(s));
+      pp.sigma[k] = a.take<double>(size_t(s));
+      pp.S[k] = a.take<double>(size_t(N) * size_t(s));
+      scratch = std::max(scratch, lowrank_scratch_doubles(kd, s));
+    }
   }
   pp.lams = a.take<double>(size_t(np) * size_t(N));
   pp.notpd = a.take<int32_t>(size_t(np) * size_t(N));
@@ -368,6 +395,11 @@ int precond_plan(tik_sketch_t sk, int32_t route, int32_t N, Arena& a, PrecondPla
     pp.C = a.take<double>(size_t(kmax) * size_t(kmax));
     pp.Dinv = a.take<double>(size_t(N) * size_t(cdiv(kmax, 64)) * 64 * 64);
     pp.Tmp = a.take<double>(size_t(N) * size_t(kmax) * 64);
+  } else {
+    pp.lr_scratch = a.take<double>(scratch);
+    pp.perm = a.take<int32_t>(size_t(smax));
+    pp.si = a.take<int32_t>(size_t(np) * size_t(N));
+    pp.cnt = a.take<unsigned int>(1);
   }
   return TIK_OK;
 }
@@ -378,8 +410,6 @@ int tik_precond_bytes(tik_sketch_t sk, int32_t route, int32_t N, size_t* bytes) 
   if (route != TIK_ROUTE_CHOL && route != TIK_ROUTE_LOWRANK)
     return fail(TIK_EINVAL, "tik_precond_bytes: route must be TIK_ROUTE_CHOL or TIK_ROUTE_LOWRANK");
   if (N < 1) return fail(TIK_EINVAL, "tik_precond_bytes: N must be >= 1");
-  if (route == TIK_ROUTE_LOWRANK)
-    return fail(TIK_ENOTSUP, "tik_precond: the low-rank route is not available in this build");
   Arena a;
   PrecondPlan pp;
   TIK_TRY(precond_plan(sk, route, N, a, pp));
@@ -387,14 +417,70 @@ int tik_precond_bytes(tik_sketch_t sk, int32_t route, int32_t N, size_t* bytes) 
   return TIK_OK;
 }
 
+// Algorithm 3 steps 4-7 (Algorithm 4 steps 4-7 for wide problems, whose
+// sketch is stored transposed): SVD of the sketch, sd_hat per lambda
+// (Section 3.1.2), s_i = min(s, ceil(alpha ceil(sd_hat_i))), S_i.
+static int precond_lowrank(tik_sketch_t sk, const double* lambdas, int32_t N, double alpha,
+                           PrecondPlan& pp, hipStream_t st, tik_precond_s* h) {
+  const int32_t np = int32_t(sk->probs.size());
+  h->sigma = pp.sigma;
+  h->V = pp.V;
+  h->S = pp.S;
+  h->srank.assign(size_t(np), 0);
+  h->si.assign(size_t(np) * N, 0);
+  h->sdhat.assign(size_t(np) * N, 0.0);
+  h->cnorm.assign(size_t(np), 0.0);
+  h->status.assign(size_t(np) * N, TIK_ST_CONVERGED);
+  h->lr_sweeps.assign(size_t(np), 0);
+  for (int32_t k = 0; k < np; ++k) {
+    const int64_t s = sk->yrows[k], kd = sk->ycols[k];
+    h->srank[k] = s;
+    int sweeps = 0;
+    TIK_TRY(launch_lowrank_svd(sk->Y[k], s, kd, pp.V[k], pp.sigma[k], pp.lr_scratch, pp.cnt,
+                               pp.perm, &sweeps, st));
+    h->lr_sweeps[k] = sweeps;
+    std::vector<double> sig(static_cast<size_t>(s));
+    TIK_HIP(hipMemcpyAsync(sig.data(), pp.sigma[k], sizeof(double) * size_t(s),
+                           hipMemcpyDeviceToHost, st));
+    TIK_HIP(hipStreamSynchronize(st));
+    bool finite = true;
+    for (double v : sig) finite = finite && std::isfinite(v);
+    h->cnorm[k] = finite && s > 0 ? sig[0] * sig[0] : std::nan("");
+    for (int32_t i = 0; i < N; ++i) {
+      const size_t q = size_t(k) * N + i;
+      const double lam = lambdas[q];
+      if (!finite) {
+        h->status[q] = TIK_ST_NOTPD;
+        h->sdhat[q] = std::nan("");
+        h->si[q] = 0;
+        continue;
+      }
+      double sd = 0.0;
+      for (int64_t j = 0; j < s; ++j)
+        if (sig[j] > 0.0) sd += 1.0 / (1.0 + lam / (sig[j] * sig[j]));
+      h->sdhat[q] = sd;
+      const double want = std::ceil(alpha * std::ceil(sd));
+      h->si[q] = int32_t(std::min<double>(double(s), want));
+    }
+  }
+  TIK_HIP(hipMemcpyAsync(pp.si, h->si.data(), sizeof(int32_t) * h->si.size(), hipMemcpyHostToDevice,
+                         st));
+  for (int32_t k = 0; k < np; ++k)
+    TIK_TRY(launch_lowrank_S(pp.sigma[k], sk->yrows[k], pp.lams + size_t(k) * N, pp.si + size_t(k) * N,
+                             N, pp.S[k], st));
+  TIK_HIP(hipStreamSynchronize(st));   // h->si is host memory the copy reads
+  return TIK_OK;
+}
+
 int tik_precond(tik_sketch_t sk, int32_t route, const double* lambdas, int32_t N, double alpha,
                 void* dws, size_t dws_bytes, tik_stream_t stream, tik_precond_t* out,
                 double* sd_hat, int32_t* status) {
-  (void)alpha;
   if (!out) return fail(TIK_EINVAL, "tik_precond: out is NULL");
   *out = nullptr;
   if (!sk) return fail(TIK_EINVAL, "tik_precond: sketch handle is NULL");
   if (!lambdas) return fail(TIK_EINVAL, "tik_precond: lambdas is NULL");
+  if (route == TIK_ROUTE_LOWRANK && !(alpha >= 1.0 && std::isfinite(alpha)))
+    return fail(TIK_EINVAL, "tik_precond: alpha must be finite and >= 1 for the low-rank route");
   const int32_t np = int32_t(sk->probs.size());
   for (int64_t q = 0; q < int64_t(np) * N; ++q)
     if (!(lambdas[q] > 0.0) || !std::isfinite(lambdas[q]))
@@ -410,35 +496,39 @@ int tik_precond(tik_sketch_t sk, int32_t route, const double* lambdas, int32_t N
   TIK_TRY(precond_plan(sk, route, N, a, pp));
   TIK_HIP(hipMemcpyAsync(pp.lams, lambdas, sizeof(double) * size_t(np) * size_t(N),
                          hipMemcpyHostToDevice, st));
-  TIK_HIP(hipMemsetAsync(pp.notpd, 0, sizeof(int32_t) * size_t(np) * size_t(N), st));
-  for (int32_t k = 0; k < np; ++k) {
-    const int64_t kd = std::min(sk->probs[k].m, sk->probs[k].n);
-    TIK_TRY(launch_syrk(sk->Y[k], sk->yrows[k], kd, sk->yrows[k], pp.C, st));
-    TIK_TRY(launch_gram_norm_bound(pp.C, kd, pp.colsum, pp.cnorm + k, st));
-    TIK_TRY(launch_chol_inv_batched(pp.C, kd, pp.lams + size_t(k) * N, N, pp.Rinv[k], pp.Dinv,
-                                    pp.Tmp, pp.notpd + size_t(k) * N, st));
-  }
-  std::vector<int32_t> bad(size_t(np) * size_t(N), 0);
-  std::vector<double> cn(size_t(np), 0.0);
-  TIK_HIP(hipMemcpyAsync(bad.data(), pp.notpd, sizeof(int32_t) * bad.size(),
-                         hipMemcpyDeviceToHost, st));
-  TIK_HIP(hipMemcpyAsync(cn.data(), pp.cnorm, sizeof(double) * cn.size(), hipMemcpyDeviceToHost, st));
-  TIK_HIP(hipStreamSynchronize(st));
-  tik_precond_s* h = new tik_precond_s();
+  std::unique_ptr<tik_precond_s> h(new tik_precond_s());
   h->probs = sk->probs;
   h->wide = sk->wide;
   h->route = route;
   h->N = N;
   h->lams.assign(lambdas, lambdas + size_t(np) * N);
-  h->Rinv = pp.Rinv;
-  h->cnorm = cn;
-  h->status.resize(bad.size());
-  for (size_t q = 0; q < bad.size(); ++q) h->status[q] = bad[q] ? TIK_ST_NOTPD : TIK_ST_CONVERGED;
   for (int32_t k = 0; k < np; ++k) h->k.push_back(std::min(sk->probs[k].m, sk->probs[k].n));
+  if (route == TIK_ROUTE_LOWRANK) {
+    TIK_TRY(precond_lowrank(sk, lambdas, N, alpha, pp, st, h.get()));
+  } else {
+    TIK_HIP(hipMemsetAsync(pp.notpd, 0, sizeof(int32_t) * size_t(np) * size_t(N), st));
+    for (int32_t k = 0; k < np; ++k) {
+      const int64_t kd = std::min(sk->probs[k].m, sk->probs[k].n);
+      TIK_TRY(launch_syrk(sk->Y[k], sk->yrows[k], kd, sk->yrows[k], pp.C, st));
+      TIK_TRY(launch_gram_norm_bound(pp.C, kd, pp.colsum, pp.cnorm + k, st));
+      TIK_TRY(launch_chol_inv_batched(pp.C, kd, pp.lams + size_t(k) * N, N, pp.Rinv[k], pp.Dinv,
+                                      pp.Tmp, pp.notpd + size_t(k) * N, st));
+    }
+    std::vector<int32_t> bad(size_t(np) * size_t(N), 0);
+    std::vector<double> cn(size_t(np), 0.0);
+    TIK_HIP(hipMemcpyAsync(bad.data(), pp.notpd, sizeof(int32_t) * bad.size(),
+                           hipMemcpyDeviceToHost, st));
+    TIK_HIP(hipMemcpyAsync(cn.data(), pp.cnorm, sizeof(double) * cn.size(), hipMemcpyDeviceToHost, st));
+    TIK_HIP(hipStreamSynchronize(st));
+    h->Rinv = pp.Rinv;
+    h->cnorm = cn;
+    h->status.resize(bad.size());
+    for (size_t q = 0; q < bad.size(); ++q) h->status[q] = bad[q] ? TIK_ST_NOTPD : TIK_ST_CONVERGED;
+    h->sdhat.assign(bad.size(), std::nan(""));
+  }
   if (status) std::memcpy(status, h->status.data(), sizeof(int32_t) * h->status.size());
-  if (sd_hat)
-    for (size_t q = 0; q < bad.size(); ++q) sd_hat[q] = std::nan("");
-  *out = h;
+  if (sd_hat) std::memcpy(sd_hat, h->sdhat.data(), sizeof(double) * h->sdhat.size());
+  *out = h.release();
   return TIK_OK;
 }
 
@@ -456,6 +546,17 @@ int tik_precond_data(tik_precond_t pc, int32_t k, int32_t i, const double** data
     *data = pc->V[k];
     *rank = pc->si[size_t(k) * pc->N + i];
   }
+  return TIK_OK;
+}
+
+int tik_precond_sigma(tik_precond_t pc, int32_t k, const double** sigma, int64_t* count) {
+  if (!pc || !sigma || !count) return fail(TIK_EINVAL, "tik_precond_sigma: NULL argument");
+  if (k < 0 || k >= int32_t(pc->probs.size()))
+    return fail(TIK_EINVAL, "tik_precond_sigma: index out of range");
+  if (pc->route != TIK_ROUTE_LOWRANK)
+    return fail(TIK_EINVAL, "tik_precond_sigma: only the low-rank route keeps singular values");
+  *sigma = pc->sigma[k];
+  *count = pc->srank[k];
   return TIK_OK;
 }
 

@@ -84,10 +84,17 @@ struct DevProb {
   const double* Rinv;  // upper-triangular inverses, k x k each (k = short dim), col-major,
                        // one per lambda of the problem; a solve uses Rinv + li * k * k
   int64_t k;           // short dimension min(m, n)
-  // low-rank route: V (n x s, ld n), S (N x s), truncation s_i
+  // low-rank route: V (k x s, ld k), S (one row of s per lambda of the
+  // problem, zero beyond that lambda's rank), s, and the largest rank smax
+  // used by the lambdas of this solve
   const double* V;
   const double* S;
-  int64_t s;
+  int64_t s, smax;
+  int64_t lrPart;      // offset of this problem in the projection partials (chunks x s x N)
+  int64_t lrOpart;     // offset in the expansion partials (column chunks x N x k)
+  int64_t lrRch;       // rows of V per projection chunk
+  int32_t lrNch;       // projection row chunks
+  int32_t lrNjc;       // expansion column chunks in use (ceil(smax / 256))
   // item bookkeeping
   int64_t pnN, pnB, pnQ; // first block of this problem in the partial-norm arrays
   int32_t nblkN, nblkB, nblkQ, nchT;
@@ -150,6 +157,18 @@ int launch_gemm_n_mfma(int ta_f32, int tc_f32, int nc, int epi, const DevProb* P
 int launch_gemm_t_mfma(int ta_f32, int tc_f32, int u_f64, int nc, const DevProb* P,
                        const Item* items, int nitems, int N, const void* U, void* part,
                        hipStream_t st);
+
+// low-rank route (k_lowrank.hip)
+size_t lowrank_scratch_doubles(int64_t n, int64_t s);
+int launch_lowrank_svd(const double* Y, int64_t s, int64_t n, double* V, double* sig,
+                       double* scratch, unsigned int* cnt, int32_t* perm, int* sweeps,
+                       hipStream_t st);
+int launch_lowrank_S(const double* sig, int64_t s, const double* lams, const int32_t* si, int N,
+                     double* S, hipStream_t st);
+int launch_lr_apply(int nc, int stage, int tall, const DevProb* P, const Item* itP, int nP,
+                    const Item* itE, int nE, const Item* itF, int nF, int N, const double* src,
+                    double* part, double* opart, double* q, double* v, double* w, double* x,
+                    double* e, const Scal* sc, double* pn, int init, hipStream_t st);
 }  // namespace tik
 
 // ----------------------------------------------------------------- handles --
@@ -172,11 +191,12 @@ struct tik_precond_s {
   std::vector<double*> Rinv;           // Cholesky route: N upper-triangular k x k inverses
   std::vector<int32_t> status;         // nprob * N breakdown flags (tik_status)
   std::vector<double> cnorm;           // per problem: upper bound on ||C||_2 of the sketch Gram
-  // low-rank route (tall): V n x s (ld n), sigma (s), S (N x s), truncation s_i
+  // low-rank route: V k x s (ld k), sigma (s), S (N x s), truncation s_i
   std::vector<double*> V, sigma, S;
   std::vector<int64_t> srank;
   std::vector<int32_t> si;             // nprob * N
   std::vector<double> sdhat;           // nprob * N
+  std::vector<int32_t> lr_sweeps;      // Jacobi sweeps the SVD took, per problem
 };
 
 namespace tik {

@@ -33,7 +33,7 @@ PLAIN_F64_PER_LAMBDA, F64_BATCHED, MIXED_BATCHED = 0, 1, 2
 
 EXPORTS = [
     "tik_sketch_bytes", "tik_sketch", "tik_sketch_data", "tik_precond_bytes", "tik_precond",
-    "tik_precond_data",
+    "tik_precond_data", "tik_precond_sigma",
     "tik_lsqr_batch_bytes", "tik_lsqr_batch", "tik_sketch_free", "tik_precond_free",
     "tik_last_error", "tik_version", "tik_prof_enable", "tik_prof_reset", "tik_prof_query",
     "tik_lsqr_info",
@@ -73,6 +73,7 @@ def lib() -> ctypes.CDLL:
     L.tik_precond_bytes.argtypes = [vp, i32, i32, P(sz)]
     L.tik_precond.argtypes = [vp, i32, P(dbl), i32, dbl, vp, sz, vp, P(vp), P(dbl), P(i32)]
     L.tik_precond_data.argtypes = [vp, i32, i32, P(vp), P(i64), P(i64)]
+    L.tik_precond_sigma.argtypes = [vp, i32, P(vp), P(i64)]
     L.tik_lsqr_batch_bytes.argtypes = [P(CProblem), i32, vp, i32, P(sz)]
     L.tik_lsqr_batch.argtypes = [P(CProblem), i32, vp, i32, dbl, i32, P(vp), vp, vp, vp, vp, sz, vp]
     L.tik_sketch_free.argtypes = [vp]
@@ -190,6 +191,20 @@ class Precond:
         nbytes = d.value * cols * 8
         host = self.ws[off:off + nbytes].cpu().numpy().view(np.float64)
         return host.reshape(cols, d.value).T.copy()
+
+    def rank(self, k: int = 0, i: int = 0) -> int:
+        """Columns of the preconditioner's factor for problem k, lambda i (s_i on the low-rank route)."""
+        ptr, d, r = ctypes.c_void_p(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().tik_precond_data(self.handle, k, i, ctypes.byref(ptr), ctypes.byref(d),
+                                      ctypes.byref(r)))
+        return int(r.value)
+
+    def sigma(self, k: int = 0) -> np.ndarray:
+        """Singular values of problem k's sketch, decreasing (low-rank route)."""
+        ptr, c = ctypes.c_void_p(), ctypes.c_int64()
+        _check(lib().tik_precond_sigma(self.handle, k, ctypes.byref(ptr), ctypes.byref(c)))
+        off = ptr.value - self.ws.data_ptr()
+        return self.ws[off:off + 8 * c.value].cpu().numpy().view(np.float64).copy()
 
     def __del__(self):
         if _lib is not None and self.handle:

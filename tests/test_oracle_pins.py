@@ -287,3 +287,25 @@ def test_generators_deterministic():
     part = W.ragged(nprob=6, m_lo=50, m_hi=90, n_lo=5, n_hi=20, first=3, count=2)
     assert np.array_equal(full[3].A, part[0].A) and np.array_equal(full[4].b, part[1].b)
     assert [(q.m, q.n) for q in full] == W.ragged_shapes(6, 50, 90, 5, 20)
+
+
+def test_lowrank_truncation_rule():
+    """Algorithm 3 steps 1 and 5: s_i = alpha ceil(sd_hat), capped at s.
+
+    sigma_j^2 = lam makes every term of the estimate exactly 1/2, so
+    sd_hat = s/2 in closed form; the rank then follows by hand.
+    """
+    lam = 0.25
+    sig = np.full(10, 0.5)                       # sigma^2 = lam
+    assert oracle.sd_hat(sig, lam) == 5.0
+    assert oracle.lowrank_truncation(sig, lam, 2.0, 10) == 10
+    assert oracle.lowrank_truncation(sig, lam, 1.0, 10) == 5
+    assert oracle.lowrank_truncation(sig, lam, 1.5, 10) == 8   # ceil(1.5 * 5)
+    assert oracle.lowrank_truncation(sig, lam, 3.0, 10) == 10  # capped at s
+    # zero singular values contribute nothing (A = 0 keeps no direction)
+    assert oracle.lowrank_truncation(np.zeros(6), lam, 2.0, 6) == 0
+    # the rank never grows with lambda (sd is decreasing in lambda)
+    rng = np.random.default_rng(4)
+    sig = np.sort(rng.uniform(0, 1, 40))[::-1]
+    ranks = [oracle.lowrank_truncation(sig, l, 2.0, 40) for l in np.logspace(-4, 1, 30)]
+    assert all(a >= b for a, b in zip(ranks, ranks[1:]))
