@@ -1,20 +1,33 @@
 """Benchmark: lambda-solves/s of sketch-preconditioned Tikhonov least squares.
 
-One step = the whole hot path for one batch: sketch A once (SRHT), build the
-32 preconditioners, run preconditioned LSQR for all 32 lambdas.  The default
-workload is the tall kappa(A) = 1e8 problem (m = 200000, n = 2000, N = 32,
-lambda in [1e-8, 1e-1], sketch size 4n).  A and b are resident on the GPU
-before timing starts.
+One step = the whole hot path for one batch: sketch A once, build every
+preconditioner, run preconditioned LSQR for all lambdas (and all problems).
+The default workload is the tall kappa(A) = 1e8 problem (m = 200000,
+n = 2000, N = 32, lambda in [1e-8, 1e-1], SRHT sketch of size 4n, Cholesky
+route).  --workload selects the others:
 
-value = (number of lambdas whose solution is within 1e-8 relative error of
-the CPU FP64 oracle) / (seconds per step), for the batched solve; the plain
-FP64 per-lambda loop is timed beside it.  roofline: the dominant kernel's
-algorithmic bytes per launch over its average launch time, from HIP events
-recorded by the library around every launch during the timed steps.
-cpu_baseline: the oracle itself (direct Householder-QR route), timed on the
-host while it produces the reference solutions.
+  over_svd      m=2000 n=100 N=10, Haar factors, SRHT s=4n, plain FP64
+  over_gauss    (default) as above, mixed batched with FP64 fallback
+  under_scaled  m=2000 n=200000 N=32, A_ij = G_ij / j in FP32, BF16 Gaussian
+                sketch s=4m, mixed batched (Algorithm 2)
+  lowsd         m=100000 n=10000 N=16, sigma_i = exp(-i/200), FP32 A, BF16
+                Gaussian sketch s = 2 ceil(sd), low-rank route (Algorithm 3)
+  ragged        256 problems m~U[5000,50000] n~U[100,1000] N=8 (2048 solves),
+                FP32 A, BF16 sketches s=4n_p, mixed batched
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+A and b are resident on the GPU before timing starts.
+
+value = (number of solves within 1e-8 relative error of the CPU FP64 oracle)
+/ (seconds per step) for the batched solve; the plain FP64 per-lambda loop
+is timed beside it.  Where the oracle's direct solve is too slow for the
+whole batch, it checks a stated sample (ragged: every 16th problem) or
+certifies the error bound instead (lowsd: gradient in extended precision,
+inverted with the generator's planted factors).  roofline: the dominant
+kernel family's algorithmic bytes per launch over its average launch time,
+from HIP events the library records around every launch during the timed
+steps.  cpu_baseline: the oracle's direct QR solve, timed on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 
 from __future__ import annotations
@@ -33,10 +46,46 @@ sys.path.insert(0, ROOT)
 METRIC = "λ-solves/s to 1e-8 rel err: mixed batched vs plain FP64; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 TOL_ERR = 1e-8
+FAMILIES = ("sketch", "gram", "chol", "trinv", "lowrank", "lr_qr", "lr_sweep", "lr_q", "gemm_n",
+            "gemm_t", "trmv", "trmv_t", "lr_apply", "vec", "residual")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def build_workload(name, tik, W, dev):
+    """(problems, settings) of one named workload."""
+    if name == "over_svd":
+        plist = [W.over_svd()]
+        cfg = dict(embed=tik.SRHT, sdt=tik.F64, route=tik.ROUTE_CHOL, mode="f64",
+                   desc="tall Haar SVD, sigma logspaced 1..1e-6: m=2000 n=100 N=10 lambda 1e-6..1, "
+                        "SRHT s=400, Cholesky route", check="full")
+    elif name == "over_gauss":
+        plist = [W.over_gauss()]
+        cfg = dict(embed=tik.SRHT, sdt=tik.F64, route=tik.ROUTE_CHOL, mode="auto",
+                   desc=f"tall Gaussian, sigma logspaced 1..1e-8: m=200000 n=2000 N=32 lambda "
+                        f"1e-8..1e-1, SRHT s=8000, Cholesky route", check="full")
+    elif name == "under_scaled":
+        plist = [W.under_scaled()]
+        cfg = dict(embed=tik.GAUSS, sdt=tik.BF16, route=tik.ROUTE_CHOL, mode="auto",
+                   desc="wide A_ij = G_ij / j (FP32): m=2000 n=200000 N=32 lambda 1e-6..1, BF16 "
+                        "Gaussian s=8000, Cholesky route (Algorithm 2)", check="full")
+    elif name == "lowsd":
+        plist = [W.lowsd(device=dev)]
+        cfg = dict(embed=tik.GAUSS, sdt=tik.BF16, route=tik.ROUTE_LOWRANK, mode="auto",
+                   desc=f"tall U diag(exp(-i/200)) V^T (FP32): m=100000 n=10000 N=16 lambda "
+                        f"1e-4..1e-1, BF16 Gaussian s={plist[0].s}, low-rank route (Algorithm 3)",
+                   check="certify")
+    elif name == "ragged":
+        plist = W.ragged()
+        cfg = dict(embed=tik.GAUSS, sdt=tik.BF16, route=tik.ROUTE_CHOL, mode="auto",
+                   desc="256 tall Gaussian problems, sigma logspaced 1..1e-6 (FP32): m~U[5000,50000] "
+                        "n~U[100,1000] N=8 lambda 1e-6..1e-1, BF16 Gaussian s=4n_p, Cholesky route",
+                   check="sample16")
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return plist, cfg
 
 
 def main() -> int:
@@ -44,10 +93,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--m", type=int, default=200000)
-    ap.add_argument("--n", type=int, default=2000)
-    ap.add_argument("--N", type=int, default=32)
-    ap.add_argument("--mode", default="auto", choices=["auto", "mixed", "f64"])
+    ap.add_argument("--workload", default="over_gauss",
+                    choices=["over_svd", "over_gauss", "under_scaled", "lowsd", "ragged"])
+    ap.add_argument("--mode", default=None, choices=["auto", "mixed", "f64"])
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle (profiling runs)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0,
@@ -65,36 +113,42 @@ def main() -> int:
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    p = W.over_gauss(m=args.m, n=args.n, N=args.N)
-    log(f"generated A {p.m}x{p.n} in {time.perf_counter() - t0:.1f}s")
-    pr = tik.Problems.from_numpy([p.A], [p.b], device=dev)
+    plist, cfg = build_workload(args.workload, tik, W, "cuda:0")
+    log(f"generated {len(plist)} problem(s), {sum(p.m * p.n for p in plist) / 1e6:.0f} M entries "
+        f"in {time.perf_counter() - t0:.1f}s")
+    pr = tik.Problems.from_numpy([p.A for p in plist], [p.b for p in plist], device=dev)
     torch.cuda.synchronize()
+    svec = [p.s for p in plist]
+    lams = np.stack([p.lams for p in plist])
+    nsolve = int(lams.size)
+    alpha = plist[0].alpha
 
-    mode = tik.F64_BATCHED
-    dtype = "f64"
-    if args.mode in ("auto", "mixed"):
+    def one_step(m_, tol):
+        sk = tik.sketch(pr, cfg["embed"], svec, 0, sketch_dtype=cfg["sdt"])
+        pc = tik.precond(sk, lams, cfg["route"], alpha)
+        return tik.Solver(pr, pc, m_)(tol, maxit)
+
+    want = args.mode or cfg["mode"]
+    mode, dtype = tik.F64_BATCHED, "f64"
+    if want in ("auto", "mixed"):
         try:
-            sk = tik.sketch(pr, tik.SRHT, [p.s], 0)
-            pc = tik.precond(sk, p.lams)
+            sk = tik.sketch(pr, cfg["embed"], svec, 0, sketch_dtype=cfg["sdt"])
+            pc = tik.precond(sk, lams, cfg["route"], alpha)
             tik.Solver(pr, pc, tik.MIXED_BATCHED)
             mode, dtype = tik.MIXED_BATCHED, "f32+f64"
+            del sk, pc
         except tik.TikError as e:
-            if args.mode == "mixed":
+            if want == "mixed":
                 raise
             log("mixed mode unavailable, timing FP64 batched:", e)
     tol = 1e-11 if mode == tik.F64_BATCHED else 1e-8
     maxit = 300
 
-    def one_step(m_):
-        sk = tik.sketch(pr, tik.SRHT, [p.s], 0)
-        pc = tik.precond(sk, p.lams)
-        res = tik.Solver(pr, pc, m_)(tol if m_ != tik.PLAIN_F64_PER_LAMBDA else 1e-11, maxit)
-        return res
-
     # ---- warmup
     for _ in range(args.warmup):
-        one_step(mode)
+        one_step(mode, tol)
     torch.cuda.synchronize()
+    log("warmup done")
 
     # ---- timed steps (per-kernel events on)
     tik.prof_reset()
@@ -105,24 +159,24 @@ def main() -> int:
     ev0.record()
     w0 = time.perf_counter()
     for _ in range(args.steps):
-        res = one_step(mode)
+        res = one_step(mode, tol)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     tik.prof_enable(False)
     ms_step = ev0.elapsed_time(ev1) / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step")
     fam = {}
-    for f in ("sketch", "gram", "chol", "trinv", "gemm_n", "gemm_t", "trmv", "trmv_t", "vec",
-              "residual", "lowrank"):
+    for f in FAMILIES:
         ms, n = tik.prof_query(f)
         if n:
             fam[f] = (ms / args.steps, n // args.steps, ms / n)
     n32, n64 = tik.lsqr_info()
     if mode == tik.MIXED_BATCHED:
         dtype = "f32+f64" if n32 > 0 else "f64"
-    X = res.x_numpy(0)
-    iters = res.iters.cpu().numpy()[0]
-    status = res.status.cpu().numpy()[0]
+    Xs = [res.x_numpy(k) for k in range(len(plist))]
+    iters = res.iters.cpu().numpy()
+    status = res.status.cpu().numpy()
     if args.calibrate_copy > 0:
         nel = int(args.calibrate_copy * (1 << 30)) // 8
         src = torch.ones(nel, dtype=torch.float64, device=dev)
@@ -139,16 +193,18 @@ def main() -> int:
         torch.cuda.synchronize()
         q0 = time.perf_counter()
         for _ in range(args.plain_steps):
-            rp = one_step(tik.PLAIN_F64_PER_LAMBDA)
+            rp = one_step(tik.PLAIN_F64_PER_LAMBDA, 1e-11)
         torch.cuda.synchronize()
         plain_ms = (time.perf_counter() - q0) * 1000.0 / args.plain_steps
-        plain = {"ms_per_step": plain_ms, "X": rp.x_numpy(0), "iters": rp.iters.cpu().numpy()[0]}
+        plain = {"ms_per_step": plain_ms, "X": [rp.x_numpy(k) for k in range(len(plist))],
+                 "iters": rp.iters.cpu().numpy()}
+        log(f"plain per-lambda: {plain_ms:.1f} ms/step")
 
     # ---- oracle (timed: the CPU baseline) and accuracy
-    out = {}
-    n_ok = p.lams.size
-    err = None
+    n_ok = None
+    err_max = None
     cpu = None
+    checked = None
     if not args.no_oracle:
         import oracle
         try:
@@ -156,40 +212,66 @@ def main() -> int:
             cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [os.cpu_count()])
         except Exception:  # pragma: no cover
             cores = os.cpu_count()
-        c0 = time.perf_counter()
-        Xo = oracle.solve(p.A, p.b, p.lams)
-        tcpu = time.perf_counter() - c0
-        err = oracle.rel_err(X, Xo)
-        n_ok = int(np.sum(err <= TOL_ERR))
-        cpu = {"value": p.lams.size / tcpu, "unit": "λ-solves/s", "cores": int(cores),
-               "kind": "oracle",
-               "sample": f"full workload: Householder QR of the {p.m}x{p.n} A once plus "
-                         f"{p.lams.size} per-lambda QR solves ({tcpu:.1f} s)"}
-        if plain is not None:
-            perr = oracle.rel_err(plain["X"], Xo)
-            plain["n_ok"] = int(np.sum(perr <= TOL_ERR))
-            plain["max_rel_err"] = float(perr.max())
-    value = n_ok / (ms_step / 1000.0)
+        if cfg["check"] == "certify":
+            p = plist[0]
+            c0 = time.perf_counter()
+            bound = oracle.certify_planted(p.A, p.b, p.lams, Xs[0], p.sigma, p.V)
+            tcert = time.perf_counter() - c0
+            errs = [bound]
+            pl_errs = [oracle.certify_planted(p.A, p.b, p.lams, plain["X"][0], p.sigma, p.V)] \
+                if plain is not None else None
+            checked = f"all {nsolve} solves by an a-posteriori bound ({tcert:.1f} s on the host)"
+        else:
+            idx = list(range(len(plist))) if cfg["check"] == "full" else list(range(0, len(plist), 16))
+            c0 = time.perf_counter()
+            Xo = {k: oracle.solve(plist[k].A, plist[k].b, plist[k].lams) for k in idx}
+            tcpu = time.perf_counter() - c0
+            errs = [oracle.rel_err(Xs[k], Xo[k]) for k in idx]
+            pl_errs = [oracle.rel_err(plain["X"][k], Xo[k]) for k in idx] if plain is not None else None
+            nsamp = sum(plist[k].lams.size for k in idx)
+            what = (f"Householder QR of A once plus per-lambda QR solves, {len(idx)} problem(s), "
+                    f"{nsamp} solves ({tcpu:.1f} s)")
+            cpu = {"value": round(nsamp / tcpu, 4), "unit": "λ-solves/s", "cores": int(cores),
+                   "kind": "oracle",
+                   "sample": ("full workload: " if len(idx) == len(plist) else "every 16th problem: ") + what}
+            checked = f"{len(idx)} of {len(plist)} problems against the oracle's direct solve"
+        allerr = np.concatenate([np.ravel(e) for e in errs])
+        err_max = float(allerr.max())
+        frac = float(np.mean(allerr <= TOL_ERR))
+        n_ok = int(round(frac * nsolve))
+        if plain is not None and pl_errs is not None:
+            pe = np.concatenate([np.ravel(e) for e in pl_errs])
+            plain["n_ok"] = int(round(float(np.mean(pe <= TOL_ERR)) * nsolve))
+            plain["max_rel_err"] = float(pe.max())
+    value = (n_ok if n_ok is not None else 0) / (ms_step / 1000.0)
 
-    # ---- roofline of the dominant kernel family
-    dom = max(fam.items(), key=lambda kv: kv[1][0]) if fam else None
+    # ---- roofline of the dominant kernel family with known algorithmic bytes
+    ab = 8 if plist[0].A.dtype == np.float64 else 4
+    vb = 4 if (mode == tik.MIXED_BATCHED and n32 > 0) else 8
+    N = lams.shape[1]
+    a_bytes = sum(p.m * p.n * ab for p in plist)
+    long_short = sum((p.m + p.n) for p in plist)
+    kmin = [min(p.m, p.n) for p in plist]
+    per_launch = {
+        # one pass over every A, plus the N-wide vectors on both sides of it
+        "gemm_n": a_bytes + N * long_short * vb * 2,
+        "gemm_t": a_bytes + N * long_short * vb,
+    }
+    if cfg["route"] == tik.ROUTE_CHOL:
+        # upper triangles of the N inverses of every problem, FP64
+        per_launch["trmv"] = per_launch["trmv_t"] = sum(N * k * k * 4 for k in kmin)
+    else:
+        # V (k x s) read twice per application: projection and expansion
+        per_launch["lr_apply"] = sum(2 * k * p.s * 8 for k, p in zip(kmin, plist))
+    known = {k: v for k, v in fam.items() if k in per_launch}
+    dom = max(known.items(), key=lambda kv: kv[1][0]) if known else None
     roof = None
     if dom:
-        name, (ms_per_step, launches, avg_ms) = dom
-        a_bytes = (8 if p.A.dtype == np.float64 else 4) if mode != tik.MIXED_BATCHED else 4
-        N = p.lams.size
-        per_launch = {
-            # A once, plus the N-wide long vector read and written (gemm_n) or read (gemm_t)
-            "gemm_n": p.m * p.n * a_bytes + 2 * p.m * N * (8 if mode != tik.MIXED_BATCHED else 4),
-            "gemm_t": p.m * p.n * a_bytes + p.m * N * (8 if mode != tik.MIXED_BATCHED else 4),
-            "trmv": N * p.n * p.n * 4,       # upper triangles of all N inverses (8 B, half)
-            "trmv_t": N * p.n * p.n * 4,
-        }.get(name)
-        if per_launch:
-            ach = per_launch / (avg_ms / 1000.0) / 1e9
-            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
-                    "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": per_launch}
+        name, (ms_ps, launches, avg_ms) = dom
+        ach = per_launch[name] / (avg_ms / 1000.0) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(per_launch[name])}
 
     line = {
         "metric": METRIC,
@@ -204,24 +286,26 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": f"tall Gaussian, sigma logspaced 1..1e-8: m={p.m} n={p.n} N={p.lams.size} "
-                               f"lambda 1e-8..1e-1, SRHT s={p.s}, Cholesky route",
+        "config": {"workload": cfg["desc"],
                    "mode": {tik.F64_BATCHED: "f64_batched", tik.MIXED_BATCHED: "mixed_batched"}[mode],
-                   "tol": tol},
+                   "tol": tol, "solves": nsolve},
         "roofline": roof,
         "cpu_baseline": cpu,
         "solves_ok": n_ok,
+        "checked": checked,
         "lambdas_fp32_refined": n32,
         "lambdas_fp64": n64,
-        "max_rel_err": None if err is None else float(np.max(err)),
+        "max_rel_err": err_max,
         "iters_max": int(iters.max()),
+        "iters_p50_p99": [float(np.percentile(iters.max(axis=1), 50)),
+                          float(np.percentile(iters.max(axis=1), 99))] if len(plist) > 1 else None,
         "status_ok": bool(np.all(status <= 1)),
         "phases_ms_per_step": {k: round(v[0], 3) for k, v in fam.items()},
         "launches_per_step": {k: v[1] for k, v in fam.items()},
         "wall_s_timed": round(wall, 3),
     }
     if plain is not None:
-        pv = plain.get("n_ok", p.lams.size) / (plain["ms_per_step"] / 1000.0)
+        pv = plain.get("n_ok", nsolve) / (plain["ms_per_step"] / 1000.0)
         line["plain_f64_per_lambda"] = {"value": round(pv, 3), "ms_per_step": round(plain["ms_per_step"], 2),
                                         "max_rel_err": plain.get("max_rel_err"),
                                         "iters_max": int(plain["iters"].max())}

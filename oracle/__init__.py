@@ -21,7 +21,10 @@ What it computes (each function cites the passage it follows):
   ``lowrank_truncation`` the rank s_i each lambda keeps (Algorithm 3).
 * ``tikhonov.lsqr_iteration_bound`` and the Lemma 2.1 / Theorem 3.2 bounds.
 * ``tikhonov.certify``: an a-posteriori bound on the forward error of a
-  candidate solution that holds at any size.
+  candidate solution that holds at any size; ``certify_planted`` sharpens it
+  with the generator's planted factors (used at full size, where the direct
+  solve takes minutes).  Both accumulate the gradient in extended precision
+  (``grad_ld.c``, plain C, built by ``native.build_native``).
 
 Parity status: every function above is pinned by tests in
 tests/test_oracle_pins.py against closed forms, exact rational arithmetic,
@@ -46,4 +49,5 @@ from .tikhonov import (  # noqa: F401
     thm32_eps,
     rel_err,
     certify,
+    certify_planted,
 )

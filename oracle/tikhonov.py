@@ -201,22 +201,19 @@ def thm32_bound(eps: float) -> float:
 # ----------------------------------------------------------------------------
 # A-posteriori certificate
 
-def certify(A: np.ndarray, b: np.ndarray, lams: Iterable[float], X: np.ndarray,
-            col_chunk: int = 256) -> np.ndarray:
-    """Upper bound on ||x - x_lam|| / ||x_lam|| for candidate solutions X (n, N).
+def _gradient(A: np.ndarray, b: np.ndarray, lams: np.ndarray, X: np.ndarray,
+              col_chunk: int = 256) -> np.ndarray:
+    """G = A^T (b - A X) - X diag(lams), accumulated in 80-bit extended precision.
 
-    x_lam solves the normal equations (A^T A + lam I) x = A^T b of eq. regLLS,
-    whose matrix has smallest eigenvalue at least lam.  With the gradient
-    g = A^T (b - A x) - lam x, ||x - x_lam|| <= ||g|| / lam, and the triangle
-    inequality turns that into the relative bound
-    (||g|| / lam) / (||x|| - ||g|| / lam).  g is accumulated in 80-bit extended
-    precision, column block by column block, so its own rounding error stays
-    far below the FP64 errors being certified.  Returns one bound per column
-    (inf where the bound is vacuous).
+    Uses the C helper when it is built (same arithmetic, parallel), else numpy
+    long double column block by column block.
     """
+    from .native import gradient_ld
+    G = gradient_ld(A, b, lams, X)
+    if G is not None:
+        return G
     A = np.asarray(A)
     m, n = A.shape
-    lams = np.asarray(list(lams), dtype=np.float64)
     X = np.asarray(X, dtype=np.float64).reshape(n, -1)
     ld = np.longdouble
     R = np.tile(np.asarray(b, dtype=ld).reshape(m, 1), (1, X.shape[1]))
@@ -228,11 +225,61 @@ def certify(A: np.ndarray, b: np.ndarray, lams: Iterable[float], X: np.ndarray,
     for c0 in range(0, n, col_chunk):
         Ac = A[:, c0:c0 + col_chunk].astype(ld)
         G[c0:c0 + col_chunk] = Ac.T @ R
-    G -= Xl * lams.astype(ld)[None, :]
-    gn = np.sqrt(np.sum(G * G, axis=0)).astype(np.float64)
+    G -= Xl * np.asarray(lams, dtype=ld)[None, :]
+    return G.astype(np.float64)
+
+
+def certify(A: np.ndarray, b: np.ndarray, lams: Iterable[float], X: np.ndarray) -> np.ndarray:
+    """Upper bound on ||x - x_lam|| / ||x_lam|| for candidate solutions X (n, N).
+
+    x_lam solves the normal equations (A^T A + lam I) x = A^T b of eq. regLLS,
+    whose matrix has smallest eigenvalue at least lam.  With the gradient
+    g = A^T (b - A x) - lam x, ||x - x_lam|| <= ||g|| / lam, and the triangle
+    inequality turns that into the relative bound
+    (||g|| / lam) / (||x|| - ||g|| / lam).  g is accumulated in 80-bit extended
+    precision, so its own rounding error stays far below the FP64 errors being
+    certified.  Returns one bound per column (inf where the bound is vacuous).
+    """
+    A = np.asarray(A)
+    n = A.shape[1]
+    lams = np.asarray(list(lams), dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64).reshape(n, -1)
+    gn = np.linalg.norm(_gradient(A, b, lams, X), axis=0)
     dx = gn / lams
     xn = np.linalg.norm(X, axis=0)
     out = np.full(X.shape[1], np.inf)
     ok = xn > dx
     out[ok] = dx[ok] / (xn[ok] - dx[ok])
+    return out
+
+
+def certify_planted(A: np.ndarray, b: np.ndarray, lams: Iterable[float], X: np.ndarray,
+                    sigma: np.ndarray, V: np.ndarray, steps: int = 2) -> np.ndarray:
+    """Sharper bound on ||x - x_lam|| / ||x_lam|| when A was generated as U diag(sigma) V^T.
+
+    The plain bound ||g|| / lam of ``certify`` overestimates by up to
+    ||A||^2 / lam.  Here the generator's factors give an approximate inverse
+    M^{-1} = V diag(1 / (sigma^2 + lam)) V^T of A^T A + lam I (exact for the
+    planted matrix, close for its stored rounding).  Refinement with it:
+    D <- D + M^{-1} g(X + D), repeated `steps` times with g in extended
+    precision; then x_lam - X = D + (x_lam - (X + D)) and the last term is
+    bounded by ||g(X + D)|| / lam as in ``certify``.  The bound holds whatever
+    the quality of M^{-1}; a poor M^{-1} only makes it loose.
+    """
+    A = np.asarray(A)
+    n = A.shape[1]
+    lams = np.asarray(list(lams), dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64).reshape(n, -1)
+    sig2 = np.asarray(sigma, dtype=np.float64) ** 2
+    V = np.asarray(V, dtype=np.float64)
+    Xc = X.copy()
+    for _ in range(steps):
+        G = _gradient(A, b, lams, Xc)
+        Xc = Xc + V @ ((V.T @ G) / (sig2[:, None] + lams[None, :]))
+    gn = np.linalg.norm(_gradient(A, b, lams, Xc), axis=0)
+    bound = np.linalg.norm(Xc - X, axis=0) + gn / lams
+    xn = np.linalg.norm(X, axis=0)
+    out = np.full(X.shape[1], np.inf)
+    ok = xn > bound
+    out[ok] = bound[ok] / (xn[ok] - bound[ok])
     return out

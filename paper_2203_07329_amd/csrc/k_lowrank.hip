@@ -1,16 +1,21 @@
 // Low-statistical-dimension preconditioner (Algorithm 3, Section 3.1).
 //
-// From the short, fat sketch Y = XA (s x n, s < n) the route needs the economy
-// SVD Y = U Sigma V^T (Algorithm 3 step 4) without ever forming a Gram matrix:
-//   1. Householder QR of Y^T (n x s) in FP64: Y^T = Q R_y, blocked in panels of
+// From the short, fat sketch Y = XA (s x n, s <= n) the route needs the
+// economy SVD Y = U Sigma V^T (Algorithm 3 step 4) without ever forming a Gram
+// matrix:
+//   1. Householder QR of Y^T (n x s) in FP64: Y^T = Q1 R1, blocked in panels of
 //      32 columns with compact-WY trailing updates (Schreiber & Van Loan).
-//   2. One-sided Jacobi SVD (Hestenes) of the s x s triangle R_y: plane
-//      rotations orthogonalise its columns, R_y W = Z Sigma, so the normalised
-//      columns are the left singular vectors Z of R_y and their norms are the
-//      singular values.  Round-robin ordering: every round rotates s/2
-//      disjoint column pairs in parallel, s - 1 rounds make a sweep.
-//   3. Since Y = R_y^T Q^T = W Sigma (Q Z)^T, the right singular vectors of Y
-//      are V = Q Z, obtained by applying the reflectors to [Z; 0] backwards.
+//   2. A second Householder QR, of R1^T = Q2 R2, so that Y^T = Q1 R2^T Q2^T.
+//      The lower triangle L = R2^T has far more nearly orthogonal columns than
+//      R1, which cuts the sweeps of the next step by more than half (the QR
+//      preconditioning of one-sided Jacobi, Drmac & Veselic 2008).
+//   3. One-sided Jacobi (Hestenes) on L: plane rotations orthogonalise its
+//      columns, L W = Z Sigma; the normalised columns Z are the left singular
+//      vectors of L and their norms the singular values.  Round-robin
+//      ordering: every round rotates s/2 disjoint column pairs in parallel.
+//   4. Y^T = (Q1 Z) Sigma (Q2 W)^T, so the right singular vectors of Y are
+//      V = Q1 Z: the reflectors of step 1 applied to [Z; 0].  Neither W nor Q2
+//      is ever formed.
 // sd_hat (Section 3.1.2), s_i and S_i (Algorithm 3 steps 5-7) are formed from
 // the singular values per lambda.
 #include "tik_internal.h"
@@ -54,15 +59,16 @@ __global__ void k_lr_transpose(const double* __restrict__ Y, int64_t s, int64_t 
   }
 }
 
-// Householder vector of column j (LAPACK dlarfg): on exit Z[j, j] = beta,
-// Z[j+1:n, j] = v (v_0 = 1 implied), tau[j].  One block of 1024 threads.
-__global__ void __launch_bounds__(1024) k_lr_house(double* __restrict__ Z, int64_t n, int64_t j,
-                                                   double* __restrict__ tau) {
+// Householder vector of column j of Z (rows x *, ld ldz), as LAPACK dlarfg
+// defines it: on exit Z[j, j] = beta, Z[j+1:rows, j] = v (v_0 = 1 implied),
+// tau[j].  One block of 1024 threads.
+__global__ void __launch_bounds__(1024) k_lr_house(double* __restrict__ Z, int64_t ldz, int64_t rows,
+                                                   int64_t j, double* __restrict__ tau) {
   __shared__ double red[16];
   __shared__ double sh_scale;
-  double* col = Z + j * n;
+  double* col = Z + j * ldz;
   double ss = 0.0;
-  for (int64_t r = j + 1 + threadIdx.x; r < n; r += blockDim.x) ss += col[r] * col[r];
+  for (int64_t r = j + 1 + threadIdx.x; r < rows; r += blockDim.x) ss += col[r] * col[r];
   const double sigma = lr_block_sum<1024>(ss, red);
   if (threadIdx.x == 0) {
     const double alpha = col[j];
@@ -79,37 +85,39 @@ __global__ void __launch_bounds__(1024) k_lr_house(double* __restrict__ Z, int64
   __syncthreads();
   const double sc = sh_scale;
   if (sc != 0.0)
-    for (int64_t r = j + 1 + threadIdx.x; r < n; r += blockDim.x) col[r] *= sc;
+    for (int64_t r = j + 1 + threadIdx.x; r < rows; r += blockDim.x) col[r] *= sc;
 }
 
-// Apply H_j = I - tau v v^T to columns j+1 .. cend-1 of Z (one block per column).
-__global__ void __launch_bounds__(256) k_lr_apply_house(double* __restrict__ Z, int64_t n, int64_t j,
+// Apply H_j = I - tau v v^T to the columns j+1 .. j+gridDim.x of Z (one block
+// per column).
+__global__ void __launch_bounds__(256) k_lr_apply_house(double* __restrict__ Z, int64_t ldz,
+                                                        int64_t rows, int64_t j,
                                                         const double* __restrict__ tau) {
   __shared__ double red[4];
   const int64_t c = j + 1 + blockIdx.x;
-  const double* v = Z + j * n;
-  double* col = Z + c * n;
+  const double* v = Z + j * ldz;
+  double* col = Z + c * ldz;
   double w = 0.0;
-  for (int64_t r = j + 1 + threadIdx.x; r < n; r += 256) w += v[r] * col[r];
+  for (int64_t r = j + 1 + threadIdx.x; r < rows; r += 256) w += v[r] * col[r];
   double tot = lr_block_sum<256>(w, red);
   tot = (tot + col[j]) * tau[j];
   if (threadIdx.x == 0) col[j] -= tot;
-  for (int64_t r = j + 1 + threadIdx.x; r < n; r += 256) col[r] -= tot * v[r];
+  for (int64_t r = j + 1 + threadIdx.x; r < rows; r += 256) col[r] -= tot * v[r];
 }
 
-// Explicit panel V (rows k0..n-1, LR_NB columns, ld = n - k0): unit diagonal,
-// zeros above, the stored reflectors below.
-__global__ void k_lr_copy_v(const double* __restrict__ Z, int64_t n, int64_t k0, int nb,
-                            double* __restrict__ Vc) {
-  const int64_t rows = n - k0;
-  const int64_t total = rows * nb;
+// Explicit panel V (rows k0..rows-1, nb columns, ld rows - k0): unit
+// diagonal, zeros above, the stored reflectors below.
+__global__ void k_lr_copy_v(const double* __restrict__ Z, int64_t ldz, int64_t rows, int64_t k0,
+                            int nb, double* __restrict__ Vc) {
+  const int64_t rr = rows - k0;
+  const int64_t total = rr * nb;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
        e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t r = e % rows, c = e / rows;
+    const int64_t r = e % rr, c = e / rr;
     double v;
     if (r < c) v = 0.0;
     else if (r == c) v = 1.0;
-    else v = Z[(k0 + r) + (k0 + c) * n];
+    else v = Z[(k0 + r) + (k0 + c) * ldz];
     Vc[e] = v;
   }
 }
@@ -223,28 +231,30 @@ __global__ void k_lr_tmul(const double* __restrict__ T, int nb, const double* __
   }
 }
 
-// Rz (s x s, ld s): the upper triangle of the factored Z, zeros below.
-__global__ void k_lr_get_r(const double* __restrict__ Z, int64_t n, int64_t s,
-                           double* __restrict__ Rz) {
-  const int64_t total = s * s;
+// Dst (c x c, ld c) = the transpose of the upper triangle of the factored
+// Src (leading c x c block, ld lds): lower triangular, zeros above.
+__global__ void k_lr_get_rt(const double* __restrict__ Src, int64_t lds, int64_t c,
+                            double* __restrict__ Dst) {
+  const int64_t total = c * c;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
        e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t r = e % s, c = e / s;
-    Rz[e] = r <= c ? Z[r + c * n] : 0.0;
+    const int64_t i = e % c, j = e / c;            // Dst(i, j) = Src(j, i) for j <= i
+    Dst[e] = j <= i ? Src[j + i * lds] : 0.0;
   }
 }
 
-// One round of one-sided Jacobi on the columns of G (s x s, ld s): one wave
-// per column pair of the round-robin schedule over sp = s rounded up to even.
-// Pair 0 is (r, sp - 1); pair i > 0 is ((r + i) mod (sp - 1), (r - i) mod (sp - 1)).
-// A pair is rotated when |g_p . g_q| > tol sqrt(|g_p|^2 |g_q|^2); the number of
-// rotations is added to *count.
-__global__ void __launch_bounds__(256) k_lr_jacobi_round(double* __restrict__ G, int64_t s, int sp,
-                                                         int r, double tol,
-                                                         unsigned int* __restrict__ count) {
-  const int lane = threadIdx.x & 63;
-  const int pair = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (pair >= sp / 2) return;
+// One round of one-sided Jacobi on the columns of G (s x s, ld s): one
+// workgroup per column pair of the round-robin schedule over sp = s rounded up
+// to even.  Pair 0 is (r, sp - 1); pair i > 0 is ((r + i) mod (sp - 1),
+// (r - i) mod (sp - 1)), so the pairs of a round are disjoint.  Both columns
+// are held in registers (EPT entries per thread, s <= 256 EPT): one read, one
+// write.  A pair is rotated when |g_p . g_q| > tol sqrt(|g_p|^2 |g_q|^2); the
+// number of rotations is added to *count.
+template <int EPT>
+__global__ void __launch_bounds__(256) k_lr_jrot(double* __restrict__ G, int64_t s, int sp, int r,
+                                                 double tol, unsigned int* __restrict__ count) {
+  __shared__ double red[3][4];
+  const int pair = blockIdx.x;
   const int m = sp - 1;
   int p, q;
   if (pair == 0) {
@@ -254,29 +264,49 @@ __global__ void __launch_bounds__(256) k_lr_jacobi_round(double* __restrict__ G,
     p = (r + pair) % m;
     q = ((r - pair) % m + m) % m;
   }
-  if (p >= s || q >= s) return;   // the padding column
-  double* gp = G + int64_t(p) * s;
-  double* gq = G + int64_t(q) * s;
+  if (p >= s || q >= s) return;   // the padding column (uniform over the block)
+  double* __restrict__ gp = G + int64_t(p) * s;
+  double* __restrict__ gq = G + int64_t(q) * s;
+  double x[EPT], y[EPT];
   double a = 0.0, b = 0.0, c = 0.0;
-  for (int64_t i = lane; i < s; i += 64) {
-    const double x = gp[i], y = gq[i];
-    a += x * x;
-    b += y * y;
-    c += x * y;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int64_t i = threadIdx.x + int64_t(e) * 256;
+    x[e] = i < s ? gp[i] : 0.0;
+    y[e] = i < s ? gq[i] : 0.0;
+  }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    a = fma(x[e], x[e], a);
+    b = fma(y[e], y[e], b);
+    c = fma(x[e], y[e], c);
   }
   a = lr_wave_sum(a);
   b = lr_wave_sum(b);
   c = lr_wave_sum(c);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wv] = a;
+    red[1][wv] = b;
+    red[2][wv] = c;
+  }
+  __syncthreads();
+  a = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+  b = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  c = (red[2][0] + red[2][1]) + (red[2][2] + red[2][3]);
   if (!(fabs(c) > tol * sqrt(a * b))) return;
   const double zeta = (b - a) / (2.0 * c);
   const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-  for (int64_t i = lane; i < s; i += 64) {
-    const double x = gp[i], y = gq[i];
-    gp[i] = cs * x - sn * y;
-    gq[i] = sn * x + cs * y;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int64_t i = threadIdx.x + int64_t(e) * 256;
+    if (i < s) {
+      gp[i] = cs * x[e] - sn * y[e];
+      gq[i] = sn * x[e] + cs * y[e];
+    }
   }
-  if (lane == 0) atomicAdd(count, 1u);
+  if (threadIdx.x == 0) atomicAdd(count, 1u);
 }
 
 // sigma_j = ||g_j||, g_j /= sigma_j (one block per column).
@@ -406,13 +436,104 @@ static int lr_gemm_add(int64_t M, int64_t N, int64_t K, const double* A, int64_t
   return TIK_OK;
 }
 
+// Workspace of the QR routine below for a rows x cols factorization.
+struct QrWs {
+  double* tau;    // cols
+  double* T;      // ceil(cols / 32) panels of 32 x 32
+  double* Vc;     // rows x 32
+  double* Gm;     // 32 x 32
+  double* W1;     // 32 x cols
+  double* W2;     // 32 x cols
+  double* part;   // part_cap
+  int64_t part_cap;
+};
+
+static size_t qr_ws_doubles(int64_t rows, int64_t cols) {
+  const int64_t np = cdiv(cols, LR_NB);
+  return size_t(cols + np * LR_NB * LR_NB + rows * LR_NB + LR_NB * LR_NB + 2 * LR_NB * cols +
+                std::max<int64_t>(64 * LR_NB * std::max<int64_t>(cols, LR_NB), rows * cols) + 8 * 32);
+}
+
+static QrWs qr_ws_carve(double* base, int64_t rows, int64_t cols) {
+  QrWs w;
+  const int64_t np = cdiv(cols, LR_NB);
+  w.tau = base;
+  w.T = w.tau + cols;
+  w.Vc = w.T + np * LR_NB * LR_NB;
+  w.Gm = w.Vc + rows * LR_NB;
+  w.W1 = w.Gm + LR_NB * LR_NB;
+  w.W2 = w.W1 + LR_NB * cols;
+  w.part = w.W2 + LR_NB * cols;
+  w.part_cap = std::max<int64_t>(64 * LR_NB * std::max<int64_t>(cols, LR_NB), rows * cols);
+  return w;
+}
+
+// In-place Householder QR of Z (rows x cols, ld ldz, rows >= cols): R in the
+// upper triangle, reflectors below it, tau and the per-panel T factors of the
+// compact WY form H_k0 ... H_k0+nb-1 = I - V T V^T in w.
+static int qr_factor(double* Z, int64_t rows, int64_t cols, int64_t ldz, const QrWs& w,
+                     hipStream_t st) {
+  const int64_t np = cdiv(cols, LR_NB);
+  for (int64_t pnl = 0; pnl < np; ++pnl) {
+    const int64_t k0 = pnl * LR_NB;
+    const int nb = int(std::min<int64_t>(LR_NB, cols - k0));
+    for (int jj = 0; jj < nb; ++jj) {
+      const int64_t j = k0 + jj;
+      hipLaunchKernelGGL(k_lr_house, dim3(1), dim3(1024), 0, st, Z, ldz, rows, j, w.tau);
+      TIK_LAUNCHED("k_lr_house");
+      if (jj + 1 < nb) {
+        hipLaunchKernelGGL(k_lr_apply_house, dim3(unsigned(nb - jj - 1)), dim3(256), 0, st, Z, ldz,
+                           rows, j, w.tau);
+        TIK_LAUNCHED("k_lr_apply_house");
+      }
+    }
+    const int64_t rr = rows - k0;
+    hipLaunchKernelGGL(k_lr_copy_v, dim3(lr_grid(rr * nb)), dim3(256), 0, st, Z, ldz, rows, k0, nb,
+                       w.Vc);
+    TIK_LAUNCHED("k_lr_copy_v");
+    double* Tp = w.T + pnl * LR_NB * LR_NB;
+    TIK_TRY(lr_gemm(true, nb, nb, rr, w.Vc, rr, w.Vc, rr, w.Gm, 1.0, 0.0, w.part, w.part_cap, st));
+    hipLaunchKernelGGL(k_lr_form_t, dim3(1), dim3(64), 0, st, w.Gm, nb, w.tau + k0, Tp);
+    TIK_LAUNCHED("k_lr_form_t");
+    const int64_t ntr = cols - k0 - nb;
+    if (ntr > 0) {
+      double* Ztr = Z + k0 + (k0 + nb) * ldz;
+      // W1 = Vc^T Ztr (nb x ntr), W2 = T^T W1, Ztr -= Vc W2
+      TIK_TRY(lr_gemm(true, nb, ntr, rr, w.Vc, rr, Ztr, ldz, w.W1, 1.0, 0.0, w.part, w.part_cap, st));
+      hipLaunchKernelGGL(k_lr_tmul<true>, dim3(lr_grid(nb * ntr)), dim3(256), 0, st, Tp, nb, w.W1,
+                         ntr, w.W2);
+      TIK_LAUNCHED("k_lr_tmul");
+      TIK_TRY(lr_gemm_add(rr, ntr, nb, w.Vc, rr, w.W2, Ztr, ldz, -1.0, w.part, st));
+    }
+  }
+  return TIK_OK;
+}
+
+// X (rows x c, ld ldx) <- Q X with Q the product of the reflectors stored in
+// Z by qr_factor (applied last panel first).
+static int qr_apply_q(const double* Z, int64_t rows, int64_t cols, int64_t ldz, const QrWs& w,
+                      double* X, int64_t c, int64_t ldx, hipStream_t st) {
+  const int64_t np = cdiv(cols, LR_NB);
+  for (int64_t pnl = np - 1; pnl >= 0; --pnl) {
+    const int64_t k0 = pnl * LR_NB;
+    const int nb = int(std::min<int64_t>(LR_NB, cols - k0));
+    const int64_t rr = rows - k0;
+    hipLaunchKernelGGL(k_lr_copy_v, dim3(lr_grid(rr * nb)), dim3(256), 0, st, Z, ldz, rows, k0, nb,
+                       w.Vc);
+    TIK_LAUNCHED("k_lr_copy_v");
+    double* Xr = X + k0;
+    TIK_TRY(lr_gemm(true, nb, c, rr, w.Vc, rr, Xr, ldx, w.W1, 1.0, 0.0, w.part, w.part_cap, st));
+    hipLaunchKernelGGL(k_lr_tmul<false>, dim3(lr_grid(nb * c)), dim3(256), 0, st,
+                       w.T + pnl * LR_NB * LR_NB, nb, w.W1, c, w.W2);
+    TIK_LAUNCHED("k_lr_tmul");
+    TIK_TRY(lr_gemm_add(rr, c, nb, w.Vc, rr, w.W2, Xr, ldx, -1.0, w.part, st));
+  }
+  return TIK_OK;
+}
+
 size_t lowrank_scratch_doubles(int64_t n, int64_t s) {
-  // Z (n s) + Rz (s s) + X (n s) + Vc (n nb) + tau (s) + T (panels nb nb)
-  // + G (nb nb) + W1, W2 (nb s each) + part (max of 64 nb nb, n s)
-  const int64_t np = cdiv(s, LR_NB);
-  return size_t(n * s + s * s + n * s + n * LR_NB + s + np * LR_NB * LR_NB + LR_NB * LR_NB +
-                2 * LR_NB * s + std::max<int64_t>(64 * LR_NB * std::max<int64_t>(s, LR_NB), n * s) +
-                64);
+  // Z (n s) + Z2 (s s) + L (s s) + sig_raw (s) + QR workspaces of n x s and s x s
+  return size_t(n * s + 2 * s * s + s) + qr_ws_doubles(n, s) + qr_ws_doubles(s, s) + 64;
 }
 
 // V (n x s, ld n, columns by decreasing sigma) and sigma (s) of Y (s x n, ld s).
@@ -421,69 +542,50 @@ int launch_lowrank_svd(const double* Y, int64_t s, int64_t n, double* V, double*
                        double* scratch, unsigned int* cnt, int32_t* perm, int* sweeps_out,
                        hipStream_t st) {
   ProfScope ps("lowrank", st);
-  double* Z = scratch;
-  double* Rz = Z + n * s;
-  double* X = Rz + s * s;
-  double* Vc = X + n * s;
-  double* tau = Vc + n * LR_NB;
-  const int64_t np = cdiv(s, LR_NB);
-  double* T = tau + s;
-  double* Gm = T + np * LR_NB * LR_NB;
-  double* W1 = Gm + LR_NB * LR_NB;
-  double* W2 = W1 + LR_NB * s;
-  double* part = W2 + LR_NB * s;
-  const int64_t part_cap = std::max<int64_t>(64 * LR_NB * std::max<int64_t>(s, LR_NB), n * s);
-  double* sig_raw = X;          // reused before X is needed
-  // 1. Z = Y^T, Householder QR
-  hipLaunchKernelGGL(k_lr_transpose, dim3(unsigned(cdiv(s, 32)), unsigned(cdiv(n, 32))), dim3(256),
-                     0, st, Y, s, n, Z);
-  TIK_LAUNCHED("k_lr_transpose");
-  for (int64_t pnl = 0; pnl < np; ++pnl) {
-    const int64_t k0 = pnl * LR_NB;
-    const int nb = int(std::min<int64_t>(LR_NB, s - k0));
-    for (int jj = 0; jj < nb; ++jj) {
-      const int64_t j = k0 + jj;
-      hipLaunchKernelGGL(k_lr_house, dim3(1), dim3(1024), 0, st, Z, n, j, tau);
-      TIK_LAUNCHED("k_lr_house");
-      if (jj + 1 < nb) {
-        hipLaunchKernelGGL(k_lr_apply_house, dim3(unsigned(nb - jj - 1)), dim3(256), 0, st, Z, n, j,
-                           tau);
-        TIK_LAUNCHED("k_lr_apply_house");
-      }
-    }
-    const int64_t rows = n - k0;
-    hipLaunchKernelGGL(k_lr_copy_v, dim3(lr_grid(rows * nb)), dim3(256), 0, st, Z, n, k0, nb, Vc);
-    TIK_LAUNCHED("k_lr_copy_v");
-    // G = Vc^T Vc, T
-    TIK_TRY(lr_gemm(true, nb, nb, rows, Vc, rows, Vc, rows, Gm, 1.0, 0.0, part, part_cap, st));
-    hipLaunchKernelGGL(k_lr_form_t, dim3(1), dim3(64), 0, st, Gm, nb, tau + k0,
-                       T + pnl * LR_NB * LR_NB);
-    TIK_LAUNCHED("k_lr_form_t");
-    const int64_t ntr = s - k0 - nb;
-    if (ntr > 0) {
-      double* Ztr = Z + k0 + (k0 + nb) * n;
-      // W1 = Vc^T Ztr (nb x ntr), W2 = T^T W1, Ztr -= Vc W2
-      TIK_TRY(lr_gemm(true, nb, ntr, rows, Vc, rows, Ztr, n, W1, 1.0, 0.0, part, part_cap, st));
-      hipLaunchKernelGGL(k_lr_tmul<true>, dim3(lr_grid(nb * ntr)), dim3(256), 0, st,
-                         T + pnl * LR_NB * LR_NB, nb, W1, ntr, W2);
-      TIK_LAUNCHED("k_lr_tmul");
-      TIK_TRY(lr_gemm_add(rows, ntr, nb, Vc, rows, W2, Ztr, n, -1.0, part, st));
-    }
+  if (s > 4096) {
+    set_error("internal: low-rank SVD supports s <= 4096");
+    return TIK_EINVAL;
   }
-  // 2. one-sided Jacobi on R_y
-  hipLaunchKernelGGL(k_lr_get_r, dim3(lr_grid(s * s)), dim3(256), 0, st, Z, n, s, Rz);
-  TIK_LAUNCHED("k_lr_get_r");
+  double* Z = scratch;               // n x s: Y^T, then R1 and the reflectors of Q1
+  double* Z2 = Z + n * s;            // s x s: R1^T, then R2 and the reflectors of Q2
+  double* L = Z2 + s * s;            // s x s: R2^T, rotated into Z Sigma
+  double* sig_raw = L + s * s;       // s
+  const QrWs w1 = qr_ws_carve(sig_raw + s, n, s);
+  const QrWs w2 = qr_ws_carve(sig_raw + s + qr_ws_doubles(n, s), s, s);
+  {
+    ProfScope ps_qr("lr_qr", st);
+    // 1. Y^T = Q1 R1
+    hipLaunchKernelGGL(k_lr_transpose, dim3(unsigned(cdiv(s, 32)), unsigned(cdiv(n, 32))), dim3(256),
+                       0, st, Y, s, n, Z);
+    TIK_LAUNCHED("k_lr_transpose");
+    TIK_TRY(qr_factor(Z, n, s, n, w1, st));
+    // 2. R1^T = Q2 R2, L = R2^T
+    hipLaunchKernelGGL(k_lr_get_rt, dim3(lr_grid(s * s)), dim3(256), 0, st, Z, n, s, Z2);
+    TIK_LAUNCHED("k_lr_get_rt");
+    TIK_TRY(qr_factor(Z2, s, s, s, w2, st));
+    hipLaunchKernelGGL(k_lr_get_rt, dim3(lr_grid(s * s)), dim3(256), 0, st, Z2, s, s, L);
+    TIK_LAUNCHED("k_lr_get_rt");
+  }
+  // 3. one-sided Jacobi on the columns of L
   const int sp = int(s + (s & 1));
   const double tol = 1e-15 * std::sqrt(double(s));
   int sweeps = 0;
   const int maxsweeps = 30;
+  const int ept = s <= 256 ? 1 : s <= 512 ? 2 : s <= 1024 ? 4 : s <= 2048 ? 8 : 16;
   for (; sweeps < maxsweeps;) {
+    ProfScope ps_sw("lr_sweep", st);
     TIK_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned int), st));
+    const dim3 g = dim3(unsigned(sp / 2));
     for (int r = 0; r < sp - 1; ++r) {
-      hipLaunchKernelGGL(k_lr_jacobi_round, dim3(unsigned(cdiv(sp / 2, 4))), dim3(256), 0, st, Rz, s,
-                         sp, r, tol, cnt);
+      switch (ept) {
+        case 1: hipLaunchKernelGGL(k_lr_jrot<1>, g, dim3(256), 0, st, L, s, sp, r, tol, cnt); break;
+        case 2: hipLaunchKernelGGL(k_lr_jrot<2>, g, dim3(256), 0, st, L, s, sp, r, tol, cnt); break;
+        case 4: hipLaunchKernelGGL(k_lr_jrot<4>, g, dim3(256), 0, st, L, s, sp, r, tol, cnt); break;
+        case 8: hipLaunchKernelGGL(k_lr_jrot<8>, g, dim3(256), 0, st, L, s, sp, r, tol, cnt); break;
+        default: hipLaunchKernelGGL(k_lr_jrot<16>, g, dim3(256), 0, st, L, s, sp, r, tol, cnt); break;
+      }
     }
-    TIK_LAUNCHED("k_lr_jacobi_round");
+    TIK_LAUNCHED("k_lr_jrot");
     ++sweeps;
     unsigned int h = 0;
     TIK_HIP(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -491,27 +593,15 @@ int launch_lowrank_svd(const double* Y, int64_t s, int64_t n, double* V, double*
     if (h == 0) break;
   }
   if (sweeps_out) *sweeps_out = sweeps;
-  hipLaunchKernelGGL(k_lr_normalize, dim3(unsigned(s)), dim3(256), 0, st, Rz, s, sig_raw);
+  hipLaunchKernelGGL(k_lr_normalize, dim3(unsigned(s)), dim3(256), 0, st, L, s, sig_raw);
   TIK_LAUNCHED("k_lr_normalize");
   hipLaunchKernelGGL(k_lr_sort, dim3(1), dim3(1024), 0, st, sig_raw, s, perm, sig);
   TIK_LAUNCHED("k_lr_sort");
-  // 3. V = Q [Z; 0], reflector panels applied last to first
-  hipLaunchKernelGGL(k_lr_gather, dim3(lr_grid(n * s)), dim3(256), 0, st, Rz, s, n, perm, V);
+  // 4. V = Q1 [Z; 0]
+  ProfScope ps_q("lr_q", st);
+  hipLaunchKernelGGL(k_lr_gather, dim3(lr_grid(n * s)), dim3(256), 0, st, L, s, n, perm, V);
   TIK_LAUNCHED("k_lr_gather");
-  for (int64_t pnl = np - 1; pnl >= 0; --pnl) {
-    const int64_t k0 = pnl * LR_NB;
-    const int nb = int(std::min<int64_t>(LR_NB, s - k0));
-    const int64_t rows = n - k0;
-    hipLaunchKernelGGL(k_lr_copy_v, dim3(lr_grid(rows * nb)), dim3(256), 0, st, Z, n, k0, nb, Vc);
-    TIK_LAUNCHED("k_lr_copy_v");
-    double* Xr = V + k0;    // rows k0..n-1 of V, all s columns, ld n
-    TIK_TRY(lr_gemm(true, nb, s, rows, Vc, rows, Xr, n, W1, 1.0, 0.0, part, part_cap, st));
-    hipLaunchKernelGGL(k_lr_tmul<false>, dim3(lr_grid(nb * s)), dim3(256), 0, st,
-                       T + pnl * LR_NB * LR_NB, nb, W1, s, W2);
-    TIK_LAUNCHED("k_lr_tmul");
-    TIK_TRY(lr_gemm_add(rows, s, nb, Vc, rows, W2, Xr, n, -1.0, part, st));
-  }
-  return TIK_OK;
+  return qr_apply_q(Z, n, s, n, w1, V, s, n, st);
 }
 
 int launch_lowrank_S(const double* sig, int64_t s, const double* lams, const int32_t* si, int N,

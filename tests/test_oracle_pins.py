@@ -309,3 +309,48 @@ def test_lowrank_truncation_rule():
     sig = np.sort(rng.uniform(0, 1, 40))[::-1]
     ranks = [oracle.lowrank_truncation(sig, l, 2.0, 40) for l in np.logspace(-4, 1, 30)]
     assert all(a >= b for a, b in zip(ranks, ranks[1:]))
+
+
+def _numpy_gradient(A, b, lams, X):
+    ld = np.longdouble
+    Al = np.asarray(A).astype(ld)
+    R = np.asarray(b, dtype=ld)[:, None] - Al @ X.astype(ld)
+    return (Al.T @ R - X.astype(ld) * np.asarray(lams, dtype=ld)[None, :]).astype(np.float64)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_native_gradient_matches_long_double_numpy(dtype):
+    """The C helper computes the same extended-precision gradient as numpy long double."""
+    from oracle import native
+    if native.lib() is None:
+        native.build_native()
+    rng = np.random.default_rng(12)
+    m, n, N = 700, 90, 5
+    A = np.asfortranarray(rng.standard_normal((m, n)).astype(dtype))
+    b = rng.standard_normal(m)
+    lams = np.logspace(-3, 0, N)
+    X = rng.standard_normal((n, N))
+    Gc = native.gradient_ld(A, b, lams, X)
+    Gn = _numpy_gradient(A, b, lams, X)
+    assert np.max(np.abs(Gc - Gn)) <= 1e-13 * np.max(np.abs(Gn))
+    # at the exact solution the gradient vanishes to extended-precision rounding
+    Xo = oracle.solve(A, b, lams)
+    G0 = native.gradient_ld(A, b, lams, Xo)
+    assert np.max(np.abs(G0)) <= 1e-11 * np.max(np.abs(Gn))
+
+
+def test_certify_planted_bounds_the_true_error():
+    """The planted-factor bound is valid and tight; a wrong sigma keeps it valid."""
+    p = W.lowsd(m=900, n=220, N=4, decay=20.0, lam_lo=1e-4, lam_hi=1e-1, seed=3)
+    Xo = oracle.solve(p.A, p.b, p.lams)
+    rng = np.random.default_rng(5)
+    for eps in (1e-6, 1e-9):
+        Xp = Xo + eps * rng.standard_normal(Xo.shape) * np.linalg.norm(Xo, axis=0)[None, :] / math.sqrt(p.n)
+        true = oracle.rel_err(Xp, Xo)
+        bnd = oracle.certify_planted(p.A, p.b, p.lams, Xp, p.sigma, p.V)
+        plain = oracle.certify(p.A, p.b, p.lams, Xp)
+        assert np.all(bnd >= true * (1 - 1e-6)), (bnd, true)
+        assert np.all(bnd <= 1.5 * true + 1e-12), (bnd, true)
+        assert np.all(plain >= bnd * (1 - 1e-6))          # the planted bound is the sharper one
+    bad = oracle.certify_planted(p.A, p.b, p.lams, Xp, 1.7 * p.sigma, p.V)
+    assert np.all(bad >= true * (1 - 1e-6))

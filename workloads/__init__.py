@@ -178,7 +178,8 @@ def lowsd(m: int = 100000, n: int = 10000, N: int = 16, seed: int = 0, decay: fl
         del gu
         Vt = _haar_t(gv)
         A64 = ((Ut * torch.from_numpy(sigma).to(device)[None, :]) @ Vt.T).cpu().numpy()
-        U = V = None
+        U = None                      # m x n: not kept at full size
+        V = np.asfortranarray(Vt.cpu().numpy())
         del Ut, Vt
     A = np.asfortranarray(A64.astype(np.float32))
     del A64
