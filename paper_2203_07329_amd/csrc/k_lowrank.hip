@@ -617,8 +617,8 @@ int launch_lowrank_S(const double* sig, int64_t s, const double* lams, const int
 // for all lambdas of a solve at once; the matrix is symmetric, so the same
 // three kernels give R^{-T}.  V (k x s, ld k) is read twice per application:
 //   proj    part[ch][j][i] = sum_{r in chunk ch} V[r, j] x_i[r]     (j < smax)
-//   expand  opart[jc][i][r] = sum_{j in column chunk jc} V[r, j] c[j, i],
-//           c[j, i] = S_i[j] sum_ch part[ch][j][i]
+//   coef    c[j, i] = S_i[j] sum_ch part[ch][j][i]
+//   expand  opart[jc][i][r] = sum_{j in column chunk jc} V[r, j] c[j, i]
 //   fin     the LSQR step that consumes R^{-1} x, with the chunk sums of opart.
 // S_i[j] is zero for j >= s_i, which truncates every lambda to its own rank.
 
@@ -684,14 +684,144 @@ __global__ void __launch_bounds__(256) k_lr_proj(const DevProb* __restrict__ P,
   }
 }
 
+// Projection on the matrix cores (16 or 32 lambdas): block = 128 columns of V
+// x one row chunk; wave w owns columns 32 w .. 32 w + 31, as two 16-column
+// tiles times NC / 16 lambda tiles of v_mfma_f64_16x16x4_f64.  V (32 rows x
+// 128 columns) and x (32 rows x NC) are staged through LDS, the next tile
+// being fetched into registers while the current one is consumed.  Blocks are
+// remapped so that the column blocks of one row chunk, which share x, run on
+// one XCD.
+typedef double lr_d4 __attribute__((ext_vector_type(4)));
+
+template <int NC, bool LMAJ>
+__global__ void __launch_bounds__(256) k_lr_proj_mfma(const DevProb* __restrict__ P,
+                                                      const Item* __restrict__ items, int nitems,
+                                                      int N, const double* __restrict__ src,
+                                                      double* __restrict__ part) {
+  constexpr int NT = NC / 16;
+  constexpr int CB = 128, RS = 32, AP = RS + 2, UP = NC + 1;
+  __shared__ double Vs[CB][AP];
+  __shared__ double Xs[RS][UP];
+  const int g = blockIdx.x;
+  const int per = (nitems + 7) >> 3;
+  const int L = (g & 7) * per + (g >> 3);
+  if (L >= nitems) return;
+  const Item it = items[L];
+  const DevProb& pr = P[it.p];
+  const double* __restrict__ V = pr.V;
+  const int64_t k = pr.k, smax = pr.smax;
+  const int64_t c0 = int64_t(it.blk) * CB;
+  const int64_t rbeg = int64_t(it.ch) * pr.lrRch;
+  const int64_t rend = min(k, rbeg + pr.lrRch);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  lr_d4 acc[2][NT];
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[ct][nt] = lr_d4{0, 0, 0, 0};
+  constexpr int QA = (RS * CB) / 256;
+  constexpr int QU = (RS * NC + 255) / 256;
+  double ra[QA], ru[QU];
+  auto fetch = [&](int64_t r0) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int rr = e % RS, cc = e / RS;
+      const int64_t rg = r0 + rr, cg = c0 + cc;
+      ra[q] = (rg < rend && cg < smax) ? V[rg + cg * k] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < QU; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      int rr, i;
+      if (LMAJ) { rr = e % RS; i = e / RS; } else { rr = e / NC; i = e % NC; }
+      const int64_t rg = r0 + rr;
+      double v = 0.0;
+      if (e < RS * NC && rg < rend && i < N)
+        v = LMAJ ? src[pr.offS * N + int64_t(i) * k + rg] : src[(pr.offS + rg) * N + i];
+      ru[q] = v;
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      Vs[e / RS][e % RS] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < QU; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (e < RS * NC) {
+        if (LMAJ) Xs[e % RS][e / RS] = ru[q];
+        else Xs[e / NC][e % NC] = ru[q];
+      }
+    }
+  };
+  if (rbeg < rend) {
+    fetch(rbeg);
+    stash();
+  }
+  __syncthreads();
+  for (int64_t r0 = rbeg; r0 < rend; r0 += RS) {
+    const bool more = r0 + RS < rend;
+    if (more) fetch(r0 + RS);
+#pragma unroll
+    for (int ks = 0; ks < RS / 4; ++ks) {
+      double a[2];
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) a[ct] = Vs[wv * 32 + ct * 16 + li][4 * ks + lk];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const double b = Xs[4 * ks + lk][nt * 16 + li];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+          acc[ct][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ct], b, acc[ct][nt], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    if (more) stash();
+    __syncthreads();
+  }
+  // result element (column 16 ct + 4 v + lane / 16 of the wave's 32, lambda 16 nt + lane % 16)
+  double* dst = part + pr.lrPart + int64_t(it.ch) * pr.s * N;
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t j = c0 + wv * 32 + ct * 16 + 4 * v + lk;
+        const int lam = nt * 16 + li;
+        if (j < smax && lam < N) dst[j * N + lam] = acc[ct][nt][v];
+      }
+}
+
+// coef[j, i] = S_i[j] sum_ch part[ch][j][i] (row-major smax x N per problem);
+// items: (problem, block of 256 entries).
+__global__ void __launch_bounds__(256) k_lr_coef(const DevProb* __restrict__ P,
+                                                 const Item* __restrict__ items, int N,
+                                                 const double* __restrict__ part,
+                                                 double* __restrict__ coef,
+                                                 const Scal* __restrict__ sc) {
+  const Item it = items[blockIdx.x];
+  const DevProb& pr = P[it.p];
+  const int64_t e = int64_t(it.blk) * 256 + threadIdx.x;
+  if (e >= pr.smax * N) return;
+  const int64_t j = e / N;
+  const int i = int(e % N);
+  double c = 0.0;
+  for (int ch = 0; ch < pr.lrNch; ++ch) c += part[pr.lrPart + (int64_t(ch) * pr.s + j) * N + i];
+  coef[pr.lrCoef + e] = c * pr.S[int64_t(sc[it.p * N + i].li) * pr.s + j];
+}
+
 static constexpr int LR_JC = 256;    // columns of V per expand block
 
 template <int NC>
 __global__ void __launch_bounds__(256) k_lr_expand(const DevProb* __restrict__ P,
                                                    const Item* __restrict__ items, int N,
-                                                   const double* __restrict__ part,
-                                                   double* __restrict__ opart,
-                                                   const Scal* __restrict__ sc) {
+                                                   const double* __restrict__ coef,
+                                                   double* __restrict__ opart) {
   __shared__ double cs[LR_JC * NC];
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
@@ -700,13 +830,7 @@ __global__ void __launch_bounds__(256) k_lr_expand(const DevProb* __restrict__ P
   const int jn = int(min<int64_t>(pr.smax - j0, LR_JC));
   for (int e = threadIdx.x; e < LR_JC * NC; e += 256) {
     const int jj = e / NC, i = e % NC;
-    double c = 0.0;
-    if (jj < jn && i < N) {
-      const int64_t j = j0 + jj;
-      for (int ch = 0; ch < pr.lrNch; ++ch) c += part[pr.lrPart + (int64_t(ch) * pr.s + j) * N + i];
-      c *= pr.S[int64_t(sc[it.p * N + i].li) * pr.s + j];
-    }
-    cs[e] = c;
+    cs[e] = (jj < jn && i < N) ? coef[pr.lrCoef + (j0 + jj) * N + i] : 0.0;
   }
   __syncthreads();
   const int64_t r = int64_t(it.blk) * 256 + threadIdx.x;
@@ -804,22 +928,34 @@ __global__ void __launch_bounds__(256) k_lr_fin(const DevProb* __restrict__ P,
 
 template <int NC>
 static int lr_apply_nc(int stage, int tall, const DevProb* P, const Item* itP, int nP,
-                       const Item* itE, int nE, const Item* itF, int nF, int N, const double* src,
-                       double* part, double* opart, double* q, double* v, double* w, double* x,
-                       double* e, const Scal* sc, double* pn, int init, hipStream_t st) {
+                       const Item* itC, int nC, const Item* itE, int nE, const Item* itF, int nF,
+                       int N, const double* src, double* part, double* coef, double* opart,
+                       double* q, double* v, double* w, double* x, double* e, const Scal* sc,
+                       double* pn, int init, hipStream_t st) {
   constexpr int CPW = NC >= 32 ? 2 : 4;
   if (nP > 0) {
-    if (stage == 0)   // t is stored lambda-major
+    // t (stage 0) is stored lambda-major, q (stage 1) row-major
+    if (NC >= 16) {
+      const dim3 g = dim3(unsigned(((nP + 7) / 8) * 8));
+      if (stage == 0)
+        hipLaunchKernelGGL((k_lr_proj_mfma<NC >= 16 ? NC : 16, true>), g, dim3(256), 0, st, P, itP, nP,
+                           N, src, part);
+      else
+        hipLaunchKernelGGL((k_lr_proj_mfma<NC >= 16 ? NC : 16, false>), g, dim3(256), 0, st, P, itP,
+                           nP, N, src, part);
+    } else if (stage == 0) {
       hipLaunchKernelGGL((k_lr_proj<NC, CPW, true>), dim3(unsigned(nP)), dim3(256), 0, st, P, itP, N,
                          src, part);
-    else
+    } else {
       hipLaunchKernelGGL((k_lr_proj<NC, CPW, false>), dim3(unsigned(nP)), dim3(256), 0, st, P, itP, N,
                          src, part);
+    }
     TIK_LAUNCHED("k_lr_proj");
+    hipLaunchKernelGGL(k_lr_coef, dim3(unsigned(nC)), dim3(256), 0, st, P, itC, N, part, coef, sc);
+    TIK_LAUNCHED("k_lr_coef");
   }
   if (nE > 0) {
-    hipLaunchKernelGGL(k_lr_expand<NC>, dim3(unsigned(nE)), dim3(256), 0, st, P, itE, N, part, opart,
-                       sc);
+    hipLaunchKernelGGL(k_lr_expand<NC>, dim3(unsigned(nE)), dim3(256), 0, st, P, itE, N, coef, opart);
     TIK_LAUNCHED("k_lr_expand");
   }
   if (nF > 0) {
@@ -843,15 +979,14 @@ static int lr_apply_nc(int stage, int tall, const DevProb* P, const Item* itP, i
   return TIK_OK;
 }
 
-int launch_lr_apply(int nc, int stage, int tall, const DevProb* P, const Item* itP, int nP,
-                    const Item* itE, int nE, const Item* itF, int nF, int N, const double* src,
-                    double* part, double* opart, double* q, double* v, double* w, double* x,
+int launch_lr_apply(int nc, int stage, int tall, const DevProb* P, const LrItems& it, int N,
+                    const double* src, const LrBufs& lb, double* q, double* v, double* w, double* x,
                     double* e, const Scal* sc, double* pn, int init, hipStream_t st) {
   switch (nc) {
-#define TIK_LR_CASE(C)                                                                          \
-  case C:                                                                                       \
-    return lr_apply_nc<C>(stage, tall, P, itP, nP, itE, nE, itF, nF, N, src, part, opart, q, v, \
-                          w, x, e, sc, pn, init, st);
+#define TIK_LR_CASE(NCV)                                                                         \
+  case NCV:                                                                                      \
+    return lr_apply_nc<NCV>(stage, tall, P, it.P, it.nP, it.C, it.nC, it.E, it.nE, it.F, it.nF, N, \
+                          src, lb.part, lb.coef, lb.opart, q, v, w, x, e, sc, pn, init, st);
     TIK_LR_CASE(1)
     TIK_LR_CASE(2)
     TIK_LR_CASE(4)

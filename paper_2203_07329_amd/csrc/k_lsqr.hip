@@ -916,13 +916,36 @@ namespace {
 
 // Item tables and partial-buffer sizes of the low-rank apply kernels.
 struct LrTables {
-  std::vector<Item> itLP, itLE, itLF;
-  int64_t totLP = 0, totLO = 0;
+  std::vector<Item> itLP, itLC, itLE, itLF;
+  int64_t totLP = 0, totLC = 0, totLO = 0;
   void clear() {
-    itLP.clear(); itLE.clear(); itLF.clear();
-    totLP = totLO = 0;
+    itLP.clear(); itLC.clear(); itLE.clear(); itLF.clear();
+    totLP = totLC = totLO = 0;
   }
 };
+
+// Device copies of one LrTables.
+struct LrDev {
+  Item *itLP, *itLC, *itLE, *itLF;
+  double *lpart, *lcoef, *lopart;
+};
+
+void take_lr(Arena& a, const LrTables& t, LrDev& d) {
+  d.itLP = a.take<Item>(t.itLP.size());
+  d.itLC = a.take<Item>(t.itLC.size());
+  d.itLE = a.take<Item>(t.itLE.size());
+  d.itLF = a.take<Item>(t.itLF.size());
+  d.lpart = a.take<double>(size_t(t.totLP));
+  d.lcoef = a.take<double>(size_t(t.totLC));
+  d.lopart = a.take<double>(size_t(t.totLO));
+}
+
+LrItems lr_items(const LrTables& t, const LrDev& d) {
+  return LrItems{d.itLP, d.itLC, d.itLE, d.itLF, int(t.itLP.size()), int(t.itLC.size()),
+                 int(t.itLE.size()), int(t.itLF.size())};
+}
+
+LrBufs lr_bufs(const LrDev& d) { return LrBufs{d.lpart, d.lcoef, d.lopart}; }
 
 // One set of (problem, lambda-range) solved together.
 struct Plan {
@@ -942,8 +965,7 @@ struct Plan {
 struct Bufs {
   DevProb* P;
   Item *itN, *itB, *itT, *itQ, *itR, *itM;
-  Item *itLP, *itLE, *itLF;
-  double *lpart, *lopart;
+  LrDev lr;
   Scal* sc;
   void* ut;
   double *ub, *v, *q, *w, *e, *x, *t;
@@ -977,7 +999,8 @@ int32_t lowrank_items(const tik_precond_s* pc, int p, int lp, const std::vector<
   d.S = pc->S[p];
   d.s = s;
   d.smax = smax;
-  const int cols = 4 * (NC >= 32 ? 2 : 4);                // columns per projection block
+  // columns per projection block: 128 on the matrix cores, 4 CPW otherwise
+  const int cols = NC >= 16 ? 128 : 4 * (NC >= 32 ? 2 : 4);
   const int64_t cbs = std::max<int64_t>(1, cdiv(s, cols));
   int64_t nch = std::max<int64_t>(1, std::min<int64_t>(1024 / cbs, cdiv(k, 64)));
   const int64_t rch = cdiv(cdiv(k, nch), 64) * 64;
@@ -986,11 +1009,14 @@ int32_t lowrank_items(const tik_precond_s* pc, int p, int lp, const std::vector<
   d.lrNch = int32_t(nch);
   d.lrNjc = int32_t(cdiv(smax, 256));
   d.lrPart = t.totLP;
+  d.lrCoef = t.totLC;
   d.lrOpart = t.totLO;
   t.totLP += nch * s * N;
+  t.totLC += s * N;
   t.totLO += cdiv(s, 256) * k * N;
   for (int64_t ch = 0; ch < nch; ++ch)
     for (int64_t jb = 0; jb < cdiv(smax, cols); ++jb) t.itLP.push_back({lp, int32_t(jb), int32_t(ch), 0});
+  for (int64_t cb = 0; cb < cdiv(smax * N, 256); ++cb) t.itLC.push_back({lp, int32_t(cb), 0, 0});
   for (int64_t jc = 0; jc < d.lrNjc; ++jc)
     for (int64_t rb = 0; rb < cdiv(k, 256); ++rb) t.itLE.push_back({lp, int32_t(rb), int32_t(jc), 0});
   const int64_t nf = cdiv(k, 256 / NC);
@@ -1083,11 +1109,7 @@ void take_bufs(Arena& a, const Plan& pl, size_t tc, Bufs& b) {
   b.itQ = a.take<Item>(pl.itQ.size());
   b.itR = a.take<Item>(pl.itR.size());
   b.itM = a.take<Item>(pl.itM.size());
-  b.itLP = a.take<Item>(pl.lr.itLP.size());
-  b.itLE = a.take<Item>(pl.lr.itLE.size());
-  b.itLF = a.take<Item>(pl.lr.itLF.size());
-  b.lpart = a.take<double>(size_t(pl.lr.totLP));
-  b.lopart = a.take<double>(size_t(pl.lr.totLO));
+  take_lr(a, pl.lr, b.lr);
   b.sc = a.take<Scal>(pl.J);
   b.ut = a.take<char>(size_t(pl.totL) * N * tc);
   b.ub = a.take<double>(size_t(pl.totS) * N);
@@ -1169,9 +1191,8 @@ int vec_steps_v(const Plan& pl, const Bufs& b, hipStream_t st, bool init, double
   }
   if (pl.lowrank) {
     ProfScope ps("lr_apply", st);
-    TIK_TRY(launch_lr_apply(pl.NC, 0, 1, b.P, b.itLP, int(pl.lr.itLP.size()), b.itLE,
-                            int(pl.lr.itLE.size()), b.itLF, int(pl.lr.itLF.size()), pl.N, b.t, b.lpart, b.lopart, b.q, b.v, b.w,
-                            b.x, b.e, b.sc, b.pnQ, init ? 1 : 0, st));
+    TIK_TRY(launch_lr_apply(pl.NC, 0, 1, b.P, lr_items(pl.lr, b.lr), pl.N, b.t, lr_bufs(b.lr),
+                            b.q, b.v, b.w, b.x, b.e, b.sc, b.pnQ, init ? 1 : 0, st));
   } else {
     ProfScope ps("trmv_t", st);
     if (pl.cpw == 16)
@@ -1190,9 +1211,8 @@ int vec_steps_v(const Plan& pl, const Bufs& b, hipStream_t st, bool init, double
   }
   if (pl.lowrank) {
     ProfScope ps("lr_apply", st);
-    TIK_TRY(launch_lr_apply(pl.NC, 1, 1, b.P, b.itLP, int(pl.lr.itLP.size()), b.itLE,
-                            int(pl.lr.itLE.size()), b.itLF, int(pl.lr.itLF.size()), pl.N, b.q, b.lpart, b.lopart, b.q, b.v, b.w,
-                            b.x, b.e, b.sc, b.pnQ, init ? 1 : 0, st));
+    TIK_TRY(launch_lr_apply(pl.NC, 1, 1, b.P, lr_items(pl.lr, b.lr), pl.N, b.q, lr_bufs(b.lr),
+                            b.q, b.v, b.w, b.x, b.e, b.sc, b.pnQ, init ? 1 : 0, st));
   } else {
     ProfScope ps("trmv", st);
     hipLaunchKernelGGL(k_trmv<false>, dim3(unsigned(pl.itM.size())), dim3(BLK), 0, st, b.P, b.itM,
@@ -1289,9 +1309,10 @@ int upload_plan(const Plan& pl, const Bufs& b, const tik_precond_s* pc, double* 
   TIK_TRY(upload(b.itR, stash(pl.itR.data(), pl.itR.size() * sizeof(Item)), pl.itR.size() * sizeof(Item), st));
   TIK_TRY(upload(b.itM, stash(pl.itM.data(), pl.itM.size() * sizeof(Item)), pl.itM.size() * sizeof(Item), st));
   const LrTables& lr = pl.lr;
-  TIK_TRY(upload(b.itLP, stash(lr.itLP.data(), lr.itLP.size() * sizeof(Item)), lr.itLP.size() * sizeof(Item), st));
-  TIK_TRY(upload(b.itLE, stash(lr.itLE.data(), lr.itLE.size() * sizeof(Item)), lr.itLE.size() * sizeof(Item), st));
-  TIK_TRY(upload(b.itLF, stash(lr.itLF.data(), lr.itLF.size() * sizeof(Item)), lr.itLF.size() * sizeof(Item), st));
+  TIK_TRY(upload(b.lr.itLP, stash(lr.itLP.data(), lr.itLP.size() * sizeof(Item)), lr.itLP.size() * sizeof(Item), st));
+  TIK_TRY(upload(b.lr.itLC, stash(lr.itLC.data(), lr.itLC.size() * sizeof(Item)), lr.itLC.size() * sizeof(Item), st));
+  TIK_TRY(upload(b.lr.itLE, stash(lr.itLE.data(), lr.itLE.size() * sizeof(Item)), lr.itLE.size() * sizeof(Item), st));
+  TIK_TRY(upload(b.lr.itLF, stash(lr.itLF.data(), lr.itLF.size() * sizeof(Item)), lr.itLF.size() * sizeof(Item), st));
   std::vector<double> lams(pl.J);
   std::vector<int32_t> pre(pl.J), jmap(pl.J), lidx(pl.J);
   std::vector<double*> xp(pl.P.size());
@@ -1801,8 +1822,7 @@ struct WPlan {
 struct WBufs {
   DevProb* P;
   Item *itNs, *itT, *itQ, *itM, *itR, *itV, *itH;
-  Item *itLP, *itLE, *itLF;
-  double *lpart, *lopart;
+  LrDev lr;
   Scal* sc;
   void *partN, *partT;
   double *vt, *dt, *xt, *u, *q, *y, *vb, *db, *zb, *t, *pnN, *pnQ;
@@ -1897,11 +1917,7 @@ void take_wbufs(Arena& a, const WPlan& pl, size_t tc, WBufs& b) {
   b.itR = a.take<Item>(pl.itR.size());
   b.itV = a.take<Item>(pl.itV.size());
   b.itH = a.take<Item>(pl.itH.size());
-  b.itLP = a.take<Item>(pl.lr.itLP.size());
-  b.itLE = a.take<Item>(pl.lr.itLE.size());
-  b.itLF = a.take<Item>(pl.lr.itLF.size());
-  b.lpart = a.take<double>(size_t(pl.lr.totLP));
-  b.lopart = a.take<double>(size_t(pl.lr.totLO));
+  take_lr(a, pl.lr, b.lr);
   b.sc = a.take<Scal>(pl.J);
   b.partN = a.take<char>(size_t(pl.totPN) * N * tc);
   b.partT = a.take<char>(size_t(pl.totPT) * N * tc);
@@ -1941,9 +1957,10 @@ int upload_wplan(const WPlan& pl, const WBufs& b, const tik_precond_s* pc, doubl
   TIK_TRY(put(b.itR, pl.itR.data(), pl.itR.size() * sizeof(Item)));
   TIK_TRY(put(b.itV, pl.itV.data(), pl.itV.size() * sizeof(Item)));
   TIK_TRY(put(b.itH, pl.itH.data(), pl.itH.size() * sizeof(Item)));
-  TIK_TRY(put(b.itLP, pl.lr.itLP.data(), pl.lr.itLP.size() * sizeof(Item)));
-  TIK_TRY(put(b.itLE, pl.lr.itLE.data(), pl.lr.itLE.size() * sizeof(Item)));
-  TIK_TRY(put(b.itLF, pl.lr.itLF.data(), pl.lr.itLF.size() * sizeof(Item)));
+  TIK_TRY(put(b.lr.itLP, pl.lr.itLP.data(), pl.lr.itLP.size() * sizeof(Item)));
+  TIK_TRY(put(b.lr.itLC, pl.lr.itLC.data(), pl.lr.itLC.size() * sizeof(Item)));
+  TIK_TRY(put(b.lr.itLE, pl.lr.itLE.data(), pl.lr.itLE.size() * sizeof(Item)));
+  TIK_TRY(put(b.lr.itLF, pl.lr.itLF.data(), pl.lr.itLF.size() * sizeof(Item)));
   std::vector<double> lams(pl.J);
   std::vector<int32_t> pre(pl.J), jmap(pl.J), lidx(pl.J);
   std::vector<double*> xp(pl.P.size());
@@ -2005,9 +2022,8 @@ template <typename TA, typename TC, int NC>
 int wide_v_steps(const WPlan& pl, const WBufs& b, hipStream_t st, bool init, double tol, int maxit) {
   if (pl.lowrank) {
     ProfScope ps("lr_apply", st);
-    TIK_TRY(launch_lr_apply(pl.NC, 1, 0, b.P, b.itLP, int(pl.lr.itLP.size()), b.itLE,
-                            int(pl.lr.itLE.size()), b.itLF, int(pl.lr.itLF.size()), pl.N, b.q,
-                            b.lpart, b.lopart, b.q, b.u, b.y, nullptr, nullptr, b.sc, nullptr, 0, st));
+    TIK_TRY(launch_lr_apply(pl.NC, 1, 0, b.P, lr_items(pl.lr, b.lr), pl.N, b.q, lr_bufs(b.lr),
+                            b.q, b.u, b.y, nullptr, nullptr, b.sc, nullptr, 0, st));
   } else {
     ProfScope ps("trmv", st);
     hipLaunchKernelGGL(k_trmv<true>, dim3(unsigned(pl.itM.size())), dim3(BLK), 0, st, b.P, b.itM,
@@ -2042,10 +2058,8 @@ int wide_u_tr(const WPlan& pl, const WBufs& b, hipStream_t st) {
 int wide_u_steps(const WPlan& pl, const WBufs& b, hipStream_t st, bool init) {
   if (pl.lowrank) {
     ProfScope ps("lr_apply", st);
-    TIK_TRY(launch_lr_apply(pl.NC, 0, 0, b.P, b.itLP, int(pl.lr.itLP.size()), b.itLE,
-                            int(pl.lr.itLE.size()), b.itLF, int(pl.lr.itLF.size()), pl.N, b.t,
-                            b.lpart, b.lopart, b.q, b.u, nullptr, nullptr, nullptr, b.sc, b.pnN, 0,
-                            st));
+    TIK_TRY(launch_lr_apply(pl.NC, 0, 0, b.P, lr_items(pl.lr, b.lr), pl.N, b.t, lr_bufs(b.lr),
+                            b.q, b.u, nullptr, nullptr, nullptr, b.sc, b.pnN, 0, st));
   } else {
     ProfScope ps("trmv_t", st);
     TIK_TRY(pl.cpw == 16 ? wide_u_tr<16>(pl, b, st) : wide_u_tr<4>(pl, b, st));

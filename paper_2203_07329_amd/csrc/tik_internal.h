@@ -92,6 +92,7 @@ struct DevProb {
   int64_t s, smax;
   int64_t lrPart;      // offset of this problem in the projection partials (chunks x s x N)
   int64_t lrOpart;     // offset in the expansion partials (column chunks x N x k)
+  int64_t lrCoef;      // offset in the scaled projections (smax x N, row-major)
   int64_t lrRch;       // rows of V per projection chunk
   int32_t lrNch;       // projection row chunks
   int32_t lrNjc;       // expansion column chunks in use (ceil(smax / 256))
@@ -165,9 +166,15 @@ int launch_lowrank_svd(const double* Y, int64_t s, int64_t n, double* V, double*
                        hipStream_t st);
 int launch_lowrank_S(const double* sig, int64_t s, const double* lams, const int32_t* si, int N,
                      double* S, hipStream_t st);
-int launch_lr_apply(int nc, int stage, int tall, const DevProb* P, const Item* itP, int nP,
-                    const Item* itE, int nE, const Item* itF, int nF, int N, const double* src,
-                    double* part, double* opart, double* q, double* v, double* w, double* x,
+struct LrItems {      // device item tables of the low-rank apply and their lengths
+  const Item *P, *C, *E, *F;
+  int nP, nC, nE, nF;
+};
+struct LrBufs {       // projection partials, scaled projections, expansion partials
+  double *part, *coef, *opart;
+};
+int launch_lr_apply(int nc, int stage, int tall, const DevProb* P, const LrItems& it, int N,
+                    const double* src, const LrBufs& lb, double* q, double* v, double* w, double* x,
                     double* e, const Scal* sc, double* pn, int init, hipStream_t st);
 }  // namespace tik
 
