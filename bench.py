@@ -88,6 +88,26 @@ def build_workload(name, tik, W, dev):
     return plist, cfg
 
 
+MAXIT = 300
+
+
+def pick_mode(tik, pr, cfg, svec, lams, alpha, want):
+    """(mode, LSQR tol) of the timed batched solve: mixed where the library offers it."""
+    mode = tik.F64_BATCHED
+    if want in ("auto", "mixed"):
+        try:
+            sk = tik.sketch(pr, cfg["embed"], svec, 0, sketch_dtype=cfg["sdt"])
+            pc = tik.precond(sk, lams, cfg["route"], alpha)
+            tik.Solver(pr, pc, tik.MIXED_BATCHED)
+            mode = tik.MIXED_BATCHED
+            del sk, pc
+        except tik.TikError as e:
+            if want == "mixed":
+                raise
+            log("mixed mode unavailable, timing FP64 batched:", e)
+    return mode, (1e-11 if mode == tik.F64_BATCHED else 1e-8)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,21 +148,9 @@ def main() -> int:
         pc = tik.precond(sk, lams, cfg["route"], alpha)
         return tik.Solver(pr, pc, m_)(tol, maxit)
 
-    want = args.mode or cfg["mode"]
-    mode, dtype = tik.F64_BATCHED, "f64"
-    if want in ("auto", "mixed"):
-        try:
-            sk = tik.sketch(pr, cfg["embed"], svec, 0, sketch_dtype=cfg["sdt"])
-            pc = tik.precond(sk, lams, cfg["route"], alpha)
-            tik.Solver(pr, pc, tik.MIXED_BATCHED)
-            mode, dtype = tik.MIXED_BATCHED, "f32+f64"
-            del sk, pc
-        except tik.TikError as e:
-            if want == "mixed":
-                raise
-            log("mixed mode unavailable, timing FP64 batched:", e)
-    tol = 1e-11 if mode == tik.F64_BATCHED else 1e-8
-    maxit = 300
+    mode, tol = pick_mode(tik, pr, cfg, svec, lams, alpha, args.mode or cfg["mode"])
+    dtype = "f32+f64" if mode == tik.MIXED_BATCHED else "f64"
+    maxit = MAXIT
 
     # ---- warmup
     for _ in range(args.warmup):
