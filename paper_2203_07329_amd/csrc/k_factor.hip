@@ -24,53 +24,105 @@ namespace tik {
 
 static constexpr int NB = 64;
 
+// ------------------------------------------------- 64 x 64 FP64 MFMA tiles --
+// acc += op(A) B for one 64 x 64 output tile on the matrix cores
+// (v_mfma_f64_16x16x4_f64).  op(A) is 64 x K: A itself (TA = false, element
+// (i, k) at A[i + k lda]) or the transpose of a K x 64 block (TA = true,
+// element (i, k) at A[k + i lda]); B is K x 64 (element (k, j) at
+// B[k + j ldb]).  Rows >= mrows, columns >= ncols and k >= K read as zero.
+// Wave w owns the 32 x 32 quarter (rows 32 (w & 1), columns 32 (w >> 1)) as
+// 2 x 2 MFMA tiles; K is staged through LDS 32 at a time.  Result element
+// (row 32 (w & 1) + 16 t + 4 v + lane / 16, column 32 (w >> 1) + 16 u +
+// lane % 16) is acc[t][u][v].
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+static constexpr int TK = 32;
+
+struct TileLds {
+  double As[64][TK + 1];
+  double Bs[TK][64 + 1];
+};
+
+template <bool TA>
+__device__ __forceinline__ void tile_mma(const double* __restrict__ A, int64_t lda,
+                                         const double* __restrict__ B, int64_t ldb, int64_t K,
+                                         int mrows, int ncols, TileLds& L, f64x4 (&acc)[2][2]) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr = 32 * (wv & 1), wc = 32 * (wv >> 1);
+  for (int64_t k0 = 0; k0 < K; k0 += TK) {
+    for (int e = tid; e < 64 * TK; e += 256) {
+      int i, kk;
+      if (TA) { kk = e % TK; i = e / TK; } else { i = e % 64; kk = e / 64; }
+      const int64_t k = k0 + kk;
+      double v = 0.0;
+      if (i < mrows && k < K) v = TA ? A[k + int64_t(i) * lda] : A[i + k * lda];
+      L.As[i][kk] = v;
+    }
+    for (int e = tid; e < TK * 64; e += 256) {
+      const int kk = e % TK, j = e / TK;
+      const int64_t k = k0 + kk;
+      L.Bs[kk][j] = (j < ncols && k < K) ? B[k + int64_t(j) * ldb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) a[t] = L.As[wr + 16 * t + li][kk + lk];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) b[u] = L.Bs[kk + lk][wc + 16 * u + li];
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+}
+
+// Visit the tile's elements: f(row, col, value) for the 64 x 64 result.
+template <typename F>
+__device__ __forceinline__ void tile_for_each(const f64x4 (&acc)[2][2], F f) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wr = 32 * (wv & 1), wc = 32 * (wv >> 1);
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        f(wr + 16 * t + 4 * v + (lane >> 4), wc + 16 * u + (lane & 15), acc[t][u][v]);
+}
+
+__device__ __forceinline__ void tile_zero(f64x4 (&acc)[2][2]) {
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) acc[t][u] = f64x4{0, 0, 0, 0};
+}
+
 // ---------------------------------------------------------------- Gram ------
-// C (n x n, ld n) = Z^T Z with Z K x n column-major (ld ldz).  Upper tile pairs
-// are computed and written to both triangles.
+// C (n x n, ld n) = Z^T Z with Z K x n column-major (ld ldz), on the matrix
+// cores.  Upper tile pairs are computed and written to both triangles.
 __global__ void __launch_bounds__(256) k_syrk(const double* __restrict__ Z, int64_t K, int64_t n,
                                               int64_t ldz, double* __restrict__ C, int nt) {
+  __shared__ TileLds L;
   // map blockIdx.x to tile pair (ti <= tj)
   int t = blockIdx.x, ti = 0;
   while (t >= nt - ti) { t -= nt - ti; ++ti; }
   const int tj = ti + t;
-  __shared__ double Za[16][64 + 1];
-  __shared__ double Zb[16][64 + 1];
-  const int tid = threadIdx.x;
-  const int ta = tid & 15, tb = tid >> 4;
   const int64_t a0 = int64_t(ti) * 64, b0 = int64_t(tj) * 64;
-  double acc[4][4] = {};
-  for (int64_t k0 = 0; k0 < K; k0 += 16) {
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int kk = e & 15, cc = e >> 4;
-      const int64_t kg = k0 + kk;
-      Za[kk][cc] = (kg < K && a0 + cc < n) ? Z[kg + (a0 + cc) * ldz] : 0.0;
-      Zb[kk][cc] = (kg < K && b0 + cc < n) ? Z[kg + (b0 + cc) * ldz] : 0.0;
+  const int na = int(min<int64_t>(64, n - a0)), nb = int(min<int64_t>(64, n - b0));
+  f64x4 acc[2][2];
+  tile_zero(acc);
+  tile_mma<true>(Z + a0 * ldz, ldz, Z + b0 * ldz, ldz, K, na, nb, L, acc);
+  tile_for_each(acc, [&](int i, int j, double v) {
+    if (i < na && j < nb) {
+      C[(a0 + i) + (b0 + j) * n] = v;
+      C[(b0 + j) + (a0 + i) * n] = v;
     }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double x[4], y[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) x[i] = Za[kk][ta + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) y[j] = Zb[kk][tb + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(x[i], y[j], acc[i][j]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t a = a0 + ta + 16 * i, b = b0 + tb + 16 * j;
-      if (a < n && b < n) {
-        C[a + b * n] = acc[i][j];
-        C[b + a * n] = acc[i][j];
-      }
-    }
+  });
 }
 
 // ----------------------------------------------------- shifted copies -------
@@ -88,112 +140,155 @@ __global__ void k_shift_copy(const double* __restrict__ C, int64_t n, const doub
 }
 
 // --------------------------------------------- diagonal block: factor+invert --
+// One 64 x 64 diagonal block per matrix.  Thread (ti, tj) = (tid % 16,
+// tid / 16) keeps the elements (ti + 16 p, tj + 16 q), p, q < 4, in registers:
+// the strided ownership keeps every thread busy while the active corner
+// shrinks.  Factorization in the right-looking LDL^T form: at step k the
+// owners of row k publish it (double-buffered LDS), one barrier, then every
+// thread updates a_ij -= a_ki a_kj / a_kk for k < i <= j; afterwards
+// R[i][j] = a_ij / sqrt(a_ii).  The inverse X = R^{-1} by back substitution
+// on B = I, last row first: the owners of row k of B publish X[k][.] =
+// B[k][.] / R[k][k] and the owners of column k of R publish it, one barrier,
+// then B[i][j] -= R[i][k] X[k][j] for i < k <= j.  The step loops are split
+// into 4 unrolled blocks of 16 so that the register index is a constant.
 __global__ void __launch_bounds__(256) k_potrf_diag(double* __restrict__ R, int64_t n, int64_t k0,
                                                     double* __restrict__ Dinv, int32_t* notpd) {
   const int64_t mat = blockIdx.x;
   double* Rm = R + mat * n * n;
   const int kb = int(min<int64_t>(NB, n - k0));
-  __shared__ double Am[NB][NB + 1];
-  __shared__ double Ai[NB][NB + 1];
+  __shared__ double rowb[2][NB];
+  __shared__ double colb[2][NB];
+  __shared__ double diag[NB];
   __shared__ int bad;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, ti = tid & 15, tj = tid >> 4;
+  double a[4][4], b[4][4];
   if (tid == 0) bad = 0;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e % NB, j = e / NB;
-    Am[i][j] = (i < kb && j < kb && i <= j) ? Rm[(k0 + i) + (k0 + j) * n] : 0.0;
-    Ai[i][j] = 0.0;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ti + 16 * p, j = tj + 16 * q;
+      a[p][q] = (i < kb && j < kb && i <= j) ? Rm[(k0 + i) + (k0 + j) * n] : 0.0;
+      b[p][q] = (i == j && i < kb) ? 1.0 : 0.0;
+    }
+  // factorization
+#pragma unroll
+  for (int P = 0; P < 4; ++P) {
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 16 * P + kk;
+      if (k >= kb) break;
+      const int buf = k & 1;
+      if (ti == kk) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rowb[buf][tj + 16 * q] = a[P][q];
+      }
+      __syncthreads();
+      double d = rowb[buf][k];
+      if (!(d > 0.0) || !isfinite(d)) d = 1.0;     // flagged below; keeps the rest finite
+      const double inv = 1.0 / d;
+      double ri[4], rj[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) ri[p] = rowb[buf][ti + 16 * p] * inv;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rj[q] = rowb[buf][tj + 16 * q];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = ti + 16 * p, j = tj + 16 * q;
+          if (i > k && i <= j && j < kb) a[p][q] -= ri[p] * rj[q];
+        }
+    }
+  }
+  // pivots: sqrt(a_ii), breakdown flag
+  if (ti == tj) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int i = ti + 16 * p;
+      if (i < kb) {
+        double d = a[p][p];
+        if (!(d > 0.0) || !isfinite(d)) {
+          bad = 1;
+          d = 1.0;
+        }
+        diag[i] = sqrt(d);
+      }
+    }
   }
   __syncthreads();
-  for (int k = 0; k < kb; ++k) {
-    if (tid == 0) {
-      double d = Am[k][k];
-      if (!(d > 0.0) || !isfinite(d)) {
-        bad = 1;
-        d = 1.0;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ti + 16 * p, j = tj + 16 * q;
+      double v = 0.0;
+      if (i < kb && j < kb && i <= j) v = (i == j) ? diag[i] : a[p][q] / diag[i];
+      a[p][q] = v;
+      if (i < kb && j < kb) Rm[(k0 + i) + (k0 + j) * n] = v;
+    }
+  // inverse
+#pragma unroll
+  for (int P = 3; P >= 0; --P) {
+    for (int kk = 15; kk >= 0; --kk) {
+      const int k = 16 * P + kk;
+      if (k >= kb || k == 0) continue;
+      const int buf = k & 1;
+      if (ti == kk) {
+        const double rk = 1.0 / diag[k];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rowb[buf][tj + 16 * q] = b[P][q] * rk;
       }
-      Am[k][k] = sqrt(d);
+      if (tj == kk) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) colb[buf][ti + 16 * p] = a[p][P];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = ti + 16 * p, j = tj + 16 * q;
+          if (i < k && j >= k && j < kb) b[p][q] -= colb[buf][i] * rowb[buf][j];
+        }
     }
-    __syncthreads();
-    const double piv = Am[k][k];
-    for (int j = k + 1 + tid; j < kb; j += 256) Am[k][j] /= piv;
-    __syncthreads();
-    const int rem = kb - k - 1;
-    for (int e = tid; e < rem * rem; e += 256) {
-      const int i = k + 1 + e % rem, j = k + 1 + e / rem;
-      if (i <= j) Am[i][j] -= Am[k][i] * Am[k][j];
-    }
-    __syncthreads();
-  }
-  // inverse of the upper-triangular block, column by column
-  for (int j = 0; j < kb; ++j) {
-    const double djj = Am[j][j];
-    if (tid < j) {
-      const int i = tid;
-      double s = 0.0;
-      for (int t = i; t < j; ++t) s += Ai[i][t] * Am[t][j];
-      Ai[i][j] = -s / djj;
-    } else if (tid == j) {
-      Ai[j][j] = 1.0 / djj;
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < kb * kb; e += 256) {
-    const int i = e % kb, j = e / kb;
-    Rm[(k0 + i) + (k0 + j) * n] = (i <= j) ? Am[i][j] : 0.0;
   }
   double* D = Dinv + (mat * cdiv(n, NB) + k0 / NB) * NB * NB;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e % NB, j = e / NB;
-    D[e] = (i < kb && j < kb) ? Ai[i][j] : 0.0;
-  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ti + 16 * p, j = tj + 16 * q;
+      D[i + j * NB] = (i < kb && j < kb && i <= j) ? b[p][q] / diag[i] : 0.0;
+    }
+  __syncthreads();
   if (tid == 0 && bad) notpd[mat] = 1;
 }
 
 // R[k0:k0+kb, cols] = D^T R[k0:k0+kb, cols] for the 64-column tile blockIdx.x
-// right of the diagonal block (D = inverse of the diagonal block).
+// right of the diagonal block (D = inverse of the diagonal block).  In place:
+// the tile is read completely before it is written.
 __global__ void __launch_bounds__(256) k_trsm_panel(double* __restrict__ R, int64_t n, int64_t k0,
                                                     const double* __restrict__ Dinv) {
+  __shared__ TileLds L;
   const int64_t mat = blockIdx.y;
   double* Rm = R + mat * n * n;
   const int kb = int(min<int64_t>(NB, n - k0));
   const int64_t c0 = k0 + kb + int64_t(blockIdx.x) * 64;
-  __shared__ double D[NB][NB + 1];
-  __shared__ double P[NB][64 + 1];
-  const int tid = threadIdx.x;
+  const int nc = int(min<int64_t>(64, n - c0));
   const double* Dm = Dinv + (mat * cdiv(n, NB) + k0 / NB) * NB * NB;
-  for (int e = tid; e < NB * NB; e += 256) D[e % NB][e / NB] = Dm[e];
-  for (int e = tid; e < NB * 64; e += 256) {
-    const int i = e % NB, c = e / NB;
-    P[i][c] = (i < kb && c0 + c < n) ? Rm[(k0 + i) + (c0 + c) * n] : 0.0;
-  }
-  __syncthreads();
-  const int ti = tid & 15, tc = tid >> 4;
-  double acc[4][4] = {};
-  for (int t = 0; t < kb; ++t) {
-    double d[4], p[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) d[a] = D[t][ti + 16 * a];   // (D^T)[i][t] = D[t][i]
-#pragma unroll
-    for (int b = 0; b < 4; ++b) p[b] = P[t][tc + 16 * b];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = fma(d[a], p[b], acc[a][b]);
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = ti + 16 * a;
-      const int64_t c = c0 + tc + 16 * b;
-      if (i < kb && c < n) Rm[(k0 + i) + c * n] = acc[a][b];
-    }
+  f64x4 acc[2][2];
+  tile_zero(acc);
+  tile_mma<true>(Dm, NB, Rm + k0 + c0 * n, n, kb, kb, nc, L, acc);
+  tile_for_each(acc, [&](int i, int c, double v) {
+    if (i < kb && c < nc) Rm[(k0 + i) + (c0 + c) * n] = v;
+  });
 }
 
 // Trailing update of the upper tiles: R[a, b] -= R[k, a]^T R[k, b] over the
 // panel rows k (tile pair blockIdx.x, a <= b, tiles counted from k0 + kb).
 __global__ void __launch_bounds__(256) k_syrk_trail(double* __restrict__ R, int64_t n, int64_t k0,
                                                     int nt) {
+  __shared__ TileLds L;
   const int64_t mat = blockIdx.y;
   double* Rm = R + mat * n * n;
   const int kb = int(min<int64_t>(NB, n - k0));
@@ -202,85 +297,33 @@ __global__ void __launch_bounds__(256) k_syrk_trail(double* __restrict__ R, int6
   const int tb = ta + t;
   const int64_t base = k0 + kb;
   const int64_t a0 = base + int64_t(ta) * 64, b0 = base + int64_t(tb) * 64;
-  __shared__ double Pa[NB][64 + 1];
-  __shared__ double Pb[NB][64 + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < NB * 64; e += 256) {
-    const int i = e % NB, c = e / NB;
-    Pa[i][c] = (i < kb && a0 + c < n) ? Rm[(k0 + i) + (a0 + c) * n] : 0.0;
-    Pb[i][c] = (i < kb && b0 + c < n) ? Rm[(k0 + i) + (b0 + c) * n] : 0.0;
-  }
-  __syncthreads();
-  const int tx = tid & 15, ty = tid >> 4;
-  double acc[4][4] = {};
-  for (int k = 0; k < kb; ++k) {
-    double x[4], y[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) x[i] = Pa[k][tx + 16 * i];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) y[j] = Pb[k][ty + 16 * j];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = fma(x[i], y[j], acc[i][j]);
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t a = a0 + tx + 16 * i, b = b0 + ty + 16 * j;
-      if (a < n && b < n) Rm[a + b * n] -= acc[i][j];
-    }
+  const int na = int(min<int64_t>(64, n - a0)), nb = int(min<int64_t>(64, n - b0));
+  f64x4 acc[2][2];
+  tile_zero(acc);
+  tile_mma<true>(Rm + k0 + a0 * n, n, Rm + k0 + b0 * n, n, kb, na, nb, L, acc);
+  tile_for_each(acc, [&](int i, int j, double v) {
+    if (i < na && j < nb) Rm[(a0 + i) + (b0 + j) * n] -= v;
+  });
 }
 
 // Tmp[rows of tile blockIdx.x, 0:lb] = Rinv[rows, 0:l0] R[0:l0, l0:l0+lb]
-// (Rinv upper triangular, already stored in columns < l0).
+// (Rinv upper triangular, already stored in columns < l0 with zeros below the
+// diagonal, so the contraction starts at the tile's first row).
 __global__ void __launch_bounds__(256) k_trinv_mul(const double* __restrict__ R, int64_t n,
                                                    int64_t l0, double* __restrict__ Tmp) {
+  __shared__ TileLds L;
   const int64_t mat = blockIdx.y;
   const double* Rm = R + mat * n * n;
   const int lb = int(min<int64_t>(NB, n - l0));
   const int64_t r0 = int64_t(blockIdx.x) * 64;
-  __shared__ double Ri[64][16 + 1];
-  __shared__ double Rb[16][NB + 1];
-  const int tid = threadIdx.x;
-  const int tr = tid & 15, tc = tid >> 4;
-  double acc[4][4] = {};
-  for (int64_t k0 = r0; k0 < l0; k0 += 16) {
-    for (int e = tid; e < 64 * 16; e += 256) {
-      const int i = e & 63, kk = e >> 6;
-      const int64_t r = r0 + i, k = k0 + kk;
-      Ri[i][kk] = (r < l0 && k < l0) ? Rm[r + k * n] : 0.0;
-    }
-    for (int e = tid; e < 16 * NB; e += 256) {
-      const int kk = e & 15, c = e >> 4;
-      const int64_t k = k0 + kk;
-      Rb[kk][c] = (k < l0 && c < lb) ? Rm[k + (l0 + c) * n] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double x[4], y[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) x[i] = Ri[tr + 16 * i][kk];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) y[j] = Rb[kk][tc + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(x[i], y[j], acc[i][j]);
-    }
-    __syncthreads();
-  }
+  const int nr = int(min<int64_t>(64, l0 - r0));
+  f64x4 acc[2][2];
+  tile_zero(acc);
+  tile_mma<false>(Rm + r0 + r0 * n, n, Rm + r0 + l0 * n, n, l0 - r0, nr, lb, L, acc);
   double* Tm = Tmp + mat * n * NB;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t r = r0 + tr + 16 * i;
-      const int c = tc + 16 * j;
-      if (r < l0 && c < lb) Tm[r + int64_t(c) * n] = acc[i][j];
-    }
+  tile_for_each(acc, [&](int i, int c, double v) {
+    if (i < nr && c < lb) Tm[(r0 + i) + int64_t(c) * n] = v;
+  });
 }
 
 // Block column l of Rinv: rows above the diagonal block get -Tmp D_l, the
@@ -288,6 +331,7 @@ __global__ void __launch_bounds__(256) k_trinv_mul(const double* __restrict__ R,
 __global__ void __launch_bounds__(256) k_trinv_fin(double* __restrict__ R, int64_t n, int64_t l0,
                                                    const double* __restrict__ Tmp,
                                                    const double* __restrict__ Dinv) {
+  __shared__ TileLds L;
   const int64_t mat = blockIdx.y;
   double* Rm = R + mat * n * n;
   const int lb = int(min<int64_t>(NB, n - l0));
@@ -307,37 +351,14 @@ __global__ void __launch_bounds__(256) k_trinv_fin(double* __restrict__ R, int64
     }
     return;
   }
-  __shared__ double Tt[64][NB + 1];
-  __shared__ double D[NB][NB + 1];
   const double* Tm = Tmp + mat * n * NB;
-  for (int e = tid; e < 64 * NB; e += 256) {
-    const int i = e & 63, c = e >> 6;
-    const int64_t r = r0 + i;
-    Tt[i][c] = (r < l0 && c < lb) ? Tm[r + int64_t(c) * n] : 0.0;
-  }
-  for (int e = tid; e < NB * NB; e += 256) D[e % NB][e / NB] = Dm[e];
-  __syncthreads();
-  const int tr = tid & 15, tc = tid >> 4;
-  double acc[4][4] = {};
-  for (int t = 0; t < lb; ++t) {
-    double x[4], y[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) x[i] = Tt[tr + 16 * i][t];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) y[j] = D[t][tc + 16 * j];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = fma(x[i], y[j], acc[i][j]);
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t r = r0 + tr + 16 * i;
-      const int c = tc + 16 * j;
-      if (r < l0 && c < lb) Rm[r + (l0 + c) * n] = -acc[i][j];
-    }
+  const int nr = int(min<int64_t>(64, l0 - r0));
+  f64x4 acc[2][2];
+  tile_zero(acc);
+  tile_mma<false>(Tm + r0, n, Dm, NB, lb, nr, lb, L, acc);
+  tile_for_each(acc, [&](int i, int c, double v) {
+    if (i < nr && c < lb) Rm[(r0 + i) + (l0 + c) * n] = -v;
+  });
 }
 
 // Column absolute sums of the symmetric Gram matrix C (k x k): their maximum

@@ -1030,8 +1030,8 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
   const int N = int(lsel.size());
   pl.N = N;
   pl.NC = pick_nc(N);
-  pl.rbN = pl.NC >= 8 ? 256 : 64;
-  pl.cpw = pl.NC >= 8 ? 16 : 4;
+  pl.rbN = pl.NC >= 16 ? 128 : pl.NC >= 8 ? 256 : 64;   // rows per gemm_n block
+  pl.cpw = 4;          // columns per wave in R^{-T} t: low registers, high occupancy
   pl.cbT = pl.NC >= 16 ? 128 : 64;
   pl.pidx = pidx;
   pl.lsel = lsel;
@@ -1097,6 +1097,15 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
     pl.nbQ += d.nblkQ;
     pl.P.push_back(d);
   }
+  // The triangular products' blocks differ in length (block b of R^{-T} t reads
+  // (b + 1) blocks of rows, row block b of R^{-1} q reads k - 16 b columns):
+  // dispatch the longest first so the short ones fill the tail.
+  auto q_work = [&](const Item& it) { return (int64_t(it.blk) + 1) * 4 * pl.cpw; };
+  auto m_work = [&](const Item& it) { return pl.P[size_t(it.p)].k - 16 * int64_t(it.blk); };
+  std::stable_sort(pl.itQ.begin(), pl.itQ.end(),
+                   [&](const Item& a, const Item& b) { return q_work(a) > q_work(b); });
+  std::stable_sort(pl.itM.begin(), pl.itM.end(),
+                   [&](const Item& a, const Item& b) { return m_work(a) > m_work(b); });
   pl.J = np * N;
 }
 
@@ -1839,8 +1848,8 @@ void make_plan_wide(const tik_problem* probs, const tik_precond_s* pc, const std
   pl = WPlan();
   pl.N = N;
   pl.NC = pick_nc(N);
-  pl.rbN = pl.NC >= 8 ? 256 : 64;
-  pl.cpw = pl.NC >= 8 ? 16 : 4;
+  pl.rbN = pl.NC >= 16 ? 128 : pl.NC >= 8 ? 256 : 64;   // rows per gemm_n block
+  pl.cpw = 4;          // columns per wave in R^{-T} t: low registers, high occupancy
   pl.cbT = pl.NC >= 16 ? 128 : 64;
   pl.pidx = pidx;
   pl.lsel = lsel;
@@ -1904,6 +1913,15 @@ void make_plan_wide(const tik_problem* probs, const tik_precond_s* pc, const std
     pl.nbQ += d.nblkQ;
     pl.P.push_back(d);
   }
+  // The triangular products' blocks differ in length (block b of R^{-T} t reads
+  // (b + 1) blocks of rows, row block b of R^{-1} q reads k - 16 b columns):
+  // dispatch the longest first so the short ones fill the tail.
+  auto q_work = [&](const Item& it) { return (int64_t(it.blk) + 1) * 4 * pl.cpw; };
+  auto m_work = [&](const Item& it) { return pl.P[size_t(it.p)].k - 16 * int64_t(it.blk); };
+  std::stable_sort(pl.itQ.begin(), pl.itQ.end(),
+                   [&](const Item& a, const Item& b) { return q_work(a) > q_work(b); });
+  std::stable_sort(pl.itM.begin(), pl.itM.end(),
+                   [&](const Item& a, const Item& b) { return m_work(a) > m_work(b); });
   pl.J = np * N;
 }
 

@@ -36,11 +36,17 @@ struct Mfma<float> {
 };
 
 // ------------------------------------------------------------------ gemm_n --
-// Block = 4 waves x 64 rows = 256 rows of one problem, all NC lambdas.  A is
-// read straight into A-operand registers (16 consecutive rows of 4 columns per
-// load: whole 64/128-byte lines); W is staged through LDS KC columns at a time.
+// Block = 4 waves x 16 RT rows = GN_ROWS rows of one problem, all NC lambdas.
+// A is read straight into A-operand registers (16 consecutive rows of 4
+// columns per load: whole 64/128-byte lines); W is staged through LDS KC
+// columns at a time.  RT = 2 keeps the registers low enough for five or more
+// waves per SIMD, which the balance of FP64 work and HBM traffic needs.
 // EPI 0: LSQR update of u~_top with partial squared norms; EPI 1: store A W;
 // EPI 2: store the partial product over column chunk it.ch (wide problems).
+static constexpr int GN_RT = 2;
+static constexpr int GN_ROWS = 64 * GN_RT;
+static_assert(GN_ROWS == 128, "rows per gemm_n block must match the plans");
+
 template <typename TA, typename TC, int NC, int EPI>
 __global__ void __launch_bounds__(256) k_gemm_n_mfma(const DevProb* __restrict__ P,
                                                      const Item* __restrict__ items, int N,
@@ -60,28 +66,29 @@ __global__ void __launch_bounds__(256) k_gemm_n_mfma(const DevProb* __restrict__
   const int64_t m = pr.m, n = pr.n, lda = pr.lda;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int64_t row0 = int64_t(it.blk) * 256 + wv * 64;
+  constexpr int RT = GN_RT;
+  const int64_t row0 = int64_t(it.blk) * GN_ROWS + wv * (16 * RT);
   const int64_t kbeg = int64_t(it.ch) * pr.cchunk;
   const int64_t kend = min(n, kbeg + pr.cchunk);
-  typename M::acc_t acc[4][NT];
+  typename M::acc_t acc[RT][NT];
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = typename M::acc_t{0, 0, 0, 0};
   // A operands of the current chunk live in `a`; those of the next chunk are
   // loaded into `an` while the matrix cores work on the current one.
-  auto load_a = [&](int64_t k0, TC (&dst)[4][KC / 4]) {
+  auto load_a = [&](int64_t k0, TC (&dst)[RT][KC / 4]) {
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
       const int64_t col = k0 + 4 * ks + lk;
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt) {
+      for (int rt = 0; rt < RT; ++rt) {
         const int64_t row = row0 + rt * 16 + li;
         dst[rt][ks] = (row < m && col < kend) ? TC(A[row + col * lda]) : TC(0);
       }
     }
   };
-  TC a[4][KC / 4], an[4][KC / 4];
+  TC a[RT][KC / 4], an[RT][KC / 4];
   load_a(kbeg, a);
   for (int64_t k0 = kbeg; k0 < kend; k0 += KC) {
     for (int e = threadIdx.x; e < KC * NC; e += 256) {
@@ -97,7 +104,7 @@ __global__ void __launch_bounds__(256) k_gemm_n_mfma(const DevProb* __restrict__
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) b[nt] = Ws[4 * ks + lk][nt * 16 + li];
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
+      for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = M::op(a[rt][ks], b[nt], acc[rt][nt]);
     }
@@ -105,7 +112,7 @@ __global__ void __launch_bounds__(256) k_gemm_n_mfma(const DevProb* __restrict__
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks)
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt) a[rt][ks] = an[rt][ks];
+      for (int rt = 0; rt < RT; ++rt) a[rt][ks] = an[rt][ks];
   }
   double nsum[NT];
 #pragma unroll
@@ -114,7 +121,7 @@ __global__ void __launch_bounds__(256) k_gemm_n_mfma(const DevProb* __restrict__
     const int lam = nt * 16 + li;
     const double uc = (EPI == 0 && lam < N) ? sc[it.p * N + lam].ucoef : 0.0;
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = row0 + rt * 16 + M::row(lane, v);
