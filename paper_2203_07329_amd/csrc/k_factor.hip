@@ -49,21 +49,41 @@ __device__ __forceinline__ void tile_mma(const double* __restrict__ A, int64_t l
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int wr = 32 * (wv & 1), wc = 32 * (wv >> 1);
-  for (int64_t k0 = 0; k0 < K; k0 += TK) {
-    for (int e = tid; e < 64 * TK; e += 256) {
+  constexpr int Q = 64 * TK / 256;     // elements of each tile per thread
+  double ra[Q], rb[Q];
+  // the next chunk is fetched into registers while the current one is used
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = tid + 256 * q;
       int i, kk;
       if (TA) { kk = e % TK; i = e / TK; } else { i = e % 64; kk = e / 64; }
       const int64_t k = k0 + kk;
       double v = 0.0;
       if (i < mrows && k < K) v = TA ? A[k + int64_t(i) * lda] : A[i + k * lda];
-      L.As[i][kk] = v;
+      ra[q] = v;
+      const int kb = e % TK, j = e / TK;
+      const int64_t kg = k0 + kb;
+      rb[q] = (j < ncols && kg < K) ? B[kg + int64_t(j) * ldb] : 0.0;
     }
-    for (int e = tid; e < TK * 64; e += 256) {
-      const int kk = e % TK, j = e / TK;
-      const int64_t k = k0 + kk;
-      L.Bs[kk][j] = (j < ncols && k < K) ? B[k + int64_t(j) * ldb] : 0.0;
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = tid + 256 * q;
+      if (TA) L.As[e / TK][e % TK] = ra[q];
+      else L.As[e % 64][e / 64] = ra[q];
+      L.Bs[e % TK][e / TK] = rb[q];
     }
-    __syncthreads();
+  };
+  if (K > 0) {
+    fetch(0);
+    stash();
+  }
+  __syncthreads();
+  for (int64_t k0 = 0; k0 < K; k0 += TK) {
+    const bool more = k0 + TK < K;
+    if (more) fetch(k0 + TK);
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
       double a[2], b[2];
@@ -77,6 +97,8 @@ __device__ __forceinline__ void tile_mma(const double* __restrict__ A, int64_t l
         for (int u = 0; u < 2; ++u)
           acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
     }
+    __syncthreads();
+    if (more) stash();
     __syncthreads();
   }
 }

@@ -48,7 +48,7 @@ static constexpr int GN_ROWS = 64 * GN_RT;
 static_assert(GN_ROWS == 128, "rows per gemm_n block must match the plans");
 
 template <typename TA, typename TC, int NC, int EPI>
-__global__ void __launch_bounds__(256) k_gemm_n_mfma(const DevProb* __restrict__ P,
+__global__ void __launch_bounds__(256, 3) k_gemm_n_mfma(const DevProb* __restrict__ P,
                                                      const Item* __restrict__ items, int N,
                                                      const double* __restrict__ W,
                                                      TC* __restrict__ ut, double* __restrict__ out,
@@ -58,7 +58,8 @@ __global__ void __launch_bounds__(256) k_gemm_n_mfma(const DevProb* __restrict__
   constexpr int NT = NC / 16;
   constexpr int KC = sizeof(TC) == 8 ? 16 : 32;
   constexpr int WP = NC + 2;
-  __shared__ TC Ws[KC][WP];
+  constexpr int QW = (KC * NC + 255) / 256;     // W elements per thread and chunk
+  __shared__ TC Ws[2][KC][WP];
   __shared__ double nred[4][NC];
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
@@ -75,8 +76,9 @@ __global__ void __launch_bounds__(256) k_gemm_n_mfma(const DevProb* __restrict__
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = typename M::acc_t{0, 0, 0, 0};
-  // A operands of the current chunk live in `a`; those of the next chunk are
-  // loaded into `an` while the matrix cores work on the current one.
+  // The A operands and the W rows of the next chunk are loaded into registers
+  // while the matrix cores work on the current chunk; W is double-buffered in
+  // LDS, so one barrier per chunk suffices.
   auto load_a = [&](int64_t k0, TC (&dst)[RT][KC / 4]) {
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
@@ -88,32 +90,55 @@ __global__ void __launch_bounds__(256) k_gemm_n_mfma(const DevProb* __restrict__
       }
     }
   };
-  TC a[RT][KC / 4], an[RT][KC / 4];
-  load_a(kbeg, a);
-  for (int64_t k0 = kbeg; k0 < kend; k0 += KC) {
-    for (int e = threadIdx.x; e < KC * NC; e += 256) {
+  auto load_w = [&](int64_t k0, TC (&dst)[QW]) {
+#pragma unroll
+    for (int q = 0; q < QW; ++q) {
+      const int e = threadIdx.x + 256 * q;
       const int kk = e / NC, i = e % NC;
       const int64_t kg = k0 + kk;
-      Ws[kk][i] = (kg < kend && i < N) ? TC(W[(pr.offC + kg) * N + i]) : TC(0);
+      dst[q] = (e < KC * NC && kg < kend && i < N) ? TC(W[(pr.offC + kg) * N + i]) : TC(0);
     }
-    __syncthreads();
-    if (k0 + KC < kend) load_a(k0 + KC, an);
+  };
+  auto store_w = [&](int buf, const TC (&src)[QW]) {
 #pragma unroll
-    for (int ks = 0; ks < KC / 4; ++ks) {
-      TC b[NT];
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) b[nt] = Ws[4 * ks + lk][nt * 16 + li];
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = M::op(a[rt][ks], b[nt], acc[rt][nt]);
+    for (int q = 0; q < QW; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (e < KC * NC) Ws[buf][e / NC][e % NC] = src[q];
     }
-    __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < KC / 4; ++ks)
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) a[rt][ks] = an[rt][ks];
+  };
+  // Two register sets take turns (loop unrolled by two), so no copy forces
+  // the prefetch to land early; W is loaded before A so that waiting for W
+  // (to stage it in LDS) leaves the A loads in flight.
+  TC a0[RT][KC / 4], a1[RT][KC / 4];
+  TC wr[QW];
+  load_w(kbeg, wr);
+  load_a(kbeg, a0);
+  store_w(0, wr);
+  __syncthreads();
+#define TIK_GN_STEP(CUR, NXT, KC0, BUF)                                                     \
+  {                                                                                         \
+    const bool more = (KC0) + KC < kend;                                                    \
+    if (more) {                                                                             \
+      load_w((KC0) + KC, wr);                                                               \
+      load_a((KC0) + KC, NXT);                                                              \
+    }                                                                                       \
+    _Pragma("unroll") for (int ks = 0; ks < KC / 4; ++ks) {                                 \
+      TC b[NT];                                                                             \
+      _Pragma("unroll") for (int nt = 0; nt < NT; ++nt) b[nt] =                             \
+          Ws[BUF][4 * ks + lk][nt * 16 + li];                                               \
+      _Pragma("unroll") for (int rt = 0; rt < RT; ++rt)                                     \
+          _Pragma("unroll") for (int nt = 0; nt < NT; ++nt) acc[rt][nt] =                   \
+              M::op(CUR[rt][ks], b[nt], acc[rt][nt]);                                       \
+    }                                                                                       \
+    if (more) store_w((BUF) ^ 1, wr);                                                       \
+    __syncthreads();                                                                        \
   }
+  for (int64_t k0 = kbeg; k0 < kend; k0 += 2 * KC) {
+    TIK_GN_STEP(a0, a1, k0, 0)
+    if (k0 + KC >= kend) break;
+    TIK_GN_STEP(a1, a0, k0 + KC, 1)
+  }
+#undef TIK_GN_STEP
   double nsum[NT];
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
