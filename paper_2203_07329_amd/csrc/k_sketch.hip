@@ -120,6 +120,74 @@ __device__ __forceinline__ bool neg_sign(const uint32_t* __restrict__ signs, int
   return (signs[r >> 5] >> (r & 31)) & 1u;
 }
 
+// In-LDS Walsh-Hadamard transform of buf[0 .. 2^bits), all threads of the
+// block taking part, for bits >= 3 whose first three stages (h = 1, 2, 4)
+// the caller has already applied: the stages commute, so the rest run as
+// radix-8 passes (three stages on 8 values in registers per LDS round trip),
+// then one radix-4 or radix-2 pass for the remainder.  Group g of a pass at
+// stage t holds the elements i + j 2^t, i = g with three zero bits inserted at t.
+__device__ __forceinline__ void fwht_lds_from3(double* buf, int bits) {
+  const int M = 1 << bits;
+  int t = 3;
+  for (; t + 3 <= bits; t += 3) {
+    const int h = 1 << t;
+    for (int g = threadIdx.x; g < (M >> 3); g += blockDim.x) {
+      const int i = ((g >> t) << (t + 3)) | (g & (h - 1));
+      double v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = buf[i + j * h];
+#pragma unroll
+      for (int hh = 1; hh < 8; hh <<= 1)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if ((j & hh) == 0) {
+            const double a = v[j], b = v[j + hh];
+            v[j] = a + b;
+            v[j + hh] = a - b;
+          }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) buf[i + j * h] = v[j];
+    }
+    __syncthreads();
+  }
+  const int r = bits - t;
+  if (r == 2) {
+    const int h = 1 << t;
+    for (int g = threadIdx.x; g < (M >> 2); g += blockDim.x) {
+      const int i = ((g >> t) << (t + 2)) | (g & (h - 1));
+      double v0 = buf[i], v1 = buf[i + h], v2 = buf[i + 2 * h], v3 = buf[i + 3 * h];
+      const double a0 = v0 + v1, a1 = v0 - v1, a2 = v2 + v3, a3 = v2 - v3;
+      buf[i] = a0 + a2;
+      buf[i + h] = a1 + a3;
+      buf[i + 2 * h] = a0 - a2;
+      buf[i + 3 * h] = a1 - a3;
+    }
+    __syncthreads();
+  } else if (r == 1) {
+    const int h = 1 << t;
+    for (int g = threadIdx.x; g < (M >> 1); g += blockDim.x) {
+      const int i = ((g >> t) << (t + 1)) | (g & (h - 1));
+      const double a = buf[i], b = buf[i + h];
+      buf[i] = a + b;
+      buf[i + h] = a - b;
+    }
+    __syncthreads();
+  }
+}
+
+// Stages h = 1, 2, 4 on 8 consecutive values in registers.
+__device__ __forceinline__ void fwht8(double (&v)[8]) {
+#pragma unroll
+  for (int hh = 1; hh < 8; hh <<= 1)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if ((j & hh) == 0) {
+        const double a = v[j], b = v[j + hh];
+        v[j] = a + b;
+        v[j + hh] = a - b;
+      }
+}
+
 // Single-pass SRHT for m' <= 2^13: one workgroup per column, the whole padded
 // column staged in LDS, log2 m' butterfly stages, then the sampled rows gathered.
 template <typename TA>
@@ -132,23 +200,44 @@ __global__ void __launch_bounds__(256) k_srht_single(const TA* __restrict__ A, i
   const int64_t c = blockIdx.x;
   const int M = 1 << k;
   const TA* col = A + c * lda;
-  for (int r = threadIdx.x; r < M; r += blockDim.x) {
-    double v = 0.0;
-    if (r < m) {
-      v = double(col[r]);
-      if (neg_sign(signs, r)) v = -v;
-    }
-    lbuf[r] = v;
-  }
-  __syncthreads();
-  for (int h = 1; h < M; h <<= 1) {
-    for (int idx = threadIdx.x; idx < (M >> 1); idx += blockDim.x) {
-      const int i = ((idx / h) * (h << 1)) + (idx % h);
-      const double a = lbuf[i], b = lbuf[i + h];
-      lbuf[i] = a + b;
-      lbuf[i + h] = a - b;
+  if (k >= 3) {
+    for (int g = threadIdx.x; g < (M >> 3); g += blockDim.x) {
+      double v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t r = 8 * int64_t(g) + j;
+        double x = 0.0;
+        if (r < m) {
+          x = double(col[r]);
+          if (neg_sign(signs, r)) x = -x;
+        }
+        v[j] = x;
+      }
+      fwht8(v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) lbuf[8 * g + j] = v[j];
     }
     __syncthreads();
+    fwht_lds_from3(lbuf, k);
+  } else {
+    for (int r = threadIdx.x; r < M; r += blockDim.x) {
+      double v = 0.0;
+      if (r < m) {
+        v = double(col[r]);
+        if (neg_sign(signs, r)) v = -v;
+      }
+      lbuf[r] = v;
+    }
+    __syncthreads();
+    for (int h = 1; h < M; h <<= 1) {
+      for (int idx = threadIdx.x; idx < (M >> 1); idx += blockDim.x) {
+        const int i = ((idx & ~(h - 1)) << 1) | (idx & (h - 1));
+        const double a = lbuf[i], b = lbuf[i + h];
+        lbuf[i] = a + b;
+        lbuf[i + h] = a - b;
+      }
+      __syncthreads();
+    }
   }
   for (int64_t q = threadIdx.x; q < s; q += blockDim.x) Y[q + c * s] = lbuf[rows[q]] * scale;
 }
@@ -208,16 +297,29 @@ __global__ void __launch_bounds__(256) k_srht_pass2(const double* __restrict__ T
   const int q0 = bstart[hb], q1 = bstart[hb + 1];
   if (q0 == q1) return;
   const double* src = T + cc * (int64_t(1) << k) + int64_t(hb) * B;
-  for (int r = threadIdx.x; r < B; r += blockDim.x) lbuf[r] = src[r];
-  __syncthreads();
-  for (int h = 1; h < B; h <<= 1) {
-    for (int idx = threadIdx.x; idx < (B >> 1); idx += blockDim.x) {
-      const int i = ((idx / h) * (h << 1)) + (idx % h);
-      const double a = lbuf[i], b = lbuf[i + h];
-      lbuf[i] = a + b;
-      lbuf[i + h] = a - b;
+  if (bbits >= 3) {
+    for (int g = threadIdx.x; g < (B >> 3); g += blockDim.x) {
+      double v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = src[8 * g + j];
+      fwht8(v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) lbuf[8 * g + j] = v[j];
     }
     __syncthreads();
+    fwht_lds_from3(lbuf, bbits);
+  } else {
+    for (int r = threadIdx.x; r < B; r += blockDim.x) lbuf[r] = src[r];
+    __syncthreads();
+    for (int h = 1; h < B; h <<= 1) {
+      for (int idx = threadIdx.x; idx < (B >> 1); idx += blockDim.x) {
+        const int i = ((idx & ~(h - 1)) << 1) | (idx & (h - 1));
+        const double a = lbuf[i], b = lbuf[i + h];
+        lbuf[i] = a + b;
+        lbuf[i + h] = a - b;
+      }
+      __syncthreads();
+    }
   }
   const int64_t base = int64_t(hb) * B;
   for (int q = q0 + threadIdx.x; q < q1; q += blockDim.x)
