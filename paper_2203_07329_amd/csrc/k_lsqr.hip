@@ -819,74 +819,82 @@ __global__ void k_wide_init_h(const DevProb* __restrict__ P, const Item* __restr
 }
 
 // v~ = [A^T y - beta v_top; sqrt(lam) y - beta v_bot] and its partial norms.
-// Items: long blocks of 256 rows of n (blk < nL), then short blocks over m.
+// One thread per (row, lambda): a block covers 256 / NC rows of all NC = 2^lgnc
+// lambda slots, so consecutive threads touch consecutive entries of the
+// row-major vectors.  Items: long blocks (blk < ceil(n / rows)), then short
+// blocks over m; the partial squared norm of each block and lambda goes to pnQ.
 template <typename TC>
 __global__ void __launch_bounds__(BLK) k_wide_v(const DevProb* __restrict__ P,
-                                                const Item* __restrict__ items, int N,
+                                                const Item* __restrict__ items, int N, int lgnc,
                                                 const TC* __restrict__ part,
                                                 const double* __restrict__ y,
                                                 double* __restrict__ vt, double* __restrict__ vb,
                                                 const Scal* __restrict__ sc,
                                                 double* __restrict__ pnQ) {
-  __shared__ double red[4];
+  __shared__ double sh[BLK];
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
-  const int nL = int(cdiv(pr.n, BLK));
+  const int RB = BLK >> lgnc;
+  const int i = threadIdx.x & ((1 << lgnc) - 1);
+  const int nL = int(cdiv(pr.n, RB));
   const bool lng = it.blk < nL;
-  const int64_t r = int64_t(lng ? it.blk : it.blk - nL) * BLK + threadIdx.x;
+  const int64_t r = int64_t(lng ? it.blk : it.blk - nL) * RB + (threadIdx.x >> lgnc);
   const int64_t rows = lng ? pr.n : pr.m;
-  for (int i = 0; i < N; ++i) {
+  double v = 0.0;
+  if (r < rows && i < N) {
     const Scal& S = sc[it.p * N + i];
-    double v = 0.0;
-    if (r < rows) {
-      if (lng) {
-        const int64_t idx = (pr.offL + r) * N + i;
-        const double nv = double(part[(pr.ptOff + r) * N + i]) - S.beta_new * vt[idx];
-        vt[idx] = nv;
-        v = nv * nv;
-      } else {
-        const int64_t idx = (pr.offS + r) * N + i;
-        const double nv = S.sqlam * y[idx] - S.beta_new * vb[idx];
-        vb[idx] = nv;
-        v = nv * nv;
-      }
+    if (lng) {
+      const int64_t idx = (pr.offL + r) * N + i;
+      const double nv = double(part[(pr.ptOff + r) * N + i]) - S.beta_new * vt[idx];
+      vt[idx] = nv;
+      v = nv * nv;
+    } else {
+      const int64_t idx = (pr.offS + r) * N + i;
+      const double nv = S.sqlam * y[idx] - S.beta_new * vb[idx];
+      vb[idx] = nv;
+      v = nv * nv;
     }
-    const double tot = block_sum(v, red);
-    if (threadIdx.x == 0) pnQ[(pr.pnQ + it.blk) * N + i] = tot;
+  }
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  if (int(threadIdx.x) < N) {
+    double tot = 0.0;
+    for (int q = 0; q < RB; ++q) tot += sh[(q << lgnc) + threadIdx.x];
+    pnQ[(pr.pnQ + it.blk) * N + threadIdx.x] = tot;
   }
 }
 
-// v = v~ / alpha; z += (phi/rho) d; d = v - (theta/rho) d (top: x, d_top; bottom: z_bot, d_bot).
+// v = v~ / alpha; z += (phi/rho) d; d = v - (theta/rho) d (top: x, d_top;
+// bottom: z_bot, d_bot).  Same (row, lambda) thread mapping as k_wide_v.
 __global__ void __launch_bounds__(BLK) k_wide_upd(const DevProb* __restrict__ P,
-                                                  const Item* __restrict__ items, int N,
+                                                  const Item* __restrict__ items, int N, int lgnc,
                                                   double* __restrict__ vt, double* __restrict__ dt,
                                                   double* __restrict__ xt, double* __restrict__ vb,
                                                   double* __restrict__ db, double* __restrict__ zb,
                                                   const Scal* __restrict__ sc, int init) {
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
-  const int nL = int(cdiv(pr.n, BLK));
+  const int RB = BLK >> lgnc;
+  const int i = threadIdx.x & ((1 << lgnc) - 1);
+  const int nL = int(cdiv(pr.n, RB));
   const bool lng = it.blk < nL;
-  const int64_t r = int64_t(lng ? it.blk : it.blk - nL) * BLK + threadIdx.x;
+  const int64_t r = int64_t(lng ? it.blk : it.blk - nL) * RB + (threadIdx.x >> lgnc);
   const int64_t rows = lng ? pr.n : pr.m;
-  if (r >= rows) return;
+  if (r >= rows || i >= N) return;
   double* V = lng ? vt : vb;
   double* D = lng ? dt : db;
   double* Z = lng ? xt : zb;
-  const int64_t base = (lng ? pr.offL : pr.offS) + r;
-  for (int i = 0; i < N; ++i) {
-    const Scal& S = sc[it.p * N + i];
-    const int64_t idx = base * N + i;
-    const double nv = V[idx] * S.ialpha;
-    V[idx] = nv;
-    if (init) {
-      D[idx] = nv;
-      Z[idx] = 0.0;
-    } else if (S.upd) {
-      const double d = D[idx];
-      Z[idx] += S.cx * d;
-      D[idx] = nv - S.ce * d;
-    }
+  const Scal& S = sc[it.p * N + i];
+  const int64_t idx = ((lng ? pr.offL : pr.offS) + r) * N + i;
+  const double nv = V[idx] * S.ialpha;
+  V[idx] = nv;
+  if (init) {
+    D[idx] = nv;
+    Z[idx] = 0.0;
+  } else if (S.upd) {
+    const double d = D[idx];
+    Z[idx] += S.cx * d;
+    D[idx] = nv - S.ce * d;
   }
 }
 
@@ -957,7 +965,7 @@ struct Plan {
   LrTables lr;                          // low-rank apply: proj, expand, fin
   bool lowrank = false;
   int cpw = 16;
-  int cbT = 64;        // columns per gemm_t block (128 on matrix cores)
+  int cbT = 64;        // columns per gemm_t block
   int64_t totL = 0, totS = 0, totPT = 0, nbN = 0, nbB = 0, nbQ = 0;
   int J = 0;
 };
@@ -978,6 +986,12 @@ struct Bufs {
   int32_t* jmap;
   int32_t* lidx;
 };
+
+int ilog2(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
 
 int pick_nc(int N) {
   int nc = 1;
@@ -1032,7 +1046,7 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
   pl.NC = pick_nc(N);
   pl.rbN = pl.NC >= 16 ? 128 : pl.NC >= 8 ? 256 : 64;   // rows per gemm_n block
   pl.cpw = 4;          // columns per wave in R^{-T} t: low registers, high occupancy
-  pl.cbT = pl.NC >= 16 ? 128 : 64;
+  pl.cbT = 64;          // columns per gemm_t block
   pl.pidx = pidx;
   pl.lsel = lsel;
   pl.P.clear();
@@ -1146,7 +1160,7 @@ struct Kern {
     ProfScope ps("gemm_n", st);
     if (NC >= 16)
       return launch_gemm_n_mfma(std::is_same<TA, float>::value, std::is_same<TC, float>::value, NC, 0,
-                                b.P, b.itN, int(pl.itN.size()), pl.N, b.w, b.ut, nullptr, b.sc,
+                                pl.rbN, b.P, b.itN, int(pl.itN.size()), pl.N, b.w, b.ut, nullptr, b.sc,
                                 b.pnN, st);
     if (NC >= 8)
       hipLaunchKernelGGL((k_gemm_n<TA, TC, NC, 256, 1, 0>), dim3(unsigned(pl.itN.size())), dim3(BLK),
@@ -1161,7 +1175,7 @@ struct Kern {
     ProfScope ps("gemm_t", st);
     if (NC >= 16)
       return launch_gemm_t_mfma(std::is_same<TA, float>::value, std::is_same<TC, float>::value, 0, NC,
-                                b.P, b.itT, int(pl.itT.size()), pl.N, b.ut, b.part, st);
+                                pl.cbT, b.P, b.itT, int(pl.itT.size()), pl.N, b.ut, b.part, st);
     hipLaunchKernelGGL((k_gemm_t<TA, TC, TC, NC>), dim3(unsigned(pl.itT.size())), dim3(BLK), 0, st,
                        b.P, b.itT, pl.N, static_cast<const TC*>(b.ut), int64_t(pl.N),
                        static_cast<TC*>(b.part));
@@ -1455,7 +1469,7 @@ template <typename TA>
 int ir_products_t(const Plan& pf, const Bufs& bf, const double* U, hipStream_t st) {
   ProfScope ps("residual", st);
   if (pf.NC >= 16)
-    return launch_gemm_t_mfma(std::is_same<TA, float>::value, 0, 1, pf.NC, bf.P, bf.itT,
+    return launch_gemm_t_mfma(std::is_same<TA, float>::value, 0, 1, pf.NC, pf.cbT, bf.P, bf.itT,
                               int(pf.itT.size()), pf.N, U, bf.part, st);
   switch (pf.NC) {
 #define GT(nc) case nc: hipLaunchKernelGGL((k_gemm_t<TA, double, double, nc>), dim3(unsigned(pf.itT.size())), dim3(BLK), 0, st, bf.P, bf.itT, pf.N, U, int64_t(pf.N), static_cast<double*>(bf.part)); break;
@@ -1470,7 +1484,7 @@ template <typename TA>
 int ir_products_n(const Plan& pf, const Bufs& bf, const double* W, double* out, hipStream_t st) {
   ProfScope ps("residual", st);
   if (pf.NC >= 16)
-    return launch_gemm_n_mfma(std::is_same<TA, float>::value, 0, pf.NC, 1, bf.P, bf.itN,
+    return launch_gemm_n_mfma(std::is_same<TA, float>::value, 0, pf.NC, 1, pf.rbN, bf.P, bf.itN,
                               int(pf.itN.size()), pf.N, W, nullptr, out, bf.sc, nullptr, st);
   switch (pf.NC) {
 #define GN(nc) case nc: hipLaunchKernelGGL((k_gemm_n<TA, double, nc, (nc >= 8 ? 256 : 64), (nc >= 8 ? 1 : 4), 1>), dim3(unsigned(pf.itN.size())), dim3(BLK), 0, st, bf.P, bf.itN, pf.N, W, static_cast<double*>(nullptr), out, bf.sc, static_cast<double*>(nullptr)); break;
@@ -1848,9 +1862,9 @@ void make_plan_wide(const tik_problem* probs, const tik_precond_s* pc, const std
   pl = WPlan();
   pl.N = N;
   pl.NC = pick_nc(N);
-  pl.rbN = pl.NC >= 16 ? 128 : pl.NC >= 8 ? 256 : 64;   // rows per gemm_n block
+  pl.rbN = pl.NC >= 8 ? 256 : 64;   // rows per gemm_n block: v_top is re-read per block
   pl.cpw = 4;          // columns per wave in R^{-T} t: low registers, high occupancy
-  pl.cbT = pl.NC >= 16 ? 128 : 64;
+  pl.cbT = pl.NC >= 16 ? 128 : 64;   // columns per gemm_t block: y is re-read per block
   pl.pidx = pidx;
   pl.lsel = lsel;
   pl.lowrank = pc->route == TIK_ROUTE_LOWRANK;
@@ -1894,7 +1908,7 @@ void make_plan_wide(const tik_problem* probs, const tik_precond_s* pc, const std
     if (pl.lowrank) d.nblkN = lowrank_items(pc, pidx[lp], lp, lsel, pl.NC, pl.lr, d);
     d.nblkB = 0;
     d.pnN = pl.nbN;
-    d.nblkQ = int32_t(cdiv(g.n, BLK) + cdiv(g.m, BLK));
+    d.nblkQ = int32_t(cdiv(g.n, BLK / pl.NC) + cdiv(g.m, BLK / pl.NC));   // k_wide_v blocks
     d.pnQ = pl.nbQ;
     if (!pl.lowrank) {
       for (int i = 0; i < N; ++i)
@@ -2012,7 +2026,7 @@ int wide_products_n(const WPlan& pl, const WBufs& b, const double* W, void* part
   ProfScope ps("gemm_n", st);
   constexpr bool a32 = std::is_same<TA, float>::value, c32 = std::is_same<TC, float>::value;
   if (NC >= 16)
-    return launch_gemm_n_mfma(a32, c32, NC, 2, b.P, b.itNs, int(pl.itNs.size()), pl.N, W, part,
+    return launch_gemm_n_mfma(a32, c32, NC, 2, pl.rbN, b.P, b.itNs, int(pl.itNs.size()), pl.N, W, part,
                               nullptr, b.sc, nullptr, st);
   if (NC >= 8)
     hipLaunchKernelGGL((k_gemm_n<TA, TC, NC, 256, 1, 2>), dim3(unsigned(pl.itNs.size())), dim3(BLK),
@@ -2029,7 +2043,7 @@ int wide_products_t(const WPlan& pl, const WBufs& b, const double* U, void* part
   ProfScope ps("gemm_t", st);
   constexpr bool a32 = std::is_same<TA, float>::value, c32 = std::is_same<TC, float>::value;
   if (NC >= 16)
-    return launch_gemm_t_mfma(a32, c32, 1, NC, b.P, b.itT, int(pl.itT.size()), pl.N, U, part, st);
+    return launch_gemm_t_mfma(a32, c32, 1, NC, pl.cbT, b.P, b.itT, int(pl.itT.size()), pl.N, U, part, st);
   hipLaunchKernelGGL((k_gemm_t<TA, TC, double, NC>), dim3(unsigned(pl.itT.size())), dim3(BLK), 0, st,
                      b.P, b.itT, pl.N, U, int64_t(pl.N), static_cast<TC*>(part));
   TIK_LAUNCHED("k_gemm_t");
@@ -2053,13 +2067,14 @@ int wide_v_steps(const WPlan& pl, const WBufs& b, hipStream_t st, bool init, dou
   {
     ProfScope ps("vec", st);
     hipLaunchKernelGGL(k_wide_v<TC>, dim3(unsigned(pl.itV.size())), dim3(BLK), 0, st, b.P, b.itV,
-                       pl.N, static_cast<const TC*>(b.partT), b.y, b.vt, b.vb, b.sc, b.pnQ);
+                       pl.N, ilog2(pl.NC), static_cast<const TC*>(b.partT), b.y, b.vt, b.vb, b.sc,
+                       b.pnQ);
     TIK_LAUNCHED("k_wide_v");
     hipLaunchKernelGGL(k_fin_alpha, dim3(unsigned(pl.J)), dim3(BLK), 0, st, b.P, pl.N, b.pnQ, b.sc,
                        init ? 1 : 0, tol, maxit);
     TIK_LAUNCHED("k_fin_alpha");
     hipLaunchKernelGGL(k_wide_upd, dim3(unsigned(pl.itV.size())), dim3(BLK), 0, st, b.P, b.itV,
-                       pl.N, b.vt, b.dt, b.xt, b.vb, b.db, b.zb, b.sc, init ? 1 : 0);
+                       pl.N, ilog2(pl.NC), b.vt, b.dt, b.xt, b.vb, b.db, b.zb, b.sc, init ? 1 : 0);
     TIK_LAUNCHED("k_wide_upd");
   }
   return TIK_OK;

@@ -36,19 +36,16 @@ struct Mfma<float> {
 };
 
 // ------------------------------------------------------------------ gemm_n --
-// Block = 4 waves x 16 RT rows = GN_ROWS rows of one problem, all NC lambdas.
+// Block = 4 waves x 16 RT rows = 64 RT rows of one problem, all NC lambdas.
 // A is read straight into A-operand registers (16 consecutive rows of 4
 // columns per load: whole 64/128-byte lines); W is staged through LDS KC
-// columns at a time.  RT = 2 keeps the registers low enough for five or more
-// waves per SIMD, which the balance of FP64 work and HBM traffic needs.
+// columns at a time.  RT = 2 (128-row blocks) keeps the registers low for tall
+// problems; RT = 4 (256 rows) halves the re-reads of W where the A rows are
+// few and W is long (wide problems).  The plan's rows per block must match.
 // EPI 0: LSQR update of u~_top with partial squared norms; EPI 1: store A W;
 // EPI 2: store the partial product over column chunk it.ch (wide problems).
-static constexpr int GN_RT = 2;
-static constexpr int GN_ROWS = 64 * GN_RT;
-static_assert(GN_ROWS == 128, "rows per gemm_n block must match the plans");
-
-template <typename TA, typename TC, int NC, int EPI>
-__global__ void __launch_bounds__(256, 3) k_gemm_n_mfma(const DevProb* __restrict__ P,
+template <typename TA, typename TC, int NC, int EPI, int RT>
+__global__ void __launch_bounds__(256, RT == 2 ? 3 : 2) k_gemm_n_mfma(const DevProb* __restrict__ P,
                                                      const Item* __restrict__ items, int N,
                                                      const double* __restrict__ W,
                                                      TC* __restrict__ ut, double* __restrict__ out,
@@ -67,8 +64,7 @@ __global__ void __launch_bounds__(256, 3) k_gemm_n_mfma(const DevProb* __restric
   const int64_t m = pr.m, n = pr.n, lda = pr.lda;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  constexpr int RT = GN_RT;
-  const int64_t row0 = int64_t(it.blk) * GN_ROWS + wv * (16 * RT);
+  const int64_t row0 = int64_t(it.blk) * (64 * RT) + wv * (16 * RT);
   const int64_t kbeg = int64_t(it.ch) * pr.cchunk;
   const int64_t kend = min(n, kbeg + pr.cchunk);
   typename M::acc_t acc[RT][NT];
@@ -179,19 +175,20 @@ __global__ void __launch_bounds__(256, 3) k_gemm_n_mfma(const DevProb* __restric
 }
 
 // ------------------------------------------------------------------ gemm_t --
-// Block = 128 columns x one row chunk; wave w owns columns 32 w .. 32 w + 31.
-// A (32 rows x 128 columns) and U (32 rows x NC) are staged through LDS, then
+// Block = CB columns x one row chunk; wave w owns CB / 4 columns (CB = 64 for
+// tall problems, 128 for wide ones, whose U is re-read by every column block).
+// A (32 rows x CB columns) and U (32 rows x NC) are staged through LDS, then
 // read in MFMA operand order (A^T as the A-operand, U as the B-operand).
 // Blocks are remapped so that consecutive items (the column blocks of one row
 // chunk, which share U) run on the same XCD and share its L2.
-template <typename TA, typename TC, typename TU, int NC>
+template <typename TA, typename TC, typename TU, int NC, int CB>
 __global__ void __launch_bounds__(256) k_gemm_t_mfma(const DevProb* __restrict__ P,
                                                      const Item* __restrict__ items, int nitems,
                                                      int N, const TU* __restrict__ U,
                                                      TC* __restrict__ part) {
   using M = Mfma<TC>;
   constexpr int NT = NC / 16;
-  constexpr int CB = 128, RS = 32, AP = RS + 4, UP = NC + 2;
+  constexpr int CT = CB / 64, RS = 32, AP = RS + 4, UP = NC + 2;
   __shared__ TC As[CB][AP];
   __shared__ TC Us[RS][UP];
   const int g = blockIdx.x;
@@ -207,9 +204,9 @@ __global__ void __launch_bounds__(256) k_gemm_t_mfma(const DevProb* __restrict__
   const int64_t rend = min(m, rbeg + pr.rchunk);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  typename M::acc_t acc[2][NT];
+  typename M::acc_t acc[CT][NT];
 #pragma unroll
-  for (int ct = 0; ct < 2; ++ct)
+  for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[ct][nt] = typename M::acc_t{0, 0, 0, 0};
   // The next tile of A and U is fetched into registers while the matrix cores
@@ -255,14 +252,14 @@ __global__ void __launch_bounds__(256) k_gemm_t_mfma(const DevProb* __restrict__
     if (more) fetch(r0 + RS);
 #pragma unroll
     for (int ks = 0; ks < RS / 4; ++ks) {
-      TC a[2];
+      TC a[CT];
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct) a[ct] = As[wv * 32 + ct * 16 + li][4 * ks + lk];
+      for (int ct = 0; ct < CT; ++ct) a[ct] = As[wv * (16 * CT) + ct * 16 + li][4 * ks + lk];
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         const TC b = Us[4 * ks + lk][nt * 16 + li];
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) acc[ct][nt] = M::op(a[ct], b, acc[ct][nt]);
+        for (int ct = 0; ct < CT; ++ct) acc[ct][nt] = M::op(a[ct], b, acc[ct][nt]);
       }
     }
     __syncthreads();
@@ -271,39 +268,48 @@ __global__ void __launch_bounds__(256) k_gemm_t_mfma(const DevProb* __restrict__
   }
   TC* dst = part + (pr.ptOff + int64_t(it.ch) * n) * N;
 #pragma unroll
-  for (int ct = 0; ct < 2; ++ct)
+  for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t c = c0 + wv * 32 + ct * 16 + M::row(lane, v);
+        const int64_t c = c0 + wv * (16 * CT) + ct * 16 + M::row(lane, v);
         const int lam = nt * 16 + li;
         if (c < n && lam < N) dst[c * N + lam] = acc[ct][nt][v];
       }
 }
 
 // --------------------------------------------------------------- launchers --
-template <typename TA, typename TC>
-static int gemm_n_nc(int nc, int epi, const DevProb* P, const Item* items, int nitems, int N,
+template <typename TA, typename TC, int RT>
+static int gemm_n_rt(int nc, int epi, const DevProb* P, const Item* items, int nitems, int N,
                      const double* W, void* ut, double* out, const Scal* sc, double* pnN,
                      hipStream_t st) {
   const dim3 g = dim3(unsigned(nitems)), b = dim3(256);
   TC* u = static_cast<TC*>(ut);
-  if (nc == 16 && epi == 0) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 16, 0>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
-  else if (nc == 32 && epi == 0) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 32, 0>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
-  else if (nc == 16 && epi == 1) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 16, 1>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
-  else if (nc == 32 && epi == 1) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 32, 1>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
-  else if (nc == 16) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 16, 2>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
-  else if (nc == 32) hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, 32, 2>), g, b, 0, st, P, items, N, W, u, out, sc, pnN);
-  else {
-    set_error("internal: MFMA gemm_n needs 16 or 32 lambdas per pass");
-    return TIK_EINVAL;
+#define TIK_GN(NCV, EPIV)                                                                     \
+  if (nc == NCV && epi == EPIV) {                                                            \
+    hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, NCV, EPIV, RT>), g, b, 0, st, P, items, N, W, u, \
+                       out, sc, pnN);                                                        \
+    TIK_LAUNCHED("k_gemm_n_mfma");                                                           \
+    return TIK_OK;                                                                           \
   }
-  TIK_LAUNCHED("k_gemm_n_mfma");
-  return TIK_OK;
+  TIK_GN(16, 0) TIK_GN(32, 0) TIK_GN(16, 1) TIK_GN(32, 1) TIK_GN(16, 2) TIK_GN(32, 2)
+#undef TIK_GN
+  set_error("internal: MFMA gemm_n needs 16 or 32 lambdas per pass");
+  return TIK_EINVAL;
 }
 
-int launch_gemm_n_mfma(int ta_f32, int tc_f32, int nc, int epi, const DevProb* P,
+template <typename TA, typename TC>
+static int gemm_n_nc(int rows, int nc, int epi, const DevProb* P, const Item* items, int nitems,
+                     int N, const double* W, void* ut, double* out, const Scal* sc, double* pnN,
+                     hipStream_t st) {
+  if (rows == 128) return gemm_n_rt<TA, TC, 2>(nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
+  if (rows == 256) return gemm_n_rt<TA, TC, 4>(nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
+  set_error("internal: MFMA gemm_n blocks are 128 or 256 rows");
+  return TIK_EINVAL;
+}
+
+int launch_gemm_n_mfma(int ta_f32, int tc_f32, int nc, int epi, int rows, const DevProb* P,
                        const Item* items, int nitems, int N, const double* W, void* ut,
                        double* out, const Scal* sc, double* pnN, hipStream_t st) {
   if (tc_f32) {
@@ -311,30 +317,33 @@ int launch_gemm_n_mfma(int ta_f32, int tc_f32, int nc, int epi, const DevProb* P
       set_error("internal: FP32 products need FP32 storage");
       return TIK_EINVAL;
     }
-    return gemm_n_nc<float, float>(nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
+    return gemm_n_nc<float, float>(rows, nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
   }
-  if (ta_f32) return gemm_n_nc<float, double>(nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
-  return gemm_n_nc<double, double>(nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
+  if (ta_f32) return gemm_n_nc<float, double>(rows, nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
+  return gemm_n_nc<double, double>(rows, nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
 }
 
 template <typename TA, typename TC, typename TU>
-static int gemm_t_nc(int nc, const DevProb* P, const Item* items, int nitems, int N,
+static int gemm_t_nc(int cols, int nc, const DevProb* P, const Item* items, int nitems, int N,
                      const void* U, void* part, hipStream_t st) {
   const dim3 g = dim3(unsigned(((nitems + 7) / 8) * 8)), b = dim3(256);
   const TU* u = static_cast<const TU*>(U);
   TC* pt = static_cast<TC*>(part);
-  if (nc == 16) hipLaunchKernelGGL((k_gemm_t_mfma<TA, TC, TU, 16>), g, b, 0, st, P, items, nitems, N, u, pt);
-  else if (nc == 32) hipLaunchKernelGGL((k_gemm_t_mfma<TA, TC, TU, 32>), g, b, 0, st, P, items, nitems, N, u, pt);
-  else {
-    set_error("internal: MFMA gemm_t needs 16 or 32 lambdas per pass");
-    return TIK_EINVAL;
+#define TIK_GT(NCV, CBV)                                                                       \
+  if (nc == NCV && cols == CBV) {                                                             \
+    hipLaunchKernelGGL((k_gemm_t_mfma<TA, TC, TU, NCV, CBV>), g, b, 0, st, P, items, nitems, N, \
+                       u, pt);                                                                \
+    TIK_LAUNCHED("k_gemm_t_mfma");                                                            \
+    return TIK_OK;                                                                            \
   }
-  TIK_LAUNCHED("k_gemm_t_mfma");
-  return TIK_OK;
+  TIK_GT(16, 64) TIK_GT(32, 64) TIK_GT(16, 128) TIK_GT(32, 128)
+#undef TIK_GT
+  set_error("internal: MFMA gemm_t needs 16 or 32 lambdas and 64 or 128 columns per block");
+  return TIK_EINVAL;
 }
 
 // U in TC (LSQR vectors) or FP64 (u_f64 = 1: refinement residuals, TC = double).
-int launch_gemm_t_mfma(int ta_f32, int tc_f32, int u_f64, int nc, const DevProb* P,
+int launch_gemm_t_mfma(int ta_f32, int tc_f32, int u_f64, int nc, int cols, const DevProb* P,
                        const Item* items, int nitems, int N, const void* U, void* part,
                        hipStream_t st) {
   if (tc_f32) {
@@ -342,11 +351,11 @@ int launch_gemm_t_mfma(int ta_f32, int tc_f32, int u_f64, int nc, const DevProb*
       set_error("internal: FP32 products need FP32 storage");
       return TIK_EINVAL;
     }
-    if (u_f64) return gemm_t_nc<float, float, double>(nc, P, items, nitems, N, U, part, st);
-    return gemm_t_nc<float, float, float>(nc, P, items, nitems, N, U, part, st);
+    if (u_f64) return gemm_t_nc<float, float, double>(cols, nc, P, items, nitems, N, U, part, st);
+    return gemm_t_nc<float, float, float>(cols, nc, P, items, nitems, N, U, part, st);
   }
-  if (ta_f32) return gemm_t_nc<float, double, double>(nc, P, items, nitems, N, U, part, st);
-  return gemm_t_nc<double, double, double>(nc, P, items, nitems, N, U, part, st);
+  if (ta_f32) return gemm_t_nc<float, double, double>(cols, nc, P, items, nitems, N, U, part, st);
+  return gemm_t_nc<double, double, double>(cols, nc, P, items, nitems, N, U, part, st);
 }
 
 }  // namespace tik

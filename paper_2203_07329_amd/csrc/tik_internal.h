@@ -152,10 +152,11 @@ int launch_chol_inv_batched(const double* C, int64_t n, const double* lams, int3
                             hipStream_t st);
 
 // matrix-core products (k_mfma.hip)
-int launch_gemm_n_mfma(int ta_f32, int tc_f32, int nc, int epi, const DevProb* P,
+// rows: rows of A per gemm_n block (128 or 256); cols: columns per gemm_t block (64 or 128)
+int launch_gemm_n_mfma(int ta_f32, int tc_f32, int nc, int epi, int rows, const DevProb* P,
                        const Item* items, int nitems, int N, const double* W, void* ut,
                        double* out, const Scal* sc, double* pnN, hipStream_t st);
-int launch_gemm_t_mfma(int ta_f32, int tc_f32, int u_f64, int nc, const DevProb* P,
+int launch_gemm_t_mfma(int ta_f32, int tc_f32, int u_f64, int nc, int cols, const DevProb* P,
                        const Item* items, int nitems, int N, const void* U, void* part,
                        hipStream_t st);
 
