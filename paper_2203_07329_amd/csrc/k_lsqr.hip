@@ -993,10 +993,13 @@ int ilog2(int v) {
   return r;
 }
 
+// Lambda slots per pass: N rounded up to a power of two; 5 to 8 lambdas use
+// 16 slots so that the products run on the matrix cores (the passes are
+// bound by the reads of A, which do not grow with the padding).
 int pick_nc(int N) {
   int nc = 1;
   while (nc < N) nc <<= 1;
-  return nc;
+  return nc == 8 ? 16 : nc;
 }
 
 // Low-rank apply tables of one problem (k = its short dimension; V holds the
@@ -1055,8 +1058,12 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
   pl.totL = pl.totS = pl.totPT = pl.nbN = pl.nbB = pl.nbQ = 0;
   pl.lowrank = pc->route == TIK_ROUTE_LOWRANK;
   const int np = int(pidx.size());
-  int64_t colblocks = 0;
-  for (int lp = 0; lp < np; ++lp) colblocks += cdiv(probs[pidx[lp]].n, pl.cbT);
+  // gemm_t row chunks: one target length for the whole batch (about 2048
+  // blocks, at most 8192 rows each), so the blocks of large and small problems
+  // of a ragged batch are of similar length
+  int64_t work = 0;
+  for (int lp = 0; lp < np; ++lp) work += cdiv(probs[pidx[lp]].n, pl.cbT) * probs[pidx[lp]].m;
+  const int64_t rtarget = std::min<int64_t>(8192, std::max<int64_t>(512, cdiv(cdiv(work, 2048), 32) * 32));
   for (int lp = 0; lp < np; ++lp) {
     const tik_problem& g = probs[pidx[lp]];
     DevProb d = {};
@@ -1083,11 +1090,9 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
     d.pnN = pl.nbN;
     d.pnB = pl.nbB;
     d.pnQ = pl.nbQ;
-    // row chunks for gemm_t: aim for about 2048 blocks over the whole batch
     const int64_t cb = cdiv(g.n, pl.cbT);
-    int64_t nch = std::max<int64_t>(1, 2048 / std::max<int64_t>(1, colblocks));
-    nch = std::min<int64_t>(nch, cdiv(g.m, 32));
-    int64_t rch = cdiv(cdiv(g.m, nch), 32) * 32;
+    int64_t nch = cdiv(g.m, rtarget);
+    const int64_t rch = cdiv(cdiv(g.m, nch), 32) * 32;
     nch = cdiv(g.m, rch);
     d.rchunk = rch;
     d.nchT = int32_t(nch);
@@ -1120,6 +1125,31 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
                    [&](const Item& a, const Item& b) { return q_work(a) > q_work(b); });
   std::stable_sort(pl.itM.begin(), pl.itM.end(),
                    [&](const Item& a, const Item& b) { return m_work(a) > m_work(b); });
+  // product blocks of a ragged batch: the longest first (rows x columns of A)
+  auto t_work = [&](const Item& it) {
+    const DevProb& d = pl.P[size_t(it.p)];
+    return std::min(d.rchunk, d.m - int64_t(it.ch) * d.rchunk);
+  };
+  if (np > 1) {
+    std::stable_sort(pl.itT.begin(), pl.itT.end(),
+                     [&](const Item& a, const Item& b) { return t_work(a) > t_work(b); });
+    // k_gemm_t_mfma gives XCD x the item range [x per, (x + 1) per): deal the
+    // sorted items round-robin over those ranges so every XCD gets a similar
+    // mix, longest first
+    const size_t nit = pl.itT.size(), per = (nit + 7) / 8;
+    std::vector<Item> dealt(nit);
+    std::vector<size_t> fill(8, 0);
+    size_t x = 0;
+    for (size_t i = 0; i < nit; ++i) {
+      while (x * per + fill[x] >= std::min(nit, (x + 1) * per)) x = (x + 1) % 8;
+      dealt[x * per + fill[x]++] = pl.itT[i];
+      x = (x + 1) % 8;
+    }
+    pl.itT.swap(dealt);
+  }
+  std::stable_sort(pl.itN.begin(), pl.itN.end(), [&](const Item& a, const Item& b) {
+    return pl.P[size_t(a.p)].n > pl.P[size_t(b.p)].n;
+  });
   pl.J = np * N;
 }
 

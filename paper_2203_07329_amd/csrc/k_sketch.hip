@@ -452,13 +452,20 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
 // are rows 8 (v / 4) + 4 (l / 32) + v % 4 of column l % 32).  Tiles are staged in
 // LDS k-contiguous (row / column major over 32 k) so each operand is one
 // 16-byte read; the next tile is fetched into registers during the MFMAs.
+// Split K (grid.z > 1): block z covers k in [z ksz, (z + 1) ksz) and stores its
+// partial product to Y + z s ncol; k_sketch_reduce adds the slices in order.
 template <typename TA, bool WIDE>
 __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* __restrict__ X,
-                                                          int64_t s, int64_t kc,
+                                                          int64_t s, int64_t kc, int64_t ksz,
                                                           const TA* __restrict__ A, int64_t lda,
                                                           int64_t r0, int64_t ncol,
                                                           float* __restrict__ Y, int first) {
   constexpr int KB = 32, LP = KB + 8;     // k per step, LDS row pitch in bf16
+  const int64_t kb = int64_t(blockIdx.z) * ksz, ke = min(kc, kb + ksz);
+  if (gridDim.z > 1) {
+    Y += int64_t(blockIdx.z) * s * ncol;
+    first = 1;
+  }
   __shared__ __attribute__((aligned(16))) uint16_t Xs[128 * LP];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[128 * LP];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -484,13 +491,13 @@ __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* 
         uint4 v = make_uint4(0, 0, 0, 0);
         if (q < s) {
           const int64_t k = kk + h * 8;
-          if (k + 8 <= kc && ((kc & 7) == 0)) {
+          if (k + 8 <= ke && ((kc & 7) == 0)) {
             v = *reinterpret_cast<const uint4*>(X + q * kc + k);
           } else {
             uint16_t t[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-              t[e] = (k + e < kc) ? *reinterpret_cast<const uint16_t*>(X + q * kc + k + e) : 0;
+              t[e] = (k + e < ke) ? *reinterpret_cast<const uint16_t*>(X + q * kc + k + e) : 0;
             v = make_uint4(t[0] | (t[1] << 16), t[2] | (t[3] << 16), t[4] | (t[5] << 16),
                            t[6] | (t[7] << 16));
           }
@@ -504,7 +511,7 @@ __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* 
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int64_t k = k0 + half * 16 + e;
-        rb[e] = (c < ncol && k < kc) ? float(A[(r0 + k) + c * lda]) : 0.f;
+        rb[e] = (c < ncol && k < ke) ? float(A[(r0 + k) + c * lda]) : 0.f;
       }
     } else {
       const int kr = tid >> 3, cg = (tid & 7) * 16;
@@ -512,7 +519,7 @@ __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* 
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int64_t c = c0 + cg + e;
-        rb[e] = (c < ncol && k < kc) ? float(A[c + (r0 + k) * lda]) : 0.f;
+        rb[e] = (c < ncol && k < ke) ? float(A[c + (r0 + k) * lda]) : 0.f;
       }
     }
   };
@@ -539,11 +546,11 @@ __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* 
       }
     }
   };
-  fetch(0);
+  fetch(kb);
   stash();
   __syncthreads();
-  for (int64_t k0 = 0; k0 < kc; k0 += KB) {
-    const bool more = k0 + KB < kc;
+  for (int64_t k0 = kb; k0 < ke; k0 += KB) {
+    const bool more = k0 + KB < ke;
     if (more) fetch(k0 + KB);
 #pragma unroll
     for (int ks = 0; ks < KB / 16; ++ks) {
@@ -581,6 +588,16 @@ __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* 
           *dst = first ? acc[a][b][v] : *dst + acc[a][b][v];
         }
       }
+}
+
+// Y (count floats) = [Y +] sum_z part[z] in order z = 0, 1, ... (deterministic).
+__global__ void k_sketch_reduce(const float* __restrict__ part, int nz, int64_t count,
+                                float* __restrict__ Y, int first) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  float acc = first ? 0.f : Y[i];
+  for (int z = 0; z < nz; ++z) acc += part[int64_t(z) * count + i];
+  Y[i] = acc;
 }
 
 __global__ void k_f32_to_f64(const float* __restrict__ src, double* __restrict__ dst, int64_t n) {
@@ -689,20 +706,40 @@ int launch_sketch_gemm_f64(const double* Xc, int64_t s, int64_t kc, const void* 
   return TIK_OK;
 }
 
+// K splits of one BF16 sketch launch: enough blocks to fill the chip when the
+// output has few 128 x 128 tiles, at least 512 k per split, partial slices
+// within `part_cap` floats.
+int sketch_bf16_splits(int64_t s, int64_t ncol, int64_t kc, int64_t part_cap) {
+  const int64_t tiles = cdiv(s, 128) * cdiv(ncol, 128);
+  int64_t z = std::max<int64_t>(1, std::min<int64_t>(1024 / std::max<int64_t>(1, tiles), kc / 512));
+  if (z > 1) z = std::min<int64_t>(z, part_cap / std::max<int64_t>(1, s * ncol));
+  return int(std::max<int64_t>(1, z));
+}
+
 int launch_sketch_gemm_bf16(const void* Xc, int64_t s, int64_t kc, const void* A, int a_f32,
                             int64_t lda, int64_t r0, int64_t ncol, int wide, float* Yacc,
-                            int first, hipStream_t st) {
-  const dim3 grid = dim3(unsigned(cdiv(s, 128)), unsigned(cdiv(ncol, 128)));
+                            int first, float* part, int64_t part_cap, hipStream_t st) {
+  int nz = sketch_bf16_splits(s, ncol, kc, part_cap);
+  const int64_t ksz = cdiv(cdiv(kc, nz), 32) * 32;
+  nz = int(cdiv(kc, ksz));
+  float* dst = nz > 1 ? part : Yacc;
+  const dim3 grid = dim3(unsigned(cdiv(s, 128)), unsigned(cdiv(ncol, 128)), unsigned(nz));
   const __hip_bfloat16* X = static_cast<const __hip_bfloat16*>(Xc);
   ProfScope ps("sketch", st);
   if (a_f32) {
-    if (wide) hipLaunchKernelGGL((k_sketch_gemm_bf16<float, true>), grid, dim3(256), 0, st, X, s, kc, static_cast<const float*>(A), lda, r0, ncol, Yacc, first);
-    else      hipLaunchKernelGGL((k_sketch_gemm_bf16<float, false>), grid, dim3(256), 0, st, X, s, kc, static_cast<const float*>(A), lda, r0, ncol, Yacc, first);
+    if (wide) hipLaunchKernelGGL((k_sketch_gemm_bf16<float, true>), grid, dim3(256), 0, st, X, s, kc, ksz, static_cast<const float*>(A), lda, r0, ncol, dst, first);
+    else      hipLaunchKernelGGL((k_sketch_gemm_bf16<float, false>), grid, dim3(256), 0, st, X, s, kc, ksz, static_cast<const float*>(A), lda, r0, ncol, dst, first);
   } else {
-    if (wide) hipLaunchKernelGGL((k_sketch_gemm_bf16<double, true>), grid, dim3(256), 0, st, X, s, kc, static_cast<const double*>(A), lda, r0, ncol, Yacc, first);
-    else      hipLaunchKernelGGL((k_sketch_gemm_bf16<double, false>), grid, dim3(256), 0, st, X, s, kc, static_cast<const double*>(A), lda, r0, ncol, Yacc, first);
+    if (wide) hipLaunchKernelGGL((k_sketch_gemm_bf16<double, true>), grid, dim3(256), 0, st, X, s, kc, ksz, static_cast<const double*>(A), lda, r0, ncol, dst, first);
+    else      hipLaunchKernelGGL((k_sketch_gemm_bf16<double, false>), grid, dim3(256), 0, st, X, s, kc, ksz, static_cast<const double*>(A), lda, r0, ncol, dst, first);
   }
   TIK_LAUNCHED("k_sketch_gemm_bf16");
+  if (nz > 1) {
+    const int64_t count = s * ncol;
+    hipLaunchKernelGGL(k_sketch_reduce, dim3(unsigned(cdiv(count, 256))), dim3(256), 0, st, part,
+                       nz, count, Yacc, first);
+    TIK_LAUNCHED("k_sketch_reduce");
+  }
   return TIK_OK;
 }
 

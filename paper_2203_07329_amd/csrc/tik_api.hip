@@ -108,6 +108,7 @@ static int ilog2_ceil(int64_t v) {
 static constexpr int SRHT_MAX_K = 18;
 static constexpr int64_t SRHT_MAX_S = 16384;
 static constexpr size_t SCRATCH_CHUNK = size_t(256) << 20;
+static constexpr int64_t kBf16PartCap = int64_t(32) << 20;   // floats of split-K partials
 
 // --------------------------------------------------------------- sketch ----
 struct SketchPlan {
@@ -117,6 +118,8 @@ struct SketchPlan {
   double* T = nullptr;       // SRHT two-pass scratch
   double* Xc = nullptr;      // Gaussian X chunk (FP64 or BF16)
   float* Yacc = nullptr;     // BF16 sketches: FP32 accumulator
+  float* Ypart = nullptr;    // BF16 sketches: split-K partial products
+  int64_t part_cap = 0;      // floats in Ypart
   int64_t tcols = 0, kc = 0;
 };
 
@@ -155,13 +158,19 @@ static int sketch_plan(const tik_problem* p, int32_t nprob, int32_t embed, int32
     } else {
       const size_t esz = sdt == TIK_BF16 ? 2 : sizeof(double);
       xsz = std::max<int64_t>(xsz, int64_t(cdiv(gauss_chunk(p[k], s[k], sdt) * s[k] * esz, 8)));
-      if (sdt == TIK_BF16) ysz = std::max<int64_t>(ysz, s[k] * sp.ycols[k]);
+      if (sdt == TIK_BF16) {
+        ysz = std::max<int64_t>(ysz, s[k] * sp.ycols[k]);
+        const int64_t kc = gauss_chunk(p[k], s[k], sdt);
+        const int z = sketch_bf16_splits(s[k], sp.ycols[k], kc, kBf16PartCap);
+        if (z > 1) sp.part_cap = std::max<int64_t>(sp.part_cap, int64_t(z) * s[k] * sp.ycols[k]);
+      }
     }
   }
   if (rows_ints) sp.rows = a.take<int32_t>(size_t(rows_ints));
   if (tsz) sp.T = a.take<double>(size_t(tsz));
   if (xsz) sp.Xc = a.take<double>(size_t(xsz));
   if (ysz) sp.Yacc = a.take<float>(size_t(ysz));
+  if (sp.part_cap) sp.Ypart = a.take<float>(size_t(sp.part_cap));
   return TIK_OK;
 }
 
@@ -300,7 +309,7 @@ int tik_sketch(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sketc
           const int64_t kc = std::min(chunk, longdim - r0);
           TIK_TRY(launch_gauss_gen(pseed, s[k], r0, kc, sp.Xc, 1, st));
           TIK_TRY(launch_sketch_gemm_bf16(sp.Xc, s[k], kc, q.A, f32, q.lda, r0, ncol, t ? 0 : 1,
-                                          sp.Yacc, r0 == 0 ? 1 : 0, st));
+                                          sp.Yacc, r0 == 0 ? 1 : 0, sp.Ypart, sp.part_cap, st));
         }
         TIK_TRY(launch_f32_to_f64(sp.Yacc, sp.Y[k], s[k] * ncol, st));
       } else {
