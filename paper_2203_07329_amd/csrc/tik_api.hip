@@ -110,16 +110,77 @@ static constexpr int64_t SRHT_MAX_S = 16384;
 static constexpr size_t SCRATCH_CHUNK = size_t(256) << 20;
 static constexpr int64_t kBf16PartCap = int64_t(32) << 20;   // floats of split-K partials
 
+// ------------------------------------------------------------------ lanes --
+// The per-problem work of a batch (sketch, Gram, factorization) is a chain of
+// small launches per problem.  Problems are spread over up to kLanes streams
+// the library owns (default priority, created once per device), each with its
+// own scratch: forked from the caller's stream with an event, joined back with
+// one event per lane, so the caller sees ordinary stream order.
+static constexpr int kLanes = 4;
+
+namespace {
+std::mutex g_lane_mu;
+std::map<int, std::vector<hipStream_t>> g_lane_streams;
+
+struct Lanes {
+  hipStream_t main = nullptr;
+  int n = 1;
+  hipStream_t s[kLanes] = {};
+  hipEvent_t ev[kLanes + 1] = {};
+  bool forked = false;
+
+  int fork(hipStream_t st, int want) {
+    main = st;
+    n = std::max(1, std::min(kLanes, want));
+    s[0] = st;
+    if (n == 1) return TIK_OK;
+    int dev = 0;
+    TIK_HIP(hipGetDevice(&dev));
+    {
+      std::lock_guard<std::mutex> lk(g_lane_mu);
+      auto& pool = g_lane_streams[dev];
+      while (int(pool.size()) < kLanes) {
+        hipStream_t x;
+        TIK_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        pool.push_back(x);
+      }
+      for (int i = 0; i < n; ++i) s[i] = pool[size_t(i)];
+    }
+    for (int i = 0; i <= n; ++i) TIK_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    forked = true;
+    TIK_HIP(hipEventRecord(ev[n], st));
+    for (int i = 0; i < n; ++i) TIK_HIP(hipStreamWaitEvent(s[i], ev[n], 0));
+    return TIK_OK;
+  }
+  hipStream_t at(int k) const { return s[k % n]; }
+  int join() {
+    if (!forked) return TIK_OK;
+    forked = false;
+    for (int i = 0; i < n; ++i) {
+      TIK_HIP(hipEventRecord(ev[i], s[i]));
+      TIK_HIP(hipStreamWaitEvent(main, ev[i], 0));
+    }
+    for (int i = 0; i <= n; ++i) (void)hipEventDestroy(ev[i]);
+    return TIK_OK;
+  }
+  ~Lanes() {
+    if (forked) (void)join();
+  }
+};
+}  // namespace
+
 // --------------------------------------------------------------- sketch ----
 struct SketchPlan {
   std::vector<double*> Y;
   std::vector<int64_t> yrows, ycols;
-  int32_t* rows = nullptr;   // SRHT: rows | bucket starts | sign words
-  double* T = nullptr;       // SRHT two-pass scratch
-  double* Xc = nullptr;      // Gaussian X chunk (FP64 or BF16)
-  float* Yacc = nullptr;     // BF16 sketches: FP32 accumulator
-  float* Ypart = nullptr;    // BF16 sketches: split-K partial products
-  int64_t part_cap = 0;      // floats in Ypart
+  // scratch, one set per lane
+  int32_t* rows[kLanes] = {};   // SRHT: rows | bucket starts | sign words
+  double* T[kLanes] = {};       // SRHT two-pass scratch
+  double* Xc[kLanes] = {};      // Gaussian X chunk (FP64 or BF16)
+  float* Yacc[kLanes] = {};     // BF16 sketches: FP32 accumulator
+  float* Ypart[kLanes] = {};    // BF16 sketches: split-K partial products
+  int64_t part_cap = 0;         // floats in each Ypart
+  int lanes = 1;
   int64_t tcols = 0, kc = 0;
 };
 
@@ -166,11 +227,14 @@ static int sketch_plan(const tik_problem* p, int32_t nprob, int32_t embed, int32
       }
     }
   }
-  if (rows_ints) sp.rows = a.take<int32_t>(size_t(rows_ints));
-  if (tsz) sp.T = a.take<double>(size_t(tsz));
-  if (xsz) sp.Xc = a.take<double>(size_t(xsz));
-  if (ysz) sp.Yacc = a.take<float>(size_t(ysz));
-  if (sp.part_cap) sp.Ypart = a.take<float>(size_t(sp.part_cap));
+  sp.lanes = std::max(1, std::min<int>(kLanes, nprob));
+  for (int l = 0; l < sp.lanes; ++l) {
+    if (rows_ints) sp.rows[l] = a.take<int32_t>(size_t(rows_ints));
+    if (tsz) sp.T[l] = a.take<double>(size_t(tsz));
+    if (xsz) sp.Xc[l] = a.take<double>(size_t(xsz));
+    if (ysz) sp.Yacc[l] = a.take<float>(size_t(ysz));
+    if (sp.part_cap) sp.Ypart[l] = a.take<float>(size_t(sp.part_cap));
+  }
   return TIK_OK;
 }
 
@@ -273,21 +337,24 @@ int tik_sketch(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sketc
   size_t need = 0;
   TIK_TRY(tik_sketch_bytes(p, nprob, embed, sketch_dtype, s, &need));
   TIK_TRY(check_ws(dws, dws_bytes, need, "tik_sketch"));
-  hipStream_t st = static_cast<hipStream_t>(stream);
   Arena a;
   a.base = static_cast<char*>(dws);
   a.cap = dws_bytes;
   SketchPlan sp;
   TIK_TRY(sketch_plan(p, nprob, embed, sketch_dtype, s, a, sp));
+  Lanes lanes;
+  TIK_TRY(lanes.fork(static_cast<hipStream_t>(stream), sp.lanes));
   for (int32_t k = 0; k < nprob; ++k) {
     const tik_problem& q = p[k];
+    const int ln = k % lanes.n;
+    hipStream_t st = lanes.at(k);
     // problem k draws from its own stream of the generator
     const uint64_t pseed = seed ^ (uint64_t(uint32_t(k)) * 0x9E3779B97F4A7C15ull);
     const int f32 = q.a_dtype == TIK_F32;
     if (embed == TIK_SRHT) {
       const int kk = ilog2_ceil(q.m);
       const int bb = kk <= 13 ? kk : 13;
-      int32_t* rows = sp.rows;
+      int32_t* rows = sp.rows[ln];
       int32_t* bstart = rows + s[k];
       TIK_TRY(launch_srht_rows(pseed, kk, s[k], rows, bstart, bb, st));
       if (kk <= 13) {
@@ -295,7 +362,7 @@ int tik_sketch(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sketc
       } else {
         for (int64_t c0 = 0; c0 < q.n; c0 += sp.tcols) {
           const int64_t nc = std::min(sp.tcols, q.n - c0);
-          TIK_TRY(launch_srht_twopass(q.A, f32, q.m, q.lda, c0, nc, kk, bb, rows, s[k], sp.T,
+          TIK_TRY(launch_srht_twopass(q.A, f32, q.m, q.lda, c0, nc, kk, bb, rows, s[k], sp.T[ln],
                                       sp.Y[k], st));
         }
       }
@@ -307,22 +374,24 @@ int tik_sketch(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sketc
       if (sketch_dtype == TIK_BF16) {
         for (int64_t r0 = 0; r0 < longdim; r0 += chunk) {
           const int64_t kc = std::min(chunk, longdim - r0);
-          TIK_TRY(launch_gauss_gen(pseed, s[k], r0, kc, sp.Xc, 1, st));
-          TIK_TRY(launch_sketch_gemm_bf16(sp.Xc, s[k], kc, q.A, f32, q.lda, r0, ncol, t ? 0 : 1,
-                                          sp.Yacc, r0 == 0 ? 1 : 0, sp.Ypart, sp.part_cap, st));
+          TIK_TRY(launch_gauss_gen(pseed, s[k], r0, kc, sp.Xc[ln], 1, st));
+          TIK_TRY(launch_sketch_gemm_bf16(sp.Xc[ln], s[k], kc, q.A, f32, q.lda, r0, ncol, t ? 0 : 1,
+                                          sp.Yacc[ln], r0 == 0 ? 1 : 0, sp.Ypart[ln], sp.part_cap,
+                                          st));
         }
-        TIK_TRY(launch_f32_to_f64(sp.Yacc, sp.Y[k], s[k] * ncol, st));
+        TIK_TRY(launch_f32_to_f64(sp.Yacc[ln], sp.Y[k], s[k] * ncol, st));
       } else {
         TIK_HIP(hipMemsetAsync(sp.Y[k], 0, size_t(s[k]) * size_t(ncol) * sizeof(double), st));
         for (int64_t r0 = 0; r0 < longdim; r0 += chunk) {
           const int64_t kc = std::min(chunk, longdim - r0);
-          TIK_TRY(launch_gauss_gen(pseed, s[k], r0, kc, sp.Xc, 0, st));
-          TIK_TRY(launch_sketch_gemm_f64(sp.Xc, s[k], kc, q.A, f32, q.lda, r0, ncol, t ? 0 : 1,
+          TIK_TRY(launch_gauss_gen(pseed, s[k], r0, kc, sp.Xc[ln], 0, st));
+          TIK_TRY(launch_sketch_gemm_f64(sp.Xc[ln], s[k], kc, q.A, f32, q.lda, r0, ncol, t ? 0 : 1,
                                          sp.Y[k], st));
         }
       }
     }
   }
+  TIK_TRY(lanes.join());
   tik_sketch_s* h = new tik_sketch_s();
   h->probs.assign(p, p + nprob);
   h->embed = embed;
@@ -352,12 +421,14 @@ void tik_sketch_free(tik_sketch_t sk) { delete sk; }
 namespace {
 struct PrecondPlan {
   std::vector<double*> Rinv;
-  double* C = nullptr;
-  double* Dinv = nullptr;
-  double* Tmp = nullptr;
   double* lams = nullptr;
   int32_t* notpd = nullptr;
   double* cnorm = nullptr;    // per problem
+  int lanes = 1;
+  double* colsum_l[kLanes] = {};   // per lane: scratch, kmax
+  double* C_l[kLanes] = {};
+  double* Dinv_l[kLanes] = {};
+  double* Tmp_l[kLanes] = {};
   double* colsum = nullptr;   // scratch, kmax
   // low-rank route
   std::vector<double*> V, sigma, S;
@@ -401,9 +472,13 @@ int precond_plan(tik_sketch_t sk, int32_t route, int32_t N, Arena& a, PrecondPla
   pp.cnorm = a.take<double>(size_t(np));
   pp.colsum = a.take<double>(size_t(kmax));
   if (route == TIK_ROUTE_CHOL) {
-    pp.C = a.take<double>(size_t(kmax) * size_t(kmax));
-    pp.Dinv = a.take<double>(size_t(N) * size_t(cdiv(kmax, 64)) * 64 * 64);
-    pp.Tmp = a.take<double>(size_t(N) * size_t(kmax) * 64);
+    pp.lanes = std::max(1, std::min<int>(kLanes, np));
+    for (int l = 0; l < pp.lanes; ++l) {
+      pp.colsum_l[l] = l == 0 ? pp.colsum : a.take<double>(size_t(kmax));
+      pp.C_l[l] = a.take<double>(size_t(kmax) * size_t(kmax));
+      pp.Dinv_l[l] = a.take<double>(size_t(N) * size_t(cdiv(kmax, 64)) * 64 * 64);
+      pp.Tmp_l[l] = a.take<double>(size_t(N) * size_t(kmax) * 64);
+    }
   } else {
     pp.lr_scratch = a.take<double>(scratch);
     pp.perm = a.take<int32_t>(size_t(smax));
@@ -516,13 +591,18 @@ int tik_precond(tik_sketch_t sk, int32_t route, const double* lambdas, int32_t N
     TIK_TRY(precond_lowrank(sk, lambdas, N, alpha, pp, st, h.get()));
   } else {
     TIK_HIP(hipMemsetAsync(pp.notpd, 0, sizeof(int32_t) * size_t(np) * size_t(N), st));
+    Lanes lanes;
+    TIK_TRY(lanes.fork(st, pp.lanes));
     for (int32_t k = 0; k < np; ++k) {
       const int64_t kd = std::min(sk->probs[k].m, sk->probs[k].n);
-      TIK_TRY(launch_syrk(sk->Y[k], sk->yrows[k], kd, sk->yrows[k], pp.C, st));
-      TIK_TRY(launch_gram_norm_bound(pp.C, kd, pp.colsum, pp.cnorm + k, st));
-      TIK_TRY(launch_chol_inv_batched(pp.C, kd, pp.lams + size_t(k) * N, N, pp.Rinv[k], pp.Dinv,
-                                      pp.Tmp, pp.notpd + size_t(k) * N, st));
+      const int ln = k % lanes.n;
+      hipStream_t ls = lanes.at(k);
+      TIK_TRY(launch_syrk(sk->Y[k], sk->yrows[k], kd, sk->yrows[k], pp.C_l[ln], ls));
+      TIK_TRY(launch_gram_norm_bound(pp.C_l[ln], kd, pp.colsum_l[ln], pp.cnorm + k, ls));
+      TIK_TRY(launch_chol_inv_batched(pp.C_l[ln], kd, pp.lams + size_t(k) * N, N, pp.Rinv[k],
+                                      pp.Dinv_l[ln], pp.Tmp_l[ln], pp.notpd + size_t(k) * N, ls));
     }
+    TIK_TRY(lanes.join());
     std::vector<int32_t> bad(size_t(np) * size_t(N), 0);
     std::vector<double> cn(size_t(np), 0.0);
     TIK_HIP(hipMemcpyAsync(bad.data(), pp.notpd, sizeof(int32_t) * bad.size(),
