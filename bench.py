@@ -89,6 +89,28 @@ def build_workload(name, tik, W, dev):
 
 
 MAXIT = 300
+FAMILY_KERNEL = {"gemm_n": "k_gemm_n", "gemm_t": "k_gemm_t", "trmv": "k_trmv<", "trmv_t": "k_trmv_t<",
+                 "lr_apply": "k_lr_"}
+
+
+def measured_traffic(workload, family):
+    """HBM bytes per launch of the family's kernel from the committed rocprofv3 counter record
+    (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE, scaled by a device-copy calibration),
+    or None when there is none or the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))[workload]
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        if h.hexdigest() != rec["source_sha256"]:
+            return None
+        key = FAMILY_KERNEL.get(family)
+        vals = [v for k, v in rec["bytes_per_dispatch"].items() if key and key in k]
+        return int(max(vals)) if vals else None
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def pick_mode(tik, pr, cfg, svec, lams, alpha, want):
@@ -278,8 +300,9 @@ def main() -> int:
         name, (ms_ps, launches, avg_ms) = dom
         ach = per_launch[name] / (avg_ms / 1000.0) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
-                "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(per_launch[name])}
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload, name),
+                "kernel": name, "avg_launch_ms": round(avg_ms, 4),
+                "algorithmic_bytes_per_launch": int(per_launch[name])}
 
     line = {
         "metric": METRIC,
