@@ -231,86 +231,330 @@ __global__ void k_lr_tmul(const double* __restrict__ T, int nb, const double* __
   }
 }
 
+// 2^-e (up = false) or 2^e (up = true) for the exponent e of the largest
+// entry recorded by k_lr_absmax (|e| <= 1000); 1 if it is zero or not finite.
+__device__ __forceinline__ double lr_pow2(const unsigned long long* mx, bool up) {
+  const double m = __longlong_as_double(static_cast<long long>(*mx));
+  if (!(m > 0.0) || !isfinite(m)) return 1.0;
+  const int e = min(1000, max(-1000, ilogb(m)));
+  return ldexp(1.0, up ? e : -e);
+}
+
 // Dst (c x c, ld c) = the transpose of the upper triangle of the factored
-// Src (leading c x c block, ld lds): lower triangular, zeros above.
+// Src (leading c x c block, ld lds): lower triangular, zeros above; times
+// lr_pow2(mx, false) when mx is given (an exact power-of-two scaling).
 __global__ void k_lr_get_rt(const double* __restrict__ Src, int64_t lds, int64_t c,
-                            double* __restrict__ Dst) {
+                            const unsigned long long* __restrict__ mx, double* __restrict__ Dst) {
+  const double sc = mx ? lr_pow2(mx, false) : 1.0;
   const int64_t total = c * c;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
        e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t i = e % c, j = e / c;            // Dst(i, j) = Src(j, i) for j <= i
-    Dst[e] = j <= i ? Src[j + i * lds] : 0.0;
+    const int64_t i = e % c, j = e / c;            // Dst(i, j) = Src(j, i) sc for j <= i
+    Dst[e] = j <= i ? Src[j + i * lds] * sc : 0.0;
   }
 }
 
-// One round of one-sided Jacobi on the columns of G (s x s, ld s): one
-// workgroup per column pair of the round-robin schedule over sp = s rounded up
-// to even.  Pair 0 is (r, sp - 1); pair i > 0 is ((r + i) mod (sp - 1),
-// (r - i) mod (sp - 1)), so the pairs of a round are disjoint.  Both columns
-// are held in registers (EPT entries per thread, s <= 256 EPT): one read, one
-// write.  A pair is rotated when |g_p . g_q| > tol sqrt(|g_p|^2 |g_q|^2); the
-// number of rotations is added to *count.
-template <int EPT>
-__global__ void __launch_bounds__(256) k_lr_jrot(double* __restrict__ G, int64_t s, int sp, int r,
-                                                 double tol, unsigned int* __restrict__ count) {
-  __shared__ double red[3][4];
-  const int pair = blockIdx.x;
-  const int m = sp - 1;
-  int p, q;
-  if (pair == 0) {
-    p = r;
-    q = m;
-  } else {
-    p = (r + pair) % m;
-    q = ((r - pair) % m + m) % m;
-  }
-  if (p >= s || q >= s) return;   // the padding column (uniform over the block)
-  double* __restrict__ gp = G + int64_t(p) * s;
-  double* __restrict__ gq = G + int64_t(q) * s;
-  double x[EPT], y[EPT];
-  double a = 0.0, b = 0.0, c = 0.0;
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int64_t i = threadIdx.x + int64_t(e) * 256;
-    x[e] = i < s ? gp[i] : 0.0;
-    y[e] = i < s ? gq[i] : 0.0;
-  }
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    a = fma(x[e], x[e], a);
-    b = fma(y[e], y[e], b);
-    c = fma(x[e], y[e], c);
-  }
-  a = lr_wave_sum(a);
-  b = lr_wave_sum(b);
-  c = lr_wave_sum(c);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) {
-    red[0][wv] = a;
-    red[1][wv] = b;
-    red[2][wv] = c;
-  }
-  __syncthreads();
-  a = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
-  b = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
-  c = (red[2][0] + red[2][1]) + (red[2][2] + red[2][3]);
-  if (!(fabs(c) > tol * sqrt(a * b))) return;
-  const double zeta = (b - a) / (2.0 * c);
-  const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int64_t i = threadIdx.x + int64_t(e) * 256;
-    if (i < s) {
-      gp[i] = cs * x[e] - sn * y[e];
-      gq[i] = sn * x[e] + cs * y[e];
+// Block one-sided Jacobi on the columns of G (s x s, ld s).  Columns in
+// blocks of 16; block pairs in round-robin order over nbp = ceil(s / 16)
+// rounded up to even (the scalar round-robin schedule, on blocks).  A visit of
+// a pair (I, J) replaces the 32 columns C = [C_I C_J] by C Q, Q orthogonal with
+// Q^T (C^T C) Q diagonal to the accuracy of one cyclic Jacobi sweep over the
+// 32 x 32 Gram matrix.  Each visit is spread over K workgroups, each owning a
+// contiguous range of rows_per rows, in two launches per round:
+//   k_lr_bgram   partial Gram matrices of the row ranges (FP64 MFMA);
+//   k_lr_bapply  their sum in a fixed order, the local Jacobi sweep (the same
+//                arithmetic in every workgroup of the pair, so the same Q),
+//                then C Q on its row range.
+// ver[b] counts the changes of block b; clean[2 (a nbp + b)] holds (ver[a],
+// ver[b]) (a < b) from the last visit of the pair that found nothing to
+// rotate: a visit with the same versions is skipped (its columns are the ones
+// already checked; k_lr_bgram records the decision in flag[pair] for
+// k_lr_bapply).  A visit rotating anything adds 1 to *count.  Columns beyond s
+// (the last block, the padding block) read as zero and are never written.
+typedef double lr_f64x4 __attribute__((ext_vector_type(4)));
+
+struct LrPair {
+  int I, J;
+  __device__ LrPair(int nbp, int r, int pair) {
+    const int m = nbp - 1;
+    if (pair == 0) {
+      I = r;
+      J = m;
+    } else {
+      I = (r + pair) % m;
+      J = ((r - pair) % m + m) % m;
     }
   }
-  if (threadIdx.x == 0) atomicAdd(count, 1u);
+  __device__ int64_t col(int t) const {
+    return t < 16 ? int64_t(I) * 16 + t : int64_t(J) * 16 + (t - 16);
+  }
+};
+
+// Rows [r0, r0 + CH) of the pair's 32 columns (zero at or beyond rhi or s):
+// thread tid holds CH / 8 of them, 64 consecutive rows of a column per wave.
+template <int CH>
+__device__ __forceinline__ void lr_fetch(double (&pf)[CH / 8], const double* __restrict__ G,
+                                         int64_t s, const LrPair& P, int64_t r0, int64_t rhi,
+                                         int tid) {
+#pragma unroll
+  for (int q = 0; q < CH / 8; ++q) {
+    const int e = tid + 256 * q, col = e / CH, row = e % CH;
+    const int64_t c = P.col(col);
+    pf[q] = (r0 + row < rhi && c < s) ? G[(r0 + row) + c * s] : 0.0;
+  }
 }
+template <int CH>
+__device__ __forceinline__ void lr_stash(double (*T)[33], const double (&pf)[CH / 8], int tid) {
+#pragma unroll
+  for (int q = 0; q < CH / 8; ++q) {
+    const int e = tid + 256 * q;
+    T[e % CH][e / CH] = pf[q];
+  }
+}
+
+__device__ __forceinline__ void lr_pair(int x, int rr, int& p, int& q) {
+  if (x == 0) {
+    p = rr;
+    q = 31;
+  } else {
+    p = (rr + x) % 31;
+    q = (rr - x + 31) % 31;
+  }
+}
+
+// 1 / x and 1 / sqrt(x) from the hardware estimates and two Newton steps
+// each (the estimates carry about half the significand; each step doubles
+// it).  For normal x > 0 (lr_rsq) and normal x (lr_rcp).
+__device__ __forceinline__ double lr_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double lr_rsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double e = fma(-h * y, y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-h * y, y, 0.5);
+  return fma(y, e, y);
+}
+
+// Rotation zeroing g_pq of the symmetric 2 x 2 [[gpp, gpq], [gpq, gqq]]
+// (new column p = c p - sn q, new column q = sn p + c q), taken when
+// |g_pq| > tol sqrt(g_pp g_qq) and |g_pq| > 1e-300: tau = (g_qq - g_pp) /
+// (2 g_pq), t the root of t^2 + 2 tau t - 1 = 0 of smaller magnitude,
+// c = 1 / sqrt(1 + t^2), sn = t c.  Branch-free: a zero column fails the test
+// (0 * inf is NaN), |tau| is clamped at 1e150 (t below 1e-150 either way),
+// and whatever the unused arithmetic gives is discarded.  The columns were
+// scaled so that the largest entry lies in [1, 2): a column needing the
+// 1e-300 floor is negligible against it.
+__device__ __forceinline__ bool lr_rot(double gpp, double gqq, double gpq, double tol, double& c,
+                                       double& sn) {
+  const double agpq = fabs(gpq);
+  const bool on = agpq > 1e-300 && agpq * __builtin_amdgcn_rsq(gpp) * __builtin_amdgcn_rsq(gqq) > tol;
+  const double tau = (gqq - gpp) * lr_rcp(2.0 * gpq);
+  const double at = fmin(fabs(tau), 1e150);
+  const double w = 1.0 + at * at;
+  const double t = copysign(lr_rcp(at + w * lr_rsq(w)), tau);
+  const double cc = lr_rsq(1.0 + t * t);
+  c = on ? cc : 1.0;
+  sn = on ? t * cc : 0.0;
+  return on;
+}
+
+template <int CH>
+__global__ void __launch_bounds__(256) k_lr_bgram(const double* __restrict__ G, int64_t s, int nbp,
+                                                  int r, int K, int64_t rows_per,
+                                                  const int* __restrict__ ver,
+                                                  const int* __restrict__ clean,
+                                                  int* __restrict__ flag, double* __restrict__ part) {
+  static_assert(CH % 128 == 0, "chunk rows: a multiple of 128");
+  __shared__ double T[CH][33];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int pair = blockIdx.x / K, k = blockIdx.x % K;
+  const LrPair P(nbp, r, pair);
+  const int ba = min(P.I, P.J), bb = max(P.I, P.J);
+  const int* const cl = clean + 2 * (int64_t(ba) * nbp + bb);
+  const bool skip = cl[0] == ver[ba] && cl[1] == ver[bb];
+  if (k == 0 && tid == 0) flag[pair] = skip ? 1 : 0;
+  if (skip) return;                          // uniform
+  const int64_t rlo = int64_t(k) * rows_per, rhi = min(s, rlo + rows_per);
+  // one 16 x 16 tile of C^T C per wave; four accumulator chains, operands
+  // read from LDS eight steps at a time
+  const int wr = 16 * (wv & 1), wc = 16 * (wv >> 1);
+  lr_f64x4 acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = lr_f64x4{0, 0, 0, 0};
+  double pf[CH / 8];
+  lr_fetch<CH>(pf, G, s, P, rlo, rhi, tid);
+  for (int64_t r0 = rlo; r0 < rhi; r0 += CH) {
+    lr_stash<CH>(T, pf, tid);
+    __syncthreads();
+    if (r0 + CH < rhi) lr_fetch<CH>(pf, G, s, P, r0 + CH, rhi, tid);
+    for (int kb = 0; kb < CH / 4; kb += 8) {
+      double x[8], y[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        x[j] = T[4 * (kb + j) + lk][wr + li];
+        y[j] = T[4 * (kb + j) + lk][wc + li];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        acc[j & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[j], y[j], acc[j & 3], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* const out = part + (int64_t(pair) * K + k) * 1024;
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    out[(wr + 4 * v + lk) * 32 + wc + li] = (acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v]);
+}
+
+template <int CH>
+__global__ void __launch_bounds__(256) k_lr_bapply(double* __restrict__ G, int64_t s, int nbp, int r,
+                                                   int K, int64_t rows_per, double tol,
+                                                   int* __restrict__ ver, int* __restrict__ clean,
+                                                   const int* __restrict__ flag,
+                                                   const double* __restrict__ part,
+                                                   unsigned int* __restrict__ count) {
+  static_assert(CH % 128 == 0, "chunk rows: a multiple of 128");
+  __shared__ double T[CH][33];
+  __shared__ double Gs[2][32][33];
+  __shared__ double Qs[32][33];
+  __shared__ int rot;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int pair = blockIdx.x / K, k = blockIdx.x % K;
+  if (flag[pair]) return;                    // uniform
+  const LrPair P(nbp, r, pair);
+  // 1. the Gram matrix: partial sums in a fixed order
+  const double* const pp = part + int64_t(pair) * K * 1024;
+  for (int e = tid; e < 1024; e += 256) {
+    double g = pp[e];
+    for (int kk = 1; kk < K; ++kk) g += pp[int64_t(kk) * 1024 + e];
+    Gs[0][e >> 5][e & 31] = g;
+    Qs[e >> 5][e & 31] = (e >> 5) == (e & 31) ? 1.0 : 0.0;
+  }
+  if (tid == 0) rot = 0;
+  __syncthreads();
+  // 2. one cyclic Jacobi sweep on it: G <- J^T G J, Q <- Q J.  Each round
+  // rotates 16 disjoint pairs; thread (xa, xb) forms the 2 x 2 block of the
+  // pairs xa (rows) and xb (columns) from the previous round's copy, and
+  // rotates columns (pb, qb) of Q in rows 2 xa, 2 xa + 1.
+  const int xa = tid >> 4, xb = tid & 15;
+  int cur = 0;
+  for (int rr = 0; rr < 31; ++rr) {
+    int pa, qa, pb, qb;
+    lr_pair(xa, rr, pa, qa);
+    lr_pair(xb, rr, pb, qb);
+    const double(*g)[33] = Gs[cur];
+    const double apa = g[pa][pa], aqa = g[qa][qa], ao = g[pa][qa];
+    const double bpb = g[pb][pb], bqb = g[qb][qb], bo = g[pb][qb];
+    const double g1 = g[pa][pb], g2 = g[pa][qb], g3 = g[qa][pb], g4 = g[qa][qb];
+    const double q1 = Qs[2 * xa][pb], q2 = Qs[2 * xa][qb];
+    const double q3 = Qs[2 * xa + 1][pb], q4 = Qs[2 * xa + 1][qb];
+    double ca, sa, cb, sb;
+    const bool on_a = lr_rot(apa, aqa, ao, tol, ca, sa);
+    lr_rot(bpb, bqb, bo, tol, cb, sb);
+    const double xpp = cb * g1 - sb * g2, xpq = sb * g1 + cb * g2;
+    const double xqp = cb * g3 - sb * g4, xqq = sb * g3 + cb * g4;
+    double(*h)[33] = Gs[cur ^ 1];
+    h[pa][pb] = ca * xpp - sa * xqp;
+    h[qa][pb] = sa * xpp + ca * xqp;
+    h[pa][qb] = ca * xpq - sa * xqq;
+    h[qa][qb] = sa * xpq + ca * xqq;
+    Qs[2 * xa][pb] = cb * q1 - sb * q2;
+    Qs[2 * xa][qb] = sb * q1 + cb * q2;
+    Qs[2 * xa + 1][pb] = cb * q3 - sb * q4;
+    Qs[2 * xa + 1][qb] = sb * q3 + cb * q4;
+    if (on_a && xb == 0) rot = 1;
+    cur ^= 1;
+    __syncthreads();
+  }
+  if (!rot) {                                // uniform: read after the barrier above
+    if (k == 0 && tid == 0) {
+      const int ba = min(P.I, P.J), bb = max(P.I, P.J);
+      int* const cl = clean + 2 * (int64_t(ba) * nbp + bb);
+      cl[0] = ver[ba];
+      cl[1] = ver[bb];
+    }
+    return;
+  }
+  // 3. C <- C Q on this workgroup's rows, computed transposed (Q^T C^T) so
+  // that 16 consecutive lanes store 16 consecutive rows of one column
+  const int64_t rlo = int64_t(k) * rows_per, rhi = min(s, rlo + rows_per);
+  const int oc = 16 * (wv & 1), rh = (CH / 2) * (wv >> 1);
+  double qv[8];                              // this wave's Q^T operand, all 8 steps
+#pragma unroll
+  for (int ks = 0; ks < 8; ++ks) qv[ks] = Qs[4 * ks + lk][oc + li];
+  double pf[CH / 8];
+  lr_fetch<CH>(pf, G, s, P, rlo, rhi, tid);
+  for (int64_t r0 = rlo; r0 < rhi; r0 += CH) {
+    lr_stash<CH>(T, pf, tid);
+    __syncthreads();
+    if (r0 + CH < rhi) lr_fetch<CH>(pf, G, s, P, r0 + CH, rhi, tid);
+    // four row tiles at a time: four independent accumulator chains
+#pragma unroll
+    for (int rt = 0; rt < CH / 32; rt += 4) {
+      lr_f64x4 o[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) o[u] = lr_f64x4{0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
+        double y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y[u] = T[rh + 16 * (rt + u) + li][4 * ks + lk];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          o[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(qv[ks], y[u], o[u], 0, 0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t row = r0 + rh + 16 * (rt + u) + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t c = P.col(oc + 4 * v + lk);
+          if (row < rhi && c < s) G[row + c * s] = o[u][v];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (k == 0 && tid == 0) {
+    ver[P.I] += 1;
+    ver[P.J] += 1;
+    atomicAdd(count, 1u);
+  }
+}
+
+// Largest |Src(j, i)|, j <= i (the upper triangle of Src, c x c, ld lds), as
+// the bit pattern of a non-negative double, into *mx (which starts at 0).
+__global__ void __launch_bounds__(256) k_lr_absmax(const double* __restrict__ Src, int64_t lds,
+                                                   int64_t c, unsigned long long* __restrict__ mx) {
+  __shared__ double red[4];
+  double m = 0.0;
+  const int64_t total = c * c;
+  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
+    const int64_t i = e % c, j = e / c;
+    if (j <= i) m = fmax(m, fabs(Src[j + i * lds]));
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    atomicMax(mx, static_cast<unsigned long long>(__double_as_longlong(m)));
+  }
+}
+
 
 // sigma_j = ||g_j||, g_j /= sigma_j (one block per column).
 __global__ void __launch_bounds__(256) k_lr_normalize(double* __restrict__ G, int64_t s,
+                                                      const unsigned long long* __restrict__ mx,
                                                       double* __restrict__ sig) {
   __shared__ double red[4];
   double* g = G + int64_t(blockIdx.x) * s;
@@ -319,7 +563,7 @@ __global__ void __launch_bounds__(256) k_lr_normalize(double* __restrict__ G, in
   const double nrm = sqrt(lr_block_sum<256>(ss, red));
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
   for (int64_t i = threadIdx.x; i < s; i += 256) g[i] *= inv;
-  if (threadIdx.x == 0) sig[blockIdx.x] = nrm;
+  if (threadIdx.x == 0) sig[blockIdx.x] = nrm * lr_pow2(mx, true);
 }
 
 // Descending order of sigma (bitonic sort of (sigma, index) in LDS, s <= 4096);
@@ -531,9 +775,24 @@ static int qr_apply_q(const double* Z, int64_t rows, int64_t cols, int64_t ldz, 
   return TIK_OK;
 }
 
+// Block Jacobi bookkeeping, in doubles: the scaling maximum (1), the partial
+// Gram matrices (npairs K <= kLrWg of them, 1024 each), then ints: ver (nbp),
+// clean (2 nbp^2) and flag (nbp / 2).
+constexpr int kLrWg = 256;
+static int64_t lr_nbp(int64_t s) {
+  const int64_t nblk = cdiv(s, 16);
+  return nblk + (nblk & 1);
+}
+static size_t lr_book_doubles(int64_t s) {
+  const int64_t nbp = lr_nbp(s);
+  return size_t(1 + int64_t(kLrWg) * 1024 + cdiv(nbp + 2 * nbp * nbp + nbp / 2, 2));
+}
+
 size_t lowrank_scratch_doubles(int64_t n, int64_t s) {
-  // Z (n s) + Z2 (s s) + L (s s) + sig_raw (s) + QR workspaces of n x s and s x s
-  return size_t(n * s + 2 * s * s + s) + qr_ws_doubles(n, s) + qr_ws_doubles(s, s) + 64;
+  // Z (n s) + Z2 (s s) + L (s s) + sig_raw (s) + QR workspaces of n x s and
+  // s x s + the block Jacobi bookkeeping
+  return size_t(n * s + 2 * s * s + s) + qr_ws_doubles(n, s) + qr_ws_doubles(s, s) +
+         lr_book_doubles(s) + 64;
 }
 
 // V (n x s, ld n, columns by decreasing sigma) and sigma (s) of Y (s x n, ld s).
@@ -552,6 +811,10 @@ int launch_lowrank_svd(const double* Y, int64_t s, int64_t n, double* V, double*
   double* sig_raw = L + s * s;       // s
   const QrWs w1 = qr_ws_carve(sig_raw + s, n, s);
   const QrWs w2 = qr_ws_carve(sig_raw + s + qr_ws_doubles(n, s), s, s);
+  double* const book = sig_raw + s + qr_ws_doubles(n, s) + qr_ws_doubles(s, s);
+  unsigned long long* const mx = reinterpret_cast<unsigned long long*>(book);
+  double* const part = book + 1;
+  int* const ver = reinterpret_cast<int*>(part + int64_t(kLrWg) * 1024);
   {
     ProfScope ps_qr("lr_qr", st);
     // 1. Y^T = Q1 R1
@@ -560,32 +823,43 @@ int launch_lowrank_svd(const double* Y, int64_t s, int64_t n, double* V, double*
     TIK_LAUNCHED("k_lr_transpose");
     TIK_TRY(qr_factor(Z, n, s, n, w1, st));
     // 2. R1^T = Q2 R2, L = R2^T
-    hipLaunchKernelGGL(k_lr_get_rt, dim3(lr_grid(s * s)), dim3(256), 0, st, Z, n, s, Z2);
+    hipLaunchKernelGGL(k_lr_get_rt, dim3(lr_grid(s * s)), dim3(256), 0, st, Z, n, s,
+                       static_cast<const unsigned long long*>(nullptr), Z2);
     TIK_LAUNCHED("k_lr_get_rt");
     TIK_TRY(qr_factor(Z2, s, s, s, w2, st));
-    hipLaunchKernelGGL(k_lr_get_rt, dim3(lr_grid(s * s)), dim3(256), 0, st, Z2, s, s, L);
+    // L = R2^T scaled by a power of two so that its largest entry lies in
+    // [1, 2): the Gram entries of the rotations stay clear of under- and
+    // overflow whatever the scale of A; sigma is scaled back exactly
+    TIK_HIP(hipMemsetAsync(mx, 0, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_lr_absmax, dim3(lr_grid(s * s)), dim3(256), 0, st, Z2, s, s, mx);
+    TIK_LAUNCHED("k_lr_absmax");
+    hipLaunchKernelGGL(k_lr_get_rt, dim3(lr_grid(s * s)), dim3(256), 0, st, Z2, s, s,
+                       static_cast<const unsigned long long*>(mx), L);
     TIK_LAUNCHED("k_lr_get_rt");
   }
   // 3. one-sided Jacobi on the columns of L
-  const int sp = int(s + (s & 1));
   const double tol = 1e-15 * std::sqrt(double(s));
   int sweeps = 0;
   const int maxsweeps = 30;
-  const int ept = s <= 256 ? 1 : s <= 512 ? 2 : s <= 1024 ? 4 : s <= 2048 ? 8 : 16;
+  const int nbp = int(lr_nbp(s)), npairs = nbp / 2;
+  // workgroups per visit: about kLrWg in all, at least 128 rows each
+  const int K = std::max(1, std::min(kLrWg / npairs, int(cdiv(s, 128))));
+  const int64_t rows_per = cdiv(cdiv(s, K), 32) * 32;
+  int* const clean = ver + nbp;
+  int* const flag = clean + 2 * nbp * nbp;
+  TIK_HIP(hipMemsetAsync(ver, 0, sizeof(int) * size_t(nbp), st));
+  TIK_HIP(hipMemsetAsync(clean, 0xff, sizeof(int) * 2 * size_t(nbp) * size_t(nbp), st));
+  const dim3 grid(unsigned(npairs * K));
   for (; sweeps < maxsweeps;) {
     ProfScope ps_sw("lr_sweep", st);
     TIK_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned int), st));
-    const dim3 g = dim3(unsigned(sp / 2));
-    for (int r = 0; r < sp - 1; ++r) {
-      switch (ept) {
-        case 1: hipLaunchKernelGGL(k_lr_jrot<1>, g, dim3(256), 0, st, L, s, sp, r, tol, cnt); break;
-        case 2: hipLaunchKernelGGL(k_lr_jrot<2>, g, dim3(256), 0, st, L, s, sp, r, tol, cnt); break;
-        case 4: hipLaunchKernelGGL(k_lr_jrot<4>, g, dim3(256), 0, st, L, s, sp, r, tol, cnt); break;
-        case 8: hipLaunchKernelGGL(k_lr_jrot<8>, g, dim3(256), 0, st, L, s, sp, r, tol, cnt); break;
-        default: hipLaunchKernelGGL(k_lr_jrot<16>, g, dim3(256), 0, st, L, s, sp, r, tol, cnt); break;
-      }
+    for (int r = 0; r < nbp - 1; ++r) {
+      hipLaunchKernelGGL(k_lr_bgram<128>, grid, dim3(256), 0, st, L, s, nbp, r, K, rows_per, ver,
+                         clean, flag, part);
+      hipLaunchKernelGGL(k_lr_bapply<128>, grid, dim3(256), 0, st, L, s, nbp, r, K, rows_per, tol, ver,
+                         clean, flag, part, cnt);
     }
-    TIK_LAUNCHED("k_lr_jrot");
+    TIK_LAUNCHED("k_lr_bapply");
     ++sweeps;
     unsigned int h = 0;
     TIK_HIP(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -593,7 +867,8 @@ int launch_lowrank_svd(const double* Y, int64_t s, int64_t n, double* V, double*
     if (h == 0) break;
   }
   if (sweeps_out) *sweeps_out = sweeps;
-  hipLaunchKernelGGL(k_lr_normalize, dim3(unsigned(s)), dim3(256), 0, st, L, s, sig_raw);
+  hipLaunchKernelGGL(k_lr_normalize, dim3(unsigned(s)), dim3(256), 0, st, L, s,
+                     static_cast<const unsigned long long*>(mx), sig_raw);
   TIK_LAUNCHED("k_lr_normalize");
   hipLaunchKernelGGL(k_lr_sort, dim3(1), dim3(1024), 0, st, sig_raw, s, perm, sig);
   TIK_LAUNCHED("k_lr_sort");
