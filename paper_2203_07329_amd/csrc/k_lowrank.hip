@@ -59,51 +59,87 @@ __global__ void k_lr_transpose(const double* __restrict__ Y, int64_t s, int64_t 
   }
 }
 
-// Householder vector of column j of Z (rows x *, ld ldz), as LAPACK dlarfg
-// defines it: on exit Z[j, j] = beta, Z[j+1:rows, j] = v (v_0 = 1 implied),
-// tau[j].  One block of 1024 threads.
+// dlarfg (as LAPACK defines it) on column c of Z, rows c .. rows-1, given
+// sigma = sum of squares of rows c+1 .. rows-1 and alpha = Z[c, c]: beta =
+// -sign(alpha) sqrt(alpha^2 + sigma), tau = (beta - alpha) / beta, v = x /
+// (alpha - beta) below the diagonal (v_0 = 1 implied).  Thread 0 writes
+// Z[c, c] = beta and tau[c] and returns the scale of v in *sh_scale (0: no
+// reflection, tau = 0).
+__device__ __forceinline__ void lr_house_head(double* col, int64_t c, double alpha, double sigma,
+                                              double* tau, double* sh_scale) {
+  if (sigma == 0.0) {
+    tau[c] = 0.0;
+    *sh_scale = 0.0;
+  } else {
+    const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+    tau[c] = (beta - alpha) / beta;
+    *sh_scale = 1.0 / (alpha - beta);
+    col[c] = beta;
+  }
+}
+
+// Rows lo + threadIdx.x + 1024 (u + U i) of a column: U independent loads per
+// thread and step.
+#define TIK_LR_ROWS(LO, ROWS, BODY)                                                   \
+  for (int64_t r0_ = (LO); r0_ < (ROWS); r0_ += 1024 * LR_U) {                        \
+    _Pragma("unroll") for (int u_ = 0; u_ < LR_U; ++u_) {                             \
+      const int64_t r = r0_ + threadIdx.x + 1024 * u_;                                \
+      if (r < (ROWS)) { BODY }                                                        \
+    }                                                                                 \
+  }
+constexpr int LR_U = 4;
+
+// Householder vector of column j of Z (rows x *, ld ldz): dlarfg on rows
+// j .. rows-1.  One block of 1024 threads.
 __global__ void __launch_bounds__(1024) k_lr_house(double* __restrict__ Z, int64_t ldz, int64_t rows,
                                                    int64_t j, double* __restrict__ tau) {
   __shared__ double red[16];
   __shared__ double sh_scale;
   double* col = Z + j * ldz;
   double ss = 0.0;
-  for (int64_t r = j + 1 + threadIdx.x; r < rows; r += blockDim.x) ss += col[r] * col[r];
+  TIK_LR_ROWS(j + 1, rows, { const double x = col[r]; ss += x * x; })
   const double sigma = lr_block_sum<1024>(ss, red);
-  if (threadIdx.x == 0) {
-    const double alpha = col[j];
-    if (sigma == 0.0) {
-      tau[j] = 0.0;
-      sh_scale = 0.0;
-    } else {
-      const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-      tau[j] = (beta - alpha) / beta;
-      sh_scale = 1.0 / (alpha - beta);
-      col[j] = beta;
-    }
-  }
+  if (threadIdx.x == 0) lr_house_head(col, j, col[j], sigma, tau, &sh_scale);
   __syncthreads();
   const double sc = sh_scale;
-  if (sc != 0.0)
-    for (int64_t r = j + 1 + threadIdx.x; r < rows; r += blockDim.x) col[r] *= sc;
+  if (sc != 0.0) TIK_LR_ROWS(j + 1, rows, { col[r] *= sc; })
 }
 
-// Apply H_j = I - tau v v^T to the columns j+1 .. j+gridDim.x of Z (one block
-// per column).
-__global__ void __launch_bounds__(256) k_lr_apply_house(double* __restrict__ Z, int64_t ldz,
-                                                        int64_t rows, int64_t j,
-                                                        const double* __restrict__ tau) {
-  __shared__ double red[4];
+// Apply H_j = I - tau_j v v^T to the columns j+1 .. j+gridDim.x of Z (one
+// block of 1024 threads per column).  With `next`, block 0 (column j+1) then
+// forms the Householder vector of its column (dlarfg on rows j+1 ..), so a
+// panel needs one launch per column.  Each thread rereads only rows it wrote.
+__global__ void __launch_bounds__(1024) k_lr_apply_house(double* __restrict__ Z, int64_t ldz,
+                                                         int64_t rows, int64_t j,
+                                                         double* __restrict__ tau, int next) {
+  __shared__ double red[16];
+  __shared__ double sh_alpha, sh_scale;
   const int64_t c = j + 1 + blockIdx.x;
   const double* v = Z + j * ldz;
   double* col = Z + c * ldz;
+  if (threadIdx.x == 0) sh_alpha = 0.0;      // (set again below when row c exists)
+  const double cj = col[j];                  // read before any thread writes it
+  const double tj = tau[j];
   double w = 0.0;
-  for (int64_t r = j + 1 + threadIdx.x; r < rows; r += 256) w += v[r] * col[r];
-  double tot = lr_block_sum<256>(w, red);
-  tot = (tot + col[j]) * tau[j];
-  if (threadIdx.x == 0) col[j] -= tot;
-  for (int64_t r = j + 1 + threadIdx.x; r < rows; r += 256) col[r] -= tot * v[r];
+  TIK_LR_ROWS(j + 1, rows, { w += v[r] * col[r]; })
+  const double tot = (lr_block_sum<1024>(w, red) + cj) * tj;
+  if (threadIdx.x == 0) col[j] = cj - tot;
+  const bool head = next && blockIdx.x == 0;
+  double ss = 0.0;
+  TIK_LR_ROWS(j + 1, rows, {
+    const double x = col[r] - tot * v[r];
+    col[r] = x;
+    if (r == c) sh_alpha = x;
+    else ss += x * x;
+  })
+  if (!head) return;                         // uniform over the block
+  const double sigma = lr_block_sum<1024>(ss, red);   // its barriers order sh_alpha
+  if (threadIdx.x == 0) lr_house_head(col, c, sh_alpha, sigma, tau, &sh_scale);
+  __syncthreads();
+  const double sc = sh_scale;
+  if (sc != 0.0) TIK_LR_ROWS(c + 1, rows, { col[r] *= sc; })
 }
+#undef TIK_LR_ROWS
 
 // Explicit panel V (rows k0..rows-1, nb columns, ld rows - k0): unit
 // diagonal, zeros above, the stored reflectors below.
@@ -122,58 +158,137 @@ __global__ void k_lr_copy_v(const double* __restrict__ Z, int64_t ldz, int64_t r
   }
 }
 
-// C (M x N, ld ldc) = alpha * op(A) B + beta * C_in, FP64, op = transpose when TA.
-// op(A) is M x K: A col-major K x M (TA) or M x K (!TA), lda; B col-major K x N, ldb.
-// Split over K: block z handles k in [z kc, (z+1) kc) and writes its own slice
-// part + z * ldc * N (alpha, no beta), reduced by k_lr_reduce.
-template <bool TA>
-__global__ void __launch_bounds__(256) k_lr_dgemm(int64_t M, int64_t N, int64_t K, int64_t kc,
-                                                  const double* __restrict__ A, int64_t lda,
-                                                  const double* __restrict__ B, int64_t ldb,
-                                                  double* __restrict__ part, int64_t ldc) {
-  __shared__ double As[16][64 + 1];
-  __shared__ double Bs[16][64 + 1];
-  const int tid = threadIdx.x, tm = tid & 15, tn = tid >> 4;
-  const int64_t m0 = int64_t(blockIdx.x) * 64, n0 = int64_t(blockIdx.y) * 64;
-  const int64_t kb = int64_t(blockIdx.z) * kc, ke = min(K, kb + kc);
-  double acc[4][4] = {};
-  for (int64_t k0 = kb; k0 < ke; k0 += 16) {
-    for (int e = tid; e < 16 * 64; e += 256) {
-      int kk, mm;
-      if (TA) { kk = e & 15; mm = e >> 4; } else { mm = e & 63; kk = e >> 6; }
-      const int64_t k = k0 + kk, mi = m0 + mm;
-      double v = 0.0;
-      if (k < ke && mi < M) v = TA ? A[k + mi * lda] : A[mi + k * lda];
-      As[kk][mm] = v;
+typedef double lr_qd4 __attribute__((ext_vector_type(4)));
+
+// part[ch] (nb x N, ld nb) = V^T Z over the rows [ch rpc, (ch + 1) rpc) of
+// [0, rr): V rr x nb (ld ldv, nb <= 32), Z rr x N (ld ldz).  FP64 MFMA: a
+// 32 x 64 output tile per workgroup, one 16-column slice per wave (both
+// 16-row halves of V^T), 32-row stages through LDS with the next stage's
+// loads in flight.  An empty row range writes zeros.
+__global__ void __launch_bounds__(256) k_lr_vtz(int64_t rr, int nb, int64_t N, int64_t rpc,
+                                                const double* __restrict__ V, int64_t ldv,
+                                                const double* __restrict__ Z, int64_t ldz,
+                                                double* __restrict__ part) {
+  __shared__ double Vs[32][33];
+  __shared__ double Zs[32][65];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t c0 = int64_t(blockIdx.x) * 64;
+  const int64_t klo = int64_t(blockIdx.y) * rpc, khi = min(rr, klo + rpc);
+  double pv[4], pz[8];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q, col = e >> 5, row = e & 31;
+      const int64_t k = k0 + row;
+      pv[q] = (k < khi && col < nb) ? V[k + col * ldv] : 0.0;
     }
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int kk = e & 15, nn = e >> 4;
-      const int64_t k = k0 + kk, ni = n0 + nn;
-      Bs[kk][nn] = (k < ke && ni < N) ? B[k + ni * ldb] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = tid + 256 * q, col = e >> 5, row = e & 31;
+      const int64_t k = k0 + row, j = c0 + col;
+      pz[q] = (k < khi && j < N) ? Z[k + j * ldz] : 0.0;
+    }
+  };
+  lr_qd4 acc[2] = {lr_qd4{0, 0, 0, 0}, lr_qd4{0, 0, 0, 0}};
+  fetch(klo);
+  for (int64_t k0 = klo; k0 < khi; k0 += 32) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      Vs[e & 31][e >> 5] = pv[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = tid + 256 * q;
+      Zs[e & 31][e >> 5] = pz[q];
     }
     __syncthreads();
+    if (k0 + 32 < khi) fetch(k0 + 32);
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
+    for (int ks = 0; ks < 8; ++ks) {
+      const double bz = Zs[4 * ks + lk][16 * wv + li];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tm + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tn + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+      for (int h = 0; h < 2; ++h)
+        acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[4 * ks + lk][16 * h + li], bz, acc[h], 0, 0, 0);
     }
     __syncthreads();
   }
-  double* C = part + int64_t(blockIdx.z) * ldc * N;
+  double* const out = part + int64_t(blockIdx.y) * nb * N;
+  const int64_t j = c0 + 16 * wv + li;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t mi = m0 + tm + 16 * i, ni = n0 + tn + 16 * j;
-      if (mi < M && ni < N) C[mi + ni * ldc] = acc[i][j];
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * h + 4 * v + lk;
+      if (i < nb && j < N) out[i + j * nb] = acc[h][v];
     }
+}
+
+// Z (rr x N, ld ldz) -= V W2 in place: V rr x nb (ld ldv, nb <= 32), W2
+// nb x N (ld nb).  FP64 MFMA on W2^T V^T, so that 16 consecutive lanes touch
+// 16 consecutive rows of one column of Z: a 128-row x 64-column tile per
+// workgroup, 32 rows x 64 columns per wave.
+__global__ void __launch_bounds__(256) k_lr_zupd(int64_t rr, int nb, int64_t N,
+                                                 const double* __restrict__ V, int64_t ldv,
+                                                 const double* __restrict__ W2,
+                                                 double* __restrict__ Z, int64_t ldz) {
+  __shared__ double Vs[128][33];
+  __shared__ double Ws[32][65];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t r0 = int64_t(blockIdx.x) * 128, c0 = int64_t(blockIdx.y) * 64;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q, col = e >> 7, row = e & 127;
+    const int64_t r = r0 + row;
+    Vs[row][col] = (r < rr && col < nb) ? V[r + col * ldv] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int e = tid + 256 * q, k = e & 31, col = e >> 5;
+    const int64_t jc = c0 + col;
+    Ws[k][col] = (k < nb && jc < N) ? W2[k + jc * nb] : 0.0;
+  }
+  // this wave's tile of Z in the result layout: row li, column 4 v + lk
+  double zo[2][4][4];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + 32 * wv + 16 * t + li, col = c0 + 16 * u + 4 * v + lk;
+        zo[t][u][v] = (row < rr && col < N) ? Z[row + col * ldz] : 0.0;
+      }
+  __syncthreads();
+  lr_qd4 acc[2][4];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[t][u] = lr_qd4{0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < 8; ++ks) {
+    double vb[2], wa[4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) vb[t] = Vs[32 * wv + 16 * t + li][4 * ks + lk];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) wa[u] = Ws[4 * ks + lk][16 * u + li];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[u], vb[t], acc[t][u], 0, 0, 0);
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + 32 * wv + 16 * t + li, col = c0 + 16 * u + 4 * v + lk;
+        if (row < rr && col < N) Z[row + col * ldz] = zo[t][u][v] - acc[t][u][v];
+      }
 }
 
 // C = beta C + alpha sum_z part[z] (M x N, ld ldc for both).
@@ -636,51 +751,32 @@ static unsigned lr_grid(int64_t total) {
 }
 
 // op(A) B for the QR updates, split over K into nz slices of `part`.
-static int lr_gemm(bool ta, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
-                   const double* B, int64_t ldb, double* C, double alpha, double beta,
-                   double* part, int64_t part_cap, hipStream_t st) {
-  int nz = int(std::max<int64_t>(1, std::min<int64_t>(cdiv(K, 512), 64)));
-  while (nz > 1 && M * N * nz > part_cap) --nz;
-  const int64_t kc = cdiv(cdiv(K, nz), 16) * 16;
-  nz = int(cdiv(K, kc));
-  const dim3 grid = dim3(unsigned(cdiv(M, 64)), unsigned(cdiv(N, 64)), unsigned(nz));
-  if (ta)
-    hipLaunchKernelGGL(k_lr_dgemm<true>, grid, dim3(256), 0, st, M, N, K, kc, A, lda, B, ldb, part, M);
-  else
-    hipLaunchKernelGGL(k_lr_dgemm<false>, grid, dim3(256), 0, st, M, N, K, kc, A, lda, B, ldb, part, M);
-  TIK_LAUNCHED("k_lr_dgemm");
-  // C has leading dimension M here (callers pass compact C) unless beta == 1 with ldc > M
-  hipLaunchKernelGGL(k_lr_reduce, dim3(lr_grid(M * N)), dim3(256), 0, st, part, nz, M, N, M, alpha,
-                     beta, C);
+// W (nb x N, ld nb) = V^T Z (V rr x nb, Z rr x N): row chunks on about 512
+// workgroups in all, partial products reduced in a fixed order.
+static int lr_vtz(int64_t rr, int nb, int64_t N, const double* V, int64_t ldv, const double* Z,
+                  int64_t ldz, double* W, double* part, int64_t part_cap, hipStream_t st) {
+  const int64_t ct = cdiv(N, 64);
+  int64_t nch = std::max<int64_t>(1, std::min<int64_t>(cdiv(512, ct), cdiv(rr, 128)));
+  while (nch > 1 && nch * nb * N > part_cap) --nch;
+  const int64_t rpc = cdiv(cdiv(rr, nch), 32) * 32;
+  nch = std::max<int64_t>(1, cdiv(rr, rpc));
+  hipLaunchKernelGGL(k_lr_vtz, dim3(unsigned(ct), unsigned(nch)), dim3(256), 0, st, rr, nb, N, rpc, V,
+                     ldv, Z, ldz, part);
+  TIK_LAUNCHED("k_lr_vtz");
+  hipLaunchKernelGGL(k_lr_reduce, dim3(lr_grid(int64_t(nb) * N)), dim3(256), 0, st, part, int(nch),
+                     int64_t(nb), N, int64_t(nb), 1.0, 0.0, W);
   TIK_LAUNCHED("k_lr_reduce");
   return TIK_OK;
 }
-
-// C (M x N, ld ldc) += alpha * A (M x K, ld lda) * B (K x N, ld K): rows independent,
-// computed by the dgemm kernel into `part` (ld M) and added by a strided reduce.
-__global__ void k_lr_add_strided(const double* __restrict__ part, int64_t M, int64_t N,
-                                 double alpha, double* __restrict__ C, int64_t ldc) {
-  const int64_t total = M * N;
-  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
-       e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t mi = e % M, ni = e / M;
-    C[mi + ni * ldc] += alpha * part[e];
-  }
-}
-
-static int lr_gemm_add(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
-                       const double* B, double* C, int64_t ldc, double alpha, double* part,
-                       hipStream_t st) {
-  const dim3 grid = dim3(unsigned(cdiv(M, 64)), unsigned(cdiv(N, 64)), 1u);
-  hipLaunchKernelGGL(k_lr_dgemm<false>, grid, dim3(256), 0, st, M, N, K, K, A, lda, B, K, part, M);
-  TIK_LAUNCHED("k_lr_dgemm");
-  hipLaunchKernelGGL(k_lr_add_strided, dim3(lr_grid(M * N)), dim3(256), 0, st, part, M, N, alpha, C,
-                     ldc);
-  TIK_LAUNCHED("k_lr_add_strided");
+// Z (rr x N, ld ldz) -= V W2 (V rr x nb, W2 nb x N).
+static int lr_zupd(int64_t rr, int nb, int64_t N, const double* V, int64_t ldv, const double* W2,
+                   double* Z, int64_t ldz, hipStream_t st) {
+  hipLaunchKernelGGL(k_lr_zupd, dim3(unsigned(cdiv(rr, 128)), unsigned(cdiv(N, 64))), dim3(256), 0, st,
+                     rr, nb, N, V, ldv, W2, Z, ldz);
+  TIK_LAUNCHED("k_lr_zupd");
   return TIK_OK;
 }
 
-// Workspace of the QR routine below for a rows x cols factorization.
 struct QrWs {
   double* tau;    // cols
   double* T;      // ceil(cols / 32) panels of 32 x 32
@@ -695,7 +791,7 @@ struct QrWs {
 static size_t qr_ws_doubles(int64_t rows, int64_t cols) {
   const int64_t np = cdiv(cols, LR_NB);
   return size_t(cols + np * LR_NB * LR_NB + rows * LR_NB + LR_NB * LR_NB + 2 * LR_NB * cols +
-                std::max<int64_t>(64 * LR_NB * std::max<int64_t>(cols, LR_NB), rows * cols) + 8 * 32);
+                64 * LR_NB * std::max<int64_t>(cols, LR_NB) + 8 * 32);
 }
 
 static QrWs qr_ws_carve(double* base, int64_t rows, int64_t cols) {
@@ -708,7 +804,7 @@ static QrWs qr_ws_carve(double* base, int64_t rows, int64_t cols) {
   w.W1 = w.Gm + LR_NB * LR_NB;
   w.W2 = w.W1 + LR_NB * cols;
   w.part = w.W2 + LR_NB * cols;
-  w.part_cap = std::max<int64_t>(64 * LR_NB * std::max<int64_t>(cols, LR_NB), rows * cols);
+  w.part_cap = 64 * LR_NB * std::max<int64_t>(cols, LR_NB);
   return w;
 }
 
@@ -721,33 +817,31 @@ static int qr_factor(double* Z, int64_t rows, int64_t cols, int64_t ldz, const Q
   for (int64_t pnl = 0; pnl < np; ++pnl) {
     const int64_t k0 = pnl * LR_NB;
     const int nb = int(std::min<int64_t>(LR_NB, cols - k0));
-    for (int jj = 0; jj < nb; ++jj) {
-      const int64_t j = k0 + jj;
-      hipLaunchKernelGGL(k_lr_house, dim3(1), dim3(1024), 0, st, Z, ldz, rows, j, w.tau);
-      TIK_LAUNCHED("k_lr_house");
-      if (jj + 1 < nb) {
-        hipLaunchKernelGGL(k_lr_apply_house, dim3(unsigned(nb - jj - 1)), dim3(256), 0, st, Z, ldz,
-                           rows, j, w.tau);
-        TIK_LAUNCHED("k_lr_apply_house");
-      }
-    }
+    // reflector of the panel's first column, then per column one launch that
+    // applies H_j to the rest of the panel and forms the reflector of j + 1
+    hipLaunchKernelGGL(k_lr_house, dim3(1), dim3(1024), 0, st, Z, ldz, rows, k0, w.tau);
+    TIK_LAUNCHED("k_lr_house");
+    for (int jj = 0; jj + 1 < nb; ++jj)
+      hipLaunchKernelGGL(k_lr_apply_house, dim3(unsigned(nb - jj - 1)), dim3(1024), 0, st, Z, ldz,
+                         rows, k0 + jj, w.tau, 1);
+    TIK_LAUNCHED("k_lr_apply_house");
     const int64_t rr = rows - k0;
     hipLaunchKernelGGL(k_lr_copy_v, dim3(lr_grid(rr * nb)), dim3(256), 0, st, Z, ldz, rows, k0, nb,
                        w.Vc);
     TIK_LAUNCHED("k_lr_copy_v");
     double* Tp = w.T + pnl * LR_NB * LR_NB;
-    TIK_TRY(lr_gemm(true, nb, nb, rr, w.Vc, rr, w.Vc, rr, w.Gm, 1.0, 0.0, w.part, w.part_cap, st));
+    TIK_TRY(lr_vtz(rr, nb, nb, w.Vc, rr, w.Vc, rr, w.Gm, w.part, w.part_cap, st));
     hipLaunchKernelGGL(k_lr_form_t, dim3(1), dim3(64), 0, st, w.Gm, nb, w.tau + k0, Tp);
     TIK_LAUNCHED("k_lr_form_t");
     const int64_t ntr = cols - k0 - nb;
     if (ntr > 0) {
       double* Ztr = Z + k0 + (k0 + nb) * ldz;
       // W1 = Vc^T Ztr (nb x ntr), W2 = T^T W1, Ztr -= Vc W2
-      TIK_TRY(lr_gemm(true, nb, ntr, rr, w.Vc, rr, Ztr, ldz, w.W1, 1.0, 0.0, w.part, w.part_cap, st));
+      TIK_TRY(lr_vtz(rr, nb, ntr, w.Vc, rr, Ztr, ldz, w.W1, w.part, w.part_cap, st));
       hipLaunchKernelGGL(k_lr_tmul<true>, dim3(lr_grid(nb * ntr)), dim3(256), 0, st, Tp, nb, w.W1,
                          ntr, w.W2);
       TIK_LAUNCHED("k_lr_tmul");
-      TIK_TRY(lr_gemm_add(rr, ntr, nb, w.Vc, rr, w.W2, Ztr, ldz, -1.0, w.part, st));
+      TIK_TRY(lr_zupd(rr, nb, ntr, w.Vc, rr, w.W2, Ztr, ldz, st));
     }
   }
   return TIK_OK;
@@ -766,11 +860,11 @@ static int qr_apply_q(const double* Z, int64_t rows, int64_t cols, int64_t ldz, 
                        w.Vc);
     TIK_LAUNCHED("k_lr_copy_v");
     double* Xr = X + k0;
-    TIK_TRY(lr_gemm(true, nb, c, rr, w.Vc, rr, Xr, ldx, w.W1, 1.0, 0.0, w.part, w.part_cap, st));
+    TIK_TRY(lr_vtz(rr, nb, c, w.Vc, rr, Xr, ldx, w.W1, w.part, w.part_cap, st));
     hipLaunchKernelGGL(k_lr_tmul<false>, dim3(lr_grid(nb * c)), dim3(256), 0, st,
                        w.T + pnl * LR_NB * LR_NB, nb, w.W1, c, w.W2);
     TIK_LAUNCHED("k_lr_tmul");
-    TIK_TRY(lr_gemm_add(rr, c, nb, w.Vc, rr, w.W2, Xr, ldx, -1.0, w.part, st));
+    TIK_TRY(lr_zupd(rr, nb, c, w.Vc, rr, w.W2, Xr, ldx, st));
   }
   return TIK_OK;
 }
