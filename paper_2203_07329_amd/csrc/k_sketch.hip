@@ -436,6 +436,41 @@ __global__ void __launch_bounds__(256) k_gauss_gen_bf16(uint64_t seed, int64_t s
 }
 
 typedef __bf16 sk_bf16x8 __attribute__((ext_vector_type(8)));
+
+// 16 consecutive values from a 16-byte-aligned address, as 16-byte loads.
+__device__ __forceinline__ void lr16(const float* src, float (&d)[16]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 v = reinterpret_cast<const float4*>(src)[q];
+    d[4 * q] = v.x;
+    d[4 * q + 1] = v.y;
+    d[4 * q + 2] = v.z;
+    d[4 * q + 3] = v.w;
+  }
+}
+__device__ __forceinline__ void lr4(const float* src, float* d) {
+  const float4 v = *reinterpret_cast<const float4*>(src);
+  d[0] = v.x;
+  d[1] = v.y;
+  d[2] = v.z;
+  d[3] = v.w;
+}
+__device__ __forceinline__ void lr4(const double* src, float* d) {
+  const double2 v0 = reinterpret_cast<const double2*>(src)[0];
+  const double2 v1 = reinterpret_cast<const double2*>(src)[1];
+  d[0] = float(v0.x);
+  d[1] = float(v0.y);
+  d[2] = float(v1.x);
+  d[3] = float(v1.y);
+}
+__device__ __forceinline__ void lr16(const double* src, float (&d)[16]) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double2 v = reinterpret_cast<const double2*>(src)[q];
+    d[2 * q] = float(v.x);
+    d[2 * q + 1] = float(v.y);
+  }
+}
 typedef float sk_f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
@@ -449,28 +484,43 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
 // 128 x 128 output tile per block, 4 waves of 64 x 64 (2 x 2 tiles of
 // v_mfma_f32_32x32x16_bf16: A-operand lane l holds row l % 32, k = 8 (l / 32) .. +7;
 // B-operand lane l holds column l % 32 at the same k; the 16 results of lane l
-// are rows 8 (v / 4) + 4 (l / 32) + v % 4 of column l % 32).  Tiles are staged in
-// LDS k-contiguous (row / column major over 32 k) so each operand is one
-// 16-byte read; the next tile is fetched into registers during the MFMAs.
+// are rows 8 (v / 4) + 4 (l / 32) + v % 4 of column l % 32).  Tiles of KB k are
+// staged in LDS k-contiguous (row / column major) so each operand is one
+// 16-byte read; LDS holds two stages, so the next step (fetched into
+// registers with 16-byte loads during the MFMAs) is written to the other stage
+// and one barrier per step suffices.
 // Split K (grid.z > 1): block z covers k in [z ksz, (z + 1) ksz) and stores its
 // partial product to Y + z s ncol; k_sketch_reduce adds the slices in order.
-template <typename TA, bool WIDE>
+// Tile placement: workgroups are dealt to the 8 XCDs in turn (block g runs on
+// XCD g mod 8), so XCD x gets the rectangle (x / pc, x mod pc) of a ps x pc
+// split of the tile grid (sR x cR tiles each), walked row by row: the
+// workgroups running together on one XCD share their X rows and A columns in
+// that XCD's L2, and each operand panel is fetched by ps or pc XCDs only.
+template <typename TA, bool WIDE, int KB>
 __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* __restrict__ X,
                                                           int64_t s, int64_t kc, int64_t ksz,
                                                           const TA* __restrict__ A, int64_t lda,
-                                                          int64_t r0, int64_t ncol,
-                                                          float* __restrict__ Y, int first) {
-  constexpr int KB = 32, LP = KB + 8;     // k per step, LDS row pitch in bf16
+                                                          int64_t r0, int64_t ncol, int sR, int cR,
+                                                          int pc, float* __restrict__ Y, int first) {
+  static_assert(KB % 32 == 0 && KB <= 128, "k per step");
+  constexpr int LP = KB + 8;              // LDS row pitch in bf16
+  constexpr int HK = KB / 2;              // k per thread (tall B, X): half a row of the step
+  constexpr int WK = KB / 8;              // k per thread (wide B)
+  const int xcd = blockIdx.x & 7, jx = blockIdx.x >> 3;
+  const int64_t stile = int64_t(xcd / pc) * sR + jx / cR, ctile = int64_t(xcd % pc) * cR + jx % cR;
+  if (jx >= sR * cR || stile * 128 >= s || ctile * 128 >= ncol) return;   // uniform
   const int64_t kb = int64_t(blockIdx.z) * ksz, ke = min(kc, kb + ksz);
   if (gridDim.z > 1) {
     Y += int64_t(blockIdx.z) * s * ncol;
     first = 1;
   }
-  __shared__ __attribute__((aligned(16))) uint16_t Xs[128 * LP];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[128 * LP];
+  __shared__ __attribute__((aligned(16))) uint16_t Xs2[2][128 * LP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs2[2][128 * LP];
+  uint16_t* Xs = Xs2[0];
+  uint16_t* Bs = Bs2[0];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wq = wv >> 1, wc = wv & 1;
-  const int64_t q0 = int64_t(blockIdx.x) * 128, c0 = int64_t(blockIdx.y) * 128;
+  const int64_t q0 = stile * 128, c0 = ctile * 128;
   sk_f32x16 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -478,80 +528,105 @@ __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* 
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
-  // register stage: X (2 x 16 bytes per thread), B (16 values per thread)
-  uint4 rx[2];
-  float rb[16];
-  auto fetch = [&](int64_t k0) {
+  // register stage of one step: X (HK bf16 per thread), B (HK values per thread).
+  // Whole steps whose runs of A start 16-byte aligned (base, lda and the
+  // chunk origin multiples of 16 bytes / sizeof(TA)) and whose X rows are
+  // whole 16-byte runs (kc a multiple of 8) are prefetched with 16-byte loads
+  // during the previous step's MFMAs; any other step (the ragged last one, a
+  // misaligned A) is copied element by element into LDS after the barrier.
+  uint4 rx[HK / 8];
+  float rb[HK];
+  constexpr int64_t VE = 16 / sizeof(TA);
+  const bool vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && lda % VE == 0 && r0 % VE == 0 &&
+                   (WIDE ? (c0 % VE == 0) : (kb % VE == 0)) && (kc & 7) == 0;
+  auto whole = [&](int64_t k0) { return vec && k0 + KB <= ke; };
+  auto fetch = [&](int64_t k0) {               // whole steps only
     {
       const int row = tid >> 1, half = tid & 1;
       const int64_t q = q0 + row;
-      const int64_t kk = k0 + half * 16;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (q < s) {
-          const int64_t k = kk + h * 8;
-          if (k + 8 <= ke && ((kc & 7) == 0)) {
-            v = *reinterpret_cast<const uint4*>(X + q * kc + k);
-          } else {
-            uint16_t t[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-              t[e] = (k + e < ke) ? *reinterpret_cast<const uint16_t*>(X + q * kc + k + e) : 0;
-            v = make_uint4(t[0] | (t[1] << 16), t[2] | (t[3] << 16), t[4] | (t[5] << 16),
-                           t[6] | (t[7] << 16));
-          }
-        }
-        rx[h] = v;
-      }
+      for (int h = 0; h < HK / 8; ++h)
+        rx[h] = q < s ? *reinterpret_cast<const uint4*>(X + q * kc + k0 + half * HK + h * 8)
+                      : make_uint4(0, 0, 0, 0);
     }
     if (!WIDE) {
       const int col = tid >> 1, half = tid & 1;
       const int64_t c = c0 + col;
+      const TA* src = A + (r0 + k0 + half * HK) + min(c, ncol - 1) * lda;
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int64_t k = k0 + half * 16 + e;
-        rb[e] = (c < ncol && k < ke) ? float(A[(r0 + k) + c * lda]) : 0.f;
-      }
+      for (int h = 0; h < HK / 16; ++h) lr16(src + 16 * h, *reinterpret_cast<float(*)[16]>(rb + 16 * h));
+      if (c >= ncol)
+#pragma unroll
+        for (int e = 0; e < HK; ++e) rb[e] = 0.f;
     } else {
-      const int kr = tid >> 3, cg = (tid & 7) * 16;
-      const int64_t k = k0 + kr;
+      // 4 consecutive rows of A (operand columns c, contiguous) at each of WK
+      // consecutive k: rb[4 kk + j] = element (k = WK k4 + kk, c = 4 c4 + j)
+      const int c4 = tid & 31, k4 = tid >> 5;
+      const int64_t c = c0 + 4 * c4;
+      const bool cin = c + 4 <= ncol;
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int64_t c = c0 + cg + e;
-        rb[e] = (c < ncol && k < ke) ? float(A[c + (r0 + k) * lda]) : 0.f;
+      for (int kk = 0; kk < WK; ++kk) {
+        const int64_t k = k0 + WK * k4 + kk;
+        if (cin) {
+          lr4(A + c + (r0 + k) * lda, rb + 4 * kk);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            rb[4 * kk + j] = c + j < ncol ? float(A[(c + j) + (r0 + k) * lda]) : 0.f;
+        }
       }
     }
   };
-  auto stash = [&]() {
+  auto stash = [&]() {                          // the fetched whole step
     {
       const int row = tid >> 1, half = tid & 1;
-      *reinterpret_cast<uint4*>(&Xs[row * LP + half * 16]) = rx[0];
-      *reinterpret_cast<uint4*>(&Xs[row * LP + half * 16 + 8]) = rx[1];
+#pragma unroll
+      for (int h = 0; h < HK / 8; ++h)
+        *reinterpret_cast<uint4*>(&Xs[row * LP + half * HK + 8 * h]) = rx[h];
     }
     if (!WIDE) {
       const int col = tid >> 1, half = tid & 1;
-      uint4 w0 = make_uint4(pack_bf16(rb[0], rb[1]), pack_bf16(rb[2], rb[3]),
-                            pack_bf16(rb[4], rb[5]), pack_bf16(rb[6], rb[7]));
-      uint4 w1 = make_uint4(pack_bf16(rb[8], rb[9]), pack_bf16(rb[10], rb[11]),
-                            pack_bf16(rb[12], rb[13]), pack_bf16(rb[14], rb[15]));
-      *reinterpret_cast<uint4*>(&Bs[col * LP + half * 16]) = w0;
-      *reinterpret_cast<uint4*>(&Bs[col * LP + half * 16 + 8]) = w1;
-    } else {
-      const int kr = tid >> 3, cg = (tid & 7) * 16;
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const __hip_bfloat16 h = __float2bfloat16(rb[e]);
-        Bs[(cg + e) * LP + kr] = *reinterpret_cast<const uint16_t*>(&h);
-      }
+      for (int h = 0; h < HK / 8; ++h)
+        *reinterpret_cast<uint4*>(&Bs[col * LP + half * HK + 8 * h]) =
+            make_uint4(pack_bf16(rb[8 * h], rb[8 * h + 1]), pack_bf16(rb[8 * h + 2], rb[8 * h + 3]),
+                       pack_bf16(rb[8 * h + 4], rb[8 * h + 5]), pack_bf16(rb[8 * h + 6], rb[8 * h + 7]));
+    } else {
+      // column 4 c4 + j gets its WK k values, 8 bytes (4 k) per write
+      const int c4 = tid & 31, k4 = tid >> 5;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int g = 0; g < WK / 4; ++g)
+          *reinterpret_cast<uint2*>(&Bs[(4 * c4 + j) * LP + WK * k4 + 4 * g]) =
+              make_uint2(pack_bf16(rb[4 * (4 * g) + j], rb[4 * (4 * g + 1) + j]),
+                         pack_bf16(rb[4 * (4 * g + 2) + j], rb[4 * (4 * g + 3) + j]));
     }
   };
-  fetch(kb);
-  stash();
+  auto stash_ragged = [&](int64_t k0) {         // element by element, zeros outside
+    for (int e = tid; e < 128 * KB; e += 256) {
+      const int r = e / KB, kk = e % KB;
+      const int64_t k = k0 + kk, q = q0 + r, c = c0 + r;
+      Xs[r * LP + kk] = (q < s && k < ke) ? *reinterpret_cast<const uint16_t*>(X + q * kc + k) : 0;
+      const float v = (c < ncol && k < ke) ? float(WIDE ? A[c + (r0 + k) * lda] : A[(r0 + k) + c * lda])
+                                           : 0.f;
+      const __hip_bfloat16 h = __float2bfloat16(v);
+      Bs[r * LP + kk] = *reinterpret_cast<const uint16_t*>(&h);
+    }
+  };
+  if (whole(kb)) {
+    fetch(kb);
+    stash();
+  } else {
+    stash_ragged(kb);
+  }
   __syncthreads();
+  int buf = 0;
   for (int64_t k0 = kb; k0 < ke; k0 += KB) {
-    const bool more = k0 + KB < ke;
-    if (more) fetch(k0 + KB);
+    const bool more = k0 + KB < ke, pre = more && whole(k0 + KB);
+    if (pre) fetch(k0 + KB);
+    Xs = Xs2[buf];
+    Bs = Bs2[buf];
 #pragma unroll
     for (int ks = 0; ks < KB / 16; ++ks) {
       sk_bf16x8 av[2], bv[2];
@@ -571,9 +646,13 @@ __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* 
         for (int b = 0; b < 2; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
+    // the next step goes to the other stage: one barrier per step
+    Xs = Xs2[buf ^ 1];
+    Bs = Bs2[buf ^ 1];
+    if (pre) stash();
+    else if (more) stash_ragged(k0 + KB);
     __syncthreads();
-    if (more) stash();
-    __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -709,6 +788,7 @@ int launch_sketch_gemm_f64(const double* Xc, int64_t s, int64_t kc, const void* 
 // K splits of one BF16 sketch launch: enough blocks to fill the chip when the
 // output has few 128 x 128 tiles, at least 512 k per split, partial slices
 // within `part_cap` floats.
+constexpr int SK_KB = 32;    // k per step of the BF16 sketch product
 int sketch_bf16_splits(int64_t s, int64_t ncol, int64_t kc, int64_t part_cap) {
   const int64_t tiles = cdiv(s, 128) * cdiv(ncol, 128);
   int64_t z = std::max<int64_t>(1, std::min<int64_t>(1024 / std::max<int64_t>(1, tiles), kc / 512));
@@ -720,18 +800,35 @@ int launch_sketch_gemm_bf16(const void* Xc, int64_t s, int64_t kc, const void* A
                             int64_t lda, int64_t r0, int64_t ncol, int wide, float* Yacc,
                             int first, float* part, int64_t part_cap, hipStream_t st) {
   int nz = sketch_bf16_splits(s, ncol, kc, part_cap);
-  const int64_t ksz = cdiv(cdiv(kc, nz), 32) * 32;
+  const int64_t ksz = cdiv(cdiv(kc, nz), SK_KB) * SK_KB;
   nz = int(cdiv(kc, ksz));
   float* dst = nz > 1 ? part : Yacc;
-  const dim3 grid = dim3(unsigned(cdiv(s, 128)), unsigned(cdiv(ncol, 128)), unsigned(nz));
+  // XCD split ps x pc of the S x C tile grid: X panels are fetched by pc XCDs,
+  // A panels by ps; take the split with the fewest bytes
+  const int64_t S = cdiv(s, 128), C = cdiv(ncol, 128);
+  const double xb = double(s) * double(ksz) * 2.0;
+  const double ab = double(ncol) * double(ksz) * (a_f32 ? 4.0 : 8.0);
+  int pc = 1;
+  double best = -1.0;
+  for (int c = 1; c <= 8; c *= 2) {
+    const int ps = 8 / c;
+    if ((c > 1 && C < c) || (ps > 1 && S < ps)) continue;
+    const double cost = xb * c + ab * ps;
+    if (best < 0.0 || cost < best) {
+      best = cost;
+      pc = c;
+    }
+  }
+  const int sR = int(cdiv(S, 8 / pc)), cR = int(cdiv(C, pc));
+  const dim3 grid = dim3(unsigned(8 * sR * cR), 1u, unsigned(nz));
   const __hip_bfloat16* X = static_cast<const __hip_bfloat16*>(Xc);
   ProfScope ps("sketch", st);
   if (a_f32) {
-    if (wide) hipLaunchKernelGGL((k_sketch_gemm_bf16<float, true>), grid, dim3(256), 0, st, X, s, kc, ksz, static_cast<const float*>(A), lda, r0, ncol, dst, first);
-    else      hipLaunchKernelGGL((k_sketch_gemm_bf16<float, false>), grid, dim3(256), 0, st, X, s, kc, ksz, static_cast<const float*>(A), lda, r0, ncol, dst, first);
+    if (wide) hipLaunchKernelGGL((k_sketch_gemm_bf16<float, true, SK_KB>), grid, dim3(256), 0, st, X, s, kc, ksz, static_cast<const float*>(A), lda, r0, ncol, sR, cR, pc, dst, first);
+    else      hipLaunchKernelGGL((k_sketch_gemm_bf16<float, false, SK_KB>), grid, dim3(256), 0, st, X, s, kc, ksz, static_cast<const float*>(A), lda, r0, ncol, sR, cR, pc, dst, first);
   } else {
-    if (wide) hipLaunchKernelGGL((k_sketch_gemm_bf16<double, true>), grid, dim3(256), 0, st, X, s, kc, ksz, static_cast<const double*>(A), lda, r0, ncol, dst, first);
-    else      hipLaunchKernelGGL((k_sketch_gemm_bf16<double, false>), grid, dim3(256), 0, st, X, s, kc, ksz, static_cast<const double*>(A), lda, r0, ncol, dst, first);
+    if (wide) hipLaunchKernelGGL((k_sketch_gemm_bf16<double, true, SK_KB>), grid, dim3(256), 0, st, X, s, kc, ksz, static_cast<const double*>(A), lda, r0, ncol, sR, cR, pc, dst, first);
+    else      hipLaunchKernelGGL((k_sketch_gemm_bf16<double, false, SK_KB>), grid, dim3(256), 0, st, X, s, kc, ksz, static_cast<const double*>(A), lda, r0, ncol, sR, cR, pc, dst, first);
   }
   TIK_LAUNCHED("k_sketch_gemm_bf16");
   if (nz > 1) {
