@@ -45,6 +45,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "λ-solves/s to 1e-8 rel err: mixed batched vs plain FP64; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFS = 2500.0   # MI355X dense BF16 matrix peak
 TOL_ERR = 1e-8
 FAMILIES = ("sketch", "gram", "chol", "trinv", "lowrank", "lr_qr", "lr_sweep", "lr_q", "gemm_n",
             "gemm_t", "trmv", "trmv_t", "lr_apply", "vec", "residual")
@@ -304,6 +305,18 @@ def main() -> int:
                 "kernel": name, "avg_launch_ms": round(avg_ms, 4),
                 "algorithmic_bytes_per_launch": int(per_launch[name])}
 
+    # ---- matrix-core use of the BF16 Gaussian sketch product (2 s m n flops per
+    # problem over the "sketch" family's time: the product and its split-K reduction)
+    sketch_mfma = None
+    if cfg["embed"] == tik.GAUSS and cfg["sdt"] == tik.BF16 and "sketch" in fam:
+        flops = sum(2.0 * p.s * p.m * p.n for p in plist)
+        sk_ms = fam["sketch"][0]
+        if sk_ms > 0:
+            tf = flops / (sk_ms / 1000.0) / 1e12
+            sketch_mfma = {"bound": "mfma", "dtype": "bf16", "achieved": round(tf, 1),
+                           "peak": BF16_PEAK_TFS, "unit": "TFLOP/s", "frac": round(tf / BF16_PEAK_TFS, 4),
+                           "ms_per_step": round(sk_ms, 3), "flops": flops}
+
     line = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -321,6 +334,7 @@ def main() -> int:
                    "mode": {tik.F64_BATCHED: "f64_batched", tik.MIXED_BATCHED: "mixed_batched"}[mode],
                    "tol": tol, "solves": nsolve},
         "roofline": roof,
+        "sketch_mfma": sketch_mfma,
         "cpu_baseline": cpu,
         "solves_ok": n_ok,
         "checked": checked,
