@@ -166,10 +166,21 @@ def main() -> int:
     nsolve = int(lams.size)
     alpha = plist[0].alpha
 
-    def one_step(m_, tol):
+    def one_step(m_, tol, marks=None):
+        """sketch, preconditioners, batched solve; `marks` collects an event after each stage."""
+        def mark():
+            if marks is not None:
+                e = torch.cuda.Event(enable_timing=True)
+                e.record()
+                marks.append(e)
+        mark()
         sk = tik.sketch(pr, cfg["embed"], svec, 0, sketch_dtype=cfg["sdt"])
+        mark()
         pc = tik.precond(sk, lams, cfg["route"], alpha)
-        return tik.Solver(pr, pc, m_)(tol, maxit)
+        mark()
+        out = tik.Solver(pr, pc, m_)(tol, maxit)
+        mark()
+        return out
 
     mode, tol = pick_mode(tik, pr, cfg, svec, lams, alpha, args.mode or cfg["mode"])
     dtype = "f32+f64" if mode == tik.MIXED_BATCHED else "f64"
@@ -189,13 +200,20 @@ def main() -> int:
     torch.cuda.synchronize()
     ev0.record()
     w0 = time.perf_counter()
+    marks = []
     for _ in range(args.steps):
-        res = one_step(mode, tol)
+        res = one_step(mode, tol, marks)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     tik.prof_enable(False)
     ms_step = ev0.elapsed_time(ev1) / args.steps
+    # wall time of each stage on the caller's stream, per step
+    stage_ms = {k: 0.0 for k in ("sketch", "precond", "solve")}
+    for st in range(args.steps):
+        e = marks[4 * st:4 * st + 4]
+        for j, k in enumerate(("sketch", "precond", "solve")):
+            stage_ms[k] += e[j].elapsed_time(e[j + 1]) / args.steps
     log(f"timed {args.steps} steps: {ms_step:.2f} ms/step")
     fam = {}
     for f in FAMILIES:
@@ -305,6 +323,16 @@ def main() -> int:
                 "kernel": name, "avg_launch_ms": round(avg_ms, 4),
                 "algorithmic_bytes_per_launch": int(per_launch[name])}
 
+    # ---- per-problem latency of a batch: every preconditioner is ready after the
+    # sketch and preconditioner stages; a problem is done when its slowest lambda
+    # converges, at (its iterations / the batch's iterations) of the solve stage
+    latency = None
+    if len(plist) > 1:
+        ready = stage_ms["sketch"] + stage_ms["precond"]
+        frac_k = iters.max(axis=1) / max(1, int(iters.max()))
+        lat = ready + stage_ms["solve"] * frac_k
+        latency = [round(float(np.percentile(lat, 50)), 2), round(float(np.percentile(lat, 99)), 2)]
+
     # ---- matrix-core use of the BF16 Gaussian sketch product (2 s m n flops per
     # problem over the "sketch" family's time: the product and its split-K reduction)
     sketch_mfma = None
@@ -344,6 +372,8 @@ def main() -> int:
         "iters_max": int(iters.max()),
         "iters_p50_p99": [float(np.percentile(iters.max(axis=1), 50)),
                           float(np.percentile(iters.max(axis=1), 99))] if len(plist) > 1 else None,
+        "latency_p50_p99_ms": latency,
+        "stage_ms_per_step": {k: round(v, 3) for k, v in stage_ms.items()},
         "status_ok": bool(np.all(status <= 1)),
         "phases_ms_per_step": {k: round(v[0], 3) for k, v in fam.items()},
         "launches_per_step": {k: v[1] for k, v in fam.items()},
