@@ -1787,7 +1787,11 @@ int mixed_group(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, Mi
       const double rel = nx > 0.0 ? nd / nx : 0.0;
       const double r_k = sweep == 1 ? 1.0 : rel / std::max(dxrel[j], 1e-300);
       rel_h[j] = rel;
-      if (rel <= tol) {
+      // converged: the correction itself is below tol, or the sweeps contract
+      // (r_k < 0.1) and the error left after this correction, about r_k rel,
+      // is a hundred times below tol.  r_k is a contraction only from the third
+      // sweep on (the first correction is the whole solution).
+      if (rel <= tol || (sweep >= 3 && r_k < 0.1 && r_k * rel <= 1e-2 * tol)) {
         st_h[j] = TIK_ST_CONVERGED;
         done[j] = 1;
       } else if (use64[j] && r_k > 0.9 && sweep > 2) {
@@ -2477,7 +2481,11 @@ int wide_mixed_group(const tik_problem* p, int32_t nprob, const tik_precond_s* p
       }
       const double rel = nx > 0.0 ? nd / nx : 0.0;
       rel_h[j] = rel;
-      if (rel <= tol) {
+      // converged as in the tall driver: small correction, or (from the third
+      // sweep on) contracting sweeps whose predicted remaining error is a
+      // hundred times below tol
+      const double r_k = sweep == 1 ? 1.0 : rel / std::max(dxrel[j], 1e-300);
+      if (rel <= tol || (sweep >= 3 && r_k < 0.1 && r_k * rel <= 1e-2 * tol)) {
         st_h[j] = TIK_ST_CONVERGED;
         done[j] = 1;
       } else if (sweep >= 3 && rel > 0.9 * dxrel[j]) {
