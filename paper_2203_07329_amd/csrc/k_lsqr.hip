@@ -1449,6 +1449,16 @@ void all_lambdas(int N0, int N, std::vector<int>& ls) {
   for (int i = N0; i < N0 + N; ++i) ls.push_back(i);
 }
 
+// Lambda counts whose plans bound the workspace of every subset of NF lambdas:
+// a plan's buffers grow with the count within one tile width (pick_nc), so the
+// largest count of each width class (capped at NF) suffices.
+std::vector<int> subset_sizes(int NF) {
+  std::vector<int> out;
+  for (int ng = 1; ng <= NF; ++ng)
+    if (ng == NF || pick_nc(ng + 1) != pick_nc(ng)) out.push_back(ng);
+  return out;
+}
+
 // Workspace layout of the mixed mode for lambda groups of at most 32.
 size_t mixed_layout(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, Arena& a,
                     MixedWs& w) {
@@ -1477,7 +1487,7 @@ size_t mixed_layout(const tik_problem* p, int32_t nprob, const tik_precond_s* pc
   w.ok = a.take<int32_t>(pl.J);
   auto region = [&](size_t tc, char*& base, size_t& cap) {
     cap = 0;
-    for (int ng = 1; ng <= NF; ++ng) {     // inner plans solve subsets of the lambdas
+    for (int ng : subset_sizes(NF)) {     // inner plans solve subsets of the lambdas
       std::vector<int> sub;
       all_lambdas(0, ng, sub);
       Plan ps_;
@@ -2301,7 +2311,7 @@ size_t wide_mixed_layout(const tik_problem* p, int32_t nprob, const tik_precond_
   w.ok = a.take<int32_t>(pl.J);
   auto region = [&](size_t tc, char*& base, size_t& cap) {
     cap = 0;
-    for (int ng = 1; ng <= NF; ++ng) {
+    for (int ng : subset_sizes(NF)) {
       std::vector<int> sub;
       all_lambdas(0, ng, sub);
       WPlan q;
