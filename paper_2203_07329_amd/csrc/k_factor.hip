@@ -173,10 +173,13 @@ __global__ void k_shift_copy(const double* __restrict__ C, int64_t n, const doub
 // B[k][.] / R[k][k] and the owners of column k of R publish it, one barrier,
 // then B[i][j] -= R[i][k] X[k][j] for i < k <= j.  The step loops are split
 // into 4 unrolled blocks of 16 so that the register index is a constant.
-__global__ void __launch_bounds__(256) k_potrf_diag(double* __restrict__ R, int64_t n, int64_t k0,
-                                                    double* __restrict__ Dinv, int32_t* notpd) {
-  const int64_t mat = blockIdx.x;
-  double* Rm = R + mat * n * n;
+// One block per job of the table (jobs whose n <= k0 are finished and return).
+__global__ void __launch_bounds__(256) k_potrf_diag(const CholJob* __restrict__ jobs, int64_t k0) {
+  const CholJob J = jobs[blockIdx.x];
+  const int64_t n = J.n;
+  if (k0 >= n) return;                       // uniform
+  double* Rm = J.R;
+  double* Dinv = J.Dinv;
   const int kb = int(min<int64_t>(NB, n - k0));
   __shared__ double rowb[2][NB];
   __shared__ double colb[2][NB];
@@ -274,7 +277,7 @@ __global__ void __launch_bounds__(256) k_potrf_diag(double* __restrict__ R, int6
         }
     }
   }
-  double* D = Dinv + (mat * cdiv(n, NB) + k0 / NB) * NB * NB;
+  double* D = Dinv + (k0 / NB) * NB * NB;
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -283,21 +286,22 @@ __global__ void __launch_bounds__(256) k_potrf_diag(double* __restrict__ R, int6
       D[i + j * NB] = (i < kb && j < kb && i <= j) ? b[p][q] / diag[i] : 0.0;
     }
   __syncthreads();
-  if (tid == 0 && bad) notpd[mat] = 1;
+  if (tid == 0 && bad) *J.notpd = 1;
 }
 
 // R[k0:k0+kb, cols] = D^T R[k0:k0+kb, cols] for the 64-column tile blockIdx.x
 // right of the diagonal block (D = inverse of the diagonal block).  In place:
 // the tile is read completely before it is written.
-__global__ void __launch_bounds__(256) k_trsm_panel(double* __restrict__ R, int64_t n, int64_t k0,
-                                                    const double* __restrict__ Dinv) {
+__global__ void __launch_bounds__(256) k_trsm_panel(const CholJob* __restrict__ jobs, int64_t k0) {
   __shared__ TileLds L;
-  const int64_t mat = blockIdx.y;
-  double* Rm = R + mat * n * n;
+  const CholJob J = jobs[blockIdx.y];
+  const int64_t n = J.n;
+  double* Rm = J.R;
   const int kb = int(min<int64_t>(NB, n - k0));
   const int64_t c0 = k0 + kb + int64_t(blockIdx.x) * 64;
+  if (k0 >= n || c0 >= n) return;           // uniform: no such tile in this job
   const int nc = int(min<int64_t>(64, n - c0));
-  const double* Dm = Dinv + (mat * cdiv(n, NB) + k0 / NB) * NB * NB;
+  const double* Dm = J.Dinv + (k0 / NB) * NB * NB;
   f64x4 acc[2][2];
   tile_zero(acc);
   tile_mma<true>(Dm, NB, Rm + k0 + c0 * n, n, kb, kb, nc, L, acc);
@@ -308,12 +312,15 @@ __global__ void __launch_bounds__(256) k_trsm_panel(double* __restrict__ R, int6
 
 // Trailing update of the upper tiles: R[a, b] -= R[k, a]^T R[k, b] over the
 // panel rows k (tile pair blockIdx.x, a <= b, tiles counted from k0 + kb).
-__global__ void __launch_bounds__(256) k_syrk_trail(double* __restrict__ R, int64_t n, int64_t k0,
-                                                    int nt) {
+__global__ void __launch_bounds__(256) k_syrk_trail(const CholJob* __restrict__ jobs, int64_t k0) {
   __shared__ TileLds L;
-  const int64_t mat = blockIdx.y;
-  double* Rm = R + mat * n * n;
+  const CholJob J = jobs[blockIdx.y];
+  const int64_t n = J.n;
+  double* Rm = J.R;
+  if (k0 >= n) return;                       // uniform
   const int kb = int(min<int64_t>(NB, n - k0));
+  const int nt = int(cdiv(n - k0 - kb, 64));    // this job's trailing tiles
+  if (int(blockIdx.x) >= nt * (nt + 1) / 2) return;   // uniform
   int t = blockIdx.x, ta = 0;
   while (t >= nt - ta) { t -= nt - ta; ++ta; }
   const int tb = ta + t;
@@ -331,18 +338,19 @@ __global__ void __launch_bounds__(256) k_syrk_trail(double* __restrict__ R, int6
 // Tmp[rows of tile blockIdx.x, 0:lb] = Rinv[rows, 0:l0] R[0:l0, l0:l0+lb]
 // (Rinv upper triangular, already stored in columns < l0 with zeros below the
 // diagonal, so the contraction starts at the tile's first row).
-__global__ void __launch_bounds__(256) k_trinv_mul(const double* __restrict__ R, int64_t n,
-                                                   int64_t l0, double* __restrict__ Tmp) {
+__global__ void __launch_bounds__(256) k_trinv_mul(const CholJob* __restrict__ jobs, int64_t l0) {
   __shared__ TileLds L;
-  const int64_t mat = blockIdx.y;
-  const double* Rm = R + mat * n * n;
+  const CholJob J = jobs[blockIdx.y];
+  const int64_t n = J.n;
+  const double* Rm = J.R;
+  if (l0 >= n) return;                       // uniform
   const int lb = int(min<int64_t>(NB, n - l0));
   const int64_t r0 = int64_t(blockIdx.x) * 64;
   const int nr = int(min<int64_t>(64, l0 - r0));
   f64x4 acc[2][2];
   tile_zero(acc);
   tile_mma<false>(Rm + r0 + r0 * n, n, Rm + r0 + l0 * n, n, l0 - r0, nr, lb, L, acc);
-  double* Tm = Tmp + mat * n * NB;
+  double* Tm = J.Tmp;
   tile_for_each(acc, [&](int i, int c, double v) {
     if (i < nr && c < lb) Tm[(r0 + i) + int64_t(c) * n] = v;
   });
@@ -350,16 +358,16 @@ __global__ void __launch_bounds__(256) k_trinv_mul(const double* __restrict__ R,
 
 // Block column l of Rinv: rows above the diagonal block get -Tmp D_l, the
 // diagonal block gets D_l, rows below get zero (the lower triangle).
-__global__ void __launch_bounds__(256) k_trinv_fin(double* __restrict__ R, int64_t n, int64_t l0,
-                                                   const double* __restrict__ Tmp,
-                                                   const double* __restrict__ Dinv) {
+__global__ void __launch_bounds__(256) k_trinv_fin(const CholJob* __restrict__ jobs, int64_t l0) {
   __shared__ TileLds L;
-  const int64_t mat = blockIdx.y;
-  double* Rm = R + mat * n * n;
-  const int lb = int(min<int64_t>(NB, n - l0));
+  const CholJob J = jobs[blockIdx.y];
+  const int64_t n = J.n;
+  double* Rm = J.R;
   const int64_t r0 = int64_t(blockIdx.x) * 64;
+  if (l0 >= n || r0 >= n) return;           // uniform
+  const int lb = int(min<int64_t>(NB, n - l0));
   const int tid = threadIdx.x;
-  const double* Dm = Dinv + (mat * cdiv(n, NB) + l0 / NB) * NB * NB;
+  const double* Dm = J.Dinv + (l0 / NB) * NB * NB;
   if (r0 >= l0 + lb || r0 == l0) {
     // below the diagonal block (zeros) or the diagonal block itself
     for (int e = tid; e < 64 * NB; e += 256) {
@@ -373,7 +381,7 @@ __global__ void __launch_bounds__(256) k_trinv_fin(double* __restrict__ R, int64
     }
     return;
   }
-  const double* Tm = Tmp + mat * n * NB;
+  const double* Tm = J.Tmp;
   const int nr = int(min<int64_t>(64, l0 - r0));
   f64x4 acc[2][2];
   tile_zero(acc);
@@ -431,30 +439,43 @@ int launch_syrk(const double* Z, int64_t K, int64_t n, int64_t ldz, double* C, h
   return TIK_OK;
 }
 
-// R (nb_mat matrices n x n) <- inverse of chol(C + lams[j] I); notpd[j] = 1 on
-// breakdown.  Dinv: nb_mat * ceil(n/64) * 64 * 64 doubles; Tmp: nb_mat * n * 64.
-int launch_chol_inv_batched(const double* C, int64_t n, const double* lams, int32_t nb_mat,
-                            double* R, double* Dinv, double* Tmp, int32_t* notpd,
-                            hipStream_t st) {
-  const int64_t nblk = cdiv(n, NB);
+int launch_shift_copy(const double* C, int64_t n, const double* lams, int32_t nb_mat, double* R,
+                      hipStream_t st) {
+  ProfScope ps("chol", st);
+  const unsigned gx = unsigned(std::min<int64_t>(cdiv(n * n, 256), 4096));
+  hipLaunchKernelGGL(k_shift_copy, dim3(gx, unsigned(nb_mat)), dim3(256), 0, st, C, n, lams, R);
+  TIK_LAUNCHED("k_shift_copy");
+  return TIK_OK;
+}
+
+// Blocked right-looking Cholesky of every job, then the blocked inverse, one
+// launch per kernel and panel for the whole table: panel kb covers the jobs
+// with n > kb NB (a prefix, the table being sorted by n), each grid sized for
+// the largest of them; blocks beyond a smaller job's tiles return at once.
+int launch_chol_inv_jobs(const CholJob* jobs, const int64_t* nsz, int32_t njobs, hipStream_t st) {
+  if (njobs <= 0) return TIK_OK;
+  const int64_t nmax = nsz[0];
+  const int64_t nblk = cdiv(nmax, NB);
+  auto active = [&](int64_t k0) {            // jobs with n > k0
+    int32_t c = 0;
+    while (c < njobs && nsz[c] > k0) ++c;
+    return c;
+  };
   {
     ProfScope ps("chol", st);
-    const unsigned gx = unsigned(std::min<int64_t>(cdiv(n * n, 256), 4096));
-    hipLaunchKernelGGL(k_shift_copy, dim3(gx, unsigned(nb_mat)), dim3(256), 0, st, C, n, lams, R);
-    TIK_LAUNCHED("k_shift_copy");
     for (int64_t kb = 0; kb < nblk; ++kb) {
       const int64_t k0 = kb * NB;
-      hipLaunchKernelGGL(k_potrf_diag, dim3(unsigned(nb_mat)), dim3(256), 0, st, R, n, k0, Dinv,
-                         notpd);
+      const int32_t na = active(k0);
+      hipLaunchKernelGGL(k_potrf_diag, dim3(unsigned(na)), dim3(256), 0, st, jobs, k0);
       TIK_LAUNCHED("k_potrf_diag");
-      const int64_t rest = n - k0 - std::min<int64_t>(NB, n - k0);
+      const int64_t rest = nmax - k0 - std::min<int64_t>(NB, nmax - k0);
       if (rest > 0) {
+        const int32_t nr = active(k0 + NB);   // jobs with trailing columns
         const int nt = int(cdiv(rest, 64));
-        hipLaunchKernelGGL(k_trsm_panel, dim3(unsigned(nt), unsigned(nb_mat)), dim3(256), 0, st,
-                           R, n, k0, Dinv);
+        hipLaunchKernelGGL(k_trsm_panel, dim3(unsigned(nt), unsigned(nr)), dim3(256), 0, st, jobs, k0);
         TIK_LAUNCHED("k_trsm_panel");
-        hipLaunchKernelGGL(k_syrk_trail, dim3(unsigned(nt * (nt + 1) / 2), unsigned(nb_mat)),
-                           dim3(256), 0, st, R, n, k0, nt);
+        hipLaunchKernelGGL(k_syrk_trail, dim3(unsigned(nt * (nt + 1) / 2), unsigned(nr)), dim3(256), 0,
+                           st, jobs, k0);
         TIK_LAUNCHED("k_syrk_trail");
       }
     }
@@ -463,13 +484,14 @@ int launch_chol_inv_batched(const double* C, int64_t n, const double* lams, int3
     ProfScope ps("trinv", st);
     for (int64_t lb = 0; lb < nblk; ++lb) {
       const int64_t l0 = lb * NB;
+      const int32_t na = active(l0);
       if (l0 > 0) {
-        hipLaunchKernelGGL(k_trinv_mul, dim3(unsigned(cdiv(l0, 64)), unsigned(nb_mat)), dim3(256),
-                           0, st, R, n, l0, Tmp);
+        hipLaunchKernelGGL(k_trinv_mul, dim3(unsigned(cdiv(l0, 64)), unsigned(na)), dim3(256), 0, st,
+                           jobs, l0);
         TIK_LAUNCHED("k_trinv_mul");
       }
-      hipLaunchKernelGGL(k_trinv_fin, dim3(unsigned(cdiv(n, 64)), unsigned(nb_mat)), dim3(256), 0,
-                         st, R, n, l0, Tmp, Dinv);
+      hipLaunchKernelGGL(k_trinv_fin, dim3(unsigned(cdiv(nmax, 64)), unsigned(na)), dim3(256), 0, st,
+                         jobs, l0);
       TIK_LAUNCHED("k_trinv_fin");
     }
   }

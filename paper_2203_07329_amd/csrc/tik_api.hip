@@ -427,8 +427,10 @@ struct PrecondPlan {
   int lanes = 1;
   double* colsum_l[kLanes] = {};   // per lane: scratch, kmax
   double* C_l[kLanes] = {};
-  double* Dinv_l[kLanes] = {};
-  double* Tmp_l[kLanes] = {};
+  // Cholesky route: one job per (problem, lambda), sorted by size, largest first
+  std::vector<CholJob> jobs;
+  std::vector<int64_t> jobn;
+  CholJob* jobs_dev = nullptr;
   double* colsum = nullptr;   // scratch, kmax
   // low-rank route
   std::vector<double*> V, sigma, S;
@@ -476,9 +478,28 @@ int precond_plan(tik_sketch_t sk, int32_t route, int32_t N, Arena& a, PrecondPla
     for (int l = 0; l < pp.lanes; ++l) {
       pp.colsum_l[l] = l == 0 ? pp.colsum : a.take<double>(size_t(kmax));
       pp.C_l[l] = a.take<double>(size_t(kmax) * size_t(kmax));
-      pp.Dinv_l[l] = a.take<double>(size_t(N) * size_t(cdiv(kmax, 64)) * 64 * 64);
-      pp.Tmp_l[l] = a.take<double>(size_t(N) * size_t(kmax) * 64);
     }
+    std::vector<int32_t> order(static_cast<size_t>(np));
+    for (int32_t k = 0; k < np; ++k) order[size_t(k)] = k;
+    auto kdim = [&](int32_t k) { return std::min(sk->probs[k].m, sk->probs[k].n); };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return kdim(x) > kdim(y); });
+    pp.jobs.clear();
+    pp.jobn.clear();
+    for (int32_t k : order) {
+      const int64_t kd = kdim(k);
+      for (int32_t i = 0; i < N; ++i) {
+        CholJob j;
+        j.R = pp.Rinv[size_t(k)] + size_t(i) * size_t(kd) * size_t(kd);
+        j.Dinv = a.take<double>(size_t(cdiv(kd, 64)) * 64 * 64);
+        j.Tmp = a.take<double>(size_t(kd) * 64);
+        j.notpd = pp.notpd + size_t(k) * size_t(N) + size_t(i);
+        j.n = kd;
+        pp.jobs.push_back(j);
+        pp.jobn.push_back(kd);
+      }
+    }
+    pp.jobs_dev = a.take<CholJob>(pp.jobs.size());
   } else {
     pp.lr_scratch = a.take<double>(scratch);
     pp.perm = a.take<int32_t>(size_t(smax));
@@ -599,10 +620,13 @@ int tik_precond(tik_sketch_t sk, int32_t route, const double* lambdas, int32_t N
       hipStream_t ls = lanes.at(k);
       TIK_TRY(launch_syrk(sk->Y[k], sk->yrows[k], kd, sk->yrows[k], pp.C_l[ln], ls));
       TIK_TRY(launch_gram_norm_bound(pp.C_l[ln], kd, pp.colsum_l[ln], pp.cnorm + k, ls));
-      TIK_TRY(launch_chol_inv_batched(pp.C_l[ln], kd, pp.lams + size_t(k) * N, N, pp.Rinv[k],
-                                      pp.Dinv_l[ln], pp.Tmp_l[ln], pp.notpd + size_t(k) * N, ls));
+      TIK_TRY(launch_shift_copy(pp.C_l[ln], kd, pp.lams + size_t(k) * N, N, pp.Rinv[k], ls));
     }
     TIK_TRY(lanes.join());
+    // every (problem, lambda) factored and inverted together, panel by panel
+    TIK_HIP(hipMemcpyAsync(pp.jobs_dev, pp.jobs.data(), pp.jobs.size() * sizeof(CholJob),
+                           hipMemcpyHostToDevice, st));
+    TIK_TRY(launch_chol_inv_jobs(pp.jobs_dev, pp.jobn.data(), int32_t(pp.jobs.size()), st));
     std::vector<int32_t> bad(size_t(np) * size_t(N), 0);
     std::vector<double> cn(size_t(np), 0.0);
     TIK_HIP(hipMemcpyAsync(bad.data(), pp.notpd, sizeof(int32_t) * bad.size(),

@@ -148,9 +148,23 @@ int launch_f32_to_f64(const float* src, double* dst, int64_t count, hipStream_t 
 int launch_syrk(const double* Z, int64_t K, int64_t n, int64_t ldz, double* C, hipStream_t st);
 int launch_gram_norm_bound(const double* C, int64_t n, double* scratch, double* out,
                            hipStream_t st);
-int launch_chol_inv_batched(const double* C, int64_t n, const double* lams, int32_t nb_mat,
-                            double* R, double* Dinv, double* Tmp, int32_t* notpd,
-                            hipStream_t st);
+// One shifted matrix of the batched Cholesky-inverse: R (n x n, ld n) holds
+// C + lambda I on entry and the upper triangle of chol(C + lambda I)^{-1} on
+// exit; Dinv (ceil(n / 64) blocks of 64 x 64) and Tmp (n x 64) are its
+// scratch; *notpd is set to 1 on breakdown.
+struct CholJob {
+  double* R;
+  double* Dinv;
+  double* Tmp;
+  int32_t* notpd;
+  int64_t n;
+};
+// R_j <- C + lams[j] I for the nb_mat lambdas of one problem (R_j at R + j n^2).
+int launch_shift_copy(const double* C, int64_t n, const double* lams, int32_t nb_mat, double* R,
+                      hipStream_t st);
+// Factor and invert every job of the table (device memory), sorted by n,
+// largest first; nsz[i] is the n of job i on the host (same order).
+int launch_chol_inv_jobs(const CholJob* jobs, const int64_t* nsz, int32_t njobs, hipStream_t st);
 
 // matrix-core products (k_mfma.hip)
 // rows: rows of A per gemm_n block (128 or 256); cols: columns per gemm_t block (64 or 128)
