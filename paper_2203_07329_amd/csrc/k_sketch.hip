@@ -416,9 +416,45 @@ __global__ void __launch_bounds__(256) k_sketch_gemm64(const double* __restrict_
 }
 
 // ------------------------------------------------------------ BF16 sketch --
+// The four normals of gauss4 from the same Philox counters, Box-Muller in
+// FP32 but with every quantity an FP32 relative error away from the exact one,
+// so that the BF16-rounded entries agree with the rounded FP64 ones:
+//   ln u = log((x + 1/2) 2^-32) for x < 2^31, else log1p(-(2^32 - x - 1/2) 2^-32)
+//     (1 - u is formed from the integer, exact);
+//   the angle 2 pi u' is reduced to a quadrant on the integer, and both its
+//   sine and cosine are sinpi of an offset formed exactly from the integer.
+__device__ __forceinline__ float lr_log_u(uint32_t x) {
+  const float inv32 = 2.3283064365386963e-10f;   // 2^-32
+  if (x < 0x80000000u) return logf((float(x) + 0.5f) * inv32);
+  return log1pf(-(float(0xFFFFFFFFu - x) + 0.5f) * inv32);
+}
+__device__ __forceinline__ void lr_sincos_2pi_u(uint32_t y, float& sn, float& cs) {
+  const uint32_t q = y >> 30, f = y & 0x3FFFFFFFu;   // quadrant, offset within it
+  const float inv31 = 4.656612873077393e-10f;      // 2^-31
+  const float a = sinpif((float(f) + 0.5f) * inv31);               // sin of the offset angle
+  const float b = sinpif((float(0x3FFFFFFFu - f) + 0.5f) * inv31); // its cosine
+  switch (q) {
+    case 0: sn = a; cs = b; break;
+    case 1: sn = b; cs = -a; break;
+    case 2: sn = -a; cs = -b; break;
+    default: sn = -b; cs = a; break;
+  }
+}
+__device__ __forceinline__ void gauss4f(uint64_t seed, uint32_t r, uint32_t qb, float out[4]) {
+  const uint4 v = philox4x32_10(make_uint4(r, qb, TAG_GAUS, 0u), seed_key(seed));
+  const float r0 = sqrtf(-2.0f * lr_log_u(v.x)), r1 = sqrtf(-2.0f * lr_log_u(v.z));
+  float s0, c0, s1, c1;
+  lr_sincos_2pi_u(v.y, s0, c0);
+  lr_sincos_2pi_u(v.w, s1, c1);
+  out[0] = r0 * c0;
+  out[1] = r0 * s0;
+  out[2] = r1 * c1;
+  out[3] = r1 * s1;
+}
+
 // X chunk in BF16, stored row-major s x kc (k contiguous), the layout the
-// matrix-core operand loads want.  Same Philox/Box-Muller entries as the FP64
-// generator, rounded to BF16.
+// matrix-core operand loads want: the Philox/Box-Muller normals of the FP64
+// generator (computed in FP32, see gauss4f), rounded to BF16.
 __global__ void __launch_bounds__(256) k_gauss_gen_bf16(uint64_t seed, int64_t s, int64_t r0,
                                                         int64_t kc, float scale,
                                                         __hip_bfloat16* __restrict__ X) {
@@ -426,12 +462,12 @@ __global__ void __launch_bounds__(256) k_gauss_gen_bf16(uint64_t seed, int64_t s
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= sq * kc) return;
   const int64_t cc = idx % kc, qb = idx / kc;
-  double z[4];
-  gauss4(seed, uint32_t(r0 + cc), uint32_t(qb), z);
+  float z[4];
+  gauss4f(seed, uint32_t(r0 + cc), uint32_t(qb), z);
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int64_t q = qb * 4 + t;
-    if (q < s) X[q * kc + cc] = __float2bfloat16(float(z[t]) * scale);
+    if (q < s) X[q * kc + cc] = __float2bfloat16(z[t] * scale);
   }
 }
 
