@@ -26,6 +26,9 @@
 // (n rows) buffers are row-major (rows x N, N lambdas per row); t is stored
 // lambda-major so the transposed triangular product reads it contiguously.
 #include "tik_internal.h"
+#ifndef WIDE_BLOCKS
+#define WIDE_BLOCKS 512
+#endif
 
 #include <algorithm>
 #include <type_traits>
@@ -790,6 +793,7 @@ __global__ void __launch_bounds__(BLK) k_wide_h(const DevProb* __restrict__ P,
   if (r >= m || i >= N) return;
   double s = 0.0;
   const TC* src = part + (pr.pnOff + r) * N + i;
+#pragma unroll 8   // the chunk partials are independent loads: keep several in flight
   for (int ch = 0; ch < pr.nchN; ++ch) s += double(src[int64_t(ch) * m * N]);
   const Scal& S = sc[it.p * N + i];
   if (EPI == 0)
@@ -1899,6 +1903,7 @@ struct WBufs {
   int32_t *pre, *jmap, *lidx;
 };
 
+constexpr int64_t kWideBlocks = 2048;   // product blocks of a wide batch
 void make_plan_wide(const tik_problem* probs, const tik_precond_s* pc, const std::vector<int>& pidx,
                     const std::vector<int>& lsel, WPlan& pl, const void* const* Aover = nullptr,
                     const int64_t* ldover = nullptr) {
@@ -1931,9 +1936,9 @@ void make_plan_wide(const tik_problem* probs, const tik_precond_s* pc, const std
     d.offC = d.offL;
     d.k = g.m;
     if (!pl.lowrank) d.Rinv = pc->Rinv[pidx[lp]];
-    // split of A v_top over column chunks: about 2048 blocks over the batch
+    // split of A v_top over column chunks: about kWideBlocks blocks over the batch
     const int64_t nrb = cdiv(g.m, pl.rbN);
-    int64_t nch = std::max<int64_t>(1, 2048 / std::max<int64_t>(1, rowblocks));
+    int64_t nch = std::max<int64_t>(1, kWideBlocks / std::max<int64_t>(1, rowblocks));
     nch = std::min<int64_t>(nch, cdiv(g.n, 32));
     const int64_t cch = cdiv(cdiv(g.n, nch), 32) * 32;
     nch = cdiv(g.n, cch);
