@@ -26,9 +26,6 @@
 // (n rows) buffers are row-major (rows x N, N lambdas per row); t is stored
 // lambda-major so the transposed triangular product reads it contiguously.
 #include "tik_internal.h"
-#ifndef WIDE_BLOCKS
-#define WIDE_BLOCKS 512
-#endif
 
 #include <algorithm>
 #include <type_traits>
