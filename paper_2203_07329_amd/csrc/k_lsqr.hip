@@ -1894,6 +1894,7 @@ struct WBufs {
   Scal* sc;
   void *partN, *partT;
   double *vt, *dt, *xt, *u, *q, *y, *vb, *db, *zb, *t, *pnN, *pnQ;
+  float* y32;      // FP32 copy of y for the FP32 products A^T y
   int32_t* cnt;
   double** Xp;
   double* lams;
@@ -2005,6 +2006,7 @@ void take_wbufs(Arena& a, const WPlan& pl, size_t tc, WBufs& b) {
   b.u = a.take<double>(size_t(pl.totS) * N);
   b.q = a.take<double>(size_t(pl.totS) * N);
   b.y = a.take<double>(size_t(pl.totS) * N);
+  b.y32 = a.take<float>(size_t(pl.totS) * N);
   b.vb = a.take<double>(size_t(pl.totS) * N);
   b.db = a.take<double>(size_t(pl.totS) * N);
   b.zb = a.take<double>(size_t(pl.totS) * N);
@@ -2084,10 +2086,26 @@ int wide_products_n(const WPlan& pl, const WBufs& b, const double* W, void* part
   return TIK_OK;
 }
 
+// FP64 -> FP32 copy of count values.
+__global__ void k_vec_to_f32(const double* __restrict__ x, int64_t count, float* __restrict__ y) {
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count;
+       e += int64_t(gridDim.x) * blockDim.x)
+    y[e] = float(x[e]);
+}
+
 template <typename TA, typename TC, int NC>
 int wide_products_t(const WPlan& pl, const WBufs& b, const double* U, void* part, hipStream_t st) {
   ProfScope ps("gemm_t", st);
   constexpr bool a32 = std::is_same<TA, float>::value, c32 = std::is_same<TC, float>::value;
+  if (NC >= 16 && c32 && U == b.y) {
+    // FP32 products: read y once as FP32 (every column block re-reads it)
+    const int64_t cnt = int64_t(pl.totS) * pl.N;
+    hipLaunchKernelGGL(k_vec_to_f32, dim3(unsigned(std::min<int64_t>(cdiv(cnt, 256), 1024))), dim3(256),
+                       0, st, b.y, cnt, b.y32);
+    TIK_LAUNCHED("k_vec_to_f32");
+    return launch_gemm_t_mfma(a32, c32, 0, NC, pl.cbT, b.P, b.itT, int(pl.itT.size()), pl.N, b.y32, part,
+                              st);
+  }
   if (NC >= 16)
     return launch_gemm_t_mfma(a32, c32, 1, NC, pl.cbT, b.P, b.itT, int(pl.itT.size()), pl.N, U, part, st);
   hipLaunchKernelGGL((k_gemm_t<TA, TC, double, NC>), dim3(unsigned(pl.itT.size())), dim3(BLK), 0, st,
