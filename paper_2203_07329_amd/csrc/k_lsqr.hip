@@ -978,6 +978,7 @@ struct Bufs {
   Scal* sc;
   void* ut;
   double *ub, *v, *q, *w, *e, *x, *t;
+  float* w32;      // FP32 copy of w for the FP32 products A w
   void* part;
   double *pnN, *pnB, *pnQ;
   int32_t* cnt;
@@ -1170,6 +1171,7 @@ void take_bufs(Arena& a, const Plan& pl, size_t tc, Bufs& b) {
   b.v = a.take<double>(size_t(pl.totS) * N);
   b.q = a.take<double>(size_t(pl.totS) * N);
   b.w = a.take<double>(size_t(pl.totS) * N);
+  b.w32 = a.take<float>(size_t(pl.totS) * N);
   b.e = a.take<double>(size_t(pl.totS) * N);
   b.x = a.take<double>(size_t(pl.totS) * N);
   b.t = a.take<double>(size_t(pl.totS) * N);
@@ -1185,14 +1187,34 @@ void take_bufs(Arena& a, const Plan& pl, size_t tc, Bufs& b) {
   b.lidx = a.take<int32_t>(pl.J);
 }
 
+// FP64 -> FP32 copy of count values.
+__global__ void k_vec_to_f32(const double* __restrict__ x, int64_t count, float* __restrict__ y) {
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count;
+       e += int64_t(gridDim.x) * blockDim.x)
+    y[e] = float(x[e]);
+}
+
+// FP32 copy of an FP64 vector block for the FP32 products (read by every block
+// of the product: converted once instead of in every block).
+static int vec_to_f32(const double* x, int64_t count, float* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_vec_to_f32, dim3(unsigned(std::min<int64_t>(cdiv(count, 256), 1024))), dim3(256),
+                     0, st, x, count, y);
+  TIK_LAUNCHED("k_vec_to_f32");
+  return TIK_OK;
+}
+
 template <typename TA, typename TC, int NC>
 struct Kern {
   static int gemm_n(const Plan& pl, const Bufs& b, hipStream_t st) {
     ProfScope ps("gemm_n", st);
-    if (NC >= 16)
-      return launch_gemm_n_mfma(std::is_same<TA, float>::value, std::is_same<TC, float>::value, NC, 0,
-                                pl.rbN, b.P, b.itN, int(pl.itN.size()), pl.N, b.w, b.ut, nullptr, b.sc,
-                                b.pnN, st);
+    if (NC >= 16) {
+      constexpr bool c32 = std::is_same<TC, float>::value;
+      if (c32) TIK_TRY(vec_to_f32(b.w, int64_t(pl.totS) * pl.N, b.w32, st));
+      return launch_gemm_n_mfma(std::is_same<TA, float>::value, c32, NC, 0, pl.rbN, b.P, b.itN,
+                                int(pl.itN.size()), pl.N,
+                                c32 ? static_cast<const void*>(b.w32) : static_cast<const void*>(b.w),
+                                b.ut, nullptr, b.sc, b.pnN, st);
+    }
     if (NC >= 8)
       hipLaunchKernelGGL((k_gemm_n<TA, TC, NC, 256, 1, 0>), dim3(unsigned(pl.itN.size())), dim3(BLK),
                          0, st, b.P, b.itN, pl.N, b.w, static_cast<TC*>(b.ut), nullptr, b.sc, b.pnN);
@@ -1895,6 +1917,7 @@ struct WBufs {
   void *partN, *partT;
   double *vt, *dt, *xt, *u, *q, *y, *vb, *db, *zb, *t, *pnN, *pnQ;
   float* y32;      // FP32 copy of y for the FP32 products A^T y
+  float* w32;      // FP32 copy of the n-side vector for the FP32 products A w
   int32_t* cnt;
   double** Xp;
   double* lams;
@@ -2007,6 +2030,7 @@ void take_wbufs(Arena& a, const WPlan& pl, size_t tc, WBufs& b) {
   b.q = a.take<double>(size_t(pl.totS) * N);
   b.y = a.take<double>(size_t(pl.totS) * N);
   b.y32 = a.take<float>(size_t(pl.totS) * N);
+  b.w32 = a.take<float>(size_t(pl.totL) * N);
   b.vb = a.take<double>(size_t(pl.totS) * N);
   b.db = a.take<double>(size_t(pl.totS) * N);
   b.zb = a.take<double>(size_t(pl.totS) * N);
@@ -2073,9 +2097,12 @@ template <typename TA, typename TC, int NC>
 int wide_products_n(const WPlan& pl, const WBufs& b, const double* W, void* part, hipStream_t st) {
   ProfScope ps("gemm_n", st);
   constexpr bool a32 = std::is_same<TA, float>::value, c32 = std::is_same<TC, float>::value;
-  if (NC >= 16)
-    return launch_gemm_n_mfma(a32, c32, NC, 2, pl.rbN, b.P, b.itNs, int(pl.itNs.size()), pl.N, W, part,
+  if (NC >= 16) {
+    if (c32) TIK_TRY(vec_to_f32(W, int64_t(pl.totL) * pl.N, b.w32, st));
+    return launch_gemm_n_mfma(a32, c32, NC, 2, pl.rbN, b.P, b.itNs, int(pl.itNs.size()), pl.N,
+                              c32 ? static_cast<const void*>(b.w32) : static_cast<const void*>(W), part,
                               nullptr, b.sc, nullptr, st);
+  }
   if (NC >= 8)
     hipLaunchKernelGGL((k_gemm_n<TA, TC, NC, 256, 1, 2>), dim3(unsigned(pl.itNs.size())), dim3(BLK),
                        0, st, b.P, b.itNs, pl.N, W, static_cast<TC*>(part), nullptr, b.sc, nullptr);
@@ -2086,23 +2113,13 @@ int wide_products_n(const WPlan& pl, const WBufs& b, const double* W, void* part
   return TIK_OK;
 }
 
-// FP64 -> FP32 copy of count values.
-__global__ void k_vec_to_f32(const double* __restrict__ x, int64_t count, float* __restrict__ y) {
-  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count;
-       e += int64_t(gridDim.x) * blockDim.x)
-    y[e] = float(x[e]);
-}
-
 template <typename TA, typename TC, int NC>
 int wide_products_t(const WPlan& pl, const WBufs& b, const double* U, void* part, hipStream_t st) {
   ProfScope ps("gemm_t", st);
   constexpr bool a32 = std::is_same<TA, float>::value, c32 = std::is_same<TC, float>::value;
   if (NC >= 16 && c32 && U == b.y) {
     // FP32 products: read y once as FP32 (every column block re-reads it)
-    const int64_t cnt = int64_t(pl.totS) * pl.N;
-    hipLaunchKernelGGL(k_vec_to_f32, dim3(unsigned(std::min<int64_t>(cdiv(cnt, 256), 1024))), dim3(256),
-                       0, st, b.y, cnt, b.y32);
-    TIK_LAUNCHED("k_vec_to_f32");
+    TIK_TRY(vec_to_f32(b.y, int64_t(pl.totS) * pl.N, b.y32, st));
     return launch_gemm_t_mfma(a32, c32, 0, NC, pl.cbT, b.P, b.itT, int(pl.itT.size()), pl.N, b.y32, part,
                               st);
   }

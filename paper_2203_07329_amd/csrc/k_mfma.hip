@@ -47,7 +47,7 @@ struct Mfma<float> {
 template <typename TA, typename TC, int NC, int EPI, int RT>
 __global__ void __launch_bounds__(256, RT == 2 ? 3 : 2) k_gemm_n_mfma(const DevProb* __restrict__ P,
                                                      const Item* __restrict__ items, int N,
-                                                     const double* __restrict__ W,
+                                                     const TC* __restrict__ W,
                                                      TC* __restrict__ ut, double* __restrict__ out,
                                                      const Scal* __restrict__ sc,
                                                      double* __restrict__ pnN) {
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(256, RT == 2 ? 3 : 2) k_gemm_n_mfma(const DevP
       const int e = threadIdx.x + 256 * q;
       const int kk = e / NC, i = e % NC;
       const int64_t kg = k0 + kk;
-      dst[q] = (e < KC * NC && kg < kend && i < N) ? TC(W[(pr.offC + kg) * N + i]) : TC(0);
+      dst[q] = (e < KC * NC && kg < kend && i < N) ? W[(pr.offC + kg) * N + i] : TC(0);
     }
   };
   auto store_w = [&](int buf, const TC (&src)[QW]) {
@@ -282,8 +282,9 @@ __global__ void __launch_bounds__(256) k_gemm_t_mfma(const DevProb* __restrict__
 // --------------------------------------------------------------- launchers --
 template <typename TA, typename TC, int RT>
 static int gemm_n_rt(int nc, int epi, const DevProb* P, const Item* items, int nitems, int N,
-                     const double* W, void* ut, double* out, const Scal* sc, double* pnN,
+                     const void* Wv, void* ut, double* out, const Scal* sc, double* pnN,
                      hipStream_t st) {
+  const TC* W = static_cast<const TC*>(Wv);
   const dim3 g = dim3(unsigned(nitems)), b = dim3(256);
   TC* u = static_cast<TC*>(ut);
 #define TIK_GN(NCV, EPIV)                                                                     \
@@ -301,7 +302,7 @@ static int gemm_n_rt(int nc, int epi, const DevProb* P, const Item* items, int n
 
 template <typename TA, typename TC>
 static int gemm_n_nc(int rows, int nc, int epi, const DevProb* P, const Item* items, int nitems,
-                     int N, const double* W, void* ut, double* out, const Scal* sc, double* pnN,
+                     int N, const void* W, void* ut, double* out, const Scal* sc, double* pnN,
                      hipStream_t st) {
   if (rows == 128) return gemm_n_rt<TA, TC, 2>(nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
   if (rows == 256) return gemm_n_rt<TA, TC, 4>(nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
@@ -310,7 +311,7 @@ static int gemm_n_nc(int rows, int nc, int epi, const DevProb* P, const Item* it
 }
 
 int launch_gemm_n_mfma(int ta_f32, int tc_f32, int nc, int epi, int rows, const DevProb* P,
-                       const Item* items, int nitems, int N, const double* W, void* ut,
+                       const Item* items, int nitems, int N, const void* W, void* ut,
                        double* out, const Scal* sc, double* pnN, hipStream_t st) {
   if (tc_f32) {
     if (!ta_f32) {

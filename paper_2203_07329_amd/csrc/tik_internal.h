@@ -167,9 +167,10 @@ int launch_shift_copy(const double* C, int64_t n, const double* lams, int32_t nb
 int launch_chol_inv_jobs(const CholJob* jobs, const int64_t* nsz, int32_t njobs, hipStream_t st);
 
 // matrix-core products (k_mfma.hip)
-// rows: rows of A per gemm_n block (128 or 256); cols: columns per gemm_t block (64 or 128)
+// rows: rows of A per gemm_n block (128 or 256); cols: columns per gemm_t block (64 or 128).
+// W is in the compute type (float when tc_f32, else double).
 int launch_gemm_n_mfma(int ta_f32, int tc_f32, int nc, int epi, int rows, const DevProb* P,
-                       const Item* items, int nitems, int N, const double* W, void* ut,
+                       const Item* items, int nitems, int N, const void* W, void* ut,
                        double* out, const Scal* sc, double* pnN, hipStream_t st);
 int launch_gemm_t_mfma(int ta_f32, int tc_f32, int u_f64, int nc, int cols, const DevProb* P,
                        const Item* items, int nitems, int N, const void* U, void* part,
