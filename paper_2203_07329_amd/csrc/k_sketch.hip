@@ -456,7 +456,7 @@ __device__ __forceinline__ void gauss4f(uint64_t seed, uint32_t r, uint32_t qb, 
 // matrix-core operand loads want: the Philox/Box-Muller normals of the FP64
 // generator (computed in FP32, see gauss4f), rounded to BF16.
 __global__ void __launch_bounds__(256) k_gauss_gen_bf16(uint64_t seed, int64_t s, int64_t r0,
-                                                        int64_t kc, float scale,
+                                                        int64_t kc, int64_t ldx, float scale,
                                                         __hip_bfloat16* __restrict__ X) {
   const int64_t sq = (s + 3) >> 2;
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -467,7 +467,7 @@ __global__ void __launch_bounds__(256) k_gauss_gen_bf16(uint64_t seed, int64_t s
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int64_t q = qb * 4 + t;
-    if (q < s) X[q * kc + cc] = __float2bfloat16(z[t] * scale);
+    if (q < s) X[q * ldx + cc] = __float2bfloat16(z[t] * scale);
   }
 }
 
@@ -534,7 +534,8 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
 // that XCD's L2, and each operand panel is fetched by ps or pc XCDs only.
 template <typename TA, bool WIDE, int KB>
 __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* __restrict__ X,
-                                                          int64_t s, int64_t kc, int64_t ksz,
+                                                          int64_t s, int64_t kc, int64_t ldx,
+                                                          int64_t ksz,
                                                           const TA* __restrict__ A, int64_t lda,
                                                           int64_t r0, int64_t ncol, int sR, int cR,
                                                           int pc, float* __restrict__ Y, int first) {
@@ -565,32 +566,39 @@ __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* 
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
   // register stage of one step: X (HK bf16 per thread), B (HK values per thread).
-  // Whole steps whose runs of A start 16-byte aligned (base, lda and the
-  // chunk origin multiples of 16 bytes / sizeof(TA)) and whose X rows are
-  // whole 16-byte runs (kc a multiple of 8) are prefetched with 16-byte loads
-  // during the previous step's MFMAs; any other step (the ragged last one, a
-  // misaligned A) is copied element by element into LDS after the barrier.
+  // Every whole step is prefetched during the previous step's MFMAs: X rows
+  // (pitch ldx, a multiple of 8) with 16-byte loads, A with 16-byte loads
+  // where its runs start 16-byte aligned (base, lda and the chunk origin
+  // multiples of 16 bytes / sizeof(TA)), else with one load per element (a
+  // tall A whose row count is odd, say).  The ragged last step is copied
+  // element by element into LDS after the barrier.
   uint4 rx[HK / 8];
   float rb[HK];
   constexpr int64_t VE = 16 / sizeof(TA);
-  const bool vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && lda % VE == 0 && r0 % VE == 0 &&
-                   (WIDE ? (c0 % VE == 0) : (kb % VE == 0)) && (kc & 7) == 0;
-  auto whole = [&](int64_t k0) { return vec && k0 + KB <= ke; };
+  const bool vx = (reinterpret_cast<uintptr_t>(X) % 16 == 0) && (ldx & 7) == 0;
+  const bool va = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && lda % VE == 0 && r0 % VE == 0 &&
+                  (WIDE ? (c0 % VE == 0) : (kb % VE == 0));
+  auto whole = [&](int64_t k0) { return vx && k0 + KB <= ke; };
   auto fetch = [&](int64_t k0) {               // whole steps only
     {
       const int row = tid >> 1, half = tid & 1;
       const int64_t q = q0 + row;
 #pragma unroll
       for (int h = 0; h < HK / 8; ++h)
-        rx[h] = q < s ? *reinterpret_cast<const uint4*>(X + q * kc + k0 + half * HK + h * 8)
+        rx[h] = q < s ? *reinterpret_cast<const uint4*>(X + q * ldx + k0 + half * HK + h * 8)
                       : make_uint4(0, 0, 0, 0);
     }
     if (!WIDE) {
       const int col = tid >> 1, half = tid & 1;
       const int64_t c = c0 + col;
       const TA* src = A + (r0 + k0 + half * HK) + min(c, ncol - 1) * lda;
+      if (va) {
 #pragma unroll
-      for (int h = 0; h < HK / 16; ++h) lr16(src + 16 * h, *reinterpret_cast<float(*)[16]>(rb + 16 * h));
+        for (int h = 0; h < HK / 16; ++h) lr16(src + 16 * h, *reinterpret_cast<float(*)[16]>(rb + 16 * h));
+      } else {
+#pragma unroll
+        for (int e = 0; e < HK; ++e) rb[e] = float(src[e]);
+      }
       if (c >= ncol)
 #pragma unroll
         for (int e = 0; e < HK; ++e) rb[e] = 0.f;
@@ -603,7 +611,7 @@ __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* 
 #pragma unroll
       for (int kk = 0; kk < WK; ++kk) {
         const int64_t k = k0 + WK * k4 + kk;
-        if (cin) {
+        if (cin && va) {
           lr4(A + c + (r0 + k) * lda, rb + 4 * kk);
         } else {
 #pragma unroll
@@ -643,7 +651,7 @@ __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* 
     for (int e = tid; e < 128 * KB; e += 256) {
       const int r = e / KB, kk = e % KB;
       const int64_t k = k0 + kk, q = q0 + r, c = c0 + r;
-      Xs[r * LP + kk] = (q < s && k < ke) ? *reinterpret_cast<const uint16_t*>(X + q * kc + k) : 0;
+      Xs[r * LP + kk] = (q < s && k < ke) ? *reinterpret_cast<const uint16_t*>(X + q * ldx + k) : 0;
       const float v = (c < ncol && k < ke) ? float(WIDE ? A[c + (r0 + k) * lda] : A[(r0 + k) + c * lda])
                                            : 0.f;
       const __hip_bfloat16 h = __float2bfloat16(v);
@@ -790,14 +798,18 @@ int launch_srht_twopass(const void* A, int a_f32, int64_t m, int64_t lda, int64_
   return TIK_OK;
 }
 
-int launch_gauss_gen(uint64_t seed, int64_t s, int64_t r0, int64_t kc, void* Xc, int bf16,
-                     hipStream_t st) {
+int launch_gauss_gen(uint64_t seed, int64_t s, int64_t r0, int64_t kc, int64_t ldx, void* Xc,
+                     int bf16, hipStream_t st) {
+  if (ldx < kc || (!bf16 && ldx != kc)) {
+    set_error("internal: Gaussian chunk pitch");
+    return TIK_EINVAL;
+  }
   const int64_t total = ((s + 3) >> 2) * kc;
   const double scale = 1.0 / sqrt(double(s));
   ProfScope ps("sketch", st);
   if (bf16)
     hipLaunchKernelGGL(k_gauss_gen_bf16, dim3(unsigned(cdiv(total, 256))), dim3(256), 0, st, seed,
-                       s, r0, kc, float(scale), static_cast<__hip_bfloat16*>(Xc));
+                       s, r0, kc, ldx, float(scale), static_cast<__hip_bfloat16*>(Xc));
   else
     hipLaunchKernelGGL(k_gauss_gen<double>, dim3(unsigned(cdiv(total, 256))), dim3(256), 0, st,
                        seed, s, r0, kc, scale, static_cast<double*>(Xc));
@@ -832,8 +844,8 @@ int sketch_bf16_splits(int64_t s, int64_t ncol, int64_t kc, int64_t part_cap) {
   return int(std::max<int64_t>(1, z));
 }
 
-int launch_sketch_gemm_bf16(const void* Xc, int64_t s, int64_t kc, const void* A, int a_f32,
-                            int64_t lda, int64_t r0, int64_t ncol, int wide, float* Yacc,
+int launch_sketch_gemm_bf16(const void* Xc, int64_t s, int64_t kc, int64_t ldx, const void* A,
+                            int a_f32, int64_t lda, int64_t r0, int64_t ncol, int wide, float* Yacc,
                             int first, float* part, int64_t part_cap, hipStream_t st) {
   int nz = sketch_bf16_splits(s, ncol, kc, part_cap);
   const int64_t ksz = cdiv(cdiv(kc, nz), SK_KB) * SK_KB;
@@ -860,11 +872,11 @@ int launch_sketch_gemm_bf16(const void* Xc, int64_t s, int64_t kc, const void* A
   const __hip_bfloat16* X = static_cast<const __hip_bfloat16*>(Xc);
   ProfScope ps("sketch", st);
   if (a_f32) {
-    if (wide) hipLaunchKernelGGL((k_sketch_gemm_bf16<float, true, SK_KB>), grid, dim3(256), 0, st, X, s, kc, ksz, static_cast<const float*>(A), lda, r0, ncol, sR, cR, pc, dst, first);
-    else      hipLaunchKernelGGL((k_sketch_gemm_bf16<float, false, SK_KB>), grid, dim3(256), 0, st, X, s, kc, ksz, static_cast<const float*>(A), lda, r0, ncol, sR, cR, pc, dst, first);
+    if (wide) hipLaunchKernelGGL((k_sketch_gemm_bf16<float, true, SK_KB>), grid, dim3(256), 0, st, X, s, kc, ldx, ksz, static_cast<const float*>(A), lda, r0, ncol, sR, cR, pc, dst, first);
+    else      hipLaunchKernelGGL((k_sketch_gemm_bf16<float, false, SK_KB>), grid, dim3(256), 0, st, X, s, kc, ldx, ksz, static_cast<const float*>(A), lda, r0, ncol, sR, cR, pc, dst, first);
   } else {
-    if (wide) hipLaunchKernelGGL((k_sketch_gemm_bf16<double, true, SK_KB>), grid, dim3(256), 0, st, X, s, kc, ksz, static_cast<const double*>(A), lda, r0, ncol, sR, cR, pc, dst, first);
-    else      hipLaunchKernelGGL((k_sketch_gemm_bf16<double, false, SK_KB>), grid, dim3(256), 0, st, X, s, kc, ksz, static_cast<const double*>(A), lda, r0, ncol, sR, cR, pc, dst, first);
+    if (wide) hipLaunchKernelGGL((k_sketch_gemm_bf16<double, true, SK_KB>), grid, dim3(256), 0, st, X, s, kc, ldx, ksz, static_cast<const double*>(A), lda, r0, ncol, sR, cR, pc, dst, first);
+    else      hipLaunchKernelGGL((k_sketch_gemm_bf16<double, false, SK_KB>), grid, dim3(256), 0, st, X, s, kc, ldx, ksz, static_cast<const double*>(A), lda, r0, ncol, sR, cR, pc, dst, first);
   }
   TIK_LAUNCHED("k_sketch_gemm_bf16");
   if (nz > 1) {

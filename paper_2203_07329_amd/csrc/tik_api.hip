@@ -194,6 +194,12 @@ static int64_t gauss_chunk(const tik_problem& q, int64_t s, int32_t sdt) {
   return kc;
 }
 
+// row pitch of a Gaussian X chunk: BF16 rows start 16-byte aligned so the
+// sketch product fetches them with vector loads
+static int64_t gauss_pitch(int64_t kc, int32_t sdt) {
+  return sdt == TIK_BF16 ? cdiv(kc, 8) * 8 : kc;
+}
+
 static int sketch_plan(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sdt,
                        const int64_t* s, Arena& a, SketchPlan& sp) {
   sp.Y.assign(size_t(nprob), nullptr);
@@ -218,7 +224,8 @@ static int sketch_plan(const tik_problem* p, int32_t nprob, int32_t embed, int32
       }
     } else {
       const size_t esz = sdt == TIK_BF16 ? 2 : sizeof(double);
-      xsz = std::max<int64_t>(xsz, int64_t(cdiv(gauss_chunk(p[k], s[k], sdt) * s[k] * esz, 8)));
+      xsz = std::max<int64_t>(xsz, int64_t(cdiv(gauss_pitch(gauss_chunk(p[k], s[k], sdt), sdt) *
+                                                s[k] * int64_t(esz), 8)));
       if (sdt == TIK_BF16) {
         ysz = std::max<int64_t>(ysz, s[k] * sp.ycols[k]);
         const int64_t kc = gauss_chunk(p[k], s[k], sdt);
@@ -374,8 +381,10 @@ int tik_sketch(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sketc
       if (sketch_dtype == TIK_BF16) {
         for (int64_t r0 = 0; r0 < longdim; r0 += chunk) {
           const int64_t kc = std::min(chunk, longdim - r0);
-          TIK_TRY(launch_gauss_gen(pseed, s[k], r0, kc, sp.Xc[ln], 1, st));
-          TIK_TRY(launch_sketch_gemm_bf16(sp.Xc[ln], s[k], kc, q.A, f32, q.lda, r0, ncol, t ? 0 : 1,
+          const int64_t ldx = gauss_pitch(kc, sketch_dtype);
+          TIK_TRY(launch_gauss_gen(pseed, s[k], r0, kc, ldx, sp.Xc[ln], 1, st));
+          TIK_TRY(launch_sketch_gemm_bf16(sp.Xc[ln], s[k], kc, ldx, q.A, f32, q.lda, r0, ncol,
+                                          t ? 0 : 1,
                                           sp.Yacc[ln], r0 == 0 ? 1 : 0, sp.Ypart[ln], sp.part_cap,
                                           st));
         }
@@ -384,7 +393,7 @@ int tik_sketch(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sketc
         TIK_HIP(hipMemsetAsync(sp.Y[k], 0, size_t(s[k]) * size_t(ncol) * sizeof(double), st));
         for (int64_t r0 = 0; r0 < longdim; r0 += chunk) {
           const int64_t kc = std::min(chunk, longdim - r0);
-          TIK_TRY(launch_gauss_gen(pseed, s[k], r0, kc, sp.Xc[ln], 0, st));
+          TIK_TRY(launch_gauss_gen(pseed, s[k], r0, kc, kc, sp.Xc[ln], 0, st));
           TIK_TRY(launch_sketch_gemm_f64(sp.Xc[ln], s[k], kc, q.A, f32, q.lda, r0, ncol, t ? 0 : 1,
                                          sp.Y[k], st));
         }

@@ -133,14 +133,15 @@ int launch_srht_single(const void* A, int a_f32, int64_t m, int64_t n, int64_t l
 int launch_srht_twopass(const void* A, int a_f32, int64_t m, int64_t lda, int64_t c0, int64_t nc,
                         int k, int bbits, const int32_t* rows, int64_t s, double* T, double* Y,
                         hipStream_t st);
-int launch_gauss_gen(uint64_t seed, int64_t s, int64_t r0, int64_t kc, void* Xc, int bf16,
-                     hipStream_t st);
+// X chunk (s rows of kc generated values, row pitch ldx; FP64 needs ldx == kc)
+int launch_gauss_gen(uint64_t seed, int64_t s, int64_t r0, int64_t kc, int64_t ldx, void* Xc,
+                     int bf16, hipStream_t st);
 int launch_sketch_gemm_f64(const double* Xc, int64_t s, int64_t kc, const void* A, int a_f32,
                            int64_t lda, int64_t r0, int64_t ncol, int wide, double* Y,
                            hipStream_t st);
 int sketch_bf16_splits(int64_t s, int64_t ncol, int64_t kc, int64_t part_cap);
-int launch_sketch_gemm_bf16(const void* Xc, int64_t s, int64_t kc, const void* A, int a_f32,
-                            int64_t lda, int64_t r0, int64_t ncol, int wide, float* Yacc,
+int launch_sketch_gemm_bf16(const void* Xc, int64_t s, int64_t kc, int64_t ldx, const void* A,
+                            int a_f32, int64_t lda, int64_t r0, int64_t ncol, int wide, float* Yacc,
                             int first, float* part, int64_t part_cap, hipStream_t st);
 int launch_f32_to_f64(const float* src, double* dst, int64_t count, hipStream_t st);
 

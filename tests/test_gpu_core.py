@@ -296,8 +296,10 @@ def _bf16(a):
     return r.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("m,s", [(1000, 64), (3000, 200)])
+@pytest.mark.parametrize("m,s", [(1000, 64), (3000, 200), (1001, 64), (2999, 200)])
 def test_bf16_sketch_matches_rounded_gaussian(m, s):
+    # odd m: the columns of A start at any 4-byte offset and the X rows are
+    # padded to a 16-byte pitch
     I = np.eye(m)
     pr = tik.Problems.from_numpy([I], [np.ones(m)])
     Xb = tik.sketch(pr, tik.GAUSS, [s], 21, sketch_dtype=tik.BF16).Y(0)
