@@ -28,6 +28,7 @@
 #include "tik_internal.h"
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 namespace tik {
@@ -144,6 +145,7 @@ __global__ void __launch_bounds__(BLK) k_gemm_n(const DevProb* __restrict__ P,
   __shared__ double nred[4];
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
+  if (pr.live && *pr.live == 0) return;   // every solve of the plan has stopped
   const TA* __restrict__ A = static_cast<const TA*>(pr.A);
   const int64_t m = pr.m, n = pr.n, lda = pr.lda;
   const int tr = threadIdx.x % RB, ks = threadIdx.x / RB;
@@ -266,6 +268,7 @@ __global__ void __launch_bounds__(BLK) k_gemm_t(const DevProb* __restrict__ P,
   __shared__ TC red[4][64][NC < 4 ? NC : 1];
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
+  if (pr.live && *pr.live == 0) return;   // every solve of the plan has stopped
   const TA* __restrict__ A = static_cast<const TA*>(pr.A);
   const int64_t m = pr.m, n = pr.n, lda = pr.lda;
   const int64_t c0 = int64_t(it.blk) * 64;
@@ -1313,6 +1316,71 @@ struct IrRhs {
   int l0;               // global index of refinement column 0
 };
 
+// ------------------------------------------------------ iteration control --
+// The solve loops read the active count of iteration i on the host while
+// iteration i + 1 already runs: the count goes to a pinned host word (two per
+// solve, alternating), an event marks its arrival.  Iteration i + 1 is then
+// queued before the host waits, so the GPU never idles on the check; when the
+// count was 0 the products of that surplus iteration return at once (the
+// plan's `live` word) and the vector steps leave finished solves unchanged.
+std::mutex g_pin_mu;
+std::vector<int32_t*> g_pin_free;   // pinned pairs, kept for the process
+
+struct IterGate {
+  int32_t* h = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool clean = false;               // no copy in flight: the pair may be reused
+  int open() {
+    {
+      std::lock_guard<std::mutex> lk(g_pin_mu);
+      if (!g_pin_free.empty()) {
+        h = g_pin_free.back();
+        g_pin_free.pop_back();
+      }
+    }
+    if (!h) {
+      void* p = nullptr;
+      TIK_HIP(hipHostMalloc(&p, 2 * sizeof(int32_t), hipHostMallocDefault));
+      h = static_cast<int32_t*>(p);
+    }
+    for (auto& e : ev) TIK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return TIK_OK;
+  }
+  // after the iteration `it` is queued: count, copy, and look at it - 1
+  int step(int it, const Scal* sc, int J, int32_t* cnt, hipStream_t st, bool& stop) {
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(BLK), 0, st, sc, J, cnt);
+    TIK_LAUNCHED("k_count_active");
+    TIK_HIP(hipMemcpyAsync(h + (it & 1), cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    TIK_HIP(hipEventRecord(ev[it & 1], st));
+    stop = false;
+    if (it > 0) {
+      TIK_HIP(hipEventSynchronize(ev[(it - 1) & 1]));
+      stop = h[(it - 1) & 1] == 0;
+    }
+    if (stop) {   // the products of iteration `it` return at once
+      prof_drop_last("gemm_n");
+      prof_drop_last("gemm_t");
+    }
+    return TIK_OK;
+  }
+  // products run again outside the loop (refinement residuals, later calls)
+  int close(int32_t* cnt, hipStream_t st) {
+    TIK_HIP(hipMemsetAsync(cnt, 1, sizeof(int32_t), st));
+    for (auto& e : ev)
+      if (e) TIK_HIP(hipEventSynchronize(e));
+    clean = true;
+    return TIK_OK;
+  }
+  ~IterGate() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (h && clean) {
+      std::lock_guard<std::mutex> lk(g_pin_mu);
+      g_pin_free.push_back(h);
+    }
+  }
+};
+
 template <typename TA, typename TC, int NC>
 int run_core(const Plan& pl, const Bufs& b, double tol, int maxit, hipStream_t st,
              const IrRhs* ir) {
@@ -1335,23 +1403,18 @@ int run_core(const Plan& pl, const Bufs& b, double tol, int maxit, hipStream_t s
   }
   TIK_TRY(K::gemm_t(pl, b, st));
   TIK_TRY((vec_steps_v<TC, NC>(pl, b, st, true, tol, maxit)));
-  const int chunk = 8;
-  int32_t active = 1;
-  for (int it = 0; it < maxit && active > 0;) {
-    const int todo = std::min(chunk, maxit - it);
-    for (int q = 0; q < todo; ++q) {
-      TIK_TRY(K::gemm_n(pl, b, st));
-      TIK_TRY(vec_steps_u<TC>(pl, b, st, false, nullptr, nullptr));
-      TIK_TRY(K::gemm_t(pl, b, st));
-      TIK_TRY((vec_steps_v<TC, NC>(pl, b, st, false, tol, maxit)));
-    }
-    it += todo;
-    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(BLK), 0, st, b.sc, pl.J, b.cnt);
-    TIK_LAUNCHED("k_count_active");
-    TIK_HIP(hipMemcpyAsync(&active, b.cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    TIK_HIP(hipStreamSynchronize(st));
+  IterGate gate;
+  TIK_TRY(gate.open());
+  for (int it = 0; it < maxit; ++it) {
+    TIK_TRY(K::gemm_n(pl, b, st));
+    TIK_TRY(vec_steps_u<TC>(pl, b, st, false, nullptr, nullptr));
+    TIK_TRY(K::gemm_t(pl, b, st));
+    TIK_TRY((vec_steps_v<TC, NC>(pl, b, st, false, tol, maxit)));
+    bool stop = false;
+    TIK_TRY(gate.step(it, b.sc, pl.J, b.cnt, st, stop));
+    if (stop) break;
   }
-  return TIK_OK;
+  return gate.close(b.cnt, st);
 }
 
 template <typename TA, typename TC>
@@ -1377,7 +1440,10 @@ int upload_plan(const Plan& pl, const Bufs& b, const tik_precond_s* pc, double* 
     keep.emplace_back(static_cast<const char*>(src), static_cast<const char*>(src) + bytes);
     return keep.back().data();
   };
-  TIK_TRY(upload(b.P, stash(pl.P.data(), pl.P.size() * sizeof(DevProb)), pl.P.size() * sizeof(DevProb), st));
+  std::vector<DevProb> P = pl.P;
+  for (auto& d : P) d.live = b.cnt;
+  TIK_HIP(hipMemsetAsync(b.cnt, 1, sizeof(int32_t), st));
+  TIK_TRY(upload(b.P, stash(P.data(), P.size() * sizeof(DevProb)), P.size() * sizeof(DevProb), st));
   TIK_TRY(upload(b.itN, stash(pl.itN.data(), pl.itN.size() * sizeof(Item)), pl.itN.size() * sizeof(Item), st));
   TIK_TRY(upload(b.itB, stash(pl.itB.data(), pl.itB.size() * sizeof(Item)), pl.itB.size() * sizeof(Item), st));
   TIK_TRY(upload(b.itT, stash(pl.itT.data(), pl.itT.size() * sizeof(Item)), pl.itT.size() * sizeof(Item), st));
@@ -2053,7 +2119,10 @@ int upload_wplan(const WPlan& pl, const WBufs& b, const tik_precond_s* pc, doubl
     TIK_HIP(hipMemcpyAsync(dst, keep.back().data(), bytes, hipMemcpyHostToDevice, st));
     return TIK_OK;
   };
-  TIK_TRY(put(b.P, pl.P.data(), pl.P.size() * sizeof(DevProb)));
+  std::vector<DevProb> P = pl.P;
+  for (auto& d : P) d.live = b.cnt;
+  TIK_HIP(hipMemsetAsync(b.cnt, 1, sizeof(int32_t), st));
+  TIK_TRY(put(b.P, P.data(), P.size() * sizeof(DevProb)));
   TIK_TRY(put(b.itNs, pl.itNs.data(), pl.itNs.size() * sizeof(Item)));
   TIK_TRY(put(b.itT, pl.itT.data(), pl.itT.size() * sizeof(Item)));
   TIK_TRY(put(b.itQ, pl.itQ.data(), pl.itQ.size() * sizeof(Item)));
@@ -2204,28 +2273,23 @@ int run_core_wide(const WPlan& pl, const WBufs& b, double tol, int maxit, hipStr
   }
   TIK_TRY(wide_u_steps(pl, b, st, true));
   TIK_TRY((wide_v_steps<TA, TC, NC>(pl, b, st, true, tol, maxit)));
-  const int chunk = 8;
-  int32_t active = 1;
-  for (int it = 0; it < maxit && active > 0;) {
-    const int todo = std::min(chunk, maxit - it);
-    for (int q = 0; q < todo; ++q) {
-      TIK_TRY((wide_products_n<TA, TC, NC>(pl, b, b.vt, b.partN, st)));
-      {
-        ProfScope ps("vec", st);
-        hipLaunchKernelGGL((k_wide_h<TC, NC, 0>), dim3(unsigned(pl.itR.size())), dim3(BLK), 0, st,
-                           b.P, b.itR, pl.N, static_cast<const TC*>(b.partN), b.vb, b.sc, b.t);
-        TIK_LAUNCHED("k_wide_h");
-      }
-      TIK_TRY(wide_u_steps(pl, b, st, false));
-      TIK_TRY((wide_v_steps<TA, TC, NC>(pl, b, st, false, tol, maxit)));
+  IterGate gate;
+  TIK_TRY(gate.open());
+  for (int it = 0; it < maxit; ++it) {
+    TIK_TRY((wide_products_n<TA, TC, NC>(pl, b, b.vt, b.partN, st)));
+    {
+      ProfScope ps("vec", st);
+      hipLaunchKernelGGL((k_wide_h<TC, NC, 0>), dim3(unsigned(pl.itR.size())), dim3(BLK), 0, st,
+                         b.P, b.itR, pl.N, static_cast<const TC*>(b.partN), b.vb, b.sc, b.t);
+      TIK_LAUNCHED("k_wide_h");
     }
-    it += todo;
-    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(BLK), 0, st, b.sc, pl.J, b.cnt);
-    TIK_LAUNCHED("k_count_active");
-    TIK_HIP(hipMemcpyAsync(&active, b.cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    TIK_HIP(hipStreamSynchronize(st));
+    TIK_TRY(wide_u_steps(pl, b, st, false));
+    TIK_TRY((wide_v_steps<TA, TC, NC>(pl, b, st, false, tol, maxit)));
+    bool stop = false;
+    TIK_TRY(gate.step(it, b.sc, pl.J, b.cnt, st, stop));
+    if (stop) break;
   }
-  return TIK_OK;
+  return gate.close(b.cnt, st);
 }
 
 template <typename TA, typename TC>

@@ -60,6 +60,7 @@ __global__ void __launch_bounds__(256, RT == 2 ? 3 : 2) k_gemm_n_mfma(const DevP
   __shared__ double nred[4][NC];
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
+  if (pr.live && *pr.live == 0) return;   // every solve of the plan has stopped
   const TA* __restrict__ A = static_cast<const TA*>(pr.A);
   const int64_t m = pr.m, n = pr.n, lda = pr.lda;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -197,6 +198,7 @@ __global__ void __launch_bounds__(256) k_gemm_t_mfma(const DevProb* __restrict__
   if (L >= nitems) return;
   const Item it = items[L];
   const DevProb& pr = P[it.p];
+  if (pr.live && *pr.live == 0) return;   // every solve of the plan has stopped
   const TA* __restrict__ A = static_cast<const TA*>(pr.A);
   const int64_t m = pr.m, n = pr.n, lda = pr.lda;
   const int64_t c0 = int64_t(it.blk) * CB;

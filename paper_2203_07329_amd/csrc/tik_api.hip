@@ -65,6 +65,17 @@ ProfScope::~ProfScope() {
   o.second = {nullptr, nullptr};
 }
 
+void prof_drop_last(const char* family) {
+  if (!g_prof_on) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  auto it = g_prof.find(family);
+  if (it == g_prof.end() || it->second.ev.empty()) return;
+  const auto e = it->second.ev.back();
+  it->second.ev.pop_back();
+  (void)hipEventDestroy(e.first);
+  (void)hipEventDestroy(e.second);
+}
+
 // ---------------------------------------------------------------- helpers --
 static bool tall(const tik_problem& p) { return p.m >= p.n; }
 

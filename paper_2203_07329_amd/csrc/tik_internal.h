@@ -45,6 +45,9 @@ struct ProfScope {
   int slot;
   hipStream_t st;
 };
+// Forget the last launch recorded for a family: a launch whose kernels
+// returned at once (the surplus iteration of a solve loop) moved no data.
+void prof_drop_last(const char* family);
 
 // --------------------------------------------------------------- workspace --
 // Bump allocator over a caller-provided device buffer.  With base == nullptr it
@@ -101,6 +104,10 @@ struct DevProb {
   int32_t nblkN, nblkB, nblkQ, nchT;
   int64_t ptOff;       // first row of this problem in the gemm_T partial buffer
   int64_t rchunk;      // rows per gemm_T chunk
+  // solves of the plan still active, as counted after the last iteration
+  // (null: always run).  The products over A return at once when it reads 0:
+  // the solve loop queues one iteration ahead of the count it has seen.
+  const int32_t* live;
 };
 
 // Per-(problem, lambda) LSQR scalars, all FP64.
