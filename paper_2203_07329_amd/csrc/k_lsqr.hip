@@ -671,12 +671,12 @@ __global__ void __launch_bounds__(BLK) k_init_u_ir(const DevProb* __restrict__ P
     for (int64_t r = r0 + threadIdx.x; r < r1; r += BLK) {
       double v;
       if (top) {
-        v = on ? f[(pr.offL + r) * NF + li] : 0.0;
+        v = on ? f[(pr.irL + r) * NF + li] : 0.0;
         const TC vc = TC(v);
         ut[(pr.offL + r) * N + i] = vc;
         v = double(vc);
       } else {
-        v = on ? g[(pr.offS + r) * NF + li] * isq : 0.0;
+        v = on ? g[(pr.irS + r) * NF + li] * isq : 0.0;
         ub[(pr.offS + r) * N + i] = v;
       }
       acc += v * v;
@@ -697,7 +697,7 @@ __global__ void k_ir_scatter(const DevProb* __restrict__ P, int N, int NF, int l
   const bool ok = use[j] && (S.status == TIK_ST_CONVERGED || S.status == TIK_ST_MAXIT);
   for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < pr.n;
        c += int64_t(gridDim.x) * blockDim.x)
-    if (ok) dx[(pr.offS + c) * NF + (S.li - l0)] = xin[(pr.offS + c) * N + i];
+    if (ok) dx[(pr.irS + c) * NF + (S.li - l0)] = xin[(pr.offS + c) * N + i];
 }
 
 // x += dx; s += a; r += f - a.  Long rows for (r, s), short rows for x.
@@ -744,13 +744,14 @@ __global__ void __launch_bounds__(BLK) k_ir_update_x(const DevProb* __restrict__
 }
 
 // Copy the inner solves' iteration counts and statuses out per global lambda.
-__global__ void k_ir_inner_stats(int J, int N, int NF, int l0, const Scal* __restrict__ sc,
-                                 const int32_t* __restrict__ use, int32_t* __restrict__ out) {
+__global__ void k_ir_inner_stats(const DevProb* __restrict__ P, int J, int N, int NF, int l0,
+                                 const Scal* __restrict__ sc, const int32_t* __restrict__ use,
+                                 int32_t* __restrict__ out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= J) return;
   const int p = j / N;
   const Scal& S = sc[j];
-  const int g = p * NF + (S.li - l0);
+  const int g = P[p].gp * NF + (S.li - l0);
   out[2 * g] = use[j] ? S.iters : 0;
   out[2 * g + 1] = use[j] ? S.status : -1;
 }
@@ -1083,6 +1084,9 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
     d.offS = pl.totS;
     d.offR = d.offL;
     d.offC = d.offS;
+    d.irL = d.offL;
+    d.irS = d.offS;
+    d.gp = pidx[lp];
     d.cchunk = g.n;
     d.nchN = 1;
     d.pnOff = 0;
@@ -1650,11 +1654,22 @@ int ir_reduce_g_nc(const Plan& pf, const Bufs& bf, const double* x, double* g, h
 // or FP64 products; the result is scattered into w.dx.
 template <typename TA64>
 int inner_solve(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, const MixedWs& w,
-                const std::vector<int>& sel, const std::vector<uint8_t>& use_h, int NF, int l0,
-                bool f32, double tol, int maxit, hipStream_t st,
+                const Plan& pf, const std::vector<int>& sel, const std::vector<uint8_t>& use_h,
+                int NF, int l0, bool f32, double tol, int maxit, hipStream_t st,
                 std::vector<std::vector<char>>& keep) {
+  // only the problems with a lambda to correct: a pass over A costs the same
+  // for one lambda as for all of a problem's, so late sweeps, where few
+  // lambdas are left, read only their problems
   std::vector<int> ps;
-  for (int k = 0; k < nprob; ++k) ps.push_back(k);
+  for (int k = 0; k < nprob; ++k) {
+    bool any = false;
+    for (int li : sel) any |= use_h[size_t(k) * NF + size_t(li - l0)] != 0;
+    if (any) ps.push_back(k);
+  }
+  if (ps.empty() || pf.P.size() != size_t(nprob)) {
+    set_error("internal: inner solve without problems");
+    return TIK_EINVAL;
+  }
   std::vector<const void*> Aov(static_cast<size_t>(nprob));
   std::vector<int64_t> ldo(static_cast<size_t>(nprob));
   bool any_override = false;
@@ -1667,8 +1682,24 @@ int inner_solve(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, co
   Plan pl;
   make_plan(p, pc, ps, sel, pl, any_override ? Aov.data() : nullptr,
             any_override ? ldo.data() : nullptr);
-  if (f32)
-    for (auto& d : pl.P) d.a_f32 = 1;
+  {
+    // the region is sized for all problems; a subset chunks its rows finer
+    // and may need more partial rows: then take them all
+    Arena m;
+    Bufs mb;
+    take_bufs(m, pl, f32 ? sizeof(float) : sizeof(double), mb);
+    if (m.used > (f32 ? w.cap32 : w.cap64) && ps.size() < size_t(nprob)) {
+      ps.clear();
+      for (int k = 0; k < nprob; ++k) ps.push_back(k);
+      make_plan(p, pc, ps, sel, pl, any_override ? Aov.data() : nullptr,
+                any_override ? ldo.data() : nullptr);
+    }
+  }
+  for (size_t lp = 0; lp < pl.P.size(); ++lp) {
+    if (f32) pl.P[lp].a_f32 = 1;
+    pl.P[lp].irL = pf.P[size_t(ps[lp])].offL;
+    pl.P[lp].irS = pf.P[size_t(ps[lp])].offS;
+  }
   Arena a;
   a.base = f32 ? w.base32 : w.base64;
   a.cap = f32 ? w.cap32 : w.cap64;
@@ -1680,8 +1711,9 @@ int inner_solve(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, co
   }
   TIK_TRY(upload_plan(pl, b, pc, nullptr, keep, st));
   std::vector<int32_t> use(size_t(pl.J));
-  for (int k = 0; k < nprob; ++k)
-    for (size_t i = 0; i < sel.size(); ++i) use[k * sel.size() + i] = use_h[size_t(k) * NF + (sel[i] - l0)];
+  for (size_t lp = 0; lp < ps.size(); ++lp)
+    for (size_t i = 0; i < sel.size(); ++i)
+      use[lp * sel.size() + i] = use_h[size_t(ps[lp]) * NF + size_t(sel[i] - l0)];
   keep.emplace_back(reinterpret_cast<const char*>(use.data()),
                     reinterpret_cast<const char*>(use.data()) + use.size() * 4);
   int32_t* dUse = f32 ? w.use32 : w.use64;
@@ -1699,8 +1731,8 @@ int inner_solve(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, co
   hipLaunchKernelGGL(k_ir_scatter, dim3(unsigned(cdiv(maxn, 256)), unsigned(pl.J)), dim3(256), 0,
                      st, b.P, pl.N, NF, l0, b.sc, dUse, b.x, w.dx);
   TIK_LAUNCHED("k_ir_scatter");
-  hipLaunchKernelGGL(k_ir_inner_stats, dim3(unsigned(cdiv(pl.J, 256))), dim3(256), 0, st, pl.J,
-                     pl.N, NF, l0, b.sc, dUse, w.stats);
+  hipLaunchKernelGGL(k_ir_inner_stats, dim3(unsigned(cdiv(pl.J, 256))), dim3(256), 0, st, b.P,
+                     pl.J, pl.N, NF, l0, b.sc, dUse, w.stats);
   TIK_LAUNCHED("k_ir_inner_stats");
   return TIK_OK;
 }
@@ -1854,9 +1886,11 @@ int mixed_group(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, Mi
     TIK_HIP(hipMemsetAsync(w.dx, 0, S * 8, st));
     TIK_HIP(hipMemsetAsync(w.stats, 0xFF, 2 * size_t(J) * 4, st));
     if (!sel32.empty())
-      TIK_TRY(inner_solve<TA64>(p, nprob, pc, w, sel32, use32, NF, l0, true, tol32, maxit, st, keep));
+      TIK_TRY(inner_solve<TA64>(p, nprob, pc, w, pf, sel32, use32, NF, l0, true, tol32, maxit, st,
+                                keep));
     if (!sel64.empty())
-      TIK_TRY(inner_solve<TA64>(p, nprob, pc, w, sel64, use64, NF, l0, false, tol64, maxit, st, keep));
+      TIK_TRY(inner_solve<TA64>(p, nprob, pc, w, pf, sel64, use64, NF, l0, false, tol64, maxit, st,
+                                keep));
     TIK_TRY(ir_products_n<TA64>(pf, bf, w.dx, w.a, st));
     {
       ProfScope ps("residual", st);

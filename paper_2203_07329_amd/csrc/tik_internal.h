@@ -108,6 +108,11 @@ struct DevProb {
   // (null: always run).  The products over A return at once when it reads 0:
   // the solve loop queues one iteration ahead of the count it has seen.
   const int32_t* live;
+  // inner solves of the mixed refinement: where this problem's rows sit in
+  // the refinement vectors (f, g, dx) and its index there; an inner plan may
+  // hold only the problems that still have a lambda to correct
+  int64_t irL, irS;
+  int32_t gp, pad2_;
 };
 
 // Per-(problem, lambda) LSQR scalars, all FP64.
