@@ -53,7 +53,9 @@ __global__ void __launch_bounds__(256, RT == 2 ? 3 : 2) k_gemm_n_mfma(const DevP
                                                      double* __restrict__ pnN) {
   using M = Mfma<TC>;
   constexpr int NT = NC / 16;
-  constexpr int KC = sizeof(TC) == 8 ? 16 : 32;
+  // columns per chunk: 128 bytes of each row (64 where FP64 operands of
+  // 256-row blocks would not fit the registers)
+  constexpr int KC = (sizeof(TA) == 8 || (sizeof(TC) == 8 && RT == 4)) ? 16 : 32;
   constexpr int WP = NC + 2;
   constexpr int QW = (KC * NC + 255) / 256;     // W elements per thread and chunk
   __shared__ TC Ws[2][KC][WP];
@@ -76,14 +78,14 @@ __global__ void __launch_bounds__(256, RT == 2 ? 3 : 2) k_gemm_n_mfma(const DevP
   // The A operands and the W rows of the next chunk are loaded into registers
   // while the matrix cores work on the current chunk; W is double-buffered in
   // LDS, so one barrier per chunk suffices.
-  auto load_a = [&](int64_t k0, TC (&dst)[RT][KC / 4]) {
+  auto load_a = [&](int64_t k0, TA (&dst)[RT][KC / 4]) {   // kept as stored, widened at use
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
       const int64_t col = k0 + 4 * ks + lk;
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
         const int64_t row = row0 + rt * 16 + li;
-        dst[rt][ks] = (row < m && col < kend) ? TC(A[row + col * lda]) : TC(0);
+        dst[rt][ks] = (row < m && col < kend) ? A[row + col * lda] : TA(0);
       }
     }
   };
@@ -106,7 +108,7 @@ __global__ void __launch_bounds__(256, RT == 2 ? 3 : 2) k_gemm_n_mfma(const DevP
   // Two register sets take turns (loop unrolled by two), so no copy forces
   // the prefetch to land early; W is loaded before A so that waiting for W
   // (to stage it in LDS) leaves the A loads in flight.
-  TC a0[RT][KC / 4], a1[RT][KC / 4];
+  TA a0[RT][KC / 4], a1[RT][KC / 4];
   TC wr[QW];
   load_w(kbeg, wr);
   load_a(kbeg, a0);
@@ -125,7 +127,7 @@ __global__ void __launch_bounds__(256, RT == 2 ? 3 : 2) k_gemm_n_mfma(const DevP
           Ws[BUF][4 * ks + lk][nt * 16 + li];                                               \
       _Pragma("unroll") for (int rt = 0; rt < RT; ++rt)                                     \
           _Pragma("unroll") for (int nt = 0; nt < NT; ++nt) acc[rt][nt] =                   \
-              M::op(CUR[rt][ks], b[nt], acc[rt][nt]);                                       \
+              M::op(TC(CUR[rt][ks]), b[nt], acc[rt][nt]);                                   \
     }                                                                                       \
     if (more) store_w((BUF) ^ 1, wr);                                                       \
     __syncthreads();                                                                        \
@@ -190,7 +192,7 @@ __global__ void __launch_bounds__(256) k_gemm_t_mfma(const DevProb* __restrict__
   using M = Mfma<TC>;
   constexpr int NT = NC / 16;
   constexpr int CT = CB / 64, RS = 32, AP = RS + 4, UP = NC + 2;
-  __shared__ TC As[CB][AP];
+  __shared__ TA As[CB][AP];   // A as stored, widened to TC as the MFMA reads it
   __shared__ TC Us[RS][UP];
   const int g = blockIdx.x;
   const int per = (nitems + 7) >> 3;
@@ -215,14 +217,15 @@ __global__ void __launch_bounds__(256) k_gemm_t_mfma(const DevProb* __restrict__
   // consume the current tile from LDS.
   constexpr int QA = (RS * CB) / 256;
   constexpr int QU = (RS * NC + 255) / 256;
-  TC ra[QA], ru[QU];
+  TA ra[QA];          // A as stored, widened when staged
+  TC ru[QU];
   auto fetch = [&](int64_t r0) {
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int e = threadIdx.x + 256 * q;
       const int rr = e % RS, cc = e / RS;
       const int64_t rg = r0 + rr, cg = c0 + cc;
-      ra[q] = (rg < rend && cg < n) ? TC(A[rg + cg * lda]) : TC(0);
+      ra[q] = (rg < rend && cg < n) ? A[rg + cg * lda] : TA(0);
     }
 #pragma unroll
     for (int q = 0; q < QU; ++q) {
@@ -256,7 +259,7 @@ __global__ void __launch_bounds__(256) k_gemm_t_mfma(const DevProb* __restrict__
     for (int ks = 0; ks < RS / 4; ++ks) {
       TC a[CT];
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) a[ct] = As[wv * (16 * CT) + ct * 16 + li][4 * ks + lk];
+      for (int ct = 0; ct < CT; ++ct) a[ct] = TC(As[wv * (16 * CT) + ct * 16 + li][4 * ks + lk]);
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         const TC b = Us[4 * ks + lk][nt * 16 + li];
