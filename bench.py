@@ -26,6 +26,8 @@ inverted with the generator's planted factors).  roofline: the dominant
 kernel family's algorithmic bytes per launch over its average launch time,
 from HIP events the library records around every launch during the timed
 steps.  cpu_baseline: the oracle's direct QR solve, timed on the host.
+Beside a mixed-mode line, f64_batched_same_input times batched FP64 LSQR on
+the same input and checks it against the same oracle solves.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -140,6 +142,8 @@ def main() -> int:
                     choices=["over_svd", "over_gauss", "under_scaled", "lowsd", "ragged"])
     ap.add_argument("--mode", default=None, choices=["auto", "mixed", "f64"])
     ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--alt-steps", type=int, default=1,
+                    help="when the timed mode is mixed: steps of batched FP64 on the same input")
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle (profiling runs)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0,
                     help="GiB: also run one plain device copy of this size (HBM counter calibration)")
@@ -249,6 +253,21 @@ def main() -> int:
                  "iters": rp.iters.cpu().numpy()}
         log(f"plain per-lambda: {plain_ms:.1f} ms/step")
 
+    # ---- batched FP64 on the same input, beside a mixed-mode line (FP32-stored A
+    # is read at the same bytes per pass in both modes)
+    alt = None
+    if mode == tik.MIXED_BATCHED and args.alt_steps > 0:
+        one_step(tik.F64_BATCHED, 1e-11)
+        torch.cuda.synchronize()
+        q0 = time.perf_counter()
+        for _ in range(args.alt_steps):
+            ra = one_step(tik.F64_BATCHED, 1e-11)
+        torch.cuda.synchronize()
+        alt_ms = (time.perf_counter() - q0) * 1000.0 / args.alt_steps
+        alt = {"ms_per_step": alt_ms, "X": [ra.x_numpy(k) for k in range(len(plist))],
+               "iters": ra.iters.cpu().numpy()}
+        log(f"batched FP64 on the same input: {alt_ms:.1f} ms/step")
+
     # ---- oracle (timed: the CPU baseline) and accuracy
     n_ok = None
     err_max = None
@@ -269,6 +288,8 @@ def main() -> int:
             errs = [bound]
             pl_errs = [oracle.certify_planted(p.A, p.b, p.lams, plain["X"][0], p.sigma, p.V)] \
                 if plain is not None else None
+            al_errs = [oracle.certify_planted(p.A, p.b, p.lams, alt["X"][0], p.sigma, p.V)] \
+                if alt is not None else None
             checked = f"all {nsolve} solves by an a-posteriori bound ({tcert:.1f} s on the host)"
         else:
             idx = list(range(len(plist))) if cfg["check"] == "full" else list(range(0, len(plist), 16))
@@ -277,6 +298,7 @@ def main() -> int:
             tcpu = time.perf_counter() - c0
             errs = [oracle.rel_err(Xs[k], Xo[k]) for k in idx]
             pl_errs = [oracle.rel_err(plain["X"][k], Xo[k]) for k in idx] if plain is not None else None
+            al_errs = [oracle.rel_err(alt["X"][k], Xo[k]) for k in idx] if alt is not None else None
             nsamp = sum(plist[k].lams.size for k in idx)
             what = (f"Householder QR of A once plus per-lambda QR solves, {len(idx)} problem(s), "
                     f"{nsamp} solves ({tcpu:.1f} s)")
@@ -288,10 +310,11 @@ def main() -> int:
         err_max = float(allerr.max())
         frac = float(np.mean(allerr <= TOL_ERR))
         n_ok = int(round(frac * nsolve))
-        if plain is not None and pl_errs is not None:
-            pe = np.concatenate([np.ravel(e) for e in pl_errs])
-            plain["n_ok"] = int(round(float(np.mean(pe <= TOL_ERR)) * nsolve))
-            plain["max_rel_err"] = float(pe.max())
+        for other, oe in ((plain, pl_errs), (alt, al_errs)):
+            if other is not None and oe is not None:
+                pe = np.concatenate([np.ravel(e) for e in oe])
+                other["n_ok"] = int(round(float(np.mean(pe <= TOL_ERR)) * nsolve))
+                other["max_rel_err"] = float(pe.max())
     value = (n_ok if n_ok is not None else 0) / (ms_step / 1000.0)
 
     # ---- roofline of the dominant kernel family with known algorithmic bytes
@@ -385,6 +408,11 @@ def main() -> int:
                                         "max_rel_err": plain.get("max_rel_err"),
                                         "iters_max": int(plain["iters"].max())}
         line["speedup_vs_plain"] = round(value / pv, 2) if pv > 0 else None
+    if alt is not None:
+        av = alt.get("n_ok", 0) / (alt["ms_per_step"] / 1000.0)
+        line["f64_batched_same_input"] = {"value": round(av, 3), "ms_per_step": round(alt["ms_per_step"], 2),
+                                          "solves_ok": alt.get("n_ok"), "max_rel_err": alt.get("max_rel_err"),
+                                          "iters_max": int(alt["iters"].max())}
     print(json.dumps(line), flush=True)
     return 0
 
