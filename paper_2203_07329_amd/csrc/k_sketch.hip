@@ -517,14 +517,15 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
 
 // Yacc (s x ncol, ld s, FP32) (+)= X (s x kc, BF16, ld kc) * Bop (kc x ncol), Bop(k, c) =
 // A[(r0 + k) + c lda] (tall) or A[c + (r0 + k) lda] (wide), rounded to BF16.
-// 128 x 128 output tile per block, 4 waves of 64 x 64 (2 x 2 tiles of
-// v_mfma_f32_32x32x16_bf16: A-operand lane l holds row l % 32, k = 8 (l / 32) .. +7;
+// ST x 128 output tile per block (ST = 128 or 256 rows of the sketch), 4 waves
+// of ST/2 x 64 (ST/64 x 2 tiles of v_mfma_f32_32x32x16_bf16: A-operand lane l holds row l % 32, k = 8 (l / 32) .. +7;
 // B-operand lane l holds column l % 32 at the same k; the 16 results of lane l
 // are rows 8 (v / 4) + 4 (l / 32) + v % 4 of column l % 32).  Tiles of KB k are
 // staged in LDS k-contiguous (row / column major) so each operand is one
 // 16-byte read; LDS holds two stages, so the next step (fetched into
 // registers with 16-byte loads during the MFMAs) is written to the other stage
-// and one barrier per step suffices.
+// and one barrier per step suffices.  ST = 256 halves the A tile loads per
+// flop (each step's A tile serves twice the sketch rows).
 // Split K (grid.z > 1): block z covers k in [z ksz, (z + 1) ksz) and stores its
 // partial product to Y + z s ncol; k_sketch_reduce adds the slices in order.
 // Tile placement: workgroups are dealt to the 8 XCDs in turn (block g runs on
@@ -532,47 +533,51 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
 // split of the tile grid (sR x cR tiles each), walked row by row: the
 // workgroups running together on one XCD share their X rows and A columns in
 // that XCD's L2, and each operand panel is fetched by ps or pc XCDs only.
-template <typename TA, bool WIDE, int KB>
-__global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* __restrict__ X,
+template <typename TA, bool WIDE, int KB, int ST>
+__global__ void __launch_bounds__(256, ST == 256 ? 2 : 1) k_sketch_gemm_bf16(const __hip_bfloat16* __restrict__ X,
                                                           int64_t s, int64_t kc, int64_t ldx,
                                                           int64_t ksz,
                                                           const TA* __restrict__ A, int64_t lda,
                                                           int64_t r0, int64_t ncol, int sR, int cR,
                                                           int pc, float* __restrict__ Y, int first) {
   static_assert(KB % 32 == 0 && KB <= 128, "k per step");
+  static_assert(ST == 128 || ST == 256, "sketch rows per tile");
   constexpr int LP = KB + 8;              // LDS row pitch in bf16
-  constexpr int HK = KB / 2;              // k per thread (tall B, X): half a row of the step
+  constexpr int HK = KB / 2;              // k per thread (tall B): half a row of the step
+  constexpr int TPR = 256 / ST;           // threads per X row
+  constexpr int XK = KB / TPR;            // k per thread (X)
+  constexpr int AT = ST / 64;             // 32-row MFMA tiles per wave
   constexpr int WK = KB / 8;              // k per thread (wide B)
   const int xcd = blockIdx.x & 7, jx = blockIdx.x >> 3;
   const int64_t stile = int64_t(xcd / pc) * sR + jx / cR, ctile = int64_t(xcd % pc) * cR + jx % cR;
-  if (jx >= sR * cR || stile * 128 >= s || ctile * 128 >= ncol) return;   // uniform
+  if (jx >= sR * cR || stile * ST >= s || ctile * 128 >= ncol) return;   // uniform
   const int64_t kb = int64_t(blockIdx.z) * ksz, ke = min(kc, kb + ksz);
   if (gridDim.z > 1) {
     Y += int64_t(blockIdx.z) * s * ncol;
     first = 1;
   }
-  __shared__ __attribute__((aligned(16))) uint16_t Xs2[2][128 * LP];
+  __shared__ __attribute__((aligned(16))) uint16_t Xs2[2][ST * LP];
   __shared__ __attribute__((aligned(16))) uint16_t Bs2[2][128 * LP];
   uint16_t* Xs = Xs2[0];
   uint16_t* Bs = Bs2[0];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wq = wv >> 1, wc = wv & 1;
-  const int64_t q0 = stile * 128, c0 = ctile * 128;
-  sk_f32x16 acc[2][2];
+  const int64_t q0 = stile * ST, c0 = ctile * 128;
+  sk_f32x16 acc[AT][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < AT; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
-  // register stage of one step: X (HK bf16 per thread), B (HK values per thread).
+  // register stage of one step: X (XK bf16 per thread), B (HK values per thread).
   // Every whole step is prefetched during the previous step's MFMAs: X rows
   // (pitch ldx, a multiple of 8) with 16-byte loads, A with 16-byte loads
   // where its runs start 16-byte aligned (base, lda and the chunk origin
   // multiples of 16 bytes / sizeof(TA)), else with one load per element (a
   // tall A whose row count is odd, say).  The ragged last step is copied
   // element by element into LDS after the barrier.
-  uint4 rx[HK / 8];
+  uint4 rx[XK / 8];
   float rb[HK];
   constexpr int64_t VE = 16 / sizeof(TA);
   const bool vx = (reinterpret_cast<uintptr_t>(X) % 16 == 0) && (ldx & 7) == 0;
@@ -581,11 +586,11 @@ __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* 
   auto whole = [&](int64_t k0) { return vx && k0 + KB <= ke; };
   auto fetch = [&](int64_t k0) {               // whole steps only
     {
-      const int row = tid >> 1, half = tid & 1;
+      const int row = tid / TPR, part = tid % TPR;
       const int64_t q = q0 + row;
 #pragma unroll
-      for (int h = 0; h < HK / 8; ++h)
-        rx[h] = q < s ? *reinterpret_cast<const uint4*>(X + q * ldx + k0 + half * HK + h * 8)
+      for (int h = 0; h < XK / 8; ++h)
+        rx[h] = q < s ? *reinterpret_cast<const uint4*>(X + q * ldx + k0 + part * XK + h * 8)
                       : make_uint4(0, 0, 0, 0);
     }
     if (!WIDE) {
@@ -623,10 +628,10 @@ __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* 
   };
   auto stash = [&]() {                          // the fetched whole step
     {
-      const int row = tid >> 1, half = tid & 1;
+      const int row = tid / TPR, part = tid % TPR;
 #pragma unroll
-      for (int h = 0; h < HK / 8; ++h)
-        *reinterpret_cast<uint4*>(&Xs[row * LP + half * HK + 8 * h]) = rx[h];
+      for (int h = 0; h < XK / 8; ++h)
+        *reinterpret_cast<uint4*>(&Xs[row * LP + part * XK + 8 * h]) = rx[h];
     }
     if (!WIDE) {
       const int col = tid >> 1, half = tid & 1;
@@ -648,10 +653,14 @@ __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* 
     }
   };
   auto stash_ragged = [&](int64_t k0) {         // element by element, zeros outside
+    for (int e = tid; e < ST * KB; e += 256) {
+      const int r = e / KB, kk = e % KB;
+      const int64_t k = k0 + kk, q = q0 + r;
+      Xs[r * LP + kk] = (q < s && k < ke) ? *reinterpret_cast<const uint16_t*>(X + q * ldx + k) : 0;
+    }
     for (int e = tid; e < 128 * KB; e += 256) {
       const int r = e / KB, kk = e % KB;
-      const int64_t k = k0 + kk, q = q0 + r, c = c0 + r;
-      Xs[r * LP + kk] = (q < s && k < ke) ? *reinterpret_cast<const uint16_t*>(X + q * ldx + k) : 0;
+      const int64_t k = k0 + kk, c = c0 + r;
       const float v = (c < ncol && k < ke) ? float(WIDE ? A[c + (r0 + k) * lda] : A[(r0 + k) + c * lda])
                                            : 0.f;
       const __hip_bfloat16 h = __float2bfloat16(v);
@@ -673,19 +682,20 @@ __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* 
     Bs = Bs2[buf];
 #pragma unroll
     for (int ks = 0; ks < KB / 16; ++ks) {
-      sk_bf16x8 av[2], bv[2];
+      sk_bf16x8 av[AT], bv[2];
+      const int kofs = ks * 16 + 8 * (lane >> 5);
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int row = wq * 64 + t * 32 + (lane & 31);
-        const int col = wc * 64 + t * 32 + (lane & 31);
-        const int kofs = ks * 16 + 8 * (lane >> 5);
-        const uint4 xa = *reinterpret_cast<const uint4*>(&Xs[row * LP + kofs]);
-        const uint4 xb = *reinterpret_cast<const uint4*>(&Bs[col * LP + kofs]);
-        av[t] = __builtin_bit_cast(sk_bf16x8, xa);
-        bv[t] = __builtin_bit_cast(sk_bf16x8, xb);
+      for (int t = 0; t < AT; ++t) {
+        const int row = wq * (ST / 2) + t * 32 + (lane & 31);
+        av[t] = __builtin_bit_cast(sk_bf16x8, *reinterpret_cast<const uint4*>(&Xs[row * LP + kofs]));
       }
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int t = 0; t < 2; ++t) {
+        const int col = wc * 64 + t * 32 + (lane & 31);
+        bv[t] = __builtin_bit_cast(sk_bf16x8, *reinterpret_cast<const uint4*>(&Bs[col * LP + kofs]));
+      }
+#pragma unroll
+      for (int a = 0; a < AT; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
@@ -699,12 +709,12 @@ __global__ void __launch_bounds__(256) k_sketch_gemm_bf16(const __hip_bfloat16* 
     buf ^= 1;
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < AT; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int64_t q = q0 + wq * 64 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int64_t q = q0 + wq * (ST / 2) + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         const int64_t c = c0 + wc * 64 + b * 32 + (lane & 31);
         if (q < s && c < ncol) {
           float* dst = Y + q + c * s;
@@ -833,12 +843,20 @@ int launch_sketch_gemm_f64(const double* Xc, int64_t s, int64_t kc, const void* 
   return TIK_OK;
 }
 
-// K splits of one BF16 sketch launch: enough blocks to fill the chip when the
-// output has few 128 x 128 tiles, at least 512 k per split, partial slices
-// within `part_cap` floats.
+// Sketch rows per output tile: 256 (it halves the A loads per flop, at two
+// blocks per CU instead of three) once the sketch has 4096 rows or more, where
+// it measured faster (s = 8000: 27.9 -> 24.8 ms); 128 below (s from 400 to
+// 4000 in a ragged batch: 120 ms either way with this threshold, 138 ms with
+// 256-row tiles from s = 1024 on).
 constexpr int SK_KB = 32;    // k per step of the BF16 sketch product
+constexpr int64_t SK_ST256_MIN = 4096;
+static int sketch_bf16_st(int64_t s) { return s >= SK_ST256_MIN ? 256 : 128; }
+
+// K splits of one BF16 sketch launch: enough blocks to fill the chip when the
+// output has few tiles, at least 512 k per split, partial slices within
+// `part_cap` floats.
 int sketch_bf16_splits(int64_t s, int64_t ncol, int64_t kc, int64_t part_cap) {
-  const int64_t tiles = cdiv(s, 128) * cdiv(ncol, 128);
+  const int64_t tiles = cdiv(s, sketch_bf16_st(s)) * cdiv(ncol, 128);
   int64_t z = std::max<int64_t>(1, std::min<int64_t>(1024 / std::max<int64_t>(1, tiles), kc / 512));
   if (z > 1) z = std::min<int64_t>(z, part_cap / std::max<int64_t>(1, s * ncol));
   return int(std::max<int64_t>(1, z));
@@ -853,7 +871,8 @@ int launch_sketch_gemm_bf16(const void* Xc, int64_t s, int64_t kc, int64_t ldx, 
   float* dst = nz > 1 ? part : Yacc;
   // XCD split ps x pc of the S x C tile grid: X panels are fetched by pc XCDs,
   // A panels by ps; take the split with the fewest bytes
-  const int64_t S = cdiv(s, 128), C = cdiv(ncol, 128);
+  const int ST = sketch_bf16_st(s);
+  const int64_t S = cdiv(s, ST), C = cdiv(ncol, 128);
   const double xb = double(s) * double(ksz) * 2.0;
   const double ab = double(ncol) * double(ksz) * (a_f32 ? 4.0 : 8.0);
   int pc = 1;
@@ -871,13 +890,17 @@ int launch_sketch_gemm_bf16(const void* Xc, int64_t s, int64_t kc, int64_t ldx, 
   const dim3 grid = dim3(unsigned(8 * sR * cR), 1u, unsigned(nz));
   const __hip_bfloat16* X = static_cast<const __hip_bfloat16*>(Xc);
   ProfScope ps("sketch", st);
-  if (a_f32) {
-    if (wide) hipLaunchKernelGGL((k_sketch_gemm_bf16<float, true, SK_KB>), grid, dim3(256), 0, st, X, s, kc, ldx, ksz, static_cast<const float*>(A), lda, r0, ncol, sR, cR, pc, dst, first);
-    else      hipLaunchKernelGGL((k_sketch_gemm_bf16<float, false, SK_KB>), grid, dim3(256), 0, st, X, s, kc, ldx, ksz, static_cast<const float*>(A), lda, r0, ncol, sR, cR, pc, dst, first);
+#define TIK_SKG(TAV, WV, STV)                                                                   \
+  hipLaunchKernelGGL((k_sketch_gemm_bf16<TAV, WV, SK_KB, STV>), grid, dim3(256), 0, st, X, s, kc, \
+                     ldx, ksz, static_cast<const TAV*>(A), lda, r0, ncol, sR, cR, pc, dst, first)
+  if (ST == 256) {
+    if (a_f32) { if (wide) TIK_SKG(float, true, 256); else TIK_SKG(float, false, 256); }
+    else       { if (wide) TIK_SKG(double, true, 256); else TIK_SKG(double, false, 256); }
   } else {
-    if (wide) hipLaunchKernelGGL((k_sketch_gemm_bf16<double, true, SK_KB>), grid, dim3(256), 0, st, X, s, kc, ldx, ksz, static_cast<const double*>(A), lda, r0, ncol, sR, cR, pc, dst, first);
-    else      hipLaunchKernelGGL((k_sketch_gemm_bf16<double, false, SK_KB>), grid, dim3(256), 0, st, X, s, kc, ldx, ksz, static_cast<const double*>(A), lda, r0, ncol, sR, cR, pc, dst, first);
+    if (a_f32) { if (wide) TIK_SKG(float, true, 128); else TIK_SKG(float, false, 128); }
+    else       { if (wide) TIK_SKG(double, true, 128); else TIK_SKG(double, false, 128); }
   }
+#undef TIK_SKG
   TIK_LAUNCHED("k_sketch_gemm_bf16");
   if (nz > 1) {
     const int64_t count = s * ncol;

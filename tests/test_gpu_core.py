@@ -296,10 +296,10 @@ def _bf16(a):
     return r.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("m,s", [(1000, 64), (3000, 200), (1001, 64), (2999, 200)])
+@pytest.mark.parametrize("m,s", [(1000, 64), (3000, 200), (1001, 64), (2999, 200), (4101, 4100)])
 def test_bf16_sketch_matches_rounded_gaussian(m, s):
     # odd m: the columns of A start at any 4-byte offset and the X rows are
-    # padded to a 16-byte pitch
+    # padded to a 16-byte pitch; s >= 4096 takes the 256-row output tiles
     I = np.eye(m)
     pr = tik.Problems.from_numpy([I], [np.ones(m)])
     Xb = tik.sketch(pr, tik.GAUSS, [s], 21, sketch_dtype=tik.BF16).Y(0)
@@ -317,8 +317,8 @@ def test_bf16_sketch_matches_rounded_gaussian(m, s):
         assert np.max(np.abs(Y - ref)) <= 1e-5 * np.max(np.abs(ref))
 
 
-def test_bf16_sketch_wide():
-    m, n, s = 150, 4000, 600
+@pytest.mark.parametrize("m,n,s", [(150, 4000, 600), (301, 9000, 4200)])
+def test_bf16_sketch_wide(m, n, s):
     rng = np.random.default_rng(6)
     A = rng.standard_normal((m, n)).astype(np.float32)
     pa = tik.Problems.from_numpy([A], [np.ones(m)])
