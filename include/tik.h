@@ -82,7 +82,13 @@ typedef enum { TIK_ROUTE_CHOL = 0, TIK_ROUTE_LOWRANK = 1 } tik_route;
                          the loop over lam parallelizes trivially);
    MIXED_BATCHED         batched FP32 LSQR inside FP64 iterative refinement:
                          residuals, preconditioner factors and the solution stay
-                         FP64 on the device. */
+                         FP64 on the device.  A group of up to 32 lam that FP32
+                         products cannot carry (12 kappa u_32 > 1/4 for one of
+                         its lam, kappa^2 bounded by (||C|| + lam) / lam) is
+                         solved by batched FP64 LSQR at max(tol / 1000, 1e-14);
+                         when that holds for every group the call runs as
+                         F64_BATCHED with that tolerance (tik_lsqr_info
+                         reports the split). */
 typedef enum {
   TIK_PLAIN_F64_PER_LAMBDA = 0,
   TIK_F64_BATCHED = 1,

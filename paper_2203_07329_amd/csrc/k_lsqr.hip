@@ -1578,16 +1578,19 @@ size_t mixed_layout(const tik_problem* p, int32_t nprob, const tik_precond_s* pc
   w.use64 = a.take<int32_t>(pl.J);
   w.stats = a.take<int32_t>(2 * size_t(pl.J));
   w.ok = a.take<int32_t>(pl.J);
+  std::vector<Plan> subs;                 // inner plans solve subsets of the lambdas
+  for (int ng : subset_sizes(NF)) {
+    std::vector<int> sub;
+    all_lambdas(0, ng, sub);
+    subs.emplace_back();
+    make_plan(p, pc, ps, sub, subs.back());
+  }
   auto region = [&](size_t tc, char*& base, size_t& cap) {
     cap = 0;
-    for (int ng : subset_sizes(NF)) {     // inner plans solve subsets of the lambdas
-      std::vector<int> sub;
-      all_lambdas(0, ng, sub);
-      Plan ps_;
-      make_plan(p, pc, ps, sub, ps_);
+    for (const Plan& q : subs) {
       Arena m;
       Bufs b;
-      take_bufs(m, ps_, tc, b);
+      take_bufs(m, q, tc, b);
       cap = std::max(cap, m.used + 256);
     }
     base = a.take<char>(cap);
@@ -2444,13 +2447,16 @@ size_t wide_mixed_layout(const tik_problem* p, int32_t nprob, const tik_precond_
   w.use = a.take<int32_t>(pl.J);
   w.stats = a.take<int32_t>(2 * size_t(pl.J));
   w.ok = a.take<int32_t>(pl.J);
+  std::vector<WPlan> subs;
+  for (int ng : subset_sizes(NF)) {
+    std::vector<int> sub;
+    all_lambdas(0, ng, sub);
+    subs.emplace_back();
+    make_plan_wide(p, pc, ps, sub, subs.back());
+  }
   auto region = [&](size_t tc, char*& base, size_t& cap) {
     cap = 0;
-    for (int ng : subset_sizes(NF)) {
-      std::vector<int> sub;
-      all_lambdas(0, ng, sub);
-      WPlan q;
-      make_plan_wide(p, pc, ps, sub, q);
+    for (const WPlan& q : subs) {
       Arena m;
       WBufs b;
       take_wbufs(m, q, tc, b);
@@ -2750,8 +2756,27 @@ int wide_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32
 
 }  // namespace
 
+// The mixed drivers solve a group of lambdas by batched FP64 LSQR when FP32
+// products cannot carry one of its lambdas (12 kappa(B) u_32 > 0.25, kappa(B)^2
+// bounded by (||C|| + lambda) / lambda).  When that holds for every group, a
+// mixed call is batched FP64 at the refinement's inner tolerance: it runs as
+// such, without planning the refinement's workspace.
+static bool all_groups_fp64(int32_t nprob, const tik_precond_s* pc) {
+  for (int l0 = 0; l0 < pc->N; l0 += 32) {
+    bool any = false;
+    for (int i = l0; i < std::min(pc->N, l0 + 32); ++i)
+      for (int k = 0; k < nprob; ++k) {
+        const double lam = pc->lams[size_t(k) * pc->N + i];
+        any |= 12.0 * std::sqrt((pc->cnorm[k] + lam) / lam) * std::ldexp(1.0, -24) > 0.25;
+      }
+    if (!any) return false;
+  }
+  return true;
+}
+
 int lsqr_bytes(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32_t mode,
                size_t* bytes) {
+  if (mode == TIK_MIXED_BATCHED && all_groups_fp64(nprob, pc)) mode = TIK_F64_BATCHED;
   if (pc->wide) return wide_bytes(p, nprob, pc, mode, bytes);
   if (mode == TIK_MIXED_BATCHED) {
     Arena a;
@@ -2778,6 +2803,10 @@ int lsqr_bytes(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int
 int lsqr_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32_t mode,
              double tol, int32_t maxit, double* const* X, int32_t* iters, int32_t* status,
              double* relres, void* dws, size_t dws_bytes, hipStream_t st) {
+  if (mode == TIK_MIXED_BATCHED && all_groups_fp64(nprob, pc)) {
+    mode = TIK_F64_BATCHED;
+    tol = std::max(1e-3 * tol, 1e-14);      // the mixed drivers' tolerance for such groups
+  }
   if (pc->wide)
     return wide_run(p, nprob, pc, mode, tol, maxit, X, iters, status, relres, dws, dws_bytes, st);
   if (mode == TIK_MIXED_BATCHED)
