@@ -256,6 +256,29 @@ def test_mixed_refinement(case):
     assert np.all(st == tik.ST_CONVERGED), st
 
 
+def test_mixed_all_fp64_groups_equal_f64_batched():
+    """A mixed call whose every lambda group needs FP64 passes (kappa(A) = 1e8, lambda down to 1e-8)
+    is batched FP64 at max(tol / 1000, 1e-14): the same iterates, bit for bit, and lsqr_info
+    reports every lambda as FP64; a well-conditioned call keeps its FP32 refinement."""
+    p = W.over_gauss(m=20000, n=400, N=32, s=1600)
+    pr = dev_problems([p])
+    sk = tik.sketch(pr, tik.SRHT, [p.s], 0)
+    pc = tik.precond(sk, p.lams[None, :])
+    rm = tik.lsqr_batch(pr, pc, tik.MIXED_BATCHED, 1e-8, 300)
+    torch.cuda.synchronize()
+    assert tik.lsqr_info() == (0, 32)
+    rf = tik.lsqr_batch(pr, pc, tik.F64_BATCHED, 1e-11, 300)
+    torch.cuda.synchronize()
+    assert np.array_equal(rm.x_numpy(0), rf.x_numpy(0))
+    assert np.array_equal(rm.iters.cpu().numpy(), rf.iters.cpu().numpy())
+    q = W.over_svd(m=1500, n=60, N=6)
+    res, _ = _solve([q], tik.MIXED_BATCHED, tol=1e-10, maxit=200)
+    n32, n64 = tik.lsqr_info()
+    assert n32 > 0 and n64 == 0, (n32, n64)
+    err = oracle.rel_err(res.x_numpy(0), oracle.solve(q.A, q.b, q.lams))
+    assert np.all(err <= 1e-8), err
+
+
 # ------------------------------------------------------------- wide problems --
 
 @pytest.mark.parametrize("mode", [tik.F64_BATCHED, tik.PLAIN_F64_PER_LAMBDA, tik.MIXED_BATCHED])
