@@ -42,17 +42,23 @@ struct TileLds {
   double Bs[TK][64 + 1];
 };
 
-template <bool TA>
+// DEPTH 1: the next chunk of K is fetched into registers while the matrix
+// cores use the current one from LDS.  DEPTH 2: two register sets take turns,
+// so the chunk after next is in flight as well; the few-chunk contractions of
+// the panel solve, the trailing update and the inverse's last step run faster
+// that way (it also leaves the compiler fewer live values: 72 VGPRs instead of
+// 142 for the trailing update), while the long contractions of k_trinv_mul
+// keep DEPTH 1 (with two sets they drop to one block per CU).
+template <bool TA, int DEPTH = 1>
 __device__ __forceinline__ void tile_mma(const double* __restrict__ A, int64_t lda,
                                          const double* __restrict__ B, int64_t ldb, int64_t K,
                                          int mrows, int ncols, TileLds& L, f64x4 (&acc)[2][2]) {
+  static_assert(DEPTH == 1 || DEPTH == 2, "prefetch depth");
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int wr = 32 * (wv & 1), wc = 32 * (wv >> 1);
   constexpr int Q = 64 * TK / 256;     // elements of each tile per thread
-  double ra[Q], rb[Q];
-  // the next chunk is fetched into registers while the current one is used
-  auto fetch = [&](int64_t k0) {
+  auto fetch = [&](int64_t k0, double (&ra)[Q], double (&rb)[Q]) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int e = tid + 256 * q;
@@ -67,7 +73,7 @@ __device__ __forceinline__ void tile_mma(const double* __restrict__ A, int64_t l
       rb[q] = (j < ncols && kg < K) ? B[kg + int64_t(j) * ldb] : 0.0;
     }
   };
-  auto stash = [&]() {
+  auto stash = [&](const double (&ra)[Q], const double (&rb)[Q]) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int e = tid + 256 * q;
@@ -76,14 +82,7 @@ __device__ __forceinline__ void tile_mma(const double* __restrict__ A, int64_t l
       L.Bs[e % TK][e / TK] = rb[q];
     }
   };
-  if (K > 0) {
-    fetch(0);
-    stash();
-  }
-  __syncthreads();
-  for (int64_t k0 = 0; k0 < K; k0 += TK) {
-    const bool more = k0 + TK < K;
-    if (more) fetch(k0 + TK);
+  auto mma = [&]() {
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
       double a[2], b[2];
@@ -97,9 +96,42 @@ __device__ __forceinline__ void tile_mma(const double* __restrict__ A, int64_t l
         for (int u = 0; u < 2; ++u)
           acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
     }
+  };
+  double ra0[Q], rb0[Q];
+  if (K > 0) {
+    fetch(0, ra0, rb0);
+    stash(ra0, rb0);
+  }
+  if constexpr (DEPTH == 1) {
     __syncthreads();
-    if (more) stash();
+    for (int64_t k0 = 0; k0 < K; k0 += TK) {
+      const bool more = k0 + TK < K;
+      if (more) fetch(k0 + TK, ra0, rb0);
+      mma();
+      __syncthreads();
+      if (more) stash(ra0, rb0);
+      __syncthreads();
+    }
+  } else {
+    double ra1[Q], rb1[Q];
+    if (K > TK) fetch(TK, ra1, rb1);
     __syncthreads();
+    // LDS holds chunk k0 and set 1 chunk k0 + TK; K is uniform, so every
+    // break is taken by the whole block right after a barrier
+    for (int64_t k0 = 0; k0 < K; k0 += 2 * TK) {
+      if (k0 + 2 * TK < K) fetch(k0 + 2 * TK, ra0, rb0);
+      mma();
+      __syncthreads();
+      if (k0 + TK >= K) break;
+      stash(ra1, rb1);
+      __syncthreads();
+      if (k0 + 3 * TK < K) fetch(k0 + 3 * TK, ra1, rb1);
+      mma();
+      __syncthreads();
+      if (k0 + 2 * TK >= K) break;
+      stash(ra0, rb0);
+      __syncthreads();
+    }
   }
 }
 
@@ -304,7 +336,7 @@ __global__ void __launch_bounds__(256) k_trsm_panel(const CholJob* __restrict__ 
   const double* Dm = J.Dinv + (k0 / NB) * NB * NB;
   f64x4 acc[2][2];
   tile_zero(acc);
-  tile_mma<true>(Dm, NB, Rm + k0 + c0 * n, n, kb, kb, nc, L, acc);
+  tile_mma<true, 2>(Dm, NB, Rm + k0 + c0 * n, n, kb, kb, nc, L, acc);
   tile_for_each(acc, [&](int i, int c, double v) {
     if (i < kb && c < nc) Rm[(k0 + i) + (c0 + c) * n] = v;
   });
@@ -329,7 +361,7 @@ __global__ void __launch_bounds__(256) k_syrk_trail(const CholJob* __restrict__ 
   const int na = int(min<int64_t>(64, n - a0)), nb = int(min<int64_t>(64, n - b0));
   f64x4 acc[2][2];
   tile_zero(acc);
-  tile_mma<true>(Rm + k0 + a0 * n, n, Rm + k0 + b0 * n, n, kb, na, nb, L, acc);
+  tile_mma<true, 2>(Rm + k0 + a0 * n, n, Rm + k0 + b0 * n, n, kb, na, nb, L, acc);
   tile_for_each(acc, [&](int i, int j, double v) {
     if (i < na && j < nb) Rm[(a0 + i) + (b0 + j) * n] -= v;
   });
@@ -385,7 +417,7 @@ __global__ void __launch_bounds__(256) k_trinv_fin(const CholJob* __restrict__ j
   const int nr = int(min<int64_t>(64, l0 - r0));
   f64x4 acc[2][2];
   tile_zero(acc);
-  tile_mma<false>(Tm + r0, n, Dm, NB, lb, nr, lb, L, acc);
+  tile_mma<false, 2>(Tm + r0, n, Dm, NB, lb, nr, lb, L, acc);
   tile_for_each(acc, [&](int i, int c, double v) {
     if (i < nr && c < lb) Rm[(r0 + i) + (l0 + c) * n] = -v;
   });
