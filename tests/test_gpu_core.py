@@ -233,6 +233,19 @@ def test_lsqr_deterministic():
     assert np.array_equal(x1, r2.x_numpy(0))
 
 
+def test_surplus_iteration_changes_nothing():
+    """The solve loop reads the active count one iteration late, so after the last lambda converges one
+    more iteration is queued; its products return at once and the vector steps leave finished solves
+    alone.  Capping maxit at the iterations the solve needed removes that iteration: same x bit for bit."""
+    p = W.over_svd(m=1500, n=60, N=6)
+    r1, _ = _solve([p], tik.F64_BATCHED, maxit=300)
+    k = int(r1.iters.cpu().numpy().max())
+    r2, _ = _solve([p], tik.F64_BATCHED, maxit=k)
+    assert np.array_equal(r1.x_numpy(0), r2.x_numpy(0))
+    assert np.array_equal(r1.iters.cpu().numpy(), r2.iters.cpu().numpy())
+    assert np.all(r1.status.cpu().numpy() == tik.ST_CONVERGED)
+
+
 # ------------------------------------------------------------ mixed precision --
 
 @pytest.mark.parametrize("case", ["over_svd", "over_gauss_reduced", "ragged_f32", "wide_lambda_set"])
