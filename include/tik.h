@@ -18,7 +18,9 @@
  *
  * Conventions shared by every entry point:
  *  - Matrices are column-major.  All pointers named "device" are HIP device
- *    pointers owned by the caller; the library never allocates device memory.
+ *    pointers owned by the caller; the library never allocates device memory
+    (it keeps a few streams per device and a pool of pinned host words for
+    the solve loop, both created on first use and held by the process).
  *    Every call that needs scratch space takes a caller-provided device
  *    workspace (dws, dws_bytes) whose required size the matching *_bytes
  *    query returns.  A handle points into the workspace it was built in: the
@@ -205,8 +207,12 @@ int tik_lsqr_batch_bytes(const tik_problem* p, int32_t nprob, tik_precond_t pc,
    status     device int32 nprob x N: tik_status values;
    relres     device double nprob x N: the final ||M^T r|| / (||M|| ||r||)
               estimate;
-   Synchronizes the stream once every few iterations to test whether every
-   lambda has stopped; otherwise stream-ordered. */
+   The host waits on each iteration's count of active lambdas one iteration
+   late (an event after an async copy into one of two pinned host words per
+   call, taken from a small per-process pool allocated on first use): the next
+   iteration is already queued, and when the count was 0 its products return
+   at once and its vector steps leave finished solves unchanged.  Returns when
+   the loop has stopped; the work is stream-ordered on `stream`. */
 int tik_lsqr_batch(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_t mode,
                    double tol, int32_t maxit, double* const* X, int32_t* iters,
                    int32_t* status, double* relres, void* dws, size_t dws_bytes,
