@@ -817,7 +817,7 @@ __global__ void k_wide_init_h(const DevProb* __restrict__ P, const Item* __restr
     double v = pr.b[r];
     if (rhs) {
       const Scal& S = sc[it.p * N + i];
-      v = use[it.p * N + i] ? rhs[(pr.offS + r) * NF + (S.li - l0)] : 0.0;
+      v = use[it.p * N + i] ? rhs[(pr.irS + r) * NF + (S.li - l0)] : 0.0;
     }
     t[pr.offS * N + int64_t(i) * pr.m + r] = v;
   }
@@ -2058,6 +2058,9 @@ void make_plan_wide(const tik_problem* probs, const tik_precond_s* pc, const std
     d.offS = pl.totS;
     d.offR = d.offS;
     d.offC = d.offL;
+    d.irL = d.offL;
+    d.irS = d.offS;
+    d.gp = pidx[lp];
     d.k = g.m;
     if (!pl.lowrank) d.Rinv = pc->Rinv[pidx[lp]];
     // split of A v_top over column chunks: about kWideBlocks blocks over the batch
@@ -2368,7 +2371,7 @@ __global__ void k_wide_ir_update(const DevProb* __restrict__ P, int N, int NF, i
   const double isq = 1.0 / S.sqlam;
   for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < pr.m;
        r += int64_t(gridDim.x) * blockDim.x)
-    yd[(pr.offS + r) * NF + (S.li - l0)] += zb[(pr.offS + r) * N + i] * isq;
+    yd[(pr.irS + r) * NF + (S.li - l0)] += zb[(pr.offS + r) * N + i] * isq;
 }
 
 // squared norms of the inner x (the correction of A^T y) and of x + dx, per refinement column
@@ -2386,15 +2389,15 @@ __global__ void __launch_bounds__(BLK) k_wide_ir_norms(const DevProb* __restrict
   double sd = 0.0, sx = 0.0;
   for (int64_t c = threadIdx.x; c < pr.n; c += BLK) {
     const double d = xin[(pr.offL + c) * N + i];
-    const double nx = (x ? x[(pr.offL + c) * NF + col] : 0.0) + d;
+    const double nx = (x ? x[(pr.irL + c) * NF + col] : 0.0) + d;
     sd += d * d;
     sx += nx * nx;
   }
   const double td = block_sum(sd, red);
   const double tx = block_sum(sx, red);
   if (threadIdx.x == 0 && use[j]) {
-    nrm[2 * (p * NF + col)] = td;
-    nrm[2 * (p * NF + col) + 1] = tx;
+    nrm[2 * (pr.gp * NF + col)] = td;
+    nrm[2 * (pr.gp * NF + col) + 1] = tx;
   }
 }
 
@@ -2409,13 +2412,14 @@ __global__ void k_wide_ir_write(const DevProb* __restrict__ P, int NF, const dou
     Xout[p][c + int64_t(l0 + i) * pr.n] = x[(pr.offL + c) * NF + i];
 }
 
-__global__ void k_ir_stats_wide(int J, int N, int NF, int l0, const Scal* __restrict__ sc,
-                                const int32_t* __restrict__ use, int32_t* __restrict__ out) {
+__global__ void k_ir_stats_wide(const DevProb* __restrict__ P, int J, int N, int NF, int l0,
+                                const Scal* __restrict__ sc, const int32_t* __restrict__ use,
+                                int32_t* __restrict__ out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= J) return;
   const int p = j / N;
   const Scal& S = sc[j];
-  const int g = p * NF + (S.li - l0);
+  const int g = P[p].gp * NF + (S.li - l0);
   out[2 * g] = use[j] ? S.iters : 0;
   out[2 * g + 1] = use[j] ? S.status : -1;
 }
@@ -2576,11 +2580,32 @@ int wide_mixed_group(const tik_problem* p, int32_t nprob, const tik_precond_s* p
       hr = w.h;
       xcur = static_cast<const double*>(bf.partT);
     }
-    // inner FP32 minimum-norm solve over the selected lambdas
+    // inner FP32 minimum-norm solve over the selected lambdas, over only the
+    // problems with a lambda to correct (the region is sized for all problems;
+    // a subset splits its columns finer and may need more partial rows: then
+    // it takes them all)
+    std::vector<int> pin;
+    for (int k = 0; k < nprob; ++k) {
+      bool any = false;
+      for (int li : sel) any |= use[size_t(k) * NF + size_t(li - l0)] != 0;
+      if (any) pin.push_back(k);
+    }
     WPlan pl;
-    const bool ov = true;
-    make_plan_wide(p, pc, ps, sel, pl, ov ? Aov.data() : nullptr, ov ? ldo.data() : nullptr);
-    for (auto& d : pl.P) d.a_f32 = 1;
+    make_plan_wide(p, pc, pin, sel, pl, Aov.data(), ldo.data());
+    {
+      Arena m;
+      WBufs mb;
+      take_wbufs(m, pl, sizeof(float), mb);
+      if (m.used > w.cap32 && pin.size() < size_t(nprob)) {
+        pin = ps;
+        make_plan_wide(p, pc, pin, sel, pl, Aov.data(), ldo.data());
+      }
+    }
+    for (size_t lp = 0; lp < pl.P.size(); ++lp) {
+      pl.P[lp].a_f32 = 1;
+      pl.P[lp].irL = pf.P[size_t(pin[lp])].offL;
+      pl.P[lp].irS = pf.P[size_t(pin[lp])].offS;
+    }
     Arena ai;
     ai.base = w.base32;
     ai.cap = w.cap32;
@@ -2592,8 +2617,9 @@ int wide_mixed_group(const tik_problem* p, int32_t nprob, const tik_precond_s* p
     }
     TIK_TRY(upload_wplan(pl, bi, pc, nullptr, keep, st));
     std::vector<int32_t> uj(size_t(pl.J));
-    for (int k = 0; k < nprob; ++k)
-      for (size_t i = 0; i < sel.size(); ++i) uj[k * sel.size() + i] = use[size_t(k) * NF + (sel[i] - l0)];
+    for (size_t lp = 0; lp < pin.size(); ++lp)
+      for (size_t i = 0; i < sel.size(); ++i)
+        uj[lp * sel.size() + i] = use[size_t(pin[lp]) * NF + size_t(sel[i] - l0)];
     keep.emplace_back(reinterpret_cast<const char*>(uj.data()), reinterpret_cast<const char*>(uj.data()) + uj.size() * 4);
     TIK_HIP(hipMemcpyAsync(w.use, keep.back().data(), uj.size() * 4, hipMemcpyHostToDevice, st));
     WideIr ir{w.use, hr, NF, l0};
@@ -2609,8 +2635,8 @@ int wide_mixed_group(const tik_problem* p, int32_t nprob, const tik_precond_s* p
                        bi.sc, w.use, bi.xt, xcur, w.nrm);
     TIK_LAUNCHED("k_wide_ir_norms");
     TIK_HIP(hipMemsetAsync(w.stats, 0xFF, stats.size() * 4, st));
-    hipLaunchKernelGGL(k_ir_stats_wide, dim3(unsigned(cdiv(pl.J, 256))), dim3(256), 0, st, pl.J,
-                       pl.N, NF, l0, bi.sc, w.use, w.stats);
+    hipLaunchKernelGGL(k_ir_stats_wide, dim3(unsigned(cdiv(pl.J, 256))), dim3(256), 0, st, bi.P,
+                       pl.J, pl.N, NF, l0, bi.sc, w.use, w.stats);
     TIK_LAUNCHED("k_ir_stats_wide");
     TIK_HIP(hipMemcpyAsync(nrm.data(), w.nrm, nrm.size() * 8, hipMemcpyDeviceToHost, st));
     TIK_HIP(hipMemcpyAsync(stats.data(), w.stats, stats.size() * 4, hipMemcpyDeviceToHost, st));

@@ -323,6 +323,26 @@ def test_wide_ragged_and_fp64_storage():
         assert np.all(res.status.cpu().numpy() == tik.ST_CONVERGED)
 
 
+def test_wide_mixed_sweeps_over_problems_left():
+    """Wide problems of different difficulty in one mixed call: the easy ones stop refining first, so
+    later sweeps run over a subset of the problems (their rows map into the refinement vectors)."""
+    rng = np.random.default_rng(11)
+    plist = []
+    for k, (m, n) in enumerate([(70, 1200), (120, 2000), (50, 900), (100, 1600)]):
+        A = np.asfortranarray(rng.standard_normal((m, n)) * np.logspace(0, -4, n)[None, :])
+        b = A @ rng.standard_normal(n) + 1e-3 * rng.standard_normal(m)
+        # large lambdas converge in the first sweeps, small ones need more
+        lams = np.logspace(1, 3, 5) if k % 2 == 0 else np.logspace(-7, -3, 5)
+        plist.append(W.Problem("wide", A, b, lams, 4 * m, "gauss", "chol", 1e-10, 0))
+    res, _ = _solve(plist, tik.MIXED_BATCHED, embed=tik.GAUSS, tol=1e-10)
+    its = res.iters.cpu().numpy()
+    for k, p in enumerate(plist):
+        err = oracle.rel_err(res.x_numpy(k), oracle.solve(p.A, p.b, p.lams))
+        print("wide mixed", k, "%.2e" % err.max(), its[k])
+        assert np.all(err <= 1e-8), (k, err)
+    assert np.all(res.status.cpu().numpy() == tik.ST_CONVERGED)
+
+
 # ------------------------------------------------------------- BF16 sketch ----
 
 def _bf16(a):
