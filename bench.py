@@ -150,7 +150,8 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of "
-              "this path is described in DESIGN.md but not built", file=sys.stderr)
+              "this path (rows or columns of A per GPU, one all-reduce per product) is not built",
+              file=sys.stderr)
         return 2
 
     import torch
