@@ -51,7 +51,7 @@ typedef enum {
   TIK_EINVAL = -1,      /* bad argument; nothing was launched */
   TIK_EWORKSPACE = -2,  /* workspace pointer NULL, misaligned or too small */
   TIK_EHIP = -3,        /* a HIP runtime call failed; see tik_last_error() */
-  TIK_ENOTSUP = -4      /* valid request outside what this build implements */
+  TIK_ENOTSUP = -4      /* valid request outside what the library implements */
 } tik_rc;
 
 /* per-(problem, lam) outcome */

@@ -64,7 +64,7 @@ def test_sketch_size_limits():
     assert _bytes(_probs(), s=(100,))[0] == tik.OK
     assert _bytes(_probs(), embed=9)[0] == tik.EINVAL
     assert _bytes(_probs(), sdt=tik.BF16)[0] == tik.EINVAL      # BF16 needs the Gaussian sketch
-    # SRHT of a wide matrix and beyond 2^18 rows are outside this build
+    # SRHT of a wide matrix and beyond 2^18 rows are outside what the library implements
     assert _bytes(_probs(m=10, n=100), s=(5,))[0] == tik.ENOTSUP
     assert _bytes(_probs(m=300000, n=10), s=(40,))[0] == tik.ENOTSUP
     assert _bytes(_probs(m=10, n=100), embed=tik.GAUSS, s=(5,))[0] == tik.OK

@@ -23,8 +23,8 @@ from paper_2203_07329_amd import tik
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
-TOL_MIXED = 1e-8     # spec tolerance after refinement
-TOL_F64 = 1e-10      # spec tolerance of the FP64 path
+TOL_MIXED = 1e-8     # target forward error of the mixed mode
+TOL_F64 = 1e-10      # target forward error of the FP64 path
 
 
 def say(*a):
@@ -75,7 +75,7 @@ def test_fullsize_benchmark_configuration(name):
 
 
 def test_fullsize_over_gauss_fp64_batched():
-    """The FP64 path at the spec FP64 tolerance: kappa(A) = 1e8, N = 32."""
+    """The FP64 path at its target forward error: kappa(A) = 1e8, N = 32."""
     plist, cfg, mode, Xs, st = _run("over_gauss", "f64", tol=1e-13)
     assert mode == tik.F64_BATCHED
     assert np.all(st <= tik.ST_MAXIT), st
