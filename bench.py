@@ -368,6 +368,10 @@ def main() -> int:
             sketch_mfma = {"bound": "mfma", "dtype": "bf16", "achieved": round(tf, 1),
                            "peak": BF16_PEAK_TFS, "unit": "TFLOP/s", "frac": round(tf / BF16_PEAK_TFS, 4),
                            "ms_per_step": round(sk_ms, 3), "flops": flops}
+            # a batch's per-problem sketches run on several streams at once, which stretches each
+            # launch: the stage's wall time gives the rate the whole GPU delivers
+            if stage_ms["sketch"] > 0:
+                sketch_mfma["stage_tflops"] = round(flops / (stage_ms["sketch"] / 1000.0) / 1e12, 1)
 
     line = {
         "metric": METRIC,
