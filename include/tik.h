@@ -19,8 +19,8 @@
  * Conventions shared by every entry point:
  *  - Matrices are column-major.  All pointers named "device" are HIP device
  *    pointers owned by the caller; the library never allocates device memory
-    (it keeps a few streams per device and a pool of pinned host words for
-    the solve loop, both created on first use and held by the process).
+ *    (it keeps a few streams per device and a pool of pinned host words for
+ *    the solve loop, both created on first use and held by the process).
  *    Every call that needs scratch space takes a caller-provided device
  *    workspace (dws, dws_bytes) whose required size the matching *_bytes
  *    query returns.  A handle points into the workspace it was built in: the
@@ -129,7 +129,8 @@ int tik_sketch_bytes(const tik_problem* p, int32_t nprob, int32_t embed,
                   BF16, FP32 accumulation; the sketch only sets the
                   preconditioner's quality);
    s[nprob]       host, sketch size per problem, 1 <= s <= the long dimension;
-                  the SRHT also needs m' <= 2^19;
+                  the SRHT also needs m' <= 2^18 and s <= 16384
+                  (TIK_ENOTSUP beyond);
    seed           fixes X completely, independently of launch shapes;
    out            receives the handle (host struct; free with tik_sketch_free).
    Returns TIK_EINVAL for bad shapes or mixed orientations (all problems must
@@ -202,7 +203,8 @@ int tik_lsqr_batch_bytes(const tik_problem* p, int32_t nprob, tik_precond_t pc,
    maxit      iteration cap per lambda (per refinement sweep in MIXED_BATCHED);
    X          host array of nprob device pointers; X[k] is n_k x N column-major
               (ld = n_k), column i receives x_{lam_i}; written only where the
-              status is CONVERGED or MAXIT;
+              status is CONVERGED or MAXIT, and in MIXED_BATCHED also where
+              it is IR_STALL (the last refined iterate);
    iters      device int32 nprob x N: LSQR iterations used (summed over sweeps);
    status     device int32 nprob x N: tik_status values;
    relres     device double nprob x N: the final ||M^T r|| / (||M|| ||r||)

@@ -28,7 +28,10 @@ What it computes (each function cites the passage it follows):
 
 Parity status: every function above is pinned by tests in
 tests/test_oracle_pins.py against closed forms, exact rational arithmetic,
-a LAPACK cross-check or the paper's own identities.
+a LAPACK cross-check, an independent LSQR (scipy's, for the iteration bound)
+or the paper's own identities (the wide-problem factors against the mirror
+of the BP2 equivalence, the underdetermined condition lemma of Section 2.2
+and the theorem of Section 3.3.2).
 """
 
 from .tikhonov import (  # noqa: F401

@@ -67,6 +67,12 @@ def test_sketch_size_limits():
     # SRHT of a wide matrix and beyond 2^18 rows are outside what the library implements
     assert _bytes(_probs(m=10, n=100), s=(5,))[0] == tik.ENOTSUP
     assert _bytes(_probs(m=300000, n=10), s=(40,))[0] == tik.ENOTSUP
+    # the first row count rejected: m' = 2^18 is accepted, 2^18 + 1 pads to 2^19
+    assert _bytes(_probs(m=1 << 18, n=10), s=(40,))[0] == tik.OK
+    assert _bytes(_probs(m=(1 << 18) + 1, n=10), s=(40,))[0] == tik.ENOTSUP
+    # s above 16384 is outside the SRHT's row sampler
+    assert _bytes(_probs(m=1 << 16, n=10), s=(16384,))[0] == tik.OK
+    assert _bytes(_probs(m=1 << 16, n=10), s=(16385,))[0] == tik.ENOTSUP
     assert _bytes(_probs(m=10, n=100), embed=tik.GAUSS, s=(5,))[0] == tik.OK
 
 

@@ -222,12 +222,134 @@ def test_thm32_bound_chol_and_lowrank():
         assert abs(kc - kl) < 1e-6 * kc      # any R with R^T R = Y^T Y + lam I
 
 
-def test_iteration_bound():
-    assert oracle.lsqr_iteration_bound(1.0, 1e-10) == 1
-    assert oracle.lsqr_iteration_bound(3.0, 1e-10) == math.ceil(math.log(2e10) / math.log(2.0))
+def _lsqr_energy_error(M, c, ys, iters):
+    """||M (y_l - y*)|| / ||M y*|| after exactly `iters` steps of scipy's LSQR from y0 = 0."""
+    from scipy.sparse.linalg import lsqr
+    y = lsqr(M, c, atol=0.0, btol=0.0, conlim=0.0, iter_lim=iters)[0]
+    return float(np.linalg.norm(M @ (y - ys)) / np.linalg.norm(c))
+
+
+@pytest.mark.parametrize("kappa", [2.0, 10.0, 100.0])
+def test_iteration_bound_against_lsqr(kappa):
+    """Section 3.3: LSQR's error contracts like CG on M^T M.
+
+    Independent check: scipy's LSQR (Paige & Saunders) on consistent systems
+    M y = c whose operator has a prescribed condition number.  After the
+    bound's count the error in the M^T M energy norm is below eps, for a
+    geometric and a Chebyshev-node spectrum.  The bound is also not loose:
+    for kappa = 2 and 10 half its count is not enough, and for kappa = 100
+    the count of the printed form (sqrt(kappa) in place of kappa) is far too
+    small.  A slip in the bound's formula fails one of these.
+    """
+    rng = np.random.default_rng(int(kappa))
+    m, n = 900, 400
+    U = W.haar(rng, m, n)
+    V = W.haar(rng, n, n)
+    t = np.cos(np.arange(n) * np.pi / (n - 1))          # Chebyshev extreme points, ends included
+    lo = 1.0 / kappa ** 2
+    spectra = {"geometric": np.logspace(0, -math.log10(kappa), n),
+               "chebyshev": np.sqrt((1 + lo) / 2 + (1 - lo) / 2 * t)}
+    for name, sig in spectra.items():
+        M = (U * sig) @ V.T
+        assert abs(np.linalg.cond(M) / kappa - 1) < 1e-6
+        ys = rng.standard_normal(n)
+        c = M @ ys
+        for eps in (1e-6, 1e-10):
+            L = oracle.lsqr_iteration_bound(kappa, eps)
+            assert _lsqr_energy_error(M, c, ys, L) <= eps, (name, eps, L)
+            if kappa <= 10:
+                assert _lsqr_energy_error(M, c, ys, L // 2) > eps, (name, eps, L)
+            else:
+                Ls = oracle.lsqr_iteration_bound(math.sqrt(kappa), eps)
+                assert _lsqr_energy_error(M, c, ys, Ls) > 1e3 * eps, (name, eps, Ls)
+
+
+def test_iteration_bound_special_cases():
+    assert oracle.lsqr_iteration_bound(1.0, 1e-10) == 1          # M orthonormal: one step
     ks = [1.5, 2, 4, 8, 16]
     its = [oracle.lsqr_iteration_bound(k, 1e-8) for k in ks]
     assert its == sorted(its)
+    # O(log 1/eps): squaring eps roughly doubles the count
+    a, b = oracle.lsqr_iteration_bound(10.0, 1e-5), oracle.lsqr_iteration_bound(10.0, 1e-10)
+    assert 1.8 * a <= b <= 2.2 * a
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2 / Algorithm 4 (wide problems): preconditioners from Y = A X
+
+def _wide_problem(m=40, n=300, s=160, seed=8, decay=6.0):
+    rng = np.random.default_rng(seed)
+    U = W.haar(rng, m, m)
+    V = W.haar(rng, n, m)
+    sig = np.exp(-np.arange(m) / decay)
+    A = (U * sig) @ V.T
+    X = rng.standard_normal((n, s)) / math.sqrt(s)
+    return A, U, sig, V, X
+
+
+def test_chol_precond_under_bp2_mirror_and_lemma():
+    """Algorithm 2 steps 3-4: R^T R = Y Y^T + lam I_m.
+
+    Pins: R equals the R factor (diagonal made positive) of the Householder QR
+    of [Y^T; sqrt(lam) I_m] (the wide mirror of BP2, Section 4.1), a route that
+    never forms Y Y^T; and the preconditioned D = [A sqrt(lam) I] obeys the
+    condition bound of the underdetermined lemma of Section 2.2, in its
+    general form max(1, s_max(X^T V_A)) / min(1, s_min(X^T V_A)).
+    """
+    A, UA, sig, VA, X = _wide_problem()
+    m = A.shape[0]
+    Y = A @ X
+    for lam in [1e-10, 1e-4, 1e-1]:
+        R = oracle.chol_precond_under(Y, lam)
+        assert R.shape == (m, m) and np.array_equal(R, np.triu(R))
+        Rq = np.linalg.qr(np.vstack([Y.T, math.sqrt(lam) * np.eye(m)]), mode="r")
+        Rq = Rq * np.sign(np.diag(Rq))[:, None]
+        assert np.linalg.norm(R - Rq) <= 1e-10 * np.linalg.norm(R), lam
+        D = np.hstack([A, math.sqrt(lam) * np.eye(m)])
+        k = _kappa(np.linalg.solve(R.T, D))
+        assert k <= oracle.lemma21_bound(X.T @ VA) * (1 + 1e-8), (lam, k)
+
+
+def test_lowrank_left_factors_rinv_and_thm34():
+    """Algorithm 4 step 4: U and sigma of Y = A X (m x s, s < m).
+
+    Pins: with R^{-T} = lam^{-1/2} (I_m - U S U^T) (the wide form of eq.
+    RinvOver), R^{-T} (Y Y^T + lam I_m) R^{-1} = I; Y = U diag(sigma) W^T
+    with W orthonormal; and the theorem of Section 3.3.2: kappa(R^{-T} D) <=
+    sqrt((1 + eps) / (1 - eps)) with eps = ||V_1^T X X^T V_1 - V_1^T V_1||,
+    V_1 the first n rows of D's right singular vectors, whose squared
+    Frobenius norm is sd_lam(A) (the underdetermined lemma of Section 3.3.2).
+    """
+    A, UA, sig, VA, _ = _wide_problem(m=60, n=500, s=0, decay=3.0)
+    m, n = A.shape
+    rng = np.random.default_rng(21)
+    for lam in [1e-3, 1e-2]:
+        sd = oracle.statistical_dimension(sig, lam)
+        s = min(m - 1, int(6 * math.ceil(sd)))
+        X = rng.standard_normal((n, s)) / math.sqrt(s)
+        Y = A @ X
+        sY, U = oracle.lowrank_factors(Y, side="left")
+        assert U.shape == (m, s) and sY.shape == (s,)
+        # U orthonormal and spans Y's columns; sigma are Y's singular values
+        # (the square roots of the eigenvalues of the s x s Gram matrix)
+        assert np.allclose(U.T @ U, np.eye(s), atol=1e-12)
+        assert np.linalg.norm(Y - U @ (U.T @ Y)) <= 1e-13 * np.linalg.norm(Y)
+        ev = np.sqrt(np.clip(np.linalg.eigvalsh(Y.T @ Y)[::-1], 0, None))
+        assert np.allclose(sY, ev, rtol=0, atol=1e-7 * sY[0])
+        RiT = oracle.lowrank_rinv(U, sY, lam)
+        G = RiT @ (Y @ Y.T + lam * np.eye(m)) @ RiT.T
+        assert np.linalg.norm(G - np.eye(m)) < 1e-13 * (1 + sY[0] ** 2 / lam)
+        D = np.hstack([A, math.sqrt(lam) * np.eye(m)])
+        VD = np.linalg.svd(D, full_matrices=False)[2].T          # (n + m) x m
+        V1 = VD[:n]
+        assert abs(np.sum(V1 ** 2) - sd) < 1e-10
+        eps = float(np.linalg.norm(V1.T @ X @ X.T @ V1 - V1.T @ V1, 2))
+        assert eps < 1
+        k = _kappa(RiT @ D)
+        assert k <= oracle.thm32_bound(eps) * (1 + 1e-8), (lam, k, eps)
+    # a plausible slip: the right factor in place of the left one fails the identity
+    sR, Vr = oracle.lowrank_factors(Y, side="right")
+    assert Vr.shape != U.shape or not np.allclose(Vr, U)
 
 
 def test_certify_bounds_error():
