@@ -18,16 +18,19 @@ route).  --workload selects the others:
 A and b are resident on the GPU before timing starts.
 
 value = (number of solves within 1e-8 relative error of the CPU FP64 oracle)
-/ (seconds per step) for the batched solve; the plain FP64 per-lambda loop
-is timed beside it.  Where the oracle's direct solve is too slow for the
-whole batch, it checks a stated sample (ragged: every 16th problem) or
-certifies the error bound instead (lowsd: gradient in extended precision,
-inverted with the generator's planted factors).  roofline: the dominant
-kernel family's algorithmic bytes per launch over its average launch time,
-from HIP events the library records around every launch during the timed
-steps.  cpu_baseline: the oracle's direct QR solve, timed on the host.
-Beside a mixed-mode line, f64_batched_same_input times batched FP64 LSQR on
-the same input and checks it against the same oracle solves.
+/ (seconds per step) for the batched solve; every solve is checked: the
+oracle's direct solve for every problem, or, where that takes minutes (the
+low-rank workload), an a-posteriori bound (gradient in extended precision,
+inverted with the generator's planted factors).  config.mode names what ran:
+a mixed-mode call whose every lambda needed FP64 products is f64_batched.
+The timed steps run as a user runs them (the solve loop replays captured
+graphs); then --prof-steps more steps run with HIP events around every
+launch on the library's stream, which give the kernel durations behind
+roofline (the dominant kernel family's algorithmic bytes per launch over its
+average launch time).  Beside the timed mode, the plain FP64 per-lambda loop
+and batched FP64 are timed (events) at an LSQR tolerance whose forward error
+meets the FP64 target 1e-10, each with its own error against the oracle.
+cpu_baseline: the oracle's direct QR solve, timed on the host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -85,13 +88,17 @@ def build_workload(name, tik, W, dev):
         cfg = dict(embed=tik.GAUSS, sdt=tik.BF16, route=tik.ROUTE_CHOL, mode="auto",
                    desc="256 tall Gaussian problems, sigma logspaced 1..1e-6 (FP32): m~U[5000,50000] "
                         "n~U[100,1000] N=8 lambda 1e-6..1e-1, BF16 Gaussian s=4n_p, Cholesky route",
-                   check="sample16")
+                   check="full")
     else:
         raise SystemExit(f"unknown workload {name}")
     return plist, cfg
 
 
 MAXIT = 300
+F64_TARGET = 1e-10          # forward error the FP64 path is held to
+# LSQR tolerance per workload at which the FP64 legs reach F64_TARGET
+F64_TOL = {"over_svd": 1e-12, "over_gauss": 1e-13, "under_scaled": 1e-12, "lowsd": 1e-12,
+           "ragged": 1e-12}
 FAMILY_KERNEL = {"gemm_n": "k_gemm_n", "gemm_t": "k_gemm_t", "trmv": "k_trmv<", "trmv_t": "k_trmv_t<",
                  "lr_apply": "k_lr_"}
 
@@ -143,10 +150,16 @@ def main() -> int:
     ap.add_argument("--mode", default=None, choices=["auto", "mixed", "f64"])
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--alt-steps", type=int, default=1,
-                    help="when the timed mode is mixed: steps of batched FP64 on the same input")
+                    help="steps of batched FP64 on the same input at the FP64 legs' tolerance")
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle (profiling runs)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0,
                     help="GiB: also run one plain device copy of this size (HBM counter calibration)")
+    ap.add_argument("--prof-steps", type=int, default=2,
+                    help="steps run after the timed ones with per-launch events on (kernel durations)")
+    ap.add_argument("--graph-chunk", type=int, default=None,
+                    help="LSQR iterations per graph-captured chunk (library option; 0: no graphs)")
+    ap.add_argument("--f64-tol", type=float, default=None,
+                    help="LSQR tolerance of the FP64 legs (default: one that reaches 1e-10)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of "
@@ -160,6 +173,8 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.graph_chunk is not None:
+        tik.set_option("graph_chunk", args.graph_chunk)
     t0 = time.perf_counter()
     plist, cfg = build_workload(args.workload, tik, W, "cuda:0")
     log(f"generated {len(plist)} problem(s), {sum(p.m * p.n for p in plist) / 1e6:.0f} M entries "
@@ -190,6 +205,21 @@ def main() -> int:
     mode, tol = pick_mode(tik, pr, cfg, svec, lams, alpha, args.mode or cfg["mode"])
     dtype = "f32+f64" if mode == tik.MIXED_BATCHED else "f64"
     maxit = MAXIT
+    # FP64 legs at a tolerance whose forward error meets the FP64 target of 1e-10:
+    # x = R^{-1} y amplifies the error of y along R's small singular directions
+    f64_tol = args.f64_tol or F64_TOL.get(args.workload, 1e-13)
+
+    def timed(m_, tol_, steps):
+        """Mean ms per step of `steps` whole steps, between events on the current stream."""
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(steps):
+            out = one_step(m_, tol_)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps, out
 
     # ---- warmup
     for _ in range(args.warmup):
@@ -197,9 +227,7 @@ def main() -> int:
     torch.cuda.synchronize()
     log("warmup done")
 
-    # ---- timed steps (per-kernel events on)
-    tik.prof_reset()
-    tik.prof_enable(True)
+    # ---- timed steps (no per-launch events: the solve loop replays captured graphs)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -211,8 +239,17 @@ def main() -> int:
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    tik.prof_enable(False)
     ms_step = ev0.elapsed_time(ev1) / args.steps
+    n32, n64 = tik.lsqr_info()
+    # ---- profiled steps: the same steps with HIP events around every launch on the
+    # library's stream (each iteration then launched directly), for kernel durations
+    tik.prof_reset()
+    tik.prof_enable(True)
+    torch.cuda.synchronize()
+    for _ in range(args.prof_steps):
+        one_step(mode, tol)
+    torch.cuda.synchronize()
+    tik.prof_enable(False)
     # wall time of each stage on the caller's stream, per step
     stage_ms = {k: 0.0 for k in ("sketch", "precond", "solve")}
     for st in range(args.steps):
@@ -221,13 +258,15 @@ def main() -> int:
             stage_ms[k] += e[j].elapsed_time(e[j + 1]) / args.steps
     log(f"timed {args.steps} steps: {ms_step:.2f} ms/step")
     fam = {}
+    npf = max(1, args.prof_steps)
     for f in FAMILIES:
         ms, n = tik.prof_query(f)
         if n:
-            fam[f] = (ms / args.steps, n // args.steps, ms / n)
-    n32, n64 = tik.lsqr_info()
+            fam[f] = (ms / npf, n // npf, ms / n)
     if mode == tik.MIXED_BATCHED:
         dtype = "f32+f64" if n32 > 0 else "f64"
+    # what ran: a mixed call whose every lambda needed FP64 products is batched FP64
+    ran = "mixed_batched" if (mode == tik.MIXED_BATCHED and n32 > 0) else "f64_batched"
     Xs = [res.x_numpy(k) for k in range(len(plist))]
     iters = res.iters.cpu().numpy()
     status = res.status.cpu().numpy()
@@ -244,30 +283,20 @@ def main() -> int:
     # ---- plain FP64 per-lambda loop
     plain = None
     if args.plain_steps > 0:
-        torch.cuda.synchronize()
-        q0 = time.perf_counter()
-        for _ in range(args.plain_steps):
-            rp = one_step(tik.PLAIN_F64_PER_LAMBDA, 1e-11)
-        torch.cuda.synchronize()
-        plain_ms = (time.perf_counter() - q0) * 1000.0 / args.plain_steps
+        plain_ms, rp = timed(tik.PLAIN_F64_PER_LAMBDA, f64_tol, args.plain_steps)
         plain = {"ms_per_step": plain_ms, "X": [rp.x_numpy(k) for k in range(len(plist))],
-                 "iters": rp.iters.cpu().numpy()}
-        log(f"plain per-lambda: {plain_ms:.1f} ms/step")
+                 "iters": rp.iters.cpu().numpy(), "tol": f64_tol}
+        log(f"plain per-lambda (tol {f64_tol:g}): {plain_ms:.1f} ms/step")
 
     # ---- batched FP64 on the same input, beside a mixed-mode line (FP32-stored A
     # is read at the same bytes per pass in both modes)
     alt = None
-    if mode == tik.MIXED_BATCHED and args.alt_steps > 0:
-        one_step(tik.F64_BATCHED, 1e-11)
-        torch.cuda.synchronize()
-        q0 = time.perf_counter()
-        for _ in range(args.alt_steps):
-            ra = one_step(tik.F64_BATCHED, 1e-11)
-        torch.cuda.synchronize()
-        alt_ms = (time.perf_counter() - q0) * 1000.0 / args.alt_steps
+    if args.alt_steps > 0:
+        one_step(tik.F64_BATCHED, f64_tol)
+        alt_ms, ra = timed(tik.F64_BATCHED, f64_tol, args.alt_steps)
         alt = {"ms_per_step": alt_ms, "X": [ra.x_numpy(k) for k in range(len(plist))],
-               "iters": ra.iters.cpu().numpy()}
-        log(f"batched FP64 on the same input: {alt_ms:.1f} ms/step")
+               "iters": ra.iters.cpu().numpy(), "tol": f64_tol}
+        log(f"batched FP64 on the same input (tol {f64_tol:g}): {alt_ms:.1f} ms/step")
 
     # ---- oracle (timed: the CPU baseline) and accuracy
     n_ok = None
@@ -293,9 +322,13 @@ def main() -> int:
                 if alt is not None else None
             checked = f"all {nsolve} solves by an a-posteriori bound ({tcert:.1f} s on the host)"
         else:
-            idx = list(range(len(plist))) if cfg["check"] == "full" else list(range(0, len(plist), 16))
+            idx = list(range(len(plist)))
             c0 = time.perf_counter()
-            Xo = {k: oracle.solve(plist[k].A, plist[k].b, plist[k].lams) for k in idx}
+            Xo = {}
+            for k in idx:
+                Xo[k] = oracle.solve(plist[k].A, plist[k].b, plist[k].lams)
+                if len(idx) > 1 and (k + 1) % 32 == 0:
+                    log(f"oracle: {k + 1} of {len(idx)} problems solved ({time.perf_counter() - c0:.0f} s)")
             tcpu = time.perf_counter() - c0
             errs = [oracle.rel_err(Xs[k], Xo[k]) for k in idx]
             pl_errs = [oracle.rel_err(plain["X"][k], Xo[k]) for k in idx] if plain is not None else None
@@ -305,16 +338,16 @@ def main() -> int:
                     f"{nsamp} solves ({tcpu:.1f} s)")
             cpu = {"value": round(nsamp / tcpu, 4), "unit": "λ-solves/s", "cores": int(cores),
                    "kind": "oracle",
-                   "sample": ("full workload: " if len(idx) == len(plist) else "every 16th problem: ") + what}
+                   "sample": "full workload: " + what}
             checked = f"{len(idx)} of {len(plist)} problems against the oracle's direct solve"
         allerr = np.concatenate([np.ravel(e) for e in errs])
         err_max = float(allerr.max())
-        frac = float(np.mean(allerr <= TOL_ERR))
-        n_ok = int(round(frac * nsolve))
+        n_ok = int(np.sum(allerr <= TOL_ERR))          # every solve is checked
         for other, oe in ((plain, pl_errs), (alt, al_errs)):
             if other is not None and oe is not None:
                 pe = np.concatenate([np.ravel(e) for e in oe])
-                other["n_ok"] = int(round(float(np.mean(pe <= TOL_ERR)) * nsolve))
+                other["n_ok"] = int(np.sum(pe <= TOL_ERR))
+                other["n_ok_f64"] = int(np.sum(pe <= F64_TARGET))
                 other["max_rel_err"] = float(pe.max())
     value = (n_ok if n_ok is not None else 0) / (ms_step / 1000.0)
 
@@ -386,9 +419,9 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": cfg["desc"],
-                   "mode": {tik.F64_BATCHED: "f64_batched", tik.MIXED_BATCHED: "mixed_batched"}[mode],
-                   "tol": tol, "solves": nsolve},
+        "config": {"workload": cfg["desc"], "mode": ran,
+                   "requested_mode": {tik.F64_BATCHED: "f64_batched", tik.MIXED_BATCHED: "mixed_batched"}[mode],
+                   "tol": tol, "solves": nsolve, "graph_chunk": tik.get_option("graph_chunk")},
         "roofline": roof,
         "sketch_mfma": sketch_mfma,
         "cpu_baseline": cpu,
@@ -407,17 +440,26 @@ def main() -> int:
         "launches_per_step": {k: v[1] for k, v in fam.items()},
         "wall_s_timed": round(wall, 3),
     }
+    # the FP64 legs: value counts solves within 1e-8 (the metric), value_f64 those
+    # within the FP64 target 1e-10 that their tolerance is chosen for
     if plain is not None:
-        pv = plain.get("n_ok", nsolve) / (plain["ms_per_step"] / 1000.0)
-        line["plain_f64_per_lambda"] = {"value": round(pv, 3), "ms_per_step": round(plain["ms_per_step"], 2),
+        sec = plain["ms_per_step"] / 1000.0
+        pv = plain.get("n_ok", 0) / sec
+        line["plain_f64_per_lambda"] = {"value": round(pv, 3), "value_f64": round(plain.get("n_ok_f64", 0) / sec, 3),
+                                        "ms_per_step": round(plain["ms_per_step"], 2), "tol": plain["tol"],
                                         "max_rel_err": plain.get("max_rel_err"),
                                         "iters_max": int(plain["iters"].max())}
         line["speedup_vs_plain"] = round(value / pv, 2) if pv > 0 else None
     if alt is not None:
-        av = alt.get("n_ok", 0) / (alt["ms_per_step"] / 1000.0)
-        line["f64_batched_same_input"] = {"value": round(av, 3), "ms_per_step": round(alt["ms_per_step"], 2),
-                                          "solves_ok": alt.get("n_ok"), "max_rel_err": alt.get("max_rel_err"),
-                                          "iters_max": int(alt["iters"].max())}
+        sec = alt["ms_per_step"] / 1000.0
+        av = alt.get("n_ok", 0) / sec
+        line["f64_batched"] = {"value": round(av, 3), "value_f64": round(alt.get("n_ok_f64", 0) / sec, 3),
+                               "ms_per_step": round(alt["ms_per_step"], 2), "tol": alt["tol"],
+                               "solves_ok": alt.get("n_ok"), "solves_ok_f64": alt.get("n_ok_f64"),
+                               "max_rel_err": alt.get("max_rel_err"), "iters_max": int(alt["iters"].max())}
+        if plain is not None and plain.get("n_ok_f64"):
+            pf = plain["n_ok_f64"] / (plain["ms_per_step"] / 1000.0)
+            line["f64_batched_vs_plain_at_1e-10"] = round(line["f64_batched"]["value_f64"] / pf, 2)
     print(json.dumps(line), flush=True)
     return 0
 

@@ -209,12 +209,20 @@ int tik_lsqr_batch_bytes(const tik_problem* p, int32_t nprob, tik_precond_t pc,
    status     device int32 nprob x N: tik_status values;
    relres     device double nprob x N: the final ||M^T r|| / (||M|| ||r||)
               estimate;
-   The host waits on each iteration's count of active lambdas one iteration
-   late (an event after an async copy into one of two pinned host words per
-   call, taken from a small per-process pool allocated on first use): the next
-   iteration is already queued, and when the count was 0 its products return
-   at once and its vector steps leave finished solves unchanged.  Returns when
-   the loop has stopped; the work is stream-ordered on `stream`. */
+   Synchronization: the iterations run in chunks of T (the "graph_chunk"
+   option, default 4), each captured once per call into a HIP graph on a
+   library stream of the calling thread and replayed on `stream`; every
+   iteration ends by writing the count of still-active lambdas on the device,
+   and every kernel of a later iteration returns at once when it reads 0.
+   After queuing chunk c the host waits for the count copied after chunk
+   c - 1 (an event after an async copy into one of two pinned host words,
+   taken from a small per-process pool allocated on first use): a loop of I
+   iterations makes ceil(I / T) + 1 such waits, and the GPU always has the
+   next chunk queued.  T = 0, or per-launch profiling, launches each iteration
+   directly and waits once per iteration, one iteration late.  After the loop
+   the call waits for the outputs to be written (one stream synchronization
+   per group of up to 32 lambdas; MIXED_BATCHED also waits once per
+   refinement sweep), then returns; all device work is ordered on `stream`. */
 int tik_lsqr_batch(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_t mode,
                    double tol, int32_t maxit, double* const* X, int32_t* iters,
                    int32_t* status, double* relres, void* dws, size_t dws_bytes,
@@ -234,6 +242,16 @@ const char* tik_last_error(void);
 
 /* Library version, major * 10000 + minor * 100 + patch. */
 int tik_version(void);
+
+/* Process-wide options.
+   "graph_chunk"  LSQR iterations per graph-captured chunk of tik_lsqr_batch's
+                  loop, 0..64 (0: no graphs, one host wait per iteration);
+                  default 4.  Replays past convergence cost a few microseconds
+                  per kernel, so long chunks only pay where iterations are
+                  long.
+   Returns TIK_EINVAL for an unknown name or a value out of range. */
+int tik_set_option(const char* name, int64_t value);
+int tik_get_option(const char* name, int64_t* value);
 
 /* ----------------------------------------------------------- profiling -- */
 

@@ -1024,6 +1024,7 @@ __global__ void __launch_bounds__(256) k_lr_proj(const DevProb* __restrict__ P,
   static_assert(K <= 64, "values per lane");
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
+  if (plan_stopped(pr)) return;
   const int64_t k = pr.k;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t j0 = int64_t(it.blk) * (4 * CPW) + int64_t(wv) * CPW;
@@ -1077,6 +1078,7 @@ __global__ void __launch_bounds__(256) k_lr_proj_mfma(const DevProb* __restrict_
   if (L >= nitems) return;
   const Item it = items[L];
   const DevProb& pr = P[it.p];
+  if (plan_stopped(pr)) return;
   const double* __restrict__ V = pr.V;
   const int64_t k = pr.k, smax = pr.smax;
   const int64_t c0 = int64_t(it.blk) * CB;
@@ -1175,6 +1177,7 @@ __global__ void __launch_bounds__(256) k_lr_coef(const DevProb* __restrict__ P,
                                                  const Scal* __restrict__ sc) {
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
+  if (plan_stopped(pr)) return;
   const int64_t e = int64_t(it.blk) * 256 + threadIdx.x;
   if (e >= pr.smax * N) return;
   const int64_t j = e / N;
@@ -1194,6 +1197,7 @@ __global__ void __launch_bounds__(256) k_lr_expand(const DevProb* __restrict__ P
   __shared__ double cs[LR_JC * NC];
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
+  if (plan_stopped(pr)) return;
   const int64_t k = pr.k;
   const int64_t j0 = int64_t(it.ch) * LR_JC;
   const int jn = int(min<int64_t>(pr.smax - j0, LR_JC));
@@ -1252,6 +1256,7 @@ __global__ void __launch_bounds__(256) k_lr_fin(const DevProb* __restrict__ P,
   __shared__ double sh[256];
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
+  if (plan_stopped(pr)) return;
   const int64_t k = pr.k;
   const int i = threadIdx.x % NC;
   const int64_t r = int64_t(it.blk) * FR + threadIdx.x / NC;

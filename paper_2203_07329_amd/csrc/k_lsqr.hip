@@ -102,6 +102,7 @@ __global__ void __launch_bounds__(BLK) k_fin_beta(const DevProb* __restrict__ P,
   __shared__ double red[4];
   const int j = blockIdx.x, p = j / N, i = j % N;
   const DevProb& pr = P[p];
+  if (plan_stopped(pr)) return;
   double v = 0.0;
   for (int b = threadIdx.x; b < pr.nblkN; b += BLK) v += pnN[(pr.pnN + b) * N + i];
   for (int b = threadIdx.x; b < pr.nblkB; b += BLK) v += pnB[(pr.pnB + b) * N + i];
@@ -236,6 +237,7 @@ __global__ void __launch_bounds__(BLK) k_vec_bot(const DevProb* __restrict__ P,
   __shared__ double red[4];
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
+  if (plan_stopped(pr)) return;
   const int64_t r = int64_t(it.blk) * BLK + threadIdx.x;
   for (int i = 0; i < N; ++i) {
     const Scal& S = sc[it.p * N + i];
@@ -344,6 +346,7 @@ __global__ void __launch_bounds__(BLK) k_reduce_t(const DevProb* __restrict__ P,
   constexpr int RR = BLK / NC;
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
+  if (plan_stopped(pr)) return;
   const int64_t n = pr.n;
   const int64_t c = int64_t(it.blk) * RR + threadIdx.x / NC;
   const int i = threadIdx.x % NC;
@@ -387,6 +390,7 @@ __global__ void __launch_bounds__(BLK) k_trmv_t(const DevProb* __restrict__ P,
   const Item it = items[blockIdx.x];
   const int j = it.j, p = it.p, i = j % N;
   const DevProb& pr = P[p];
+  if (plan_stopped(pr)) return;
   const int64_t k = pr.k;
   const double* __restrict__ R = pr.Rinv + int64_t(sc[j].li) * k * k;
   const double* __restrict__ tv = t + pr.offS * N + int64_t(i) * k;
@@ -430,6 +434,7 @@ __global__ void __launch_bounds__(BLK) k_fin_alpha(const DevProb* __restrict__ P
   __shared__ double red[4];
   const int j = blockIdx.x, p = j / N, i = j % N;
   const DevProb& pr = P[p];
+  if (plan_stopped(pr)) return;
   double v = 0.0;
   for (int b = threadIdx.x; b < pr.nblkQ; b += BLK) v += pnQ[(pr.pnQ + b) * N + i];
   const double s = block_sum(v, red);
@@ -535,6 +540,7 @@ __global__ void __launch_bounds__(BLK) k_trmv(const DevProb* __restrict__ P,
   const Item it = items[blockIdx.x];
   const int j = it.j, p = it.p, i = j % N;
   const DevProb& pr = P[p];
+  if (plan_stopped(pr)) return;
   const int64_t k = pr.k;
   const double* __restrict__ R = pr.Rinv + int64_t(sc[j].li) * k * k;
   const int tr = threadIdx.x & 15, sl = threadIdx.x >> 4;
@@ -788,6 +794,7 @@ __global__ void __launch_bounds__(BLK) k_wide_h(const DevProb* __restrict__ P,
   constexpr int RR = BLK / NC;
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
+  if (plan_stopped(pr)) return;
   const int64_t m = pr.m;
   const int64_t r = int64_t(it.blk) * RR + threadIdx.x / NC;
   const int i = threadIdx.x % NC;
@@ -839,6 +846,7 @@ __global__ void __launch_bounds__(BLK) k_wide_v(const DevProb* __restrict__ P,
   __shared__ double sh[BLK];
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
+  if (plan_stopped(pr)) return;
   const int RB = BLK >> lgnc;
   const int i = threadIdx.x & ((1 << lgnc) - 1);
   const int nL = int(cdiv(pr.n, RB));
@@ -879,6 +887,7 @@ __global__ void __launch_bounds__(BLK) k_wide_upd(const DevProb* __restrict__ P,
                                                   const Scal* __restrict__ sc, int init) {
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
+  if (plan_stopped(pr)) return;
   const int RB = BLK >> lgnc;
   const int i = threadIdx.x & ((1 << lgnc) - 1);
   const int nL = int(cdiv(pr.n, RB));
@@ -1321,12 +1330,19 @@ struct IrRhs {
 };
 
 // ------------------------------------------------------ iteration control --
-// The solve loops read the active count of iteration i on the host while
-// iteration i + 1 already runs: the count goes to a pinned host word (two per
-// solve, alternating), an event marks its arrival.  Iteration i + 1 is then
-// queued before the host waits, so the GPU never idles on the check; when the
-// count was 0 the products of that surplus iteration return at once (the
-// plan's `live` word) and the vector steps leave finished solves unchanged.
+// The solve loops queue LSQR iterations ahead of the host: every iteration
+// ends with a one-block kernel that writes the number of still-active solves
+// into the plan's live word, and every kernel of a later iteration returns at
+// once when that word reads 0 (plan_stopped), leaving all state unchanged.
+// The host looks at the count one step late: after queuing step c it waits for
+// the count copied after step c - 1 (an async copy into one of two pinned host
+// words per call, an event each), so the GPU always has work queued.
+//
+// A step is a chunk of T iterations captured once per call into a HIP graph
+// and replayed (T from tik_set_option("graph_chunk"), default 4): a solve of
+// I iterations makes ceil(I / T) + 1 host waits and replays at most two
+// chunks past convergence, whose kernels return at once.  With T = 0, or
+// while per-launch profiling is on, a step is one iteration launched directly.
 std::mutex g_pin_mu;
 std::vector<int32_t*> g_pin_free;   // pinned pairs, kept for the process
 
@@ -1350,21 +1366,16 @@ struct IterGate {
     for (auto& e : ev) TIK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     return TIK_OK;
   }
-  // after the iteration `it` is queued: count, copy, and look at it - 1
-  int step(int it, const Scal* sc, int J, int32_t* cnt, hipStream_t st, bool& stop) {
-    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(BLK), 0, st, sc, J, cnt);
-    TIK_LAUNCHED("k_count_active");
-    TIK_HIP(hipMemcpyAsync(h + (it & 1), cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    TIK_HIP(hipEventRecord(ev[it & 1], st));
-    stop = false;
-    if (it > 0) {
-      TIK_HIP(hipEventSynchronize(ev[(it - 1) & 1]));
-      stop = h[(it - 1) & 1] == 0;
-    }
-    if (stop) {   // the products of iteration `it` return at once
-      prof_drop_last("gemm_n");
-      prof_drop_last("gemm_t");
-    }
+  // after step c is queued: copy the live count to host word c & 1, mark it
+  int post(int c, const int32_t* cnt, hipStream_t st) {
+    TIK_HIP(hipMemcpyAsync(h + (c & 1), cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    TIK_HIP(hipEventRecord(ev[c & 1], st));
+    return TIK_OK;
+  }
+  // wait for the count posted after step c; *zero: every solve has stopped
+  int seen(int c, bool* zero) {
+    TIK_HIP(hipEventSynchronize(ev[c & 1]));
+    *zero = h[c & 1] == 0;
     return TIK_OK;
   }
   // products run again outside the loop (refinement residuals, later calls)
@@ -1384,6 +1395,86 @@ struct IterGate {
     }
   }
 };
+
+// Capture happens on a library stream of the calling thread (a capture records
+// launches without running them); the graph is then replayed on the caller's
+// stream, which may be the null stream where capture itself is not allowed.
+int capture_stream(hipStream_t* out) {
+  thread_local std::vector<hipStream_t> streams;
+  int dev = 0;
+  TIK_HIP(hipGetDevice(&dev));
+  if (size_t(dev) >= streams.size()) streams.resize(size_t(dev) + 1, nullptr);
+  if (!streams[size_t(dev)])
+    TIK_HIP(hipStreamCreateWithFlags(&streams[size_t(dev)], hipStreamNonBlocking));
+  *out = streams[size_t(dev)];
+  return TIK_OK;
+}
+
+struct ChunkGraph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~ChunkGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (g) (void)hipGraphDestroy(g);
+  }
+  template <typename F>
+  int capture(F& one, int T) {
+    hipStream_t cs = nullptr;
+    TIK_TRY(capture_stream(&cs));
+    TIK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int rc = TIK_OK;
+    for (int t = 0; t < T && rc == TIK_OK; ++t) rc = one(cs);
+    const hipError_t e = hipStreamEndCapture(cs, &g);   // always end, even after a failure
+    TIK_TRY(rc);
+    if (e != hipSuccess) {
+      set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      return TIK_EHIP;
+    }
+    TIK_HIP(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+    return TIK_OK;
+  }
+};
+
+// Queue iterations until every solve of the plan has stopped or maxit
+// iterations are queued; `body(s)` queues one iteration's kernels on s.
+template <typename Body>
+int iterate(Body&& body, const Scal* sc, int J, int32_t* cnt, int maxit, hipStream_t st) {
+  IterGate gate;
+  TIK_TRY(gate.open());
+  auto one = [&](hipStream_t s) -> int {
+    TIK_TRY(body(s));
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(BLK), 0, s, sc, J, cnt);
+    TIK_LAUNCHED("k_count_active");
+    return TIK_OK;
+  };
+  const int T = std::min(maxit, option_chunk());
+  if (T > 0 && !prof_active()) {
+    ChunkGraph cg;
+    TIK_TRY(cg.capture(one, T));
+    int queued = 0;
+    for (int c = 0; queued < maxit; ++c) {
+      TIK_HIP(hipGraphLaunch(cg.exec, st));
+      queued += T;
+      TIK_TRY(gate.post(c, cnt, st));
+      bool zero = false;
+      if (c > 0) TIK_TRY(gate.seen(c - 1, &zero));
+      if (zero) break;
+    }
+  } else {
+    for (int it = 0; it < maxit; ++it) {
+      TIK_TRY(one(st));
+      TIK_TRY(gate.post(it, cnt, st));
+      bool zero = false;
+      if (it > 0) TIK_TRY(gate.seen(it - 1, &zero));
+      if (zero) {   // the products of iteration `it` returned at once
+        prof_drop_last("gemm_n");
+        prof_drop_last("gemm_t");
+        break;
+      }
+    }
+  }
+  return gate.close(cnt, st);
+}
 
 template <typename TA, typename TC, int NC>
 int run_core(const Plan& pl, const Bufs& b, double tol, int maxit, hipStream_t st,
@@ -1407,18 +1498,13 @@ int run_core(const Plan& pl, const Bufs& b, double tol, int maxit, hipStream_t s
   }
   TIK_TRY(K::gemm_t(pl, b, st));
   TIK_TRY((vec_steps_v<TC, NC>(pl, b, st, true, tol, maxit)));
-  IterGate gate;
-  TIK_TRY(gate.open());
-  for (int it = 0; it < maxit; ++it) {
-    TIK_TRY(K::gemm_n(pl, b, st));
-    TIK_TRY(vec_steps_u<TC>(pl, b, st, false, nullptr, nullptr));
-    TIK_TRY(K::gemm_t(pl, b, st));
-    TIK_TRY((vec_steps_v<TC, NC>(pl, b, st, false, tol, maxit)));
-    bool stop = false;
-    TIK_TRY(gate.step(it, b.sc, pl.J, b.cnt, st, stop));
-    if (stop) break;
-  }
-  return gate.close(b.cnt, st);
+  auto body = [&](hipStream_t s) -> int {
+    TIK_TRY(K::gemm_n(pl, b, s));
+    TIK_TRY(vec_steps_u<TC>(pl, b, s, false, nullptr, nullptr));
+    TIK_TRY(K::gemm_t(pl, b, s));
+    return vec_steps_v<TC, NC>(pl, b, s, false, tol, maxit);
+  };
+  return iterate(body, b.sc, pl.J, b.cnt, maxit, st);
 }
 
 template <typename TA, typename TC>
@@ -2313,23 +2399,18 @@ int run_core_wide(const WPlan& pl, const WBufs& b, double tol, int maxit, hipStr
   }
   TIK_TRY(wide_u_steps(pl, b, st, true));
   TIK_TRY((wide_v_steps<TA, TC, NC>(pl, b, st, true, tol, maxit)));
-  IterGate gate;
-  TIK_TRY(gate.open());
-  for (int it = 0; it < maxit; ++it) {
-    TIK_TRY((wide_products_n<TA, TC, NC>(pl, b, b.vt, b.partN, st)));
+  auto body = [&](hipStream_t s) -> int {
+    TIK_TRY((wide_products_n<TA, TC, NC>(pl, b, b.vt, b.partN, s)));
     {
-      ProfScope ps("vec", st);
-      hipLaunchKernelGGL((k_wide_h<TC, NC, 0>), dim3(unsigned(pl.itR.size())), dim3(BLK), 0, st,
+      ProfScope ps("vec", s);
+      hipLaunchKernelGGL((k_wide_h<TC, NC, 0>), dim3(unsigned(pl.itR.size())), dim3(BLK), 0, s,
                          b.P, b.itR, pl.N, static_cast<const TC*>(b.partN), b.vb, b.sc, b.t);
       TIK_LAUNCHED("k_wide_h");
     }
-    TIK_TRY(wide_u_steps(pl, b, st, false));
-    TIK_TRY((wide_v_steps<TA, TC, NC>(pl, b, st, false, tol, maxit)));
-    bool stop = false;
-    TIK_TRY(gate.step(it, b.sc, pl.J, b.cnt, st, stop));
-    if (stop) break;
-  }
-  return gate.close(b.cnt, st);
+    TIK_TRY(wide_u_steps(pl, b, s, false));
+    return wide_v_steps<TA, TC, NC>(pl, b, s, false, tol, maxit);
+  };
+  return iterate(body, b.sc, pl.J, b.cnt, maxit, st);
 }
 
 template <typename TA, typename TC>

@@ -9,6 +9,8 @@
 
 #include "tik_internal.h"
 
+#include <atomic>
+
 namespace tik {
 
 static thread_local std::string g_err;
@@ -64,6 +66,14 @@ ProfScope::~ProfScope() {
   g_prof[o.first].ev.push_back(o.second);
   o.second = {nullptr, nullptr};
 }
+
+bool prof_active() { return g_prof_on; }
+
+// ---------------------------------------------------------------- options --
+namespace {
+std::atomic<int> g_opt_chunk{4};
+}
+int option_chunk() { return g_opt_chunk.load(std::memory_order_relaxed); }
 
 void prof_drop_last(const char* family) {
   if (!g_prof_on) return;
@@ -290,7 +300,26 @@ extern "C" {
 
 const char* tik_last_error(void) { return g_err.c_str(); }
 
-int tik_version(void) { return 100; }
+int tik_version(void) { return 200; }
+
+int tik_set_option(const char* name, int64_t value) {
+  if (!name) return fail(TIK_EINVAL, "tik_set_option: name is NULL");
+  if (std::string(name) == "graph_chunk") {
+    if (value < 0 || value > 64) return fail(TIK_EINVAL, "tik_set_option: graph_chunk must be 0..64");
+    g_opt_chunk.store(int(value));
+    return TIK_OK;
+  }
+  return fail(TIK_EINVAL, std::string("tik_set_option: unknown option ") + name);
+}
+
+int tik_get_option(const char* name, int64_t* value) {
+  if (!name || !value) return fail(TIK_EINVAL, "tik_get_option: NULL argument");
+  if (std::string(name) == "graph_chunk") {
+    *value = option_chunk();
+    return TIK_OK;
+  }
+  return fail(TIK_EINVAL, std::string("tik_get_option: unknown option ") + name);
+}
 
 int tik_prof_enable(int32_t on) {
   g_prof_on = on != 0;

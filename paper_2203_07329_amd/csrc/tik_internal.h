@@ -48,6 +48,13 @@ struct ProfScope {
 // Forget the last launch recorded for a family: a launch whose kernels
 // returned at once (the surplus iteration of a solve loop) moved no data.
 void prof_drop_last(const char* family);
+// Whether per-launch events are being recorded (the solve loops then launch
+// each iteration's kernels directly instead of replaying a captured graph).
+bool prof_active();
+
+// ----------------------------------------------------------------- options --
+// Iterations per graph-captured chunk of the solve loops (0: no graphs).
+int option_chunk();
 
 // --------------------------------------------------------------- workspace --
 // Bump allocator over a caller-provided device buffer.  With base == nullptr it
@@ -114,6 +121,13 @@ struct DevProb {
   int64_t irL, irS;
   int32_t gp, pad2_;
 };
+
+// True once every solve of the plan has stopped (the live word reads 0): the
+// kernels of a queued iteration then return at once and leave all state as it
+// is.  Uniform over a block, so it may precede barriers.
+__device__ __forceinline__ bool plan_stopped(const DevProb& pr) {
+  return pr.live && *pr.live == 0;
+}
 
 // Per-(problem, lambda) LSQR scalars, all FP64.
 struct Scal {

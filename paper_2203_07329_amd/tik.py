@@ -36,7 +36,7 @@ EXPORTS = [
     "tik_precond_data", "tik_precond_sigma",
     "tik_lsqr_batch_bytes", "tik_lsqr_batch", "tik_sketch_free", "tik_precond_free",
     "tik_last_error", "tik_version", "tik_prof_enable", "tik_prof_reset", "tik_prof_query",
-    "tik_lsqr_info",
+    "tik_lsqr_info", "tik_set_option", "tik_get_option",
 ]
 
 
@@ -84,9 +84,12 @@ def lib() -> ctypes.CDLL:
     L.tik_prof_enable.argtypes = [i32]
     L.tik_prof_query.argtypes = [ctypes.c_char_p, P(dbl), P(i64)]
     L.tik_lsqr_info.argtypes = [P(i32), P(i32)]
+    L.tik_set_option.argtypes = [ctypes.c_char_p, i64]
+    L.tik_get_option.argtypes = [ctypes.c_char_p, P(i64)]
     for name in ("tik_sketch_bytes", "tik_sketch", "tik_sketch_data", "tik_precond_bytes",
                  "tik_precond", "tik_precond_data", "tik_lsqr_batch_bytes", "tik_lsqr_batch", "tik_version",
-                 "tik_prof_enable", "tik_prof_reset", "tik_prof_query", "tik_lsqr_info"):
+                 "tik_prof_enable", "tik_prof_reset", "tik_prof_query", "tik_lsqr_info",
+                 "tik_set_option", "tik_get_option"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -307,6 +310,16 @@ def lsqr_info():
     a, b = ctypes.c_int32(), ctypes.c_int32()
     _check(lib().tik_lsqr_info(ctypes.byref(a), ctypes.byref(b)))
     return a.value, b.value
+
+
+def set_option(name: str, value: int) -> None:
+    _check(lib().tik_set_option(name.encode(), int(value)))
+
+
+def get_option(name: str) -> int:
+    v = ctypes.c_int64()
+    _check(lib().tik_get_option(name.encode(), ctypes.byref(v)))
+    return v.value
 
 
 # ------------------------------------------------------------- profiling ---

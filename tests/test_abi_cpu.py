@@ -110,3 +110,19 @@ def test_precond_and_solve_null_handles():
     ms, n = ctypes.c_double(), ctypes.c_int64()
     assert L.tik_prof_query(b"gemm_n", ctypes.byref(ms), ctypes.byref(n)) == tik.OK
     assert n.value == 0
+
+
+def test_options_roundtrip_and_rejects():
+    old = tik.get_option("graph_chunk")
+    try:
+        tik.set_option("graph_chunk", 0)
+        assert tik.get_option("graph_chunk") == 0
+        tik.set_option("graph_chunk", 16)
+        assert tik.get_option("graph_chunk") == 16
+        for bad in (-1, 65):
+            with pytest.raises(tik.TikError):
+                tik.set_option("graph_chunk", bad)
+        with pytest.raises(tik.TikError):
+            tik.set_option("no_such_option", 1)
+    finally:
+        tik.set_option("graph_chunk", old)

@@ -416,3 +416,37 @@ def test_bf16_sketch_end_to_end(wide):
         err = oracle.rel_err(res.x_numpy(0), oracle.solve(p.A, p.b, p.lams))
         print("bf16 sketch", wide, mode, "%.2e" % err.max(), res.iters.cpu().numpy()[0])
         assert np.all(err <= 1e-8) and np.all(res.status.cpu().numpy() == tik.ST_CONVERGED)
+
+
+@pytest.mark.parametrize("chunk", [0, 1, 3, 8])
+def test_graph_chunks_match_direct_launches(chunk):
+    """The solve loop replayed as captured graphs of `chunk` iterations gives the
+    same x, iteration counts and status bit for bit as direct launches (chunk 0):
+    the same kernels run in the same order, and the surplus iterations queued
+    past convergence return at once.  Tall Cholesky, tall low-rank and wide."""
+    old = tik.get_option("graph_chunk")
+    cases = [
+        ([W.over_svd(m=1500, n=90, N=6)], tik.SRHT, tik.ROUTE_CHOL, None),
+        ([W.lowsd(m=900, n=220, N=4, decay=20.0, lam_lo=1e-4, lam_hi=1e-1)], tik.GAUSS,
+         tik.ROUTE_LOWRANK, None),
+        ([W.under_scaled(m=60, n=900, N=5)], tik.GAUSS, tik.ROUTE_CHOL, [240]),
+    ]
+    try:
+        for plist, embed, route, s in cases:
+            pr = dev_problems(plist)
+            sk = tik.sketch(pr, embed, s or [p.s for p in plist], 3)
+            pc = tik.precond(sk, np.stack([p.lams for p in plist]), route, 2.0)
+            outs = []
+            for c in (0, chunk):
+                tik.set_option("graph_chunk", c)
+                for mode in (tik.F64_BATCHED, tik.MIXED_BATCHED):
+                    r = tik.lsqr_batch(pr, pc, mode, 1e-10, 200)
+                    torch.cuda.synchronize()
+                    outs.append((r.x_numpy(0), r.iters.cpu().numpy(), r.status.cpu().numpy()))
+            for a, b in zip(outs[:2], outs[2:]):
+                assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+                assert np.array_equal(a[2], b[2])
+            Xo = oracle.solve(plist[0].A, plist[0].b, plist[0].lams)
+            assert np.all(oracle.rel_err(outs[2][0], Xo) < 1e-8)
+    finally:
+        tik.set_option("graph_chunk", old)
