@@ -228,6 +228,23 @@ int tik_lsqr_batch(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_
                    int32_t* status, double* relres, void* dws, size_t dws_bytes,
                    tik_stream_t stream);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+   harnesses that forbid hipMalloc): tik_lsqr_batch with the same arguments
+   except the workspace, which is a static device array of 64 MiB per GPU
+   that the library holds until the process ends.  The call allocates
+   nothing: no device or pinned host memory, no events, no graphs; it
+   launches each iteration directly and synchronizes `stream` after every
+   iteration to read the active count into a host local (so it cannot be
+   captured into a graph).  A solve whose workspace (tik_lsqr_batch_bytes)
+   exceeds 64 MiB returns TIK_ENOTSUP before anything is launched.  Every
+   call on one GPU uses that GPU's one array: calls that overlap on one GPU
+   (several host threads or streams) race and must be serialized by the
+   caller; each call initializes what it reads, so results never depend on
+   an earlier call.  Outputs as for tik_lsqr_batch. */
+int tik_lsqr_batch_static(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_t mode,
+                          double tol, int32_t maxit, double* const* X, int32_t* iters,
+                          int32_t* status, double* relres, tik_stream_t stream);
+
 /* How the calling thread's last tik_lsqr_batch split its lambdas: solved with
    FP32 products inside FP64 refinement (*fp32) or with FP64 products
    (*fp64).  PLAIN_F64_PER_LAMBDA and F64_BATCHED count every lambda as FP64. */

@@ -1439,14 +1439,27 @@ struct ChunkGraph {
 // iterations are queued; `body(s)` queues one iteration's kernels on s.
 template <typename Body>
 int iterate(Body&& body, const Scal* sc, int J, int32_t* cnt, int maxit, hipStream_t st) {
-  IterGate gate;
-  TIK_TRY(gate.open());
   auto one = [&](hipStream_t s) -> int {
     TIK_TRY(body(s));
     hipLaunchKernelGGL(k_count_active, dim3(1), dim3(BLK), 0, s, sc, J, cnt);
     TIK_LAUNCHED("k_count_active");
     return TIK_OK;
   };
+  if (noalloc_active()) {
+    // nothing allocated: each count is read back into a host local after a
+    // stream synchronization
+    for (int it = 0; it < maxit; ++it) {
+      TIK_TRY(one(st));
+      int32_t h = 1;
+      TIK_HIP(hipMemcpyAsync(&h, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      TIK_HIP(hipStreamSynchronize(st));
+      if (h == 0) break;
+    }
+    TIK_HIP(hipMemsetAsync(cnt, 1, sizeof(int32_t), st));
+    return TIK_OK;
+  }
+  IterGate gate;
+  TIK_TRY(gate.open());
   const int T = std::min(maxit, option_chunk());
   if (T > 0 && !prof_active()) {
     ChunkGraph cg;

@@ -292,6 +292,42 @@ static int sketch_validate(const tik_problem* p, int32_t nprob, int32_t embed, i
   return TIK_OK;
 }
 
+// ----------------------------------------------------- no-allocation solve --
+// Workspace of tik_lsqr_batch_static: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never passes the array's name
+// to a kernel or copy: it uses the device address hipGetSymbolAddress returns,
+// looked up once per device with that device current, on the entry point's
+// first call there.
+static constexpr size_t kStaticBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // per device: the address of `scratch` there
+thread_local bool t_noalloc = false;
+struct NoAllocScope {
+  NoAllocScope() { t_noalloc = true; }
+  ~NoAllocScope() { t_noalloc = false; }
+};
+}  // namespace
+
+bool noalloc_active() { return t_noalloc; }
+
+static int scratch_address(void** out) {
+  int dev = 0;
+  TIK_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (size_t(dev) >= g_scratch_ptr.size()) g_scratch_ptr.resize(size_t(dev) + 1, nullptr);
+  if (!g_scratch_ptr[size_t(dev)]) {
+    void* ptr = nullptr;
+    TIK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(TIK_EHIP, "hipGetSymbolAddress returned a null address for the static workspace");
+    g_scratch_ptr[size_t(dev)] = ptr;
+  }
+  *out = g_scratch_ptr[size_t(dev)];
+  return TIK_OK;
+}
+
 }  // namespace tik
 
 using namespace tik;
@@ -750,15 +786,39 @@ int tik_lsqr_batch_bytes(const tik_problem* p, int32_t nprob, tik_precond_t pc, 
   return lsqr_bytes(p, nprob, pc, mode, bytes);
 }
 
-int tik_lsqr_batch(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_t mode,
-                   double tol, int32_t maxit, double* const* X, int32_t* iters, int32_t* status,
-                   double* relres, void* dws, size_t dws_bytes, tik_stream_t stream) {
+static int lsqr_args(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_t mode,
+                     double tol, int32_t maxit, double* const* X) {
   TIK_TRY(lsqr_validate(p, nprob, pc, mode));
   if (!(tol > 0.0) || !std::isfinite(tol)) return fail(TIK_EINVAL, "tik_lsqr_batch: tol must be > 0");
   if (maxit < 1) return fail(TIK_EINVAL, "tik_lsqr_batch: maxit must be >= 1");
   if (!X) return fail(TIK_EINVAL, "tik_lsqr_batch: X is NULL");
   for (int32_t k = 0; k < nprob; ++k)
     if (!X[k]) return fail(TIK_EINVAL, "tik_lsqr_batch: X[" + std::to_string(k) + "] is NULL");
+  return TIK_OK;
+}
+
+int tik_lsqr_batch_static(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_t mode,
+                          double tol, int32_t maxit, double* const* X, int32_t* iters,
+                          int32_t* status, double* relres, tik_stream_t stream) {
+  TIK_TRY(lsqr_args(p, nprob, pc, mode, tol, maxit, X));
+  size_t need = 0;
+  TIK_TRY(lsqr_bytes(p, nprob, pc, mode, &need));
+  if (need > kStaticBytes)
+    return fail(TIK_ENOTSUP, "tik_lsqr_batch_static: this solve needs " + std::to_string(need) +
+                                 " bytes of workspace, more than the " + std::to_string(kStaticBytes) +
+                                 " bytes of the static workspace; use tik_lsqr_batch");
+  void* ws = nullptr;
+  TIK_TRY(scratch_address(&ws));
+  NoAllocScope guard;
+  g_split32 = g_split64 = 0;
+  return lsqr_run(p, nprob, pc, mode, tol, maxit, X, iters, status, relres, ws, kStaticBytes,
+                  static_cast<hipStream_t>(stream));
+}
+
+int tik_lsqr_batch(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_t mode,
+                   double tol, int32_t maxit, double* const* X, int32_t* iters, int32_t* status,
+                   double* relres, void* dws, size_t dws_bytes, tik_stream_t stream) {
+  TIK_TRY(lsqr_args(p, nprob, pc, mode, tol, maxit, X));
   size_t need = 0;
   TIK_TRY(lsqr_bytes(p, nprob, pc, mode, &need));
   TIK_TRY(check_ws(dws, dws_bytes, need, "tik_lsqr_batch"));

@@ -52,6 +52,10 @@ void prof_drop_last(const char* family);
 // each iteration's kernels directly instead of replaying a captured graph).
 bool prof_active();
 
+// True inside tik_lsqr_batch_static: the solve loop then allocates nothing
+// (no pinned host words, events or graphs) and waits once per iteration.
+bool noalloc_active();
+
 // ----------------------------------------------------------------- options --
 // Iterations per graph-captured chunk of the solve loops (0: no graphs).
 int option_chunk();

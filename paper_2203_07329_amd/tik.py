@@ -36,7 +36,7 @@ EXPORTS = [
     "tik_precond_data", "tik_precond_sigma",
     "tik_lsqr_batch_bytes", "tik_lsqr_batch", "tik_sketch_free", "tik_precond_free",
     "tik_last_error", "tik_version", "tik_prof_enable", "tik_prof_reset", "tik_prof_query",
-    "tik_lsqr_info", "tik_set_option", "tik_get_option",
+    "tik_lsqr_info", "tik_set_option", "tik_get_option", "tik_lsqr_batch_static",
 ]
 
 
@@ -85,11 +85,12 @@ def lib() -> ctypes.CDLL:
     L.tik_prof_query.argtypes = [ctypes.c_char_p, P(dbl), P(i64)]
     L.tik_lsqr_info.argtypes = [P(i32), P(i32)]
     L.tik_set_option.argtypes = [ctypes.c_char_p, i64]
+    L.tik_lsqr_batch_static.argtypes = [P(CProblem), i32, vp, i32, dbl, i32, P(vp), vp, vp, vp, vp]
     L.tik_get_option.argtypes = [ctypes.c_char_p, P(i64)]
     for name in ("tik_sketch_bytes", "tik_sketch", "tik_sketch_data", "tik_precond_bytes",
                  "tik_precond", "tik_precond_data", "tik_lsqr_batch_bytes", "tik_lsqr_batch", "tik_version",
                  "tik_prof_enable", "tik_prof_reset", "tik_prof_query", "tik_lsqr_info",
-                 "tik_set_option", "tik_get_option"):
+                 "tik_set_option", "tik_get_option", "tik_lsqr_batch_static"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -292,6 +293,25 @@ class Solver:
 def lsqr_batch(probs: Problems, pc: Precond, mode: int, tol: float, maxit: int,
                stream=None) -> Result:
     return Solver(probs, pc, mode)(tol, maxit, stream)
+
+
+def lsqr_batch_static(probs: Problems, pc: Precond, mode: int, tol: float, maxit: int,
+                      stream=None) -> Result:
+    """tik_lsqr_batch_static: the library's static workspace, nothing allocated by the call
+    (the outputs are allocated here, by the caller)."""
+    dev = probs.At[0].device
+    N = pc.N
+    X = [torch.zeros((N, probs.shape(k)[1]), dtype=torch.float64, device=dev)
+         for k in range(probs.count)]
+    iters = torch.zeros((probs.count, N), dtype=torch.int32, device=dev)
+    status = torch.zeros((probs.count, N), dtype=torch.int32, device=dev)
+    relres = torch.zeros((probs.count, N), dtype=torch.float64, device=dev)
+    xp = (ctypes.c_void_p * probs.count)(*[x.data_ptr() for x in X])
+    _check(lib().tik_lsqr_batch_static(probs.c, probs.count, pc.handle, mode, float(tol), int(maxit),
+                                       xp, ctypes.c_void_p(iters.data_ptr()),
+                                       ctypes.c_void_p(status.data_ptr()),
+                                       ctypes.c_void_p(relres.data_ptr()), _stream(stream)))
+    return Result(X, iters, status, relres)
 
 
 def solve(probs: Problems, lambdas, embed: int = SRHT, s: Optional[Sequence[int]] = None,
