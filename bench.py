@@ -267,6 +267,22 @@ def main() -> int:
         dtype = "f32+f64" if n32 > 0 else "f64"
     # what ran: a mixed call whose every lambda needed FP64 products is batched FP64
     ran = "mixed_batched" if (mode == tik.MIXED_BATCHED and n32 > 0) else "f64_batched"
+    # ---- L-curve of the timed step's solutions (Section 4.3): both norms in FP64 on
+    # the GPU (one pass over each A), the corner on the host; outside the timed region
+    lc = None
+    if lams.shape[1] >= 3:
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        xn_d, rn_d = tik.lcurve(pr, res.X)
+        b.record()
+        torch.cuda.synchronize()
+        xn_h, rn_h = xn_d.cpu().numpy(), rn_d.cpu().numpy()
+        corners = [tik.lcurve_corner(lams[k], xn_h[k], rn_h[k])[0] for k in range(len(plist))]
+        lc = {"ms": round(a.elapsed_time(b), 3), "corner_index": corners[0],
+              "corner_lambda": float(lams[0][corners[0]])}
+        if len(plist) > 1:
+            lc["corner_index_p50"] = float(np.percentile(corners, 50))
     Xs = [res.x_numpy(k) for k in range(len(plist))]
     iters = res.iters.cpu().numpy()
     status = res.status.cpu().numpy()
@@ -439,6 +455,7 @@ def main() -> int:
         "phases_ms_per_step": {k: round(v[0], 3) for k, v in fam.items()},
         "launches_per_step": {k: v[1] for k, v in fam.items()},
         "wall_s_timed": round(wall, 3),
+        "lcurve": lc,
     }
     # the FP64 legs: value counts solves within 1e-8 (the metric), value_f64 those
     # within the FP64 target 1e-10 that their tolerance is chosen for

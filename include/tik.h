@@ -250,6 +250,32 @@ int tik_lsqr_batch_static(const tik_problem* p, int32_t nprob, tik_precond_t pc,
    (*fp64).  PLAIN_F64_PER_LAMBDA and F64_BATCHED count every lambda as FP64. */
 int tik_lsqr_info(int32_t* fp32, int32_t* fp64);
 
+/* --------------------------------------------------------------- L-curve -- */
+
+/* Workspace bytes tik_lcurve needs for these problems. */
+int tik_lcurve_bytes(const tik_problem* p, int32_t nprob, size_t* bytes);
+
+/* The L-curve of Section 4.3 (Fig. 4): for every problem k and lambda i,
+   xnorm[k*N + i] = ||x_i||_2 and rnorm[k*N + i] = ||A_k x_i - b_k||_2, in FP64,
+   where x_i is column i of X[k] (device, n_k x N column-major, ld = n_k; what
+   tik_lsqr_batch writes).  One pass over each A serves up to 32 lambdas.
+   xnorm, rnorm: device double nprob x N (either may be NULL, not both).
+   All problems must share A's storage type.  Synchronizes the stream once
+   before returning. */
+int tik_lcurve(const tik_problem* p, int32_t nprob, int32_t N, double* const* X, double* xnorm,
+               double* rnorm, void* dws, size_t dws_bytes, tik_stream_t stream);
+
+/* Corner of an L-curve (Section 4.3; Hansen's maximum-curvature criterion):
+   on the curve (log rnorm, log xnorm) parametrized by t = log lambda with
+   lambda increasing, the signed curvature (x'y'' - x''y') / (x'^2 + y'^2)^(3/2)
+   from second-order three-point differences on the uneven grid; *corner is the
+   index (into the caller's order) of its largest value over the interior
+   points (the first one on ties).  Host arrays of N >= 3 entries: lambdas
+   positive, finite and distinct (any order), norms positive and finite;
+   curvature (host N, or NULL) receives the values, NaN at both ends. */
+int tik_lcurve_corner(const double* lambdas, const double* xnorm, const double* rnorm, int32_t N,
+                      int32_t* corner, double* curvature);
+
 /* Free the host structs (device workspaces belong to the caller). */
 void tik_sketch_free(tik_sketch_t sk);
 void tik_precond_free(tik_precond_t pc);

@@ -20,6 +20,8 @@ What it computes (each function cites the passage it follows):
   preconditioners of Algorithms 1-3 written out densely for small checks;
   ``lowrank_truncation`` the rank s_i each lambda keeps (Algorithm 3).
 * ``tikhonov.lsqr_iteration_bound`` and the Lemma 2.1 / Theorem 3.2 bounds.
+* ``tikhonov.lcurve_norms`` / ``lcurve_curvature`` / ``lcurve_corner``: the
+  L-curve of Section 4.3 and its maximum-curvature corner.
 * ``tikhonov.certify``: an a-posteriori bound on the forward error of a
   candidate solution that holds at any size; ``certify_planted`` sharpens it
   with the generator's planted factors (used at full size, where the direct
@@ -53,4 +55,7 @@ from .tikhonov import (  # noqa: F401
     rel_err,
     certify,
     certify_planted,
+    lcurve_norms,
+    lcurve_curvature,
+    lcurve_corner,
 )

@@ -199,6 +199,44 @@ def thm32_bound(eps: float) -> float:
 
 
 # ----------------------------------------------------------------------------
+# L-curve (Section 4.3, Fig. 4)
+
+def lcurve_norms(A: np.ndarray, b: np.ndarray, X: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """(||x_i||_2, ||A x_i - b||_2) for every column x_i of X: the two axes of the L-curve."""
+    A = _as_f64(A)
+    X = np.asarray(X, dtype=np.float64).reshape(A.shape[1], -1)
+    R = A @ X - np.asarray(b, dtype=np.float64).reshape(-1, 1)
+    return np.linalg.norm(X, axis=0), np.linalg.norm(R, axis=0)
+
+
+def lcurve_curvature(t: np.ndarray, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Signed curvature (x'y'' - x''y') / (x'^2 + y'^2)^(3/2) of the plane curve
+    (x(t), y(t)) at the interior sample points, t increasing, derivatives by the
+    second-order three-point differences of an uneven grid; NaN at both ends."""
+    t, x, y = (np.asarray(v, dtype=np.float64) for v in (t, x, y))
+    k = np.full(t.size, np.nan)
+    for j in range(1, t.size - 1):
+        h1, h2 = t[j] - t[j - 1], t[j + 1] - t[j]
+        d1 = np.array([-h2 / (h1 * (h1 + h2)), (h2 - h1) / (h1 * h2), h1 / (h2 * (h1 + h2))])
+        d2 = np.array([2.0 / (h1 * (h1 + h2)), -2.0 / (h1 * h2), 2.0 / (h2 * (h1 + h2))])
+        xs, ys = x[j - 1:j + 2], y[j - 1:j + 2]
+        x1, y1, x2, y2 = d1 @ xs, d1 @ ys, d2 @ xs, d2 @ ys
+        k[j] = (x1 * y2 - x2 * y1) / (x1 * x1 + y1 * y1) ** 1.5
+    return k
+
+
+def lcurve_corner(lams: np.ndarray, xnorm: np.ndarray, rnorm: np.ndarray) -> int:
+    """Index of the L-curve's corner (Section 4.3): the largest curvature of
+    (log ||A x - b||, log ||x||) as a function of log lambda (Hansen's
+    criterion), over the interior points, lambda taken in increasing order."""
+    lams = np.asarray(lams, dtype=np.float64)
+    order = np.argsort(lams, kind="stable")
+    k = lcurve_curvature(np.log(lams[order]), np.log(np.asarray(rnorm)[order]),
+                         np.log(np.asarray(xnorm)[order]))
+    return int(order[int(np.nanargmax(k))])
+
+
+# ----------------------------------------------------------------------------
 # A-posteriori certificate
 
 def _gradient(A: np.ndarray, b: np.ndarray, lams: np.ndarray, X: np.ndarray,

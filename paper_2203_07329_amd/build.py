@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtik.so")
 SOURCES = ["tik_api.hip", "k_sketch.hip", "k_factor.hip", "k_lsqr.hip", "k_lowrank.hip",
-           "k_mfma.hip", "k_mixed.hip"]
+           "k_mfma.hip", "k_mixed.hip", "k_lcurve.hip"]
 
 ARCH = "gfx950"
 FLAGS = [

@@ -827,6 +827,80 @@ int tik_lsqr_batch(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_
                   static_cast<hipStream_t>(stream));
 }
 
+// --------------------------------------------------------------- L-curve --
+int tik_lcurve_bytes(const tik_problem* p, int32_t nprob, size_t* bytes) {
+  if (!bytes) return fail(TIK_EINVAL, "tik_lcurve_bytes: bytes is NULL");
+  TIK_TRY(validate_problems(p, nprob, "tik_lcurve"));
+  return lcurve_bytes(p, nprob, bytes);
+}
+
+int tik_lcurve(const tik_problem* p, int32_t nprob, int32_t N, double* const* X, double* xnorm,
+               double* rnorm, void* dws, size_t dws_bytes, tik_stream_t stream) {
+  TIK_TRY(validate_problems(p, nprob, "tik_lcurve"));
+  if (N < 1) return fail(TIK_EINVAL, "tik_lcurve: N must be >= 1");
+  if (!X) return fail(TIK_EINVAL, "tik_lcurve: X is NULL");
+  for (int32_t k = 0; k < nprob; ++k)
+    if (!X[k]) return fail(TIK_EINVAL, "tik_lcurve: X[" + std::to_string(k) + "] is NULL");
+  if (!xnorm && !rnorm) return fail(TIK_EINVAL, "tik_lcurve: both outputs are NULL");
+  size_t need = 0;
+  TIK_TRY(lcurve_bytes(p, nprob, &need));
+  TIK_TRY(check_ws(dws, dws_bytes, need, "tik_lcurve"));
+  return lcurve_run(p, nprob, N, X, xnorm, rnorm, dws, dws_bytes, static_cast<hipStream_t>(stream));
+}
+
+int tik_lcurve_corner(const double* lambdas, const double* xnorm, const double* rnorm, int32_t N,
+                      int32_t* corner, double* curvature) {
+  if (!lambdas || !xnorm || !rnorm || !corner)
+    return fail(TIK_EINVAL, "tik_lcurve_corner: NULL argument");
+  if (N < 3) return fail(TIK_EINVAL, "tik_lcurve_corner: needs at least 3 lambdas");
+  std::vector<int> ord(static_cast<size_t>(N));
+  for (int j = 0; j < N; ++j) ord[size_t(j)] = j;
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return lambdas[a] < lambdas[b]; });
+  for (int j = 0; j < N; ++j) {
+    const int i = ord[size_t(j)];
+    if (!(lambdas[i] > 0.0) || !std::isfinite(lambdas[i]))
+      return fail(TIK_EINVAL, "tik_lcurve_corner: lambdas must be positive and finite");
+    if (j > 0 && !(lambdas[i] > lambdas[ord[size_t(j - 1)]]))
+      return fail(TIK_EINVAL, "tik_lcurve_corner: lambdas must be distinct");
+    if (!(xnorm[i] > 0.0) || !(rnorm[i] > 0.0) || !std::isfinite(xnorm[i]) || !std::isfinite(rnorm[i]))
+      return fail(TIK_EINVAL, "tik_lcurve_corner: norms must be positive and finite");
+  }
+  // the curve (log ||A x - b||, log ||x||) as a function of t = log lambda,
+  // lambda increasing; signed curvature (x' y'' - x'' y') / (x'^2 + y'^2)^(3/2)
+  // with second-order three-point differences on the uneven grid; the corner
+  // is its largest value over the interior points (Hansen's criterion)
+  const size_t nn = static_cast<size_t>(N);
+  std::vector<double> t(nn), cx(nn), cy(nn);
+  for (int j = 0; j < N; ++j) {
+    const int i = ord[size_t(j)];
+    t[size_t(j)] = std::log(lambdas[i]);
+    cx[size_t(j)] = std::log(rnorm[i]);
+    cy[size_t(j)] = std::log(xnorm[i]);
+  }
+  if (curvature)
+    for (int j = 0; j < N; ++j) curvature[j] = std::nan("");
+  int best = -1;
+  double kbest = 0.0;
+  for (int j = 1; j + 1 < N; ++j) {
+    const double h1 = t[size_t(j)] - t[size_t(j - 1)], h2 = t[size_t(j + 1)] - t[size_t(j)];
+    const double wm = -h2 / (h1 * (h1 + h2)), w0 = (h2 - h1) / (h1 * h2), wp = h1 / (h2 * (h1 + h2));
+    const double vm = 2.0 / (h1 * (h1 + h2)), v0 = -2.0 / (h1 * h2), vp = 2.0 / (h2 * (h1 + h2));
+    const double x1 = wm * cx[size_t(j - 1)] + w0 * cx[size_t(j)] + wp * cx[size_t(j + 1)];
+    const double y1 = wm * cy[size_t(j - 1)] + w0 * cy[size_t(j)] + wp * cy[size_t(j + 1)];
+    const double x2 = vm * cx[size_t(j - 1)] + v0 * cx[size_t(j)] + vp * cx[size_t(j + 1)];
+    const double y2 = vm * cy[size_t(j - 1)] + v0 * cy[size_t(j)] + vp * cy[size_t(j + 1)];
+    const double k = (x1 * y2 - x2 * y1) / std::pow(x1 * x1 + y1 * y1, 1.5);
+    if (curvature) curvature[ord[size_t(j)]] = k;
+    if (std::isfinite(k) && (best < 0 || k > kbest)) {
+      best = ord[size_t(j)];
+      kbest = k;
+    }
+  }
+  if (best < 0) return fail(TIK_EINVAL, "tik_lcurve_corner: the curve has no finite curvature");
+  *corner = best;
+  return TIK_OK;
+}
+
 int tik_lsqr_info(int32_t* fp32, int32_t* fp64) {
   if (!fp32 || !fp64) return fail(TIK_EINVAL, "tik_lsqr_info: NULL argument");
   last_split(fp32, fp64);

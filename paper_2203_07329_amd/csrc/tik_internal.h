@@ -224,6 +224,10 @@ struct LrBufs {       // projection partials, scaled projections, expansion part
 int launch_lr_apply(int nc, int stage, int tall, const DevProb* P, const LrItems& it, int N,
                     const double* src, const LrBufs& lb, double* q, double* v, double* w, double* x,
                     double* e, const Scal* sc, double* pn, int init, hipStream_t st);
+// L-curve norms (k_lcurve.hip)
+int lcurve_bytes(const tik_problem* p, int32_t nprob, size_t* bytes);
+int lcurve_run(const tik_problem* p, int32_t nprob, int32_t N, double* const* X, double* xnorm,
+               double* rnorm, void* dws, size_t dws_bytes, hipStream_t st);
 }  // namespace tik
 
 // ----------------------------------------------------------------- handles --

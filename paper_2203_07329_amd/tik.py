@@ -37,6 +37,7 @@ EXPORTS = [
     "tik_lsqr_batch_bytes", "tik_lsqr_batch", "tik_sketch_free", "tik_precond_free",
     "tik_last_error", "tik_version", "tik_prof_enable", "tik_prof_reset", "tik_prof_query",
     "tik_lsqr_info", "tik_set_option", "tik_get_option", "tik_lsqr_batch_static",
+    "tik_lcurve_bytes", "tik_lcurve", "tik_lcurve_corner",
 ]
 
 
@@ -85,12 +86,16 @@ def lib() -> ctypes.CDLL:
     L.tik_prof_query.argtypes = [ctypes.c_char_p, P(dbl), P(i64)]
     L.tik_lsqr_info.argtypes = [P(i32), P(i32)]
     L.tik_set_option.argtypes = [ctypes.c_char_p, i64]
+    L.tik_lcurve_bytes.argtypes = [P(CProblem), i32, P(sz)]
+    L.tik_lcurve.argtypes = [P(CProblem), i32, i32, P(vp), vp, vp, vp, sz, vp]
+    L.tik_lcurve_corner.argtypes = [P(dbl), P(dbl), P(dbl), i32, P(i32), P(dbl)]
     L.tik_lsqr_batch_static.argtypes = [P(CProblem), i32, vp, i32, dbl, i32, P(vp), vp, vp, vp, vp]
     L.tik_get_option.argtypes = [ctypes.c_char_p, P(i64)]
     for name in ("tik_sketch_bytes", "tik_sketch", "tik_sketch_data", "tik_precond_bytes",
                  "tik_precond", "tik_precond_data", "tik_lsqr_batch_bytes", "tik_lsqr_batch", "tik_version",
                  "tik_prof_enable", "tik_prof_reset", "tik_prof_query", "tik_lsqr_info",
-                 "tik_set_option", "tik_get_option", "tik_lsqr_batch_static"):
+                 "tik_set_option", "tik_get_option", "tik_lsqr_batch_static",
+                 "tik_lcurve_bytes", "tik_lcurve", "tik_lcurve_corner"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -323,6 +328,38 @@ def solve(probs: Problems, lambdas, embed: int = SRHT, s: Optional[Sequence[int]
     sk = sketch(probs, embed, s, seed, sketch_dtype)
     pc = precond(sk, lambdas, route, alpha)
     return lsqr_batch(probs, pc, mode, tol, maxit), pc
+
+
+def lcurve(probs: Problems, X: Sequence[torch.Tensor], stream=None):
+    """tik_lcurve: (xnorm, rnorm) device tensors (nprob, N) of the solutions X[k]
+    ((N, n_k) tensors as Result.X holds them: column-major n_k x N)."""
+    L = lib()
+    N = int(X[0].shape[0])
+    nb = ctypes.c_size_t()
+    _check(L.tik_lcurve_bytes(probs.c, probs.count, ctypes.byref(nb)))
+    dev = X[0].device
+    ws = _workspace(nb.value, dev)
+    xn = torch.zeros((probs.count, N), dtype=torch.float64, device=dev)
+    rn = torch.zeros((probs.count, N), dtype=torch.float64, device=dev)
+    xp = (ctypes.c_void_p * probs.count)(*[x.data_ptr() for x in X])
+    _check(L.tik_lcurve(probs.c, probs.count, N, xp, ctypes.c_void_p(xn.data_ptr()),
+                        ctypes.c_void_p(rn.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                        _stream(stream)))
+    return xn, rn
+
+
+def lcurve_corner(lambdas, xnorm, rnorm):
+    """tik_lcurve_corner on host arrays: (corner index, curvature array)."""
+    lam = np.ascontiguousarray(lambdas, dtype=np.float64)
+    xn = np.ascontiguousarray(xnorm, dtype=np.float64)
+    rn = np.ascontiguousarray(rnorm, dtype=np.float64)
+    n = lam.size
+    curv = np.empty(n, dtype=np.float64)
+    c = ctypes.c_int32()
+    P = ctypes.POINTER(ctypes.c_double)
+    _check(lib().tik_lcurve_corner(lam.ctypes.data_as(P), xn.ctypes.data_as(P), rn.ctypes.data_as(P),
+                                   n, ctypes.byref(c), curv.ctypes.data_as(P)))
+    return c.value, curv
 
 
 def lsqr_info():

@@ -3,6 +3,8 @@ the header declares, and rejects bad arguments before launching anything.
 Runs without a GPU (no call here reaches the HIP runtime)."""
 
 import ctypes
+
+import numpy as np
 import os
 import re
 
@@ -126,3 +128,37 @@ def test_options_roundtrip_and_rejects():
             tik.set_option("no_such_option", 1)
     finally:
         tik.set_option("graph_chunk", old)
+
+
+def test_lcurve_corner_host_routine_matches_oracle():
+    """tik_lcurve_corner (host C) against the oracle's corner and curvature: an
+    ellipse in log space and the L-curve of a Tikhonov problem, in any order."""
+    import oracle
+    import workloads as W
+    rng = np.random.default_rng(0)
+    t = np.sort(rng.uniform(-1.2, 1.2, 31))
+    cases = [(np.exp(t), np.exp(0.5 * np.sin(t)), np.exp(2.0 * np.cos(t)))]
+    p = W.over_svd(m=600, n=50, N=16, lam_lo=1e-12, lam_hi=1.0)
+    xn, rn = oracle.lcurve_norms(p.A, p.b, oracle.solve(p.A, p.b, p.lams))
+    cases.append((p.lams, xn, rn))
+    for lams, xn, rn in cases:
+        for perm in (np.arange(lams.size), rng.permutation(lams.size)):
+            c, curv = tik.lcurve_corner(lams[perm], xn[perm], rn[perm])
+            assert c == oracle.lcurve_corner(lams[perm], xn[perm], rn[perm])
+            order = np.argsort(lams[perm])
+            want = oracle.lcurve_curvature(np.log(lams[perm][order]), np.log(rn[perm][order]),
+                                           np.log(xn[perm][order]))
+            got = curv[order]
+            assert np.isnan(got[0]) and np.isnan(got[-1])
+            assert np.allclose(got[1:-1], want[1:-1], rtol=1e-12, atol=1e-12 * np.nanmax(np.abs(want)))
+
+
+def test_lcurve_corner_rejects_bad_input():
+    lam = np.array([1e-3, 1e-2, 1e-1, 1.0])
+    one = np.ones(4)
+    for args in [(lam[:2], one[:2], one[:2]),                       # fewer than 3
+                 (np.array([1e-3, 1e-2, 1e-2, 1.0]), one, one),    # repeated lambda
+                 (-lam, one, one),                                  # non-positive lambda
+                 (lam, np.array([1.0, 0.0, 1.0, 1.0]), one)]:       # zero norm
+        with pytest.raises(tik.TikError):
+            tik.lcurve_corner(*args)

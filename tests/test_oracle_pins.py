@@ -476,3 +476,56 @@ def test_certify_planted_bounds_the_true_error():
         assert np.all(plain >= bnd * (1 - 1e-6))          # the planted bound is the sharper one
     bad = oracle.certify_planted(p.A, p.b, p.lams, Xp, 1.7 * p.sigma, p.V)
     assert np.all(bad >= true * (1 - 1e-6))
+
+
+# ---------------------------------------------------------------------------
+# L-curve (Section 4.3)
+
+def _ellipse(a=3.0, b=1.0, n=41, seed=0):
+    """Samples of (a cos t, b sin t) on an uneven grid of t in [-1.2, 1.2]."""
+    rng = np.random.default_rng(seed)
+    t = np.sort(rng.uniform(-1.2, 1.2, n))
+    return t, a * np.cos(t), b * np.sin(t)
+
+
+def test_lcurve_curvature_ellipse():
+    """Curvature of an ellipse traversed counter-clockwise: ab / (a^2 sin^2 t + b^2 cos^2 t)^(3/2),
+    largest at t = 0 when a > b; the three-point differences are second order."""
+    a, b = 3.0, 1.0
+    for n in (41, 161):
+        t, x, y = _ellipse(a, b, n)
+        k = oracle.lcurve_curvature(t, x, y)
+        exact = a * b / (a * a * np.sin(t) ** 2 + b * b * np.cos(t) ** 2) ** 1.5
+        assert np.isnan(k[0]) and np.isnan(k[-1])
+        h = np.max(np.diff(t))
+        assert np.max(np.abs(k[1:-1] - exact[1:-1]) / exact[1:-1]) < 40 * h * h, n
+        assert int(np.nanargmax(k)) == int(np.argmin(np.abs(t[1:-1]))) + 1
+    # clockwise traversal flips the sign
+    t, x, y = _ellipse(a, b, 41)
+    assert np.all(oracle.lcurve_curvature(t, x, -y)[1:-1] < 0)
+
+
+def test_lcurve_corner_through_logs():
+    """lcurve_corner takes logs of lambda and of both norms: an ellipse in log space
+    has its corner where t = log lambda is closest to 0, whatever the input order."""
+    t, x, y = _ellipse(2.0, 0.5, 31, seed=4)
+    lams, rn, xn = np.exp(t), np.exp(x), np.exp(y)
+    want = int(np.argmin(np.abs(t[1:-1]))) + 1
+    assert oracle.lcurve_corner(lams, xn, rn) == want
+    perm = np.random.default_rng(1).permutation(t.size)
+    assert perm[oracle.lcurve_corner(lams[perm], xn[perm], rn[perm])] == want
+
+
+def test_lcurve_norms_closed_form():
+    """||x_lam||^2 = sum (sigma c / (sigma^2 + lam))^2 and ||A x_lam - b||^2 =
+    sum (lam c / (sigma^2 + lam))^2 + ||b - U U^T b||^2 with c = U^T b (SVD identity)."""
+    p = W.over_svd(m=600, n=50, N=9, lam_lo=1e-10, lam_hi=1e2)
+    X = oracle.solve(p.A, p.b, p.lams)
+    xn, rn = oracle.lcurve_norms(p.A, p.b, X)
+    c = p.U.T @ p.b
+    perp = np.linalg.norm(p.b - p.U @ c)
+    for i, lam in enumerate(p.lams):
+        d = p.sigma ** 2 + lam
+        xw = np.linalg.norm(p.sigma * c / d)
+        rw = math.sqrt(np.sum((lam * c / d) ** 2) + perp ** 2)
+        assert abs(xn[i] - xw) <= 1e-11 * xw and abs(rn[i] - rw) <= 1e-10 * rw, (lam, xn[i], xw, rn[i], rw)
