@@ -61,7 +61,10 @@ typedef enum {
   TIK_ST_NOTPD = 2,     /* chol(C + lam I) broke down: the paper assumes
                            kappa(C + lam I) < O(1/u) (Section 2.1); X is not written */
   TIK_ST_IR_STALL = 3,  /* mixed precision: refinement stopped contracting */
-  TIK_ST_NONFINITE = 4  /* NaN/Inf met in the data or the recurrence; X not written */
+  TIK_ST_NONFINITE = 4, /* NaN/Inf met in the data or the recurrence; X not written */
+  TIK_ST_QR = 5         /* tik_precond only: chol(C + lam I) broke down and R came
+                           from the Householder QR of [Y; sqrt(lam) I] instead (the
+                           BP2 preconditioner of Section 4.1); the lam is solved */
 } tik_status;
 
 typedef enum { TIK_F64 = 0, TIK_F32 = 1, TIK_BF16 = 2 } tik_dtype;
@@ -164,9 +167,15 @@ int tik_precond_bytes(tik_sketch_t sk, int32_t route, int32_t N, size_t* bytes);
    alpha    oversampling factor of Algorithm 3, >= 1 (ignored by TIK_ROUTE_CHOL);
    sd_hat   host nprob x N, or NULL: the statistical-dimension estimates
             (TIK_ROUTE_LOWRANK; NaN for TIK_ROUTE_CHOL);
-   status   host nprob x N, or NULL: TIK_ST_NOTPD where chol(C + lam I)
-            broke down, else TIK_ST_CONVERGED.
-   Synchronizes the stream once, to read the breakdown flags. */
+   status   host nprob x N, or NULL: TIK_ST_CONVERGED, TIK_ST_QR where
+            chol(C + lam I) broke down (a pivot not above chol_pivot_ulps *
+            2^-53 times its diagonal entry of C + lam I; by default not
+            positive) and R was built from the Householder QR of [Y; sqrt(lam) I]
+            instead (Section 4.1; this Gram-free factor exists however
+            ill-conditioned C + lam I is), or TIK_ST_NOTPD where that failed too
+            (non-finite data).
+   Synchronizes the stream once to read the breakdown flags, and once more
+   when some lambda took the QR fallback. */
 int tik_precond(tik_sketch_t sk, int32_t route, const double* lambdas, int32_t N,
                 double alpha, void* dws, size_t dws_bytes, tik_stream_t stream,
                 tik_precond_t* out, double* sd_hat, int32_t* status);
@@ -287,6 +296,12 @@ const char* tik_last_error(void);
 int tik_version(void);
 
 /* Process-wide options.
+   "chol_pivot_ulps"  tik_precond's Cholesky route treats a pivot d_j as a
+                  breakdown when d_j <= value * 2^-53 * (C + lam I)_jj, 0..2^53
+                  (default 0: only pivots that are not positive); such lambdas
+                  take the QR fallback (TIK_ST_QR).  A larger value sends the
+                  lambdas whose factorization lost that many ulps of a pivot
+                  to the Gram-free route.
    "graph_chunk"  LSQR iterations per graph-captured chunk of tik_lsqr_batch's
                   loop, 0..64 (0: no graphs, one host wait per iteration);
                   default 4.  Replays past convergence cost a few microseconds

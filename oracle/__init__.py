@@ -16,7 +16,8 @@ What it computes (each function cites the passage it follows):
   [A sqrt(lam) I] z = b (eq. regLLSunder) when m < n.
 * ``tikhonov.statistical_dimension`` (Definition 1) and ``sd_hat`` (the
   estimate from the sketch's singular values, Section 3.1.2).
-* ``tikhonov.chol_precond`` / ``lowrank_factors`` / ``lowrank_rinv``: the
+* ``tikhonov.chol_precond`` / ``bp2_precond`` (the QR route of Section 4.1)
+  / ``lowrank_factors`` / ``lowrank_rinv``: the
   preconditioners of Algorithms 1-3 written out densely for small checks;
   ``lowrank_truncation`` the rank s_i each lambda keeps (Algorithm 3).
 * ``tikhonov.lsqr_iteration_bound`` and the Lemma 2.1 / Theorem 3.2 bounds.
@@ -48,6 +49,7 @@ from .tikhonov import (  # noqa: F401
     lowrank_truncation,
     chol_precond,
     chol_precond_under,
+    bp2_precond,
     lsqr_iteration_bound,
     lemma21_bound,
     thm32_bound,

@@ -117,6 +117,16 @@ def chol_precond(Y: np.ndarray, lam: float) -> np.ndarray:
     return np.linalg.cholesky(C).T
 
 
+def bp2_precond(Y: np.ndarray, lam: float) -> np.ndarray:
+    """R of the Householder QR of [Y; sqrt(lam) I] with a positive diagonal (the BP2
+    preconditioner of Section 4.1): R^T R = Y^T Y + lam I without forming Y^T Y.
+    For Algorithm 2 pass Y^T (the wide mirror)."""
+    Y = _as_f64(Y)
+    k = Y.shape[1]
+    R = np.linalg.qr(np.vstack([Y, math.sqrt(lam) * np.eye(k)]), mode="r")
+    return R * np.sign(np.diag(R))[:, None]
+
+
 def chol_precond_under(Y: np.ndarray, lam: float) -> np.ndarray:
     """Upper-triangular R with R^T R = Y Y^T + lam I_m (Algorithm 2, steps 3-4)."""
     Y = _as_f64(Y)

@@ -228,9 +228,10 @@ __global__ void __launch_bounds__(256) k_potrf_diag(const CholJob* __restrict__ 
       a[p][q] = (i < kb && j < kb && i <= j) ? Rm[(k0 + i) + (k0 + j) * n] : 0.0;
       b[p][q] = (i == j && i < kb) ? 1.0 : 0.0;
     }
-  // factorization
+  // factorization (skipped when the job holds a factor already)
 #pragma unroll
   for (int P = 0; P < 4; ++P) {
+    if (J.given) break;
     for (int kk = 0; kk < 16; ++kk) {
       const int k = 16 * P + kk;
       if (k >= kb) break;
@@ -257,18 +258,27 @@ __global__ void __launch_bounds__(256) k_potrf_diag(const CholJob* __restrict__ 
         }
     }
   }
-  // pivots: sqrt(a_ii), breakdown flag
+  // pivots: sqrt(a_ii), breakdown flag (a given factor: its own diagonal)
   if (ti == tj) {
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const int i = ti + 16 * p;
       if (i < kb) {
         double d = a[p][p];
-        if (!(d > 0.0) || !isfinite(d)) {
-          bad = 1;
-          d = 1.0;
+        if (J.given) {
+          if (!(d != 0.0) || !isfinite(d)) {
+            bad = 1;
+            d = 1.0;
+          }
+          diag[i] = d;
+        } else {
+          const double fl = J.dg ? J.floor * J.dg[k0 + i] : 0.0;
+          if (!(d > fl) || !isfinite(d)) {
+            bad = 1;
+            d = 1.0;
+          }
+          diag[i] = sqrt(d);
         }
-        diag[i] = sqrt(d);
       }
     }
   }
@@ -279,7 +289,7 @@ __global__ void __launch_bounds__(256) k_potrf_diag(const CholJob* __restrict__ 
     for (int q = 0; q < 4; ++q) {
       const int i = ti + 16 * p, j = tj + 16 * q;
       double v = 0.0;
-      if (i < kb && j < kb && i <= j) v = (i == j) ? diag[i] : a[p][q] / diag[i];
+      if (i < kb && j < kb && i <= j) v = J.given ? a[p][q] : ((i == j) ? diag[i] : a[p][q] / diag[i]);
       a[p][q] = v;
       if (i < kb && j < kb) Rm[(k0 + i) + (k0 + j) * n] = v;
     }
@@ -484,7 +494,22 @@ int launch_shift_copy(const double* C, int64_t n, const double* lams, int32_t nb
 // launch per kernel and panel for the whole table: panel kb covers the jobs
 // with n > kb NB (a prefix, the table being sorted by n), each grid sized for
 // the largest of them; blocks beyond a smaller job's tiles return at once.
-int launch_chol_inv_jobs(const CholJob* jobs, const int64_t* nsz, int32_t njobs, hipStream_t st) {
+__global__ void k_save_diag(const CholJob* __restrict__ jobs) {
+  const CholJob J = jobs[blockIdx.y];
+  const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (J.dg && c < J.n) J.dg[c] = J.R[c + c * J.n];
+}
+
+int launch_save_diag(const CholJob* jobs, int32_t njobs, int64_t nmax, hipStream_t st) {
+  if (njobs <= 0) return TIK_OK;
+  hipLaunchKernelGGL(k_save_diag, dim3(unsigned(cdiv(nmax, 256)), unsigned(njobs)), dim3(256), 0, st,
+                     jobs);
+  TIK_LAUNCHED("k_save_diag");
+  return TIK_OK;
+}
+
+int launch_chol_inv_jobs(const CholJob* jobs, const int64_t* nsz, int32_t njobs, hipStream_t st,
+                         bool given) {
   if (njobs <= 0) return TIK_OK;
   const int64_t nmax = nsz[0];
   const int64_t nblk = cdiv(nmax, NB);
@@ -501,7 +526,7 @@ int launch_chol_inv_jobs(const CholJob* jobs, const int64_t* nsz, int32_t njobs,
       hipLaunchKernelGGL(k_potrf_diag, dim3(unsigned(na)), dim3(256), 0, st, jobs, k0);
       TIK_LAUNCHED("k_potrf_diag");
       const int64_t rest = nmax - k0 - std::min<int64_t>(NB, nmax - k0);
-      if (rest > 0) {
+      if (rest > 0 && !given) {
         const int32_t nr = active(k0 + NB);   // jobs with trailing columns
         const int nt = int(cdiv(rest, 64));
         hipLaunchKernelGGL(k_trsm_panel, dim3(unsigned(nt), unsigned(nr)), dim3(256), 0, st, jobs, k0);

@@ -20,6 +20,8 @@
 // the singular values per lambda.
 #include "tik_internal.h"
 
+#include <cmath>
+
 namespace tik {
 
 static constexpr int LR_NB = 32;      // Householder panel width
@@ -866,6 +868,49 @@ static int qr_apply_q(const double* Z, int64_t rows, int64_t cols, int64_t ldz, 
     TIK_LAUNCHED("k_lr_tmul");
     TIK_TRY(lr_zupd(rr, nb, c, w.Vc, rr, w.W2, Xr, ldx, st));
   }
+  return TIK_OK;
+}
+
+// ------------------------------------------------------ BP2 fallback -------
+// Z ((s + k) x k, ld s + k) = [Y; sqrt(lam) I_k], Y s x k (ld s).
+__global__ void k_bp2_stack(const double* __restrict__ Y, int64_t s, int64_t k, double sq,
+                            double* __restrict__ Z) {
+  const int64_t rows = s + k;
+  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < rows * k;
+       e += int64_t(gridDim.x) * 256) {
+    const int64_t r = e % rows, c = e / rows;
+    Z[e] = r < s ? Y[r + c * s] : (r - s == c ? sq : 0.0);
+  }
+}
+
+// R (k x k, ld k) = the upper triangle of Z's leading k x k block, zeros below.
+__global__ void k_bp2_take_r(const double* __restrict__ Z, int64_t ldz, int64_t k,
+                             double* __restrict__ R) {
+  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < k * k; e += int64_t(gridDim.x) * 256) {
+    const int64_t r = e % k, c = e / k;
+    R[e] = r <= c ? Z[r + c * ldz] : 0.0;
+  }
+}
+
+size_t bp2_scratch_doubles(int64_t s, int64_t k) {
+  return size_t((s + k) * k) + qr_ws_doubles(s + k, k) + 64;
+}
+
+// R with R^T R = Y^T Y + lam I from the Householder QR of [Y; sqrt(lam) I]
+// (the BP2 preconditioner of Section 4.1; R's diagonal may carry either sign,
+// which R^{-1} absorbs).  The Gram matrix is never formed, so the factor
+// exists however ill-conditioned Y^T Y + lam I is.
+int launch_bp2_r(const double* Y, int64_t s, int64_t k, double lam, double* R, double* scratch,
+                 hipStream_t st) {
+  ProfScope ps("bp2", st);
+  const int64_t rows = s + k;
+  double* Z = scratch;
+  const QrWs w = qr_ws_carve(Z + rows * k, rows, k);
+  hipLaunchKernelGGL(k_bp2_stack, dim3(lr_grid(rows * k)), dim3(256), 0, st, Y, s, k, std::sqrt(lam), Z);
+  TIK_LAUNCHED("k_bp2_stack");
+  TIK_TRY(qr_factor(Z, rows, k, rows, w, st));
+  hipLaunchKernelGGL(k_bp2_take_r, dim3(lr_grid(k * k)), dim3(256), 0, st, Z, rows, k, R);
+  TIK_LAUNCHED("k_bp2_take_r");
   return TIK_OK;
 }
 

@@ -72,8 +72,10 @@ bool prof_active() { return g_prof_on; }
 // ---------------------------------------------------------------- options --
 namespace {
 std::atomic<int> g_opt_chunk{4};
+std::atomic<int64_t> g_opt_pivot{0};
 }
 int option_chunk() { return g_opt_chunk.load(std::memory_order_relaxed); }
+int64_t option_pivot_ulps() { return g_opt_pivot.load(std::memory_order_relaxed); }
 
 void prof_drop_last(const char* family) {
   if (!g_prof_on) return;
@@ -345,6 +347,12 @@ int tik_set_option(const char* name, int64_t value) {
     g_opt_chunk.store(int(value));
     return TIK_OK;
   }
+  if (std::string(name) == "chol_pivot_ulps") {
+    if (value < 0 || value > (int64_t(1) << 53))
+      return fail(TIK_EINVAL, "tik_set_option: chol_pivot_ulps must be 0..2^53");
+    g_opt_pivot.store(value);
+    return TIK_OK;
+  }
   return fail(TIK_EINVAL, std::string("tik_set_option: unknown option ") + name);
 }
 
@@ -352,6 +360,10 @@ int tik_get_option(const char* name, int64_t* value) {
   if (!name || !value) return fail(TIK_EINVAL, "tik_get_option: NULL argument");
   if (std::string(name) == "graph_chunk") {
     *value = option_chunk();
+    return TIK_OK;
+  }
+  if (std::string(name) == "chol_pivot_ulps") {
+    *value = option_pivot_ulps();
     return TIK_OK;
   }
   return fail(TIK_EINVAL, std::string("tik_get_option: unknown option ") + name);
@@ -515,7 +527,9 @@ struct PrecondPlan {
   // Cholesky route: one job per (problem, lambda), sorted by size, largest first
   std::vector<CholJob> jobs;
   std::vector<int64_t> jobn;
+  std::vector<int32_t> jobq;      // (problem, lambda) index k * N + i of each job
   CholJob* jobs_dev = nullptr;
+  double* bp2 = nullptr;          // QR scratch of the breakdown fallback (largest problem)
   double* colsum = nullptr;   // scratch, kmax
   // low-rank route
   std::vector<double*> V, sigma, S;
@@ -571,20 +585,26 @@ int precond_plan(tik_sketch_t sk, int32_t route, int32_t N, Arena& a, PrecondPla
                      [&](int32_t x, int32_t y) { return kdim(x) > kdim(y); });
     pp.jobs.clear();
     pp.jobn.clear();
+    pp.jobq.clear();
+    size_t bp2 = 0;
     for (int32_t k : order) {
       const int64_t kd = kdim(k);
+      bp2 = std::max(bp2, bp2_scratch_doubles(sk->yrows[size_t(k)], kd));
       for (int32_t i = 0; i < N; ++i) {
-        CholJob j;
+        CholJob j = {};
         j.R = pp.Rinv[size_t(k)] + size_t(i) * size_t(kd) * size_t(kd);
         j.Dinv = a.take<double>(size_t(cdiv(kd, 64)) * 64 * 64);
         j.Tmp = a.take<double>(size_t(kd) * 64);
         j.notpd = pp.notpd + size_t(k) * size_t(N) + size_t(i);
         j.n = kd;
+        j.dg = a.take<double>(size_t(kd));
         pp.jobs.push_back(j);
         pp.jobn.push_back(kd);
+        pp.jobq.push_back(k * N + i);
       }
     }
     pp.jobs_dev = a.take<CholJob>(pp.jobs.size());
+    pp.bp2 = a.take<double>(bp2);
   } else {
     pp.lr_scratch = a.take<double>(scratch);
     pp.perm = a.take<int32_t>(size_t(smax));
@@ -709,8 +729,12 @@ int tik_precond(tik_sketch_t sk, int32_t route, const double* lambdas, int32_t N
     }
     TIK_TRY(lanes.join());
     // every (problem, lambda) factored and inverted together, panel by panel
+    const double floor = double(option_pivot_ulps()) * std::ldexp(1.0, -53);
+    for (auto& j : pp.jobs) j.floor = floor;
     TIK_HIP(hipMemcpyAsync(pp.jobs_dev, pp.jobs.data(), pp.jobs.size() * sizeof(CholJob),
                            hipMemcpyHostToDevice, st));
+    if (floor > 0.0)
+      TIK_TRY(launch_save_diag(pp.jobs_dev, int32_t(pp.jobs.size()), pp.jobn.empty() ? 0 : pp.jobn[0], st));
     TIK_TRY(launch_chol_inv_jobs(pp.jobs_dev, pp.jobn.data(), int32_t(pp.jobs.size()), st));
     std::vector<int32_t> bad(size_t(np) * size_t(N), 0);
     std::vector<double> cn(size_t(np), 0.0);
@@ -721,10 +745,51 @@ int tik_precond(tik_sketch_t sk, int32_t route, const double* lambdas, int32_t N
     h->Rinv = pp.Rinv;
     h->cnorm = cn;
     h->status.resize(bad.size());
+    h->qr.assign(bad.size(), 0);
     for (size_t q = 0; q < bad.size(); ++q) h->status[q] = bad[q] ? TIK_ST_NOTPD : TIK_ST_CONVERGED;
     h->sdhat.assign(bad.size(), std::nan(""));
+    // Breakdown fallback (the BP2 preconditioner of Section 4.1): for every
+    // (problem, lambda) whose Cholesky factorization broke down, R from the
+    // Householder QR of [Y; sqrt(lambda) I], which never forms the Gram matrix,
+    // then its inverse; all of them inverted in one batched pass
+    std::vector<CholJob> fb;
+    std::vector<int64_t> fbn;
+    std::vector<int32_t> fbq;
+    for (size_t jx = 0; jx < pp.jobs.size(); ++jx) {
+      const int32_t q = pp.jobq[jx];
+      if (!bad[size_t(q)]) continue;
+      const int32_t k = q / N;
+      const double lam = h->lams[size_t(q)];
+      if (!(lam > 0.0) || !std::isfinite(lam)) continue;
+      CholJob j = pp.jobs[jx];
+      TIK_TRY(launch_bp2_r(sk->Y[size_t(k)], sk->yrows[size_t(k)], j.n, lam, j.R, pp.bp2, st));
+      j.given = 1;
+      j.dg = nullptr;
+      fb.push_back(j);
+      fbn.push_back(j.n);
+      fbq.push_back(q);
+    }
+    if (!fb.empty()) {
+      // jobs of one problem are contiguous and the table is sorted by size:
+      // the fallback subset keeps that order
+      TIK_HIP(hipMemsetAsync(pp.notpd, 0, sizeof(int32_t) * size_t(np) * size_t(N), st));
+      TIK_HIP(hipMemcpyAsync(pp.jobs_dev, fb.data(), fb.size() * sizeof(CholJob), hipMemcpyHostToDevice, st));
+      TIK_TRY(launch_chol_inv_jobs(pp.jobs_dev, fbn.data(), int32_t(fb.size()), st, true));
+      TIK_HIP(hipMemcpyAsync(bad.data(), pp.notpd, sizeof(int32_t) * bad.size(),
+                             hipMemcpyDeviceToHost, st));
+      TIK_HIP(hipStreamSynchronize(st));
+      for (int32_t q : fbq)
+        if (!bad[size_t(q)]) {
+          h->status[size_t(q)] = TIK_ST_CONVERGED;
+          h->qr[size_t(q)] = 1;
+        }
+    }
   }
-  if (status) std::memcpy(status, h->status.data(), sizeof(int32_t) * h->status.size());
+  if (status) {
+    std::memcpy(status, h->status.data(), sizeof(int32_t) * h->status.size());
+    for (size_t q = 0; q < h->qr.size(); ++q)
+      if (h->qr[q]) status[q] = TIK_ST_QR;
+  }
   if (sd_hat) std::memcpy(sd_hat, h->sdhat.data(), sizeof(double) * h->sdhat.size());
   *out = h.release();
   return TIK_OK;

@@ -59,6 +59,9 @@ bool noalloc_active();
 // ----------------------------------------------------------------- options --
 // Iterations per graph-captured chunk of the solve loops (0: no graphs).
 int option_chunk();
+// A Cholesky pivot d_j counts as a breakdown when d_j <= ulps * 2^-53 * (the
+// j-th diagonal entry of C + lambda I); 0: only non-positive pivots.
+int64_t option_pivot_ulps();
 
 // --------------------------------------------------------------- workspace --
 // Bump allocator over a caller-provided device buffer.  With base == nullptr it
@@ -183,19 +186,36 @@ int launch_gram_norm_bound(const double* C, int64_t n, double* scratch, double* 
 // C + lambda I on entry and the upper triangle of chol(C + lambda I)^{-1} on
 // exit; Dinv (ceil(n / 64) blocks of 64 x 64) and Tmp (n x 64) are its
 // scratch; *notpd is set to 1 on breakdown.
+// given = 1: R already holds an upper-triangular factor (the QR route of a
+// breakdown); only its inverse is formed.  dg (n values, or null): the
+// diagonal of C + lambda I saved before the factorization; a pivot d_j counts
+// as a breakdown when d_j <= floor * dg[j] (floor = 0: only non-positive or
+// non-finite pivots).
 struct CholJob {
   double* R;
   double* Dinv;
   double* Tmp;
   int32_t* notpd;
   int64_t n;
+  double* dg;
+  double floor;
+  int32_t given, pad_;
 };
 // R_j <- C + lams[j] I for the nb_mat lambdas of one problem (R_j at R + j n^2).
 int launch_shift_copy(const double* C, int64_t n, const double* lams, int32_t nb_mat, double* R,
                       hipStream_t st);
 // Factor and invert every job of the table (device memory), sorted by n,
 // largest first; nsz[i] is the n of job i on the host (same order).
-int launch_chol_inv_jobs(const CholJob* jobs, const int64_t* nsz, int32_t njobs, hipStream_t st);
+// given: the jobs hold triangular factors already; only invert them.
+int launch_chol_inv_jobs(const CholJob* jobs, const int64_t* nsz, int32_t njobs, hipStream_t st,
+                         bool given = false);
+// dg of every job <- the diagonal of its R (C + lambda I before factoring).
+int launch_save_diag(const CholJob* jobs, int32_t njobs, int64_t nmax, hipStream_t st);
+// BP2 (Section 4.1): R (k x k, ld k; zeros below the diagonal) from the
+// Householder QR of [Y; sqrt(lam) I_k], Y the stored sketch (s x k, ld s).
+size_t bp2_scratch_doubles(int64_t s, int64_t k);
+int launch_bp2_r(const double* Y, int64_t s, int64_t k, double lam, double* R, double* scratch,
+                 hipStream_t st);
 
 // matrix-core products (k_mfma.hip)
 // rows: rows of A per gemm_n block (128 or 256); cols: columns per gemm_t block (64 or 128).
@@ -249,6 +269,7 @@ struct tik_precond_s {
   std::vector<int64_t> k;              // short dimension per problem
   std::vector<double*> Rinv;           // Cholesky route: N upper-triangular k x k inverses
   std::vector<int32_t> status;         // nprob * N breakdown flags (tik_status)
+  std::vector<uint8_t> qr;             // nprob * N: R came from the QR fallback
   std::vector<double> cnorm;           // per problem: upper bound on ||C||_2 of the sketch Gram
   // low-rank route: V k x s (ld k), sigma (s), S (N x s), truncation s_i
   std::vector<double*> V, sigma, S;

@@ -529,3 +529,27 @@ def test_lcurve_norms_closed_form():
         xw = np.linalg.norm(p.sigma * c / d)
         rw = math.sqrt(np.sum((lam * c / d) ** 2) + perp ** 2)
         assert abs(xn[i] - xw) <= 1e-11 * xw and abs(rn[i] - rw) <= 1e-10 * rw, (lam, xn[i], xw, rn[i], rw)
+
+
+def test_bp2_precond_matches_cholesky_and_survives_breakdown():
+    """BP2 (Section 4.1): R from the QR of [Y; sqrt(lam) I] equals chol(Y^T Y + lam I)
+    where that exists; where the Cholesky factorization of the Gram matrix breaks down
+    (kappa(C + lam I) beyond 1/u), the QR factor still exists and still preconditions
+    B = [A; sqrt(lam) I] to the Lemma 2.1 bound."""
+    from numpy.linalg import LinAlgError
+    rng = np.random.default_rng(7)
+    Y = rng.standard_normal((80, 30)) * np.logspace(0, -5, 30)
+    for lam in [1e-8, 1e-2]:
+        assert np.allclose(oracle.bp2_precond(Y, lam), oracle.chol_precond(Y, lam), rtol=1e-9,
+                           atol=1e-12 * np.abs(Y).max() ** 2)
+    A, UA, sig, V = _lowsd_problem(m=600, n=40, decay=40 / (10 * math.log(10)))   # sigma 1 .. ~1e-10
+    X = rng.standard_normal((160, 600)) / math.sqrt(160)
+    Y = X @ A
+    lam = 1e-24
+    with pytest.raises(LinAlgError):
+        oracle.chol_precond(Y, lam)
+    R = oracle.bp2_precond(Y, lam)
+    assert np.all(np.diag(R) > 0) and np.array_equal(R, np.triu(R))
+    B = np.vstack([A, math.sqrt(lam) * np.eye(40)])
+    k = _kappa(np.linalg.solve(R.T, B.T).T)
+    assert k <= oracle.lemma21_bound(X @ UA) * 1.01, k
