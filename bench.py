@@ -140,6 +140,103 @@ def pick_mode(tik, pr, cfg, svec, lams, alpha, want):
     return mode, (1e-11 if mode == tik.F64_BATCHED else 1e-8)
 
 
+def run_study(args, tik, W, torch) -> int:
+    """Embedding study of Section 4.2 (the comparison of Fig. 3) on the paper's kind of
+    matrix: for each embedding (SRHT, Gaussian, sparse with 1 or 8 nonzeros per column)
+    and sketch size on the Cholesky route, and for the low-rank route, the condition
+    number of the preconditioned matrix B R^{-1} per lambda, the LSQR iterations and the
+    time of each stage; unpreconditioned LSQR beside it.  kappa(B R^{-1}) is measured
+    from the downloaded preconditioner: W = A R^{-1} on the GPU, then the eigenvalues of
+    W^T W + lam R^{-T} R^{-1} on the host (well conditioned: the preconditioned Gram)."""
+    import math
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    p = W.decay50(m=args.study_m, n=args.study_n, N=args.study_N)
+    log(f"generated the {p.m} x {p.n} study matrix in {time.perf_counter() - t0:.1f}s")
+    pr = tik.Problems.from_numpy([p.A], [p.b], device=dev)
+    A_d = torch.from_numpy(np.ascontiguousarray(p.A)).to(dev)
+    n = p.n
+    lams = p.lams
+    sd = np.array([float(np.sum(1.0 / (1.0 + lam / p.sigma ** 2))) for lam in lams])
+    sdm = int(math.ceil(sd.max()))
+    cases = [("chol", "srht", 1, s) for s in (2 * n, 4 * n, 10 * n)]
+    cases += [("chol", "gauss", 1, s) for s in (2 * n, 4 * n)]
+    cases += [("chol", "sparse", 1, s) for s in (4 * n, 10 * n)]
+    cases += [("chol", "sparse", 8, 2 * n)]
+    cases += [("lowrank", "gauss", 1, min(n, 2 * sdm)), ("lowrank", "srht", 1, min(n, 10 * sdm))]
+    embeds = {"srht": tik.SRHT, "gauss": tik.GAUSS, "sparse": tik.SPARSE}
+    rows = []
+
+    def kappa_of(Rinv, lam):
+        R_d = torch.from_numpy(Rinv).to(dev)
+        Wm = A_d @ R_d
+        G = (Wm.T @ Wm + lam * (R_d.T @ R_d)).cpu().numpy()
+        ev = np.linalg.eigvalsh(0.5 * (G + G.T))
+        return float(math.sqrt(ev[-1] / ev[0])) if ev[0] > 0 else float("inf")
+
+    # one untimed pass of each kind first: module loading and first-call setup
+    for route, emb in (("chol", "srht"), ("chol", "gauss"), ("chol", "sparse"), ("lowrank", "gauss")):
+        sk = tik.sketch(pr, embeds[emb], [min(n, 2 * sdm) if route == "lowrank" else 2 * n], 1)
+        pc = tik.precond(sk, lams, tik.ROUTE_CHOL if route == "chol" else tik.ROUTE_LOWRANK, 2.0)
+        tik.lsqr_batch(pr, pc, tik.F64_BATCHED, args.study_tol, 2000)
+    torch.cuda.synchronize()
+    for route, emb, zeta, s in cases:
+        tik.set_option("sparse_nnz", zeta)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        sk = tik.sketch(pr, embeds[emb], [s], 1)
+        ev[1].record()
+        rt = tik.ROUTE_CHOL if route == "chol" else tik.ROUTE_LOWRANK
+        pc = tik.precond(sk, lams, rt, 2.0)
+        ev[2].record()
+        res = tik.lsqr_batch(pr, pc, tik.F64_BATCHED, args.study_tol, 2000)
+        ev[3].record()
+        torch.cuda.synchronize()
+        its = res.iters.cpu().numpy()[0].tolist()
+        kap = []
+        for i, lam in enumerate(lams):
+            if route == "chol":
+                Rinv = pc.data(0, i)
+            else:
+                V = pc.data(0, i)
+                sig = pc.sigma(0)[:V.shape[1]]
+                Sd = 1.0 - 1.0 / np.sqrt(1.0 + sig ** 2 / lam)
+                Rinv = (np.eye(n) - (V * Sd[None, :]) @ V.T) / math.sqrt(lam)
+            kap.append(round(kappa_of(Rinv, lam), 3))
+        row = {"route": route, "embedding": emb if emb != "sparse" else f"sparse{zeta}", "s": s,
+               "s_over_n": round(s / n, 2), "kappa_BRinv": kap, "iters": its,
+               "status_ok": bool(np.all(res.status.cpu().numpy() <= 1)),
+               "ranks": [pc.rank(0, i) for i in range(len(lams))] if route == "lowrank" else None,
+               "ms": {"sketch": round(ev[0].elapsed_time(ev[1]), 3), "precond": round(ev[1].elapsed_time(ev[2]), 3),
+                      "solve": round(ev[2].elapsed_time(ev[3]), 3)}}
+        rows.append(row)
+        log(f"{route:8s} {row['embedding']:8s} s={s:6d} kappa max {max(kap):9.3f} iters max {max(its):4d} "
+            f"ms {row['ms']}")
+        del sk, pc, res
+    tik.set_option("sparse_nnz", 1)
+    # unpreconditioned LSQR (scipy, on the host) for a few lambdas, capped
+    none = None
+    if args.study_none:
+        from scipy.sparse.linalg import lsqr
+        kB = [float(math.sqrt((p.sigma[0] ** 2 + lam) / (p.sigma[-1] ** 2 + lam))) for lam in lams]
+        pick = [0, len(lams) // 2, len(lams) - 1]
+        it_none = {}
+        for i in pick:
+            lam = float(lams[i])
+            out = lsqr(p.A, p.b, damp=math.sqrt(lam), atol=args.study_tol, btol=args.study_tol,
+                       iter_lim=args.study_none)
+            it_none[f"{lam:.1e}"] = int(out[2])
+        none = {"kappa_B": [round(k, 3) for k in kB], "iters_at": it_none, "iter_cap": args.study_none}
+        log(f"unpreconditioned: iterations {it_none} (cap {args.study_none})")
+    line = {"study": "embedding", "matrix": f"A = U diag(logspace(0, -50, {n})) V^T, {p.m} x {n}, FP64",
+            "lambdas": [float(v) for v in lams], "sd": [round(float(v), 1) for v in sd],
+            "tol": args.study_tol, "cases": rows, "unpreconditioned": none}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +257,14 @@ def main() -> int:
                     help="LSQR iterations per graph-captured chunk (library option; 0: no graphs)")
     ap.add_argument("--f64-tol", type=float, default=None,
                     help="LSQR tolerance of the FP64 legs (default: one that reaches 1e-10)")
+    ap.add_argument("--study", default=None, choices=["embedding"],
+                    help="run the embedding study (Section 4.2) instead of the benchmark")
+    ap.add_argument("--study-m", type=int, default=50000)
+    ap.add_argument("--study-n", type=int, default=1000)
+    ap.add_argument("--study-N", type=int, default=16)
+    ap.add_argument("--study-tol", type=float, default=1e-10)
+    ap.add_argument("--study-none", type=int, default=1000,
+                    help="iteration cap of the unpreconditioned LSQR runs (0: skip them)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of "
@@ -171,6 +276,8 @@ def main() -> int:
     import workloads as W
     from paper_2203_07329_amd import tik
 
+    if args.study:
+        return run_study(args, tik, W, torch)
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     if args.graph_chunk is not None:

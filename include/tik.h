@@ -72,8 +72,12 @@ typedef enum { TIK_F64 = 0, TIK_F32 = 1, TIK_BF16 = 2 } tik_dtype;
 /* embedding X (Section 2.1.1): subsampled randomized Hadamard transform
    X = sqrt(m'/s) S H D (H orthonormal Hadamard of order m' = 2^ceil(log2 m),
    A zero-padded to m' rows), or Gaussian with i.i.d. N(0, 1/s) entries so that
-   E[X^T X] = I, the scaling the embedding definition of Section 1.3 fixes. */
-typedef enum { TIK_SRHT = 0, TIK_GAUSS = 1 } tik_embed;
+   E[X^T X] = I, the scaling the embedding definition of Section 1.3 fixes, or
+   the sparse subspace embedding of Section 3.4 (tall problems): each column
+   of X has zeta nonzeros +-1/sqrt(zeta) (option "sparse_nnz", default 1) in
+   distinct random rows, one in each of zeta consecutive row blocks; its sketch
+   is X A up to the rounding order of its FP64 sums. */
+typedef enum { TIK_SRHT = 0, TIK_GAUSS = 1, TIK_SPARSE = 2 } tik_embed;
 
 /* preconditioner: Cholesky of the partly exact sketch (Algorithms 1, 2) or the
    low-rank factor R^{-1} = lam^{-1/2} (I - V S V^T) (eq. RinvOver, Algorithm 3) */
@@ -126,7 +130,7 @@ int tik_sketch_bytes(const tik_problem* p, int32_t nprob, int32_t embed,
    s x n; Algorithm 2 steps 1-2 for m < n: Y = A X, m x s).
    p[nprob]       host array of problem descriptors (copied into the handle;
                   the device buffers they point to are not);
-   embed          TIK_SRHT (m >= n only) or TIK_GAUSS;
+   embed          TIK_SRHT or TIK_SPARSE (m >= n only), or TIK_GAUSS;
    sketch_dtype   arithmetic of the sketch product: TIK_F64, or TIK_BF16 for
                   the Gaussian embedding on matrix cores (A and X rounded to
                   BF16, FP32 accumulation; the sketch only sets the
@@ -302,6 +306,8 @@ int tik_version(void);
                   take the QR fallback (TIK_ST_QR).  A larger value sends the
                   lambdas whose factorization lost that many ulps of a pivot
                   to the Gram-free route.
+   "sparse_nnz"   nonzeros per column of the sparse embedding, 1..16
+                  (default 1, the sparse subspace embedding of Section 3.4).
    "graph_chunk"  LSQR iterations per graph-captured chunk of tik_lsqr_batch's
                   loop, 0..64 (0: no graphs, one host wait per iteration);
                   default 4.  Replays past convergence cost a few microseconds

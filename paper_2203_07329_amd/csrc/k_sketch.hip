@@ -35,6 +35,7 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
 static constexpr uint32_t TAG_PERM = 0x5052504Du;   // row subset
 static constexpr uint32_t TAG_SIGN = 0x5349474Eu;   // random signs D
 static constexpr uint32_t TAG_GAUS = 0x47415553u;   // Gaussian entries
+static constexpr uint32_t TAG_SPAR = 0x53504152u;   // sparse embedding rows and signs
 
 __device__ __forceinline__ uint2 seed_key(uint64_t seed) {
   return make_uint2(uint32_t(seed), uint32_t(seed >> 32));
@@ -908,6 +909,80 @@ int launch_sketch_gemm_bf16(const void* Xc, int64_t s, int64_t kc, int64_t ldx, 
                        nz, count, Yacc, first);
     TIK_LAUNCHED("k_sketch_reduce");
   }
+  return TIK_OK;
+}
+
+// ------------------------------------------------------ sparse embedding ---
+// X (s x m) with zeta nonzeros per column, each +-1/sqrt(zeta): column i (row i
+// of A) puts nonzero t < zeta in a uniformly drawn row of the t-th of zeta
+// consecutive row blocks of X (block sizes differ by at most one), so the
+// zeta rows are distinct and every column of X has unit norm, E[X^T X] = I.
+// map[i zeta + t] = row | (sign bit 31).
+__global__ void __launch_bounds__(256) k_sparse_map(uint64_t seed, int64_t m, int64_t s, int zeta,
+                                                    int32_t* __restrict__ map) {
+  const uint2 key = seed_key(seed);
+  const int64_t bs = s / zeta, rem = s % zeta;
+  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < m * zeta; e += int64_t(gridDim.x) * 256) {
+    const int64_t i = e / zeta;
+    const int t = int(e % zeta);
+    const uint4 r = philox4x32_10(make_uint4(uint32_t(i), uint32_t(i >> 32) ^ (uint32_t(t) << 16), TAG_SPAR, 0u),
+                                  key);
+    const int64_t len = bs + (t < rem ? 1 : 0);
+    const int64_t start = int64_t(t) * bs + min<int64_t>(t, rem);
+    const int64_t row = start + int64_t((uint64_t(r.x) * uint64_t(len)) >> 32);
+    map[e] = int32_t(row) | int32_t((r.y & 1u) << 31);
+  }
+}
+
+// Y[:, c] = X A[:, c] for one column c per block: the column streams through
+// once (coalesced) and its entries are added into the s rows of Y kept in LDS.
+// The additions into one row arrive in no fixed order, so Y is X A up to the
+// rounding order of FP64 sums (X itself is fixed by the seed).
+// Rows of Y per block: larger sketches split Y's rows over several blocks per
+// column, each reading the column (the blocks of one column are adjacent).
+static constexpr int64_t SP_ROWS = 8192;
+
+template <typename TA>
+__global__ void __launch_bounds__(512) k_sparse_apply(const TA* __restrict__ A, int64_t m, int64_t lda,
+                                                      int64_t s, int zeta, int nr,
+                                                      const int32_t* __restrict__ map,
+                                                      double* __restrict__ Y) {
+  __shared__ double acc[SP_ROWS];
+  const int64_t c = blockIdx.x / nr;
+  const int64_t r0 = int64_t(blockIdx.x % nr) * SP_ROWS;
+  const int64_t rn = min<int64_t>(SP_ROWS, s - r0);
+  for (int64_t r = threadIdx.x; r < rn; r += 512) acc[r] = 0.0;
+  __syncthreads();
+  const TA* __restrict__ col = A + c * lda;
+  for (int64_t i = threadIdx.x; i < m; i += 512) {
+    const double a = double(col[i]);
+    for (int t = 0; t < zeta; ++t) {
+      const int32_t e = map[i * zeta + t];
+      const int64_t r = int64_t(e & 0x7fffffff) - r0;
+      if (r >= 0 && r < rn) atomicAdd(&acc[r], e < 0 ? -a : a);
+    }
+  }
+  __syncthreads();
+  const double sc = 1.0 / sqrt(double(zeta));
+  for (int64_t r = threadIdx.x; r < rn; r += 512) Y[r0 + r + c * s] = acc[r] * sc;
+}
+
+int launch_sparse_sketch(const void* A, int a_f32, int64_t m, int64_t n, int64_t lda, int64_t s,
+                         int zeta, uint64_t seed, int32_t* map, double* Y, hipStream_t st) {
+  ProfScope ps("sketch", st);
+  const int64_t tot = m * zeta;
+  hipLaunchKernelGGL(k_sparse_map, dim3(unsigned(std::min<int64_t>(cdiv(tot, 256), 65536))), dim3(256), 0, st,
+                     seed, m, s, zeta, map);
+  TIK_LAUNCHED("k_sparse_map");
+  const int nr = int(cdiv(s, SP_ROWS));
+  const dim3 g(unsigned(n * nr));
+  if (a_f32)
+    hipLaunchKernelGGL(k_sparse_apply<float>, g, dim3(512), 0, st, static_cast<const float*>(A), m, lda, s,
+                       zeta, nr, map, Y);
+  else
+    hipLaunchKernelGGL(k_sparse_apply<double>, g, dim3(512), 0, st, static_cast<const double*>(A), m, lda,
+                       s, zeta, nr, map, Y);
+  TIK_LAUNCHED("k_sparse_apply");
   return TIK_OK;
 }
 

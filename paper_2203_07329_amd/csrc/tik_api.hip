@@ -73,7 +73,9 @@ bool prof_active() { return g_prof_on; }
 namespace {
 std::atomic<int> g_opt_chunk{4};
 std::atomic<int64_t> g_opt_pivot{0};
+std::atomic<int> g_opt_nnz{1};
 }
+int option_sparse_nnz() { return g_opt_nnz.load(std::memory_order_relaxed); }
 int option_chunk() { return g_opt_chunk.load(std::memory_order_relaxed); }
 int64_t option_pivot_ulps() { return g_opt_pivot.load(std::memory_order_relaxed); }
 
@@ -234,7 +236,9 @@ static int sketch_plan(const tik_problem* p, int32_t nprob, int32_t embed, int32
     sp.yrows[k] = s[k];
     sp.ycols[k] = t ? p[k].n : p[k].m;
     sp.Y[k] = a.take<double>(size_t(s[k]) * size_t(sp.ycols[k]));
-    if (embed == TIK_SRHT) {
+    if (embed == TIK_SPARSE) {
+      rows_ints = std::max<int64_t>(rows_ints, p[k].m * int64_t(option_sparse_nnz()));
+    } else if (embed == TIK_SRHT) {
       const int kk = ilog2_ceil(p[k].m);
       const int bb = kk <= 13 ? kk : 13;
       rows_ints = std::max<int64_t>(rows_ints, s[k] + (int64_t(1) << (kk - bb)) + 1 +
@@ -271,8 +275,8 @@ static int sketch_plan(const tik_problem* p, int32_t nprob, int32_t embed, int32
 static int sketch_validate(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sdt,
                            const int64_t* s) {
   TIK_TRY(validate_problems(p, nprob, "tik_sketch"));
-  if (embed != TIK_SRHT && embed != TIK_GAUSS)
-    return fail(TIK_EINVAL, "tik_sketch: embed must be TIK_SRHT or TIK_GAUSS");
+  if (embed != TIK_SRHT && embed != TIK_GAUSS && embed != TIK_SPARSE)
+    return fail(TIK_EINVAL, "tik_sketch: embed must be TIK_SRHT, TIK_GAUSS or TIK_SPARSE");
   if (sdt != TIK_F64 && sdt != TIK_BF16)
     return fail(TIK_EINVAL, "tik_sketch: sketch_dtype must be TIK_F64 or TIK_BF16");
   if (sdt == TIK_BF16 && embed != TIK_GAUSS)
@@ -289,6 +293,14 @@ static int sketch_validate(const tik_problem* p, int32_t nprob, int32_t embed, i
       if (ilog2_ceil(p[k].m) > SRHT_MAX_K)
         return fail(TIK_ENOTSUP, "tik_sketch: SRHT needs m <= 2^18");
       if (s[k] > SRHT_MAX_S) return fail(TIK_ENOTSUP, "tik_sketch: SRHT needs s <= 16384");
+    }
+    if (embed == TIK_SPARSE) {
+      if (!tall(p[k]))
+        return fail(TIK_ENOTSUP, "tik_sketch: the sparse embedding is implemented for tall problems only");
+      if (s[k] < option_sparse_nnz())
+        return fail(TIK_EINVAL, "tik_sketch: the sparse embedding needs s >= its nonzeros per column");
+      if (p[k].m * int64_t(option_sparse_nnz()) >= (int64_t(1) << 31))
+        return fail(TIK_ENOTSUP, "tik_sketch: the sparse embedding needs m * nonzeros < 2^31");
     }
   }
   return TIK_OK;
@@ -347,6 +359,11 @@ int tik_set_option(const char* name, int64_t value) {
     g_opt_chunk.store(int(value));
     return TIK_OK;
   }
+  if (std::string(name) == "sparse_nnz") {
+    if (value < 1 || value > 16) return fail(TIK_EINVAL, "tik_set_option: sparse_nnz must be 1..16");
+    g_opt_nnz.store(int(value));
+    return TIK_OK;
+  }
   if (std::string(name) == "chol_pivot_ulps") {
     if (value < 0 || value > (int64_t(1) << 53))
       return fail(TIK_EINVAL, "tik_set_option: chol_pivot_ulps must be 0..2^53");
@@ -364,6 +381,10 @@ int tik_get_option(const char* name, int64_t* value) {
   }
   if (std::string(name) == "chol_pivot_ulps") {
     *value = option_pivot_ulps();
+    return TIK_OK;
+  }
+  if (std::string(name) == "sparse_nnz") {
+    *value = option_sparse_nnz();
     return TIK_OK;
   }
   return fail(TIK_EINVAL, std::string("tik_get_option: unknown option ") + name);
@@ -446,7 +467,10 @@ int tik_sketch(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sketc
     // problem k draws from its own stream of the generator
     const uint64_t pseed = seed ^ (uint64_t(uint32_t(k)) * 0x9E3779B97F4A7C15ull);
     const int f32 = q.a_dtype == TIK_F32;
-    if (embed == TIK_SRHT) {
+    if (embed == TIK_SPARSE) {
+      TIK_TRY(launch_sparse_sketch(q.A, f32, q.m, q.n, q.lda, s[k], option_sparse_nnz(), pseed,
+                                   sp.rows[ln], sp.Y[k], st));
+    } else if (embed == TIK_SRHT) {
       const int kk = ilog2_ceil(q.m);
       const int bb = kk <= 13 ? kk : 13;
       int32_t* rows = sp.rows[ln];

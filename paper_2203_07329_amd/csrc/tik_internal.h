@@ -62,6 +62,8 @@ int option_chunk();
 // A Cholesky pivot d_j counts as a breakdown when d_j <= ulps * 2^-53 * (the
 // j-th diagonal entry of C + lambda I); 0: only non-positive pivots.
 int64_t option_pivot_ulps();
+// Nonzeros per column of the sparse embedding (1..16).
+int option_sparse_nnz();
 
 // --------------------------------------------------------------- workspace --
 // Bump allocator over a caller-provided device buffer.  With base == nullptr it
@@ -177,6 +179,9 @@ int launch_sketch_gemm_bf16(const void* Xc, int64_t s, int64_t kc, int64_t ldx, 
                             int a_f32, int64_t lda, int64_t r0, int64_t ncol, int wide, float* Yacc,
                             int first, float* part, int64_t part_cap, hipStream_t st);
 int launch_f32_to_f64(const float* src, double* dst, int64_t count, hipStream_t st);
+// sparse embedding of a tall A (m x n): map holds m * zeta ints; Y s x n (ld s)
+int launch_sparse_sketch(const void* A, int a_f32, int64_t m, int64_t n, int64_t lda, int64_t s,
+                         int zeta, uint64_t seed, int32_t* map, double* Y, hipStream_t st);
 
 // factorization (k_factor.hip)
 int launch_syrk(const double* Z, int64_t K, int64_t n, int64_t ldz, double* C, hipStream_t st);

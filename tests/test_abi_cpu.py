@@ -162,3 +162,19 @@ def test_lcurve_corner_rejects_bad_input():
                  (lam, np.array([1.0, 0.0, 1.0, 1.0]), one)]:       # zero norm
         with pytest.raises(tik.TikError):
             tik.lcurve_corner(*args)
+
+
+def test_sparse_embedding_limits():
+    assert _bytes(_probs(m=1000, n=10), embed=tik.SPARSE, s=(40,))[0] == tik.OK
+    assert _bytes(_probs(m=10, n=100), embed=tik.SPARSE, s=(5,))[0] == tik.ENOTSUP   # wide
+    assert _bytes(_probs(m=1000, n=10), embed=tik.SPARSE, sdt=tik.BF16, s=(40,))[0] == tik.EINVAL
+    old = tik.get_option("sparse_nnz")
+    try:
+        tik.set_option("sparse_nnz", 8)
+        assert _bytes(_probs(m=1000, n=10), embed=tik.SPARSE, s=(7,))[0] == tik.EINVAL   # s < zeta
+        assert _bytes(_probs(m=1000, n=10), embed=tik.SPARSE, s=(8,))[0] == tik.OK
+        for bad in (0, 17):
+            with pytest.raises(tik.TikError):
+                tik.set_option("sparse_nnz", bad)
+    finally:
+        tik.set_option("sparse_nnz", old)

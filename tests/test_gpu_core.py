@@ -450,3 +450,81 @@ def test_graph_chunks_match_direct_launches(chunk):
             assert np.all(oracle.rel_err(outs[2][0], Xo) < 1e-8)
     finally:
         tik.set_option("graph_chunk", old)
+
+
+# ------------------------------------------------------- sparse embedding ---
+
+@pytest.mark.parametrize("zeta", [1, 4])
+def test_sparse_structure(zeta):
+    """Sketching the identity gives X itself (one term per entry): every column
+    has exactly zeta nonzeros +-1/sqrt(zeta), one in each of zeta consecutive row
+    blocks, so columns have unit norm and E[X^T X] = I; X is fixed by the seed."""
+    m, s = 1500, 61
+    old = tik.get_option("sparse_nnz")
+    tik.set_option("sparse_nnz", zeta)
+    try:
+        X = _extract_X(m, s, tik.SPARSE, seed=4)
+        X2 = _extract_X(m, s, tik.SPARSE, seed=4)
+        X3 = _extract_X(m, s, tik.SPARSE, seed=5)
+    finally:
+        tik.set_option("sparse_nnz", old)
+    assert np.array_equal(X, X2) and not np.array_equal(X, X3)
+    nz = X != 0
+    assert np.all(nz.sum(axis=0) == zeta)
+    assert np.allclose(np.abs(X[nz]), 1 / math.sqrt(zeta), rtol=0, atol=1e-16)
+    bs, rem = s // zeta, s % zeta
+    starts = [t * bs + min(t, rem) for t in range(zeta + 1)]
+    for t in range(zeta):
+        assert np.all(nz[starts[t]:starts[t + 1]].sum(axis=0) == 1)
+    assert np.allclose(np.linalg.norm(X, axis=0), 1.0, atol=1e-15)
+    G = X.T @ X
+    off = G[~np.eye(m, dtype=bool)]
+    assert abs(off.mean()) < 4 * off.std() / math.sqrt(off.size)
+    # signs are balanced and rows are used roughly uniformly
+    assert abs(np.mean(np.sign(X[nz]))) < 0.1
+    assert nz.sum(axis=1).max() <= 3 * m * zeta / s
+
+
+def _sparse_rows(m, s, seed, width=512):
+    """Row and sign of the single nonzero of each column of a one-nonzero sparse
+    X, read from sketches of column slices of the identity (X[:, j0:j1] = X I[:, j0:j1])."""
+    rows = np.empty(m, dtype=np.int64)
+    signs = np.empty(m)
+    for j0 in range(0, m, width):
+        w = min(width, m - j0)
+        I = np.zeros((m, w))
+        I[np.arange(j0, j0 + w), np.arange(w)] = 1.0
+        pr = tik.Problems.from_numpy([I], [np.ones(m)])
+        Xs = tik.sketch(pr, tik.SPARSE, [s], seed).Y(0)
+        assert np.all((Xs != 0).sum(axis=0) == 1)
+        rows[j0:j0 + w] = np.argmax(Xs != 0, axis=0)
+        signs[j0:j0 + w] = Xs[rows[j0:j0 + w], np.arange(w)]
+    return rows, signs
+
+
+@pytest.mark.parametrize("m,n,s,dtype", [(5000, 7, 300, np.float64), (4000, 5, 200, np.float32),
+                                         (20000, 3, 9000, np.float64)])
+def test_sparse_linear(m, n, s, dtype):
+    """Y_A = X A for the same seed, including s > 8192 (rows of Y split over blocks)."""
+    rows, signs = _sparse_rows(m, s, 7)
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((m, n)).astype(dtype)
+    pr = tik.Problems.from_numpy([A], [np.ones(m)])
+    Y = tik.sketch(pr, tik.SPARSE, [s], 7).Y(0)
+    ref = np.zeros((s, n))
+    np.add.at(ref, rows, signs[:, None] * A.astype(np.float64))
+    assert np.allclose(Y, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_sparse_sketch_solves():
+    p = W.over_svd()
+    for zeta, s in ((1, 8 * p.n), (8, 2 * p.n)):
+        tik.set_option("sparse_nnz", zeta)
+        try:
+            res, _ = _solve([p], tik.F64_BATCHED, embed=tik.SPARSE, s=[s], tol=1e-12)
+        finally:
+            tik.set_option("sparse_nnz", 1)
+        err = oracle.rel_err(res.x_numpy(0), oracle.solve(p.A, p.b, p.lams))
+        print("sparse zeta", zeta, "s", s, "iters", res.iters.cpu().numpy().max(), "err", err.max())
+        assert np.all(res.status.cpu().numpy() == tik.ST_CONVERGED)
+        assert np.all(err <= 1e-10)

@@ -20,6 +20,9 @@ mirror the five workloads of the benchmark plan:
                (m=100000, n=10000, decay=200, N=16 lambdas in [1e-4, 1e-1])
   ragged       many independent G_p diag(logspace(0,-6,n_p)) problems, FP32
                (256 problems, m_p ~ U[5000,50000], n_p ~ U[100,1000], 8 lambdas)
+  decay50      the embedding-study matrices of Section 4.2: A = U diag(sigma) V^T,
+               sigma logspaced 1 -> 1e-50, ||noise|| = 1e-3, lambdas 10 -> 1e-15,
+               FP64 (m=50000, n=1000)
 
 Every generator takes its sizes as arguments so tests can draw the same
 family at reduced size.  Seeds derive from numpy.random.SeedSequence(seed)
@@ -40,7 +43,8 @@ from typing import List, Optional
 
 import numpy as np
 
-FAMILY_IDS = {"over_svd": 0, "over_gauss": 1, "under_scaled": 2, "lowsd": 3, "ragged": 4}
+FAMILY_IDS = {"over_svd": 0, "over_gauss": 1, "under_scaled": 2, "lowsd": 3, "ragged": 4,
+              "decay50": 5}
 
 
 @dataclasses.dataclass
@@ -191,6 +195,24 @@ def lowsd(m: int = 100000, n: int = 10000, N: int = 16, seed: int = 0, decay: fl
         s = int(alpha * math.ceil(hint))
     return Problem("lowsd", A, b, lams, int(s), "gauss", "lowrank", tol, seed,
                    sigma=sigma, U=U, V=V, x0=x0, alpha=alpha)
+
+
+def decay50(m: int = 50000, n: int = 1000, N: int = 16, seed: int = 0, sig_lo: float = 1e-50,
+            lam_lo: float = 1e-15, lam_hi: float = 10.0, noise_norm: float = 1e-3) -> Problem:
+    """A = U diag(logspace(0, log10 sig_lo, n)) V^T with Haar U (m x n), V (n x n), FP64;
+    b = A x0 + eta with ||eta|| about noise_norm (the matrices of the paper's
+    experiments: orthogonal factors of Gaussians, singular values decaying from 1
+    to 1e-50, lambdas from 10 down to 1e-15)."""
+    ru, rv, rx, re = _rngs("decay50", seed, 4)
+    U = haar(ru, m, n)
+    V = haar(rv, n, n)
+    sigma = np.logspace(0, math.log10(sig_lo), n)
+    A = np.asfortranarray((U * sigma[None, :]) @ V.T)
+    x0 = rx.standard_normal(n)
+    b = A @ x0 + (noise_norm / math.sqrt(m)) * re.standard_normal(m)
+    lams = np.logspace(math.log10(lam_hi), math.log10(lam_lo), N)
+    return Problem("decay50", A, b, lams, 2 * n, "gauss", "chol", 1e-10, seed,
+                   sigma=sigma, U=U, V=V, x0=x0)
 
 
 def haar_from(g: np.ndarray) -> np.ndarray:
