@@ -60,38 +60,81 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def generate(name, W, dev):
+    """The problems of one named workload."""
+    gens = {"over_svd": lambda: [W.over_svd()], "over_gauss": lambda: [W.over_gauss()],
+            "under_scaled": lambda: [W.under_scaled()], "lowsd": lambda: [W.lowsd(device=dev)],
+            "ragged": lambda: W.ragged()}
+    if name not in gens:
+        raise SystemExit(f"unknown workload {name}")
+    return gens[name]()
+
+
+def workload_cfg(name, tik, plist):
+    """Settings (embedding, sketch precision, route, mode, description, check) of a workload."""
+    if name == "over_svd":
+        return dict(embed=tik.SRHT, sdt=tik.F64, route=tik.ROUTE_CHOL, mode="f64",
+                    desc="tall Haar SVD, sigma logspaced 1..1e-6: m=2000 n=100 N=10 lambda 1e-6..1, "
+                         "SRHT s=400, Cholesky route", check="full")
+    if name == "over_gauss":
+        return dict(embed=tik.SRHT, sdt=tik.F64, route=tik.ROUTE_CHOL, mode="auto",
+                    desc="tall Gaussian, sigma logspaced 1..1e-8: m=200000 n=2000 N=32 lambda "
+                         "1e-8..1e-1, SRHT s=8000, Cholesky route", check="full")
+    if name == "under_scaled":
+        return dict(embed=tik.GAUSS, sdt=tik.BF16, route=tik.ROUTE_CHOL, mode="auto",
+                    desc="wide A_ij = G_ij / j (FP32): m=2000 n=200000 N=32 lambda 1e-6..1, BF16 "
+                         "Gaussian s=8000, Cholesky route (Algorithm 2)", check="full")
+    if name == "lowsd":
+        return dict(embed=tik.GAUSS, sdt=tik.BF16, route=tik.ROUTE_LOWRANK, mode="auto",
+                    desc=f"tall U diag(exp(-i/200)) V^T (FP32): m=100000 n=10000 N=16 lambda "
+                         f"1e-4..1e-1, BF16 Gaussian s={plist[0].s}, low-rank route (Algorithm 3)",
+                    check="certify")
+    if name == "ragged":
+        return dict(embed=tik.GAUSS, sdt=tik.BF16, route=tik.ROUTE_CHOL, mode="auto",
+                    desc="256 tall Gaussian problems, sigma logspaced 1..1e-6 (FP32): m~U[5000,50000] "
+                         "n~U[100,1000] N=8 lambda 1e-6..1e-1, BF16 Gaussian s=4n_p, Cholesky route",
+                    check="full")
+    raise SystemExit(f"unknown workload {name}")
+
+
 def build_workload(name, tik, W, dev):
     """(problems, settings) of one named workload."""
-    if name == "over_svd":
-        plist = [W.over_svd()]
-        cfg = dict(embed=tik.SRHT, sdt=tik.F64, route=tik.ROUTE_CHOL, mode="f64",
-                   desc="tall Haar SVD, sigma logspaced 1..1e-6: m=2000 n=100 N=10 lambda 1e-6..1, "
-                        "SRHT s=400, Cholesky route", check="full")
-    elif name == "over_gauss":
-        plist = [W.over_gauss()]
-        cfg = dict(embed=tik.SRHT, sdt=tik.F64, route=tik.ROUTE_CHOL, mode="auto",
-                   desc=f"tall Gaussian, sigma logspaced 1..1e-8: m=200000 n=2000 N=32 lambda "
-                        f"1e-8..1e-1, SRHT s=8000, Cholesky route", check="full")
-    elif name == "under_scaled":
-        plist = [W.under_scaled()]
-        cfg = dict(embed=tik.GAUSS, sdt=tik.BF16, route=tik.ROUTE_CHOL, mode="auto",
-                   desc="wide A_ij = G_ij / j (FP32): m=2000 n=200000 N=32 lambda 1e-6..1, BF16 "
-                        "Gaussian s=8000, Cholesky route (Algorithm 2)", check="full")
-    elif name == "lowsd":
-        plist = [W.lowsd(device=dev)]
-        cfg = dict(embed=tik.GAUSS, sdt=tik.BF16, route=tik.ROUTE_LOWRANK, mode="auto",
-                   desc=f"tall U diag(exp(-i/200)) V^T (FP32): m=100000 n=10000 N=16 lambda "
-                        f"1e-4..1e-1, BF16 Gaussian s={plist[0].s}, low-rank route (Algorithm 3)",
-                   check="certify")
-    elif name == "ragged":
-        plist = W.ragged()
-        cfg = dict(embed=tik.GAUSS, sdt=tik.BF16, route=tik.ROUTE_CHOL, mode="auto",
-                   desc="256 tall Gaussian problems, sigma logspaced 1..1e-6 (FP32): m~U[5000,50000] "
-                        "n~U[100,1000] N=8 lambda 1e-6..1e-1, BF16 Gaussian s=4n_p, Cholesky route",
-                   check="full")
-    else:
-        raise SystemExit(f"unknown workload {name}")
-    return plist, cfg
+    plist = generate(name, W, dev)
+    return plist, workload_cfg(name, tik, plist)
+
+
+SAVED_FIELDS = ("A", "b", "lams", "sigma", "U", "V", "x0")
+
+
+def save_workload(path, plist):
+    """Problems as .npy files (array fields) plus meta.json (the scalar settings)."""
+    os.makedirs(path, exist_ok=True)
+    meta = []
+    for k, p in enumerate(plist):
+        d = {"name": p.name, "s": p.s, "embed": p.embed, "route": p.route, "tol": p.tol,
+             "seed": p.seed, "alpha": p.alpha, "arrays": []}
+        for f in SAVED_FIELDS:
+            v = getattr(p, f)
+            if v is not None:
+                np.save(os.path.join(path, f"{k}_{f}.npy"), v, allow_pickle=False)
+                d["arrays"].append(f)
+        meta.append(d)
+    with open(os.path.join(path, "meta.json"), "w") as fh:
+        json.dump(meta, fh)
+
+
+def load_workload(path, name, tik, W):
+    """Problems written by save_workload (arrays memory-mapped), with the workload's settings."""
+    with open(os.path.join(path, "meta.json")) as fh:
+        meta = json.load(fh)
+    plist = []
+    for k, d in enumerate(meta):
+        arrs = {f: np.load(os.path.join(path, f"{k}_{f}.npy"), mmap_mode="r", allow_pickle=False)
+                for f in d["arrays"]}
+        plist.append(W.Problem(d["name"], arrs["A"], np.asarray(arrs["b"]), np.asarray(arrs["lams"]), d["s"],
+                               d["embed"], d["route"], d["tol"], d["seed"], sigma=arrs.get("sigma"),
+                               U=arrs.get("U"), V=arrs.get("V"), x0=arrs.get("x0"), alpha=d["alpha"]))
+    return plist, workload_cfg(name, tik, plist)
 
 
 MAXIT = 300
@@ -257,6 +300,11 @@ def main() -> int:
                     help="LSQR iterations per graph-captured chunk (library option; 0: no graphs)")
     ap.add_argument("--f64-tol", type=float, default=None,
                     help="LSQR tolerance of the FP64 legs (default: one that reaches 1e-10)")
+    ap.add_argument("--save-inputs", default=None, metavar="DIR",
+                    help="generate the workload, write it to DIR as .npy files and exit (lets a "
+                         "profiled run load inputs made by an unprofiled process)")
+    ap.add_argument("--load-inputs", default=None, metavar="DIR",
+                    help="load the workload from DIR (written by --save-inputs) instead of generating it")
     ap.add_argument("--study", default=None, choices=["embedding"],
                     help="run the embedding study (Section 4.2) instead of the benchmark")
     ap.add_argument("--study-m", type=int, default=50000)
@@ -283,9 +331,17 @@ def main() -> int:
     if args.graph_chunk is not None:
         tik.set_option("graph_chunk", args.graph_chunk)
     t0 = time.perf_counter()
-    plist, cfg = build_workload(args.workload, tik, W, "cuda:0")
-    log(f"generated {len(plist)} problem(s), {sum(p.m * p.n for p in plist) / 1e6:.0f} M entries "
-        f"in {time.perf_counter() - t0:.1f}s")
+    if args.load_inputs:
+        plist, cfg = load_workload(args.load_inputs, args.workload, tik, W)
+        log(f"loaded {len(plist)} problem(s) from {args.load_inputs} in {time.perf_counter() - t0:.1f}s")
+    else:
+        plist, cfg = build_workload(args.workload, tik, W, "cuda:0")
+        log(f"generated {len(plist)} problem(s), {sum(p.m * p.n for p in plist) / 1e6:.0f} M entries "
+            f"in {time.perf_counter() - t0:.1f}s")
+    if args.save_inputs:
+        save_workload(args.save_inputs, plist)
+        log(f"saved to {args.save_inputs}")
+        return 0
     pr = tik.Problems.from_numpy([p.A for p in plist], [p.b for p in plist], device=dev)
     torch.cuda.synchronize()
     svec = [p.s for p in plist]

@@ -553,3 +553,13 @@ def test_bp2_precond_matches_cholesky_and_survives_breakdown():
     B = np.vstack([A, math.sqrt(lam) * np.eye(40)])
     k = _kappa(np.linalg.solve(R.T, B.T).T)
     assert k <= oracle.lemma21_bound(X @ UA) * 1.01, k
+
+
+def test_host_philox_known_answers_cpu():
+    """The tests' host Philox4x32-10 reproduces the published known-answer vectors."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from philox_ref import philox4x32_10
+    got = philox4x32_10(np.array([[0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344]], dtype=np.uint32),
+                        np.array([0xA4093822, 0x299F31D0], dtype=np.uint32))[0]
+    assert [int(v) for v in got] == [0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1]
