@@ -51,6 +51,8 @@ sys.path.insert(0, ROOT)
 METRIC = "λ-solves/s to 1e-8 rel err: mixed batched vs plain FP64; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFS = 2500.0   # MI355X dense BF16 matrix peak
+FP64_PEAK_TFS = 78.6     # MI355X FP64 matrix (and vector) peak
+FP32_PEAK_TFS = 157.3    # MI355X FP32 matrix peak
 TOL_ERR = 1e-8
 FAMILIES = ("sketch", "gram", "chol", "trinv", "lowrank", "lr_qr", "lr_sweep", "lr_q", "gemm_n",
             "gemm_t", "trmv", "trmv_t", "lr_apply", "vec", "residual")
@@ -403,6 +405,7 @@ def main() -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     ms_step = ev0.elapsed_time(ev1) / args.steps
+    launch_shape = tik.last_tiles()    # the product launch shape of the last solve group timed
     n32, n64 = tik.lsqr_info()
     # ---- profiled steps: the same steps with HIP events around every launch on the
     # library's stream (each iteration then launched directly), for kernel durations
@@ -548,6 +551,9 @@ def main() -> int:
     else:
         # V (k x s) read twice per application: projection and expansion
         per_launch["lr_apply"] = sum(2 * k * p.s * 8 for k, p in zip(kmin, plist))
+    # algorithmic flops per launch of the products: 2 m n N per problem (one product over A)
+    flops_launch = {"gemm_n": sum(2.0 * p.m * p.n * N for p in plist),
+                    "gemm_t": sum(2.0 * p.m * p.n * N for p in plist)}
     known = {k: v for k, v in fam.items() if k in per_launch}
     dom = max(known.items(), key=lambda kv: kv[1][0]) if known else None
     roof = None
@@ -558,6 +564,12 @@ def main() -> int:
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload, name),
                 "kernel": name, "avg_launch_ms": round(avg_ms, 4),
                 "algorithmic_bytes_per_launch": int(per_launch[name])}
+        if name in flops_launch:
+            # the same launches against the matrix-core peak of their arithmetic
+            pk = FP64_PEAK_TFS if (vb == 8) else FP32_PEAK_TFS
+            tf = flops_launch[name] / (avg_ms / 1000.0) / 1e12
+            roof["matrix_core"] = {"achieved": round(tf, 2), "peak": pk, "unit": "TFLOP/s",
+                                   "frac": round(tf / pk, 4), "flops_per_launch": flops_launch[name]}
 
     # ---- per-problem latency of a batch: every preconditioner is ready after the
     # sketch and preconditioner stages; a problem is done when its slowest lambda
@@ -602,6 +614,7 @@ def main() -> int:
                    "requested_mode": {tik.F64_BATCHED: "f64_batched", tik.MIXED_BATCHED: "mixed_batched"}[mode],
                    "tol": tol, "solves": nsolve, "graph_chunk": tik.get_option("graph_chunk")},
         "roofline": roof,
+        "launch_shape": launch_shape,
         "sketch_mfma": sketch_mfma,
         "cpu_baseline": cpu,
         "solves_ok": n_ok,

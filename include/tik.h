@@ -289,6 +289,40 @@ int tik_lcurve(const tik_problem* p, int32_t nprob, int32_t N, double* const* X,
 int tik_lcurve_corner(const double* lambdas, const double* xnorm, const double* rnorm, int32_t N,
                       int32_t* corner, double* curvature);
 
+/* ------------------------------------------------------------- tuning -- */
+
+/* Launch shapes of the two products over A (rows of A per A W block: 128 or
+   256; columns per A^T U block: 64 or 128; the number of product blocks a
+   batch is split into: 1024, 2048 or 4096) come from a table keyed by shape
+   class: orientation, FP32 storage, lambda slots per pass, log2 of the
+   largest m and of the largest n, and one / up to 16 / more problems.
+   Classes without an entry use fixed defaults.  The table file tuning.txt
+   beside the library is read on first use when present.  Tables change what
+   workspace a solve needs: query the *_bytes functions after tuning or
+   loading. */
+
+/* Workspace bytes tik_tune needs for these problems and preconditioner. */
+int tik_tune_bytes(const tik_problem* p, int32_t nprob, tik_precond_t pc, size_t* bytes);
+
+/* Time `iters` (2..1000) batched FP64 LSQR iterations of the first (up to 32)
+   lambdas of every problem with each candidate shape (twice each, the faster
+   second run counts), record the fastest in the table for the problems'
+   class, and return it: best[3] = {rows, cols, blocks} (host, or NULL),
+   *best_ms and the default shape's *default_ms (host, or NULL).  Overwrites the
+   workspace; synchronizes the stream after every timed run. */
+int tik_tune(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_t iters, void* dws,
+             size_t dws_bytes, tik_stream_t stream, int32_t* best, double* best_ms, double* default_ms);
+
+/* Write the table to a text file / merge a text file into the table (one
+   class per line: wide a32 nc log2m log2n problems rows cols blocks; '#'
+   starts a comment).  A malformed line rejects the whole file. */
+int tik_tune_save(const char* path);
+int tik_tune_load(const char* path, int32_t* loaded);
+
+/* The launch shape and its source (tuned or default) of the last plan the
+   calling thread made, as text (truncated to len - 1 characters). */
+int tik_last_tiles(char* buf, int32_t len);
+
 /* Free the host structs (device workspaces belong to the caller). */
 void tik_sketch_free(tik_sketch_t sk);
 void tik_precond_free(tik_precond_t pc);

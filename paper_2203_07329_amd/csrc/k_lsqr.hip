@@ -27,8 +27,14 @@
 // lambda-major so the transposed triangular product reads it contiguously.
 #include "tik_internal.h"
 
+#include <dlfcn.h>
+
 #include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <type_traits>
 
 namespace tik {
@@ -934,6 +940,8 @@ __global__ void k_wide_write(const DevProb* __restrict__ P, int N, const double*
 
 // ============================================================ host driver ===
 
+void tile_autoload();
+
 namespace {
 
 // Item tables and partial-buffer sizes of the low-rank apply kernels.
@@ -1056,15 +1064,87 @@ int32_t lowrank_items(const tik_precond_s* pc, int p, int lp, const std::vector<
   return int32_t(nf);
 }
 
+// ------------------------------------------------------------ tile table ----
+// Launch shapes of the products over A per shape class: rows of A per gemm_n
+// block (128 or 256; matrix-core tiles), columns per gemm_t block (64 or 128)
+// and the number of product blocks the row or column split of a batch aims
+// at.  A class is (orientation, FP32 storage, lambda slots per pass, log2 of
+// the largest m and of the largest n, one / few / many problems).  Entries
+// come from tik_tune (which times every candidate on the caller's problems)
+// or from a table file (tik_tune_load; the file tuning.txt beside the library
+// is read on first use); classes without an entry use the defaults below.
+struct TileKey {
+  int wide, a32, nc, lm, ln, lp;
+  bool operator<(const TileKey& o) const {
+    return std::tie(wide, a32, nc, lm, ln, lp) < std::tie(o.wide, o.a32, o.nc, o.lm, o.ln, o.lp);
+  }
+};
+struct Tile {
+  int rbN, cbT, blocks;
+};
+std::mutex g_tile_mu;
+std::map<TileKey, Tile> g_tiles;
+std::once_flag g_tile_once;
+thread_local const Tile* t_tile_override = nullptr;   // set by the tuner
+thread_local std::string t_last_tile;
+
+int floor_log2(int64_t v) {
+  int r = 0;
+  while ((int64_t(1) << (r + 1)) <= v) ++r;
+  return r;
+}
+
+TileKey tile_key(int wide, const tik_problem* probs, const std::vector<int>& pidx, bool a32, int nc) {
+  int64_t mm = 1, nn = 1;
+  for (int k : pidx) {
+    mm = std::max(mm, probs[k].m);
+    nn = std::max(nn, probs[k].n);
+  }
+  const int np = int(pidx.size());
+  return TileKey{wide, a32 ? 1 : 0, nc, floor_log2(mm), floor_log2(nn), np == 1 ? 0 : (np <= 16 ? 1 : 2)};
+}
+
+Tile tile_default(int wide) { return wide ? Tile{256, 128, 2048} : Tile{128, 64, 2048}; }
+
+Tile tile_for(const TileKey& key, bool* tuned) {
+  if (t_tile_override) {
+    *tuned = true;
+    return *t_tile_override;
+  }
+  tile_autoload();
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  auto it = g_tiles.find(key);
+  *tuned = it != g_tiles.end();
+  return *tuned ? it->second : tile_default(key.wide);
+}
+
+void note_tile(const char* what, const TileKey& k, const Tile& t, bool tuned, int nc) {
+  char buf[256];
+  std::snprintf(buf, sizeof(buf),
+                "%s lambda slots %d: gemm_n rows %d, gemm_t cols %d, product blocks %d (%s; class wide=%d "
+                "a32=%d nc=%d lm=%d ln=%d lp=%d)",
+                what, nc, t.rbN, t.cbT, t.blocks, tuned ? "tuned" : "default", k.wide, k.a32, k.nc, k.lm,
+                k.ln, k.lp);
+  t_last_tile = buf;
+}
+
 void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vector<int>& pidx,
                const std::vector<int>& lsel, Plan& pl, const void* const* Aover = nullptr,
                const int64_t* ldover = nullptr) {
   const int N = int(lsel.size());
   pl.N = N;
   pl.NC = pick_nc(N);
-  pl.rbN = pl.NC >= 16 ? 128 : pl.NC >= 8 ? 256 : 64;   // rows per gemm_n block
+  bool a32 = Aover != nullptr;
+  for (int k : pidx) a32 |= probs[k].a_dtype == TIK_F32;
+  const TileKey key = tile_key(0, probs, pidx, a32, pl.NC);
+  bool tuned = false;
+  const Tile tl = tile_for(key, &tuned);
+  note_tile("tall", key, tl, tuned, pl.NC);
+  // rows per gemm_n block and columns per gemm_t block: the table's on the
+  // matrix cores, fixed for the few-lambda VALU kernels
+  pl.rbN = pl.NC >= 16 ? tl.rbN : pl.NC >= 8 ? 256 : 64;
   pl.cpw = 4;          // columns per wave in R^{-T} t: low registers, high occupancy
-  pl.cbT = 64;          // columns per gemm_t block
+  pl.cbT = pl.NC >= 16 ? tl.cbT : 64;
   pl.pidx = pidx;
   pl.lsel = lsel;
   pl.P.clear();
@@ -1078,7 +1158,8 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
   // of a ragged batch are of similar length
   int64_t work = 0;
   for (int lp = 0; lp < np; ++lp) work += cdiv(probs[pidx[lp]].n, pl.cbT) * probs[pidx[lp]].m;
-  const int64_t rtarget = std::min<int64_t>(8192, std::max<int64_t>(512, cdiv(cdiv(work, 2048), 32) * 32));
+  const int64_t rtarget =
+      std::min<int64_t>(8192, std::max<int64_t>(512, cdiv(cdiv(work, tl.blocks), 32) * 32));
   for (int lp = 0; lp < np; ++lp) {
     const tik_problem& g = probs[pidx[lp]];
     DevProb d = {};
@@ -2126,7 +2207,6 @@ struct WBufs {
   int32_t *pre, *jmap, *lidx;
 };
 
-constexpr int64_t kWideBlocks = 2048;   // product blocks of a wide batch
 void make_plan_wide(const tik_problem* probs, const tik_precond_s* pc, const std::vector<int>& pidx,
                     const std::vector<int>& lsel, WPlan& pl, const void* const* Aover = nullptr,
                     const int64_t* ldover = nullptr) {
@@ -2134,9 +2214,17 @@ void make_plan_wide(const tik_problem* probs, const tik_precond_s* pc, const std
   pl = WPlan();
   pl.N = N;
   pl.NC = pick_nc(N);
-  pl.rbN = pl.NC >= 8 ? 256 : 64;   // rows per gemm_n block: v_top is re-read per block
+  bool a32 = Aover != nullptr;
+  for (int k : pidx) a32 |= probs[k].a_dtype == TIK_F32;
+  const TileKey key = tile_key(1, probs, pidx, a32, pl.NC);
+  bool tuned = false;
+  const Tile tl = tile_for(key, &tuned);
+  note_tile("wide", key, tl, tuned, pl.NC);
+  // rows per gemm_n block (v_top is re-read per block) and columns per gemm_t
+  // block (y is re-read per block): the table's on the matrix cores
+  pl.rbN = pl.NC >= 16 ? tl.rbN : pl.NC >= 8 ? 256 : 64;
   pl.cpw = 4;          // columns per wave in R^{-T} t: low registers, high occupancy
-  pl.cbT = pl.NC >= 16 ? 128 : 64;   // columns per gemm_t block: y is re-read per block
+  pl.cbT = pl.NC >= 16 ? tl.cbT : 64;
   pl.pidx = pidx;
   pl.lsel = lsel;
   pl.lowrank = pc->route == TIK_ROUTE_LOWRANK;
@@ -2164,7 +2252,7 @@ void make_plan_wide(const tik_problem* probs, const tik_precond_s* pc, const std
     if (!pl.lowrank) d.Rinv = pc->Rinv[pidx[lp]];
     // split of A v_top over column chunks: about kWideBlocks blocks over the batch
     const int64_t nrb = cdiv(g.m, pl.rbN);
-    int64_t nch = std::max<int64_t>(1, kWideBlocks / std::max<int64_t>(1, rowblocks));
+    int64_t nch = std::max<int64_t>(1, tl.blocks / std::max<int64_t>(1, rowblocks));
     nch = std::min<int64_t>(nch, cdiv(g.n, 32));
     const int64_t cch = cdiv(cdiv(g.n, nch), 32) * 32;
     nch = cdiv(g.n, cch);
@@ -2876,6 +2964,146 @@ int wide_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32
 
 }  // namespace
 
+// ---------------------------------------------------------------- tuning ----
+// Candidate launch shapes: rows per gemm_n block x columns per gemm_t block x
+// product-block target (only the target applies to the few-lambda kernels).
+std::vector<Tile> tile_candidates(int nc) {
+  std::vector<Tile> c;
+  const int blocks[] = {1024, 2048, 4096};
+  if (nc < 16) {
+    for (int b : blocks) c.push_back(Tile{0, 0, b});
+    return c;
+  }
+  for (int r : {128, 256})
+    for (int t : {64, 128})
+      for (int b : blocks) c.push_back(Tile{r, t, b});
+  return c;
+}
+
+struct OverrideScope {
+  explicit OverrideScope(const Tile* t) { t_tile_override = t; }
+  ~OverrideScope() { t_tile_override = nullptr; }
+};
+
+// Time `iters` batched FP64 LSQR iterations of the first (up to 32) lambdas of
+// every problem with each candidate and keep the fastest for the class.
+int tune_class(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32_t iters, void* dws,
+               size_t dws_bytes, hipStream_t st, int* best_out, double* best_ms_out, double* default_ms_out) {
+  tile_autoload();   // a later first load must not replace what this call stores
+  std::vector<int> ps, ls;
+  for (int k = 0; k < nprob; ++k) ps.push_back(k);
+  for (int i = 0; i < std::min(32, pc->N); ++i) ls.push_back(i);
+  const bool wide = pc->wide;
+  const bool f32 = p[0].a_dtype == TIK_F32;
+  const int nc = pick_nc(int(ls.size()));
+  const std::vector<Tile> cand = tile_candidates(nc);
+  hipEvent_t e0, e1;
+  TIK_HIP(hipEventCreate(&e0));
+  TIK_HIP(hipEventCreate(&e1));
+  double best = 1e300, dflt = -1.0;
+  int bi = -1;
+  int rc = TIK_OK;
+  const Tile def = tile_default(wide ? 1 : 0);
+  for (size_t ci = 0; ci < cand.size() && rc == TIK_OK; ++ci) {
+    Tile t = cand[ci];
+    if (nc < 16) {
+      t.rbN = def.rbN;
+      t.cbT = def.cbT;
+    }
+    OverrideScope ov(&t);
+    double ms_min = 1e300;
+    for (int rep = 0; rep < 2 && rc == TIK_OK; ++rep) {
+      std::vector<std::vector<char>> keep;
+      Arena a;
+      a.base = static_cast<char*>(dws);
+      a.cap = dws_bytes;
+      if (wide) {
+        WPlan pl;
+        make_plan_wide(p, pc, ps, ls, pl);
+        WBufs b;
+        take_wbufs(a, pl, sizeof(double), b);
+        if (!a.fits()) { set_error("tik_tune: workspace too small"); rc = TIK_EWORKSPACE; break; }
+        if ((rc = upload_wplan(pl, b, pc, nullptr, keep, st)) != TIK_OK) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = TIK_EHIP; break; }
+        rc = f32 ? run_core_wide_nc<float, double>(pl, b, 0.0, iters, st, nullptr)
+                 : run_core_wide_nc<double, double>(pl, b, 0.0, iters, st, nullptr);
+      } else {
+        Plan pl;
+        make_plan(p, pc, ps, ls, pl);
+        Bufs b;
+        take_bufs(a, pl, sizeof(double), b);
+        if (!a.fits()) { set_error("tik_tune: workspace too small"); rc = TIK_EWORKSPACE; break; }
+        if ((rc = upload_plan(pl, b, pc, nullptr, keep, st)) != TIK_OK) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = TIK_EHIP; break; }
+        rc = f32 ? run_core_nc<float, double>(pl, b, 0.0, iters, st, nullptr)
+                 : run_core_nc<double, double>(pl, b, 0.0, iters, st, nullptr);
+      }
+      if (rc != TIK_OK) break;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = TIK_EHIP; break; }
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = TIK_EHIP; break; }
+      if (rep > 0) ms_min = std::min(ms_min, double(ms));   // the first run captures its graph
+    }
+    if (rc != TIK_OK) break;
+    if (t.rbN == def.rbN && t.cbT == def.cbT && t.blocks == def.blocks) dflt = ms_min;
+    if (ms_min < best) {
+      best = ms_min;
+      bi = int(ci);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  TIK_TRY(rc);
+  Tile t = cand[size_t(bi)];
+  if (nc < 16) {
+    t.rbN = def.rbN;
+    t.cbT = def.cbT;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    g_tiles[tile_key(wide ? 1 : 0, p, ps, f32, nc)] = t;
+  }
+  if (best_out) {
+    best_out[0] = t.rbN;
+    best_out[1] = t.cbT;
+    best_out[2] = t.blocks;
+  }
+  if (best_ms_out) *best_ms_out = best;
+  if (default_ms_out) *default_ms_out = dflt;
+  return TIK_OK;
+}
+
+int tune_bytes(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, size_t* bytes) {
+  std::vector<int> ps, ls;
+  for (int k = 0; k < nprob; ++k) ps.push_back(k);
+  for (int i = 0; i < std::min(32, pc->N); ++i) ls.push_back(i);
+  size_t need = 0;
+  for (const Tile& c : tile_candidates(pick_nc(int(ls.size())))) {
+    Tile t = c;
+    const Tile def = tile_default(pc->wide ? 1 : 0);
+    if (t.rbN == 0) {
+      t.rbN = def.rbN;
+      t.cbT = def.cbT;
+    }
+    OverrideScope ov(&t);
+    Arena a;
+    if (pc->wide) {
+      WPlan pl;
+      make_plan_wide(p, pc, ps, ls, pl);
+      WBufs b;
+      take_wbufs(a, pl, sizeof(double), b);
+    } else {
+      Plan pl;
+      make_plan(p, pc, ps, ls, pl);
+      Bufs b;
+      take_bufs(a, pl, sizeof(double), b);
+    }
+    need = std::max(need, a.used + 256);
+  }
+  *bytes = need;
+  return TIK_OK;
+}
+
 // The mixed drivers solve a group of lambdas by batched FP64 LSQR when FP32
 // products cannot carry one of its lambdas (12 kappa(B) u_32 > 0.25, kappa(B)^2
 // bounded by (||C|| + lambda) / lambda).  When that holds for every group, a
@@ -2962,5 +3190,88 @@ int lsqr_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32
   }
   return TIK_OK;
 }
+
+// ------------------------------------------------------ tile persistence ----
+// Text format, one class per line:
+//   wide a32 nc lm ln lp  rbN cbT blocks
+// '#' starts a comment.
+const char* g_autoload_path = nullptr;
+
+int tiles_save(const char* path) {
+  tile_autoload();
+  FILE* f = std::fopen(path, "w");
+  if (!f) {
+    set_error(std::string("tik_tune_save: cannot open ") + path);
+    return TIK_EINVAL;
+  }
+  std::fprintf(f, "# libtik launch-shape table: wide a32 nc log2(m) log2(n) problems(0:1,1:<=16,2:more)"
+                  "  rows_per_gemm_n_block cols_per_gemm_t_block product_blocks\n");
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  for (const auto& kv : g_tiles)
+    std::fprintf(f, "%d %d %d %d %d %d  %d %d %d\n", kv.first.wide, kv.first.a32, kv.first.nc, kv.first.lm,
+                 kv.first.ln, kv.first.lp, kv.second.rbN, kv.second.cbT, kv.second.blocks);
+  std::fclose(f);
+  return TIK_OK;
+}
+
+int tiles_load(const char* path, int* loaded) {
+  if (path != g_autoload_path) tile_autoload();   // an explicit file overrides the automatic one
+  FILE* f = std::fopen(path, "r");
+  if (!f) {
+    set_error(std::string("tik_tune_load: cannot open ") + path);
+    return TIK_EINVAL;
+  }
+  char line[512];
+  int n = 0, lineno = 0;
+  std::map<TileKey, Tile> add;
+  while (std::fgets(line, sizeof(line), f)) {
+    ++lineno;
+    char* h = std::strchr(line, '#');
+    if (h) *h = 0;
+    if (std::strspn(line, " \t\r\n") == std::strlen(line)) continue;   // blank or comment only
+    TileKey k;
+    Tile t;
+    int used = 0;
+    const int got = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %n", &k.wide, &k.a32, &k.nc, &k.lm, &k.ln,
+                                &k.lp, &t.rbN, &t.cbT, &t.blocks, &used);
+    const bool whole = got == 9 && line[used] == 0;
+    const bool ok = whole && (k.wide == 0 || k.wide == 1) && (k.a32 == 0 || k.a32 == 1) &&
+                    (k.nc == 1 || k.nc == 2 || k.nc == 4 || k.nc == 8 || k.nc == 16 || k.nc == 32) &&
+                    (t.rbN == 64 || t.rbN == 128 || t.rbN == 256) && (t.cbT == 64 || t.cbT == 128) &&
+                    t.blocks >= 64 && t.blocks <= (1 << 16) && k.lp >= 0 && k.lp <= 2;
+    if (!ok) {
+      std::fclose(f);
+      set_error(std::string("tik_tune_load: malformed line ") + std::to_string(lineno) + " in " + path);
+      return TIK_EINVAL;
+    }
+    add[k] = t;
+    ++n;
+  }
+  std::fclose(f);
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  for (const auto& kv : add) g_tiles[kv.first] = kv.second;
+  if (loaded) *loaded = n;
+  return TIK_OK;
+}
+
+// tuning.txt beside the library, read once on first use when present
+void tile_autoload() {
+  std::call_once(g_tile_once, []() {
+    Dl_info info;
+    if (!dladdr(reinterpret_cast<void*>(&tik_version), &info) || !info.dli_fname) return;
+    std::string dir(info.dli_fname);
+    const size_t slash = dir.rfind('/');
+    dir = slash == std::string::npos ? std::string(".") : dir.substr(0, slash);
+    static std::string path;
+    path = dir + "/tuning.txt";
+    if (FILE* f = std::fopen(path.c_str(), "r")) {
+      std::fclose(f);
+      g_autoload_path = path.c_str();
+      (void)tiles_load(path.c_str(), nullptr);   // a malformed file leaves the defaults in place
+    }
+  });
+}
+
+const std::string& last_tile() { return t_last_tile; }
 
 }  // namespace tik

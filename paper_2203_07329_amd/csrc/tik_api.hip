@@ -990,6 +990,50 @@ int tik_lcurve_corner(const double* lambdas, const double* xnorm, const double* 
   return TIK_OK;
 }
 
+// ------------------------------------------------------------ autotuner --
+int tik_tune_bytes(const tik_problem* p, int32_t nprob, tik_precond_t pc, size_t* bytes) {
+  if (!bytes) return fail(TIK_EINVAL, "tik_tune_bytes: bytes is NULL");
+  TIK_TRY(lsqr_validate(p, nprob, pc, TIK_F64_BATCHED));
+  return tune_bytes(p, nprob, pc, bytes);
+}
+
+int tik_tune(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_t iters, void* dws,
+             size_t dws_bytes, tik_stream_t stream, int32_t* best, double* best_ms, double* default_ms) {
+  TIK_TRY(lsqr_validate(p, nprob, pc, TIK_F64_BATCHED));
+  if (iters < 2 || iters > 1000) return fail(TIK_EINVAL, "tik_tune: iters must be 2..1000");
+  size_t need = 0;
+  TIK_TRY(tune_bytes(p, nprob, pc, &need));
+  TIK_TRY(check_ws(dws, dws_bytes, need, "tik_tune"));
+  int b[3] = {0, 0, 0};
+  TIK_TRY(tune_class(p, nprob, pc, iters, dws, dws_bytes, static_cast<hipStream_t>(stream), b, best_ms,
+                     default_ms));
+  if (best)
+    for (int i = 0; i < 3; ++i) best[i] = b[i];
+  return TIK_OK;
+}
+
+int tik_tune_save(const char* path) {
+  if (!path) return fail(TIK_EINVAL, "tik_tune_save: path is NULL");
+  return tiles_save(path);
+}
+
+int tik_tune_load(const char* path, int32_t* loaded) {
+  if (!path) return fail(TIK_EINVAL, "tik_tune_load: path is NULL");
+  int n = 0;
+  TIK_TRY(tiles_load(path, &n));
+  if (loaded) *loaded = n;
+  return TIK_OK;
+}
+
+int tik_last_tiles(char* buf, int32_t len) {
+  if (!buf || len < 1) return fail(TIK_EINVAL, "tik_last_tiles: empty buffer");
+  const std::string& t = last_tile();
+  const size_t n = std::min(t.size(), size_t(len - 1));
+  std::memcpy(buf, t.data(), n);
+  buf[n] = 0;
+  return TIK_OK;
+}
+
 int tik_lsqr_info(int32_t* fp32, int32_t* fp64) {
   if (!fp32 || !fp64) return fail(TIK_EINVAL, "tik_lsqr_info: NULL argument");
   last_split(fp32, fp64);

@@ -294,4 +294,11 @@ int lsqr_bytes(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int
 int lsqr_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32_t mode,
              double tol, int32_t maxit, double* const* X, int32_t* iters, int32_t* status,
              double* relres, void* dws, size_t dws_bytes, hipStream_t st);
+// launch-shape tuning (k_lsqr.hip)
+int tune_bytes(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, size_t* bytes);
+int tune_class(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32_t iters, void* dws,
+               size_t dws_bytes, hipStream_t st, int* best, double* best_ms, double* default_ms);
+int tiles_save(const char* path);
+int tiles_load(const char* path, int* loaded);
+const std::string& last_tile();
 }  // namespace tik

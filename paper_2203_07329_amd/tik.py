@@ -38,6 +38,7 @@ EXPORTS = [
     "tik_last_error", "tik_version", "tik_prof_enable", "tik_prof_reset", "tik_prof_query",
     "tik_lsqr_info", "tik_set_option", "tik_get_option", "tik_lsqr_batch_static",
     "tik_lcurve_bytes", "tik_lcurve", "tik_lcurve_corner",
+    "tik_tune_bytes", "tik_tune", "tik_tune_save", "tik_tune_load", "tik_last_tiles",
 ]
 
 
@@ -89,13 +90,19 @@ def lib() -> ctypes.CDLL:
     L.tik_lcurve_bytes.argtypes = [P(CProblem), i32, P(sz)]
     L.tik_lcurve.argtypes = [P(CProblem), i32, i32, P(vp), vp, vp, vp, sz, vp]
     L.tik_lcurve_corner.argtypes = [P(dbl), P(dbl), P(dbl), i32, P(i32), P(dbl)]
+    L.tik_tune_bytes.argtypes = [P(CProblem), i32, vp, P(sz)]
+    L.tik_tune.argtypes = [P(CProblem), i32, vp, i32, vp, sz, vp, P(i32), P(dbl), P(dbl)]
+    L.tik_tune_save.argtypes = [ctypes.c_char_p]
+    L.tik_tune_load.argtypes = [ctypes.c_char_p, P(i32)]
+    L.tik_last_tiles.argtypes = [ctypes.c_char_p, i32]
     L.tik_lsqr_batch_static.argtypes = [P(CProblem), i32, vp, i32, dbl, i32, P(vp), vp, vp, vp, vp]
     L.tik_get_option.argtypes = [ctypes.c_char_p, P(i64)]
     for name in ("tik_sketch_bytes", "tik_sketch", "tik_sketch_data", "tik_precond_bytes",
                  "tik_precond", "tik_precond_data", "tik_lsqr_batch_bytes", "tik_lsqr_batch", "tik_version",
                  "tik_prof_enable", "tik_prof_reset", "tik_prof_query", "tik_lsqr_info",
                  "tik_set_option", "tik_get_option", "tik_lsqr_batch_static",
-                 "tik_lcurve_bytes", "tik_lcurve", "tik_lcurve_corner"):
+                 "tik_lcurve_bytes", "tik_lcurve", "tik_lcurve_corner", "tik_tune_bytes", "tik_tune",
+                 "tik_tune_save", "tik_tune_load", "tik_last_tiles"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -360,6 +367,36 @@ def lcurve_corner(lambdas, xnorm, rnorm):
     _check(lib().tik_lcurve_corner(lam.ctypes.data_as(P), xn.ctypes.data_as(P), rn.ctypes.data_as(P),
                                    n, ctypes.byref(c), curv.ctypes.data_as(P)))
     return c.value, curv
+
+
+def tune(probs: Problems, pc: Precond, iters: int = 10, stream=None):
+    """tik_tune: time the candidate launch shapes on these problems, keep the fastest.
+    Returns ((rows, cols, blocks), best_ms, default_ms)."""
+    L = lib()
+    nb = ctypes.c_size_t()
+    _check(L.tik_tune_bytes(probs.c, probs.count, pc.handle, ctypes.byref(nb)))
+    ws = _workspace(nb.value, probs.At[0].device)
+    best = (ctypes.c_int32 * 3)()
+    bms, dms = ctypes.c_double(), ctypes.c_double()
+    _check(L.tik_tune(probs.c, probs.count, pc.handle, int(iters), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                      _stream(stream), best, ctypes.byref(bms), ctypes.byref(dms)))
+    return (best[0], best[1], best[2]), bms.value, dms.value
+
+
+def tune_save(path: str) -> None:
+    _check(lib().tik_tune_save(path.encode()))
+
+
+def tune_load(path: str) -> int:
+    n = ctypes.c_int32()
+    _check(lib().tik_tune_load(path.encode(), ctypes.byref(n)))
+    return n.value
+
+
+def last_tiles() -> str:
+    buf = ctypes.create_string_buffer(512)
+    _check(lib().tik_last_tiles(buf, 512))
+    return buf.value.decode()
 
 
 def lsqr_info():

@@ -178,3 +178,46 @@ def test_sparse_embedding_limits():
                 tik.set_option("sparse_nnz", bad)
     finally:
         tik.set_option("sparse_nnz", old)
+
+
+def test_tune_table_roundtrip(tmp_path):
+    """tik_tune_load / tik_tune_save: the text table survives a round trip
+    (classes at log2 sizes no workload reaches, so no solve picks them up)."""
+    f = tmp_path / "in.txt"
+    f.write_text("# header comment\n"
+                 "0 0 32 40 40 2  256 128 4096\n"
+                 "\n"
+                 "1 1 16 41 41 1  128 64 1024   # trailing comment\n")
+    assert tik.tune_load(str(f)) == 2
+    g = tmp_path / "out.txt"
+    tik.tune_save(str(g))
+    rows = [ln.split() for ln in g.read_text().splitlines() if ln.strip() and not ln.startswith("#")]
+    assert "0 0 32 40 40 2 256 128 4096".split() in rows
+    assert "1 1 16 41 41 1 128 64 1024".split() in rows
+    assert tik.tune_load(str(g)) == len(rows)
+
+
+@pytest.mark.parametrize("line", [
+    "0 0 32 40 40 2  256 128",          # too few fields
+    "0 0 3 40 40 2  256 128 4096",      # lambda slots not a power of two up to 32
+    "0 0 32 40 40 2  100 128 4096",     # rows per block not 64/128/256
+    "0 0 32 40 40 2  256 96 4096",      # columns per block not 64/128
+    "2 0 32 40 40 2  256 128 4096",     # orientation not 0/1
+    "0 0 32 40 40 3  256 128 4096",     # problem-count class not 0..2
+    "0 0 32 40 40 2  256 128 10",       # too few product blocks
+    "x 0 32 40 40 2  256 128 4096",     # not a number
+])
+def test_tune_table_rejects_malformed(tmp_path, line):
+    f = tmp_path / "bad.txt"
+    f.write_text("0 0 32 42 42 2  256 128 4096\n" + line + "\n")
+    with pytest.raises(tik.TikError):
+        tik.tune_load(str(f))
+    with pytest.raises(tik.TikError):
+        tik.tune_load(str(tmp_path / "missing.txt"))
+
+
+def test_tune_table_rejects_extra_fields(tmp_path):
+    f = tmp_path / "bad.txt"
+    f.write_text("0 0 32 40 40 2  256 128 4096 7\n")
+    with pytest.raises(tik.TikError):
+        tik.tune_load(str(f))
