@@ -198,6 +198,10 @@ int tik_precond_data(tik_precond_t pc, int32_t k, int32_t i, const double** data
    while the preconditioner workspace is. */
 int tik_precond_sigma(tik_precond_t pc, int32_t k, const double** sigma, int64_t* count);
 
+/* Sweeps of one-sided Jacobi the SVD of problem k's sketch took, the last
+   one finding nothing to rotate (TIK_ROUTE_LOWRANK only). */
+int tik_precond_sweeps(tik_precond_t pc, int32_t k, int32_t* sweeps);
+
 /* ------------------------------------------------------------- solve ---- */
 
 /* Workspace bytes tik_lsqr_batch needs in this mode. */

@@ -768,6 +768,24 @@ __global__ void k_ir_inner_stats(const DevProb* __restrict__ P, int J, int N, in
   out[2 * g + 1] = use[j] ? S.status : -1;
 }
 
+// Per-lambda outputs of a refined group, scattered from one table the host
+// fills (one record per lambda the refinement wrote).
+struct OutRec {
+  int64_t gpos;
+  int32_t it, st;
+  double rel;
+};
+
+__global__ void k_scatter_outs(const OutRec* __restrict__ rec, int n, int32_t* __restrict__ iters,
+                               int32_t* __restrict__ status, double* __restrict__ relres) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const OutRec r = rec[i];
+  if (iters) iters[r.gpos] = r.it;
+  if (status) status[r.gpos] = r.st;
+  if (relres) relres[r.gpos] = r.rel;
+}
+
 __global__ void k_ir_write(const DevProb* __restrict__ P, int NF, const double* __restrict__ x,
                            const int32_t* __restrict__ ok, double* const* __restrict__ Xout,
                            int32_t l0) {
@@ -1709,6 +1727,7 @@ struct MixedWs {
   std::vector<float*> A32;        // FP32 copies of FP64-stored problems (null if stored FP32)
   double *r, *s, *f, *a, *x, *dx, *g, *nrm;
   int32_t *use32, *use64, *stats, *ok;
+  OutRec* rec;                    // per-lambda output records
   char* base32 = nullptr;         // inner FP32 plan region
   char* base64 = nullptr;         // inner FP64 plan region
   size_t cap32 = 0, cap64 = 0;
@@ -1733,6 +1752,20 @@ std::vector<int> subset_sizes(int NF) {
 }
 
 // Workspace layout of the mixed mode for lambda groups of at most 32.
+// One copy of the records and one scatter instead of three small copies per lambda.
+int scatter_outs(const std::vector<OutRec>& recs, OutRec* dev, int32_t* iters, int32_t* status,
+                 double* relres, std::vector<std::vector<char>>& keep, hipStream_t st) {
+  if (recs.empty() || (!iters && !status && !relres)) return TIK_OK;
+  const char* h = reinterpret_cast<const char*>(recs.data());
+  keep.emplace_back(h, h + recs.size() * sizeof(OutRec));
+  TIK_HIP(hipMemcpyAsync(dev, keep.back().data(), recs.size() * sizeof(OutRec), hipMemcpyHostToDevice, st));
+  const int n = int(recs.size());
+  hipLaunchKernelGGL(k_scatter_outs, dim3(unsigned(cdiv(n, 256))), dim3(256), 0, st, dev, n, iters, status,
+                     relres);
+  TIK_LAUNCHED("k_scatter_outs");
+  return TIK_OK;
+}
+
 size_t mixed_layout(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, Arena& a,
                     MixedWs& w) {
   std::vector<int> ps;
@@ -1758,6 +1791,7 @@ size_t mixed_layout(const tik_problem* p, int32_t nprob, const tik_precond_s* pc
   w.use64 = a.take<int32_t>(pl.J);
   w.stats = a.take<int32_t>(2 * size_t(pl.J));
   w.ok = a.take<int32_t>(pl.J);
+  w.rec = a.take<OutRec>(pl.J);
   std::vector<Plan> subs;                 // inner plans solve subsets of the lambdas
   for (int ng : subset_sizes(NF)) {
     std::vector<int> sub;
@@ -2146,13 +2180,11 @@ int mixed_group(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, Mi
                      bf.P, NF, w.x, w.ok, bf.Xp, l0);
   TIK_LAUNCHED("k_ir_write");
   // per-lambda outputs at global positions k * N + l0 + i (refined lambdas only)
-  for (int j = 0; j < J; ++j) {
-    if (done[j] == 2) continue;
-    const size_t gpos = size_t(j / NF) * pc->N + l0 + (j % NF);
-    if (iters) TIK_HIP(hipMemcpyAsync(iters + gpos, &it_h[j], 4, hipMemcpyHostToDevice, st));
-    if (status) TIK_HIP(hipMemcpyAsync(status + gpos, &st_h[j], 4, hipMemcpyHostToDevice, st));
-    if (relres) TIK_HIP(hipMemcpyAsync(relres + gpos, &rel_h[j], 8, hipMemcpyHostToDevice, st));
-  }
+  std::vector<OutRec> recs;
+  for (int j = 0; j < J; ++j)
+    if (done[j] != 2)
+      recs.push_back(OutRec{int64_t(j / NF) * pc->N + l0 + (j % NF), it_h[j], st_h[j], rel_h[j]});
+  TIK_TRY(scatter_outs(recs, w.rec, iters, status, relres, keep, st));
   TIK_HIP(hipStreamSynchronize(st));
   return TIK_OK;
 }
@@ -2610,6 +2642,7 @@ struct WMixedWs {
   std::vector<float*> A32;
   double *yd, *h, *nrm;
   int32_t *use, *stats, *ok;
+  OutRec* rec;
   char *baseF = nullptr, *base32 = nullptr, *base64 = nullptr;
   size_t capF = 0, cap32 = 0, cap64 = 0;
   bool converted = false;
@@ -2633,6 +2666,7 @@ size_t wide_mixed_layout(const tik_problem* p, int32_t nprob, const tik_precond_
   w.use = a.take<int32_t>(pl.J);
   w.stats = a.take<int32_t>(2 * size_t(pl.J));
   w.ok = a.take<int32_t>(pl.J);
+  w.rec = a.take<OutRec>(pl.J);
   std::vector<WPlan> subs;
   for (int ng : subset_sizes(NF)) {
     std::vector<int> sub;
@@ -2879,12 +2913,10 @@ int wide_mixed_group(const tik_problem* p, int32_t nprob, const tik_precond_s* p
   hipLaunchKernelGGL(k_wide_ir_write, dim3(unsigned(std::min<int64_t>(cdiv(maxn, 256), 4096)), unsigned(J)),
                      dim3(256), 0, st, bf.P, NF, static_cast<const double*>(bf.partT), w.ok, bf.Xp, l0);
   TIK_LAUNCHED("k_wide_ir_write");
-  for (int j = 0; j < J; ++j) {
-    const size_t gpos = size_t(j / NF) * pc->N + l0 + (j % NF);
-    if (iters) TIK_HIP(hipMemcpyAsync(iters + gpos, &it_h[j], 4, hipMemcpyHostToDevice, st));
-    if (status) TIK_HIP(hipMemcpyAsync(status + gpos, &st_h[j], 4, hipMemcpyHostToDevice, st));
-    if (relres) TIK_HIP(hipMemcpyAsync(relres + gpos, &rel_h[j], 8, hipMemcpyHostToDevice, st));
-  }
+  std::vector<OutRec> recs;
+  for (int j = 0; j < J; ++j)
+    recs.push_back(OutRec{int64_t(j / NF) * pc->N + l0 + (j % NF), it_h[j], st_h[j], rel_h[j]});
+  TIK_TRY(scatter_outs(recs, w.rec, iters, status, relres, keep, st));
   TIK_HIP(hipStreamSynchronize(st));
   return TIK_OK;
 }

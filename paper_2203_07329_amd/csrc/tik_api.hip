@@ -847,6 +847,16 @@ int tik_precond_sigma(tik_precond_t pc, int32_t k, const double** sigma, int64_t
   return TIK_OK;
 }
 
+int tik_precond_sweeps(tik_precond_t pc, int32_t k, int32_t* sweeps) {
+  if (!pc || !sweeps) return fail(TIK_EINVAL, "tik_precond_sweeps: NULL argument");
+  if (k < 0 || k >= int32_t(pc->probs.size()))
+    return fail(TIK_EINVAL, "tik_precond_sweeps: index out of range");
+  if (pc->route != TIK_ROUTE_LOWRANK)
+    return fail(TIK_EINVAL, "tik_precond_sweeps: only the low-rank route computes an SVD");
+  *sweeps = pc->lr_sweeps[size_t(k)];
+  return TIK_OK;
+}
+
 void tik_precond_free(tik_precond_t pc) { delete pc; }
 
 // ------------------------------------------------------------------ solve --

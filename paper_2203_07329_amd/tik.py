@@ -39,6 +39,7 @@ EXPORTS = [
     "tik_lsqr_info", "tik_set_option", "tik_get_option", "tik_lsqr_batch_static",
     "tik_lcurve_bytes", "tik_lcurve", "tik_lcurve_corner",
     "tik_tune_bytes", "tik_tune", "tik_tune_save", "tik_tune_load", "tik_last_tiles",
+    "tik_precond_sweeps",
 ]
 
 
@@ -91,6 +92,7 @@ def lib() -> ctypes.CDLL:
     L.tik_lcurve.argtypes = [P(CProblem), i32, i32, P(vp), vp, vp, vp, sz, vp]
     L.tik_lcurve_corner.argtypes = [P(dbl), P(dbl), P(dbl), i32, P(i32), P(dbl)]
     L.tik_tune_bytes.argtypes = [P(CProblem), i32, vp, P(sz)]
+    L.tik_precond_sweeps.argtypes = [vp, i32, P(i32)]
     L.tik_tune.argtypes = [P(CProblem), i32, vp, i32, vp, sz, vp, P(i32), P(dbl), P(dbl)]
     L.tik_tune_save.argtypes = [ctypes.c_char_p]
     L.tik_tune_load.argtypes = [ctypes.c_char_p, P(i32)]
@@ -102,7 +104,7 @@ def lib() -> ctypes.CDLL:
                  "tik_prof_enable", "tik_prof_reset", "tik_prof_query", "tik_lsqr_info",
                  "tik_set_option", "tik_get_option", "tik_lsqr_batch_static",
                  "tik_lcurve_bytes", "tik_lcurve", "tik_lcurve_corner", "tik_tune_bytes", "tik_tune",
-                 "tik_tune_save", "tik_tune_load", "tik_last_tiles"):
+                 "tik_tune_save", "tik_tune_load", "tik_last_tiles", "tik_precond_sweeps"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -214,6 +216,12 @@ class Precond:
         _check(lib().tik_precond_data(self.handle, k, i, ctypes.byref(ptr), ctypes.byref(d),
                                       ctypes.byref(r)))
         return int(r.value)
+
+    def sweeps(self, k: int = 0) -> int:
+        """Jacobi sweeps of problem k's SVD (low-rank route)."""
+        n = ctypes.c_int32()
+        _check(lib().tik_precond_sweeps(self.handle, k, ctypes.byref(n)))
+        return int(n.value)
 
     def sigma(self, k: int = 0) -> np.ndarray:
         """Singular values of problem k's sketch, decreasing (low-rank route)."""
