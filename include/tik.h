@@ -346,6 +346,15 @@ int tik_version(void);
                   to the Gram-free route.
    "sparse_nnz"   nonzeros per column of the sparse embedding, 1..16
                   (default 1, the sparse subspace embedding of Section 3.4).
+   "cholqr_panels"  1 (default): the Householder QRs inside tik_precond (the
+                  low-rank route's SVD, the QR fallback) factor each 32-column
+                  panel P by two passes of Cholesky QR on its column-scaled
+                  Gram matrix and rebuild the panel's reflectors from the
+                  orthonormal factor, about a dozen launches and one stream
+                  synchronization per panel; a panel whose scaled Gram matrix
+                  has a pivot below 1e-10 (kappa above about 1e5) is factored
+                  column by column instead.  0: always column by column (one
+                  launch per column).
    "graph_chunk"  LSQR iterations per graph-captured chunk of tik_lsqr_batch's
                   loop, 0..64 (0: no graphs, one host wait per iteration);
                   default 4.  Replays past convergence cost a few microseconds

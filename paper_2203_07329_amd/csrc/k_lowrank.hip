@@ -5,6 +5,9 @@
 // matrix:
 //   1. Householder QR of Y^T (n x s) in FP64: Y^T = Q1 R1, blocked in panels of
 //      32 columns with compact-WY trailing updates (Schreiber & Van Loan).
+//      Each panel is factored by two Cholesky QR passes and a reconstruction
+//      of its reflectors (a fixed dozen launches), or, where its scaled Gram
+//      matrix is nearly singular, column by column (one launch per column).
 //   2. A second Householder QR, of R1^T = Q2 R2, so that Y^T = Q1 R2^T Q2^T.
 //      The lower triangle L = R2^T has far more nearly orthogonal columns than
 //      R1, which cuts the sweeps of the next step by more than half (the QR
@@ -300,8 +303,19 @@ __global__ void k_lr_reduce(const double* __restrict__ part, int nz, int64_t M, 
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
        e += int64_t(gridDim.x) * blockDim.x) {
     const int64_t mi = e % M, ni = e / M;
+    const double* src = part + mi + ni * ldc;
+    const int64_t zs = ldc * N;
+    // batches of 16 loads in flight, summed in the order z = 0, 1, ...
     double s = 0.0;
-    for (int z = 0; z < nz; ++z) s += part[int64_t(z) * ldc * N + mi + ni * ldc];
+    int z = 0;
+    for (; z + 16 <= nz; z += 16) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = src[int64_t(z + u) * zs];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += v[u];
+    }
+    for (; z < nz; ++z) s += src[int64_t(z) * zs];
     const int64_t idx = mi + ni * ldc;
     C[idx] = (beta == 0.0 ? 0.0 : beta * C[idx]) + alpha * s;
   }
@@ -346,6 +360,211 @@ __global__ void k_lr_tmul(const double* __restrict__ T, int nb, const double* __
       for (int k = i; k < nb; ++k) s += T[i + k * nb] * W1[k + c * nb];
     W2[e] = s;
   }
+}
+
+// ------------------------------------------------- Cholesky QR panels ----
+// A panel P (rr x nb, nb <= 32, rr >= nb) of the Householder QR is factored
+// in a fixed number of launches instead of one per column: two passes of
+// Cholesky QR on the column-scaled Gram matrix give P = Q1 R1, Q1 = Q R2
+// with Q orthonormal to rounding when kappa(P D) is moderate (D the column
+// scaling), and the compact WY form of a Householder QR with the same
+// columns is then rebuilt from Q (the reconstruction of Ballard, Demmel,
+// Grigori, Jacquelin, Knight and Nguyen): an LU factorization of the top
+// block with the signs S = diag(+-1) chosen on the way, Q_top - S = L W (L
+// unit lower, W upper), gives the reflectors V = [L; Q_bot W^{-1}] and
+// T = -W S L^{-T}, and then H = I - V T V^T has H^T P = [S R2 R1; 0].
+constexpr double LR_CQR_PIVOT = 1e-10;
+
+// R (nb x nb upper, ld nb) with R^T R = G and Rinv = R^{-1}, from the
+// Cholesky factor of D G D, D = diag(G)^{-1/2}: R = Rt D^{-1}, R^{-1} = D
+// Rt^{-1}.  A pivot of D G D below LR_CQR_PIVOT (or not a number), or a
+// diagonal entry of G that is not positive and finite, marks the panel:
+// *flag = mark (`first`) or *flag |= mark.  The factors stay finite when the
+// panel is marked (pivots are clamped), but are not used.  One thread per
+// entry (i, j) = (tid % 32, tid / 32), which keeps its entry in a register;
+// each elimination step publishes one row through LDS (two alternating
+// buffers, one barrier per step).  (One wavefront holding 16 entries per lane
+// measured several times slower: its steps serialize the 16 updates.)
+__global__ void __launch_bounds__(1024) k_lr_cqr_chol(const double* __restrict__ G, int nb, int first,
+                                                      double* __restrict__ R, double* __restrict__ Rinv,
+                                                      int* __restrict__ flag) {
+  __shared__ double d[LR_NB];
+  __shared__ double rowb[2][LR_NB];
+  __shared__ double Rs[LR_NB][LR_NB + 1];
+  __shared__ int bad;
+  const int tid = threadIdx.x, i = tid & 31, j = tid >> 5;
+  const bool in = i < nb && j < nb;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  if (tid < nb) {
+    const double g = G[tid + tid * nb];
+    const bool ok = g > 0.0 && g < INFINITY;
+    d[tid] = ok ? 1.0 / sqrt(g) : 1.0;
+    if (!ok) bad = 1;
+  }
+  __syncthreads();
+  double a = in ? d[i] * G[i + j * nb] * d[j] : 0.0;
+  // D G D = Rt^T Rt (upper): step k publishes row k of the reduced matrix
+  for (int k = 0; k < nb; ++k) {
+    double* rb = rowb[k & 1];
+    if (i == k && j >= k && j < nb) rb[j] = a;
+    __syncthreads();
+    const double p = rb[k];
+    const double pc = p >= LR_CQR_PIVOT ? p : LR_CQR_PIVOT;
+    if (tid == 0 && !(p >= LR_CQR_PIVOT)) bad = 1;
+    if (i == k && j >= k && j < nb) a = j == k ? sqrt(pc) : a / sqrt(pc);
+    else if (i > k && j >= i && j < nb) a -= rb[i] * rb[j] / pc;
+  }
+  if (in) Rs[i][j] = a;
+  __syncthreads();
+  // Rt^{-1}, bottom-up and right-looking: step k finishes row k
+  double x = i == j ? 1.0 : 0.0;
+  for (int k = nb - 1; k >= 0; --k) {
+    double* rb = rowb[k & 1];
+    if (i == k && j < nb) {
+      x = j >= k ? x / Rs[k][k] : 0.0;
+      rb[j] = x;
+    }
+    __syncthreads();
+    if (i < k && j < nb) x -= Rs[i][k] * rb[j];
+  }
+  if (in) {
+    R[i + j * nb] = i <= j ? a / d[j] : 0.0;
+    Rinv[i + j * nb] = i <= j ? d[i] * x : 0.0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (first) *flag = bad;
+    else if (bad) *flag = 1;
+  }
+}
+
+// Q[r, :] = P[r, :] B for the rows r0 <= r < rr (B nb x nb upper, ld nb), and
+// the same values into Q2 when it is given.  One thread per row, which reads
+// its whole row before writing it, so Q may be P (no restrict on them).
+__global__ void __launch_bounds__(256) k_lr_cqr_rmul(const double* P, int64_t ldp, int64_t r0, int64_t rr,
+                                                     int nb, const double* __restrict__ B, double* Q,
+                                                     int64_t ldq, double* Q2, int64_t ldq2) {
+  __shared__ double Bs[LR_NB][LR_NB + 1];
+  for (int e = threadIdx.x; e < LR_NB * LR_NB; e += 256) {
+    const int i = e % LR_NB, j = e / LR_NB;
+    Bs[i][j] = (i < nb && j < nb) ? B[i + j * nb] : 0.0;
+  }
+  __syncthreads();
+  const int64_t r = r0 + int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (r >= rr) return;
+  double p[LR_NB];
+#pragma unroll
+  for (int k = 0; k < LR_NB; ++k) p[k] = k < nb ? P[r + k * ldp] : 0.0;
+#pragma unroll
+  for (int c = 0; c < LR_NB; ++c) {
+    if (c < nb) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k <= c; ++k) acc += p[k] * Bs[k][c];
+      Q[r + c * ldq] = acc;
+      if (Q2) Q2[r + c * ldq2] = acc;
+    }
+  }
+}
+
+// The reconstruction for one panel.  In: the first nb rows of Q1 (rows of
+// Vc, ld ldv), R1, R2, R2inv (nb x nb, ld nb).  Out: the panel's top block of
+// Zp (ld ldz: S R2 R1 on and above the diagonal, L below it), the top block
+// of Vc (L with its unit diagonal, zeros above), T and tau (its diagonal), and
+// M = R2^{-1} W^{-1}, which turns the remaining rows of Q1 into the
+// reflectors' remaining rows.  One thread per entry (i, j), as in
+// k_lr_cqr_chol.
+__global__ void __launch_bounds__(1024) k_lr_cqr_recon(double* __restrict__ Vc, int64_t ldv, int nb,
+                                                       const double* __restrict__ R1,
+                                                       const double* __restrict__ R2,
+                                                       const double* __restrict__ R2inv,
+                                                       double* __restrict__ Zp, int64_t ldz,
+                                                       double* __restrict__ T, double* __restrict__ tau,
+                                                       double* __restrict__ M) {
+  __shared__ double B1[LR_NB][LR_NB + 1];   // R1
+  __shared__ double B2[LR_NB][LR_NB + 1];   // R2
+  __shared__ double B2i[LR_NB][LR_NB + 1];  // R2^{-1}
+  __shared__ double Qt[LR_NB][LR_NB + 1];   // Q1_top, later L \ W
+  __shared__ double Li[LR_NB][LR_NB + 1];   // L^{-1}
+  __shared__ double Wi[LR_NB][LR_NB + 1];   // W^{-1}
+  __shared__ double rowb[2][LR_NB], colb[2][LR_NB];
+  __shared__ double S[LR_NB];
+  const int tid = threadIdx.x, i = tid & 31, j = tid >> 5;
+  const bool in = i < nb && j < nb;
+  if (in) {
+    B1[i][j] = R1[i + j * nb];
+    B2[i][j] = R2[i + j * nb];
+    B2i[i][j] = R2inv[i + j * nb];
+    Qt[i][j] = Vc[i + j * ldv];
+  }
+  __syncthreads();
+  // own entry of Q_top = Q1_top R2^{-1}
+  double a = 0.0;
+  if (in)
+    for (int k = 0; k <= j; ++k) a += Qt[i][k] * B2i[k][j];
+  // LU without pivoting of Q_top - S, the sign S_p chosen at step p so that
+  // the pivot's magnitude is at least 1; step p publishes row p and column p
+  for (int p = 0; p < nb; ++p) {
+    double* rb = rowb[p & 1];
+    double* cb = colb[p & 1];
+    if (i == p && j >= p && j < nb) rb[j] = a;
+    if (j == p && i > p && i < nb) cb[i] = a;
+    __syncthreads();
+    const double app = rb[p];
+    const double sp = app >= 0.0 ? -1.0 : 1.0;
+    const double piv = app - sp;
+    if (i == p && j == p) {
+      a = piv;
+      S[p] = sp;
+    } else if (j == p && i > p && i < nb) {
+      a = a / piv;
+    } else if (i > p && j > p && in) {
+      a -= cb[i] / piv * rb[j];
+    }
+  }
+  if (in) Qt[i][j] = a;     // L below the diagonal, W on and above it
+  __syncthreads();
+  // W^{-1}: bottom-up, right-looking
+  double w = i == j ? 1.0 : 0.0;
+  for (int k = nb - 1; k >= 0; --k) {
+    double* rb = rowb[k & 1];
+    if (i == k && j < nb) {
+      w = j >= k ? w / Qt[k][k] : 0.0;
+      rb[j] = w;
+    }
+    __syncthreads();
+    if (i < k && j < nb) w -= Qt[i][k] * rb[j];
+  }
+  // L^{-1} (unit diagonal): top-down, right-looking
+  double l = i == j ? 1.0 : 0.0;
+  for (int k = 0; k < nb; ++k) {
+    double* cb = colb[k & 1];
+    if (i == k && j < nb) cb[j] = j <= k ? l : 0.0;
+    __syncthreads();
+    if (i > k && i < nb && j < nb) l -= Qt[i][k] * cb[j];
+  }
+  if (in) {
+    Wi[i][j] = i <= j ? w : 0.0;
+    Li[i][j] = i >= j ? l : 0.0;
+  }
+  __syncthreads();
+  if (!in) return;
+  // T = -W S L^{-T}, M = R2^{-1} W^{-1}, S R2 R1: entry (i, j), i <= j
+  double tv = 0.0, mv = 0.0, rv = 0.0;
+  if (i <= j) {
+    for (int k = i; k <= j; ++k) {
+      tv -= Qt[i][k] * S[k] * Li[j][k];
+      mv += B2i[i][k] * Wi[k][j];
+      rv += B2[i][k] * B1[k][j];
+    }
+    rv *= S[i];
+  }
+  T[i + j * nb] = tv;
+  M[i + j * nb] = mv;
+  Zp[i + j * ldz] = i <= j ? rv : Qt[i][j];
+  Vc[i + j * ldv] = i < j ? 0.0 : (i == j ? 1.0 : Qt[i][j]);
+  if (i == j) tau[j] = tv;
 }
 
 // 2^-e (up = false) or 2^e (up = true) for the exponent e of the largest
@@ -549,18 +768,40 @@ __global__ void __launch_bounds__(256) k_lr_bapply(double* __restrict__ G, int64
   const LrPair P(nbp, r, pair);
   // 1. the Gram matrix: partial sums in a fixed order
   const double* const pp = part + int64_t(pair) * K * 1024;
-  for (int e = tid; e < 1024; e += 256) {
-    double g = pp[e];
-    for (int kk = 1; kk < K; ++kk) g += pp[int64_t(kk) * 1024 + e];
-    Gs[0][e >> 5][e & 31] = g;
-    Qs[e >> 5][e & 31] = (e >> 5) == (e & 31) ? 1.0 : 0.0;
+  {
+    // every partial this thread needs is loaded before the sums (up to 16 in
+    // flight); the sums keep the order k = 0, 1, ...
+    double g[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) g[q] = pp[tid + 256 * q];
+    for (int k0 = 1; k0 < K; k0 += 4) {
+      double v[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[u][q] = k0 + u < K ? pp[int64_t(k0 + u) * 1024 + tid + 256 * q] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (k0 + u < K) g[q] += v[u][q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      Gs[0][e >> 5][e & 31] = g[q];
+      Qs[e >> 5][e & 31] = (e >> 5) == (e & 31) ? 1.0 : 0.0;
+    }
   }
   if (tid == 0) rot = 0;
   __syncthreads();
   // 2. one cyclic Jacobi sweep on it: G <- J^T G J, Q <- Q J.  Each round
   // rotates 16 disjoint pairs; thread (xa, xb) forms the 2 x 2 block of the
   // pairs xa (rows) and xb (columns) from the previous round's copy, and
-  // rotates columns (pb, qb) of Q in rows 2 xa, 2 xa + 1.
+  // rotates columns (pb, qb) of Q in rows 2 xa, 2 xa + 1.  Every thread forms
+  // the two rotations it needs itself: forming each once, in 16 threads, costs
+  // a second barrier per round and measured slower (the rounds are bound by the
+  // rotation's chain of dependent operations, not by its arithmetic).
   const int xa = tid >> 4, xb = tid & 15;
   int cur = 0;
   for (int rr = 0; rr < 31; ++rr) {
@@ -788,12 +1029,14 @@ struct QrWs {
   double* W2;     // 32 x cols
   double* part;   // part_cap
   int64_t part_cap;
+  double *R1, *R1i, *R2, *R2i, *M;   // 32 x 32 each: the Cholesky QR panel factors
+  int* flag;                         // the panel's Cholesky QR mark
 };
 
 static size_t qr_ws_doubles(int64_t rows, int64_t cols) {
   const int64_t np = cdiv(cols, LR_NB);
   return size_t(cols + np * LR_NB * LR_NB + rows * LR_NB + LR_NB * LR_NB + 2 * LR_NB * cols +
-                64 * LR_NB * std::max<int64_t>(cols, LR_NB) + 8 * 32);
+                64 * LR_NB * std::max<int64_t>(cols, LR_NB) + 5 * LR_NB * LR_NB + 8 + 8 * 32);
 }
 
 static QrWs qr_ws_carve(double* base, int64_t rows, int64_t cols) {
@@ -807,6 +1050,12 @@ static QrWs qr_ws_carve(double* base, int64_t rows, int64_t cols) {
   w.W2 = w.W1 + LR_NB * cols;
   w.part = w.W2 + LR_NB * cols;
   w.part_cap = 64 * LR_NB * std::max<int64_t>(cols, LR_NB);
+  w.R1 = w.part + w.part_cap;
+  w.R1i = w.R1 + LR_NB * LR_NB;
+  w.R2 = w.R1i + LR_NB * LR_NB;
+  w.R2i = w.R2 + LR_NB * LR_NB;
+  w.M = w.R2i + LR_NB * LR_NB;
+  w.flag = reinterpret_cast<int*>(w.M + LR_NB * LR_NB);
   return w;
 }
 
@@ -819,24 +1068,59 @@ static int qr_factor(double* Z, int64_t rows, int64_t cols, int64_t ldz, const Q
   for (int64_t pnl = 0; pnl < np; ++pnl) {
     const int64_t k0 = pnl * LR_NB;
     const int nb = int(std::min<int64_t>(LR_NB, cols - k0));
-    // reflector of the panel's first column, then per column one launch that
-    // applies H_j to the rest of the panel and forms the reflector of j + 1
-    hipLaunchKernelGGL(k_lr_house, dim3(1), dim3(1024), 0, st, Z, ldz, rows, k0, w.tau);
-    TIK_LAUNCHED("k_lr_house");
-    for (int jj = 0; jj + 1 < nb; ++jj)
-      hipLaunchKernelGGL(k_lr_apply_house, dim3(unsigned(nb - jj - 1)), dim3(1024), 0, st, Z, ldz,
-                         rows, k0 + jj, w.tau, 1);
-    TIK_LAUNCHED("k_lr_apply_house");
     const int64_t rr = rows - k0;
-    hipLaunchKernelGGL(k_lr_copy_v, dim3(lr_grid(rr * nb)), dim3(256), 0, st, Z, ldz, rows, k0, nb,
-                       w.Vc);
-    TIK_LAUNCHED("k_lr_copy_v");
+    double* const P = Z + k0 + k0 * ldz;
     double* Tp = w.T + pnl * LR_NB * LR_NB;
-    TIK_TRY(lr_vtz(rr, nb, nb, w.Vc, rr, w.Vc, rr, w.Gm, w.part, w.part_cap, st));
-    hipLaunchKernelGGL(k_lr_form_t, dim3(1), dim3(64), 0, st, w.Gm, nb, w.tau + k0, Tp);
-    TIK_LAUNCHED("k_lr_form_t");
+    bool cqr = false;
+    if (option_cholqr_panels()) {
+      // two Cholesky QR passes; the host reads the panel's mark before anything
+      // in Z is written, so a marked panel is still intact for the fallback
+      ProfScope ps_c("lr_cqr", st);
+      TIK_TRY(lr_vtz(rr, nb, nb, P, ldz, P, ldz, w.Gm, w.part, w.part_cap, st));
+      hipLaunchKernelGGL(k_lr_cqr_chol, dim3(1), dim3(1024), 0, st, w.Gm, nb, 1, w.R1, w.R1i, w.flag);
+      TIK_LAUNCHED("k_lr_cqr_chol");
+      hipLaunchKernelGGL(k_lr_cqr_rmul, dim3(unsigned(cdiv(rr, 256))), dim3(256), 0, st, P, ldz, int64_t(0),
+                         rr, nb, w.R1i, w.Vc, rr, static_cast<double*>(nullptr), int64_t(0));
+      TIK_LAUNCHED("k_lr_cqr_rmul");
+      TIK_TRY(lr_vtz(rr, nb, nb, w.Vc, rr, w.Vc, rr, w.Gm, w.part, w.part_cap, st));
+      hipLaunchKernelGGL(k_lr_cqr_chol, dim3(1), dim3(1024), 0, st, w.Gm, nb, 0, w.R2, w.R2i, w.flag);
+      TIK_LAUNCHED("k_lr_cqr_chol");
+      int mark = 1;
+      TIK_HIP(hipMemcpyAsync(&mark, w.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+      TIK_HIP(hipStreamSynchronize(st));
+      if (mark == 0) {
+        ProfScope ps_r("lr_cqr_recon", st);
+        hipLaunchKernelGGL(k_lr_cqr_recon, dim3(1), dim3(1024), 0, st, w.Vc, rr, nb, w.R1, w.R2, w.R2i, P, ldz,
+                           Tp, w.tau + k0, w.M);
+        TIK_LAUNCHED("k_lr_cqr_recon");
+        if (rr > nb) {
+          hipLaunchKernelGGL(k_lr_cqr_rmul, dim3(unsigned(cdiv(rr - nb, 256))), dim3(256), 0, st, w.Vc, rr,
+                             int64_t(nb), rr, nb, w.M, w.Vc, rr, P, ldz);
+          TIK_LAUNCHED("k_lr_cqr_rmul");
+        }
+        cqr = true;
+      }
+    }
+    if (!cqr) {
+      ProfScope ps_h("lr_colqr", st);
+      // reflector of the panel's first column, then per column one launch that
+      // applies H_j to the rest of the panel and forms the reflector of j + 1
+      hipLaunchKernelGGL(k_lr_house, dim3(1), dim3(1024), 0, st, Z, ldz, rows, k0, w.tau);
+      TIK_LAUNCHED("k_lr_house");
+      for (int jj = 0; jj + 1 < nb; ++jj)
+        hipLaunchKernelGGL(k_lr_apply_house, dim3(unsigned(nb - jj - 1)), dim3(1024), 0, st, Z, ldz,
+                           rows, k0 + jj, w.tau, 1);
+      TIK_LAUNCHED("k_lr_apply_house");
+      hipLaunchKernelGGL(k_lr_copy_v, dim3(lr_grid(rr * nb)), dim3(256), 0, st, Z, ldz, rows, k0, nb,
+                         w.Vc);
+      TIK_LAUNCHED("k_lr_copy_v");
+      TIK_TRY(lr_vtz(rr, nb, nb, w.Vc, rr, w.Vc, rr, w.Gm, w.part, w.part_cap, st));
+      hipLaunchKernelGGL(k_lr_form_t, dim3(1), dim3(64), 0, st, w.Gm, nb, w.tau + k0, Tp);
+      TIK_LAUNCHED("k_lr_form_t");
+    }
     const int64_t ntr = cols - k0 - nb;
     if (ntr > 0) {
+      ProfScope ps_t("lr_trail", st);
       double* Ztr = Z + k0 + (k0 + nb) * ldz;
       // W1 = Vc^T Ztr (nb x ntr), W2 = T^T W1, Ztr -= Vc W2
       TIK_TRY(lr_vtz(rr, nb, ntr, w.Vc, rr, Ztr, ldz, w.W1, w.part, w.part_cap, st));
@@ -917,6 +1201,11 @@ int launch_bp2_r(const double* Y, int64_t s, int64_t k, double lam, double* R, d
 // Block Jacobi bookkeeping, in doubles: the scaling maximum (1), the partial
 // Gram matrices (npairs K <= kLrWg of them, 1024 each), then ints: ver (nbp),
 // clean (2 nbp^2) and flag (nbp / 2).
+// About kLrWg workgroups per round in all: K = kLrWg / (s / 32) per visit.
+// At s = 1844 (58 pairs) K = 4 measured fastest: the sweeps took 99, 70, 51,
+// 63 and 101 ms with K = 1, 2, 4, 8 and 15 (fewer rows per workgroup, but
+// every workgroup repeats the visit's 32 x 32 sweep and more of them share a
+// compute unit).
 constexpr int kLrWg = 256;
 static int64_t lr_nbp(int64_t s) {
   const int64_t nblk = cdiv(s, 16);

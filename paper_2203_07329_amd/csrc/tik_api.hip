@@ -74,8 +74,10 @@ namespace {
 std::atomic<int> g_opt_chunk{4};
 std::atomic<int64_t> g_opt_pivot{0};
 std::atomic<int> g_opt_nnz{1};
+std::atomic<int> g_opt_cqr{1};
 }
 int option_sparse_nnz() { return g_opt_nnz.load(std::memory_order_relaxed); }
+int option_cholqr_panels() { return g_opt_cqr.load(std::memory_order_relaxed); }
 int option_chunk() { return g_opt_chunk.load(std::memory_order_relaxed); }
 int64_t option_pivot_ulps() { return g_opt_pivot.load(std::memory_order_relaxed); }
 
@@ -364,6 +366,11 @@ int tik_set_option(const char* name, int64_t value) {
     g_opt_nnz.store(int(value));
     return TIK_OK;
   }
+  if (std::string(name) == "cholqr_panels") {
+    if (value < 0 || value > 1) return fail(TIK_EINVAL, "tik_set_option: cholqr_panels must be 0 or 1");
+    g_opt_cqr.store(int(value));
+    return TIK_OK;
+  }
   if (std::string(name) == "chol_pivot_ulps") {
     if (value < 0 || value > (int64_t(1) << 53))
       return fail(TIK_EINVAL, "tik_set_option: chol_pivot_ulps must be 0..2^53");
@@ -385,6 +392,10 @@ int tik_get_option(const char* name, int64_t* value) {
   }
   if (std::string(name) == "sparse_nnz") {
     *value = option_sparse_nnz();
+    return TIK_OK;
+  }
+  if (std::string(name) == "cholqr_panels") {
+    *value = option_cholqr_panels();
     return TIK_OK;
   }
   return fail(TIK_EINVAL, std::string("tik_get_option: unknown option ") + name);

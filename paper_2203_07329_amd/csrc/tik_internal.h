@@ -64,6 +64,11 @@ int option_chunk();
 int64_t option_pivot_ulps();
 // Nonzeros per column of the sparse embedding (1..16).
 int option_sparse_nnz();
+// 1: the Householder QRs of the low-rank route and of the QR fallback factor
+// each 32-column panel by two Cholesky QR passes and a reconstruction of its
+// reflectors, falling back to one launch per column where the panel's scaled
+// Gram matrix is nearly singular; 0: one launch per column always.
+int option_cholqr_panels();
 
 // --------------------------------------------------------------- workspace --
 // Bump allocator over a caller-provided device buffer.  With base == nullptr it

@@ -8,6 +8,7 @@ the estimates and the dense preconditioners are compared with the oracle's
 direct QR solve.  Every call goes through the C ABI.
 """
 
+import contextlib
 import math
 
 import numpy as np
@@ -47,9 +48,22 @@ def _check_ranks(pc, sig_o, lams, alpha, s, k=0):
             assert abs(sd - round(sd)) < 1e-9 and abs(got - want) <= math.ceil(alpha), (i, got, want)
 
 
-def test_svd_and_preconditioner_match_oracle(small):
+@contextlib.contextmanager
+def cholqr(value):
+    old = tik.get_option("cholqr_panels")
+    tik.set_option("cholqr_panels", value)
+    try:
+        yield
+    finally:
+        tik.set_option("cholqr_panels", old)
+
+
+@pytest.mark.parametrize("panels", [1, 0])
+def test_svd_and_preconditioner_match_oracle(small, panels):
+    """panels = 1: QR panels by Cholesky QR and reflector reconstruction; 0: one launch per column."""
     p = small
-    pr, sk, pc = _lowrank([p])
+    with cholqr(panels):
+        pr, sk, pc = _lowrank([p])
     Y = sk.Y(0)
     s, n = Y.shape
     assert (s, n) == (p.s, p.n)
@@ -183,3 +197,32 @@ def test_lowrank_argument_errors(small):
     pc = tik.precond(sk, p.lams, tik.ROUTE_CHOL)
     with pytest.raises(tik.TikError):
         pc.sigma(0)                                          # Cholesky route keeps no SVD
+
+
+def test_svd_rank_deficient_sketch_mixes_panel_paths():
+    """A of exact rank 10 and a sketch of 64 rows: the first QR panel (32 columns
+    of rank 10) has a singular scaled Gram matrix and is factored column by
+    column; the later panels hold rounding-level residuals and take the
+    Cholesky QR path.  The singular values still match numpy's SVD of the same
+    downloaded sketch, V stays orthonormal, and the solutions match the oracle."""
+    rng = np.random.default_rng(7)
+    m, n, r, N = 3000, 400, 10, 4
+    Ua = np.linalg.qr(rng.standard_normal((m, r)))[0]
+    Va = np.linalg.qr(rng.standard_normal((n, r)))[0]
+    A = np.asfortranarray((Ua * np.logspace(0, -3, r)[None, :]) @ Va.T)
+    b = A @ rng.standard_normal(n) + 1e-3 * rng.standard_normal(m)
+    lams = np.logspace(-4, -1, N)
+    p = W.Problem("rank10", A, b, lams, 64, "gauss", "lowrank", 1e-10, 0)
+    pr, sk, pc = _lowrank([p])
+    Y = sk.Y(0)
+    sig_o = np.linalg.svd(Y, compute_uv=False)
+    sig = pc.sigma(0)
+    print("sigma", sig[:12], "max |dsigma| / sigma_0 = %.2e" % (np.max(np.abs(sig - sig_o)) / sig_o[0]))
+    assert np.max(np.abs(sig - sig_o)) <= 1e-12 * sig_o[0]
+    assert np.all(sig[r:] <= 1e-12 * sig[0])
+    V = pc.data(0, int(np.argmax([pc.rank(0, i) for i in range(N)])))
+    assert np.max(np.abs(V.T @ V - np.eye(V.shape[1]))) <= 1e-12
+    res = tik.lsqr_batch(pr, pc, tik.F64_BATCHED, 1e-13, 300)
+    err = oracle.rel_err(res.x_numpy(0), oracle.solve(A, b, lams))
+    assert np.all(res.status.cpu().numpy() == tik.ST_CONVERGED)
+    assert np.all(err <= 1e-10), err
