@@ -245,6 +245,15 @@ int tik_lsqr_batch(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_
                    int32_t* status, double* relres, void* dws, size_t dws_bytes,
                    tik_stream_t stream);
 
+/* Completion times of the calling thread's last tik_lsqr_batch (or
+   tik_lsqr_batch_static) call made with the option "record_times" = 1:
+   ms[k * N + i] (host, count = nprob * N of that call) = milliseconds from
+   the start of the call's first solve loop to the iteration at which the
+   solve of problem k, lambda i stopped, read from the device's constant-rate
+   wall clock (hipDeviceAttributeWallClockRate).  Lambdas solved by the mixed
+   mode's refinement are not timed (NaN).  TIK_EINVAL if count differs. */
+int tik_lsqr_times(double* ms, int64_t count);
+
 /* For callers that cannot allocate device memory (tight serving loops,
    harnesses that forbid hipMalloc): tik_lsqr_batch with the same arguments
    except the workspace, which is a static device array of 64 MiB per GPU
@@ -355,6 +364,11 @@ int tik_version(void);
                   has a pivot below 1e-10 (kappa above about 1e5) is factored
                   column by column instead.  0: always column by column (one
                   launch per column).
+   "record_times"  1: tik_lsqr_batch records, for every (problem, lambda)
+                  of a batched FP64 or plain per-lambda call, the device wall
+                  clock when its iteration stopped, and tik_lsqr_times returns
+                  them (one extra read-back and synchronization per group of
+                  up to 32 lambdas); default 0.
    "graph_chunk"  LSQR iterations per graph-captured chunk of tik_lsqr_batch's
                   loop, 0..64 (0: no graphs, one host wait per iteration);
                   default 4.  Replays past convergence cost a few microseconds

@@ -125,9 +125,11 @@ __global__ void __launch_bounds__(BLK) k_fin_beta(const DevProb* __restrict__ P,
     if (!isfinite(beta)) {
       S.status = TIK_ST_NONFINITE;
       S.active = 0;
+      S.tdone = int64_t(wall_clock64());
     } else if (beta == 0.0) {
       S.status = TIK_ST_CONVERGED;   // b = 0: x = 0
       S.active = 0;
+      S.tdone = int64_t(wall_clock64());
     }
   }
 }
@@ -463,6 +465,7 @@ __global__ void __launch_bounds__(BLK) k_fin_alpha(const DevProb* __restrict__ P
     if (!isfinite(alpha)) {
       S.status = TIK_ST_NONFINITE;
       S.active = 0;
+      S.tdone = int64_t(wall_clock64());
       S.ialpha = 0.0;
       S.ucoef = 0.0;
       return;
@@ -470,6 +473,7 @@ __global__ void __launch_bounds__(BLK) k_fin_alpha(const DevProb* __restrict__ P
     if (alpha == 0.0) {   // A^T b = 0: x = 0 is the solution
       S.status = TIK_ST_CONVERGED;
       S.active = 0;
+      S.tdone = int64_t(wall_clock64());
       S.ialpha = 0.0;
       S.ucoef = 0.0;
       S.relres = 0.0;
@@ -510,6 +514,7 @@ __global__ void __launch_bounds__(BLK) k_fin_alpha(const DevProb* __restrict__ P
   if (!(isfinite(alpha) && isfinite(beta) && isfinite(rho) && rho > 0.0)) {
     S.status = TIK_ST_NONFINITE;
     S.active = 0;
+    S.tdone = int64_t(wall_clock64());
     S.upd = 0;
     S.ialpha = 0.0;
     S.ucoef = 0.0;
@@ -518,9 +523,11 @@ __global__ void __launch_bounds__(BLK) k_fin_alpha(const DevProb* __restrict__ P
   if (test1 <= tol || test2 <= tol || alpha == 0.0) {
     S.status = TIK_ST_CONVERGED;
     S.active = 0;
+    S.tdone = int64_t(wall_clock64());
   } else if (S.iters >= maxit) {
     S.status = TIK_ST_MAXIT;
     S.active = 0;
+    S.tdone = int64_t(wall_clock64());
   }
   S.alpha = alpha;
   S.beta = beta;
@@ -601,6 +608,8 @@ __global__ void k_scal_init(Scal* sc, int J, int N, const double* __restrict__ l
   S.sqlam = sqrt(S.lam);
   S.active = 1;
   S.status = TIK_ST_MAXIT;
+  S.tstart = int64_t(wall_clock64());
+  S.tdone = S.tstart;
   if (pre_status && pre_status[j] != TIK_ST_CONVERGED) {
     S.active = 0;
     S.status = pre_status[j];
@@ -2990,6 +2999,12 @@ int wide_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32
       TIK_TRY((run_core_wide_nc<double, double>(pl, b, tol, maxit, st, nullptr)));
     TIK_TRY(wide_write(pl, b, iters, status, relres, st));
     TIK_HIP(hipStreamSynchronize(st));
+    if (option_record_times()) {
+      std::vector<Scal> hs(static_cast<size_t>(pl.J));
+      TIK_HIP(hipMemcpyAsync(hs.data(), b.sc, hs.size() * sizeof(Scal), hipMemcpyDeviceToHost, st));
+      TIK_HIP(hipStreamSynchronize(st));
+      times_note(hs.data(), pl.J, pl.N, pl.pidx, pl.lsel, pc->N, st);
+    }
   }
   return TIK_OK;
 }
@@ -3219,6 +3234,12 @@ int lsqr_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32
                        st, b.P, pl.N, b.x, b.sc, b.Xp, b.jmap, iters, status, relres);
     TIK_LAUNCHED("k_write_out");
     TIK_HIP(hipStreamSynchronize(st));   // staging vectors in `keep` die here
+    if (option_record_times()) {
+      std::vector<Scal> hs(static_cast<size_t>(pl.J));
+      TIK_HIP(hipMemcpyAsync(hs.data(), b.sc, hs.size() * sizeof(Scal), hipMemcpyDeviceToHost, st));
+      TIK_HIP(hipStreamSynchronize(st));
+      times_note(hs.data(), pl.J, pl.N, pl.pidx, pl.lsel, pc->N, st);
+    }
   }
   return TIK_OK;
 }

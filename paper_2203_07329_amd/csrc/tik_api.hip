@@ -16,6 +16,29 @@ namespace tik {
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 
+static thread_local std::vector<double> g_times;    // ms, NaN where not recorded
+static thread_local int64_t g_t0 = -1;               // tstart of the call's first group
+static std::atomic<int> g_opt_times{0};
+bool option_record_times() { return g_opt_times.load(std::memory_order_relaxed) != 0; }
+void times_reset(int64_t count) {
+  g_times.assign(size_t(std::max<int64_t>(count, 0)), std::nan(""));
+  g_t0 = -1;
+}
+void times_note(const Scal* hs, int J, int N, const std::vector<int>& pidx, const std::vector<int>& lsel,
+                int Ntot, hipStream_t st) {
+  int dev = 0;
+  int khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    return;
+  (void)st;
+  if (g_t0 < 0 && J > 0) g_t0 = hs[0].tstart;
+  for (int j = 0; j < J; ++j) {
+    const size_t g = size_t(pidx[size_t(j / N)]) * size_t(Ntot) + size_t(lsel[size_t(j % N)]);
+    if (g < g_times.size()) g_times[g] = double(hs[j].tdone - g_t0) / double(khz);
+  }
+}
+
 static thread_local int32_t g_split32 = 0, g_split64 = 0;
 void note_split(int32_t fp32, int32_t fp64) {
   g_split32 += fp32;
@@ -366,6 +389,11 @@ int tik_set_option(const char* name, int64_t value) {
     g_opt_nnz.store(int(value));
     return TIK_OK;
   }
+  if (std::string(name) == "record_times") {
+    if (value < 0 || value > 1) return fail(TIK_EINVAL, "tik_set_option: record_times must be 0 or 1");
+    g_opt_times.store(int(value));
+    return TIK_OK;
+  }
   if (std::string(name) == "cholqr_panels") {
     if (value < 0 || value > 1) return fail(TIK_EINVAL, "tik_set_option: cholqr_panels must be 0 or 1");
     g_opt_cqr.store(int(value));
@@ -396,6 +424,10 @@ int tik_get_option(const char* name, int64_t* value) {
   }
   if (std::string(name) == "cholqr_panels") {
     *value = option_cholqr_panels();
+    return TIK_OK;
+  }
+  if (std::string(name) == "record_times") {
+    *value = option_record_times() ? 1 : 0;
     return TIK_OK;
   }
   return fail(TIK_EINVAL, std::string("tik_get_option: unknown option ") + name);
@@ -921,6 +953,7 @@ int tik_lsqr_batch_static(const tik_problem* p, int32_t nprob, tik_precond_t pc,
   TIK_TRY(scratch_address(&ws));
   NoAllocScope guard;
   g_split32 = g_split64 = 0;
+  times_reset(option_record_times() ? int64_t(nprob) * pc->N : 0);
   return lsqr_run(p, nprob, pc, mode, tol, maxit, X, iters, status, relres, ws, kStaticBytes,
                   static_cast<hipStream_t>(stream));
 }
@@ -933,6 +966,7 @@ int tik_lsqr_batch(const tik_problem* p, int32_t nprob, tik_precond_t pc, int32_
   TIK_TRY(lsqr_bytes(p, nprob, pc, mode, &need));
   TIK_TRY(check_ws(dws, dws_bytes, need, "tik_lsqr_batch"));
   g_split32 = g_split64 = 0;
+  times_reset(option_record_times() ? int64_t(nprob) * pc->N : 0);
   return lsqr_run(p, nprob, pc, mode, tol, maxit, X, iters, status, relres, dws, dws_bytes,
                   static_cast<hipStream_t>(stream));
 }
@@ -1052,6 +1086,15 @@ int tik_last_tiles(char* buf, int32_t len) {
   const size_t n = std::min(t.size(), size_t(len - 1));
   std::memcpy(buf, t.data(), n);
   buf[n] = 0;
+  return TIK_OK;
+}
+
+int tik_lsqr_times(double* ms, int64_t count) {
+  if (!ms || count < 0) return fail(TIK_EINVAL, "tik_lsqr_times: NULL or negative");
+  if (int64_t(g_times.size()) != count)
+    return fail(TIK_EINVAL, "tik_lsqr_times: count must equal nprob * N of the last tik_lsqr_batch call "
+                            "made with record_times = 1");
+  std::copy(g_times.begin(), g_times.end(), ms);
   return TIK_OK;
 }
 

@@ -156,7 +156,8 @@ struct Scal {
   double relres, rnorm, arnorm;
   int32_t active, upd, iters, status;
   int32_t li;               // lambda index inside its problem (selects R^{-1} and the X column)
-  int32_t pad1, pad2, pad3;
+  int32_t pad1;
+  int64_t tstart, tdone;    // device wall clock when the solve loop started and when this solve stopped
 };
 
 // item tables: x = problem, y = block index (and z = chunk for gemm_T)
@@ -292,6 +293,14 @@ struct tik_precond_s {
 namespace tik {
 // split of the last solve on this thread (fp32-refined, fp64) lambdas
 void note_split(int32_t fp32, int32_t fp64);
+// Completion times of the last tik_lsqr_batch call of this thread (option
+// "record_times"): after each batched group's loop, the group's scalars are
+// read back and, for every (problem k, lambda i) it solved, (tdone - tstart
+// of the call's first group) in ms is stored at k * N + i.
+bool option_record_times();
+void times_reset(int64_t count);
+void times_note(const Scal* host_sc, int J, int N, const std::vector<int>& pidx, const std::vector<int>& lsel,
+                int Ntot, hipStream_t st);
 void last_split(int32_t* fp32, int32_t* fp64);
 // solve driver (k_lsqr.hip)
 int lsqr_bytes(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32_t mode,

@@ -39,7 +39,7 @@ EXPORTS = [
     "tik_lsqr_info", "tik_set_option", "tik_get_option", "tik_lsqr_batch_static",
     "tik_lcurve_bytes", "tik_lcurve", "tik_lcurve_corner",
     "tik_tune_bytes", "tik_tune", "tik_tune_save", "tik_tune_load", "tik_last_tiles",
-    "tik_precond_sweeps",
+    "tik_precond_sweeps", "tik_lsqr_times",
 ]
 
 
@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
     L.tik_lcurve_corner.argtypes = [P(dbl), P(dbl), P(dbl), i32, P(i32), P(dbl)]
     L.tik_tune_bytes.argtypes = [P(CProblem), i32, vp, P(sz)]
     L.tik_precond_sweeps.argtypes = [vp, i32, P(i32)]
+    L.tik_lsqr_times.argtypes = [P(dbl), i64]
     L.tik_tune.argtypes = [P(CProblem), i32, vp, i32, vp, sz, vp, P(i32), P(dbl), P(dbl)]
     L.tik_tune_save.argtypes = [ctypes.c_char_p]
     L.tik_tune_load.argtypes = [ctypes.c_char_p, P(i32)]
@@ -104,7 +105,7 @@ def lib() -> ctypes.CDLL:
                  "tik_prof_enable", "tik_prof_reset", "tik_prof_query", "tik_lsqr_info",
                  "tik_set_option", "tik_get_option", "tik_lsqr_batch_static",
                  "tik_lcurve_bytes", "tik_lcurve", "tik_lcurve_corner", "tik_tune_bytes", "tik_tune",
-                 "tik_tune_save", "tik_tune_load", "tik_last_tiles", "tik_precond_sweeps"):
+                 "tik_tune_save", "tik_tune_load", "tik_last_tiles", "tik_precond_sweeps", "tik_lsqr_times"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -405,6 +406,14 @@ def last_tiles() -> str:
     buf = ctypes.create_string_buffer(512)
     _check(lib().tik_last_tiles(buf, 512))
     return buf.value.decode()
+
+
+def lsqr_times(nprob: int, N: int) -> np.ndarray:
+    """tik_lsqr_times: (nprob, N) ms from the start of the last call's first solve loop to
+    each solve's stop (NaN where not timed); needs set_option("record_times", 1)."""
+    out = np.empty(nprob * N, dtype=np.float64)
+    _check(lib().tik_lsqr_times(out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nprob * N))
+    return out.reshape(nprob, N)
 
 
 def lsqr_info():

@@ -221,3 +221,16 @@ def test_tune_table_rejects_extra_fields(tmp_path):
     f.write_text("0 0 32 40 40 2  256 128 4096 7\n")
     with pytest.raises(tik.TikError):
         tik.tune_load(str(f))
+
+
+def test_record_times_option_and_query_without_call():
+    old = tik.get_option("record_times")
+    try:
+        tik.set_option("record_times", 1)
+        assert tik.get_option("record_times") == 1
+        with pytest.raises(tik.TikError):
+            tik.set_option("record_times", 2)
+    finally:
+        tik.set_option("record_times", old)
+    with pytest.raises(tik.TikError):
+        tik.lsqr_times(3, 7)       # no call of that size was recorded on this thread

@@ -528,3 +528,38 @@ def test_sparse_sketch_solves():
         print("sparse zeta", zeta, "s", s, "iters", res.iters.cpu().numpy().max(), "err", err.max())
         assert np.all(res.status.cpu().numpy() == tik.ST_CONVERGED)
         assert np.all(err <= 1e-10)
+
+
+def test_completion_times_follow_iterations():
+    """record_times: per-(problem, lambda) stop times from the device clock.  Recording
+    changes no result; within one solve loop a solve that stopped at a later iteration
+    stopped later; the mixed refinement is not timed (NaN)."""
+    plist = W.ragged(nprob=6, m_lo=500, m_hi=3000, n_lo=10, n_hi=120, N=4)
+    pr = dev_problems(plist)
+    sk = tik.sketch(pr, tik.GAUSS, [p.s for p in plist], 0)
+    pc = tik.precond(sk, np.stack([p.lams for p in plist]))
+    r0 = tik.lsqr_batch(pr, pc, tik.F64_BATCHED, 1e-12, 300)
+    tik.set_option("record_times", 1)
+    try:
+        r1 = tik.lsqr_batch(pr, pc, tik.F64_BATCHED, 1e-12, 300)
+        t = tik.lsqr_times(len(plist), 4)
+        with pytest.raises(tik.TikError):
+            tik.lsqr_times(len(plist), 5)
+        rm = tik.lsqr_batch(pr, pc, tik.MIXED_BATCHED, 1e-10, 300)
+        tm = tik.lsqr_times(len(plist), 4)
+    finally:
+        tik.set_option("record_times", 0)
+    for k in range(len(plist)):
+        assert np.array_equal(r0.x_numpy(k), r1.x_numpy(k))
+    it = r1.iters.cpu().numpy()
+    print("iterations", it.ravel(), "ms", np.round(t.ravel(), 3))
+    assert np.all(np.isfinite(t)) and np.all(t >= 0) and t.max() < 1000.0
+    a, b = it.ravel(), t.ravel()
+    for x in range(a.size):
+        for y in range(a.size):
+            if a[x] < a[y]:
+                assert b[x] < b[y], (a[x], a[y], b[x], b[y])
+    n32, _ = tik.lsqr_info()
+    if n32 > 0:
+        assert np.isnan(tm).any()
+    assert np.all(rm.status.cpu().numpy() != tik.ST_NONFINITE)
