@@ -576,3 +576,39 @@ def test_completion_times_follow_iterations():
     if n32 > 0:
         assert np.isnan(tm).any()
     assert np.all(rm.status.cpu().numpy() != tik.ST_NONFINITE)
+
+
+def test_size_limits_on_the_gpu():
+    """Sizes at and beyond the SRHT limits: m = 2^18 runs, m = 2^18 + 1 and s > 16384
+    return TIK_ENOTSUP before any launch; the Gaussian sketch has neither limit
+    (s = 20000, m = 300000) and its solves match the oracle."""
+    rng = np.random.default_rng(12)
+    lams = np.array([1e-6, 1e-3, 1.0])
+    # SRHT at m = 2^18 exactly (two-pass transform, largest supported order)
+    m, n = 1 << 18, 8
+    A = np.asfortranarray(rng.standard_normal((m, n)) * np.logspace(0, -4, n)[None, :])
+    b = A @ rng.standard_normal(n) + 1e-3 * rng.standard_normal(m)
+    p = W.Problem("srht_max", A, b, lams, 64, "srht", "chol", 1e-10, 0)
+    res, _ = _solve([p], tik.F64_BATCHED, tol=1e-13)
+    assert np.all(oracle.rel_err(res.x_numpy(0), oracle.solve(A, b, lams)) <= 1e-10)
+    # beyond it: rejected with TIK_ENOTSUP, nothing launched
+    A1 = np.asfortranarray(rng.standard_normal((m + 1, 4)))
+    pr1 = tik.Problems.from_numpy([A1], [np.ones(m + 1)])
+    with pytest.raises(tik.TikError) as e:
+        tik.sketch(pr1, tik.SRHT, [16], 0)
+    assert e.value.rc == tik.ENOTSUP
+    A2 = np.asfortranarray(rng.standard_normal((20000, 4)))
+    pr2 = tik.Problems.from_numpy([A2], [np.ones(20000)])
+    with pytest.raises(tik.TikError) as e:
+        tik.sketch(pr2, tik.SRHT, [16385], 0)
+    assert e.value.rc == tik.ENOTSUP
+    # Gaussian: s = 20000 > 16384 (FP64 and BF16) and m = 300000 > 2^18
+    for (mm, nn, ss, sdt) in [(24000, 64, 20000, tik.F64), (24000, 64, 20000, tik.BF16), (300000, 20, 80, tik.F64)]:
+        A = np.asfortranarray(rng.standard_normal((mm, nn)) * np.logspace(0, -4, nn)[None, :])
+        b = A @ rng.standard_normal(nn) + 1e-3 * rng.standard_normal(mm)
+        pr = tik.Problems.from_numpy([A], [b])
+        pc = tik.precond(tik.sketch(pr, tik.GAUSS, [ss], 0, sketch_dtype=sdt), lams)
+        res = tik.lsqr_batch(pr, pc, tik.F64_BATCHED, 1e-13, 300)
+        err = oracle.rel_err(res.x_numpy(0), oracle.solve(A, b, lams))
+        print("gauss", mm, nn, ss, sdt, "max rel err %.2e" % err.max(), res.iters.cpu().numpy()[0])
+        assert np.all(err <= 1e-10), (mm, nn, ss, sdt, err)
