@@ -87,11 +87,19 @@ __global__ void __launch_bounds__(256) k_lc_sq(const LcProb* __restrict__ P,
   for (int i = 0; i < NG; ++i) v[i] = 0.0;
   if (rowblk && r < pr.m) {
     const double br = pr.b[r];
+    // the row's NG partial products of each chunk are contiguous: read them
+    // chunk by chunk (each sum still runs over the chunks in order)
+    double ax[NG];
+#pragma unroll
+    for (int i = 0; i < NG; ++i) ax[i] = 0.0;
+    for (int ch = 0; ch < pr.nch; ++ch) {
+      const double* src = part + pr.part + (int64_t(ch) * pr.m + r) * NG;
+#pragma unroll
+      for (int i = 0; i < NG; ++i) ax[i] += src[i];
+    }
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
-      double ax = 0.0;
-      for (int ch = 0; ch < pr.nch; ++ch) ax += part[pr.part + (int64_t(ch) * pr.m + r) * NG + i];
-      const double d = br - ax;
+      const double d = br - ax[i];
       v[i] = d * d;
     }
   } else if (!rowblk && r < pr.n) {
