@@ -19,8 +19,10 @@
  * Conventions shared by every entry point:
  *  - Matrices are column-major.  All pointers named "device" are HIP device
  *    pointers owned by the caller; the library never allocates device memory
- *    (it keeps a few streams per device and a pool of pinned host words for
- *    the solve loop, both created on first use and held by the process).
+ *    at run time (it keeps a few streams per device and a pool of pinned host
+ *    words, created on first use and held by the process; the solve loop's
+ *    HIP graphs live for one call; the static workspace of
+ *    tik_lsqr_batch_static is a device array of the loaded module).
  *    Every call that needs scratch space takes a caller-provided device
  *    workspace (dws, dws_bytes) whose required size the matching *_bytes
  *    query returns.  A handle points into the workspace it was built in: the
