@@ -148,6 +148,17 @@ FAMILY_KERNEL = {"gemm_n": "k_gemm_n", "gemm_t": "k_gemm_t", "trmv": "k_trmv<", 
                  "lr_apply": "k_lr_"}
 
 
+def cpu_model():
+    """The host CPU's model name (Linux), for the CPU baseline's record."""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def measured_traffic(workload, family):
     """HBM bytes per launch of the family's kernel from the committed rocprofv3 counter record
     (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE, scaled by a device-copy calibration),
@@ -519,7 +530,7 @@ def main() -> int:
             what = (f"Householder QR of A once plus per-lambda QR solves, {len(idx)} problem(s), "
                     f"{nsamp} solves ({tcpu:.1f} s)")
             cpu = {"value": round(nsamp / tcpu, 4), "unit": "λ-solves/s", "cores": int(cores),
-                   "kind": "oracle",
+                   "kind": "oracle", "cpu": cpu_model(),
                    "sample": "full workload: " + what}
             checked = f"{len(idx)} of {len(plist)} problems against the oracle's direct solve"
         allerr = np.concatenate([np.ravel(e) for e in errs])
