@@ -69,7 +69,7 @@ typedef enum {
                            BP2 preconditioner of Section 4.1); the lam is solved */
 } tik_status;
 
-typedef enum { TIK_F64 = 0, TIK_F32 = 1, TIK_BF16 = 2 } tik_dtype;
+typedef enum { TIK_F64 = 0, TIK_F32 = 1, TIK_BF16 = 2, TIK_F16 = 3 } tik_dtype;
 
 /* embedding X (Section 2.1.1): subsampled randomized Hadamard transform
    X = sqrt(m'/s) S H D (H orthonormal Hadamard of order m' = 2^ceil(log2 m),
@@ -136,14 +136,21 @@ int tik_sketch_bytes(const tik_problem* p, int32_t nprob, int32_t embed,
    sketch_dtype   arithmetic of the sketch product: TIK_F64, or TIK_BF16 for
                   the Gaussian embedding on matrix cores (A and X rounded to
                   BF16, FP32 accumulation; the sketch only sets the
-                  preconditioner's quality);
+                  preconditioner's quality), or TIK_F16 for the same with
+                  FP16 operands (three more significand bits, FP16's narrow
+                  range): tall problems only (TIK_ENOTSUP for wide ones), each
+                  column of A multiplied by the power of two that puts its
+                  largest entry in [1, 2) before rounding and the sketch's
+                  column divided by it afterwards (exact); one extra pass over
+                  A finds the scales;
    s[nprob]       host, sketch size per problem, 1 <= s <= the long dimension;
                   the SRHT also needs m' <= 2^18 and s <= 16384
                   (TIK_ENOTSUP beyond);
    seed           fixes X completely, independently of launch shapes;
    out            receives the handle (host struct; free with tik_sketch_free).
    Returns TIK_EINVAL for bad shapes or mixed orientations (all problems must
-   be tall, or all wide), TIK_ENOTSUP for an SRHT of a wide matrix. */
+   be tall, or all wide), TIK_ENOTSUP for an SRHT, sparse or FP16 sketch of a
+   wide matrix. */
 int tik_sketch(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sketch_dtype,
                const int64_t* s, uint64_t seed, void* dws, size_t dws_bytes,
                tik_stream_t stream, tik_sketch_t* out);

@@ -14,6 +14,9 @@
 #include "tik_internal.h"
 
 #include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include <type_traits>
 
 namespace tik {
 
@@ -453,12 +456,20 @@ __device__ __forceinline__ void gauss4f(uint64_t seed, uint32_t r, uint32_t qb, 
   out[3] = r1 * s1;
 }
 
-// X chunk in BF16, stored row-major s x kc (k contiguous), the layout the
-// matrix-core operand loads want: the Philox/Box-Muller normals of the FP64
-// generator (computed in FP32, see gauss4f), rounded to BF16.
-__global__ void __launch_bounds__(256) k_gauss_gen_bf16(uint64_t seed, int64_t s, int64_t r0,
-                                                        int64_t kc, int64_t ldx, float scale,
-                                                        __hip_bfloat16* __restrict__ X) {
+// X chunk in BF16 or FP16, stored row-major s x kc (k contiguous), the layout
+// the matrix-core operand loads want: the Philox/Box-Muller normals of the
+// FP64 generator (computed in FP32, see gauss4f), rounded to the 16-bit type.
+__device__ __forceinline__ uint16_t to16(float v, __hip_bfloat16*) {
+  const __hip_bfloat16 h = __float2bfloat16(v);
+  return *reinterpret_cast<const uint16_t*>(&h);
+}
+__device__ __forceinline__ uint16_t to16(float v, _Float16*) {
+  const _Float16 h = static_cast<_Float16>(v);    // round to nearest even
+  return *reinterpret_cast<const uint16_t*>(&h);
+}
+template <typename T16>
+__device__ __forceinline__ void gauss_gen16(uint64_t seed, int64_t s, int64_t r0, int64_t kc, int64_t ldx,
+                                            float scale, uint16_t* __restrict__ X) {
   const int64_t sq = (s + 3) >> 2;
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= sq * kc) return;
@@ -468,8 +479,18 @@ __global__ void __launch_bounds__(256) k_gauss_gen_bf16(uint64_t seed, int64_t s
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int64_t q = qb * 4 + t;
-    if (q < s) X[q * ldx + cc] = __float2bfloat16(z[t] * scale);
+    if (q < s) X[q * ldx + cc] = to16(z[t] * scale, static_cast<T16*>(nullptr));
   }
+}
+__global__ void __launch_bounds__(256) k_gauss_gen_bf16(uint64_t seed, int64_t s, int64_t r0,
+                                                        int64_t kc, int64_t ldx, float scale,
+                                                        __hip_bfloat16* __restrict__ X) {
+  gauss_gen16<__hip_bfloat16>(seed, s, r0, kc, ldx, scale, reinterpret_cast<uint16_t*>(X));
+}
+__global__ void __launch_bounds__(256) k_gauss_gen_f16(uint64_t seed, int64_t s, int64_t r0,
+                                                       int64_t kc, int64_t ldx, float scale,
+                                                       _Float16* __restrict__ X) {
+  gauss_gen16<_Float16>(seed, s, r0, kc, ldx, scale, reinterpret_cast<uint16_t*>(X));
 }
 
 typedef __bf16 sk_bf16x8 __attribute__((ext_vector_type(8)));
@@ -510,11 +531,11 @@ __device__ __forceinline__ void lr16(const double* src, float (&d)[16]) {
 }
 typedef float sk_f32x16 __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
-  const __hip_bfloat16 x = __float2bfloat16(a), y = __float2bfloat16(b);
-  return uint32_t(*reinterpret_cast<const uint16_t*>(&x)) |
-         (uint32_t(*reinterpret_cast<const uint16_t*>(&y)) << 16);
+template <typename T16>
+__device__ __forceinline__ uint32_t pack16(float a, float b) {
+  return uint32_t(to16(a, static_cast<T16*>(nullptr))) | (uint32_t(to16(b, static_cast<T16*>(nullptr))) << 16);
 }
+typedef _Float16 sk_f16x8 __attribute__((ext_vector_type(8)));
 
 // Yacc (s x ncol, ld s, FP32) (+)= X (s x kc, BF16, ld kc) * Bop (kc x ncol), Bop(k, c) =
 // A[(r0 + k) + c lda] (tall) or A[c + (r0 + k) lda] (wide), rounded to BF16.
@@ -534,13 +555,12 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
 // split of the tile grid (sR x cR tiles each), walked row by row: the
 // workgroups running together on one XCD share their X rows and A columns in
 // that XCD's L2, and each operand panel is fetched by ps or pc XCDs only.
-template <typename TA, bool WIDE, int KB, int ST>
-__global__ void __launch_bounds__(256, ST == 256 ? 2 : 1) k_sketch_gemm_bf16(const __hip_bfloat16* __restrict__ X,
-                                                          int64_t s, int64_t kc, int64_t ldx,
-                                                          int64_t ksz,
-                                                          const TA* __restrict__ A, int64_t lda,
-                                                          int64_t r0, int64_t ncol, int sR, int cR,
-                                                          int pc, float* __restrict__ Y, int first) {
+template <typename T16, typename TA, bool WIDE, int KB, int ST>
+__device__ __forceinline__ void sketch_gemm_body(const uint16_t* __restrict__ X, int64_t s, int64_t kc,
+                                                 int64_t ldx, int64_t ksz, const TA* __restrict__ A,
+                                                 int64_t lda, int64_t r0, int64_t ncol, int sR, int cR,
+                                                 int pc, float* __restrict__ Y, int first,
+                                                 const float* __restrict__ cscale) {
   static_assert(KB % 32 == 0 && KB <= 128, "k per step");
   static_assert(ST == 128 || ST == 256, "sketch rows per tile");
   constexpr int LP = KB + 8;              // LDS row pitch in bf16
@@ -636,11 +656,13 @@ __global__ void __launch_bounds__(256, ST == 256 ? 2 : 1) k_sketch_gemm_bf16(con
     }
     if (!WIDE) {
       const int col = tid >> 1, half = tid & 1;
+      // the column's power-of-two scale (FP16 operands), exact
+      const float sc = cscale ? cscale[min(c0 + col, ncol - 1)] : 1.f;
 #pragma unroll
       for (int h = 0; h < HK / 8; ++h)
         *reinterpret_cast<uint4*>(&Bs[col * LP + half * HK + 8 * h]) =
-            make_uint4(pack_bf16(rb[8 * h], rb[8 * h + 1]), pack_bf16(rb[8 * h + 2], rb[8 * h + 3]),
-                       pack_bf16(rb[8 * h + 4], rb[8 * h + 5]), pack_bf16(rb[8 * h + 6], rb[8 * h + 7]));
+            make_uint4(pack16<T16>(sc * rb[8 * h], sc * rb[8 * h + 1]), pack16<T16>(sc * rb[8 * h + 2], sc * rb[8 * h + 3]),
+                       pack16<T16>(sc * rb[8 * h + 4], sc * rb[8 * h + 5]), pack16<T16>(sc * rb[8 * h + 6], sc * rb[8 * h + 7]));
     } else {
       // column 4 c4 + j gets its WK k values, 8 bytes (4 k) per write
       const int c4 = tid & 31, k4 = tid >> 5;
@@ -649,23 +671,23 @@ __global__ void __launch_bounds__(256, ST == 256 ? 2 : 1) k_sketch_gemm_bf16(con
 #pragma unroll
         for (int g = 0; g < WK / 4; ++g)
           *reinterpret_cast<uint2*>(&Bs[(4 * c4 + j) * LP + WK * k4 + 4 * g]) =
-              make_uint2(pack_bf16(rb[4 * (4 * g) + j], rb[4 * (4 * g + 1) + j]),
-                         pack_bf16(rb[4 * (4 * g + 2) + j], rb[4 * (4 * g + 3) + j]));
+              make_uint2(pack16<T16>(rb[4 * (4 * g) + j], rb[4 * (4 * g + 1) + j]),
+                         pack16<T16>(rb[4 * (4 * g + 2) + j], rb[4 * (4 * g + 3) + j]));
     }
   };
   auto stash_ragged = [&](int64_t k0) {         // element by element, zeros outside
     for (int e = tid; e < ST * KB; e += 256) {
       const int r = e / KB, kk = e % KB;
       const int64_t k = k0 + kk, q = q0 + r;
-      Xs[r * LP + kk] = (q < s && k < ke) ? *reinterpret_cast<const uint16_t*>(X + q * ldx + k) : 0;
+      Xs[r * LP + kk] = (q < s && k < ke) ? X[q * ldx + k] : 0;
     }
     for (int e = tid; e < 128 * KB; e += 256) {
       const int r = e / KB, kk = e % KB;
       const int64_t k = k0 + kk, c = c0 + r;
       const float v = (c < ncol && k < ke) ? float(WIDE ? A[c + (r0 + k) * lda] : A[(r0 + k) + c * lda])
                                            : 0.f;
-      const __hip_bfloat16 h = __float2bfloat16(v);
-      Bs[r * LP + kk] = *reinterpret_cast<const uint16_t*>(&h);
+      const float sc = (cscale && c < ncol) ? cscale[c] : 1.f;
+      Bs[r * LP + kk] = to16(sc * v, static_cast<T16*>(nullptr));
     }
   };
   if (whole(kb)) {
@@ -683,23 +705,29 @@ __global__ void __launch_bounds__(256, ST == 256 ? 2 : 1) k_sketch_gemm_bf16(con
     Bs = Bs2[buf];
 #pragma unroll
     for (int ks = 0; ks < KB / 16; ++ks) {
-      sk_bf16x8 av[AT], bv[2];
+      uint4 av[AT], bv[2];
       const int kofs = ks * 16 + 8 * (lane >> 5);
 #pragma unroll
       for (int t = 0; t < AT; ++t) {
         const int row = wq * (ST / 2) + t * 32 + (lane & 31);
-        av[t] = __builtin_bit_cast(sk_bf16x8, *reinterpret_cast<const uint4*>(&Xs[row * LP + kofs]));
+        av[t] = *reinterpret_cast<const uint4*>(&Xs[row * LP + kofs]);
       }
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         const int col = wc * 64 + t * 32 + (lane & 31);
-        bv[t] = __builtin_bit_cast(sk_bf16x8, *reinterpret_cast<const uint4*>(&Bs[col * LP + kofs]));
+        bv[t] = *reinterpret_cast<const uint4*>(&Bs[col * LP + kofs]);
       }
 #pragma unroll
       for (int a = 0; a < AT; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < 2; ++b) {
+          if constexpr (std::is_same<T16, _Float16>::value)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(sk_f16x8, av[a]),
+                                                               __builtin_bit_cast(sk_f16x8, bv[b]), acc[a][b], 0, 0, 0);
+          else
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(sk_bf16x8, av[a]),
+                                                                __builtin_bit_cast(sk_bf16x8, bv[b]), acc[a][b], 0, 0, 0);
+        }
     }
     // the next step goes to the other stage: one barrier per step
     Xs = Xs2[buf ^ 1];
@@ -724,6 +752,33 @@ __global__ void __launch_bounds__(256, ST == 256 ? 2 : 1) k_sketch_gemm_bf16(con
       }
 }
 
+
+template <typename TA, bool WIDE, int KB, int ST>
+__global__ void __launch_bounds__(256, ST == 256 ? 2 : 1) k_sketch_gemm_bf16(const __hip_bfloat16* __restrict__ X,
+                                                          int64_t s, int64_t kc, int64_t ldx,
+                                                          int64_t ksz,
+                                                          const TA* __restrict__ A, int64_t lda,
+                                                          int64_t r0, int64_t ncol, int sR, int cR,
+                                                          int pc, float* __restrict__ Y, int first) {
+  sketch_gemm_body<__hip_bfloat16, TA, WIDE, KB, ST>(reinterpret_cast<const uint16_t*>(X), s, kc, ldx, ksz, A,
+                                                     lda, r0, ncol, sR, cR, pc, Y, first, nullptr);
+}
+
+// The FP16 product of a tall problem: A's column c enters times cscale[c], a
+// power of two that puts the column's largest entry in [1, 2), so FP16's
+// range holds it; the caller divides the sketch's column c by the same power.
+template <typename TA, int KB, int ST>
+__global__ void __launch_bounds__(256, ST == 256 ? 2 : 1) k_sketch_gemm_f16(const _Float16* __restrict__ X,
+                                                         int64_t s, int64_t kc, int64_t ldx,
+                                                         int64_t ksz,
+                                                         const TA* __restrict__ A, int64_t lda,
+                                                         int64_t r0, int64_t ncol, int sR, int cR,
+                                                         int pc, float* __restrict__ Y, int first,
+                                                         const float* __restrict__ cscale) {
+  sketch_gemm_body<_Float16, TA, false, KB, ST>(reinterpret_cast<const uint16_t*>(X), s, kc, ldx, ksz, A, lda,
+                                                r0, ncol, sR, cR, pc, Y, first, cscale);
+}
+
 // Y (count floats) = [Y +] sum_z part[z] in order z = 0, 1, ... (deterministic).
 __global__ void k_sketch_reduce(const float* __restrict__ part, int nz, int64_t count,
                                 float* __restrict__ Y, int first) {
@@ -737,6 +792,34 @@ __global__ void k_sketch_reduce(const float* __restrict__ part, int nz, int64_t 
 __global__ void k_f32_to_f64(const float* __restrict__ src, double* __restrict__ dst, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = double(src[i]);
+}
+
+// dst (s x ncol) = src / cscale[column]: undoes the power-of-two column scaling
+// of the FP16 product exactly.
+__global__ void k_f32_to_f64_cols(const float* __restrict__ src, double* __restrict__ dst, int64_t s,
+                                  int64_t ncol, const float* __restrict__ cscale) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < s * ncol) dst[i] = double(src[i]) / double(cscale[i / s]);
+}
+
+// cscale[c] = 2^-e with e the exponent of column c's largest |A(r, c)|
+// (largest entry scaled into [1, 2)); 1 for a zero or non-finite column.  One
+// block per column.
+template <typename TA>
+__global__ void __launch_bounds__(256) k_col_pow2(const TA* __restrict__ A, int64_t m, int64_t lda,
+                                                  float* __restrict__ cscale) {
+  __shared__ float red[4];
+  const int64_t c = blockIdx.x;
+  float mx = 0.f;
+  for (int64_t r = threadIdx.x; r < m; r += 256) mx = fmaxf(mx, fabsf(float(A[r + c * lda])));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float v = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    cscale[c] = (v > 0.f && v < INFINITY) ? ldexpf(1.f, -ilogbf(v)) : 1.f;
+  }
 }
 
 // ---------------------------------------------------------------- launchers --
@@ -810,17 +893,20 @@ int launch_srht_twopass(const void* A, int a_f32, int64_t m, int64_t lda, int64_
 }
 
 int launch_gauss_gen(uint64_t seed, int64_t s, int64_t r0, int64_t kc, int64_t ldx, void* Xc,
-                     int bf16, hipStream_t st) {
-  if (ldx < kc || (!bf16 && ldx != kc)) {
+                     int kind, hipStream_t st) {
+  if (ldx < kc || (kind == 0 && ldx != kc)) {
     set_error("internal: Gaussian chunk pitch");
     return TIK_EINVAL;
   }
   const int64_t total = ((s + 3) >> 2) * kc;
   const double scale = 1.0 / sqrt(double(s));
   ProfScope ps("sketch", st);
-  if (bf16)
+  if (kind == 1)
     hipLaunchKernelGGL(k_gauss_gen_bf16, dim3(unsigned(cdiv(total, 256))), dim3(256), 0, st, seed,
                        s, r0, kc, ldx, float(scale), static_cast<__hip_bfloat16*>(Xc));
+  else if (kind == 2)
+    hipLaunchKernelGGL(k_gauss_gen_f16, dim3(unsigned(cdiv(total, 256))), dim3(256), 0, st, seed,
+                       s, r0, kc, ldx, float(scale), static_cast<_Float16*>(Xc));
   else
     hipLaunchKernelGGL(k_gauss_gen<double>, dim3(unsigned(cdiv(total, 256))), dim3(256), 0, st,
                        seed, s, r0, kc, scale, static_cast<double*>(Xc));
@@ -865,7 +951,12 @@ int sketch_bf16_splits(int64_t s, int64_t ncol, int64_t kc, int64_t part_cap) {
 
 int launch_sketch_gemm_bf16(const void* Xc, int64_t s, int64_t kc, int64_t ldx, const void* A,
                             int a_f32, int64_t lda, int64_t r0, int64_t ncol, int wide, float* Yacc,
-                            int first, float* part, int64_t part_cap, hipStream_t st) {
+                            int first, float* part, int64_t part_cap, hipStream_t st,
+                            const float* cscale) {
+  if (cscale && wide) {
+    set_error("internal: the FP16 sketch product is for tall problems");
+    return TIK_EINVAL;
+  }
   int nz = sketch_bf16_splits(s, ncol, kc, part_cap);
   const int64_t ksz = cdiv(cdiv(kc, nz), SK_KB) * SK_KB;
   nz = int(cdiv(kc, ksz));
@@ -894,7 +985,14 @@ int launch_sketch_gemm_bf16(const void* Xc, int64_t s, int64_t kc, int64_t ldx, 
 #define TIK_SKG(TAV, WV, STV)                                                                   \
   hipLaunchKernelGGL((k_sketch_gemm_bf16<TAV, WV, SK_KB, STV>), grid, dim3(256), 0, st, X, s, kc, \
                      ldx, ksz, static_cast<const TAV*>(A), lda, r0, ncol, sR, cR, pc, dst, first)
-  if (ST == 256) {
+#define TIK_SKH(TAV, STV)                                                                       \
+  hipLaunchKernelGGL((k_sketch_gemm_f16<TAV, SK_KB, STV>), grid, dim3(256), 0, st,              \
+                     static_cast<const _Float16*>(Xc), s, kc, ldx, ksz, static_cast<const TAV*>(A), lda, r0, \
+                     ncol, sR, cR, pc, dst, first, cscale)
+  if (cscale) {
+    if (ST == 256) { if (a_f32) TIK_SKH(float, 256); else TIK_SKH(double, 256); }
+    else           { if (a_f32) TIK_SKH(float, 128); else TIK_SKH(double, 128); }
+  } else if (ST == 256) {
     if (a_f32) { if (wide) TIK_SKG(float, true, 256); else TIK_SKG(float, false, 256); }
     else       { if (wide) TIK_SKG(double, true, 256); else TIK_SKG(double, false, 256); }
   } else {
@@ -902,7 +1000,8 @@ int launch_sketch_gemm_bf16(const void* Xc, int64_t s, int64_t kc, int64_t ldx, 
     else       { if (wide) TIK_SKG(double, true, 128); else TIK_SKG(double, false, 128); }
   }
 #undef TIK_SKG
-  TIK_LAUNCHED("k_sketch_gemm_bf16");
+#undef TIK_SKH
+  TIK_LAUNCHED("k_sketch_gemm_16");
   if (nz > 1) {
     const int64_t count = s * ncol;
     hipLaunchKernelGGL(k_sketch_reduce, dim3(unsigned(cdiv(count, 256))), dim3(256), 0, st, part,
@@ -983,6 +1082,27 @@ int launch_sparse_sketch(const void* A, int a_f32, int64_t m, int64_t n, int64_t
     hipLaunchKernelGGL(k_sparse_apply<double>, g, dim3(512), 0, st, static_cast<const double*>(A), m, lda,
                        s, zeta, nr, map, Y);
   TIK_LAUNCHED("k_sparse_apply");
+  return TIK_OK;
+}
+
+int launch_col_pow2(const void* A, int a_f32, int64_t m, int64_t n, int64_t lda, float* cscale,
+                    hipStream_t st) {
+  ProfScope ps("sketch", st);
+  if (a_f32)
+    hipLaunchKernelGGL(k_col_pow2<float>, dim3(unsigned(n)), dim3(256), 0, st, static_cast<const float*>(A), m,
+                       lda, cscale);
+  else
+    hipLaunchKernelGGL(k_col_pow2<double>, dim3(unsigned(n)), dim3(256), 0, st, static_cast<const double*>(A),
+                       m, lda, cscale);
+  TIK_LAUNCHED("k_col_pow2");
+  return TIK_OK;
+}
+
+int launch_f32_to_f64_cols(const float* src, double* dst, int64_t s, int64_t ncol, const float* cscale,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_f32_to_f64_cols, dim3(unsigned(cdiv(s * ncol, 256))), dim3(256), 0, st, src, dst, s,
+                     ncol, cscale);
+  TIK_LAUNCHED("k_f32_to_f64");
   return TIK_OK;
 }
 

@@ -229,6 +229,7 @@ struct SketchPlan {
   double* Xc[kLanes] = {};      // Gaussian X chunk (FP64 or BF16)
   float* Yacc[kLanes] = {};     // BF16 sketches: FP32 accumulator
   float* Ypart[kLanes] = {};    // BF16 sketches: split-K partial products
+  float* cscale[kLanes] = {};   // FP16 sketches: power-of-two column scales of A
   int64_t part_cap = 0;         // floats in each Ypart
   int lanes = 1;
   int64_t tcols = 0, kc = 0;
@@ -237,17 +238,18 @@ struct SketchPlan {
 // long-dimension rows of the Gaussian X generated per chunk for problem q
 static int64_t gauss_chunk(const tik_problem& q, int64_t s, int32_t sdt) {
   const int64_t longdim = tall(q) ? q.m : q.n;
-  const size_t esz = sdt == TIK_BF16 ? 2 : sizeof(double);
+  const bool h16 = sdt == TIK_BF16 || sdt == TIK_F16;
+  const size_t esz = h16 ? 2 : sizeof(double);
   int64_t kc = int64_t(SCRATCH_CHUNK / (esz * size_t(s)));
   kc = std::max<int64_t>(64, std::min<int64_t>(longdim, kc));
-  if (sdt == TIK_BF16 && kc < longdim) kc = std::max<int64_t>(32, kc / 32 * 32);
+  if (h16 && kc < longdim) kc = std::max<int64_t>(32, kc / 32 * 32);
   return kc;
 }
 
-// row pitch of a Gaussian X chunk: BF16 rows start 16-byte aligned so the
+// row pitch of a Gaussian X chunk: 16-bit rows start 16-byte aligned so the
 // sketch product fetches them with vector loads
 static int64_t gauss_pitch(int64_t kc, int32_t sdt) {
-  return sdt == TIK_BF16 ? cdiv(kc, 8) * 8 : kc;
+  return (sdt == TIK_BF16 || sdt == TIK_F16) ? cdiv(kc, 8) * 8 : kc;
 }
 
 static int sketch_plan(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sdt,
@@ -255,7 +257,7 @@ static int sketch_plan(const tik_problem* p, int32_t nprob, int32_t embed, int32
   sp.Y.assign(size_t(nprob), nullptr);
   sp.yrows.assign(size_t(nprob), 0);
   sp.ycols.assign(size_t(nprob), 0);
-  int64_t rows_ints = 0, tsz = 0, xsz = 0, ysz = 0;
+  int64_t rows_ints = 0, tsz = 0, xsz = 0, ysz = 0, csz = 0;
   for (int32_t k = 0; k < nprob; ++k) {
     const bool t = tall(p[k]);
     sp.yrows[k] = s[k];
@@ -275,10 +277,12 @@ static int sketch_plan(const tik_problem* p, int32_t nprob, int32_t embed, int32
         tsz = std::max<int64_t>(tsz, cols << kk);
       }
     } else {
-      const size_t esz = sdt == TIK_BF16 ? 2 : sizeof(double);
+      const bool h16 = sdt == TIK_BF16 || sdt == TIK_F16;
+      const size_t esz = h16 ? 2 : sizeof(double);
       xsz = std::max<int64_t>(xsz, int64_t(cdiv(gauss_pitch(gauss_chunk(p[k], s[k], sdt), sdt) *
                                                 s[k] * int64_t(esz), 8)));
-      if (sdt == TIK_BF16) {
+      if (sdt == TIK_F16) csz = std::max<int64_t>(csz, sp.ycols[k]);
+      if (h16) {
         ysz = std::max<int64_t>(ysz, s[k] * sp.ycols[k]);
         const int64_t kc = gauss_chunk(p[k], s[k], sdt);
         const int z = sketch_bf16_splits(s[k], sp.ycols[k], kc, kBf16PartCap);
@@ -293,6 +297,7 @@ static int sketch_plan(const tik_problem* p, int32_t nprob, int32_t embed, int32
     if (xsz) sp.Xc[l] = a.take<double>(size_t(xsz));
     if (ysz) sp.Yacc[l] = a.take<float>(size_t(ysz));
     if (sp.part_cap) sp.Ypart[l] = a.take<float>(size_t(sp.part_cap));
+    if (csz) sp.cscale[l] = a.take<float>(size_t(csz));
   }
   return TIK_OK;
 }
@@ -302,10 +307,14 @@ static int sketch_validate(const tik_problem* p, int32_t nprob, int32_t embed, i
   TIK_TRY(validate_problems(p, nprob, "tik_sketch"));
   if (embed != TIK_SRHT && embed != TIK_GAUSS && embed != TIK_SPARSE)
     return fail(TIK_EINVAL, "tik_sketch: embed must be TIK_SRHT, TIK_GAUSS or TIK_SPARSE");
-  if (sdt != TIK_F64 && sdt != TIK_BF16)
-    return fail(TIK_EINVAL, "tik_sketch: sketch_dtype must be TIK_F64 or TIK_BF16");
-  if (sdt == TIK_BF16 && embed != TIK_GAUSS)
-    return fail(TIK_EINVAL, "tik_sketch: TIK_BF16 sketches need the Gaussian embedding");
+  if (sdt != TIK_F64 && sdt != TIK_BF16 && sdt != TIK_F16)
+    return fail(TIK_EINVAL, "tik_sketch: sketch_dtype must be TIK_F64, TIK_BF16 or TIK_F16");
+  if ((sdt == TIK_BF16 || sdt == TIK_F16) && embed != TIK_GAUSS)
+    return fail(TIK_EINVAL, "tik_sketch: 16-bit sketches need the Gaussian embedding");
+  if (sdt == TIK_F16)
+    for (int32_t k = 0; k < nprob; ++k)
+      if (!tall(p[k]))
+        return fail(TIK_ENOTSUP, "tik_sketch: the FP16 sketch is implemented for tall problems only");
   if (!s) return fail(TIK_EINVAL, "tik_sketch: s is NULL");
   for (int32_t k = 0; k < nprob; ++k) {
     const int64_t longdim = tall(p[k]) ? p[k].m : p[k].n;
@@ -533,17 +542,22 @@ int tik_sketch(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sketc
       const int64_t longdim = t ? q.m : q.n;
       const int64_t ncol = t ? q.n : q.m;
       const int64_t chunk = gauss_chunk(q, s[k], sketch_dtype);
-      if (sketch_dtype == TIK_BF16) {
+      if (sketch_dtype == TIK_BF16 || sketch_dtype == TIK_F16) {
+        const bool f16 = sketch_dtype == TIK_F16;
+        if (f16) TIK_TRY(launch_col_pow2(q.A, f32, q.m, q.n, q.lda, sp.cscale[ln], st));
         for (int64_t r0 = 0; r0 < longdim; r0 += chunk) {
           const int64_t kc = std::min(chunk, longdim - r0);
           const int64_t ldx = gauss_pitch(kc, sketch_dtype);
-          TIK_TRY(launch_gauss_gen(pseed, s[k], r0, kc, ldx, sp.Xc[ln], 1, st));
+          TIK_TRY(launch_gauss_gen(pseed, s[k], r0, kc, ldx, sp.Xc[ln], f16 ? 2 : 1, st));
           TIK_TRY(launch_sketch_gemm_bf16(sp.Xc[ln], s[k], kc, ldx, q.A, f32, q.lda, r0, ncol,
                                           t ? 0 : 1,
                                           sp.Yacc[ln], r0 == 0 ? 1 : 0, sp.Ypart[ln], sp.part_cap,
-                                          st));
+                                          st, f16 ? sp.cscale[ln] : nullptr));
         }
-        TIK_TRY(launch_f32_to_f64(sp.Yacc[ln], sp.Y[k], s[k] * ncol, st));
+        if (f16)
+          TIK_TRY(launch_f32_to_f64_cols(sp.Yacc[ln], sp.Y[k], s[k], ncol, sp.cscale[ln], st));
+        else
+          TIK_TRY(launch_f32_to_f64(sp.Yacc[ln], sp.Y[k], s[k] * ncol, st));
       } else {
         TIK_HIP(hipMemsetAsync(sp.Y[k], 0, size_t(s[k]) * size_t(ncol) * sizeof(double), st));
         for (int64_t r0 = 0; r0 < longdim; r0 += chunk) {

@@ -175,15 +175,23 @@ int launch_srht_twopass(const void* A, int a_f32, int64_t m, int64_t lda, int64_
                         int k, int bbits, const int32_t* rows, int64_t s, double* T, double* Y,
                         hipStream_t st);
 // X chunk (s rows of kc generated values, row pitch ldx; FP64 needs ldx == kc)
+// kind: 0 FP64, 1 BF16, 2 FP16
 int launch_gauss_gen(uint64_t seed, int64_t s, int64_t r0, int64_t kc, int64_t ldx, void* Xc,
-                     int bf16, hipStream_t st);
+                     int kind, hipStream_t st);
 int launch_sketch_gemm_f64(const double* Xc, int64_t s, int64_t kc, const void* A, int a_f32,
                            int64_t lda, int64_t r0, int64_t ncol, int wide, double* Y,
                            hipStream_t st);
 int sketch_bf16_splits(int64_t s, int64_t ncol, int64_t kc, int64_t part_cap);
+// 16-bit sketch product: BF16 when cscale is NULL, else FP16 with A's columns
+// times cscale (tall problems only)
 int launch_sketch_gemm_bf16(const void* Xc, int64_t s, int64_t kc, int64_t ldx, const void* A,
                             int a_f32, int64_t lda, int64_t r0, int64_t ncol, int wide, float* Yacc,
-                            int first, float* part, int64_t part_cap, hipStream_t st);
+                            int first, float* part, int64_t part_cap, hipStream_t st,
+                            const float* cscale = nullptr);
+int launch_col_pow2(const void* A, int a_f32, int64_t m, int64_t n, int64_t lda, float* cscale,
+                    hipStream_t st);
+int launch_f32_to_f64_cols(const float* src, double* dst, int64_t s, int64_t ncol, const float* cscale,
+                           hipStream_t st);
 int launch_f32_to_f64(const float* src, double* dst, int64_t count, hipStream_t st);
 // sparse embedding of a tall A (m x n): map holds m * zeta ints; Y s x n (ld s)
 int launch_sparse_sketch(const void* A, int a_f32, int64_t m, int64_t n, int64_t lda, int64_t s,

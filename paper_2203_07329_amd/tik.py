@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(_HERE, "libtik.so")
 # enums (include/tik.h)
 OK, EINVAL, EWORKSPACE, EHIP, ENOTSUP = 0, -1, -2, -3, -4
 ST_CONVERGED, ST_MAXIT, ST_NOTPD, ST_IR_STALL, ST_NONFINITE, ST_QR = 0, 1, 2, 3, 4, 5
-F64, F32, BF16 = 0, 1, 2
+F64, F32, BF16, F16 = 0, 1, 2, 3
 SRHT, GAUSS, SPARSE = 0, 1, 2
 ROUTE_CHOL, ROUTE_LOWRANK = 0, 1
 PLAIN_F64_PER_LAMBDA, F64_BATCHED, MIXED_BATCHED = 0, 1, 2

@@ -234,3 +234,12 @@ def test_record_times_option_and_query_without_call():
         tik.set_option("record_times", old)
     with pytest.raises(tik.TikError):
         tik.lsqr_times(3, 7)       # no call of that size was recorded on this thread
+
+
+def test_f16_sketch_rejects_wide_and_non_gaussian():
+    rc, _ = _bytes(_probs(m=10, n=100), sdt=tik.F16, embed=tik.GAUSS, s=(40,))
+    assert rc == tik.ENOTSUP                    # wide: the FP16 sketch is for tall problems
+    rc, _ = _bytes(_probs(m=100, n=10), sdt=tik.F16, embed=tik.SRHT, s=(40,))
+    assert rc == tik.EINVAL                     # 16-bit sketches are Gaussian
+    rc, nb = _bytes(_probs(m=100, n=10), sdt=tik.F16, embed=tik.GAUSS, s=(40,))
+    assert rc == tik.OK and nb > 0

@@ -612,3 +612,58 @@ def test_size_limits_on_the_gpu():
         err = oracle.rel_err(res.x_numpy(0), oracle.solve(A, b, lams))
         print("gauss", mm, nn, ss, sdt, "max rel err %.2e" % err.max(), res.iters.cpu().numpy()[0])
         assert np.all(err <= 1e-10), (mm, nn, ss, sdt, err)
+
+
+# -------------------------------------------------------------- FP16 sketch ----
+
+def _f16_colscale(A):
+    """2^-e per column, e the exponent of the column's largest |entry| (largest scaled into [1, 2))."""
+    mx = np.max(np.abs(A), axis=0).astype(np.float64)
+    _, e = np.frexp(mx)                      # mx = f 2^e, f in [0.5, 1)
+    return np.where(mx > 0, np.ldexp(1.0, -(e - 1)), 1.0)
+
+
+@pytest.mark.parametrize("m,s", [(1000, 64), (2999, 200), (4101, 4100)])
+def test_f16_sketch_matches_rounded_gaussian(m, s):
+    """TIK_F16: X is the Gaussian of the FP64 path rounded to FP16; A's columns enter scaled by
+    powers of two (so columns whose entries span 1e-8 .. 1e8 keep FP16's precision) and the
+    sketch is X_f16 (A D)_f16 D^{-1} with FP32 accumulation."""
+    I = np.eye(m)
+    pr = tik.Problems.from_numpy([I], [np.ones(m)])
+    Xh = tik.sketch(pr, tik.GAUSS, [s], 21, sketch_dtype=tik.F16).Y(0)
+    Xd = tik.sketch(pr, tik.GAUSS, [s], 21).Y(0)
+    ref16 = Xd.astype(np.float16).astype(np.float64)
+    assert np.all(np.abs(Xh - Xd) <= 2.0 ** -10 * np.abs(Xd) + 2.0 ** -24)
+    assert np.mean(Xh == ref16) > 0.9
+    rng = np.random.default_rng(8)
+    for shape, dt in [((m, 37), np.float32), ((m, 130), np.float64)]:
+        A = rng.standard_normal(shape) * (10.0 ** rng.uniform(-8, 8, size=shape[1]))[None, :]
+        A = A.astype(dt)
+        pa = tik.Problems.from_numpy([A], [np.ones(m)])
+        Y = tik.sketch(pa, tik.GAUSS, [s], 21, sketch_dtype=tik.F16).Y(0)
+        d = _f16_colscale(A)
+        # the device widens or narrows A to FP32, scales (exactly), then rounds to FP16
+        As = (A.astype(np.float32) * d[None, :].astype(np.float32)).astype(np.float16).astype(np.float64)
+        ref = (Xh @ As) / d[None, :]
+        colmax = np.max(np.abs(ref), axis=0)
+        err = np.max(np.abs(Y - ref) / colmax[None, :])
+        print("fp16 sketch", m, s, shape, "max column-relative error %.2e" % err)
+        # FP32 accumulation over m products; an unscaled column of size 1e-8 would lose every
+        # entry to FP16 underflow, a wrong scale would be off by powers of two
+        assert err <= 1e-5
+
+
+def test_f16_sketch_end_to_end_and_wide_rejected():
+    p = W.over_gauss(m=20000, n=400, N=8, s=1600)            # sigma down to 1e-8: FP16 needs the scaling
+    pr = dev_problems([p])
+    pc = tik.precond(tik.sketch(pr, tik.GAUSS, [p.s], 0, sketch_dtype=tik.F16), p.lams)
+    res = tik.lsqr_batch(pr, pc, tik.F64_BATCHED, 1e-13, 300)
+    err = oracle.rel_err(res.x_numpy(0), oracle.solve(p.A, p.b, p.lams))
+    print("fp16 sketch end to end: max rel err %.2e, iterations" % err.max(), res.iters.cpu().numpy()[0])
+    assert np.all(err <= 1e-10) and np.all(res.status.cpu().numpy() == tik.ST_CONVERGED)
+    assert res.iters.cpu().numpy().max() <= 60
+    q = W.under_scaled(m=100, n=3000, N=2)
+    pw = dev_problems([q])
+    with pytest.raises(tik.TikError) as e:
+        tik.sketch(pw, tik.GAUSS, [400], 0, sketch_dtype=tik.F16)
+    assert e.value.rc == tik.ENOTSUP
