@@ -581,6 +581,19 @@ def main() -> int:
             tf = flops_launch[name] / (avg_ms / 1000.0) / 1e12
             roof["matrix_core"] = {"achieved": round(tf, 2), "peak": pk, "unit": "TFLOP/s",
                                    "frac": round(tf / pk, 4), "flops_per_launch": flops_launch[name]}
+        # one whole LSQR iteration (batched FP64 loop) against the bound of a single fused
+        # pass: max(A once plus the preconditioner's bytes at 8 TB/s, both products' flops
+        # at the matrix-core peak)
+        if ran == "f64_batched" and fam.get("gemm_n", (0, 0, 0))[1] > 0:
+            loop = [f for f in ("gemm_n", "gemm_t", "trmv", "trmv_t", "lr_apply", "vec") if f in fam]
+            it_ms = sum(fam[f][0] for f in loop) / fam["gemm_n"][1]
+            bytes_it = a_bytes + sum(per_launch.get(f, 0) for f in ("trmv", "trmv_t", "lr_apply"))
+            flops_it = 2.0 * flops_launch["gemm_n"]
+            pk = FP64_PEAK_TFS
+            bound_ms = max(bytes_it / (HBM_PEAK_GBS * 1e9), flops_it / (pk * 1e12)) * 1e3
+            roof["iteration"] = {"ms": round(it_ms, 4), "bound_ms": round(bound_ms, 4),
+                                 "frac": round(bound_ms / it_ms, 4), "families": loop,
+                                 "bytes": int(bytes_it), "flops": flops_it}
 
     # ---- per-problem latency of a batch, measured: one more (untimed) step with the
     # library recording, on the device's constant-rate clock, when each (problem,
