@@ -3248,8 +3248,6 @@ int lsqr_run(const tik_problem* p, int32_t nprob, const tik_precond_s* pc, int32
 // Text format, one class per line:
 //   wide a32 nc lm ln lp  rbN cbT blocks
 // '#' starts a comment.
-const char* g_autoload_path = nullptr;
-
 int tiles_save(const char* path) {
   tile_autoload();
   FILE* f = std::fopen(path, "w");
@@ -3267,8 +3265,15 @@ int tiles_save(const char* path) {
   return TIK_OK;
 }
 
+static int tiles_read(const char* path, int* loaded);
+
 int tiles_load(const char* path, int* loaded) {
-  if (path != g_autoload_path) tile_autoload();   // an explicit file overrides the automatic one
+  tile_autoload();   // an explicit file then overrides the automatic one
+  return tiles_read(path, loaded);
+}
+
+// Merge a table file into the table (all of it, or nothing when a line is malformed).
+static int tiles_read(const char* path, int* loaded) {
   FILE* f = std::fopen(path, "r");
   if (!f) {
     set_error(std::string("tik_tune_load: cannot open ") + path);
@@ -3315,12 +3320,10 @@ void tile_autoload() {
     std::string dir(info.dli_fname);
     const size_t slash = dir.rfind('/');
     dir = slash == std::string::npos ? std::string(".") : dir.substr(0, slash);
-    static std::string path;
-    path = dir + "/tuning.txt";
+    const std::string path = dir + "/tuning.txt";
     if (FILE* f = std::fopen(path.c_str(), "r")) {
       std::fclose(f);
-      g_autoload_path = path.c_str();
-      (void)tiles_load(path.c_str(), nullptr);   // a malformed file leaves the defaults in place
+      (void)tiles_read(path.c_str(), nullptr);   // a malformed file leaves the defaults in place
     }
   });
 }
