@@ -213,7 +213,16 @@ def test_svd_rank_deficient_sketch_mixes_panel_paths():
     b = A @ rng.standard_normal(n) + 1e-3 * rng.standard_normal(m)
     lams = np.logspace(-4, -1, N)
     p = W.Problem("rank10", A, b, lams, 64, "gauss", "lowrank", 1e-10, 0)
-    pr, sk, pc = _lowrank([p])
+    tik.prof_reset()
+    tik.prof_enable(True)
+    try:
+        pr, sk, pc = _lowrank([p])
+        col_panels = tik.prof_query("lr_colqr")[1]
+        cqr_panels = tik.prof_query("lr_cqr_recon")[1]
+    finally:
+        tik.prof_enable(False)
+    print("panels: column by column", col_panels, "Cholesky QR", cqr_panels)
+    assert col_panels >= 1 and cqr_panels >= 1
     Y = sk.Y(0)
     sig_o = np.linalg.svd(Y, compute_uv=False)
     sig = pc.sigma(0)
