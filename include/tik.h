@@ -373,6 +373,16 @@ int tik_version(void);
                   has a pivot below 1e-10 (kappa above about 1e5) is factored
                   column by column instead.  0: always column by column (one
                   launch per column).
+   "srht_cols"    1 (default): an SRHT sketch with m' >= 2^14, at least 256
+                  columns and s <= 8192 transforms each column in one
+                  workgroup (buckets of 2^14 rows in LDS, the sampled rows
+                  summed across buckets with their Hadamard signs): A is read
+                  once and no transform scratch is used.  0: the two-pass
+                  transform with a column-chunk scratch.  Both give the same
+                  X; sums are taken in a different order, so Y can differ in
+                  the last bits (integer-valued A gives identical Y).
+                  tik_sketch_bytes reflects the setting at the time of the
+                  query.
    "record_times"  1: tik_lsqr_batch records, for every (problem, lambda)
                   of a batched FP64 or plain per-lambda call, the device wall
                   clock when its iteration stopped, and tik_lsqr_times returns

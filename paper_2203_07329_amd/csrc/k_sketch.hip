@@ -330,6 +330,148 @@ __global__ void __launch_bounds__(256) k_srht_pass2(const double* __restrict__ T
     Y[q + (c0 + cc) * s] = lbuf[rows[q] - base] * scale;
 }
 
+// Column-resident SRHT for m' = 2^k >= 2^14: one 512-thread workgroup per
+// column (the bucket fills most of a CU's LDS, so one workgroup per CU).
+// Writing a row index as r = hi 2^14 + lo, H_{2^k} = H_{2^(k-14)} (x) H_{2^14},
+// so entry (ihi, ilo) of H D a is the sum over buckets hi of
+// (-1)^popcount(ihi & hi) times entry ilo of H_{2^14} applied to bucket hi.
+// Each bucket of 2^14 rows is transformed in LDS in three register phases (32
+// entries per thread: five, five and four butterfly stages) and every sampled
+// row adds its entry with its sign, so A is read from HBM once and only Y is
+// written.  Buckets wholly beyond row m are zero and skipped.  Loading the next
+// bucket into registers while the current one is transformed was measured
+// slower (1.45 against 1.08 ms for the 200000 x 2000 sketch with s = 8000: the
+// extra 64 registers spill), as were buckets of 2^13 rows with two workgroups
+// per CU (1.85 ms: 32 sampled rows per thread spill).
+static constexpr int SRC_BITS = 14;
+static constexpr int SRC_T = 1 << (SRC_BITS - 5);
+// two doubles of padding per 32 entries: a thread's run of 32 consecutive
+// entries starts 34 doubles after its neighbour's, four banks further on
+__device__ __forceinline__ int src_pad(int x) { return x + 2 * (x >> 5); }
+
+// butterfly stages of v over the low NB bits of the register index
+template <int NB>
+__device__ __forceinline__ void fwht32_low(double (&v)[32]) {
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int hh = 1 << b;
+#pragma unroll
+    for (int j = 0; j < 32; ++j)
+      if ((j & hh) == 0) {
+        const double a = v[j], c = v[j + hh];
+        v[j] = a + c;
+        v[j + hh] = a - c;
+      }
+  }
+}
+
+template <typename TA, int QV>
+__global__ void __launch_bounds__(SRC_T) k_srht_cols(const TA* __restrict__ A, int64_t m,
+                                                     int64_t lda,
+                                                     const uint32_t* __restrict__ signs,
+                                                     const int32_t* __restrict__ rows, int64_t s,
+                                                     double scale, double* __restrict__ Y) {
+  constexpr int BITS = SRC_BITS;
+  constexpr int B = 1 << BITS;
+  constexpr int T = SRC_T;   // threads, and sign words per bucket
+  __shared__ double lb[B + B / 16];
+  __shared__ uint32_t sg[2][T];
+  const int t = threadIdx.x;
+  const TA* col = A + int64_t(blockIdx.x) * lda;
+  const int m32 = int(m);
+  const int nbk = (m32 + B - 1) >> BITS;
+  // sampled row q = t + T u: its padded LDS position within a bucket in the
+  // low 15 bits, its bucket index ihi above them (-1: no such row)
+  int32_t gq[QV];
+  double acc[QV];
+#pragma unroll
+  for (int u = 0; u < QV; ++u) {
+    const int64_t q = t + int64_t(T) * u;
+    const int32_t r = q < s ? rows[q] : -1;
+    gq[u] = r < 0 ? -1 : ((r >> BITS) << 15) | src_pad(r & (B - 1));
+    acc[u] = 0.0;
+  }
+  // phase 1: register j holds lo = T j + t (coalesced).  Buffer loads through a
+  // resource based at the bucket's first row and bounded at row m, with the
+  // whole offset in the VGPR: entries past row m lie outside the resource and
+  // read as zero (the select zeroes them again).
+  TA raw[32];
+  auto load = [&](int hi) {
+    const int r0 = hi << BITS;
+    const int nrec = m32 - r0;
+    // stride 0 (raw buffer), size in bytes, and the gfx9 word 3 for untyped
+    // dword access
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<TA*>(col + r0), 0, nrec * int(sizeof(TA)), 0x00020000);
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      const int lo = j * T + t;
+      TA x;
+      if constexpr (sizeof(TA) == 8)
+        x = __builtin_bit_cast(TA, __builtin_amdgcn_raw_buffer_load_b64(rs, lo * 8, 0, 0));
+      else
+        x = __builtin_bit_cast(TA, __builtin_amdgcn_raw_buffer_load_b32(rs, lo * 4, 0, 0));
+      raw[j] = lo < nrec ? x : TA(0);
+    }
+  };
+  sg[0][t] = signs[t];
+  __syncthreads();
+  // LDS positions as a per-thread base plus a constant per register
+  const int b1 = t + 2 * (t >> 5);                       // src_pad(T j + t) = b1 + (17 T / 16) j
+  const int b2 = 34 * t;                                 // src_pad(32 t + j) = b2 + j
+  const int b3 = src_pad((t & 31) | ((t >> 5) << 10));   // src_pad(lo3 | 32 j) = b3 + 34 j
+  // one bucket; with `more` the next bucket's sign words are staged (the last
+  // bucket is peeled off below)
+  auto bucket = [&](int hi, auto more_tag) {
+    constexpr bool more = decltype(more_tag)::value;
+    load(hi);
+    const uint32_t* sgc = sg[hi & 1];
+    double v[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      const double x = double(raw[j]);
+      v[j] = ((sgc[j * (T / 32) + (t >> 5)] >> (t & 31)) & 1u) ? -x : x;
+    }
+    // the next bucket's sign word, staged in LDS before the gather
+    uint32_t snext = 0;
+    if (more) snext = signs[int64_t(hi + 1) * T + t];
+    fwht32_low<5>(v);  // lo bits BITS-5 .. BITS-1
+    __syncthreads();   // every thread has gathered from the previous bucket
+#pragma unroll
+    for (int j = 0; j < 32; ++j) lb[b1 + (17 * T / 16) * j] = v[j];
+    __syncthreads();
+    // phase 2: thread t holds lo = 32 t + j
+#pragma unroll
+    for (int j = 0; j < 32; ++j) v[j] = lb[b2 + j];
+    fwht32_low<5>(v);  // lo bits 0..4
+#pragma unroll
+    for (int j = 0; j < 32; ++j) lb[b2 + j] = v[j];
+    __syncthreads();
+    // phase 3: lo bits 0..4 from t % 32, 5..9 from j, 10.. from t / 32; the
+    // bits from BITS - 5 on were done in phase 1
+#pragma unroll
+    for (int j = 0; j < 32; ++j) v[j] = lb[b3 + 34 * j];
+    fwht32_low<BITS - 10>(v);  // lo bits 5 .. BITS-6
+#pragma unroll
+    for (int j = 0; j < 32; ++j) lb[b3 + 34 * j] = v[j];
+    if (more) sg[(hi + 1) & 1][t] = snext;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < QV; ++u)
+      if (gq[u] >= 0) {
+        const double z = lb[gq[u] & 0x7FFF];
+        acc[u] += (__popc(uint32_t(gq[u] >> 15) & uint32_t(hi)) & 1) ? -z : z;
+      }
+  };
+  for (int hi = 0; hi + 1 < nbk; ++hi) bucket(hi, std::true_type{});
+  bucket(nbk - 1, std::false_type{});
+#pragma unroll
+  for (int u = 0; u < QV; ++u) {
+    const int64_t q = t + int64_t(T) * u;
+    if (q < s) Y[q + int64_t(blockIdx.x) * s] = acc[u] * scale;
+  }
+}
+
 // ---------------------------------------------------------------- Gaussian --
 // Entry (q, r) of the s x (long dim) Gaussian matrix: Philox of counter
 // (r, q/4) gives four 32-bit words, Box-Muller turns them into four normals
@@ -889,6 +1031,42 @@ int launch_srht_twopass(const void* A, int a_f32, int64_t m, int64_t lda, int64_
   hipLaunchKernelGGL(k_srht_pass2, dim3(1u << abits, unsigned(nc)), dim3(256), lds, st, T, c0, k,
                      bbits, rows, bstart, s, 1.0 / sqrt(double(s)), Y);
   TIK_LAUNCHED("k_srht_pass2");
+  return TIK_OK;
+}
+
+bool srht_cols_ok(int k, int64_t n, int64_t s) {
+  return k >= SRC_BITS && k <= 30 && n >= kSrhtColsMinN && s <= 8192;
+}
+
+template <typename TA>
+static void srht_cols_launch(const TA* A, int64_t m, int64_t n, int64_t lda, const uint32_t* signs,
+                             const int32_t* rows, int64_t s, double scale, double* Y,
+                             hipStream_t st) {
+  const dim3 grid = dim3(unsigned(n)), block = dim3(SRC_T);
+  static_assert(8192 == 16 * SRC_T, "sampled rows per thread");
+  if (s <= 8 * SRC_T)
+    hipLaunchKernelGGL((k_srht_cols<TA, 8>), grid, block, 0, st, A, m, lda, signs, rows, s, scale, Y);
+  else
+    hipLaunchKernelGGL((k_srht_cols<TA, 16>), grid, block, 0, st, A, m, lda, signs, rows, s, scale, Y);
+}
+
+// Column-resident transform of every column; rows | bstart | signs laid out by
+// the caller with buckets of 2^bbits rows.
+int launch_srht_cols(const void* A, int a_f32, int64_t m, int64_t n, int64_t lda, int k, int bbits,
+                     const int32_t* rows, int64_t s, double* Y, hipStream_t st) {
+  if (!srht_cols_ok(k, n, s)) {
+    set_error("internal: column-resident SRHT outside its range");
+    return TIK_EINVAL;
+  }
+  const int32_t* bstart = rows + s;
+  const uint32_t* signs = signs_of(bstart, k, bbits);
+  const double scale = 1.0 / sqrt(double(s));
+  ProfScope ps("sketch", st);
+  if (a_f32)
+    srht_cols_launch(static_cast<const float*>(A), m, n, lda, signs, rows, s, scale, Y, st);
+  else
+    srht_cols_launch(static_cast<const double*>(A), m, n, lda, signs, rows, s, scale, Y, st);
+  TIK_LAUNCHED("k_srht_cols");
   return TIK_OK;
 }
 

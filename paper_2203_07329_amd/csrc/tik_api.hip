@@ -98,9 +98,11 @@ std::atomic<int> g_opt_chunk{4};
 std::atomic<int64_t> g_opt_pivot{0};
 std::atomic<int> g_opt_nnz{1};
 std::atomic<int> g_opt_cqr{1};
+std::atomic<int> g_opt_srht_cols{1};
 }
 int option_sparse_nnz() { return g_opt_nnz.load(std::memory_order_relaxed); }
 int option_cholqr_panels() { return g_opt_cqr.load(std::memory_order_relaxed); }
+int option_srht_cols() { return g_opt_srht_cols.load(std::memory_order_relaxed); }
 int option_chunk() { return g_opt_chunk.load(std::memory_order_relaxed); }
 int64_t option_pivot_ulps() { return g_opt_pivot.load(std::memory_order_relaxed); }
 
@@ -252,6 +254,11 @@ static int64_t gauss_pitch(int64_t kc, int32_t sdt) {
   return (sdt == TIK_BF16 || sdt == TIK_F16) ? cdiv(kc, 8) * 8 : kc;
 }
 
+// the column-resident transform where it applies and is not switched off
+static bool srht_cols_use(int k, int64_t n, int64_t s) {
+  return option_srht_cols() && srht_cols_ok(k, n, s);
+}
+
 static int sketch_plan(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sdt,
                        const int64_t* s, Arena& a, SketchPlan& sp) {
   sp.Y.assign(size_t(nprob), nullptr);
@@ -270,7 +277,7 @@ static int sketch_plan(const tik_problem* p, int32_t nprob, int32_t embed, int32
       const int bb = kk <= 13 ? kk : 13;
       rows_ints = std::max<int64_t>(rows_ints, s[k] + (int64_t(1) << (kk - bb)) + 1 +
                                                    (((int64_t(1) << kk) + 31) >> 5));
-      if (kk > 13) {
+      if (kk > 13 && !srht_cols_use(kk, p[k].n, s[k])) {
         const int64_t cols = std::max<int64_t>(
             1, std::min<int64_t>(p[k].n, int64_t(SCRATCH_CHUNK / (sizeof(double) << kk))));
         sp.tcols = std::max(sp.tcols, cols);
@@ -408,6 +415,11 @@ int tik_set_option(const char* name, int64_t value) {
     g_opt_cqr.store(int(value));
     return TIK_OK;
   }
+  if (std::string(name) == "srht_cols") {
+    if (value < 0 || value > 1) return fail(TIK_EINVAL, "tik_set_option: srht_cols must be 0 or 1");
+    g_opt_srht_cols.store(int(value));
+    return TIK_OK;
+  }
   if (std::string(name) == "chol_pivot_ulps") {
     if (value < 0 || value > (int64_t(1) << 53))
       return fail(TIK_EINVAL, "tik_set_option: chol_pivot_ulps must be 0..2^53");
@@ -437,6 +449,10 @@ int tik_get_option(const char* name, int64_t* value) {
   }
   if (std::string(name) == "record_times") {
     *value = option_record_times() ? 1 : 0;
+    return TIK_OK;
+  }
+  if (std::string(name) == "srht_cols") {
+    *value = option_srht_cols();
     return TIK_OK;
   }
   return fail(TIK_EINVAL, std::string("tik_get_option: unknown option ") + name);
@@ -530,6 +546,8 @@ int tik_sketch(const tik_problem* p, int32_t nprob, int32_t embed, int32_t sketc
       TIK_TRY(launch_srht_rows(pseed, kk, s[k], rows, bstart, bb, st));
       if (kk <= 13) {
         TIK_TRY(launch_srht_single(q.A, f32, q.m, q.n, q.lda, kk, pseed, rows, s[k], sp.Y[k], st));
+      } else if (srht_cols_use(kk, q.n, s[k])) {
+        TIK_TRY(launch_srht_cols(q.A, f32, q.m, q.n, q.lda, kk, bb, rows, s[k], sp.Y[k], st));
       } else {
         for (int64_t c0 = 0; c0 < q.n; c0 += sp.tcols) {
           const int64_t nc = std::min(sp.tcols, q.n - c0);

@@ -69,6 +69,9 @@ int option_sparse_nnz();
 // reflectors, falling back to one launch per column where the panel's scaled
 // Gram matrix is nearly singular; 0: one launch per column always.
 int option_cholqr_panels();
+// 1: SRHT sketches use the column-resident transform where it applies (0: the
+// two-pass transform everywhere).
+int option_srht_cols();
 
 // --------------------------------------------------------------- workspace --
 // Bump allocator over a caller-provided device buffer.  With base == nullptr it
@@ -174,6 +177,12 @@ int launch_srht_single(const void* A, int a_f32, int64_t m, int64_t n, int64_t l
 int launch_srht_twopass(const void* A, int a_f32, int64_t m, int64_t lda, int64_t c0, int64_t nc,
                         int k, int bbits, const int32_t* rows, int64_t s, double* T, double* Y,
                         hipStream_t st);
+// Column-resident SRHT (one read of A, no scratch) for m' >= 2^14, at least
+// kSrhtColsMinN columns (one workgroup each) and s <= 8192.
+constexpr int64_t kSrhtColsMinN = 256;
+bool srht_cols_ok(int k, int64_t n, int64_t s);
+int launch_srht_cols(const void* A, int a_f32, int64_t m, int64_t n, int64_t lda, int k, int bbits,
+                     const int32_t* rows, int64_t s, double* Y, hipStream_t st);
 // X chunk (s rows of kc generated values, row pitch ldx; FP64 needs ldx == kc)
 // kind: 0 FP64, 1 BF16, 2 FP16
 int launch_gauss_gen(uint64_t seed, int64_t s, int64_t r0, int64_t kc, int64_t ldx, void* Xc,

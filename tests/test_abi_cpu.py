@@ -236,6 +236,25 @@ def test_record_times_option_and_query_without_call():
         tik.lsqr_times(3, 7)       # no call of that size was recorded on this thread
 
 
+def test_srht_cols_option_and_workspace():
+    """The column-resident SRHT needs no transform scratch: with it switched off
+    the same sketch asks for the column-chunk scratch of the two-pass form."""
+    old = tik.get_option("srht_cols")
+    try:
+        probs = _probs(m=20000, n=256)
+        tik.set_option("srht_cols", 1)
+        rc1, b1 = _bytes(probs, embed=tik.SRHT, s=(300,))
+        tik.set_option("srht_cols", 0)
+        assert tik.get_option("srht_cols") == 0
+        rc0, b0 = _bytes(probs, embed=tik.SRHT, s=(300,))
+        assert rc0 == rc1 == tik.OK
+        assert b0 > b1
+        with pytest.raises(tik.TikError):
+            tik.set_option("srht_cols", 2)
+    finally:
+        tik.set_option("srht_cols", old)
+
+
 def test_f16_sketch_rejects_wide_and_non_gaussian():
     rc, _ = _bytes(_probs(m=10, n=100), sdt=tik.F16, embed=tik.GAUSS, s=(40,))
     assert rc == tik.ENOTSUP                    # wide: the FP16 sketch is for tall problems

@@ -89,6 +89,84 @@ def test_srht_equals_explicit_sylvester(m, n, s, seed):
     assert np.array_equal(Y, Yh)
 
 
+def _signs_rows(m, s, seed):
+    k = max(0, int(math.ceil(math.log2(m))))
+    mp = 1 << k
+    key = _key(seed)
+    rows = np.sort([0 if k == 0 else _feistel(i, k, key) for i in range(s)])
+    words = (mp + 31) >> 5
+    w = np.arange(words)
+    ctr = np.stack([w >> 2, np.zeros(words), np.full(words, TAG_SIGN), np.zeros(words)], axis=1).astype(np.uint32)
+    bits = philox4x32_10(ctr, key)[np.arange(words), w & 3].astype(np.uint64)
+    neg = ((bits[np.arange(mp) >> 5] >> (np.arange(mp) & 31).astype(np.uint64)) & np.uint64(1)).astype(bool)
+    return mp, rows, neg
+
+
+def srht_host_sylvester(A, s, seed):
+    """The same sketch through Sylvester's recursion H_2h = [[H_h, H_h], [H_h, -H_h]]
+    applied level by level to the padded, sign-flipped columns (exact on integers);
+    for orders whose explicit matrix does not fit in memory."""
+    m = A.shape[0]
+    mp, rows, neg = _signs_rows(m, s, seed)
+    Z = np.zeros((mp, A.shape[1]))
+    Z[:m] = A
+    Z[neg] *= -1.0
+    h = 1
+    while h < mp:
+        V = Z.reshape(mp // (2 * h), 2, h, -1)
+        top, bot = V[:, 0].copy(), V[:, 1].copy()
+        V[:, 0] = top + bot
+        V[:, 1] = top - bot
+        h *= 2
+    return rows, (1.0 / math.sqrt(s)) * Z[rows]
+
+
+@pytest.mark.parametrize("m,n,s,seed,f32", [(20000, 256, 300, 3, False), (40000, 260, 5000, 11, True),
+                                            (16384, 300, 8192, 2**33 + 1, False)])
+def test_srht_column_resident_equals_sylvester(m, n, s, seed, f32):
+    """The column-resident transform (m' >= 2^14, n >= 256, s <= 8192: one
+    workgroup per column, buckets of 2^14 rows) on integer data: identical to the
+    host's Sylvester recursion and to the two-pass transform, for a partial last
+    bucket, a bucket wholly past m, FP32 storage and both register layouts of the
+    sampled rows (s <= 4096 and s up to 8192)."""
+    rng = np.random.default_rng(m + n)
+    A = rng.integers(-8, 9, size=(m, n)).astype(np.float32 if f32 else np.float64)
+    pr = tik.Problems.from_numpy([A], [np.ones(m)])
+    old = tik.get_option("srht_cols")
+    try:
+        tik.set_option("srht_cols", 1)
+        Y1 = tik.sketch(pr, tik.SRHT, [s], seed).Y(0)
+        tik.set_option("srht_cols", 0)
+        Y0 = tik.sketch(pr, tik.SRHT, [s], seed).Y(0)
+    finally:
+        tik.set_option("srht_cols", old)
+    rows, Yh = srht_host_sylvester(A.astype(np.float64), s, seed)
+    assert len(set(rows.tolist())) == s
+    assert np.array_equal(Y1, Yh)
+    assert np.array_equal(Y0, Yh)
+
+
+def test_srht_column_resident_rounding_matches_two_pass():
+    """On real-valued data the two transforms sum in different orders: the
+    sketches agree to a few ulps of the column norms."""
+    m, n, s = 30000, 256, 2000
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((m, n)) * np.logspace(0, -8, n)[None, :]
+    pr = tik.Problems.from_numpy([A], [np.ones(m)])
+    old = tik.get_option("srht_cols")
+    try:
+        tik.set_option("srht_cols", 1)
+        Y1 = tik.sketch(pr, tik.SRHT, [s], 9).Y(0)
+        tik.set_option("srht_cols", 0)
+        Y0 = tik.sketch(pr, tik.SRHT, [s], 9).Y(0)
+    finally:
+        tik.set_option("srht_cols", old)
+    scale = np.linalg.norm(A, axis=0) * math.sqrt(1 << 15) / math.sqrt(s)
+    err = np.max(np.abs(Y1 - Y0) / scale[None, :])
+    print("max |Y_cols - Y_twopass| / (column scale) = %.2e" % err)
+    assert err <= 1e-14
+
+
 def _extract_X(m, s, embed, seed, sdt=tik.F64):
     I = np.eye(m)
     pr = tik.Problems.from_numpy([I], [np.ones(m)])
