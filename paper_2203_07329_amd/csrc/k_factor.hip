@@ -206,10 +206,10 @@ __global__ void k_shift_copy(const double* __restrict__ C, int64_t n, const doub
 // then B[i][j] -= R[i][k] X[k][j] for i < k <= j.  The step loops are split
 // into 4 unrolled blocks of 16 so that the register index is a constant.
 // One block per job of the table (jobs whose n <= k0 are finished and return).
-__global__ void __launch_bounds__(256) k_potrf_diag(const CholJob* __restrict__ jobs, int64_t k0) {
-  const CholJob J = jobs[blockIdx.x];
+// src: the block's input, 64 x 64 with leading dimension 64, in LDS (the
+// trailing update that produced it hands it over), or null to read it from R.
+__device__ void potrf_diag_block(const CholJob& J, int64_t k0, const double* src) {
   const int64_t n = J.n;
-  if (k0 >= n) return;                       // uniform
   double* Rm = J.R;
   double* Dinv = J.Dinv;
   const int kb = int(min<int64_t>(NB, n - k0));
@@ -225,7 +225,8 @@ __global__ void __launch_bounds__(256) k_potrf_diag(const CholJob* __restrict__ 
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = ti + 16 * p, j = tj + 16 * q;
-      a[p][q] = (i < kb && j < kb && i <= j) ? Rm[(k0 + i) + (k0 + j) * n] : 0.0;
+      a[p][q] = (i < kb && j < kb && i <= j) ? (src ? src[i + 64 * j] : Rm[(k0 + i) + (k0 + j) * n])
+                                             : 0.0;
       b[p][q] = (i == j && i < kb) ? 1.0 : 0.0;
     }
   // factorization (skipped when the job holds a factor already)
@@ -331,6 +332,12 @@ __global__ void __launch_bounds__(256) k_potrf_diag(const CholJob* __restrict__ 
   if (tid == 0 && bad) *J.notpd = 1;
 }
 
+__global__ void __launch_bounds__(256) k_potrf_diag(const CholJob* __restrict__ jobs, int64_t k0) {
+  const CholJob J = jobs[blockIdx.x];
+  if (k0 >= J.n) return;                     // uniform
+  potrf_diag_block(J, k0, nullptr);
+}
+
 // R[k0:k0+kb, cols] = D^T R[k0:k0+kb, cols] for the 64-column tile blockIdx.x
 // right of the diagonal block (D = inverse of the diagonal block).  In place:
 // the tile is read completely before it is written.
@@ -354,7 +361,11 @@ __global__ void __launch_bounds__(256) k_trsm_panel(const CholJob* __restrict__ 
 
 // Trailing update of the upper tiles: R[a, b] -= R[k, a]^T R[k, b] over the
 // panel rows k (tile pair blockIdx.x, a <= b, tiles counted from k0 + kb).
-__global__ void __launch_bounds__(256) k_syrk_trail(const CholJob* __restrict__ jobs, int64_t k0) {
+// Block 0 of each job updates the next diagonal block and then factors and
+// inverts it (the diagonal step of the next panel, from the updated values it
+// keeps in LDS): launched first, it runs beside the other tiles' updates
+// instead of in a launch of its own after them.
+__global__ void __launch_bounds__(256, 4) k_syrk_trail(const CholJob* __restrict__ jobs, int64_t k0) {
   __shared__ TileLds L;
   const CholJob J = jobs[blockIdx.y];
   const int64_t n = J.n;
@@ -372,9 +383,24 @@ __global__ void __launch_bounds__(256) k_syrk_trail(const CholJob* __restrict__ 
   f64x4 acc[2][2];
   tile_zero(acc);
   tile_mma<true, 2>(Rm + k0 + a0 * n, n, Rm + k0 + b0 * n, n, kb, na, nb, L, acc);
+  if (blockIdx.x != 0) {
+    tile_for_each(acc, [&](int i, int j, double v) {
+      if (i < na && j < nb) Rm[(a0 + i) + (b0 + j) * n] -= v;
+    });
+    return;
+  }
+  // the next diagonal block: tile_mma ended on a barrier, so its LDS is free
+  static_assert(sizeof(TileLds) >= 64 * 64 * sizeof(double), "diagonal block in the tile's LDS");
+  double* dblk = reinterpret_cast<double*>(&L);
   tile_for_each(acc, [&](int i, int j, double v) {
-    if (i < na && j < nb) Rm[(a0 + i) + (b0 + j) * n] -= v;
+    if (i < na && j < nb) {
+      const double nv = Rm[(a0 + i) + (b0 + j) * n] - v;
+      Rm[(a0 + i) + (b0 + j) * n] = nv;
+      dblk[i + 64 * j] = nv;
+    }
   });
+  __syncthreads();
+  potrf_diag_block(J, a0, dblk);
 }
 
 // Tmp[rows of tile blockIdx.x, 0:lb] = Rinv[rows, 0:l0] R[0:l0, l0:l0+lb]
@@ -523,8 +549,11 @@ int launch_chol_inv_jobs(const CholJob* jobs, const int64_t* nsz, int32_t njobs,
     for (int64_t kb = 0; kb < nblk; ++kb) {
       const int64_t k0 = kb * NB;
       const int32_t na = active(k0);
-      hipLaunchKernelGGL(k_potrf_diag, dim3(unsigned(na)), dim3(256), 0, st, jobs, k0);
-      TIK_LAUNCHED("k_potrf_diag");
+      // after the first panel the trailing update has done the diagonal step
+      if (kb == 0 || given) {
+        hipLaunchKernelGGL(k_potrf_diag, dim3(unsigned(na)), dim3(256), 0, st, jobs, k0);
+        TIK_LAUNCHED("k_potrf_diag");
+      }
       const int64_t rest = nmax - k0 - std::min<int64_t>(NB, nmax - k0);
       if (rest > 0 && !given) {
         const int32_t nr = active(k0 + NB);   // jobs with trailing columns
