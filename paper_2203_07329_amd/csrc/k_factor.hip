@@ -29,7 +29,7 @@ static constexpr int NB = 64;
 // (v_mfma_f64_16x16x4_f64).  op(A) is 64 x K: A itself (TA = false, element
 // (i, k) at A[i + k lda]) or the transpose of a K x 64 block (TA = true,
 // element (i, k) at A[k + i lda]); B is K x 64 (element (k, j) at
-// B[k + j ldb]).  Rows >= mrows, columns >= ncols and k >= K read as zero.
+// B[k + j ldb], or at B[j + k ldb] with TB).  Rows >= mrows, columns >= ncols and k >= K read as zero.
 // Wave w owns the 32 x 32 quarter (rows 32 (w & 1), columns 32 (w >> 1)) as
 // 2 x 2 MFMA tiles; K is staged through LDS 32 at a time.  Result element
 // (row 32 (w & 1) + 16 t + 4 v + lane / 16, column 32 (w >> 1) + 16 u +
@@ -49,7 +49,7 @@ struct TileLds {
 // that way (it also leaves the compiler fewer live values: 72 VGPRs instead of
 // 142 for the trailing update), while the long contractions of k_trinv_mul
 // keep DEPTH 1 (with two sets they drop to one block per CU).
-template <bool TA, int DEPTH = 1>
+template <bool TA, int DEPTH = 1, bool TB = false>
 __device__ __forceinline__ void tile_mma(const double* __restrict__ A, int64_t lda,
                                          const double* __restrict__ B, int64_t ldb, int64_t K,
                                          int mrows, int ncols, TileLds& L, f64x4 (&acc)[2][2]) {
@@ -68,9 +68,10 @@ __device__ __forceinline__ void tile_mma(const double* __restrict__ A, int64_t l
       double v = 0.0;
       if (i < mrows && k < K) v = TA ? A[k + int64_t(i) * lda] : A[i + k * lda];
       ra[q] = v;
-      const int kb = e % TK, j = e / TK;
+      int kb, j;
+      if (TB) { j = e % 64; kb = e / 64; } else { kb = e % TK; j = e / TK; }
       const int64_t kg = k0 + kb;
-      rb[q] = (j < ncols && kg < K) ? B[kg + int64_t(j) * ldb] : 0.0;
+      rb[q] = (j < ncols && kg < K) ? (TB ? B[j + kg * ldb] : B[kg + int64_t(j) * ldb]) : 0.0;
     }
   };
   auto stash = [&](const double (&ra)[Q], const double (&rb)[Q]) {
@@ -79,7 +80,8 @@ __device__ __forceinline__ void tile_mma(const double* __restrict__ A, int64_t l
       const int e = tid + 256 * q;
       if (TA) L.As[e / TK][e % TK] = ra[q];
       else L.As[e % 64][e / 64] = ra[q];
-      L.Bs[e % TK][e / TK] = rb[q];
+      if (TB) L.Bs[e / 64][e % 64] = rb[q];
+      else L.Bs[e % TK][e / TK] = rb[q];
     }
   };
   auto mma = [&]() {
@@ -361,20 +363,24 @@ __global__ void __launch_bounds__(256) k_trsm_panel(const CholJob* __restrict__ 
 
 // Trailing update of the upper tiles: R[a, b] -= R[k, a]^T R[k, b] over the
 // panel rows k (tile pair blockIdx.x, a <= b, tiles counted from k0 + kb).
-// Block 0 of each job updates the next diagonal block and then factors and
+// Tile 0 of each job updates the next diagonal block and then factors and
 // inverts it (the diagonal step of the next panel, from the updated values it
 // keeps in LDS): launched first, it runs beside the other tiles' updates
 // instead of in a launch of its own after them.
 __global__ void __launch_bounds__(256, 4) k_syrk_trail(const CholJob* __restrict__ jobs, int64_t k0) {
   __shared__ TileLds L;
-  const CholJob J = jobs[blockIdx.y];
+  // blocks in dispatch order take tile 0 of every job first, then tile 1, ...:
+  // the diagonal steps start before the other tiles, not one job at a time
+  const int64_t lin = int64_t(blockIdx.x) + int64_t(blockIdx.y) * gridDim.x;
+  const int tile = int(lin / gridDim.y);
+  const CholJob J = jobs[lin % gridDim.y];
   const int64_t n = J.n;
   double* Rm = J.R;
   if (k0 >= n) return;                       // uniform
   const int kb = int(min<int64_t>(NB, n - k0));
   const int nt = int(cdiv(n - k0 - kb, 64));    // this job's trailing tiles
-  if (int(blockIdx.x) >= nt * (nt + 1) / 2) return;   // uniform
-  int t = blockIdx.x, ta = 0;
+  if (tile >= nt * (nt + 1) / 2) return;   // uniform
+  int t = tile, ta = 0;
   while (t >= nt - ta) { t -= nt - ta; ++ta; }
   const int tb = ta + t;
   const int64_t base = k0 + kb;
@@ -383,7 +389,7 @@ __global__ void __launch_bounds__(256, 4) k_syrk_trail(const CholJob* __restrict
   f64x4 acc[2][2];
   tile_zero(acc);
   tile_mma<true, 2>(Rm + k0 + a0 * n, n, Rm + k0 + b0 * n, n, kb, na, nb, L, acc);
-  if (blockIdx.x != 0) {
+  if (tile != 0) {
     tile_for_each(acc, [&](int i, int j, double v) {
       if (i < na && j < nb) Rm[(a0 + i) + (b0 + j) * n] -= v;
     });
@@ -403,60 +409,101 @@ __global__ void __launch_bounds__(256, 4) k_syrk_trail(const CholJob* __restrict
   potrf_diag_block(J, a0, dblk);
 }
 
-// Tmp[rows of tile blockIdx.x, 0:lb] = Rinv[rows, 0:l0] R[0:l0, l0:l0+lb]
-// (Rinv upper triangular, already stored in columns < l0 with zeros below the
-// diagonal, so the contraction starts at the tile's first row).
-__global__ void __launch_bounds__(256) k_trinv_mul(const CholJob* __restrict__ jobs, int64_t l0) {
+// Triangular inverse by recursive doubling, in place.  With the diagonal
+// blocks of size s already inverted, each pair of neighbouring blocks A =
+// [A0, A0 + s), B = [A0 + s, A0 + 2 s) gets its off-diagonal block
+//   Rinv[A, B] = -Rinv[A, A] (R[A, B] Rinv[B, B])
+// in two launches over every pair and job: T = R[A, B] Rinv[B, B], kept
+// transposed in the strict lower triangle (rows B, columns A: free space), then
+// Rinv[A, B] = -Rinv[A, A] T over R[A, B].  Starting from the 64 x 64 inverses
+// of the diagonal step, log2(n / 64) levels give R^{-1}; the lower triangle is
+// cleared at the end.  Every level is a batch of 64 x 64 MFMA tiles over all
+// jobs, instead of one narrow launch per 64-column block.
+
+// Level start: each 64 x 64 diagonal block of R becomes its inverse D_l, with
+// zeros below its diagonal (contractions over a diagonal block read them).
+__global__ void __launch_bounds__(256) k_trinv_diag(const CholJob* __restrict__ jobs) {
+  const CholJob J = jobs[blockIdx.y];
+  const int64_t n = J.n;
+  const int64_t l0 = int64_t(blockIdx.x) * NB;
+  if (l0 >= n) return;                       // uniform
+  const int lb = int(min<int64_t>(NB, n - l0));
+  const double* Dm = J.Dinv + (l0 / NB) * NB * NB;
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int i = e & 63, c = e >> 6;
+    if (i < lb && c < lb) J.R[(l0 + i) + (l0 + c) * n] = (i <= c) ? Dm[i + c * NB] : 0.0;
+  }
+}
+
+// pair and tile of a level's launch: tiles of the pair numbered ti * (s / 64) + tj
+struct LvlTile {
+  int64_t a0, b0;
+  int ti, tj, bsz;
+  bool ok;
+};
+__device__ __forceinline__ LvlTile lvl_tile(int64_t n, int64_t s) {
+  const int64_t per = (s / 64) * (s / 64);
+  const int64_t p = blockIdx.x / per, r = blockIdx.x % per;
+  LvlTile t;
+  t.a0 = 2 * s * p;
+  t.b0 = t.a0 + s;
+  t.ti = int(r / (s / 64));
+  t.tj = int(r % (s / 64));
+  t.bsz = int(min<int64_t>(s, n - t.b0));
+  t.ok = t.b0 < n && 64 * t.tj < t.bsz;
+  return t;
+}
+
+// T = R[A, B] Rinv[B, B] for tile (ti, tj), stored transposed at rows B,
+// columns A.  Rinv[B, B] is upper triangular, so the contraction stops at the
+// tile's last column.
+__global__ void __launch_bounds__(256) k_trinv_lvl_t(const CholJob* __restrict__ jobs, int64_t s) {
   __shared__ TileLds L;
   const CholJob J = jobs[blockIdx.y];
   const int64_t n = J.n;
-  const double* Rm = J.R;
-  if (l0 >= n) return;                       // uniform
-  const int lb = int(min<int64_t>(NB, n - l0));
-  const int64_t r0 = int64_t(blockIdx.x) * 64;
-  const int nr = int(min<int64_t>(64, l0 - r0));
+  const LvlTile t = lvl_tile(n, s);
+  if (!t.ok) return;                         // uniform
+  double* Rm = J.R;
+  const int64_t r0 = t.a0 + 64 * t.ti, c0 = t.b0 + 64 * t.tj;
+  const int nc = int(min<int64_t>(64, t.bsz - 64 * t.tj));
+  const int64_t K = min<int64_t>(t.bsz, 64 * (t.tj + 1));
   f64x4 acc[2][2];
   tile_zero(acc);
-  tile_mma<false>(Rm + r0 + r0 * n, n, Rm + r0 + l0 * n, n, l0 - r0, nr, lb, L, acc);
-  double* Tm = J.Tmp;
+  tile_mma<false, 1>(Rm + r0 + t.b0 * n, n, Rm + t.b0 + c0 * n, n, K, 64, nc, L, acc);
   tile_for_each(acc, [&](int i, int c, double v) {
-    if (i < nr && c < lb) Tm[(r0 + i) + int64_t(c) * n] = v;
+    if (c < nc) Rm[(c0 + c) + (r0 + i) * n] = v;
   });
 }
 
-// Block column l of Rinv: rows above the diagonal block get -Tmp D_l, the
-// diagonal block gets D_l, rows below get zero (the lower triangle).
-__global__ void __launch_bounds__(256) k_trinv_fin(const CholJob* __restrict__ jobs, int64_t l0) {
+// Rinv[A, B] = -Rinv[A, A] T for tile (ti, tj); Rinv[A, A] is upper
+// triangular, so the contraction starts at the tile's first row.
+__global__ void __launch_bounds__(256, 4) k_trinv_lvl_x(const CholJob* __restrict__ jobs, int64_t s) {
   __shared__ TileLds L;
   const CholJob J = jobs[blockIdx.y];
   const int64_t n = J.n;
+  const LvlTile t = lvl_tile(n, s);
+  if (!t.ok) return;                         // uniform
   double* Rm = J.R;
-  const int64_t r0 = int64_t(blockIdx.x) * 64;
-  if (l0 >= n || r0 >= n) return;           // uniform
-  const int lb = int(min<int64_t>(NB, n - l0));
-  const int tid = threadIdx.x;
-  const double* Dm = J.Dinv + (l0 / NB) * NB * NB;
-  if (r0 >= l0 + lb || r0 == l0) {
-    // below the diagonal block (zeros) or the diagonal block itself
-    for (int e = tid; e < 64 * NB; e += 256) {
-      const int i = e & 63, c = e >> 6;
-      const int64_t r = r0 + i;
-      if (r < n && c < lb) {
-        double v = 0.0;
-        if (r0 == l0 && i <= c) v = Dm[i + c * NB];
-        Rm[r + (l0 + c) * n] = v;
-      }
-    }
-    return;
-  }
-  const double* Tm = J.Tmp;
-  const int nr = int(min<int64_t>(64, l0 - r0));
+  const int64_t r0 = t.a0 + 64 * t.ti, c0 = t.b0 + 64 * t.tj;
+  const int nc = int(min<int64_t>(64, t.bsz - 64 * t.tj));
+  const int64_t K = s - 64 * t.ti;
   f64x4 acc[2][2];
   tile_zero(acc);
-  tile_mma<false, 2>(Tm + r0, n, Dm, NB, lb, nr, lb, L, acc);
+  // T(k, j) of this tile sits at Rm[(c0 + j) + (r0 + k) n]
+  tile_mma<false, 1, true>(Rm + r0 + r0 * n, n, Rm + c0 + r0 * n, n, K, 64, nc, L, acc);
   tile_for_each(acc, [&](int i, int c, double v) {
-    if (i < nr && c < lb) Rm[(r0 + i) + (l0 + c) * n] = -v;
+    if (c < nc) Rm[(r0 + i) + (c0 + c) * n] = -v;
   });
+}
+
+// Clear the strict lower triangle (the level temporaries and the lower half
+// of C + lam I left by the factorization).
+__global__ void __launch_bounds__(256) k_zero_lower(const CholJob* __restrict__ jobs) {
+  const CholJob J = jobs[blockIdx.y];
+  const int64_t n = J.n;
+  const int64_t c = blockIdx.x;
+  if (c >= n) return;                        // uniform
+  for (int64_t i = c + 1 + threadIdx.x; i < n; i += 256) J.R[i + c * n] = 0.0;
 }
 
 // Column absolute sums of the symmetric Gram matrix C (k x k): their maximum
@@ -568,18 +615,19 @@ int launch_chol_inv_jobs(const CholJob* jobs, const int64_t* nsz, int32_t njobs,
   }
   {
     ProfScope ps("trinv", st);
-    for (int64_t lb = 0; lb < nblk; ++lb) {
-      const int64_t l0 = lb * NB;
-      const int32_t na = active(l0);
-      if (l0 > 0) {
-        hipLaunchKernelGGL(k_trinv_mul, dim3(unsigned(cdiv(l0, 64)), unsigned(na)), dim3(256), 0, st,
-                           jobs, l0);
-        TIK_LAUNCHED("k_trinv_mul");
-      }
-      hipLaunchKernelGGL(k_trinv_fin, dim3(unsigned(cdiv(nmax, 64)), unsigned(na)), dim3(256), 0, st,
-                         jobs, l0);
-      TIK_LAUNCHED("k_trinv_fin");
+    hipLaunchKernelGGL(k_trinv_diag, dim3(unsigned(nblk), unsigned(njobs)), dim3(256), 0, st, jobs);
+    TIK_LAUNCHED("k_trinv_diag");
+    for (int64_t s = NB; s < nmax; s *= 2) {
+      const int32_t na = active(s);          // jobs with a pair at this level
+      const int64_t pairs = cdiv(nmax - s, 2 * s);
+      const dim3 grid(unsigned(pairs * (s / 64) * (s / 64)), unsigned(na));
+      hipLaunchKernelGGL(k_trinv_lvl_t, grid, dim3(256), 0, st, jobs, s);
+      TIK_LAUNCHED("k_trinv_lvl_t");
+      hipLaunchKernelGGL(k_trinv_lvl_x, grid, dim3(256), 0, st, jobs, s);
+      TIK_LAUNCHED("k_trinv_lvl_x");
     }
+    hipLaunchKernelGGL(k_zero_lower, dim3(unsigned(nmax), unsigned(njobs)), dim3(256), 0, st, jobs);
+    TIK_LAUNCHED("k_zero_lower");
   }
   return TIK_OK;
 }

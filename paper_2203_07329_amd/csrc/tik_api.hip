@@ -693,7 +693,6 @@ int precond_plan(tik_sketch_t sk, int32_t route, int32_t N, Arena& a, PrecondPla
         CholJob j = {};
         j.R = pp.Rinv[size_t(k)] + size_t(i) * size_t(kd) * size_t(kd);
         j.Dinv = a.take<double>(size_t(cdiv(kd, 64)) * 64 * 64);
-        j.Tmp = a.take<double>(size_t(kd) * 64);
         j.notpd = pp.notpd + size_t(k) * size_t(N) + size_t(i);
         j.n = kd;
         j.dg = a.take<double>(size_t(kd));

@@ -212,8 +212,9 @@ int launch_gram_norm_bound(const double* C, int64_t n, double* scratch, double* 
                            hipStream_t st);
 // One shifted matrix of the batched Cholesky-inverse: R (n x n, ld n) holds
 // C + lambda I on entry and the upper triangle of chol(C + lambda I)^{-1} on
-// exit; Dinv (ceil(n / 64) blocks of 64 x 64) and Tmp (n x 64) are its
-// scratch; *notpd is set to 1 on breakdown.
+// exit (its strict lower triangle serves as scratch on the way and is zero at
+// the end); Dinv (ceil(n / 64) blocks of 64 x 64) holds the inverses of the
+// diagonal blocks; *notpd is set to 1 on breakdown.
 // given = 1: R already holds an upper-triangular factor (the QR route of a
 // breakdown); only its inverse is formed.  dg (n values, or null): the
 // diagonal of C + lambda I saved before the factorization; a pivot d_j counts
@@ -222,7 +223,6 @@ int launch_gram_norm_bound(const double* C, int64_t n, double* scratch, double* 
 struct CholJob {
   double* R;
   double* Dinv;
-  double* Tmp;
   int32_t* notpd;
   int64_t n;
   double* dg;
