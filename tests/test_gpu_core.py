@@ -95,8 +95,10 @@ def test_gauss_wide_sketch():
 
 # ---------------------------------------------------------- preconditioner --
 
-@pytest.mark.parametrize("n,s", [(100, 400), (130, 300), (64, 64), (1, 4)])
+@pytest.mark.parametrize("n,s", [(100, 400), (130, 300), (64, 64), (1, 4), (700, 1400)])
 def test_chol_inverse(n, s):
+    """R_i^{-1} of every lambda against numpy's inverse of the oracle's factor: one to four levels of the
+    recursive-doubling inverse, with partial last blocks (n = 100, 130, 700), one block and n = 1."""
     m = max(4 * s, 256)
     p = W.over_svd(m=m, n=n, N=5, sig_lo=1e-4)
     pr = dev_problems([p])
