@@ -383,6 +383,16 @@ int tik_version(void);
                   the last bits (integer-valued A gives identical Y).
                   tik_sketch_bytes reflects the setting at the time of the
                   query.
+   "gemm_n_tail"  1 (default): for a single tall problem whose row blocks in
+                  the product A W (128 rows each, at least 256 columns, 16 or
+                  32 lambdas per pass) outnumber the blocks resident at once,
+                  with the last round at most half full, that round's blocks
+                  are computed as column pieces spread over the whole GPU
+                  (partial products in the workspace, summed in piece order by
+                  a second kernel) instead of one block per CU.  0: every row
+                  block whole.  The two sum the columns in a different order,
+                  so results can differ in the last bits.  Read when a solve
+                  is planned.
    "record_times"  1: tik_lsqr_batch records, for every (problem, lambda)
                   of a batched FP64 or plain per-lambda call, the device wall
                   clock when its iteration stopped, and tik_lsqr_times returns

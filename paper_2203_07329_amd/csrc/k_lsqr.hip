@@ -1011,6 +1011,13 @@ struct Plan {
   std::vector<int> lsel;      // lambda indices solved (the same list for every problem)
   std::vector<DevProb> P;
   std::vector<Item> itN, itB, itT, itQ, itR, itM;
+  // A W tail (single-problem plans): row blocks tailBlk0.. are computed as
+  // tailQ column pieces of tailPW columns (partial products of the rows from
+  // tailBlk0 * 128 on, then summed and applied by k_gemm_n_tail_fin)
+  int64_t tailBlk0 = 0, tailPW = 0, tailMt = 0;
+  int tailQ = 0;
+  DevProb Ptail = {};
+  std::vector<Item> itTail;
   LrTables lr;                          // low-rank apply: proj, expand, fin
   bool lowrank = false;
   int cpw = 16;
@@ -1022,6 +1029,9 @@ struct Plan {
 struct Bufs {
   DevProb* P;
   Item *itN, *itB, *itT, *itQ, *itR, *itM;
+  DevProb* Ptail;     // the A W tail's problem (rows from the tail on)
+  Item* itTail;       // its column pieces
+  void* tailPart;     // their partial products (compute type)
   LrDev lr;
   Scal* sc;
   void* ut;
@@ -1276,8 +1286,96 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
   std::stable_sort(pl.itN.begin(), pl.itN.end(), [&](const Item& a, const Item& b) {
     return pl.P[size_t(a.p)].n > pl.P[size_t(b.p)].n;
   });
+  // The A W launch of B row blocks with C resident at a time ends with a round
+  // of B mod C blocks, each bound by one CU's matrix-core rate for its whole
+  // row block (200000 x 2000, 32 lambdas: 1563 blocks, 768 resident, 0.79 ms
+  // per launch against 0.70 ms for 1536 blocks).  When that round is at most
+  // half full, its row blocks are computed instead as column pieces spread
+  // over the whole GPU: a second launch of the product stores the pieces'
+  // partial products, and k_gemm_n_tail_fin sums them in piece order and
+  // applies the update (kernel boundaries order the two, so no fences).
+  pl.tailQ = 0;
+  pl.itTail.clear();
+  pl.tailBlk0 = pl.P.empty() ? 0 : pl.P[0].nblkN;
+  if (option_gemm_n_tail() && np == 1 && pl.NC >= 16 && pl.rbN == 128 && pl.P[0].n >= 256) {
+    const DevProb& d = pl.P[0];
+    const int64_t B = d.nblkN, C = gemm_n_resident(d.a_f32, 0, pl.NC);
+    const int64_t r = C > 0 ? B % C : 0;
+    if (C > 0 && B > C && r > 0 && 2 * r <= C) {
+      int64_t q = std::min<int64_t>(std::min<int64_t>(64, C / r), d.n / 64);
+      const int64_t pw = cdiv(cdiv(d.n, q), 16) * 16;
+      q = cdiv(d.n, pw);
+      if (q >= 2) {
+        pl.tailQ = int(q);
+        pl.tailPW = pw;
+        pl.tailBlk0 = B - r;
+        const int64_t row0 = pl.tailBlk0 * 128;
+        pl.tailMt = d.m - row0;
+        DevProb t = d;
+        t.A = static_cast<const char*>(d.A) + row0 * (d.a_f32 ? 4 : 8);
+        t.m = pl.tailMt;
+        t.cchunk = pw;
+        t.nchN = int32_t(q);
+        t.pnOff = 0;
+        pl.Ptail = t;
+        for (int64_t b = 0; b < r; ++b)
+          for (int64_t c = 0; c < q; ++c) pl.itTail.push_back({0, int32_t(b), int32_t(c), 0});
+      }
+    }
+  }
   pl.J = np * N;
 }
+
+// Sum of the tail's column-piece products in piece order, then the EPI 0
+// update u~ = A W - ucoef u~ of those rows and their squared-norm partials,
+// one 1024-thread block per 128-row block of the tail (single-problem plans).
+// Thread t handles lambda t % N of rows t / N, t / N + 1024 / N, ...; the
+// pieces are loaded eight at a time and added in piece order.
+static constexpr int TAILF = 1024;
+template <typename TC>
+__global__ void __launch_bounds__(TAILF) k_gemm_n_tail_fin(const DevProb* __restrict__ P, int N,
+                                                           int64_t blk0, int64_t mt, int q,
+                                                           const TC* __restrict__ part,
+                                                           TC* __restrict__ ut,
+                                                           const Scal* __restrict__ sc,
+                                                           double* __restrict__ pnN) {
+  __shared__ double red[TAILF];
+  const DevProb& pr = P[0];
+  if (plan_stopped(pr)) return;
+  const int rpp = TAILF / N;                  // rows per pass
+  const int t = threadIdx.x, i = t % N, rr = t / N;
+  const int64_t r0 = int64_t(blockIdx.x) * 128, r1 = min(mt, r0 + 128);
+  double loc = 0.0;
+  if (rr < rpp) {
+    const TC uc = TC(sc[i].ucoef);
+    for (int64_t r = r0 + rr; r < r1; r += rpp) {
+      const TC* pp = part + r * N + i;
+      const int64_t stride = mt * N;
+      TC acc = TC(0);
+      int c = 0;
+      for (; c + 8 <= q; c += 8) {
+        TC v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = pp[int64_t(c + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+      }
+      for (; c < q; ++c) acc += pp[int64_t(c) * stride];
+      const int64_t idx = (pr.offR + blk0 * 128 + r) * N + i;
+      const TC nv = TC(acc - uc * ut[idx]);
+      ut[idx] = nv;
+      loc += double(nv) * double(nv);
+    }
+  }
+  red[t] = loc;
+  __syncthreads();
+  if (t < N) {
+    double s = 0.0;
+    for (int j = 0; j < rpp; ++j) s += red[t + j * N];
+    pnN[(pr.pnN + blk0 + blockIdx.x) * N + t] = s;
+  }
+}
+
 
 void take_bufs(Arena& a, const Plan& pl, size_t tc, Bufs& b) {
   const int N = pl.N;
@@ -1288,6 +1386,9 @@ void take_bufs(Arena& a, const Plan& pl, size_t tc, Bufs& b) {
   b.itQ = a.take<Item>(pl.itQ.size());
   b.itR = a.take<Item>(pl.itR.size());
   b.itM = a.take<Item>(pl.itM.size());
+  b.Ptail = a.take<DevProb>(pl.tailQ ? 1 : 0);
+  b.itTail = a.take<Item>(pl.itTail.size());
+  b.tailPart = a.take<double>(size_t(pl.tailQ) * size_t(pl.tailMt) * size_t(N));
   take_lr(a, pl.lr, b.lr);
   b.sc = a.take<Scal>(pl.J);
   b.ut = a.take<char>(size_t(pl.totL) * N * tc);
@@ -1334,10 +1435,20 @@ struct Kern {
     if (NC >= 16) {
       constexpr bool c32 = std::is_same<TC, float>::value;
       if (c32) TIK_TRY(vec_to_f32(b.w, int64_t(pl.totS) * pl.N, b.w32, st));
-      return launch_gemm_n_mfma(std::is_same<TA, float>::value, c32, NC, 0, pl.rbN, b.P, b.itN,
-                                int(pl.itN.size()), pl.N,
-                                c32 ? static_cast<const void*>(b.w32) : static_cast<const void*>(b.w),
-                                b.ut, nullptr, b.sc, b.pnN, st);
+      const void* W = c32 ? static_cast<const void*>(b.w32) : static_cast<const void*>(b.w);
+      constexpr int a32 = std::is_same<TA, float>::value;
+      if (!pl.tailQ)
+        return launch_gemm_n_mfma(a32, c32, NC, 0, pl.rbN, b.P, b.itN, int(pl.itN.size()), pl.N, W,
+                                  b.ut, nullptr, b.sc, b.pnN, st);
+      TIK_TRY(launch_gemm_n_mfma(a32, c32, NC, 0, pl.rbN, b.P, b.itN, int(pl.tailBlk0), pl.N, W, b.ut,
+                                 nullptr, b.sc, b.pnN, st));
+      TIK_TRY(launch_gemm_n_mfma(a32, c32, NC, 2, pl.rbN, b.Ptail, b.itTail, int(pl.itTail.size()),
+                                 pl.N, W, b.tailPart, nullptr, b.sc, nullptr, st));
+      hipLaunchKernelGGL(k_gemm_n_tail_fin<TC>, dim3(unsigned(int64_t(pl.itN.size()) - pl.tailBlk0)),
+                         dim3(TAILF), 0, st, b.P, pl.N, pl.tailBlk0, pl.tailMt, pl.tailQ,
+                         static_cast<const TC*>(b.tailPart), static_cast<TC*>(b.ut), b.sc, b.pnN);
+      TIK_LAUNCHED("k_gemm_n_tail_fin");
+      return TIK_OK;
     }
     if (NC >= 8)
       hipLaunchKernelGGL((k_gemm_n<TA, TC, NC, 256, 1, 0>), dim3(unsigned(pl.itN.size())), dim3(BLK),
@@ -1661,6 +1772,13 @@ int upload_plan(const Plan& pl, const Bufs& b, const tik_precond_s* pc, double* 
   TIK_TRY(upload(b.itQ, stash(pl.itQ.data(), pl.itQ.size() * sizeof(Item)), pl.itQ.size() * sizeof(Item), st));
   TIK_TRY(upload(b.itR, stash(pl.itR.data(), pl.itR.size() * sizeof(Item)), pl.itR.size() * sizeof(Item), st));
   TIK_TRY(upload(b.itM, stash(pl.itM.data(), pl.itM.size() * sizeof(Item)), pl.itM.size() * sizeof(Item), st));
+  if (pl.tailQ) {
+    DevProb t = pl.Ptail;
+    t.live = b.cnt;
+    TIK_TRY(upload(b.Ptail, stash(&t, sizeof(DevProb)), sizeof(DevProb), st));
+    TIK_TRY(upload(b.itTail, stash(pl.itTail.data(), pl.itTail.size() * sizeof(Item)),
+                   pl.itTail.size() * sizeof(Item), st));
+  }
   const LrTables& lr = pl.lr;
   TIK_TRY(upload(b.lr.itLP, stash(lr.itLP.data(), lr.itLP.size() * sizeof(Item)), lr.itLP.size() * sizeof(Item), st));
   TIK_TRY(upload(b.lr.itLC, stash(lr.itLC.data(), lr.itLC.size() * sizeof(Item)), lr.itLC.size() * sizeof(Item), st));

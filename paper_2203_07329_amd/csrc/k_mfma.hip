@@ -9,6 +9,10 @@
 // i = 4 v + lane / 16 for FP64 and i = 4 (lane / 16) + v for FP32 (v = 0..3).
 #include "tik_internal.h"
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 namespace tik {
 
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
@@ -327,6 +331,36 @@ int launch_gemm_n_mfma(int ta_f32, int tc_f32, int nc, int epi, int rows, const 
   }
   if (ta_f32) return gemm_n_nc<float, double>(rows, nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
   return gemm_n_nc<double, double>(rows, nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
+}
+
+// Blocks of the 128-row EPI 0 product resident at once on the current device
+// (blocks per CU from the occupancy calculator times the CU count), cached per
+// device and shape; 0 if unknown.
+int gemm_n_resident(int ta_f32, int tc_f32, int nc) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  const auto key = std::make_tuple(dev, ta_f32, tc_f32, nc);
+  std::lock_guard<std::mutex> lk(mu);
+  auto hit = cache.find(key);
+  if (hit != cache.end()) return hit->second;
+  int cus = 0, per = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const void* fn;
+  if (tc_f32)
+    fn = nc == 32 ? reinterpret_cast<const void*>(&k_gemm_n_mfma<float, float, 32, 0, 2>)
+                  : reinterpret_cast<const void*>(&k_gemm_n_mfma<float, float, 16, 0, 2>);
+  else if (ta_f32)
+    fn = nc == 32 ? reinterpret_cast<const void*>(&k_gemm_n_mfma<float, double, 32, 0, 2>)
+                  : reinterpret_cast<const void*>(&k_gemm_n_mfma<float, double, 16, 0, 2>);
+  else
+    fn = nc == 32 ? reinterpret_cast<const void*>(&k_gemm_n_mfma<double, double, 32, 0, 2>)
+                  : reinterpret_cast<const void*>(&k_gemm_n_mfma<double, double, 16, 0, 2>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0) != hipSuccess) per = 0;
+  (void)hipGetLastError();
+  cache[key] = per * cus;
+  return per * cus;
 }
 
 template <typename TA, typename TC, typename TU>

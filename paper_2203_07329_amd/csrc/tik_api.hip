@@ -99,10 +99,12 @@ std::atomic<int64_t> g_opt_pivot{0};
 std::atomic<int> g_opt_nnz{1};
 std::atomic<int> g_opt_cqr{1};
 std::atomic<int> g_opt_srht_cols{1};
+std::atomic<int> g_opt_gn_tail{1};
 }
 int option_sparse_nnz() { return g_opt_nnz.load(std::memory_order_relaxed); }
 int option_cholqr_panels() { return g_opt_cqr.load(std::memory_order_relaxed); }
 int option_srht_cols() { return g_opt_srht_cols.load(std::memory_order_relaxed); }
+int option_gemm_n_tail() { return g_opt_gn_tail.load(std::memory_order_relaxed); }
 int option_chunk() { return g_opt_chunk.load(std::memory_order_relaxed); }
 int64_t option_pivot_ulps() { return g_opt_pivot.load(std::memory_order_relaxed); }
 
@@ -415,6 +417,11 @@ int tik_set_option(const char* name, int64_t value) {
     g_opt_cqr.store(int(value));
     return TIK_OK;
   }
+  if (std::string(name) == "gemm_n_tail") {
+    if (value < 0 || value > 1) return fail(TIK_EINVAL, "tik_set_option: gemm_n_tail must be 0 or 1");
+    g_opt_gn_tail.store(int(value));
+    return TIK_OK;
+  }
   if (std::string(name) == "srht_cols") {
     if (value < 0 || value > 1) return fail(TIK_EINVAL, "tik_set_option: srht_cols must be 0 or 1");
     g_opt_srht_cols.store(int(value));
@@ -453,6 +460,10 @@ int tik_get_option(const char* name, int64_t* value) {
   }
   if (std::string(name) == "srht_cols") {
     *value = option_srht_cols();
+    return TIK_OK;
+  }
+  if (std::string(name) == "gemm_n_tail") {
+    *value = option_gemm_n_tail();
     return TIK_OK;
   }
   return fail(TIK_EINVAL, std::string("tik_get_option: unknown option ") + name);

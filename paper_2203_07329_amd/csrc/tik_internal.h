@@ -72,6 +72,9 @@ int option_cholqr_panels();
 // 1: SRHT sketches use the column-resident transform where it applies (0: the
 // two-pass transform everywhere).
 int option_srht_cols();
+// 1: the last, partly filled round of the A W product's row blocks is computed
+// as column pieces over the whole GPU (single-problem plans); 0: whole blocks.
+int option_gemm_n_tail();
 
 // --------------------------------------------------------------- workspace --
 // Bump allocator over a caller-provided device buffer.  With base == nullptr it
@@ -251,6 +254,8 @@ int launch_bp2_r(const double* Y, int64_t s, int64_t k, double lam, double* R, d
 int launch_gemm_n_mfma(int ta_f32, int tc_f32, int nc, int epi, int rows, const DevProb* P,
                        const Item* items, int nitems, int N, const void* W, void* ut,
                        double* out, const Scal* sc, double* pnN, hipStream_t st);
+// 128-row EPI 0 blocks resident at once on the current device; 0 if unknown.
+int gemm_n_resident(int ta_f32, int tc_f32, int nc);
 int launch_gemm_t_mfma(int ta_f32, int tc_f32, int u_f64, int nc, int cols, const DevProb* P,
                        const Item* items, int nitems, int N, const void* U, void* part,
                        hipStream_t st);

@@ -255,6 +255,18 @@ def test_srht_cols_option_and_workspace():
         tik.set_option("srht_cols", old)
 
 
+def test_gemm_n_tail_option():
+    old = tik.get_option("gemm_n_tail")
+    try:
+        tik.set_option("gemm_n_tail", 0)
+        assert tik.get_option("gemm_n_tail") == 0
+        with pytest.raises(tik.TikError):
+            tik.set_option("gemm_n_tail", 2)
+    finally:
+        tik.set_option("gemm_n_tail", old)
+    assert tik.get_option("gemm_n_tail") == old
+
+
 def test_f16_sketch_rejects_wide_and_non_gaussian():
     rc, _ = _bytes(_probs(m=10, n=100), sdt=tik.F16, embed=tik.GAUSS, s=(40,))
     assert rc == tik.ENOTSUP                    # wide: the FP16 sketch is for tall problems

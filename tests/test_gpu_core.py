@@ -157,6 +157,38 @@ def test_lsqr_over_svd_small(mode):
     assert np.all(err <= p.tol), err
 
 
+@pytest.mark.parametrize("m,n,N", [(110000, 256, 32), (140000, 300, 16)])
+def test_gemm_n_tail_split(m, n, N):
+    """More 128-row blocks than are resident at once with a last round at most half
+    full (860 blocks, 1094 blocks): that round is computed as column pieces over the
+    whole GPU (partial products, then their sum and the update in a second kernel).
+    Solutions with and without the split against the oracle, the two within rounding
+    of each other, and the split run bit for bit reproducible."""
+    p = W.over_gauss(m=m, n=n, N=N, sig_lo=1e-6, lam_lo=1e-6, tol=1e-10)
+    props = torch.cuda.get_device_properties(0)
+    print("CUs", props.multi_processor_count, "row blocks", -(-m // 128))
+    old = tik.get_option("gemm_n_tail")
+    try:
+        out = {}
+        for opt in (1, 0, 1):
+            tik.set_option("gemm_n_tail", opt)
+            res, _ = _solve([p], tik.F64_BATCHED, tol=1e-13)
+            out.setdefault(opt, []).append((res.x_numpy(0), res.status.cpu().numpy()[0]))
+    finally:
+        tik.set_option("gemm_n_tail", old)
+    Xo = oracle.solve(p.A, p.b, p.lams)
+    for opt, runs in out.items():
+        for X, st in runs:
+            err = oracle.rel_err(X, Xo)
+            print("tail", opt, "max rel err %.2e" % err.max())
+            assert np.all(st == tik.ST_CONVERGED)
+            assert np.all(err <= 1e-10), err
+    assert np.array_equal(out[1][0][0], out[1][1][0])
+    d = np.max(np.abs(out[1][0][0] - out[0][0][0])) / np.max(np.abs(out[0][0][0]))
+    print("split vs unsplit: max rel difference %.2e" % d)
+    assert d <= 1e-10
+
+
 def test_lsqr_iterations_flat_in_kappa():
     """O(log 1/eps) iterations, independent of kappa(A) (Lemma 2.1, Section 3.3).
 
