@@ -173,7 +173,27 @@ def measured_traffic(workload, family):
         if h.hexdigest() != rec["source_sha256"]:
             return None
         key = FAMILY_KERNEL.get(family)
-        vals = [v for k, v in rec["bytes_per_dispatch"].items() if key and key in k]
+        bpd = rec["bytes_per_dispatch"]
+        if family == "gemm_n":
+            # one A W launch of the family can be three kernels: the row blocks of
+            # k_gemm_n_mfma<TA, TC, NC, 0, RT>, the column pieces of its last round
+            # (<TA, TC, NC, 2, RT>) and their sum (k_gemm_n_tail_fin<TC>)
+            best = None
+            for k, v in bpd.items():
+                if "k_gemm_n_mfma<" not in k:
+                    continue
+                args = k.split("k_gemm_n_mfma<", 1)[1].split(">", 1)[0].split(",")
+                if len(args) != 5 or args[3].strip() != "0":
+                    continue
+                tot = v
+                args[3] = " 2"
+                tot += bpd.get(k.replace(k.split("k_gemm_n_mfma<", 1)[1].split(">", 1)[0], ",".join(args)), 0)
+                if tot > v:     # the tail's pieces ran: add their sum
+                    tot += max([w for kk, w in bpd.items()
+                                if "k_gemm_n_tail_fin<" + args[1].strip() + ">" in kk] or [0])
+                best = tot if best is None else max(best, tot)
+            return int(best) if best is not None else None
+        vals = [v for k, v in bpd.items() if key and key in k]
         return int(max(vals)) if vals else None
     except (OSError, KeyError, ValueError):
         return None
