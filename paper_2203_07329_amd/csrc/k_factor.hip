@@ -362,12 +362,14 @@ __global__ void __launch_bounds__(256) k_trsm_panel(const CholJob* __restrict__ 
 }
 
 // Trailing update of the upper tiles: R[a, b] -= R[k, a]^T R[k, b] over the
-// panel rows k (tile pair blockIdx.x, a <= b, tiles counted from k0 + kb).
+// KW panel rows k from k0 (tile pair a <= b, tiles counted from k0 + KW), or
+// with ROW_ONLY over the first tile row only (a = 0).
 // Tile 0 of each job updates the next diagonal block and then factors and
 // inverts it (the diagonal step of the next panel, from the updated values it
 // keeps in LDS): launched first, it runs beside the other tiles' updates
 // instead of in a launch of its own after them.
-__global__ void __launch_bounds__(256, 4) k_syrk_trail(const CholJob* __restrict__ jobs, int64_t k0) {
+template <int KW, bool ROW_ONLY>
+__global__ void __launch_bounds__(256, KW == 64 ? 4 : 3) k_syrk_trail(const CholJob* __restrict__ jobs, int64_t k0) {
   __shared__ TileLds L;
   // blocks in dispatch order take tile 0 of every job first, then tile 1, ...:
   // the diagonal steps start before the other tiles, not one job at a time
@@ -377,18 +379,19 @@ __global__ void __launch_bounds__(256, 4) k_syrk_trail(const CholJob* __restrict
   const int64_t n = J.n;
   double* Rm = J.R;
   if (k0 >= n) return;                       // uniform
-  const int kb = int(min<int64_t>(NB, n - k0));
+  const int kb = int(min<int64_t>(KW, n - k0));
   const int nt = int(cdiv(n - k0 - kb, 64));    // this job's trailing tiles
-  if (tile >= nt * (nt + 1) / 2) return;   // uniform
+  if (tile >= (ROW_ONLY ? nt : nt * (nt + 1) / 2)) return;   // uniform
   int t = tile, ta = 0;
-  while (t >= nt - ta) { t -= nt - ta; ++ta; }
+  if (!ROW_ONLY)
+    while (t >= nt - ta) { t -= nt - ta; ++ta; }
   const int tb = ta + t;
   const int64_t base = k0 + kb;
   const int64_t a0 = base + int64_t(ta) * 64, b0 = base + int64_t(tb) * 64;
   const int na = int(min<int64_t>(64, n - a0)), nb = int(min<int64_t>(64, n - b0));
   f64x4 acc[2][2];
   tile_zero(acc);
-  tile_mma<true, 2>(Rm + k0 + a0 * n, n, Rm + k0 + b0 * n, n, kb, na, nb, L, acc);
+  tile_mma<true, KW == 64 ? 2 : 1>(Rm + k0 + a0 * n, n, Rm + k0 + b0 * n, n, kb, na, nb, L, acc);
   if (tile != 0) {
     tile_for_each(acc, [&](int i, int j, double v) {
       if (i < na && j < nb) Rm[(a0 + i) + (b0 + j) * n] -= v;
@@ -593,22 +596,39 @@ int launch_chol_inv_jobs(const CholJob* jobs, const int64_t* nsz, int32_t njobs,
   };
   {
     ProfScope ps("chol", st);
-    for (int64_t kb = 0; kb < nblk; ++kb) {
-      const int64_t k0 = kb * NB;
-      const int32_t na = active(k0);
-      // after the first panel the trailing update has done the diagonal step
-      if (kb == 0 || given) {
-        hipLaunchKernelGGL(k_potrf_diag, dim3(unsigned(na)), dim3(256), 0, st, jobs, k0);
+    if (given) {
+      // triangular factors already: only the diagonal blocks' inverses
+      for (int64_t kb = 0; kb < nblk; ++kb) {
+        hipLaunchKernelGGL(k_potrf_diag, dim3(unsigned(active(kb * NB))), dim3(256), 0, st, jobs, kb * NB);
         TIK_LAUNCHED("k_potrf_diag");
       }
-      const int64_t rest = nmax - k0 - std::min<int64_t>(NB, nmax - k0);
-      if (rest > 0 && !given) {
-        const int32_t nr = active(k0 + NB);   // jobs with trailing columns
-        const int nt = int(cdiv(rest, 64));
-        hipLaunchKernelGGL(k_trsm_panel, dim3(unsigned(nt), unsigned(nr)), dim3(256), 0, st, jobs, k0);
+    } else {
+      // Two 64-column panels per step: panel k0 is solved and applied to the
+      // next tile row only (which factors the next diagonal block), panel
+      // k0 + 64 is solved, and both update the rest of the trailing matrix in
+      // one pass with 128 contraction rows, so each trailing tile is read and
+      // written once per 128 columns instead of once per 64.
+      hipLaunchKernelGGL(k_potrf_diag, dim3(unsigned(active(0))), dim3(256), 0, st, jobs, int64_t(0));
+      TIK_LAUNCHED("k_potrf_diag");
+      for (int64_t k0 = 0; k0 < nmax; k0 += 2 * NB) {
+        const int64_t rest1 = nmax - k0 - std::min<int64_t>(NB, nmax - k0);
+        if (rest1 <= 0) break;
+        const int32_t nr1 = active(k0 + NB);
+        const int nt1 = int(cdiv(rest1, 64));
+        hipLaunchKernelGGL(k_trsm_panel, dim3(unsigned(nt1), unsigned(nr1)), dim3(256), 0, st, jobs, k0);
         TIK_LAUNCHED("k_trsm_panel");
-        hipLaunchKernelGGL(k_syrk_trail, dim3(unsigned(nt * (nt + 1) / 2), unsigned(nr)), dim3(256), 0,
-                           st, jobs, k0);
+        hipLaunchKernelGGL((k_syrk_trail<NB, true>), dim3(unsigned(nt1), unsigned(nr1)), dim3(256), 0, st,
+                           jobs, k0);
+        TIK_LAUNCHED("k_syrk_trail");
+        const int64_t rest2 = nmax - k0 - 2 * NB;
+        if (rest2 <= 0) break;
+        const int32_t nr2 = active(k0 + 2 * NB);
+        const int nt2 = int(cdiv(rest2, 64));
+        hipLaunchKernelGGL(k_trsm_panel, dim3(unsigned(nt2), unsigned(nr2)), dim3(256), 0, st, jobs,
+                           k0 + NB);
+        TIK_LAUNCHED("k_trsm_panel");
+        hipLaunchKernelGGL((k_syrk_trail<2 * NB, false>), dim3(unsigned(nt2 * (nt2 + 1) / 2), unsigned(nr2)),
+                           dim3(256), 0, st, jobs, k0);
         TIK_LAUNCHED("k_syrk_trail");
       }
     }
