@@ -438,20 +438,22 @@ __global__ void __launch_bounds__(256) k_trinv_diag(const CholJob* __restrict__ 
   }
 }
 
-// pair and tile of a level's launch: tiles of the pair numbered ti * (s / 64) + tj
+// pair and tile of a level's launch, in an order that dispatches the longest
+// contractions first: for T (contraction over 64 (tj + 1) rows) the tiles of a
+// pair run by descending tj, for Rinv[A, B] (over s - 64 ti rows) by ascending ti
 struct LvlTile {
   int64_t a0, b0;
   int ti, tj, bsz;
   bool ok;
 };
-__device__ __forceinline__ LvlTile lvl_tile(int64_t n, int64_t s) {
-  const int64_t per = (s / 64) * (s / 64);
-  const int64_t p = blockIdx.x / per, r = blockIdx.x % per;
+__device__ __forceinline__ LvlTile lvl_tile(int64_t tile, int64_t n, int64_t s, bool tj_major) {
+  const int64_t w = s / 64, per = w * w;
+  const int64_t p = tile / per, r = tile % per;
   LvlTile t;
   t.a0 = 2 * s * p;
   t.b0 = t.a0 + s;
-  t.ti = int(r / (s / 64));
-  t.tj = int(r % (s / 64));
+  t.ti = int(tj_major ? r % w : r / w);
+  t.tj = int(tj_major ? w - 1 - r / w : r % w);
   t.bsz = int(min<int64_t>(s, n - t.b0));
   t.ok = t.b0 < n && 64 * t.tj < t.bsz;
   return t;
@@ -462,9 +464,11 @@ __device__ __forceinline__ LvlTile lvl_tile(int64_t n, int64_t s) {
 // tile's last column.
 __global__ void __launch_bounds__(256) k_trinv_lvl_t(const CholJob* __restrict__ jobs, int64_t s) {
   __shared__ TileLds L;
-  const CholJob J = jobs[blockIdx.y];
+  // the jobs' tiles interleaved in dispatch order, so the longest of every job go first
+  const int64_t lin = int64_t(blockIdx.x) + int64_t(blockIdx.y) * gridDim.x;
+  const CholJob J = jobs[lin % gridDim.y];
   const int64_t n = J.n;
-  const LvlTile t = lvl_tile(n, s);
+  const LvlTile t = lvl_tile(lin / gridDim.y, n, s, true);
   if (!t.ok) return;                         // uniform
   double* Rm = J.R;
   const int64_t r0 = t.a0 + 64 * t.ti, c0 = t.b0 + 64 * t.tj;
@@ -482,9 +486,10 @@ __global__ void __launch_bounds__(256) k_trinv_lvl_t(const CholJob* __restrict__
 // triangular, so the contraction starts at the tile's first row.
 __global__ void __launch_bounds__(256, 4) k_trinv_lvl_x(const CholJob* __restrict__ jobs, int64_t s) {
   __shared__ TileLds L;
-  const CholJob J = jobs[blockIdx.y];
+  const int64_t lin = int64_t(blockIdx.x) + int64_t(blockIdx.y) * gridDim.x;
+  const CholJob J = jobs[lin % gridDim.y];
   const int64_t n = J.n;
-  const LvlTile t = lvl_tile(n, s);
+  const LvlTile t = lvl_tile(lin / gridDim.y, n, s, false);
   if (!t.ok) return;                         // uniform
   double* Rm = J.R;
   const int64_t r0 = t.a0 + 64 * t.ti, c0 = t.b0 + 64 * t.tj;
