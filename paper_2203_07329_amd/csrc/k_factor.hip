@@ -368,8 +368,11 @@ __global__ void __launch_bounds__(256) k_trsm_panel(const CholJob* __restrict__ 
 // inverts it (the diagonal step of the next panel, from the updated values it
 // keeps in LDS): launched first, it runs beside the other tiles' updates
 // instead of in a launch of its own after them.
+// The 128-row contraction prefetches one K chunk ahead and runs three blocks
+// per CU (two chunks ahead, or four blocks per CU, spill its registers).
 template <int KW, bool ROW_ONLY>
-__global__ void __launch_bounds__(256, KW == 64 ? 4 : 3) k_syrk_trail(const CholJob* __restrict__ jobs, int64_t k0) {
+__global__ void __launch_bounds__(256, KW == 64 ? 4 : 3)
+    k_syrk_trail(const CholJob* __restrict__ jobs, int64_t k0) {
   __shared__ TileLds L;
   // blocks in dispatch order take tile 0 of every job first, then tile 1, ...:
   // the diagonal steps start before the other tiles, not one job at a time
