@@ -236,28 +236,41 @@ __global__ void __launch_bounds__(BLK) k_gemm_n(const DevProb* __restrict__ P,
 }
 
 // -------------------------------------------------------------- vec_bot ----
+// u~_bot = sqrt(lam) w - ucoef u~_bot and its squared-norm partials for a
+// block of BLK rows.  Thread t handles lambda t % N of rows t / N, t / N + BLK / N,
+// ... (consecutive threads read consecutive lambdas of a row), and the partials
+// of a lambda are summed over its threads in a fixed order: one barrier per
+// block instead of one reduction per lambda.
 __global__ void __launch_bounds__(BLK) k_vec_bot(const DevProb* __restrict__ P,
                                                  const Item* __restrict__ items, int N,
                                                  const double* __restrict__ w,
                                                  double* __restrict__ ub,
                                                  const Scal* __restrict__ sc,
                                                  double* __restrict__ pnB) {
-  __shared__ double red[4];
+  __shared__ double red[BLK];
   const Item it = items[blockIdx.x];
   const DevProb& pr = P[it.p];
   if (plan_stopped(pr)) return;
-  const int64_t r = int64_t(it.blk) * BLK + threadIdx.x;
-  for (int i = 0; i < N; ++i) {
+  const int rpp = BLK / N;                    // rows per pass
+  const int t = threadIdx.x, i = t % N, rr = t / N;
+  const int64_t r0 = int64_t(it.blk) * BLK, r1 = min(pr.n, r0 + BLK);
+  double loc = 0.0;
+  if (rr < rpp) {
     const Scal& S = sc[it.p * N + i];
-    double v = 0.0;
-    if (r < pr.n) {
+    const double sql = S.sqlam, uc = S.ucoef;
+    for (int64_t r = r0 + rr; r < r1; r += rpp) {
       const int64_t idx = (pr.offS + r) * N + i;
-      const double nv = S.sqlam * w[idx] - S.ucoef * ub[idx];
+      const double nv = sql * w[idx] - uc * ub[idx];
       ub[idx] = nv;
-      v = nv * nv;
+      loc += nv * nv;
     }
-    const double s = block_sum(v, red);
-    if (threadIdx.x == 0) pnB[(pr.pnB + it.blk) * N + i] = s;
+  }
+  red[t] = loc;
+  __syncthreads();
+  if (t < N) {
+    double s = 0.0;
+    for (int j = 0; j < rpp; ++j) s += red[t + j * N];
+    pnB[(pr.pnB + it.blk) * N + t] = s;
   }
 }
 
