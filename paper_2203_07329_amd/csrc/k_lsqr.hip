@@ -1343,7 +1343,7 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
 // update u~ = A W - ucoef u~ of those rows and their squared-norm partials,
 // one 1024-thread block per 128-row block of the tail (single-problem plans).
 // Thread t handles lambda t % N of rows t / N, t / N + 1024 / N, ...; the
-// pieces are loaded eight at a time and added in piece order.
+// pieces of four such rows are loaded four at a time and added in piece order.
 static constexpr int TAILF = 1024;
 template <typename TC>
 __global__ void __launch_bounds__(TAILF) k_gemm_n_tail_fin(const DevProb* __restrict__ P, int N,
@@ -1361,23 +1361,39 @@ __global__ void __launch_bounds__(TAILF) k_gemm_n_tail_fin(const DevProb* __rest
   double loc = 0.0;
   if (rr < rpp) {
     const TC uc = TC(sc[i].ucoef);
-    for (int64_t r = r0 + rr; r < r1; r += rpp) {
-      const TC* pp = part + r * N + i;
-      const int64_t stride = mt * N;
-      TC acc = TC(0);
+    const int64_t stride = mt * N;
+    // four of the thread's rows at a time, so that their pieces' loads are in
+    // flight together (rows past the block's end read the last row, unused)
+    for (int64_t rb = r0 + rr; rb < r1; rb += 4 * rpp) {
+      const TC* pp[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) pp[j] = part + min(rb + j * rpp, r1 - 1) * N + i;
+      TC acc[4] = {TC(0), TC(0), TC(0), TC(0)};
       int c = 0;
-      for (; c + 8 <= q; c += 8) {
-        TC v[8];
+      for (; c + 4 <= q; c += 4) {
+        TC v[4][4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = pp[int64_t(c + u) * stride];
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += v[u];
+          for (int u = 0; u < 4; ++u) v[j][u] = pp[j][int64_t(c + u) * stride];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[j] += v[j][u];
       }
-      for (; c < q; ++c) acc += pp[int64_t(c) * stride];
-      const int64_t idx = (pr.offR + blk0 * 128 + r) * N + i;
-      const TC nv = TC(acc - uc * ut[idx]);
-      ut[idx] = nv;
-      loc += double(nv) * double(nv);
+      for (; c < q; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] += pp[j][int64_t(c) * stride];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t r = rb + j * rpp;
+        if (r < r1) {
+          const int64_t idx = (pr.offR + blk0 * 128 + r) * N + i;
+          const TC nv = TC(acc[j] - uc * ut[idx]);
+          ut[idx] = nv;
+          loc += double(nv) * double(nv);
+        }
+      }
     }
   }
   red[t] = loc;
