@@ -101,10 +101,13 @@ __global__ void __launch_bounds__(BLK) k_init_u(const DevProb* __restrict__ P,
 
 // ------------------------------------------------------------- fin_beta ----
 // beta_{i+1} = sqrt(sum of partials).  One block per (problem, lambda).
+// pnX, nX: nX more partials of problem 0 (the split A W tail's sub-blocks),
+// added after an iteration's product only (init = 0).
 __global__ void __launch_bounds__(BLK) k_fin_beta(const DevProb* __restrict__ P, int N,
                                                   const double* __restrict__ pnN,
                                                   const double* __restrict__ pnB,
-                                                  Scal* __restrict__ sc, int init) {
+                                                  Scal* __restrict__ sc, int init,
+                                                  const double* __restrict__ pnX, int nX) {
   __shared__ double red[4];
   const int j = blockIdx.x, p = j / N, i = j % N;
   const DevProb& pr = P[p];
@@ -112,6 +115,8 @@ __global__ void __launch_bounds__(BLK) k_fin_beta(const DevProb* __restrict__ P,
   double v = 0.0;
   for (int b = threadIdx.x; b < pr.nblkN; b += BLK) v += pnN[(pr.pnN + b) * N + i];
   for (int b = threadIdx.x; b < pr.nblkB; b += BLK) v += pnB[(pr.pnB + b) * N + i];
+  if (!init && p == 0)
+    for (int b = threadIdx.x; b < nX; b += BLK) v += pnX[int64_t(b) * N + i];
   const double s = block_sum(v, red);
   if (threadIdx.x != 0) return;
   Scal& S = sc[j];
@@ -1029,6 +1034,7 @@ struct Plan {
   // tailBlk0 * 128 on, then summed and applied by k_gemm_n_tail_fin)
   int64_t tailBlk0 = 0, tailPW = 0, tailMt = 0;
   int tailQ = 0;
+  int64_t tailNX = 0;                   // norm partials of the sum's sub-blocks 1.. (tailPn)
   DevProb Ptail = {};
   std::vector<Item> itTail;
   LrTables lr;                          // low-rank apply: proj, expand, fin
@@ -1045,6 +1051,7 @@ struct Bufs {
   DevProb* Ptail;     // the A W tail's problem (rows from the tail on)
   Item* itTail;       // its column pieces
   void* tailPart;     // their partial products (compute type)
+  double* tailPn;     // norm partials of the tail sum's sub-blocks 1..
   LrDev lr;
   Scal* sc;
   void* ut;
@@ -1178,6 +1185,10 @@ void note_tile(const char* what, const TileKey& k, const Tile& t, bool tuned, in
   t_last_tile = buf;
 }
 
+// The sum of the A W tail's column pieces (k_gemm_n_tail_fin): TAILF threads
+// per block, TAILR rows per block, TAILS blocks per 128-row block of the tail.
+static constexpr int TAILF = 512, TAILR = 16, TAILS = 128 / TAILR;
+
 void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vector<int>& pidx,
                const std::vector<int>& lsel, Plan& pl, const void* const* Aover = nullptr,
                const int64_t* ldover = nullptr) {
@@ -1308,9 +1319,11 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
   // partial products, and k_gemm_n_tail_fin sums them in piece order and
   // applies the update (kernel boundaries order the two, so no fences).
   pl.tailQ = 0;
+  pl.tailNX = 0;
   pl.itTail.clear();
   pl.tailBlk0 = pl.P.empty() ? 0 : pl.P[0].nblkN;
-  if (option_gemm_n_tail() && np == 1 && pl.NC >= 16 && pl.rbN == 128 && pl.P[0].n >= 256) {
+  if (option_gemm_n_tail() && np == 1 && pl.NC >= 16 && N <= TAILF / TAILR && pl.rbN == 128 &&
+      pl.P[0].n >= 256) {
     const DevProb& d = pl.P[0];
     const int64_t B = d.nblkN, C = gemm_n_resident(d.a_f32, 0, pl.NC);
     const int64_t r = C > 0 ? B % C : 0;
@@ -1333,6 +1346,7 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
         pl.Ptail = t;
         for (int64_t b = 0; b < r; ++b)
           for (int64_t c = 0; c < q; ++c) pl.itTail.push_back({0, int32_t(b), int32_t(c), 0});
+        pl.tailNX = r * (TAILS - 1);
       }
     }
   }
@@ -1340,68 +1354,56 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
 }
 
 // Sum of the tail's column-piece products in piece order, then the EPI 0
-// update u~ = A W - ucoef u~ of those rows and their squared-norm partials,
-// one 1024-thread block per 128-row block of the tail (single-problem plans).
-// Thread t handles lambda t % N of rows t / N, t / N + 1024 / N, ...; the
-// pieces of four such rows are loaded four at a time and added in piece order.
-static constexpr int TAILF = 1024;
+// update u~ = A W - ucoef u~ of those rows and their squared-norm partials
+// (single-problem plans).  Block g takes rows TAILR (g mod TAILS) .. of 128-row
+// block g / TAILS of the tail: spread over about TAILS times as many compute
+// units as 128-row blocks would be, since one unit's share of the pieces is
+// bound by its own bandwidth.  Thread t handles lambda t % N of row t / N
+// (N <= TAILF / TAILR, so one row each); its pieces are loaded eight at a time
+// and added in piece order.  Sub-block 0 of each 128-row block writes that
+// block's norm-partial slot, the others the extra partials pnX that k_fin_beta
+// adds (every sub-block writes its partial, zero where it has no rows).
 template <typename TC>
 __global__ void __launch_bounds__(TAILF) k_gemm_n_tail_fin(const DevProb* __restrict__ P, int N,
                                                            int64_t blk0, int64_t mt, int q,
                                                            const TC* __restrict__ part,
                                                            TC* __restrict__ ut,
                                                            const Scal* __restrict__ sc,
-                                                           double* __restrict__ pnN) {
+                                                           double* __restrict__ pnN,
+                                                           double* __restrict__ pnX) {
   __shared__ double red[TAILF];
   const DevProb& pr = P[0];
   if (plan_stopped(pr)) return;
-  const int rpp = TAILF / N;                  // rows per pass
   const int t = threadIdx.x, i = t % N, rr = t / N;
-  const int64_t r0 = int64_t(blockIdx.x) * 128, r1 = min(mt, r0 + 128);
+  const int64_t blk = blockIdx.x / TAILS;
+  const int sub = int(blockIdx.x % TAILS);
+  const int64_t r = blk * 128 + int64_t(sub) * TAILR + rr;
   double loc = 0.0;
-  if (rr < rpp) {
-    const TC uc = TC(sc[i].ucoef);
+  if (rr < TAILR && r < mt) {
+    const TC* pp = part + r * N + i;
     const int64_t stride = mt * N;
-    // four of the thread's rows at a time, so that their pieces' loads are in
-    // flight together (rows past the block's end read the last row, unused)
-    for (int64_t rb = r0 + rr; rb < r1; rb += 4 * rpp) {
-      const TC* pp[4];
+    TC acc = TC(0);
+    int c = 0;
+    for (; c + 8 <= q; c += 8) {
+      TC v[8];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) pp[j] = part + min(rb + j * rpp, r1 - 1) * N + i;
-      TC acc[4] = {TC(0), TC(0), TC(0), TC(0)};
-      int c = 0;
-      for (; c + 4 <= q; c += 4) {
-        TC v[4][4];
+      for (int u = 0; u < 8; ++u) v[u] = pp[int64_t(c + u) * stride];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int u = 0; u < 4; ++u) v[j][u] = pp[j][int64_t(c + u) * stride];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int u = 0; u < 4; ++u) acc[j] += v[j][u];
-      }
-      for (; c < q; ++c)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[j] += pp[j][int64_t(c) * stride];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t r = rb + j * rpp;
-        if (r < r1) {
-          const int64_t idx = (pr.offR + blk0 * 128 + r) * N + i;
-          const TC nv = TC(acc[j] - uc * ut[idx]);
-          ut[idx] = nv;
-          loc += double(nv) * double(nv);
-        }
-      }
+      for (int u = 0; u < 8; ++u) acc += v[u];
     }
+    for (; c < q; ++c) acc += pp[int64_t(c) * stride];
+    const int64_t idx = (pr.offR + blk0 * 128 + r) * N + i;
+    const TC nv = TC(acc - TC(sc[i].ucoef) * ut[idx]);
+    ut[idx] = nv;
+    loc = double(nv) * double(nv);
   }
   red[t] = loc;
   __syncthreads();
   if (t < N) {
     double s = 0.0;
-    for (int j = 0; j < rpp; ++j) s += red[t + j * N];
-    pnN[(pr.pnN + blk0 + blockIdx.x) * N + t] = s;
+    for (int j = 0; j < TAILR; ++j) s += red[t + j * N];
+    if (sub == 0) pnN[(pr.pnN + blk0 + blk) * N + t] = s;
+    else pnX[(blk * (TAILS - 1) + sub - 1) * N + t] = s;
   }
 }
 
@@ -1418,6 +1420,7 @@ void take_bufs(Arena& a, const Plan& pl, size_t tc, Bufs& b) {
   b.Ptail = a.take<DevProb>(pl.tailQ ? 1 : 0);
   b.itTail = a.take<Item>(pl.itTail.size());
   b.tailPart = a.take<double>(size_t(pl.tailQ) * size_t(pl.tailMt) * size_t(N));
+  b.tailPn = a.take<double>(size_t(pl.tailNX) * size_t(N));
   take_lr(a, pl.lr, b.lr);
   b.sc = a.take<Scal>(pl.J);
   b.ut = a.take<char>(size_t(pl.totL) * N * tc);
@@ -1473,9 +1476,11 @@ struct Kern {
                                  nullptr, b.sc, b.pnN, st));
       TIK_TRY(launch_gemm_n_mfma(a32, c32, NC, 2, pl.rbN, b.Ptail, b.itTail, int(pl.itTail.size()),
                                  pl.N, W, b.tailPart, nullptr, b.sc, nullptr, st));
-      hipLaunchKernelGGL(k_gemm_n_tail_fin<TC>, dim3(unsigned(int64_t(pl.itN.size()) - pl.tailBlk0)),
-                         dim3(TAILF), 0, st, b.P, pl.N, pl.tailBlk0, pl.tailMt, pl.tailQ,
-                         static_cast<const TC*>(b.tailPart), static_cast<TC*>(b.ut), b.sc, b.pnN);
+      hipLaunchKernelGGL(k_gemm_n_tail_fin<TC>,
+                         dim3(unsigned((int64_t(pl.itN.size()) - pl.tailBlk0) * TAILS)), dim3(TAILF), 0,
+                         st, b.P, pl.N, pl.tailBlk0, pl.tailMt, pl.tailQ,
+                         static_cast<const TC*>(b.tailPart), static_cast<TC*>(b.ut), b.sc, b.pnN,
+                         b.tailPn);
       TIK_LAUNCHED("k_gemm_n_tail_fin");
       return TIK_OK;
     }
@@ -1516,7 +1521,7 @@ int vec_steps_u(const Plan& pl, const Bufs& b, hipStream_t st, bool init, const 
     TIK_LAUNCHED("k_vec_bot");
   }
   hipLaunchKernelGGL(k_fin_beta, dim3(unsigned(pl.J)), dim3(BLK), 0, st, b.P, pl.N, b.pnN, b.pnB,
-                     b.sc, init ? 1 : 0);
+                     b.sc, init ? 1 : 0, static_cast<const double*>(b.tailPn), int(pl.tailNX));
   TIK_LAUNCHED("k_fin_beta");
   return TIK_OK;
 }
@@ -1752,7 +1757,7 @@ int run_core(const Plan& pl, const Bufs& b, double tol, int maxit, hipStream_t s
                        ir->f, ir->g, static_cast<TC*>(b.ut), b.ub, b.pnN, b.pnB);
     TIK_LAUNCHED("k_init_u_ir");
     hipLaunchKernelGGL(k_fin_beta, dim3(unsigned(pl.J)), dim3(BLK), 0, st, b.P, pl.N, b.pnN, b.pnB,
-                       b.sc, 1);
+                       b.sc, 1, static_cast<const double*>(nullptr), 0);
     TIK_LAUNCHED("k_fin_beta");
   } else {
     TIK_TRY(vec_steps_u<TC>(pl, b, st, true, nullptr, nullptr));
@@ -2664,7 +2669,8 @@ int wide_u_steps(const WPlan& pl, const WBufs& b, hipStream_t st, bool init) {
   }
   ProfScope ps("vec", st);
   hipLaunchKernelGGL(k_fin_beta, dim3(unsigned(pl.J)), dim3(BLK), 0, st, b.P, pl.N, b.pnN,
-                     static_cast<const double*>(nullptr), b.sc, init ? 1 : 0);
+                     static_cast<const double*>(nullptr), b.sc, init ? 1 : 0,
+                     static_cast<const double*>(nullptr), 0);
   TIK_LAUNCHED("k_fin_beta");
   return TIK_OK;
 }

@@ -157,11 +157,12 @@ def test_lsqr_over_svd_small(mode):
     assert np.all(err <= p.tol), err
 
 
-@pytest.mark.parametrize("m,n,N", [(110000, 256, 32), (140000, 300, 16)])
+@pytest.mark.parametrize("m,n,N", [(110000, 256, 32), (140000, 300, 16), (120000, 400, 20)])
 def test_gemm_n_tail_split(m, n, N):
     """More 128-row blocks than are resident at once with a last round at most half
-    full (860 blocks, 1094 blocks): that round is computed as column pieces over the
-    whole GPU (partial products, then their sum and the update in a second kernel).
+    full (860, 1094 and 938 blocks): that round is computed as column pieces over the
+    whole GPU (partial products, then their sum and the update in 16-row blocks whose
+    norm partials k_fin_beta adds; N = 20 leaves part of each block's threads idle).
     Solutions with and without the split against the oracle, the two within rounding
     of each other, and the split run bit for bit reproducible."""
     p = W.over_gauss(m=m, n=n, N=N, sig_lo=1e-6, lam_lo=1e-6, tol=1e-10)
