@@ -58,6 +58,10 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return red[0] + red[1] + red[2] + red[3];
 }
 
+// Rows per block of the bottom part u~_bot (n rows per problem): small blocks,
+// so that the few thousand rows are spread over many compute units.
+static constexpr int VB = 32;
+
 // -------------------------------------------------------------- init u -----
 // u~ = [rhs_top; rhs_bot] (rhs_top == null: b for every lambda; rhs_bot == null:
 // zero) and partial squared norms.  Items: gemm_n blocks (top) then vec_bot
@@ -75,7 +79,7 @@ __global__ void __launch_bounds__(BLK) k_init_u(const DevProb* __restrict__ P,
   const Item it = top ? itN[blockIdx.x] : itB[blockIdx.x - nItN];
   const DevProb& pr = P[it.p];
   const int64_t rows = top ? pr.m : pr.n;
-  const int64_t rb = top ? rbN : BLK;
+  const int64_t rb = top ? rbN : VB;
   const int64_t r0 = int64_t(it.blk) * rb;
   const int64_t r1 = min(rows, r0 + rb);
   double* pn = top ? pnN + (pr.pnN + it.blk) * N : pnB + (pr.pnB + it.blk) * N;
@@ -242,7 +246,7 @@ __global__ void __launch_bounds__(BLK) k_gemm_n(const DevProb* __restrict__ P,
 
 // -------------------------------------------------------------- vec_bot ----
 // u~_bot = sqrt(lam) w - ucoef u~_bot and its squared-norm partials for a
-// block of BLK rows.  Thread t handles lambda t % N of rows t / N, t / N + BLK / N,
+// block of VB rows.  Thread t handles lambda t % N of rows t / N, t / N + BLK / N,
 // ... (consecutive threads read consecutive lambdas of a row), and the partials
 // of a lambda are summed over its threads in a fixed order: one barrier per
 // block instead of one reduction per lambda.
@@ -258,7 +262,7 @@ __global__ void __launch_bounds__(BLK) k_vec_bot(const DevProb* __restrict__ P,
   if (plan_stopped(pr)) return;
   const int rpp = BLK / N;                    // rows per pass
   const int t = threadIdx.x, i = t % N, rr = t / N;
-  const int64_t r0 = int64_t(it.blk) * BLK, r1 = min(pr.n, r0 + BLK);
+  const int64_t r0 = int64_t(it.blk) * VB, r1 = min(pr.n, r0 + VB);
   double loc = 0.0;
   if (rr < rpp) {
     const Scal& S = sc[it.p * N + i];
@@ -697,7 +701,7 @@ __global__ void __launch_bounds__(BLK) k_init_u_ir(const DevProb* __restrict__ P
   const Item it = top ? itN[blockIdx.x] : itB[blockIdx.x - nItN];
   const DevProb& pr = P[it.p];
   const int64_t rows = top ? pr.m : pr.n;
-  const int64_t rb = top ? rbN : BLK;
+  const int64_t rb = top ? rbN : VB;
   const int64_t r0 = int64_t(it.blk) * rb;
   const int64_t r1 = min(rows, r0 + rb);
   double* pn = top ? pnN + (pr.pnN + it.blk) * N : pnB + (pr.pnB + it.blk) * N;
@@ -1244,7 +1248,7 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
     d.k = g.n;
     if (pc->route == TIK_ROUTE_CHOL) d.Rinv = pc->Rinv[pidx[lp]];
     d.nblkN = int32_t(cdiv(g.m, pl.rbN));
-    d.nblkB = int32_t(cdiv(g.n, BLK));
+    d.nblkB = int32_t(cdiv(g.n, VB));
     d.nblkQ = int32_t(cdiv(g.n, 4 * pl.cpw));
     if (pl.lowrank) d.nblkQ = lowrank_items(pc, pidx[lp], lp, lsel, pl.NC, pl.lr, d);
     d.pnN = pl.nbN;
