@@ -343,6 +343,31 @@ def test_mixed_all_fp64_groups_equal_f64_batched():
     assert np.all(err <= 1e-8), err
 
 
+def test_mixed_tail_split():
+    """Mixed refinement of a tall problem (860 row blocks of 128) whose A W product computes its
+    last round as column pieces: the FP32 inner solves sum their pieces in FP32 and in 16-row
+    blocks whose extra norm partials the beta reduction adds after each product, but not after the
+    refinement's initial residual.  FP32 refinement must actually run, and every lambda must be
+    within 1e-8 of the oracle with the split and without it."""
+    p = W.over_gauss(m=110000, n=256, N=32, sig_lo=1e-2, lam_lo=1e-4, s=1024)
+    old = tik.get_option("gemm_n_tail")
+    try:
+        out = {}
+        for opt in (1, 0):
+            tik.set_option("gemm_n_tail", opt)
+            res, _ = _solve([p], tik.MIXED_BATCHED, tol=1e-10, maxit=200)
+            out[opt] = (res.x_numpy(0), res.status.cpu().numpy()[0], tik.lsqr_info())
+    finally:
+        tik.set_option("gemm_n_tail", old)
+    Xo = oracle.solve(p.A, p.b, p.lams)
+    for opt, (X, st, info) in out.items():
+        err = oracle.rel_err(X, Xo)
+        print("tail", opt, "max rel err %.2e" % err.max(), "(fp32, fp64) lambdas", info)
+        assert info[0] > 0, info
+        assert np.all(st == tik.ST_CONVERGED), st
+        assert np.all(err <= 1e-8), err
+
+
 # ------------------------------------------------------------- wide problems --
 
 @pytest.mark.parametrize("mode", [tik.F64_BATCHED, tik.PLAIN_F64_PER_LAMBDA, tik.MIXED_BATCHED])
