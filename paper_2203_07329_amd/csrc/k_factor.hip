@@ -182,6 +182,9 @@ __global__ void __launch_bounds__(256) k_syrk(const double* __restrict__ Z, int6
 }
 
 // ----------------------------------------------------- shifted copies -------
+// The upper triangle (diagonal included) of C + lam I: the factorization reads
+// nothing else, and everything below the diagonal is written before it is read
+// (diagonal blocks by k_trinv_diag, the inverse's temporaries, k_zero_lower).
 __global__ void k_shift_copy(const double* __restrict__ C, int64_t n, const double* __restrict__ lams,
                              double* __restrict__ R) {
   const int64_t mat = blockIdx.y;
@@ -191,7 +194,7 @@ __global__ void k_shift_copy(const double* __restrict__ C, int64_t n, const doub
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < nn;
        e += int64_t(gridDim.x) * blockDim.x) {
     const int64_t r = e % n, c = e / n;
-    Rm[e] = C[e] + (r == c ? lam : 0.0);
+    if (r <= c) Rm[e] = C[e] + (r == c ? lam : 0.0);
   }
 }
 
@@ -507,8 +510,8 @@ __global__ void __launch_bounds__(256, 4) k_trinv_lvl_x(const CholJob* __restric
   });
 }
 
-// Clear the strict lower triangle (the level temporaries and the lower half
-// of C + lam I left by the factorization).
+// Clear the strict lower triangle (the level temporaries and whatever the
+// factorization's diagonal tiles left below the diagonal).
 __global__ void __launch_bounds__(256) k_zero_lower(const CholJob* __restrict__ jobs) {
   const CholJob J = jobs[blockIdx.y];
   const int64_t n = J.n;

@@ -232,7 +232,8 @@ struct CholJob {
   double floor;
   int32_t given, pad_;
 };
-// R_j <- C + lams[j] I for the nb_mat lambdas of one problem (R_j at R + j n^2).
+// R_j <- upper triangle of C + lams[j] I for the nb_mat lambdas of one problem
+// (R_j at R + j n^2; below the diagonal R_j is left as it was).
 int launch_shift_copy(const double* C, int64_t n, const double* lams, int32_t nb_mat, double* R,
                       hipStream_t st);
 // Factor and invert every job of the table (device memory), sorted by n,
