@@ -160,9 +160,14 @@ __device__ __forceinline__ void tile_zero(f64x4 (&acc)[2][2]) {
 
 // ---------------------------------------------------------------- Gram ------
 // C (n x n, ld n) = Z^T Z with Z K x n column-major (ld ldz), on the matrix
-// cores.  Upper tile pairs are computed and written to both triangles.
+// cores.  Upper tile pairs are computed and written to both triangles.  The
+// contraction is split into gridDim.y slices of kc rows of Z: slice 0 writes
+// C, slice z > 0 the n x n block P + (z - 1) n^2, and k_gram_sum adds those to
+// C in slice order (the few hundred tile pairs of a 2000-column Gram would
+// otherwise leave some CUs a third block while most have two).
 __global__ void __launch_bounds__(256) k_syrk(const double* __restrict__ Z, int64_t K, int64_t n,
-                                              int64_t ldz, double* __restrict__ C, int nt) {
+                                              int64_t ldz, double* __restrict__ C,
+                                              double* __restrict__ P, int nt, int64_t kc) {
   __shared__ TileLds L;
   // map blockIdx.x to tile pair (ti <= tj)
   int t = blockIdx.x, ti = 0;
@@ -170,15 +175,27 @@ __global__ void __launch_bounds__(256) k_syrk(const double* __restrict__ Z, int6
   const int tj = ti + t;
   const int64_t a0 = int64_t(ti) * 64, b0 = int64_t(tj) * 64;
   const int na = int(min<int64_t>(64, n - a0)), nb = int(min<int64_t>(64, n - b0));
+  const int64_t k0 = int64_t(blockIdx.y) * kc, k1 = min(K, k0 + kc);
+  double* __restrict__ out = blockIdx.y == 0 ? C : P + int64_t(blockIdx.y - 1) * n * n;
   f64x4 acc[2][2];
   tile_zero(acc);
-  tile_mma<true>(Z + a0 * ldz, ldz, Z + b0 * ldz, ldz, K, na, nb, L, acc);
+  tile_mma<true>(Z + k0 + a0 * ldz, ldz, Z + k0 + b0 * ldz, ldz, max<int64_t>(0, k1 - k0), na, nb, L, acc);
   tile_for_each(acc, [&](int i, int j, double v) {
     if (i < na && j < nb) {
-      C[(a0 + i) + (b0 + j) * n] = v;
-      C[(b0 + j) + (a0 + i) * n] = v;
+      out[(a0 + i) + (b0 + j) * n] = v;
+      out[(b0 + j) + (a0 + i) * n] = v;
     }
   });
+}
+
+// C += P_0 + P_1 + ... (np blocks of nn values at P), in that order.
+__global__ void k_gram_sum(double* __restrict__ C, const double* __restrict__ P, int np, int64_t nn) {
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < nn;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    double s = C[e];
+    for (int z = 0; z < np; ++z) s += P[int64_t(z) * nn + e];
+    C[e] = s;
+  }
 }
 
 // ----------------------------------------------------- shifted copies -------
@@ -559,12 +576,32 @@ int launch_gram_norm_bound(const double* C, int64_t n, double* scratch, double* 
 }
 
 // ---------------------------------------------------------------- launchers --
-int launch_syrk(const double* Z, int64_t K, int64_t n, int64_t ldz, double* C, hipStream_t st) {
+int launch_syrk(const double* Z, int64_t K, int64_t n, int64_t ldz, double* C, double* P, int maxp,
+                hipStream_t st) {
   const int nt = int(cdiv(n, 64));
+  const int64_t pairs = int64_t(nt) * (nt + 1) / 2;
   ProfScope ps("gram", st);
-  hipLaunchKernelGGL(k_syrk, dim3(unsigned(nt * (nt + 1) / 2)), dim3(256), 0, st, Z, K, n, ldz,
-                     C, nt);
+  // slices: about eight blocks per CU in all, each slice at least 512 rows of Z
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 0;
+  int64_t ks = 1;
+  if (P && maxp > 0 && cus > 0) {
+    const int64_t hi = std::max<int64_t>(1, std::min<int64_t>(1 + maxp, K / 512));
+    ks = std::min<int64_t>(hi, std::max<int64_t>(1, cdiv(8 * int64_t(cus), pairs)));
+  }
+  const int64_t kc = cdiv(std::max<int64_t>(K, 1), ks);
+  ks = cdiv(std::max<int64_t>(K, 1), kc);          // no empty slice
+  hipLaunchKernelGGL(k_syrk, dim3(unsigned(pairs), unsigned(ks)), dim3(256), 0, st, Z, K, n, ldz, C, P,
+                     nt, kc);
   TIK_LAUNCHED("k_syrk");
+  if (ks > 1) {
+    const int64_t nn = n * n;
+    hipLaunchKernelGGL(k_gram_sum, dim3(unsigned(std::min<int64_t>(cdiv(nn, 256), 4096))), dim3(256), 0,
+                       st, C, static_cast<const double*>(P), int(ks - 1), nn);
+    TIK_LAUNCHED("k_gram_sum");
+  }
   return TIK_OK;
 }
 

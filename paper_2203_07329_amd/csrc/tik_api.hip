@@ -832,7 +832,8 @@ int tik_precond(tik_sketch_t sk, int32_t route, const double* lambdas, int32_t N
       const int64_t kd = std::min(sk->probs[k].m, sk->probs[k].n);
       const int ln = k % lanes.n;
       hipStream_t ls = lanes.at(k);
-      TIK_TRY(launch_syrk(sk->Y[k], sk->yrows[k], kd, sk->yrows[k], pp.C_l[ln], ls));
+      // the problem's N lambda copies are written after the Gram: room for its partial products
+      TIK_TRY(launch_syrk(sk->Y[k], sk->yrows[k], kd, sk->yrows[k], pp.C_l[ln], pp.Rinv[k], N, ls));
       TIK_TRY(launch_gram_norm_bound(pp.C_l[ln], kd, pp.colsum_l[ln], pp.cnorm + k, ls));
       TIK_TRY(launch_shift_copy(pp.C_l[ln], kd, pp.lams + size_t(k) * N, N, pp.Rinv[k], ls));
     }

@@ -210,7 +210,10 @@ int launch_sparse_sketch(const void* A, int a_f32, int64_t m, int64_t n, int64_t
                          int zeta, uint64_t seed, int32_t* map, double* Y, hipStream_t st);
 
 // factorization (k_factor.hip)
-int launch_syrk(const double* Z, int64_t K, int64_t n, int64_t ldz, double* C, hipStream_t st);
+// C = Z^T Z (n x n).  P: room for up to maxp more n x n blocks (or null), where
+// the partial products of a split contraction are kept until they are added.
+int launch_syrk(const double* Z, int64_t K, int64_t n, int64_t ldz, double* C, double* P, int maxp,
+                hipStream_t st);
 int launch_gram_norm_bound(const double* C, int64_t n, double* scratch, double* out,
                            hipStream_t st);
 // One shifted matrix of the batched Cholesky-inverse: R (n x n, ld n) holds
