@@ -67,53 +67,57 @@ __device__ uint32_t feistel_perm(uint32_t x, int k, uint2 key) {
   return 0xFFFFFFFFu;
 }
 
-// One workgroup: draw the s sampled rows, sort them ascending (bitonic sort in
-// LDS), write them, and for the two-pass transform the start of every bucket
-// of 2^bbits consecutive rows.  Also writes the sign bits of D (m'/32 words).
-static constexpr int ROWS_MAX = 16384;
+// One workgroup: draw the s sampled rows (the first s values of the Feistel
+// permutation of [0, 2^k)), mark them in an LDS bitmap of 2^k bits, and write
+// them in ascending order: each thread owns a contiguous range of the bitmap's
+// words, a prefix count over the block gives the rank of its first row, and
+// its set bits follow in order.  The start of every bucket of 2^bbits
+// consecutive rows (the number of sampled rows below it) comes from the same
+// counts.  Also writes the sign bits of D (m'/32 words).  k <= ROWS_KMAX.
+static constexpr int ROWS_KMAX = 18;
 
 __global__ void __launch_bounds__(1024) k_srht_rows(uint64_t seed, int k, int64_t s,
                                                     int32_t* __restrict__ rows,
                                                     int32_t* __restrict__ bstart, int bbits,
                                                     uint32_t* __restrict__ signs) {
-  __shared__ int32_t buf[ROWS_MAX];
+  __shared__ uint32_t bits[1 << (ROWS_KMAX - 5)];
+  __shared__ int32_t wsum[16];
   const uint2 key = seed_key(seed);
-  const int tid = threadIdx.x;
-  int P = 1;
-  while (P < s) P <<= 1;
-  for (int i = tid; i < P; i += blockDim.x)
-    buf[i] = (i < s) ? (k == 0 ? 0 : int32_t(feistel_perm(uint32_t(i), k, key))) : 0x7FFFFFFF;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int words = k >= 5 ? 1 << (k - 5) : 1;
+  const uint32_t lim = 1u << k;
+  for (int w = tid; w < words; w += 1024) bits[w] = 0u;
   __syncthreads();
-  for (int len = 2; len <= P; len <<= 1) {
-    for (int str = len >> 1; str > 0; str >>= 1) {
-      for (int i = tid; i < P; i += blockDim.x) {
-        const int j = i ^ str;
-        if (j > i) {
-          const bool up = (i & len) == 0;
-          const int32_t a = buf[i], b = buf[j];
-          if ((a > b) == up) {
-            buf[i] = b;
-            buf[j] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
+  for (int64_t i = tid; i < s; i += 1024) {
+    const uint32_t x = k == 0 ? 0u : feistel_perm(uint32_t(i), k, key);
+    if (x < lim) atomicOr(&bits[x >> 5], 1u << (x & 31u));
   }
-  for (int i = tid; i < s; i += blockDim.x) rows[i] = buf[i];
-  const int nb = 1 << (k - bbits);
-  for (int hb = tid; hb <= nb; hb += blockDim.x) {
-    // first q with rows[q] >= hb << bbits
-    const int32_t key_row = (hb == nb) ? 0x7FFFFFFF : (hb << bbits);
-    int lo = 0, hi = int(s);
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (buf[mid] < key_row) lo = mid + 1; else hi = mid;
-    }
-    bstart[hb] = (hb == nb) ? int32_t(s) : lo;
+  __syncthreads();
+  const int wpt = (words + 1023) / 1024;
+  const int w0 = min(words, tid * wpt), w1 = min(words, w0 + wpt);
+  int cnt = 0;
+  for (int w = w0; w < w1; ++w) cnt += __popc(bits[w]);
+  int inc = cnt;                               // inclusive count within the wave
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
   }
-  const int words = ((1 << k) + 31) >> 5;
-  for (int w = tid; w < words; w += blockDim.x) {
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  int rank = inc - cnt;                        // rows below this thread's first word
+  for (int q = 0; q < wv; ++q) rank += wsum[q];
+  const int64_t step = int64_t(1) << bbits;
+  for (int w = w0; w < w1; ++w) {
+    const uint32_t v0 = bits[w];
+    const int64_t p0 = int64_t(w) << 5;
+    for (int64_t pos = (p0 + step - 1) / step * step; pos < p0 + 32 && pos < int64_t(lim); pos += step)
+      bstart[pos >> bbits] = rank + __popc(v0 & ((1u << uint32_t(pos - p0)) - 1u));
+    for (uint32_t v = v0; v; v &= v - 1u) rows[rank++] = int32_t(p0 + __ffs(v) - 1);
+  }
+  if (tid == 0) bstart[1 << (k - bbits)] = int32_t(s);
+  const int nwords = ((1 << k) + 31) >> 5;
+  for (int w = tid; w < nwords; w += blockDim.x) {
     const uint4 v = philox4x32_10(make_uint4(uint32_t(w >> 2), 0u, TAG_SIGN, 0u), key);
     const uint32_t sel = w & 3;
     signs[w] = sel == 0 ? v.x : sel == 1 ? v.y : sel == 2 ? v.z : v.w;
@@ -967,6 +971,10 @@ __global__ void __launch_bounds__(256) k_col_pow2(const TA* __restrict__ A, int6
 // ---------------------------------------------------------------- launchers --
 int launch_srht_rows(uint64_t seed, int k, int64_t s, int32_t* rows, int32_t* bstart, int bbits,
                      hipStream_t st) {
+  if (k < 0 || k > ROWS_KMAX || bbits < 0 || bbits > k || s < 0 || s > (int64_t(1) << k)) {
+    set_error("internal: SRHT row sampler needs 0 <= bbits <= k <= 18 and s <= 2^k");
+    return TIK_EINVAL;
+  }
   // signs live right after the bucket table (caller sized it)
   uint32_t* signs = reinterpret_cast<uint32_t*>(bstart + (1 << (k - bbits)) + 1);
   ProfScope ps("sketch", st);
