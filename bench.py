@@ -175,20 +175,19 @@ def measured_traffic(workload, family):
         key = FAMILY_KERNEL.get(family)
         bpd = rec["bytes_per_dispatch"]
         if family == "gemm_n":
-            # one A W launch of the family can be three kernels: the row blocks of
-            # k_gemm_n_mfma<TA, TC, NC, 0, RT>, the column pieces of its last round
-            # (<TA, TC, NC, 2, RT>) and their sum (k_gemm_n_tail_fin<TC>)
+            # one A W launch of the family is k_gemm_n_mfma<TA, TC, NC, 0, RT> (every
+            # row block), or, where the last round is split into column pieces,
+            # k_gemm_n_mfma<TA, TC, NC, 3, RT> (the row blocks and the pieces) and
+            # their sum (k_gemm_n_tail_fin<TC>)
             best = None
             for k, v in bpd.items():
                 if "k_gemm_n_mfma<" not in k:
                     continue
                 args = k.split("k_gemm_n_mfma<", 1)[1].split(">", 1)[0].split(",")
-                if len(args) != 5 or args[3].strip() != "0":
+                if len(args) != 5 or args[3].strip() not in ("0", "3"):
                     continue
                 tot = v
-                args[3] = " 2"
-                tot += bpd.get(k.replace(k.split("k_gemm_n_mfma<", 1)[1].split(">", 1)[0], ",".join(args)), 0)
-                if tot > v:     # the tail's pieces ran: add their sum
+                if args[3].strip() == "3":
                     tot += max([w for kk, w in bpd.items()
                                 if "k_gemm_n_tail_fin<" + args[1].strip() + ">" in kk] or [0])
                 best = tot if best is None else max(best, tot)

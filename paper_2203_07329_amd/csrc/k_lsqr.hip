@@ -1041,6 +1041,7 @@ struct Plan {
   int64_t tailNX = 0;                   // norm partials of the sum's sub-blocks 1.. (tailPn)
   DevProb Ptail = {};
   std::vector<Item> itTail;
+  std::vector<Item> itNT;               // the row blocks before the tail, then its pieces (j = 1)
   LrTables lr;                          // low-rank apply: proj, expand, fin
   bool lowrank = false;
   int cpw = 16;
@@ -1053,8 +1054,8 @@ struct Bufs {
   DevProb* P;
   Item *itN, *itB, *itT, *itQ, *itR, *itM;
   DevProb* Ptail;     // the A W tail's problem (rows from the tail on)
-  Item* itTail;       // its column pieces
-  void* tailPart;     // their partial products (compute type)
+  Item* itNT;         // one launch's items: the row blocks before the tail, then its pieces
+  void* tailPart;     // the tail pieces' partial products (compute type)
   double* tailPn;     // norm partials of the tail sum's sub-blocks 1..
   LrDev lr;
   Scal* sc;
@@ -1319,12 +1320,15 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
   // row block (200000 x 2000, 32 lambdas: 1563 blocks, 768 resident, 0.79 ms
   // per launch against 0.70 ms for 1536 blocks).  When that round is at most
   // half full, its row blocks are computed instead as column pieces spread
-  // over the whole GPU: a second launch of the product stores the pieces'
-  // partial products, and k_gemm_n_tail_fin sums them in piece order and
-  // applies the update (kernel boundaries order the two, so no fences).
+  // over the whole GPU: the pieces follow the other row blocks in the same
+  // launch (they fill the compute units as the last full round drains) and
+  // store their partial products, and k_gemm_n_tail_fin sums them in piece
+  // order and applies the update (the kernel boundary orders the two, so no
+  // fences).
   pl.tailQ = 0;
   pl.tailNX = 0;
   pl.itTail.clear();
+  pl.itNT.clear();
   pl.tailBlk0 = pl.P.empty() ? 0 : pl.P[0].nblkN;
   if (option_gemm_n_tail() && np == 1 && pl.NC >= 16 && N <= TAILF / TAILR && pl.rbN == 128 &&
       pl.P[0].n >= 256) {
@@ -1351,6 +1355,11 @@ void make_plan(const tik_problem* probs, const tik_precond_s* pc, const std::vec
         for (int64_t b = 0; b < r; ++b)
           for (int64_t c = 0; c < q; ++c) pl.itTail.push_back({0, int32_t(b), int32_t(c), 0});
         pl.tailNX = r * (TAILS - 1);
+        pl.itNT.assign(pl.itN.begin(), pl.itN.begin() + pl.tailBlk0);
+        for (Item t2 : pl.itTail) {
+          t2.j = 1;
+          pl.itNT.push_back(t2);
+        }
       }
     }
   }
@@ -1422,7 +1431,7 @@ void take_bufs(Arena& a, const Plan& pl, size_t tc, Bufs& b) {
   b.itR = a.take<Item>(pl.itR.size());
   b.itM = a.take<Item>(pl.itM.size());
   b.Ptail = a.take<DevProb>(pl.tailQ ? 1 : 0);
-  b.itTail = a.take<Item>(pl.itTail.size());
+  b.itNT = a.take<Item>(pl.itNT.size());
   b.tailPart = a.take<double>(size_t(pl.tailQ) * size_t(pl.tailMt) * size_t(N));
   b.tailPn = a.take<double>(size_t(pl.tailNX) * size_t(N));
   take_lr(a, pl.lr, b.lr);
@@ -1476,10 +1485,8 @@ struct Kern {
       if (!pl.tailQ)
         return launch_gemm_n_mfma(a32, c32, NC, 0, pl.rbN, b.P, b.itN, int(pl.itN.size()), pl.N, W,
                                   b.ut, nullptr, b.sc, b.pnN, st);
-      TIK_TRY(launch_gemm_n_mfma(a32, c32, NC, 0, pl.rbN, b.P, b.itN, int(pl.tailBlk0), pl.N, W, b.ut,
-                                 nullptr, b.sc, b.pnN, st));
-      TIK_TRY(launch_gemm_n_mfma(a32, c32, NC, 2, pl.rbN, b.Ptail, b.itTail, int(pl.itTail.size()),
-                                 pl.N, W, b.tailPart, nullptr, b.sc, nullptr, st));
+      TIK_TRY(launch_gemm_n_mfma(a32, c32, NC, 3, pl.rbN, b.P, b.itNT, int(pl.itNT.size()), pl.N, W,
+                                 b.ut, nullptr, b.sc, b.pnN, st, b.Ptail, b.tailPart));
       hipLaunchKernelGGL(k_gemm_n_tail_fin<TC>,
                          dim3(unsigned((int64_t(pl.itN.size()) - pl.tailBlk0) * TAILS)), dim3(TAILF), 0,
                          st, b.P, pl.N, pl.tailBlk0, pl.tailMt, pl.tailQ,
@@ -1814,8 +1821,8 @@ int upload_plan(const Plan& pl, const Bufs& b, const tik_precond_s* pc, double* 
     DevProb t = pl.Ptail;
     t.live = b.cnt;
     TIK_TRY(upload(b.Ptail, stash(&t, sizeof(DevProb)), sizeof(DevProb), st));
-    TIK_TRY(upload(b.itTail, stash(pl.itTail.data(), pl.itTail.size() * sizeof(Item)),
-                   pl.itTail.size() * sizeof(Item), st));
+    TIK_TRY(upload(b.itNT, stash(pl.itNT.data(), pl.itNT.size() * sizeof(Item)),
+                   pl.itNT.size() * sizeof(Item), st));
   }
   const LrTables& lr = pl.lr;
   TIK_TRY(upload(b.lr.itLP, stash(lr.itLP.data(), lr.itLP.size() * sizeof(Item)), lr.itLP.size() * sizeof(Item), st));

@@ -54,7 +54,9 @@ __global__ void __launch_bounds__(256, RT == 2 ? 3 : 2) k_gemm_n_mfma(const DevP
                                                      const TC* __restrict__ W,
                                                      TC* __restrict__ ut, double* __restrict__ out,
                                                      const Scal* __restrict__ sc,
-                                                     double* __restrict__ pnN) {
+                                                     double* __restrict__ pnN,
+                                                     const DevProb* __restrict__ P2,
+                                                     TC* __restrict__ part2) {
   using M = Mfma<TC>;
   constexpr int NT = NC / 16;
   // columns per chunk: 128 bytes of each row (64 where FP64 operands of
@@ -65,7 +67,13 @@ __global__ void __launch_bounds__(256, RT == 2 ? 3 : 2) k_gemm_n_mfma(const DevP
   __shared__ TC Ws[2][KC][WP];
   __shared__ double nred[4][NC];
   const Item it = items[blockIdx.x];
-  const DevProb& pr = P[it.p];
+  // EPI 3: the row blocks (EPI 0) and, flagged by it.j, the column pieces of
+  // the last round's row blocks (EPI 2 on descriptor P2, stored to part2) in
+  // one launch, listed after the row blocks so that they fill the compute
+  // units the row blocks' last round leaves idle
+  const bool piece = EPI == 3 && it.j != 0;
+  const bool ep0 = EPI == 0 || (EPI == 3 && !piece);
+  const DevProb& pr = piece ? *P2 : P[it.p];
   if (pr.live && *pr.live == 0) return;   // every solve of the plan has stopped
   const TA* __restrict__ A = static_cast<const TA*>(pr.A);
   const int64_t m = pr.m, n = pr.n, lda = pr.lda;
@@ -147,7 +155,7 @@ __global__ void __launch_bounds__(256, RT == 2 ? 3 : 2) k_gemm_n_mfma(const DevP
   for (int nt = 0; nt < NT; ++nt) {
     nsum[nt] = 0.0;
     const int lam = nt * 16 + li;
-    const double uc = (EPI == 0 && lam < N) ? sc[it.p * N + lam].ucoef : 0.0;
+    const double uc = (ep0 && lam < N) ? sc[it.p * N + lam].ucoef : 0.0;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -155,19 +163,19 @@ __global__ void __launch_bounds__(256, RT == 2 ? 3 : 2) k_gemm_n_mfma(const DevP
         const int64_t row = row0 + rt * 16 + M::row(lane, v);
         if (row < m && lam < N) {
           const int64_t idx = (pr.offR + row) * N + lam;
-          if (EPI == 0) {
+          if (ep0) {
             const TC nv = TC(acc[rt][nt][v] - TC(uc) * ut[idx]);
             ut[idx] = nv;
             nsum[nt] += double(nv) * double(nv);
           } else if (EPI == 1) {
             out[idx] = double(acc[rt][nt][v]);
           } else {
-            ut[(pr.pnOff + int64_t(it.ch) * m + row) * N + lam] = acc[rt][nt][v];
+            (EPI == 3 ? part2 : ut)[(pr.pnOff + int64_t(it.ch) * m + row) * N + lam] = acc[rt][nt][v];
           }
         }
       }
   }
-  if (EPI != 0) return;
+  if (!ep0) return;                       // uniform over the block
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
     double v = nsum[nt];
@@ -292,18 +300,22 @@ __global__ void __launch_bounds__(256) k_gemm_t_mfma(const DevProb* __restrict__
 template <typename TA, typename TC, int RT>
 static int gemm_n_rt(int nc, int epi, const DevProb* P, const Item* items, int nitems, int N,
                      const void* Wv, void* ut, double* out, const Scal* sc, double* pnN,
-                     hipStream_t st) {
+                     const DevProb* P2, void* part2, hipStream_t st) {
   const TC* W = static_cast<const TC*>(Wv);
   const dim3 g = dim3(unsigned(nitems)), b = dim3(256);
   TC* u = static_cast<TC*>(ut);
+  TC* p2 = static_cast<TC*>(part2);
 #define TIK_GN(NCV, EPIV)                                                                     \
   if (nc == NCV && epi == EPIV) {                                                            \
     hipLaunchKernelGGL((k_gemm_n_mfma<TA, TC, NCV, EPIV, RT>), g, b, 0, st, P, items, N, W, u, \
-                       out, sc, pnN);                                                        \
+                       out, sc, pnN, P2, p2);                                                \
     TIK_LAUNCHED("k_gemm_n_mfma");                                                           \
     return TIK_OK;                                                                           \
   }
   TIK_GN(16, 0) TIK_GN(32, 0) TIK_GN(16, 1) TIK_GN(32, 1) TIK_GN(16, 2) TIK_GN(32, 2)
+  if constexpr (RT == 2) {
+    TIK_GN(16, 3) TIK_GN(32, 3)
+  }
 #undef TIK_GN
   set_error("internal: MFMA gemm_n needs 16 or 32 lambdas per pass");
   return TIK_EINVAL;
@@ -312,25 +324,33 @@ static int gemm_n_rt(int nc, int epi, const DevProb* P, const Item* items, int n
 template <typename TA, typename TC>
 static int gemm_n_nc(int rows, int nc, int epi, const DevProb* P, const Item* items, int nitems,
                      int N, const void* W, void* ut, double* out, const Scal* sc, double* pnN,
-                     hipStream_t st) {
-  if (rows == 128) return gemm_n_rt<TA, TC, 2>(nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
-  if (rows == 256) return gemm_n_rt<TA, TC, 4>(nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
-  set_error("internal: MFMA gemm_n blocks are 128 or 256 rows");
+                     const DevProb* P2, void* part2, hipStream_t st) {
+  if (rows == 128)
+    return gemm_n_rt<TA, TC, 2>(nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, P2, part2, st);
+  if (rows == 256 && epi != 3)
+    return gemm_n_rt<TA, TC, 4>(nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, P2, part2, st);
+  set_error("internal: MFMA gemm_n blocks are 128 or 256 rows (128 with the tail's pieces)");
   return TIK_EINVAL;
 }
 
 int launch_gemm_n_mfma(int ta_f32, int tc_f32, int nc, int epi, int rows, const DevProb* P,
                        const Item* items, int nitems, int N, const void* W, void* ut,
-                       double* out, const Scal* sc, double* pnN, hipStream_t st) {
+                       double* out, const Scal* sc, double* pnN, hipStream_t st,
+                       const DevProb* P2, void* part2) {
+  if (epi == 3 && (!P2 || !part2)) {
+    set_error("internal: the combined A W launch needs the tail's descriptor and buffer");
+    return TIK_EINVAL;
+  }
   if (tc_f32) {
     if (!ta_f32) {
       set_error("internal: FP32 products need FP32 storage");
       return TIK_EINVAL;
     }
-    return gemm_n_nc<float, float>(rows, nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
+    return gemm_n_nc<float, float>(rows, nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, P2, part2, st);
   }
-  if (ta_f32) return gemm_n_nc<float, double>(rows, nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
-  return gemm_n_nc<double, double>(rows, nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, st);
+  if (ta_f32)
+    return gemm_n_nc<float, double>(rows, nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, P2, part2, st);
+  return gemm_n_nc<double, double>(rows, nc, epi, P, items, nitems, N, W, ut, out, sc, pnN, P2, part2, st);
 }
 
 // Blocks of the 128-row EPI 0 product resident at once on the current device

@@ -255,9 +255,14 @@ int launch_bp2_r(const double* Y, int64_t s, int64_t k, double lam, double* R, d
 // matrix-core products (k_mfma.hip)
 // rows: rows of A per gemm_n block (128 or 256); cols: columns per gemm_t block (64 or 128).
 // W is in the compute type (float when tc_f32, else double).
+// epi 0: u~_top update and norm partials; 1: store A W to out; 2: partial
+// products of column chunk it.ch into ut; 3 (128-row blocks): epi 0 for the
+// items with j == 0 and, for those with j != 0, epi 2 on descriptor P2 into
+// part2, in one launch.
 int launch_gemm_n_mfma(int ta_f32, int tc_f32, int nc, int epi, int rows, const DevProb* P,
                        const Item* items, int nitems, int N, const void* W, void* ut,
-                       double* out, const Scal* sc, double* pnN, hipStream_t st);
+                       double* out, const Scal* sc, double* pnN, hipStream_t st,
+                       const DevProb* P2 = nullptr, void* part2 = nullptr);
 // 128-row EPI 0 blocks resident at once on the current device; 0 if unknown.
 int gemm_n_resident(int ta_f32, int tc_f32, int nc);
 int launch_gemm_t_mfma(int ta_f32, int tc_f32, int u_f64, int nc, int cols, const DevProb* P,
