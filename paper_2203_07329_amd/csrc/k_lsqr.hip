@@ -65,7 +65,9 @@ static constexpr int VB = 32;
 // -------------------------------------------------------------- init u -----
 // u~ = [rhs_top; rhs_bot] (rhs_top == null: b for every lambda; rhs_bot == null:
 // zero) and partial squared norms.  Items: gemm_n blocks (top) then vec_bot
-// blocks (bottom), one launch.  Top rows stored in TC.
+// blocks (bottom), one launch.  Top rows stored in TC.  Thread t handles
+// lambda t % N of rows t / N, t / N + BLK / N, ... of the block, and each
+// lambda's partial is summed over its threads in a fixed order (one barrier).
 template <typename TC>
 __global__ void __launch_bounds__(BLK) k_init_u(const DevProb* __restrict__ P,
                                                 const Item* __restrict__ itN, int nItN, int rbN,
@@ -74,7 +76,7 @@ __global__ void __launch_bounds__(BLK) k_init_u(const DevProb* __restrict__ P,
                                                 const double* __restrict__ rhs_bot,
                                                 TC* __restrict__ ut, double* __restrict__ ub,
                                                 double* __restrict__ pnN, double* __restrict__ pnB) {
-  __shared__ double red[4];
+  __shared__ double red[BLK];
   const bool top = int(blockIdx.x) < nItN;
   const Item it = top ? itN[blockIdx.x] : itB[blockIdx.x - nItN];
   const DevProb& pr = P[it.p];
@@ -83,9 +85,11 @@ __global__ void __launch_bounds__(BLK) k_init_u(const DevProb* __restrict__ P,
   const int64_t r0 = int64_t(it.blk) * rb;
   const int64_t r1 = min(rows, r0 + rb);
   double* pn = top ? pnN + (pr.pnN + it.blk) * N : pnB + (pr.pnB + it.blk) * N;
-  for (int i = 0; i < N; ++i) {
-    double acc = 0.0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += BLK) {
+  const int rpp = BLK / N;                    // rows per pass
+  const int t = threadIdx.x, i = t % N, rr = t / N;
+  double loc = 0.0;
+  if (rr < rpp) {
+    for (int64_t r = r0 + rr; r < r1; r += rpp) {
       double v;
       if (top) {
         v = rhs_top ? rhs_top[(pr.offL + r) * N + i] : pr.b[r];
@@ -96,10 +100,15 @@ __global__ void __launch_bounds__(BLK) k_init_u(const DevProb* __restrict__ P,
         v = rhs_bot ? rhs_bot[(pr.offS + r) * N + i] : 0.0;
         ub[(pr.offS + r) * N + i] = v;
       }
-      acc += v * v;
+      loc += v * v;
     }
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) pn[i] = s;
+  }
+  red[t] = loc;
+  __syncthreads();
+  if (t < N) {
+    double sum = 0.0;
+    for (int j = 0; j < rpp; ++j) sum += red[t + j * N];
+    pn[t] = sum;
   }
 }
 
@@ -696,7 +705,7 @@ __global__ void __launch_bounds__(BLK) k_init_u_ir(const DevProb* __restrict__ P
                                                    const double* __restrict__ g,
                                                    TC* __restrict__ ut, double* __restrict__ ub,
                                                    double* __restrict__ pnN, double* __restrict__ pnB) {
-  __shared__ double red[4];
+  __shared__ double red[BLK];
   const bool top = int(blockIdx.x) < nItN;
   const Item it = top ? itN[blockIdx.x] : itB[blockIdx.x - nItN];
   const DevProb& pr = P[it.p];
@@ -705,13 +714,15 @@ __global__ void __launch_bounds__(BLK) k_init_u_ir(const DevProb* __restrict__ P
   const int64_t r0 = int64_t(it.blk) * rb;
   const int64_t r1 = min(rows, r0 + rb);
   double* pn = top ? pnN + (pr.pnN + it.blk) * N : pnB + (pr.pnB + it.blk) * N;
-  for (int i = 0; i < N; ++i) {
+  const int rpp = BLK / N;                    // rows per pass, as in k_init_u
+  const int t = threadIdx.x, i = t % N, rr = t / N;
+  double loc = 0.0;
+  if (rr < rpp) {
     const Scal& S = sc[it.p * N + i];
     const int li = S.li - l0;
     const bool on = use[it.p * N + i] != 0;
     const double isq = 1.0 / S.sqlam;
-    double acc = 0.0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += BLK) {
+    for (int64_t r = r0 + rr; r < r1; r += rpp) {
       double v;
       if (top) {
         v = on ? f[(pr.irL + r) * NF + li] : 0.0;
@@ -722,10 +733,15 @@ __global__ void __launch_bounds__(BLK) k_init_u_ir(const DevProb* __restrict__ P
         v = on ? g[(pr.irS + r) * NF + li] * isq : 0.0;
         ub[(pr.offS + r) * N + i] = v;
       }
-      acc += v * v;
+      loc += v * v;
     }
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) pn[i] = s;
+  }
+  red[t] = loc;
+  __syncthreads();
+  if (t < N) {
+    double sum = 0.0;
+    for (int j = 0; j < rpp; ++j) sum += red[t + j * N];
+    pn[t] = sum;
   }
 }
 
