@@ -125,7 +125,8 @@ __global__ void __launch_bounds__(BLK) k_fin_beta(const DevProb* __restrict__ P,
   const int j = blockIdx.x, p = j / N, i = j % N;
   const DevProb& pr = P[p];
   if (plan_stopped(pr)) return;
-  double v = 0.0;
+  double v = 0.0;                             // (unrolled: the loads go out together)
+#pragma unroll 4
   for (int b = threadIdx.x; b < pr.nblkN; b += BLK) v += pnN[(pr.pnN + b) * N + i];
   for (int b = threadIdx.x; b < pr.nblkB; b += BLK) v += pnB[(pr.pnB + b) * N + i];
   if (!init && p == 0)
@@ -394,13 +395,12 @@ __global__ void __launch_bounds__(BLK) k_reduce_t(const DevProb* __restrict__ P,
   const TC* src = part + (pr.ptOff + c) * N + i;
   const int64_t stride = n * N;
   int ch = 0;
-  for (; ch + 3 < pr.nchT; ch += 4) {
-    const double a0 = double(src[int64_t(ch) * stride]), a1 = double(src[int64_t(ch + 1) * stride]);
-    const double a2 = double(src[int64_t(ch + 2) * stride]), a3 = double(src[int64_t(ch + 3) * stride]);
-    s += a0;
-    s += a1;
-    s += a2;
-    s += a3;
+  for (; ch + 7 < pr.nchT; ch += 8) {      // eight loads in flight, added in chunk order
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = double(src[int64_t(ch + u) * stride]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += a[u];
   }
   for (; ch < pr.nchT; ++ch) s += double(src[int64_t(ch) * stride]);
   const Scal& S = sc[it.p * N + i];
